@@ -1,0 +1,188 @@
+/*
+ * vos.h -- C ABI of the MI355X (gfx950) Volume-of-Solid dissolution step.
+ *
+ * The library advances the micro-continuum model of Maes, Soulaine & Menke
+ * ("Improved Volume-of-Solid formulations for micro-continuum simulation of
+ * mineral dissolution at the pore-scale") on a uniform Cartesian voxel grid:
+ * Darcy-Brinkman-Stokes momentum with Kozeny-Carman drag (Section 2.2,
+ * Eq. momentumDBS, Eq. perm), the pressure equation from continuity
+ * (Eq. contDBSQS), quasi-static advection-diffusion-reaction of the acid
+ * (Eq. concentrationDBSQS) and the solid update (Eq. mbs) with the reaction
+ * rate of iVoS (Eq. RfiVoS), VoS-psi or VoS-psi' (Eq. RfVoSpsi, Section 2.4).
+ *
+ * Conventions
+ *  - Every call returns vos_status; VOS_OK is 0.  On failure the message of
+ *    the calling thread is available from vos_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - Units are SI with mol (the paper's kmol -> mol); p is the dynamic
+ *    pressure in Pa.
+ *  - Fields are FP64, x fastest: cell (i,j,k) at i + nx*(j + ny*k).  Face
+ *    grids (MAC): x-faces (nx+1)*ny*nz, y-faces nx*(ny+1)*nz, z-faces
+ *    nx*ny*(nz+1), indexed the same way over their own dims; face i of the
+ *    x grid sits between cells i-1 and i.  nz == 1 is a 2-D problem (no z
+ *    faces are used).
+ *  - Boundaries: x = 0 inlet (plug velocity u_in, concentration c_in),
+ *    x = nx*dx outlet (pressure p_out, zero normal gradient of u and c),
+ *    all other sides no-slip, no-flux walls.
+ *  - Memory: the library never allocates device memory.  The caller sizes a
+ *    workspace with vos_workspace_bytes(), allocates it (e.g. a torch
+ *    tensor) and hands it to vos_create(); the library carves every device
+ *    array from it.  The caller keeps ownership and must keep it alive until
+ *    vos_destroy().  A small pinned host buffer is allocated for reading
+ *    solver scalars back.
+ *  - Streams: all work is enqueued on the hipStream_t given to vos_create().
+ *    Calls on one handle are not thread-safe; different handles are
+ *    independent.  Every call that returns data to the host synchronises
+ *    that stream.
+ */
+#ifndef VOS_H
+#define VOS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VOS_OK = 0,
+  VOS_ERR_ARG = 1,     /* invalid argument (sizes, pointers, parameter ranges) */
+  VOS_ERR_DEVICE = 2,  /* a HIP runtime call failed */
+  VOS_ERR_NOCONV = 3,  /* a Krylov solve hit its iteration cap */
+  VOS_ERR_OOM = 4,     /* the workspace is smaller than vos_workspace_bytes() */
+  VOS_ERR_STATE = 5    /* call out of order (e.g. a step before the geometry) */
+} vos_status;
+
+/* Uniform voxel grid: nx >= 2, ny >= 1, nz >= 1 cells of edge dx [m]. */
+typedef struct { int nx, ny, nz; double dx; } vos_grid;
+
+/* Reaction-rate closure (Section 2.3 / 2.4). */
+typedef enum {
+  VOS_IVOS = 0,        /* Eq. RfiVoS: divergence of the reactive flux */
+  VOS_PSI = 1,         /* Eq. RfVoSpsi with psi = 4 eps (1 - eps) */
+  VOS_PSI_PRIME = 2    /* psi = lambda(eps) eps (1 - eps), lambda refitted every step */
+} vos_model;
+
+/* Arithmetic of the pressure multigrid preconditioner. */
+typedef enum {
+  VOS_FP64 = 0,        /* everything FP64 */
+  VOS_MIXED = 1        /* FP32 multigrid (smoothing, restriction, prolongation)
+                          inside FP64 CG: residuals, dot products, right-hand
+                          side and every global balance stay FP64 */
+} vos_precision;
+
+/* Physical parameters (Tables 1-3 of the paper give realistic values). */
+typedef struct {
+  double mu;        /* dynamic viscosity [Pa s] */
+  double rho;       /* fluid density [kg/m3] */
+  double D;         /* molecular diffusion coefficient [m2/s]; D* = D */
+  double k0;        /* Kozeny-Carman constant [m2] (Eq. perm) */
+  double kc;        /* surface reaction constant [m/s], R = kc c */
+  double Vm;        /* M_ws / rho_s [m3/mol] (Eq. mbs) */
+  double zeta;      /* stoichiometric coefficient of the acid */
+  double c_in;      /* inlet concentration [mol/m3] */
+  double eps_min;   /* porosity floor of the solid (Appendix C uses 1e-4) */
+  double u_in;      /* inlet plug velocity [m/s], >= 0 */
+  double p_out;     /* outlet pressure [Pa] */
+  int model;        /* vos_model */
+} vos_params;
+
+/* Solver options.  Tolerances are relative Jacobi-scaled residual norms:
+ * momentum and pressure ||D^-1/2 r|| <= rtol ||D^-1/2 b||, transport
+ * ||D^-1 r|| <= rtol ||D^-1 b|| (D the matrix diagonal). */
+typedef struct {
+  double rtol_u, rtol_p, rtol_c;
+  int maxit_u, maxit_p, maxit_c;
+  int precision;    /* vos_precision (pressure multigrid) */
+  int mg_nu;        /* Jacobi sweeps before and after each coarse correction (>= 1) */
+  int check_every;  /* Krylov iterations launched between host convergence checks (>= 1) */
+} vos_opts;
+
+/* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */
+typedef struct {
+  int it_u[3], it_p, it_c;       /* Krylov iterations of the last step */
+  double res_u[3], res_p, res_c; /* final relative residuals (see vos_opts) */
+  double lambda;                 /* psi prefactor used (4 for iVoS / VoS-psi) */
+  double solid_volume;           /* sum (1 - eps) V after the update       [m3] */
+  double surface_area;           /* sum |grad eps| V at the step's start    [m2] */
+  double porosity;               /* mean eps after the update */
+  double dP;                     /* mean inlet-cell p - p_out              [Pa] */
+  double K;                      /* mu u_in (nx - 1/2) dx / dP             [m2] */
+  double acid_in, acid_out;      /* inlet / outlet acid flux            [mol/s] */
+  double acid_consumed;          /* zeta * sum of the acid sink         [mol/s] */
+  double solid_rate;             /* sum Rbar V                          [mol/s] */
+  double acid_balance_rel;       /* (in - out - consumed) / in */
+  double solid_balance_rel;      /* (sum d(eps)V - dt Vm sum Rbar V + clipped) / (dt Vm |sum Rbar V|) */
+  double clipped_volume;         /* sum (eps_unclipped - eps_clipped) V    [m3] */
+  double max_deps;               /* max |eps^{n+1} - eps^n| */
+  double alpha;                  /* (1/a) sum c|grad eps|V / sum eps c V (Section 2.5) */
+  double t_ms[6];                /* GPU time of coefficients, momentum, pressure,
+                                    correction, transport, reaction+update [ms] */
+} vos_diag;
+
+/* Fields for vos_set_field / vos_get_field / vos_field_ptr. */
+typedef enum {
+  VOS_FIELD_EPS = 0,     /* porosity eps (cells) */
+  VOS_FIELD_UX = 1,      /* face velocities (x, y, z face grids) */
+  VOS_FIELD_UY = 2,
+  VOS_FIELD_UZ = 3,
+  VOS_FIELD_P = 4,       /* pressure (cells) */
+  VOS_FIELD_C = 5,       /* acid concentration (cells) */
+  VOS_FIELD_USTAR_X = 6, /* last momentum predictor (face grids; read only) */
+  VOS_FIELD_USTAR_Y = 7,
+  VOS_FIELD_USTAR_Z = 8,
+  VOS_FIELD_RBAR = 9,    /* last reaction rate Rbar [mol/m3/s] (cells; read only) */
+  VOS_FIELD_GMAG = 10    /* |grad eps| of the last step's start (cells; read only) */
+} vos_field;
+
+typedef struct vos_sim vos_sim;
+
+/* Bytes of device workspace a simulation of this grid and options needs. */
+vos_status vos_workspace_bytes(const vos_grid *grid, const vos_opts *opts, size_t *bytes);
+
+/* Create a simulation.  workspace: device pointer of at least
+ * vos_workspace_bytes() bytes, 256-byte aligned, owned by the caller.
+ * hip_stream: a hipStream_t (NULL = the null stream).  The state starts
+ * as fluid everywhere at rest with p = p_out and c = 0. */
+vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_opts *opts,
+                      void *workspace, size_t workspace_bytes, void *hip_stream, vos_sim **out);
+
+vos_status vos_destroy(vos_sim *sim);
+
+/* Geometry from the solid fraction eps_s in [0,1] (one value per cell):
+ * eps = clamp(1 - eps_s, eps_min, 1) (Appendix C).  Also resets the inlet
+ * face velocities to u_in.  eps_s is a host pointer (on_device = 0) or a
+ * device pointer (on_device = 1).  Values outside [0,1] give VOS_ERR_ARG. */
+vos_status vos_set_solid_fraction(vos_sim *sim, const double *eps_s, int on_device);
+
+/* Copy a whole field in or out (host or device buffer of the field's size).
+ * Read-only fields reject vos_set_field with VOS_ERR_ARG. */
+vos_status vos_set_field(vos_sim *sim, int field, const double *src, int on_device);
+vos_status vos_get_field(vos_sim *sim, int field, double *dst, int on_device);
+
+/* Borrowed device pointer of a field, valid until vos_destroy(). */
+vos_status vos_field_ptr(vos_sim *sim, int field, double **dev_ptr);
+
+/* Advance nsteps time steps of size dt [s].  Each step: coefficients from
+ * eps^n, momentum predictor, pressure equation (multigrid-preconditioned CG),
+ * velocity correction, quasi-static transport (BiCGStab), reaction rate and
+ * solid update.  flags bit 0 (VOS_FREEZE_SOLID): skip the solid update (flow
+ * and transport only; used to relax the initial state).  last (may be NULL)
+ * receives the diagnostics of the final step.  A solve that reaches its
+ * iteration cap stops the call with VOS_ERR_NOCONV after that step's update
+ * (the diagnostics say which solve). */
+#define VOS_FREEZE_SOLID 1
+vos_status vos_step(vos_sim *sim, double dt, int nsteps, int flags, vos_diag *last);
+
+/* Diagnostics of the current state without advancing it (iteration counts
+ * and balances are those of the last step). */
+vos_status vos_diagnostics(vos_sim *sim, vos_diag *out);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *vos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOS_H */

@@ -1,0 +1,848 @@
+// vos_api.hip -- host orchestration of the gfx950 Volume-of-Solid step and
+// the C ABI declared in include/vos.h.
+//
+// Everything runs on the caller's stream.  Krylov scalars (alpha, beta, rho,
+// omega, residuals, the convergence flag) live in device memory and are
+// produced by one-block kernels, so a solve is a fixed sequence of launches
+// per iteration with no host round trip; the host reads the flag every
+// `check_every` iterations.  Once the flag is set every remaining kernel of
+// the solve returns immediately, so over-launched iterations change nothing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "vos.h"
+#include "vos_device.h"
+#include "vos_kernels.h"
+#include "vos_mg.h"
+
+using namespace vos;
+
+namespace {
+
+thread_local std::string g_err;
+
+vos_status fail(vos_status st, const std::string &msg)
+{
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(VOS_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+
+struct Plan {
+  size_t off = 0;
+  size_t take(size_t bytes)
+  {
+    size_t o = off;
+    off += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+    return o;
+  }
+};
+
+int grid_blocks(size_t n)
+{
+  size_t b = (n + TPB - 1) / TPB;
+  if (b < 1) b = 1;
+  if (b > (size_t)MAXB) b = MAXB;
+  return (int)b;
+}
+
+struct LevelDims {
+  int n[3];
+  unsigned nc;
+  unsigned nf[3];
+  int fd[3][3];
+};
+
+LevelDims level_dims(int nx, int ny, int nz)
+{
+  LevelDims L;
+  L.n[0] = nx; L.n[1] = ny; L.n[2] = nz;
+  L.nc = (unsigned)nx * ny * nz;
+  for (int d = 0; d < 3; ++d) {
+    for (int e = 0; e < 3; ++e) L.fd[d][e] = L.n[e] + (e == d);
+    L.nf[d] = (unsigned)L.fd[d][0] * L.fd[d][1] * L.fd[d][2];
+  }
+  return L;
+}
+
+// Hierarchy: halve every active dimension while all are even, stop once the
+// level has <= MG_COARSE_MAX cells.
+int mg_hierarchy(const vos_grid &g, LevelDims *out)
+{
+  const int nd = g.nz == 1 ? 2 : 3;
+  int n[3] = {g.nx, g.ny, g.nz};
+  int L = 0;
+  out[L++] = level_dims(n[0], n[1], n[2]);
+  while (L < MG_MAX_LEVELS) {
+    unsigned nc = (unsigned)n[0] * n[1] * n[2];
+    if (nc <= (unsigned)MG_COARSE_MAX) break;
+    bool ok = true;
+    for (int d = 0; d < nd; ++d) ok = ok && (n[d] % 2 == 0) && n[d] >= 2;
+    if (!ok) break;
+    for (int d = 0; d < nd; ++d) n[d] /= 2;
+    out[L++] = level_dims(n[0], n[1], n[2]);
+  }
+  return L;
+}
+
+struct Layout {
+  size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
+  size_t vec[8];
+  size_t part, part_max, scal, ainv;
+  size_t mgT[MG_MAX_LEVELS][3], mgdiag[MG_MAX_LEVELS], mgx[MG_MAX_LEVELS], mgb[MG_MAX_LEVELS], mgt[MG_MAX_LEVELS];
+  int nlev;
+  size_t total;
+};
+
+constexpr int NSC = 8;  // scalar blocks: mom x/y/z, pressure, transport, misc, diag, spare
+
+Layout make_layout(const vos_grid &g, int precision)
+{
+  Layout Lo;
+  Plan P;
+  LevelDims D0 = level_dims(g.nx, g.ny, g.nz);
+  const size_t nc = D0.nc;
+  const size_t dbl = sizeof(double);
+  Lo.eps = P.take(nc * dbl);
+  Lo.p = P.take(nc * dbl);
+  Lo.c = P.take(nc * dbl);
+  Lo.pn = P.take(nc * dbl);
+  Lo.cold = P.take(nc * dbl);
+  Lo.rbar = P.take(nc * dbl);
+  Lo.gmag = P.take(nc * dbl);
+  for (int d = 0; d < 3; ++d) Lo.nrm[d] = P.take(nc * dbl);
+  Lo.pdiag = P.take(nc * dbl);
+  Lo.off = P.take(6 * nc * dbl);
+  size_t nmax = nc;
+  for (int d = 0; d < 3; ++d) {
+    nmax = std::max(nmax, (size_t)D0.nf[d]);
+    Lo.u[d] = P.take(D0.nf[d] * dbl);
+    Lo.ustar[d] = P.take(D0.nf[d] * dbl);
+    Lo.dmom[d] = P.take(D0.nf[d] * dbl);
+    Lo.af[d] = P.take(D0.nf[d] * dbl);
+    Lo.T[d] = P.take(D0.nf[d] * dbl);
+    Lo.w[d] = P.take(D0.nf[d] * dbl);
+  }
+  for (int k = 0; k < 8; ++k) Lo.vec[k] = P.take(nmax * dbl);
+  Lo.part = P.take((size_t)NSLOT * MAXB * dbl);
+  Lo.part_max = P.take((size_t)MAXB * dbl);
+  Lo.scal = P.take((size_t)NSC * S_COUNT * 2 * dbl);
+  Lo.ainv = P.take((size_t)MG_COARSE_MAX * MG_COARSE_MAX * dbl);
+  LevelDims lv[MG_MAX_LEVELS];
+  Lo.nlev = mg_hierarchy(g, lv);
+  const size_t rs = precision == VOS_MIXED ? sizeof(float) : sizeof(double);
+  for (int l = 0; l < Lo.nlev; ++l) {
+    for (int d = 0; d < 3; ++d) Lo.mgT[l][d] = (l == 0 && precision != VOS_MIXED) ? 0 : P.take(lv[l].nf[d] * rs);
+    Lo.mgdiag[l] = P.take(lv[l].nc * rs);
+    Lo.mgx[l] = P.take(lv[l].nc * rs);
+    Lo.mgb[l] = P.take(lv[l].nc * rs);
+    Lo.mgt[l] = P.take(lv[l].nc * rs);
+  }
+  Lo.total = P.off;
+  return Lo;
+}
+
+}  // namespace
+
+struct vos_sim {
+  vos_grid grid;
+  vos_params prm;
+  vos_opts opt;
+  hipStream_t stream;
+  Dev g;
+  Phys P;
+  Layout lo;
+  char *ws;
+  double *eps, *p, *c, *pn, *cold, *rbar, *gmag, *nrm[3], *pdiag, *off;
+  double *u[3], *ustar[3], *dmom[3], *af[3], *T[3], *w[3];
+  double *vec[8];
+  double *part, *part_max, *scal, *ainv;
+  int nlev;
+  MgLevel<float> mgf[MG_MAX_LEVELS];
+  MgLevel<double> mgd[MG_MAX_LEVELS];
+  double *host;       // pinned scalar read-back buffer
+  hipEvent_t ev[7];
+  bool have_geometry;
+  vos_diag last;
+};
+
+namespace {
+
+double *sc_block(vos_sim *s, int k) { return s->scal + (size_t)k * S_COUNT * 2; }
+enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6 };
+
+template <typename R>
+void fill_levels(vos_sim *s, MgLevel<R> *lv)
+{
+  const vos_grid &g = s->grid;
+  LevelDims ld[MG_MAX_LEVELS];
+  int nl = mg_hierarchy(g, ld);
+  for (int l = 0; l < nl; ++l) {
+    MgLevel<R> &L = lv[l];
+    for (int d = 0; d < 3; ++d) {
+      L.n[d] = ld[l].n[d];
+      L.nf[d] = ld[l].nf[d];
+      for (int e = 0; e < 3; ++e) L.fd[d][e] = ld[l].fd[d][e];
+      if (l == 0 && s->opt.precision != VOS_MIXED)
+        L.T[d] = (R *)s->T[d];
+      else
+        L.T[d] = (R *)(s->ws + s->lo.mgT[l][d]);
+    }
+    L.nc = ld[l].nc;
+    L.diag = (R *)(s->ws + s->lo.mgdiag[l]);
+    L.x = (R *)(s->ws + s->lo.mgx[l]);
+    L.b = (R *)(s->ws + s->lo.mgb[l]);
+    L.t = (R *)(s->ws + s->lo.mgt[l]);
+  }
+}
+
+vos_status check_grid(const vos_grid *g)
+{
+  if (!g) return fail(VOS_ERR_ARG, "grid is NULL");
+  if (g->nx < 2 || g->ny < 1 || g->nz < 1 || !(g->dx > 0.0))
+    return fail(VOS_ERR_ARG, "grid needs nx >= 2, ny >= 1, nz >= 1, dx > 0");
+  if ((double)g->nx * g->ny * g->nz > 2.0e9 || (double)(g->nx + 1) * g->ny * g->nz > 2.0e9)
+    return fail(VOS_ERR_ARG, "grid too large for 32-bit indexing");
+  return VOS_OK;
+}
+
+vos_status check_opts(const vos_opts *o)
+{
+  if (!o) return fail(VOS_ERR_ARG, "opts is NULL");
+  if (!(o->rtol_u > 0) || !(o->rtol_p > 0) || !(o->rtol_c > 0)) return fail(VOS_ERR_ARG, "tolerances must be > 0");
+  if (o->maxit_u < 1 || o->maxit_p < 1 || o->maxit_c < 1) return fail(VOS_ERR_ARG, "maxit must be >= 1");
+  if (o->precision != VOS_FP64 && o->precision != VOS_MIXED) return fail(VOS_ERR_ARG, "unknown precision");
+  if (o->mg_nu < 1 || o->mg_nu > 8) return fail(VOS_ERR_ARG, "mg_nu must be in [1, 8]");
+  if (o->check_every < 1) return fail(VOS_ERR_ARG, "check_every must be >= 1");
+  return VOS_OK;
+}
+
+vos_status check_params(const vos_params *p)
+{
+  if (!p) return fail(VOS_ERR_ARG, "params is NULL");
+  if (!(p->mu > 0) || !(p->rho > 0) || !(p->k0 > 0) || !(p->D >= 0) || !(p->kc >= 0) || !(p->Vm >= 0) ||
+      !(p->zeta >= 0) || !(p->eps_min > 0 && p->eps_min < 1) || !(p->u_in >= 0))
+    return fail(VOS_ERR_ARG, "physical parameters out of range");
+  if (p->model < 0 || p->model > 2) return fail(VOS_ERR_ARG, "unknown model");
+  return VOS_OK;
+}
+
+// Host read of n doubles from device memory (synchronises the stream).
+vos_status read_back(vos_sim *s, const double *dev, size_t n)
+{
+  HIP_TRY(hipMemcpyAsync(s->host, dev, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return VOS_OK;
+}
+
+// Run iterations until the device flag says converged or maxit is reached.
+template <typename F>
+vos_status krylov_loop(vos_sim *s, double *sc, int maxit, F &&iter, int *its, double *res2, double *tol2, bool *conv)
+{
+  HIP_TRY(hipGetLastError());
+  int launched = 0;
+  vos_status st = read_back(s, sc, S_COUNT);
+  if (st) return st;
+  bool done = s->host[S_CONV] != 0.0;
+  while (!done && launched < maxit) {
+    const int k = std::min(s->opt.check_every, maxit - launched);
+    for (int i = 0; i < k; ++i) iter();
+    launched += k;
+    HIP_TRY(hipGetLastError());
+    st = read_back(s, sc, S_COUNT);
+    if (st) return st;
+    done = s->host[S_CONV] != 0.0;
+  }
+  *its = (int)s->host[S_ITS];
+  *res2 = s->host[S_RES2];
+  *tol2 = s->host[S_TOL2];
+  *conv = (s->host[S_RES2] <= s->host[S_TOL2]) || (s->host[S_RES2] == 0.0);
+  return VOS_OK;
+}
+
+// ---------------------------------------------------------------- stage S1
+
+void launch_coefficients(vos_sim *s, double dt)
+{
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  k_face_coef<0><<<grid_blocks(g.nf[0]), TPB, 0, st>>>(g, s->P, dt, s->eps, s->dmom[0], s->af[0], s->T[0]);
+  k_face_coef<1><<<grid_blocks(g.nf[1]), TPB, 0, st>>>(g, s->P, dt, s->eps, s->dmom[1], s->af[1], s->T[1]);
+  if (g.nd == 3)
+    k_face_coef<2><<<grid_blocks(g.nf[2]), TPB, 0, st>>>(g, s->P, dt, s->eps, s->dmom[2], s->af[2], s->T[2]);
+  const int nb = grid_blocks(g.nc);
+  k_cell_grad<<<nb, TPB, 0, st>>>(g, s->eps, s->gmag, s->nrm[0], s->nrm[1], s->nrm[2], s->part);
+  k_lambda<<<1, TPB, 0, st>>>(s->part, nb, s->P.model, sc_block(s, SC_MISC));
+  k_face_w<0><<<grid_blocks(g.nf[0]), TPB, 0, st>>>(g, s->P.kc, s->nrm[0], s->w[0]);
+  k_face_w<1><<<grid_blocks(g.nf[1]), TPB, 0, st>>>(g, s->P.kc, s->nrm[1], s->w[1]);
+  if (g.nd == 3) k_face_w<2><<<grid_blocks(g.nf[2]), TPB, 0, st>>>(g, s->P.kc, s->nrm[2], s->w[2]);
+  k_pdiag<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pdiag);
+}
+
+// ---------------------------------------------------------------- stage S2
+
+template <int D>
+vos_status solve_momentum(vos_sim *s, double dt, int *its, double *res)
+{
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  const unsigned n = g.nf[D];
+  const int nb = grid_blocks(n);
+  double *b = s->vec[0], *r = s->vec[1], *z = s->vec[2], *pv = s->vec[3], *q = s->vec[4];
+  double *x = s->ustar[D];
+  double *sc = sc_block(s, SC_MOM + D);
+  const double cvis = s->P.mu / (g.dx * g.dx);
+  const double rt2 = s->opt.rtol_u * s->opt.rtol_u;
+  k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x);
+  // q = A x with a dummy (unconverged) flag: the misc block's S_CONV is always 0
+  double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
+  k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, s->part, zero_flag);
+  k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 1, s->part);
+  k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
+  auto iter = [&]() {
+    k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, s->part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
+    k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 1, s->part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
+    k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
+  };
+  double res2, tol2;
+  bool conv;
+  vos_status stt = krylov_loop(s, sc, s->opt.maxit_u, iter, its, &res2, &tol2, &conv);
+  if (stt) return stt;
+  k_mom_fix<D><<<nb, TPB, 0, st>>>(g, s->P.u_in, x);
+  const double bn2 = s->host[S_BN2];
+  *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
+  if (!conv) return fail(VOS_ERR_NOCONV, "momentum predictor did not converge");
+  return VOS_OK;
+}
+
+// ---------------------------------------------------------------- stage S3
+
+template <typename R>
+void mg_setup(vos_sim *s, MgLevel<R> *lv)
+{
+  hipStream_t st = s->stream;
+  const int nd = s->g.nd;
+  if (s->opt.precision == VOS_MIXED)
+    for (int d = 0; d < nd; ++d)
+      k_mg_cast_faces<R><<<grid_blocks(lv[0].nf[d]), TPB, 0, st>>>(lv[0].nf[d], s->T[d], lv[0].T[d]);
+  for (int l = 0; l + 1 < s->nlev; ++l) {
+    k_mg_coarsen<R, 0><<<grid_blocks(lv[l + 1].nf[0]), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
+    k_mg_coarsen<R, 1><<<grid_blocks(lv[l + 1].nf[1]), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
+    if (nd == 3) k_mg_coarsen<R, 2><<<grid_blocks(lv[l + 1].nf[2]), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
+  }
+  for (int l = 0; l < s->nlev; ++l) k_mg_diag<R><<<grid_blocks(lv[l].nc), TPB, 0, st>>>(lv[l], nd);
+  const MgLevel<R> &C = lv[s->nlev - 1];
+  if (C.nc <= (unsigned)MG_COARSE_MAX) k_mg_coarse_inverse<R><<<1, TPB, 0, st>>>(C, nd, s->ainv);
+}
+
+// Coarsest-level solve: the dense inverse when the level has <= MG_COARSE_MAX
+// cells, otherwise 64 damped-Jacobi sweeps from zero.
+template <typename R>
+void mg_coarsest(vos_sim *s, MgLevel<R> &C, R om, const double *sc)
+{
+  hipStream_t st = s->stream;
+  const int nd = s->g.nd;
+  if (C.nc <= (unsigned)MG_COARSE_MAX) {
+    k_mg_coarse_solve<R><<<1, TPB, 0, st>>>(C, s->ainv, sc);
+    return;
+  }
+  const int nb = grid_blocks(C.nc);
+  k_mg_first<R><<<nb, TPB, 0, st>>>(C, om, sc);
+  for (int k = 1; k < 64; ++k) {
+    k_mg_jacobi<R, false><<<nb, TPB, 0, st>>>(C, nd, C.x, C.t, om, nullptr, sc);
+    std::swap(C.x, C.t);
+  }
+}
+
+// z = V-cycle(r).
+template <typename R>
+void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const double *sc)
+{
+  hipStream_t st = s->stream;
+  const int nd = s->g.nd;
+  const R om = (R)(nd == 3 ? 6.0 / 7.0 : 0.8);
+  const int nu = s->opt.mg_nu;
+  const int L = s->nlev;
+  if (L == 1) {
+    // one level only: the coarsest solve is the whole preconditioner
+    MgLevel<R> &F = lv[0];
+    const int nb = grid_blocks(F.nc);
+    k_mg_enter<R><<<nb, TPB, 0, st>>>(F, r, om, sc);
+    mg_coarsest<R>(s, F, om, sc);
+    k_mg_jacobi<R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, (R)0, z, sc);
+    std::swap(F.x, F.t);
+    return;
+  }
+  for (int l = 0; l < L - 1; ++l) {
+    MgLevel<R> &F = lv[l];
+    const int nb = grid_blocks(F.nc);
+    if (l == 0) k_mg_enter<R><<<nb, TPB, 0, st>>>(F, r, om, sc);
+    else k_mg_first<R><<<nb, TPB, 0, st>>>(F, om, sc);
+    for (int k = 1; k < nu; ++k) {
+      k_mg_jacobi<R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
+      std::swap(F.x, F.t);
+    }
+    k_mg_restrict<R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(F, lv[l + 1], nd, sc);
+  }
+  mg_coarsest<R>(s, lv[L - 1], om, sc);
+  for (int l = L - 2; l >= 0; --l) {
+    MgLevel<R> &F = lv[l];
+    const int nb = grid_blocks(F.nc);
+    k_mg_prolong<R><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, sc);
+    for (int k = 0; k < nu; ++k) {
+      const bool last = (l == 0 && k == nu - 1);
+      if (last) k_mg_jacobi<R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, z, sc);
+      else k_mg_jacobi<R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
+      std::swap(F.x, F.t);
+    }
+  }
+}
+
+template <typename R>
+vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
+{
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  const unsigned n = g.nc;
+  const int nb = grid_blocks(n);
+  double *b = s->vec[0], *r = s->vec[1], *z = s->vec[2], *pv = s->vec[3], *q = s->vec[4];
+  double *sc = sc_block(s, SC_P);
+  double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
+  const double rt2 = s->opt.rtol_p * s->opt.rtol_p;
+  mg_setup<R>(s, lv);
+  HIP_TRY(hipMemcpyAsync(s->pn, s->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b);
+  k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
+  k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, r, z, pv, 0, s->part);
+  k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
+  mg_vcycle<R>(s, lv, r, z, sc);
+  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
+  k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
+  HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  auto iter = [&]() {
+    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], pv, q, s->part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
+    k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->pdiag, s->p, r, z, 0, s->part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
+    mg_vcycle<R>(s, lv, r, z, sc);
+    k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
+    k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
+  };
+  double res2, tol2;
+  bool conv;
+  vos_status stt = krylov_loop(s, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv);
+  if (stt) return stt;
+  const double bn2 = s->host[S_BN2];
+  *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
+  if (!conv) return fail(VOS_ERR_NOCONV, "pressure solve did not converge");
+  return VOS_OK;
+}
+
+vos_status solve_pressure(vos_sim *s, int *its, double *res)
+{
+  if (s->opt.precision == VOS_MIXED) return solve_pressure_t<float>(s, s->mgf, its, res);
+  return solve_pressure_t<double>(s, s->mgd, its, res);
+}
+
+// ---------------------------------------------------------------- stage S4
+
+void launch_correct(vos_sim *s)
+{
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  k_correct<0><<<grid_blocks(g.nf[0]), TPB, 0, st>>>(g, s->ustar[0], s->af[0], s->p, s->pn, s->u[0]);
+  k_correct<1><<<grid_blocks(g.nf[1]), TPB, 0, st>>>(g, s->ustar[1], s->af[1], s->p, s->pn, s->u[1]);
+  if (g.nd == 3) k_correct<2><<<grid_blocks(g.nf[2]), TPB, 0, st>>>(g, s->ustar[2], s->af[2], s->p, s->pn, s->u[2]);
+}
+
+// ---------------------------------------------------------------- stage S5
+
+vos_status solve_transport(vos_sim *s, int *its, double *res)
+{
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  const unsigned n = g.nc;
+  const int nb = grid_blocks(n);
+  double *b = s->vec[0], *r = s->vec[1], *rh = s->vec[2], *pv = s->vec[3], *v = s->vec[4], *sv = s->vec[5],
+         *t = s->vec[6], *y = s->vec[7];
+  double *sc = sc_block(s, SC_C);
+  double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
+  const double rt2 = s->opt.rtol_c * s->opt.rtol_c;
+  HIP_TRY(hipMemcpyAsync(s->cold, s->c, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
+                                     s->gmag, sc_block(s, SC_MISC), s->off, b, y);
+  k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
+  k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
+  k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
+  auto iter = [&]() {
+    k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, sc);
+    k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, pv, v, rh, s->part, sc);
+    k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
+    k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, s->part, sc);
+    k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
+    k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sv, t, sv, s->part, sc);
+    k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
+    k_bi_xr<<<nb, TPB, 0, st>>>(n, pv, sv, t, rh, s->c, r, s->part, sc);
+    k_bi_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
+  };
+  double res2, tol2;
+  bool conv;
+  vos_status stt = krylov_loop(s, sc, s->opt.maxit_c, iter, its, &res2, &tol2, &conv);
+  if (stt) return stt;
+  const double bn2 = s->host[S_BN2];
+  *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
+  if (!conv) return fail(VOS_ERR_NOCONV, "transport solve did not converge");
+  return VOS_OK;
+}
+
+// ---------------------------------------------------------------- stages S6-S7
+
+// Sum the reaction / update partials into the diag scalar block:
+// [0] sink sum, [1] rate sum, [2..11] k_eps_update slots 0..9, [12] max |d eps|.
+__global__ void k_diag_final(const double *__restrict__ prt, const double *__restrict__ pupd,
+                             const double *__restrict__ pmax, int nb, double *__restrict__ out)
+{
+  double v[13];
+  v[0] = sum_partials(prt, 0, nb);
+  v[1] = sum_partials(prt, 1, nb);
+  for (int q = 0; q < 10; ++q) v[2 + q] = sum_partials(pupd, q, nb);
+  v[12] = max_partials(pmax, 0, nb);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 13; ++q) out[q] = v[q];
+}
+
+void launch_reaction(vos_sim *s, double dt, int freeze)
+{
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  const int nb = grid_blocks(g.nc);
+  double *prt = s->part + 12 * MAXB;    // 2 slots, kept apart from the update's 10
+  k_react<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->c, s->cold, s->w[0], s->w[1], s->w[2], s->gmag,
+                              sc_block(s, SC_MISC), s->rbar, prt);
+  k_eps_update<<<nb, TPB, 0, st>>>(g, s->P, dt, freeze, s->eps, s->rbar, s->c, s->p, s->u[0], s->gmag, s->part,
+                                   s->part_max);
+  k_diag_final<<<1, TPB, 0, st>>>(prt, s->part, s->part_max, nb, sc_block(s, SC_DIAG));
+}
+
+vos_status fill_diag(vos_sim *s, double dt, vos_diag *dg)
+{
+  vos_status st = read_back(s, sc_block(s, SC_MISC), 2);
+  if (st) return st;
+  const double lam = s->host[0];
+  st = read_back(s, sc_block(s, SC_DIAG), 13);
+  if (st) return st;
+  const double *h = s->host;
+  const Dev &g = s->g;
+  const double V = g.V;
+  const double sink = h[0], rate = h[1];
+  dg->lambda = lam;
+  dg->clipped_volume = h[2];
+  const double dvol = h[3];
+  dg->solid_volume = h[4];
+  dg->porosity = h[5] / (double)g.nc;
+  dg->acid_in = h[6];
+  dg->acid_out = h[7];
+  const double nin = (double)g.n[1] * g.n[2];
+  dg->dP = h[8] / nin - s->P.p_out;
+  dg->K = dg->dP != 0.0 ? s->P.mu * s->P.u_in * (g.n[0] - 0.5) * g.dx / dg->dP : 0.0;
+  const double cg = h[9], ec = h[10], area = h[11];
+  dg->surface_area = area;
+  const double a = area / (g.nc * V);
+  dg->alpha = (a > 0.0 && ec > 0.0) ? cg / (a * ec) : 0.0;
+  dg->max_deps = h[12];
+  dg->acid_consumed = s->P.zeta * sink;
+  dg->solid_rate = rate;
+  dg->acid_balance_rel = dg->acid_in != 0.0 ? (dg->acid_in - dg->acid_out - dg->acid_consumed) / dg->acid_in : 0.0;
+  const double ref = dt * s->P.Vm * std::fabs(rate);
+  dg->solid_balance_rel = ref > 0.0 ? (dvol - dt * s->P.Vm * rate + dg->clipped_volume) / ref : 0.0;
+  return VOS_OK;
+}
+
+vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
+{
+  hipStream_t st = s->stream;
+  std::memset(dg, 0, sizeof(*dg));
+  vos_status rc = VOS_OK, r2;
+  HIP_TRY(hipEventRecord(s->ev[0], st));
+  launch_coefficients(s, dt);
+  HIP_TRY(hipEventRecord(s->ev[1], st));
+  r2 = solve_momentum<0>(s, dt, &dg->it_u[0], &dg->res_u[0]);
+  if (r2 == VOS_ERR_DEVICE) return r2;
+  if (r2 && !rc) rc = r2;
+  r2 = solve_momentum<1>(s, dt, &dg->it_u[1], &dg->res_u[1]);
+  if (r2 == VOS_ERR_DEVICE) return r2;
+  if (r2 && !rc) rc = r2;
+  if (s->g.nd == 3) {
+    r2 = solve_momentum<2>(s, dt, &dg->it_u[2], &dg->res_u[2]);
+    if (r2 == VOS_ERR_DEVICE) return r2;
+    if (r2 && !rc) rc = r2;
+  }
+  HIP_TRY(hipEventRecord(s->ev[2], st));
+  r2 = solve_pressure(s, &dg->it_p, &dg->res_p);
+  if (r2 == VOS_ERR_DEVICE) return r2;
+  if (r2 && !rc) rc = r2;
+  HIP_TRY(hipEventRecord(s->ev[3], st));
+  launch_correct(s);
+  HIP_TRY(hipEventRecord(s->ev[4], st));
+  r2 = solve_transport(s, &dg->it_c, &dg->res_c);
+  if (r2 == VOS_ERR_DEVICE) return r2;
+  if (r2 && !rc) rc = r2;
+  HIP_TRY(hipEventRecord(s->ev[5], st));
+  launch_reaction(s, dt, flags & VOS_FREEZE_SOLID);
+  HIP_TRY(hipEventRecord(s->ev[6], st));
+  HIP_TRY(hipGetLastError());
+  r2 = fill_diag(s, dt, dg);
+  if (r2) return r2;
+  for (int k = 0; k < 6; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
+    dg->t_ms[k] = ms;
+  }
+  if (rc) {
+    std::string m = g_err;
+    return fail(rc, m);
+  }
+  return VOS_OK;
+}
+
+double *field_ptr(vos_sim *s, int field, size_t *n, bool *writable)
+{
+  const Dev &g = s->g;
+  *writable = true;
+  switch (field) {
+    case VOS_FIELD_EPS: *n = g.nc; return s->eps;
+    case VOS_FIELD_UX: *n = g.nf[0]; return s->u[0];
+    case VOS_FIELD_UY: *n = g.nf[1]; return s->u[1];
+    case VOS_FIELD_UZ: *n = g.nf[2]; return s->u[2];
+    case VOS_FIELD_P: *n = g.nc; return s->p;
+    case VOS_FIELD_C: *n = g.nc; return s->c;
+    case VOS_FIELD_USTAR_X: *writable = false; *n = g.nf[0]; return s->ustar[0];
+    case VOS_FIELD_USTAR_Y: *writable = false; *n = g.nf[1]; return s->ustar[1];
+    case VOS_FIELD_USTAR_Z: *writable = false; *n = g.nf[2]; return s->ustar[2];
+    case VOS_FIELD_RBAR: *writable = false; *n = g.nc; return s->rbar;
+    case VOS_FIELD_GMAG: *writable = false; *n = g.nc; return s->gmag;
+    default: return nullptr;
+  }
+}
+
+__global__ void k_set_eps(unsigned n, const double *__restrict__ es, double eps_min, double *__restrict__ eps,
+                          int *__restrict__ bad)
+{
+  for (unsigned i = gtid(); i < n; i += gstride()) {
+    const double v = es[i];
+    if (!(v >= 0.0 && v <= 1.0)) bad[0] = 1;
+    double e = 1.0 - v;
+    e = e < eps_min ? eps_min : (e > 1.0 ? 1.0 : e);
+    eps[i] = e;
+  }
+}
+
+__global__ void k_fill(unsigned n, double v, double *__restrict__ a)
+{
+  for (unsigned i = gtid(); i < n; i += gstride()) a[i] = v;
+}
+
+// Inlet faces (i = 0) of the x grid get u_in.
+__global__ void k_inlet(Dev g, double u_in, double *__restrict__ ux)
+{
+  const unsigned n = (unsigned)g.n[1] * g.n[2];
+  for (unsigned t = gtid(); t < n; t += gstride()) ux[t * (unsigned)g.fd[0][0]] = u_in;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char *vos_last_error(void) { return g_err.c_str(); }
+
+vos_status vos_workspace_bytes(const vos_grid *grid, const vos_opts *opts, size_t *bytes)
+{
+  vos_status st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_opts(opts))) return st;
+  if (!bytes) return fail(VOS_ERR_ARG, "bytes is NULL");
+  *bytes = make_layout(*grid, opts->precision).total;
+  return VOS_OK;
+}
+
+vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_opts *opts, void *workspace,
+                      size_t workspace_bytes, void *hip_stream, vos_sim **out)
+{
+  vos_status st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_params(params))) return st;
+  if ((st = check_opts(opts))) return st;
+  if (!out) return fail(VOS_ERR_ARG, "out is NULL");
+  if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return fail(VOS_ERR_ARG, "workspace must be 256-byte aligned");
+  Layout lo = make_layout(*grid, opts->precision);
+  if (workspace_bytes < lo.total) return fail(VOS_ERR_OOM, "workspace smaller than vos_workspace_bytes()");
+  vos_sim *s = new (std::nothrow) vos_sim();
+  if (!s) return fail(VOS_ERR_OOM, "host allocation failed");
+  s->grid = *grid;
+  s->prm = *params;
+  s->opt = *opts;
+  s->stream = (hipStream_t)hip_stream;
+  s->lo = lo;
+  s->ws = (char *)workspace;
+  Dev &g = s->g;
+  g.n[0] = grid->nx; g.n[1] = grid->ny; g.n[2] = grid->nz;
+  g.nd = grid->nz == 1 ? 2 : 3;
+  for (int d = 0; d < 3; ++d) {
+    for (int e = 0; e < 3; ++e) g.fd[d][e] = g.n[e] + (e == d);
+    g.nf[d] = (unsigned)g.fd[d][0] * g.fd[d][1] * g.fd[d][2];
+  }
+  g.nc = (unsigned)grid->nx * grid->ny * grid->nz;
+  g.dx = grid->dx; g.S = grid->dx * grid->dx; g.V = g.S * grid->dx;
+  Phys &P = s->P;
+  P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
+  P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
+  P.u_in = params->u_in; P.p_out = params->p_out; P.model = params->model;
+  char *w = s->ws;
+  auto D = [&](size_t o) { return (double *)(w + o); };
+  s->eps = D(lo.eps); s->p = D(lo.p); s->c = D(lo.c); s->pn = D(lo.pn); s->cold = D(lo.cold);
+  s->rbar = D(lo.rbar); s->gmag = D(lo.gmag); s->pdiag = D(lo.pdiag); s->off = D(lo.off);
+  for (int d = 0; d < 3; ++d) {
+    s->nrm[d] = D(lo.nrm[d]); s->u[d] = D(lo.u[d]); s->ustar[d] = D(lo.ustar[d]); s->dmom[d] = D(lo.dmom[d]);
+    s->af[d] = D(lo.af[d]); s->T[d] = D(lo.T[d]); s->w[d] = D(lo.w[d]);
+  }
+  for (int k = 0; k < 8; ++k) s->vec[k] = D(lo.vec[k]);
+  s->part = D(lo.part); s->part_max = D(lo.part_max); s->scal = D(lo.scal); s->ainv = D(lo.ainv);
+  s->nlev = lo.nlev;
+  fill_levels<float>(s, s->mgf);
+  fill_levels<double>(s, s->mgd);
+  s->have_geometry = false;
+  std::memset(&s->last, 0, sizeof(s->last));
+  hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
+  for (int k = 0; k < 7; ++k) {
+    e = hipEventCreate(&s->ev[k]);
+    if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, "hipEventCreate failed"); }
+  }
+  // initial state: fluid at rest, p = p_out, c = 0, eps = 1
+  hipStream_t stq = s->stream;
+  HIP_TRY(hipMemsetAsync(s->ws, 0, lo.total, stq));
+  k_fill<<<grid_blocks(g.nc), TPB, 0, stq>>>(g.nc, 1.0, s->eps);
+  k_fill<<<grid_blocks(g.nc), TPB, 0, stq>>>(g.nc, P.p_out, s->p);
+  k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, stq>>>(g, P.u_in, s->u[0]);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(stq));
+  *out = s;
+  return VOS_OK;
+}
+
+vos_status vos_destroy(vos_sim *s)
+{
+  if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
+  (void)hipStreamSynchronize(s->stream);
+  for (int k = 0; k < 7; ++k) (void)hipEventDestroy(s->ev[k]);
+  (void)hipHostFree(s->host);
+  delete s;
+  return VOS_OK;
+}
+
+vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device)
+{
+  if (!s || !eps_s) return fail(VOS_ERR_ARG, "NULL argument");
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  double *src = s->vec[0];
+  HIP_TRY(hipMemcpyAsync(src, eps_s, g.nc * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  int *bad = (int *)(s->vec[1]);
+  HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), st));
+  k_set_eps<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, src, s->P.eps_min, s->eps, bad);
+  k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, s->P.u_in, s->u[0]);
+  HIP_TRY(hipGetLastError());
+  int hbad = 0;
+  HIP_TRY(hipMemcpyAsync(s->host, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memcpy(&hbad, s->host, sizeof(int));
+  if (hbad) return fail(VOS_ERR_ARG, "solid fraction outside [0, 1]");
+  s->have_geometry = true;
+  return VOS_OK;
+}
+
+vos_status vos_set_field(vos_sim *s, int field, const double *src, int on_device)
+{
+  if (!s || !src) return fail(VOS_ERR_ARG, "NULL argument");
+  size_t n;
+  bool wr;
+  double *d = field_ptr(s, field, &n, &wr);
+  if (!d) return fail(VOS_ERR_ARG, "unknown field");
+  if (!wr) return fail(VOS_ERR_ARG, "field is read-only");
+  HIP_TRY(hipMemcpyAsync(d, src, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (field == VOS_FIELD_EPS) s->have_geometry = true;
+  return VOS_OK;
+}
+
+vos_status vos_get_field(vos_sim *s, int field, double *dst, int on_device)
+{
+  if (!s || !dst) return fail(VOS_ERR_ARG, "NULL argument");
+  size_t n;
+  bool wr;
+  double *d = field_ptr(s, field, &n, &wr);
+  if (!d) return fail(VOS_ERR_ARG, "unknown field");
+  HIP_TRY(hipMemcpyAsync(dst, d, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return VOS_OK;
+}
+
+vos_status vos_field_ptr(vos_sim *s, int field, double **dev_ptr)
+{
+  if (!s || !dev_ptr) return fail(VOS_ERR_ARG, "NULL argument");
+  size_t n;
+  bool wr;
+  double *d = field_ptr(s, field, &n, &wr);
+  if (!d) return fail(VOS_ERR_ARG, "unknown field");
+  *dev_ptr = d;
+  return VOS_OK;
+}
+
+vos_status vos_step(vos_sim *s, double dt, int nsteps, int flags, vos_diag *last)
+{
+  if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
+  if (!(dt > 0.0) || nsteps < 0) return fail(VOS_ERR_ARG, "dt must be > 0 and nsteps >= 0");
+  if (!s->have_geometry) return fail(VOS_ERR_STATE, "set the solid fraction before stepping");
+  vos_diag dg;
+  std::memset(&dg, 0, sizeof(dg));
+  for (int k = 0; k < nsteps; ++k) {
+    vos_status st = one_step(s, dt, flags, &dg);
+    s->last = dg;
+    if (st) {
+      if (last) *last = dg;
+      return st;
+    }
+  }
+  if (last) *last = s->last;
+  return VOS_OK;
+}
+
+vos_status vos_diagnostics(vos_sim *s, vos_diag *out)
+{
+  if (!s || !out) return fail(VOS_ERR_ARG, "NULL argument");
+  *out = s->last;
+  return VOS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// vos_device.h -- device-side helpers shared by the gfx950 kernels of the VoS step.
+//
+// Layout: cells x fastest, id = i + nx*(j + ny*k).  Face grid of direction d
+// has dims n + e_d; face (d, x) lies between cells x - e_d and x.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace vos {
+
+constexpr int TPB = 256;         // threads per block of every sweep (4 wave64s)
+constexpr int MAXB = 1024;       // blocks of a grid-stride sweep == partial-sum slots per quantity
+constexpr int NSLOT = 16;        // partial-sum quantities one sweep may produce
+
+struct Dev {
+  int n[3];
+  int nd;                        // 2 (nz == 1) or 3
+  int fd[3][3];                  // face-grid dims
+  unsigned nc;
+  unsigned nf[3];
+  double dx, S, V;
+};
+
+struct Phys {
+  double mu, rho, D, k0, kc, Vm, zeta, c_in, eps_min, u_in, p_out;
+  int model;
+};
+
+__device__ __forceinline__ unsigned gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ unsigned gstride() { return gridDim.x * blockDim.x; }
+
+__device__ __forceinline__ void unflat(const int dims[3], unsigned id, int x[3])
+{
+  unsigned t = id / (unsigned)dims[0];
+  x[0] = (int)(id - t * (unsigned)dims[0]);
+  unsigned k = t / (unsigned)dims[1];
+  x[1] = (int)(t - k * (unsigned)dims[1]);
+  x[2] = (int)k;
+}
+
+__device__ __forceinline__ unsigned cidx(const Dev &g, int i, int j, int k)
+{
+  return (unsigned)i + (unsigned)g.n[0] * ((unsigned)j + (unsigned)g.n[1] * (unsigned)k);
+}
+
+__device__ __forceinline__ unsigned fidx(const Dev &g, int d, int i, int j, int k)
+{
+  return (unsigned)i + (unsigned)g.fd[d][0] * ((unsigned)j + (unsigned)g.fd[d][1] * (unsigned)k);
+}
+
+// Stride of a unit step along direction e in a grid of dims.
+__device__ __forceinline__ unsigned dstride(const int dims[3], int e)
+{
+  return e == 0 ? 1u : (e == 1 ? (unsigned)dims[0] : (unsigned)dims[0] * (unsigned)dims[1]);
+}
+
+// Sum over a block of TPB threads (wave64 shuffles, then LDS); result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += lds[i];
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double *lds)
+{
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmax(s, lds[i]);
+  return s;
+}
+
+// Write NQ block partial sums: part[q * MAXB + blockIdx.x].
+template <int NQ>
+__device__ __forceinline__ void write_partials(const double (&v)[NQ], double *part)
+{
+  __shared__ double lds[NQ][TPB / 64];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = block_sum(v[q], lds[q]);
+    if (threadIdx.x == 0) part[q * MAXB + blockIdx.x] = s;
+  }
+}
+
+// Fixed-order sum of nb partials of quantity q by one block; valid in thread 0.
+__device__ __forceinline__ double sum_partials(const double *part, int q, int nb)
+{
+  __shared__ double lds[TPB / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[q * MAXB + b];
+  return block_sum(s, lds);
+}
+
+__device__ __forceinline__ double max_partials(const double *part, int q, int nb)
+{
+  __shared__ double lds[TPB / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s = fmax(s, part[q * MAXB + b]);
+  return block_max(s, lds);
+}
+
+// van Leer (1974) correction to the upwind face value: with a = phi_C - phi_U and
+// b = phi_D - phi_C the face value is phi_C + a b / (a + b) when a b > 0, else phi_C.
+__device__ __forceinline__ double vanleer_corr(double pu, double pc, double pd)
+{
+  const double a = pc - pu, b = pd - pc;
+  return (a * b > 0.0) ? a * b / (a + b) : 0.0;
+}
+
+}  // namespace vos

@@ -1,0 +1,252 @@
+// vos_mg.h -- cell-centred geometric multigrid V-cycle for the pressure
+// equation, templated on the arithmetic of the hierarchy (float: the mixed
+// mode; double: the FP64 mode).  Used as the preconditioner of FP64 flexible
+// CG; it never decides convergence.
+//
+// Level l+1 halves every active dimension of level l.  Coarse transmissibility
+// T_c = 1/2 * sum of the fine transmissibilities crossing the coarse face
+// (parallel faces add, two fine cells in series halve it), which reproduces a
+// rediscretisation on the coarse grid, including the outlet (Dirichlet) faces.
+// Restriction sums the residual of the 2^nd children; prolongation is
+// piecewise constant.  Smoother: damped Jacobi, nu sweeps before and after.
+// The coarsest level (<= 64 cells) is solved with its dense inverse, rebuilt
+// once per time step.
+#pragma once
+#include "vos_device.h"
+#include "vos_kernels.h"
+
+namespace vos {
+
+constexpr int MG_MAX_LEVELS = 16;
+constexpr int MG_COARSE_MAX = 64;
+
+template <typename R>
+struct MgLevel {
+  int n[3];
+  unsigned nc;
+  unsigned nf[3];
+  int fd[3][3];
+  R *T[3];
+  R *diag;
+  R *x, *b, *t;
+};
+
+template <typename R>
+__device__ __forceinline__ R mg_apply_cell(const MgLevel<R> &L, int nd, const R *x, unsigned id, const int c[3])
+{
+  const R xc = x[id];
+  const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
+  const R tw = L.T[0][f0], te = L.T[0][f0 + 1];
+  R v = L.diag[id] * xc;
+  if (c[0] > 0) v -= tw * x[id - 1];
+  if (c[0] < L.n[0] - 1) v -= te * x[id + 1];
+  const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
+  const R ts = L.T[1][f1], tn = L.T[1][f1 + L.fd[1][0]];
+  if (c[1] > 0) v -= ts * x[id - L.n[0]];
+  if (c[1] < L.n[1] - 1) v -= tn * x[id + L.n[0]];
+  if (nd == 3) {
+    const unsigned sz = (unsigned)L.n[0] * L.n[1];
+    const unsigned f2 = (unsigned)c[0] + (unsigned)L.fd[2][0] * ((unsigned)c[1] + (unsigned)L.fd[2][1] * c[2]);
+    const R tb = L.T[2][f2], tt = L.T[2][f2 + sz];
+    if (c[2] > 0) v -= tb * x[id - sz];
+    if (c[2] < L.n[2] - 1) v -= tt * x[id + sz];
+  }
+  (void)tw; (void)te; (void)ts; (void)tn;
+  return v;
+}
+
+// Level-0 transmissibilities in R and the diagonal (sum of face T).
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_cast_faces(unsigned n, const double *__restrict__ src, R *__restrict__ dst)
+{
+  for (unsigned i = gtid(); i < n; i += gstride()) dst[i] = (R)src[i];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_diag(MgLevel<R> L, int nd)
+{
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+    int c[3];
+    unflat(L.n, id, c);
+    const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
+    const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
+    R s = L.T[0][f0] + L.T[0][f0 + 1] + L.T[1][f1] + L.T[1][f1 + L.fd[1][0]];
+    if (nd == 3) {
+      const unsigned f2 = (unsigned)c[0] + (unsigned)L.fd[2][0] * ((unsigned)c[1] + (unsigned)L.fd[2][1] * c[2]);
+      s += L.T[2][f2] + L.T[2][f2 + (unsigned)L.n[0] * L.n[1]];
+    }
+    L.diag[id] = s;
+  }
+}
+
+// Coarse face transmissibilities of direction D from the fine level.
+template <typename R, int D>
+__global__ void __launch_bounds__(TPB) k_mg_coarsen(MgLevel<R> F, MgLevel<R> Cc, int nd)
+{
+  for (unsigned f = gtid(); f < Cc.nf[D]; f += gstride()) {
+    int X[3];
+    unflat(Cc.fd[D], f, X);
+    int x0[3];
+    for (int e = 0; e < 3; ++e) x0[e] = (e < nd) ? 2 * X[e] : 0;
+    R s = 0;
+    const int c1 = (1 < nd && D != 1) ? 2 : 1;
+    const int c2 = (2 < nd && D != 2) ? 2 : 1;
+    const int c0 = (D != 0) ? 2 : 1;
+    for (int a = 0; a < c0; ++a)
+      for (int bq = 0; bq < c1; ++bq)
+        for (int cq = 0; cq < c2; ++cq) {
+          const int i = x0[0] + a, j = x0[1] + bq, k = x0[2] + cq;
+          s += F.T[D][(unsigned)i + (unsigned)F.fd[D][0] * ((unsigned)j + (unsigned)F.fd[D][1] * (unsigned)k)];
+        }
+    Cc.T[D][f] = (R)0.5 * s;
+  }
+}
+
+// Level-0 entry: b = (R) r and the first Jacobi sweep from zero, x = omega b / diag.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_enter(MgLevel<R> L, const double *__restrict__ r, R omega,
+                                                  const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+    const R bb = (R)r[id];
+    L.b[id] = bb;
+    L.x[id] = omega * bb / L.diag[id];
+  }
+}
+
+// First sweep from zero on a coarse level: x = omega b / diag.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_first(MgLevel<R> L, R omega, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) L.x[id] = omega * L.b[id] / L.diag[id];
+}
+
+// One damped-Jacobi sweep xo = x + omega (b - A x) / diag; optionally also
+// writes the FP64 result (the preconditioned residual z).
+template <typename R, bool OUT64>
+__global__ void __launch_bounds__(TPB) k_mg_jacobi(MgLevel<R> L, int nd, const R *__restrict__ x, R *__restrict__ xo,
+                                                   R omega, double *__restrict__ z, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+    int c[3];
+    unflat(L.n, id, c);
+    const R ax = mg_apply_cell(L, nd, x, id, c);
+    const R v = x[id] + omega * (L.b[id] - ax) / L.diag[id];
+    xo[id] = v;
+    if (OUT64) z[id] = (double)v;
+  }
+}
+
+// Residual of the fine level, summed over the children of each coarse cell.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_restrict(MgLevel<R> F, MgLevel<R> Cc, int nd, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned I = gtid(); I < Cc.nc; I += gstride()) {
+    int X[3];
+    unflat(Cc.n, I, X);
+    R s = 0;
+    const int c1 = nd >= 2 ? 2 : 1, c2 = nd >= 3 ? 2 : 1;
+    for (int cq = 0; cq < c2; ++cq)
+      for (int bq = 0; bq < c1; ++bq)
+        for (int a = 0; a < 2; ++a) {
+          const int c[3] = {2 * X[0] + a, 2 * X[1] + bq, nd == 3 ? 2 * X[2] + cq : 0};
+          const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * (unsigned)c[2]);
+          s += F.b[id] - mg_apply_cell(F, nd, F.x, id, c);
+        }
+    Cc.b[I] = s;
+  }
+}
+
+// x_fine += x_coarse(parent)
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_prolong(MgLevel<R> F, MgLevel<R> Cc, int nd, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < F.nc; id += gstride()) {
+    int c[3];
+    unflat(F.n, id, c);
+    const unsigned I = (unsigned)(c[0] >> 1) + (unsigned)Cc.n[0] *
+                       ((unsigned)(c[1] >> 1) + (unsigned)Cc.n[1] * (unsigned)(nd == 3 ? (c[2] >> 1) : 0));
+    F.x[id] += Cc.x[I];
+  }
+}
+
+// Dense inverse of the coarsest operator (n <= 64), FP64, one block: build
+// A, scale to unit diagonal, Gauss-Jordan in place (SPD: no pivoting), unscale.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_coarse_inverse(MgLevel<R> L, int nd, double *__restrict__ Ainv)
+{
+  __shared__ double M[MG_COARSE_MAX][MG_COARSE_MAX + 1];
+  __shared__ double sc[MG_COARSE_MAX];
+  const int n = (int)L.nc;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e / n][e % n] = 0.0;
+  __syncthreads();
+  for (int id = threadIdx.x; id < n; id += blockDim.x) {
+    int c[3];
+    unflat(L.n, (unsigned)id, c);
+    M[id][id] = (double)L.diag[id];
+    const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
+    const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
+    if (c[0] > 0) M[id][id - 1] = -(double)L.T[0][f0];
+    if (c[0] < L.n[0] - 1) M[id][id + 1] = -(double)L.T[0][f0 + 1];
+    if (c[1] > 0) M[id][id - L.n[0]] = -(double)L.T[1][f1];
+    if (c[1] < L.n[1] - 1) M[id][id + L.n[0]] = -(double)L.T[1][f1 + L.fd[1][0]];
+    if (nd == 3) {
+      const int sz = L.n[0] * L.n[1];
+      const unsigned f2 = (unsigned)c[0] + (unsigned)L.fd[2][0] * ((unsigned)c[1] + (unsigned)L.fd[2][1] * c[2]);
+      if (c[2] > 0) M[id][id - sz] = -(double)L.T[2][f2];
+      if (c[2] < L.n[2] - 1) M[id][id + sz] = -(double)L.T[2][f2 + sz];
+    }
+    sc[id] = 1.0 / sqrt((double)L.diag[id]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    M[i][j] *= sc[i] * sc[j];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = 1.0 / M[k][k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+      if (j != k) M[k][j] *= piv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      if (i != k && j != k) M[i][j] -= M[i][k] * M[k][j];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      if (i != k) M[i][k] = -M[i][k] * piv;
+    __syncthreads();
+    if (threadIdx.x == 0) M[k][k] = piv;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    Ainv[e] = M[i][j] * sc[i] * sc[j];
+  }
+}
+
+// x = Ainv b on the coarsest level.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_coarse_solve(MgLevel<R> L, const double *__restrict__ Ainv,
+                                                         const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  __shared__ double bb[MG_COARSE_MAX];
+  const int n = (int)L.nc;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) bb[i] = (double)L.b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Ainv[i * n + j] * bb[j];
+    L.x[i] = (R)s;
+  }
+}
+
+}  // namespace vos

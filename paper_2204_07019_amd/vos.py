@@ -1,0 +1,201 @@
+"""Thin ctypes binding of libvos.so (include/vos.h): argument marshalling only.
+
+Every step of the method runs in the gfx950 kernels of libvos.so.  PyTorch is
+used for device memory (the workspace and field buffers) and the stream.  If
+the library is missing the import of this module fails loudly: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, asdict, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libvos.so")
+
+VOS_OK, VOS_ERR_ARG, VOS_ERR_DEVICE, VOS_ERR_NOCONV, VOS_ERR_OOM, VOS_ERR_STATE = range(6)
+IVOS, PSI, PSI_PRIME = 0, 1, 2
+FP64, MIXED = 0, 1
+FREEZE_SOLID = 1
+FIELDS = {"eps": 0, "ux": 1, "uy": 2, "uz": 3, "p": 4, "c": 5, "ustar_x": 6, "ustar_y": 7,
+          "ustar_z": 8, "rbar": 9, "gmag": 10}
+
+
+class VosError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"vos status {status}: {msg}")
+        self.status = status
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("mu", C.c_double), ("rho", C.c_double), ("D", C.c_double), ("k0", C.c_double),
+                ("kc", C.c_double), ("Vm", C.c_double), ("zeta", C.c_double), ("c_in", C.c_double),
+                ("eps_min", C.c_double), ("u_in", C.c_double), ("p_out", C.c_double),
+                ("model", C.c_int)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("rtol_u", C.c_double), ("rtol_p", C.c_double), ("rtol_c", C.c_double),
+                ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
+                ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int)]
+
+
+class _Diag(C.Structure):
+    _fields_ = [("it_u", C.c_int * 3), ("it_p", C.c_int), ("it_c", C.c_int),
+                ("res_u", C.c_double * 3), ("res_p", C.c_double), ("res_c", C.c_double),
+                ("lam", C.c_double), ("solid_volume", C.c_double), ("surface_area", C.c_double),
+                ("porosity", C.c_double), ("dP", C.c_double), ("K", C.c_double),
+                ("acid_in", C.c_double), ("acid_out", C.c_double), ("acid_consumed", C.c_double),
+                ("solid_rate", C.c_double), ("acid_balance_rel", C.c_double),
+                ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
+                ("max_deps", C.c_double), ("alpha", C.c_double), ("t_ms", C.c_double * 6)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvos.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2204_07019_amd/build.py "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.vos_workspace_bytes.argtypes = [C.POINTER(_Grid), C.POINTER(_Opts), C.POINTER(C.c_size_t)]
+        L.vos_create.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Opts), vp, C.c_size_t,
+                                 vp, C.POINTER(vp)]
+        L.vos_destroy.argtypes = [vp]
+        L.vos_set_solid_fraction.argtypes = [vp, vp, C.c_int]
+        L.vos_set_field.argtypes = [vp, C.c_int, vp, C.c_int]
+        L.vos_get_field.argtypes = [vp, C.c_int, vp, C.c_int]
+        L.vos_field_ptr.argtypes = [vp, C.c_int, C.POINTER(vp)]
+        L.vos_step.argtypes = [vp, C.c_double, C.c_int, C.c_int, C.POINTER(_Diag)]
+        L.vos_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
+        L.vos_last_error.restype = C.c_char_p
+        for name in ("vos_workspace_bytes", "vos_create", "vos_destroy", "vos_set_solid_fraction",
+                     "vos_set_field", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != VOS_OK:
+        raise VosError(rc, lib().vos_last_error().decode())
+
+
+def diag_to_dict(dg: _Diag) -> dict:
+    d = {}
+    for k, _ in _Diag._fields_:
+        v = getattr(dg, k)
+        d[k] = list(v) if k in ("it_u", "res_u", "t_ms") else v
+    d["lambda"] = d.pop("lam")
+    return d
+
+
+@dataclass
+class Opts:
+    rtol_u: float = 1e-8
+    rtol_p: float = 1e-8
+    rtol_c: float = 1e-8
+    maxit_u: int = 20000
+    maxit_p: int = 2000
+    maxit_c: int = 20000
+    precision: int = FP64
+    mg_nu: int = 2
+    check_every: int = 8
+
+
+class Sim:
+    """One simulation on one GPU.  ``params`` holds the vos_params fields
+    (mu, rho, D, k0, kc, Vm, zeta, c_in, eps_min, u_in, p_out, model)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, dx: float, params: dict,
+                 opts: Optional[Opts] = None, device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shape = (nz, ny, nx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.grid = _Grid(nx, ny, nz, dx)
+        keys = [k for k, _ in _Params._fields_]
+        self.params = _Params(**{k: params[k] for k in keys})
+        self.opts = _Opts(**asdict(opts or Opts()))
+        nbytes = C.c_size_t()
+        _check(lib().vos_workspace_bytes(C.byref(self.grid), C.byref(self.opts), C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().vos_create(C.byref(self.grid), C.byref(self.params), C.byref(self.opts),
+                                C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vos_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- fields
+    def field_shape(self, name: str):
+        nz, ny, nx = self.shape
+        if name in ("ux", "ustar_x"):
+            return (nz, ny, nx + 1)
+        if name in ("uy", "ustar_y"):
+            return (nz, ny + 1, nx)
+        if name in ("uz", "ustar_z"):
+            return (nz + 1, ny, nx)
+        return self.shape
+
+    def set_solid_fraction(self, eps_s):
+        t = self._as_device(eps_s, self.shape)
+        _check(lib().vos_set_solid_fraction(self._h, C.c_void_p(t.data_ptr()), 1))
+
+    def set(self, name: str, arr):
+        t = self._as_device(arr, self.field_shape(name))
+        _check(lib().vos_set_field(self._h, FIELDS[name], C.c_void_p(t.data_ptr()), 1))
+
+    def get(self, name: str):
+        """Copy of a field as a device tensor (float64)."""
+        out = self.torch.empty(self.field_shape(name), dtype=self.torch.float64, device=self.device)
+        _check(lib().vos_get_field(self._h, FIELDS[name], C.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def get_numpy(self, name: str) -> np.ndarray:
+        return self.get(name).cpu().numpy()
+
+    def _as_device(self, arr, shape):
+        torch = self.torch
+        t = torch.as_tensor(np.asarray(arr) if not isinstance(arr, torch.Tensor) else arr)
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
+            raise ValueError(f"expected {shape}, got {tuple(t.shape)}")
+        return t
+
+    # ---------------------------------------------------------------- stepping
+    def step(self, dt: float, nsteps: int = 1, freeze_solid: bool = False) -> dict:
+        dg = _Diag()
+        rc = lib().vos_step(self._h, dt, nsteps, FREEZE_SOLID if freeze_solid else 0, C.byref(dg))
+        _check(rc)
+        return diag_to_dict(dg)
+
+    def diagnostics(self) -> dict:
+        dg = _Diag()
+        _check(lib().vos_diagnostics(self._h, C.byref(dg)))
+        return diag_to_dict(dg)

@@ -1,0 +1,49 @@
+"""The C-ABI library builds for gfx950, loads, and exports every entry point
+include/vos.h declares (no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "vos.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vos_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("vos_create", "vos_step", "vos_set_solid_fraction", "vos_get_field",
+                 "vos_workspace_bytes", "vos_destroy", "vos_last_error", "vos_diagnostics"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2204_07019_amd import vos
+    if not os.path.exists(vos.LIB_PATH):
+        from paper_2204_07019_amd import build
+        build.build()
+    lib = ctypes.CDLL(vos.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_argument_errors_without_a_device():
+    """Host-side validation runs before any device call."""
+    from paper_2204_07019_amd import vos
+    L = vos.lib()
+    g = vos._Grid(1, 4, 1, 1e-6)
+    o = vos._Opts(**vos.asdict(vos.Opts()))
+    n = ctypes.c_size_t()
+    assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) == vos.VOS_ERR_ARG
+    assert b"nx >= 2" in L.vos_last_error()
+    g = vos._Grid(64, 32, 1, 5e-6)
+    assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) == vos.VOS_OK
+    assert n.value > 64 * 32 * 8 * 20
+    bad = vos._Opts(**dict(vos.asdict(vos.Opts()), mg_nu=0))
+    assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(n)) == vos.VOS_ERR_ARG
+    mixed = vos._Opts(**dict(vos.asdict(vos.Opts()), precision=vos.MIXED))
+    m = ctypes.c_size_t()
+    assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(mixed), ctypes.byref(m)) == vos.VOS_OK
