@@ -155,6 +155,12 @@ vos_status vos_destroy(vos_sim *sim);
  * device pointer (on_device = 1).  Values outside [0,1] give VOS_ERR_ARG. */
 vos_status vos_set_solid_fraction(vos_sim *sim, const double *eps_s, int on_device);
 
+/* Replace the physical parameters (same grid and workspace).  The fields are
+ * kept, except the inlet faces, which take the new u_in.  Used e.g. to set
+ * the inlet velocity and kc for a target Peclet / Damkohler number once the
+ * permeability of the geometry is known (Section 3.2). */
+vos_status vos_set_params(vos_sim *sim, const vos_params *params);
+
 /* Copy a whole field in or out (host or device buffer of the field's size).
  * Read-only fields reject vos_set_field with VOS_ERR_ARG. */
 vos_status vos_set_field(vos_sim *sim, int field, const double *src, int on_device);

@@ -226,8 +226,22 @@ static int pcg_jacobi(const stencil_t *A, const double *b, double *x, double rto
   return status;
 }
 
+/* splitmix64 (Steele, Lea & Flood 2014): the 64-bit output of counter i,
+ * mapped to a double in [-1, 1). */
+static double splitmix_unit(unsigned long long i)
+{
+  unsigned long long z = (i + 1ULL) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
 /* Plain BiCGStab (van der Vorst 1992) on A x = b where A already has unit
- * diagonal (rows scaled by their diagonal).  Stops when ||r|| <= rtol ||b||. */
+ * diagonal (rows scaled by their diagonal).  Stops when ||r|| <= rtol ||b||.
+ * The shadow residual is a fixed pseudo-random vector: the textbook choice
+ * r^ = r0 is supported only near the inlet for transport from a cold start,
+ * and r^.r collapses as the residual moves downstream (breakdown). */
 static int bicgstab(const stencil_t *A, const double *b, double *x, double rtol,
                     int maxit, int *its, double *relres)
 {
@@ -240,7 +254,7 @@ static int bicgstab(const stencil_t *A, const double *b, double *x, double rtol,
   }
   double bnorm = sqrt(dot(N, b, b));
   stencil_apply(A, x, t);
-  for (long i = 0; i < N; ++i) { r[i] = b[i] - t[i]; rh[i] = r[i]; }
+  for (long i = 0; i < N; ++i) { r[i] = b[i] - t[i]; rh[i] = splitmix_unit((unsigned long long)i); }
   double rho = 1.0, alpha = 1.0, omega = 1.0;
   double rnorm = sqrt(dot(N, r, r));
   double tol = rtol * bnorm;

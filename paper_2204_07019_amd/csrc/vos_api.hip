@@ -780,6 +780,22 @@ vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device
   return VOS_OK;
 }
 
+vos_status vos_set_params(vos_sim *s, const vos_params *params)
+{
+  if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
+  vos_status st = check_params(params);
+  if (st) return st;
+  s->prm = *params;
+  Phys &P = s->P;
+  P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
+  P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
+  P.u_in = params->u_in; P.p_out = params->p_out; P.model = params->model;
+  k_inlet<<<grid_blocks((size_t)s->g.n[1] * s->g.n[2]), TPB, 0, s->stream>>>(s->g, P.u_in, s->u[0]);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return VOS_OK;
+}
+
 vos_status vos_set_field(vos_sim *s, int field, const double *src, int on_device)
 {
   if (!s || !src) return fail(VOS_ERR_ARG, "NULL argument");

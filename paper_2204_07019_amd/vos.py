@@ -26,9 +26,10 @@ FIELDS = {"eps": 0, "ux": 1, "uy": 2, "uz": 3, "p": 4, "c": 5, "ustar_x": 6, "us
 
 
 class VosError(RuntimeError):
-    def __init__(self, status: int, msg: str):
+    def __init__(self, status: int, msg: str, diag: Optional[dict] = None):
         super().__init__(f"vos status {status}: {msg}")
         self.status = status
+        self.diag = diag
 
 
 class _Grid(C.Structure):
@@ -77,21 +78,22 @@ def lib():
         L.vos_destroy.argtypes = [vp]
         L.vos_set_solid_fraction.argtypes = [vp, vp, C.c_int]
         L.vos_set_field.argtypes = [vp, C.c_int, vp, C.c_int]
+        L.vos_set_params.argtypes = [vp, C.POINTER(_Params)]
         L.vos_get_field.argtypes = [vp, C.c_int, vp, C.c_int]
         L.vos_field_ptr.argtypes = [vp, C.c_int, C.POINTER(vp)]
         L.vos_step.argtypes = [vp, C.c_double, C.c_int, C.c_int, C.POINTER(_Diag)]
         L.vos_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
         L.vos_last_error.restype = C.c_char_p
         for name in ("vos_workspace_bytes", "vos_create", "vos_destroy", "vos_set_solid_fraction",
-                     "vos_set_field", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics"):
+                     "vos_set_field", "vos_set_params", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
 
 
-def _check(rc: int):
+def _check(rc: int, diag=None):
     if rc != VOS_OK:
-        raise VosError(rc, lib().vos_last_error().decode())
+        raise VosError(rc, lib().vos_last_error().decode(), diag)
 
 
 def diag_to_dict(dg: _Diag) -> dict:
@@ -167,6 +169,13 @@ class Sim:
         t = self._as_device(eps_s, self.shape)
         _check(lib().vos_set_solid_fraction(self._h, C.c_void_p(t.data_ptr()), 1))
 
+    def set_params(self, params: dict):
+        keys = [k for k, _ in _Params._fields_]
+        merged = {k: params.get(k, getattr(self.params, k)) for k in keys}
+        p = _Params(**merged)
+        _check(lib().vos_set_params(self._h, C.byref(p)))
+        self.params = p
+
     def set(self, name: str, arr):
         t = self._as_device(arr, self.field_shape(name))
         _check(lib().vos_set_field(self._h, FIELDS[name], C.c_void_p(t.data_ptr()), 1))
@@ -192,7 +201,7 @@ class Sim:
     def step(self, dt: float, nsteps: int = 1, freeze_solid: bool = False) -> dict:
         dg = _Diag()
         rc = lib().vos_step(self._h, dt, nsteps, FREEZE_SOLID if freeze_solid else 0, C.byref(dg))
-        _check(rc)
+        _check(rc, diag_to_dict(dg))
         return diag_to_dict(dg)
 
     def diagnostics(self) -> dict:
