@@ -1,0 +1,226 @@
+"""Benchmark of the Volume-of-Solid step on one MI355X.
+
+Workload (default): the 1024x512 2-D polydisperse disc micromodel (dx = 5 um,
+RSA discs with radii 10-40 cells to porosity 0.6, seed 11), iVoS, dt = 1 ms,
+inlet velocity and k_c set for Pe = 10, Da = 0.1 from the measured
+permeability (L = sqrt(12 K / phi), U = U_D / phi).  A step is one pass of the
+whole step: coefficients, momentum predictor, pressure equation
+(multigrid-preconditioned CG to a 1e-8 relative residual), correction,
+transport (BiCGStab), reaction and solid update.  Inputs stay resident in HBM.
+
+Prints ONE JSON line: cell-steps/s of the mixed-precision step (FP32
+multigrid inside FP64 Krylov), with the plain-FP64 step, the pressure-solve
+bandwidth, the live roofline of the dominant kernel and the CPU oracle beside
+it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per cell of one pressure PCG iteration in 2-D with the FP32
+# hierarchy (each array read or written once): outer FP64 CG 136 B (apply
+# 32, x/r update 56, z.r/z.q 24, direction 24) + V-cycle 173 B (finest level
+# 130 B x 4/3 for the coarser levels).  FP64 hierarchy: 136 + 292.
+P_ITER_BYTES = {("mixed", 2): 136 + 173, ("fp64", 2): 136 + 292,
+                ("mixed", 3): 152 + 187, ("fp64", 3): 152 + 318}
+# Per-step pressure setup (hierarchy build, right-hand side, initial residual):
+P_SETUP_BYTES = {2: 150, 3: 200}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def setup_sim(vos, inputs, scaling, workload, pe, da, precision, model, dt, relax_steps):
+    import torch
+    es, prm = inputs.workload(workload)
+    nz, ny, nx = es.shape
+    params = dict(prm, model=model)
+    opts = vos.Opts(precision=precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=8)
+    sim = vos.Sim(nx, ny, nz, prm["dx"], dict(params, kc=0.0), opts)
+    sim.set_solid_fraction(es)
+    d = None
+    for k in range(relax_steps):
+        d = sim.step(dt, 1, freeze_solid=True)
+    K = d["K"]
+    phi = float(sim.get("eps").mean())
+    ndim = 2 if nz == 1 else 3
+    u_in, kc = scaling.inlet_for(pe, da, K, phi, prm["D"], ndim)
+    r = u_in / prm["u_in"]
+    for name in ("ux", "uy", "uz"):
+        sim.set(name, sim.get(name) * r)
+    sim.set("p", (sim.get("p") - prm["p_out"]) * r + prm["p_out"])
+    sim.set_params(dict(params, u_in=u_in, kc=kc))
+    for _ in range(3):
+        sim.step(dt, 1, freeze_solid=True)
+    torch.cuda.synchronize()
+    return sim, es, dict(params, u_in=u_in, kc=kc), dict(K=K, phi=phi, u_in=u_in, kc=kc, ndim=ndim)
+
+
+def timed_steps(sim, dt, steps, warmup, timer_family=None):
+    import torch
+    for _ in range(warmup):
+        sim.step(dt)
+    if timer_family:
+        sim.kernel_timer(timer_family)
+    diags = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        diags.append(sim.step(dt))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tk = sim.kernel_timer_read() if timer_family else None
+    if timer_family:
+        sim.kernel_timer("off")
+    return el, diags, tk
+
+
+def cpu_baseline(workload, params, dt, budget_s):
+    """The oracle (plain C, one thread) on a bounded sample of the workload:
+    a crop of the same geometry, one step at a time until the budget is used."""
+    import numpy as np
+    import oracle
+    from paper_2204_07019_amd import inputs
+    oracle.build(force=False)
+    es, prm = inputs.workload(workload)
+    nz, ny, nx = es.shape
+    cy, cx = max(1, ny // 4), max(2, nx // 4)
+    crop = np.ascontiguousarray(es[:, :cy, :cx]) if nz == 1 else np.ascontiguousarray(es[:cy, :cy, :cx])
+    cz = crop.shape[0]
+    keys = ("mu", "rho", "D", "k0", "kc", "Vm", "zeta", "c_in", "eps_min", "u_in", "p_out", "model")
+    prob = oracle.Problem(nx=crop.shape[2], ny=crop.shape[1], nz=cz, dx=prm["dx"],
+                          **{k: params[k] for k in keys}, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8)
+    st = oracle.initial_state(prob, crop)
+    oracle.step(prob, st, dt, check=False)           # leave the cold start
+    n, t = 0, 0.0
+    while t < budget_s and n < 50:
+        t0 = time.perf_counter()
+        oracle.step(prob, st, dt, check=False)
+        t += time.perf_counter() - t0
+        n += 1
+    cells = prob.nx * prob.ny * prob.nz
+    return {"value": cells * n / t, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} steps of a {prob.nx}x{prob.ny}x{prob.nz} crop of the {workload} geometry "
+                      f"(same parameters, FP64, single-threaded C), {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="micromodel")
+    ap.add_argument("--pe", type=float, default=10.0)
+    ap.add_argument("--da", type=float, default=0.1)
+    ap.add_argument("--model", type=int, default=0)
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--relax", type=int, default=40)
+    ap.add_argument("--timer", default="smg_jacobi", help="kernel family for the live roofline")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2204_07019_amd import inputs, scaling, vos
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    vos.lib()
+
+    log(f"setup {args.workload} Pe={args.pe} Da={args.da}")
+    sim, es, params, info = setup_sim(vos, inputs, scaling, args.workload, args.pe, args.da,
+                                      vos.MIXED, args.model, args.dt, args.relax)
+    nz, ny, nx = es.shape
+    cells = nx * ny * nz
+    log(f"K={info['K']:.3e} phi={info['phi']:.3f} u_in={info['u_in']:.3e} kc={info['kc']:.3e}")
+
+    el, diags, tk = timed_steps(sim, args.dt, args.steps, args.warmup, timer_family=args.timer)
+    value = cells * args.steps / el
+    ms_step = el / args.steps * 1e3
+    log(f"mixed: {ms_step:.2f} ms/step, {value:.3e} cell-steps/s")
+
+    nd = info["ndim"]
+    its_p = sum(d["it_p"] for d in diags)
+    t_p = sum(d["t_ms"][2] for d in diags) * 1e-3
+    p_bytes = cells * (P_ITER_BYTES[("mixed", nd)] * its_p + P_SETUP_BYTES[nd] * len(diags))
+    p_gbs = p_bytes / t_p / 1e9
+
+    plain = None
+    if not args.skip_plain:
+        # same relaxed state, plain FP64 multigrid
+        sim64 = vos.Sim(nx, ny, nz, inputs.workload(args.workload)[1]["dx"], params,
+                        vos.Opts(precision=vos.FP64, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=8))
+        for k in ("eps", "ux", "uy", "uz", "p", "c"):
+            sim64.set(k, sim.get(k))
+        el64, d64, _ = timed_steps(sim64, args.dt, args.steps, args.warmup)
+        its64 = sum(d["it_p"] for d in d64)
+        t64 = sum(d["t_ms"][2] for d in d64) * 1e-3
+        pb64 = cells * (P_ITER_BYTES[("fp64", nd)] * its64 + P_SETUP_BYTES[nd] * len(d64))
+        plain = {"value": cells * args.steps / el64, "ms_per_step": el64 / args.steps * 1e3,
+                 "pressure_its_per_step": its64 / len(d64), "pressure_GBs": pb64 / t64 / 1e9}
+        log(f"fp64: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} cell-steps/s")
+        sim64.close()
+
+    roof = None
+    if tk and tk["launches"] > 0:
+        avg_ms = tk["total_ms"] / tk["launches"]
+        avg_bytes = tk["bytes"] / tk["launches"]
+        achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"{args.timer} (all levels)", "launches": tk["launches"],
+                "avg_launch_us": round(avg_ms * 1e3, 3), "avg_bytes_per_launch": round(avg_bytes)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(args.workload, params, args.dt, args.cpu_budget)
+
+    last = diags[-1]
+    out = {
+        "metric": "cell-steps/s + pressure-solve HBM GB/s at 1e-8 residual; learned+mixed vs plain",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (FP32 multigrid preconditioners)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {nx}x{ny}x{nz} dx=5um RSA discs seed 11, iVoS, "
+                               f"Pe={args.pe:g} Da={args.da:g}, dt={args.dt:g}s, rtol 1e-8",
+                   "precision": "mixed", "cells": cells},
+        "pressure_solve": {"GBs_algorithmic": round(p_gbs, 1), "frac_hbm": round(p_gbs / HBM_PEAK_GBS, 4),
+                           "its_per_step": its_p / len(diags), "ms_per_step": t_p / len(diags) * 1e3},
+        "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)],
+        "iterations": {"u": last["it_u"], "p": last["it_p"], "c": last["it_c"]},
+        "plain_fp64": plain,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,7 +95,11 @@ typedef struct {
   int maxit_u, maxit_p, maxit_c;
   int precision;    /* vos_precision (pressure multigrid) */
   int mg_nu;        /* Jacobi sweeps before and after each coarse correction (>= 1) */
-  int check_every;  /* Krylov iterations launched between host convergence checks (>= 1) */
+  int check_every;  /* Krylov iterations launched between host convergence checks, 1..256 */
+  int use_graphs;   /* 1: capture each solve's chunk of check_every iterations in a HIP graph
+                       once and replay it (iteration counts then round up to a multiple of
+                       check_every in the worst case; results are identical); 0: plain launches.
+                       Ignored (off) when vos_create() is given the null stream. */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */
@@ -183,6 +187,26 @@ vos_status vos_step(vos_sim *sim, double dt, int nsteps, int flags, vos_diag *la
 /* Diagnostics of the current state without advancing it (iteration counts
  * and balances are those of the last step). */
 vos_status vos_diagnostics(vos_sim *sim, vos_diag *out);
+
+/* Kernel families that vos_kernel_timer can time. */
+typedef enum {
+  VOS_TIMER_OFF = -1,
+  VOS_TIMER_SMG_JACOBI = 0,   /* Jacobi sweeps of the momentum / transport multigrid */
+  VOS_TIMER_MG_JACOBI = 1,    /* Jacobi sweeps of the pressure multigrid */
+  VOS_TIMER_ADR_APPLY = 2,    /* transport operator applications */
+  VOS_TIMER_P_APPLY = 3,      /* pressure operator applications */
+  VOS_TIMER_MOM_APPLY = 4     /* momentum operator applications */
+} vos_timer_family;
+
+/* Time every launch of one kernel family with a HIP event pair on the
+ * simulation's stream (VOS_TIMER_OFF stops timing) and reset the totals.
+ * Timing adds two event records per launch of that family only. */
+vos_status vos_kernel_timer(vos_sim *sim, int family);
+
+/* Totals since vos_kernel_timer(): summed launch durations [ms], number of
+ * timed launches, and the algorithmic bytes those launches move (each array
+ * read or written once per launch; neighbour re-reads are not counted). */
+vos_status vos_kernel_timer_read(vos_sim *sim, double *total_ms, long long *launches, double *bytes);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *vos_last_error(void);

@@ -19,6 +19,8 @@
 #include "vos_device.h"
 #include "vos_kernels.h"
 #include "vos_mg.h"
+#include "vos_smg.h"
+#include "vos_vcycle.h"
 
 using namespace vos;
 
@@ -98,16 +100,47 @@ int mg_hierarchy(const vos_grid &g, LevelDims *out)
   return L;
 }
 
+constexpr int NVEC = 10;
+constexpr int NSMG = 4;   // stencil hierarchies: momentum x, y, z; transport
+
+struct SmgPlan {
+  int nlev;
+  int n[SMG_MAX_LEVELS][3];
+  size_t off[SMG_MAX_LEVELS], diag[SMG_MAX_LEVELS], x[SMG_MAX_LEVELS], b[SMG_MAX_LEVELS], t[SMG_MAX_LEVELS];
+  size_t ainv;
+};
+
 struct Layout {
   size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
-  size_t vec[8];
+  size_t vec[NVEC];
   size_t part, part_max, scal, ainv;
   size_t mgT[MG_MAX_LEVELS][3], mgdiag[MG_MAX_LEVELS], mgx[MG_MAX_LEVELS], mgb[MG_MAX_LEVELS], mgt[MG_MAX_LEVELS];
   int nlev;
+  SmgPlan smg[NSMG];
   size_t total;
 };
 
 constexpr int NSC = 8;  // scalar blocks: mom x/y/z, pressure, transport, misc, diag, spare
+
+// Aggregation hierarchy: ceil-halve every active dimension until <= SMG_COARSE_MAX cells.
+void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs)
+{
+  int n[3] = {nx, ny, nz};
+  S.nlev = 0;
+  while (S.nlev < SMG_MAX_LEVELS) {
+    const int l = S.nlev++;
+    for (int d = 0; d < 3; ++d) S.n[l][d] = n[d];
+    const size_t nc = (size_t)n[0] * n[1] * n[2];
+    S.off[l] = P.take(6 * nc * rs);
+    S.diag[l] = P.take(nc * rs);
+    S.x[l] = P.take(nc * rs);
+    S.b[l] = P.take(nc * rs);
+    S.t[l] = P.take(nc * rs);
+    if (nc <= (size_t)SMG_COARSE_MAX) break;
+    for (int d = 0; d < nd; ++d) n[d] = (n[d] + 1) / 2;
+  }
+  S.ainv = P.take((size_t)SMG_COARSE_MAX * SMG_COARSE_MAX * sizeof(double));
+}
 
 Layout make_layout(const vos_grid &g, int precision)
 {
@@ -136,7 +169,7 @@ Layout make_layout(const vos_grid &g, int precision)
     Lo.T[d] = P.take(D0.nf[d] * dbl);
     Lo.w[d] = P.take(D0.nf[d] * dbl);
   }
-  for (int k = 0; k < 8; ++k) Lo.vec[k] = P.take(nmax * dbl);
+  for (int k = 0; k < NVEC; ++k) Lo.vec[k] = P.take(nmax * dbl);
   Lo.part = P.take((size_t)NSLOT * MAXB * dbl);
   Lo.part_max = P.take((size_t)MAXB * dbl);
   Lo.scal = P.take((size_t)NSC * S_COUNT * 2 * dbl);
@@ -151,6 +184,12 @@ Layout make_layout(const vos_grid &g, int precision)
     Lo.mgb[l] = P.take(lv[l].nc * rs);
     Lo.mgt[l] = P.take(lv[l].nc * rs);
   }
+  const int nd = g.nz == 1 ? 2 : 3;
+  for (int d = 0; d < 3; ++d) {
+    if (d < nd) plan_smg(P, Lo.smg[d], D0.fd[d][0], D0.fd[d][1], D0.fd[d][2], nd, rs);
+    else Lo.smg[d].nlev = 0;
+  }
+  plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, rs);
   Lo.total = P.off;
   return Lo;
 }
@@ -168,18 +207,41 @@ struct vos_sim {
   char *ws;
   double *eps, *p, *c, *pn, *cold, *rbar, *gmag, *nrm[3], *pdiag, *off;
   double *u[3], *ustar[3], *dmom[3], *af[3], *T[3], *w[3];
-  double *vec[8];
+  double *vec[NVEC];
   double *part, *part_max, *scal, *ainv;
   int nlev;
   MgLevel<float> mgf[MG_MAX_LEVELS];
   MgLevel<double> mgd[MG_MAX_LEVELS];
+  int snlev[NSMG];
+  SLevel<float> smgf[NSMG][SMG_MAX_LEVELS];
+  SLevel<double> smgd[NSMG][SMG_MAX_LEVELS];
+  double *sainv[NSMG];
   double *host;       // pinned scalar read-back buffer
   hipEvent_t ev[7];
+  // kernel-family timer: event pairs around each launch of one family
+  int timer_family;
+  int timer_n;
+  bool capturing;
+  bool use_graphs;
+  hipGraphExec_t gexec[8];  // one captured iteration chunk per solve
+  hipEvent_t *tev;      // 2 * TIMER_CAP events
+  double timer_ms, timer_bytes;
+  long long timer_launches;
   bool have_geometry;
   vos_diag last;
 };
 
 namespace {
+
+constexpr int TIMER_CAP = 8192;
+
+// Wrap a launch of kernel family `fam` moving `bytes` algorithmic bytes.
+struct TimedLaunch {
+  vos_sim *s;
+  bool on;
+  TimedLaunch(vos_sim *s_, int fam, double bytes, bool enabled = true);
+  ~TimedLaunch();
+};
 
 double *sc_block(vos_sim *s, int k) { return s->scal + (size_t)k * S_COUNT * 2; }
 enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6 };
@@ -209,6 +271,55 @@ void fill_levels(vos_sim *s, MgLevel<R> *lv)
   }
 }
 
+template <typename R>
+void fill_smg(vos_sim *s, int h, SLevel<R> *lv)
+{
+  const SmgPlan &S = s->lo.smg[h];
+  s->snlev[h] = S.nlev;
+  for (int l = 0; l < S.nlev; ++l) {
+    SLevel<R> &L = lv[l];
+    for (int d = 0; d < 3; ++d) L.n[d] = S.n[l][d];
+    L.nc = (unsigned)L.n[0] * L.n[1] * L.n[2];
+    L.off = (R *)(s->ws + S.off[l]);
+    L.diag = (R *)(s->ws + S.diag[l]);
+    L.x = (R *)(s->ws + S.x[l]);
+    L.b = (R *)(s->ws + S.b[l]);
+    L.t = (R *)(s->ws + S.t[l]);
+  }
+  if (S.nlev) s->sainv[h] = (double *)(s->ws + S.ainv);
+}
+
+TimedLaunch::TimedLaunch(vos_sim *s_, int fam, double bytes, bool enabled) : s(s_), on(false)
+{
+  if (enabled && !s->capturing && s->timer_family == fam && s->timer_n < TIMER_CAP) {
+    on = (hipEventRecord(s->tev[2 * s->timer_n], s->stream) == hipSuccess);
+    if (on) s->timer_bytes += bytes;
+  }
+}
+
+TimedLaunch::~TimedLaunch()
+{
+  if (on) {
+    (void)hipEventRecord(s->tev[2 * s->timer_n + 1], s->stream);
+    ++s->timer_n;
+  }
+}
+
+// Fold the recorded event pairs into the totals (synchronises the stream).
+vos_status timer_flush(vos_sim *s)
+{
+  if (s->timer_n == 0) return VOS_OK;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < s->timer_n; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->tev[2 * k], s->tev[2 * k + 1]));
+    s->timer_ms += ms;
+  }
+  s->timer_launches += s->timer_n;
+  s->timer_n = 0;
+  return VOS_OK;
+}
+
 vos_status check_grid(const vos_grid *g)
 {
   if (!g) return fail(VOS_ERR_ARG, "grid is NULL");
@@ -226,7 +337,7 @@ vos_status check_opts(const vos_opts *o)
   if (o->maxit_u < 1 || o->maxit_p < 1 || o->maxit_c < 1) return fail(VOS_ERR_ARG, "maxit must be >= 1");
   if (o->precision != VOS_FP64 && o->precision != VOS_MIXED) return fail(VOS_ERR_ARG, "unknown precision");
   if (o->mg_nu < 1 || o->mg_nu > 8) return fail(VOS_ERR_ARG, "mg_nu must be in [1, 8]");
-  if (o->check_every < 1) return fail(VOS_ERR_ARG, "check_every must be >= 1");
+  if (o->check_every < 1 || o->check_every > 256) return fail(VOS_ERR_ARG, "check_every must be in [1, 256]");
   return VOS_OK;
 }
 
@@ -249,18 +360,40 @@ vos_status read_back(vos_sim *s, const double *dev, size_t n)
 }
 
 // Run iterations until the device flag says converged or maxit is reached.
+// With graphs on, a chunk of check_every iterations is captured once per
+// solve (gid) and replayed; every kernel in it returns at once after the flag
+// is set, so replaying a whole chunk past convergence changes nothing.
 template <typename F>
-vos_status krylov_loop(vos_sim *s, double *sc, int maxit, F &&iter, int *its, double *res2, double *tol2, bool *conv)
+vos_status krylov_loop(vos_sim *s, int gid, double *sc, int maxit, F &&iter, int *its, double *res2, double *tol2,
+                       bool *conv)
 {
   HIP_TRY(hipGetLastError());
   int launched = 0;
   vos_status st = read_back(s, sc, S_COUNT);
   if (st) return st;
   bool done = s->host[S_CONV] != 0.0;
+  const int chunk = s->opt.check_every;
   while (!done && launched < maxit) {
-    const int k = std::min(s->opt.check_every, maxit - launched);
-    for (int i = 0; i < k; ++i) iter();
-    launched += k;
+    if (s->use_graphs) {
+      if (!s->gexec[gid]) {
+        hipGraph_t graph;
+        s->capturing = true;
+        HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < chunk; ++i) iter();
+        hipError_t e = hipStreamEndCapture(s->stream, &graph);
+        s->capturing = false;
+        if (e != hipSuccess) return fail(VOS_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&s->gexec[gid], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) { s->gexec[gid] = nullptr; return fail(VOS_ERR_DEVICE, "hipGraphInstantiate failed"); }
+      }
+      HIP_TRY(hipGraphLaunch(s->gexec[gid], s->stream));
+      launched += chunk;
+    } else {
+      const int k = std::min(chunk, maxit - launched);
+      for (int i = 0; i < k; ++i) iter();
+      launched += k;
+    }
     HIP_TRY(hipGetLastError());
     st = read_back(s, sc, S_COUNT);
     if (st) return st;
@@ -271,6 +404,12 @@ vos_status krylov_loop(vos_sim *s, double *sc, int maxit, F &&iter, int *its, do
   *tol2 = s->host[S_TOL2];
   *conv = (s->host[S_RES2] <= s->host[S_TOL2]) || (s->host[S_RES2] == 0.0);
   return VOS_OK;
+}
+
+void drop_graphs(vos_sim *s)
+{
+  for (int k = 0; k < 8; ++k)
+    if (s->gexec[k]) { (void)hipGraphExecDestroy(s->gexec[k]); s->gexec[k] = nullptr; }
 }
 
 // ---------------------------------------------------------------- stage S1
@@ -292,10 +431,99 @@ void launch_coefficients(vos_sim *s, double dt)
   k_pdiag<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pdiag);
 }
 
+// ---------------------------------------------------------------- algorithmic bytes
+// Each array read or written once per launch (neighbour re-reads come from
+// cache and are not counted).  R = arithmetic of the hierarchy.  Finest-level
+// Jacobi sweep on an explicit stencil: read x, b, diag and 2nd off-diagonals,
+// write x (+ the FP64 result on the last sweep).
+template <typename R>
+double jacobi_bytes(unsigned nc, int nd, bool out64, bool finest)
+{
+  (void)finest;
+  return ((4.0 + 2 * nd) * sizeof(R) + (out64 ? 8.0 : 0.0)) * nc;
+}
+
+// ---------------------------------------------------------------- stencil multigrid
+
+// Coarse levels and coarsest inverse of hierarchy h (level 0 already filled).
+template <typename R>
+void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv)
+{
+  hipStream_t st = s->stream;
+  const int nd = s->g.nd;
+  const int L = s->snlev[h];
+  for (int l = 0; l + 1 < L; ++l)
+    k_smg_coarsen<R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
+  k_smg_coarse_inverse<R><<<1, TPB, 0, st>>>(lv[L - 1], nd, s->sainv[h]);
+}
+
+// z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
+template <typename Lv, typename R>
+void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, double *z, const double *sc,
+            double omega)
+{
+  hipStream_t st = s->stream;
+  const int nd = s->g.nd;
+  const R om = (R)omega;
+  const int nu = s->opt.mg_nu;
+  int lc = 0;
+  while (lc < L - 1 && lv[lc].nc > (unsigned)VC_BLOCK_MAX) ++lc;
+  for (int l = 0; l < lc; ++l) {
+    Lv &F = lv[l];
+    const int nb = grid_blocks(F.nc);
+    {
+      TimedLaunch tl(s, VOS_TIMER_SMG_JACOBI, l == 0 ? jacobi_bytes<R>(F.nc, nd, false, l == 0) : 0.0, l == 0);
+      if (nu == 1) {
+        if (l == 0) k_v_pre<Lv, R, true, 1><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
+        else k_v_pre<Lv, R, false, 1><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
+      } else {
+        if (l == 0) k_v_pre<Lv, R, true, 2><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
+        else k_v_pre<Lv, R, false, 2><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
+      }
+    }
+    for (int k = 2; k < nu; ++k) {
+      k_v_jacobi<Lv, R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
+      std::swap(F.x, F.t);
+    }
+    k_v_restrict<Lv, R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(F, lv[l + 1], nd, sc);
+  }
+  LevelPack<Lv> pack;
+  for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
+  if (lc == 0) k_v_cast_in<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], r, sc);
+  k_v_coarse_cycle<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, nu, om, Ainv, sc);
+  if (lc == 0) {
+    k_v_cast_out<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], z, sc);
+    return;
+  }
+  for (int l = lc - 1; l >= 0; --l) {
+    Lv &F = lv[l];
+    const int nb = grid_blocks(F.nc);
+    {
+      const bool out = (l == 0 && nu == 1);
+      if (out) k_v_post<Lv, R, true><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, F.t, om, z, sc);
+      else k_v_post<Lv, R, false><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, F.t, om, nullptr, sc);
+      std::swap(F.x, F.t);
+    }
+    for (int k = 1; k < nu; ++k) {
+      const bool last = (l == 0 && k == nu - 1);
+      TimedLaunch tl(s, VOS_TIMER_SMG_JACOBI, jacobi_bytes<R>(F.nc, nd, last, l == 0), l == 0);
+      if (last) k_v_jacobi<Lv, R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, z, sc);
+      else k_v_jacobi<Lv, R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
+      std::swap(F.x, F.t);
+    }
+  }
+}
+
+template <typename R>
+void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc)
+{
+  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7);
+}
+
 // ---------------------------------------------------------------- stage S2
 
-template <int D>
-vos_status solve_momentum(vos_sim *s, double dt, int *its, double *res)
+template <int D, typename R>
+vos_status solve_momentum_t(vos_sim *s, SLevel<R> *lv, double dt, int *its, double *res)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
@@ -304,30 +532,48 @@ vos_status solve_momentum(vos_sim *s, double dt, int *its, double *res)
   double *b = s->vec[0], *r = s->vec[1], *z = s->vec[2], *pv = s->vec[3], *q = s->vec[4];
   double *x = s->ustar[D];
   double *sc = sc_block(s, SC_MOM + D);
+  double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
   const double cvis = s->P.mu / (g.dx * g.dx);
   const double rt2 = s->opt.rtol_u * s->opt.rtol_u;
   k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x);
-  // q = A x with a dummy (unconverged) flag: the misc block's S_CONV is always 0
-  double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
+  k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);
+  smg_coarsen_all<R>(s, D, lv);
   k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, s->part, zero_flag);
-  k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 1, s->part);
+  k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 0, s->part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
+  smg_vcycle<R>(s, D, lv, r, z, sc);
+  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
+  k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
+  HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
-    k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, s->part, sc);
+    {
+      TimedLaunch tl(s, VOS_TIMER_MOM_APPLY, 24.0 * n);
+      k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, s->part, sc);
+    }
     k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
-    k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 1, s->part, sc);
-    k_cg_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
+    k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 0, s->part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
+    smg_vcycle<R>(s, D, lv, r, z, sc);
+    k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
     k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
   };
   double res2, tol2;
   bool conv;
-  vos_status stt = krylov_loop(s, sc, s->opt.maxit_u, iter, its, &res2, &tol2, &conv);
+  vos_status stt = krylov_loop(s, D, sc, s->opt.maxit_u, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
   k_mom_fix<D><<<nb, TPB, 0, st>>>(g, s->P.u_in, x);
   const double bn2 = s->host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "momentum predictor did not converge");
   return VOS_OK;
+}
+
+template <int D>
+vos_status solve_momentum(vos_sim *s, double dt, int *its, double *res)
+{
+  if (s->opt.precision == VOS_MIXED) return solve_momentum_t<D, float>(s, s->smgf[D], dt, its, res);
+  return solve_momentum_t<D, double>(s, s->smgd[D], dt, its, res);
 }
 
 // ---------------------------------------------------------------- stage S3
@@ -350,67 +596,10 @@ void mg_setup(vos_sim *s, MgLevel<R> *lv)
   if (C.nc <= (unsigned)MG_COARSE_MAX) k_mg_coarse_inverse<R><<<1, TPB, 0, st>>>(C, nd, s->ainv);
 }
 
-// Coarsest-level solve: the dense inverse when the level has <= MG_COARSE_MAX
-// cells, otherwise 64 damped-Jacobi sweeps from zero.
-template <typename R>
-void mg_coarsest(vos_sim *s, MgLevel<R> &C, R om, const double *sc)
-{
-  hipStream_t st = s->stream;
-  const int nd = s->g.nd;
-  if (C.nc <= (unsigned)MG_COARSE_MAX) {
-    k_mg_coarse_solve<R><<<1, TPB, 0, st>>>(C, s->ainv, sc);
-    return;
-  }
-  const int nb = grid_blocks(C.nc);
-  k_mg_first<R><<<nb, TPB, 0, st>>>(C, om, sc);
-  for (int k = 1; k < 64; ++k) {
-    k_mg_jacobi<R, false><<<nb, TPB, 0, st>>>(C, nd, C.x, C.t, om, nullptr, sc);
-    std::swap(C.x, C.t);
-  }
-}
-
-// z = V-cycle(r).
 template <typename R>
 void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const double *sc)
 {
-  hipStream_t st = s->stream;
-  const int nd = s->g.nd;
-  const R om = (R)(nd == 3 ? 6.0 / 7.0 : 0.8);
-  const int nu = s->opt.mg_nu;
-  const int L = s->nlev;
-  if (L == 1) {
-    // one level only: the coarsest solve is the whole preconditioner
-    MgLevel<R> &F = lv[0];
-    const int nb = grid_blocks(F.nc);
-    k_mg_enter<R><<<nb, TPB, 0, st>>>(F, r, om, sc);
-    mg_coarsest<R>(s, F, om, sc);
-    k_mg_jacobi<R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, (R)0, z, sc);
-    std::swap(F.x, F.t);
-    return;
-  }
-  for (int l = 0; l < L - 1; ++l) {
-    MgLevel<R> &F = lv[l];
-    const int nb = grid_blocks(F.nc);
-    if (l == 0) k_mg_enter<R><<<nb, TPB, 0, st>>>(F, r, om, sc);
-    else k_mg_first<R><<<nb, TPB, 0, st>>>(F, om, sc);
-    for (int k = 1; k < nu; ++k) {
-      k_mg_jacobi<R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
-      std::swap(F.x, F.t);
-    }
-    k_mg_restrict<R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(F, lv[l + 1], nd, sc);
-  }
-  mg_coarsest<R>(s, lv[L - 1], om, sc);
-  for (int l = L - 2; l >= 0; --l) {
-    MgLevel<R> &F = lv[l];
-    const int nb = grid_blocks(F.nc);
-    k_mg_prolong<R><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, sc);
-    for (int k = 0; k < nu; ++k) {
-      const bool last = (l == 0 && k == nu - 1);
-      if (last) k_mg_jacobi<R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, z, sc);
-      else k_mg_jacobi<R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
-      std::swap(F.x, F.t);
-    }
-  }
+  vcycle<MgLevel<R>, R>(s, lv, s->nlev, s->ainv, r, z, sc, s->g.nd == 3 ? 6.0 / 7.0 : 0.8);
 }
 
 template <typename R>
@@ -435,7 +624,10 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
   HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
-    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], pv, q, s->part, sc);
+    {
+      TimedLaunch tl(s, VOS_TIMER_P_APPLY, (2.0 + g.nd) * 8.0 * n);
+      k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], pv, q, s->part, sc);
+    }
     k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->pdiag, s->p, r, z, 0, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
@@ -446,7 +638,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   };
   double res2, tol2;
   bool conv;
-  vos_status stt = krylov_loop(s, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv);
+  vos_status stt = krylov_loop(s, 3, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
   const double bn2 = s->host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
@@ -473,42 +665,60 @@ void launch_correct(vos_sim *s)
 
 // ---------------------------------------------------------------- stage S5
 
-vos_status solve_transport(vos_sim *s, int *its, double *res)
+template <typename R>
+vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
   const unsigned n = g.nc;
   const int nb = grid_blocks(n);
   double *b = s->vec[0], *r = s->vec[1], *rh = s->vec[2], *pv = s->vec[3], *v = s->vec[4], *sv = s->vec[5],
-         *t = s->vec[6], *y = s->vec[7];
+         *t = s->vec[6], *y = s->vec[7], *ph = s->vec[8], *sh = s->vec[9];
   double *sc = sc_block(s, SC_C);
   double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
+  const int H = 3;
   const double rt2 = s->opt.rtol_c * s->opt.rtol_c;
   HIP_TRY(hipMemcpyAsync(s->cold, s->c, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
                                      s->gmag, sc_block(s, SC_MISC), s->off, b, y);
+  k_smg_from_scaled<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, lv[0]);
+  smg_coarsen_all<R>(s, H, lv);
   k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
   k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
   k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, sc);
-    k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, pv, v, rh, s->part, sc);
+    smg_vcycle<R>(s, H, lv, pv, ph, sc);
+    {
+      TimedLaunch tl(s, VOS_TIMER_ADR_APPLY, (3.0 + 2 * g.nd) * 8.0 * n);
+      k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
+    }
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
-    k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sv, t, sv, s->part, sc);
+    smg_vcycle<R>(s, H, lv, sv, sh, sc);
+    {
+      TimedLaunch tl(s, VOS_TIMER_ADR_APPLY, (3.0 + 2 * g.nd) * 8.0 * n);
+      k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
+    }
     k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
-    k_bi_xr<<<nb, TPB, 0, st>>>(n, pv, sv, t, rh, s->c, r, s->part, sc);
+    k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, rh, s->c, r, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
   };
   double res2, tol2;
   bool conv;
-  vos_status stt = krylov_loop(s, sc, s->opt.maxit_c, iter, its, &res2, &tol2, &conv);
+  vos_status stt = krylov_loop(s, 4, sc, s->opt.maxit_c, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
   const double bn2 = s->host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "transport solve did not converge");
   return VOS_OK;
+}
+
+vos_status solve_transport(vos_sim *s, int *its, double *res)
+{
+  if (s->opt.precision == VOS_MIXED) return solve_transport_t<float>(s, s->smgf[3], its, res);
+  return solve_transport_t<double>(s, s->smgd[3], its, res);
 }
 
 // ---------------------------------------------------------------- stages S6-S7
@@ -608,6 +818,8 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   HIP_TRY(hipEventRecord(s->ev[6], st));
   HIP_TRY(hipGetLastError());
   r2 = fill_diag(s, dt, dg);
+  if (r2) return r2;
+  r2 = timer_flush(s);
   if (r2) return r2;
   for (int k = 0; k < 6; ++k) {
     float ms = 0.f;
@@ -723,11 +935,15 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     s->nrm[d] = D(lo.nrm[d]); s->u[d] = D(lo.u[d]); s->ustar[d] = D(lo.ustar[d]); s->dmom[d] = D(lo.dmom[d]);
     s->af[d] = D(lo.af[d]); s->T[d] = D(lo.T[d]); s->w[d] = D(lo.w[d]);
   }
-  for (int k = 0; k < 8; ++k) s->vec[k] = D(lo.vec[k]);
+  for (int k = 0; k < NVEC; ++k) s->vec[k] = D(lo.vec[k]);
   s->part = D(lo.part); s->part_max = D(lo.part_max); s->scal = D(lo.scal); s->ainv = D(lo.ainv);
   s->nlev = lo.nlev;
   fill_levels<float>(s, s->mgf);
   fill_levels<double>(s, s->mgd);
+  for (int h = 0; h < NSMG; ++h) {
+    fill_smg<float>(s, h, s->smgf[h]);
+    fill_smg<double>(s, h, s->smgd[h]);
+  }
   s->have_geometry = false;
   std::memset(&s->last, 0, sizeof(s->last));
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
@@ -736,6 +952,14 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     e = hipEventCreate(&s->ev[k]);
     if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, "hipEventCreate failed"); }
   }
+  s->capturing = false;
+  s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
+  for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
+  s->timer_family = VOS_TIMER_OFF;
+  s->timer_n = 0;
+  s->timer_ms = s->timer_bytes = 0.0;
+  s->timer_launches = 0;
+  s->tev = nullptr;
   // initial state: fluid at rest, p = p_out, c = 0, eps = 1
   hipStream_t stq = s->stream;
   HIP_TRY(hipMemsetAsync(s->ws, 0, lo.total, stq));
@@ -752,7 +976,12 @@ vos_status vos_destroy(vos_sim *s)
 {
   if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
   (void)hipStreamSynchronize(s->stream);
+  drop_graphs(s);
   for (int k = 0; k < 7; ++k) (void)hipEventDestroy(s->ev[k]);
+  if (s->tev) {
+    for (int k = 0; k < 2 * TIMER_CAP; ++k) (void)hipEventDestroy(s->tev[k]);
+    delete[] s->tev;
+  }
   (void)hipHostFree(s->host);
   delete s;
   return VOS_OK;
@@ -786,6 +1015,7 @@ vos_status vos_set_params(vos_sim *s, const vos_params *params)
   vos_status st = check_params(params);
   if (st) return st;
   s->prm = *params;
+  drop_graphs(s);   // captured iterations hold mu / dx^2 by value
   Phys &P = s->P;
   P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
   P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
@@ -851,6 +1081,34 @@ vos_status vos_step(vos_sim *s, double dt, int nsteps, int flags, vos_diag *last
     }
   }
   if (last) *last = s->last;
+  return VOS_OK;
+}
+
+vos_status vos_kernel_timer(vos_sim *s, int family)
+{
+  if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
+  if (family < VOS_TIMER_OFF || family > VOS_TIMER_MOM_APPLY) return fail(VOS_ERR_ARG, "unknown kernel family");
+  vos_status st = timer_flush(s);
+  if (st) return st;
+  if (family != VOS_TIMER_OFF && !s->tev) {
+    s->tev = new (std::nothrow) hipEvent_t[2 * TIMER_CAP];
+    if (!s->tev) return fail(VOS_ERR_OOM, "host allocation failed");
+    for (int k = 0; k < 2 * TIMER_CAP; ++k) HIP_TRY(hipEventCreate(&s->tev[k]));
+  }
+  s->timer_family = family;
+  s->timer_ms = s->timer_bytes = 0.0;
+  s->timer_launches = 0;
+  return VOS_OK;
+}
+
+vos_status vos_kernel_timer_read(vos_sim *s, double *total_ms, long long *launches, double *bytes)
+{
+  if (!s || !total_ms || !launches || !bytes) return fail(VOS_ERR_ARG, "NULL argument");
+  vos_status st = timer_flush(s);
+  if (st) return st;
+  *total_ms = s->timer_ms;
+  *launches = s->timer_launches;
+  *bytes = s->timer_bytes;
   return VOS_OK;
 }
 

@@ -670,20 +670,34 @@ __global__ void k_cg_scal(int op, const double *__restrict__ part, int nb, doubl
 
 // ---------------------------------------------------------------- BiCGStab vector kernels
 
-// r = b - y; rh = r; p = v = 0; partials b.b, r.r
+// splitmix64 (Steele, Lea & Flood 2014) of counter i, as a double in [-1, 1).
+__device__ __forceinline__ double splitmix_unit(unsigned long long i)
+{
+  unsigned long long z = (i + 1ULL) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// r = b - y; rh = fixed pseudo-random shadow residual (global support, so
+// rh.r cannot vanish as a cold-start residual travels downstream); p = v = 0;
+// partials b.b, r.r, rh.r
 __global__ void __launch_bounds__(TPB) k_bi_init(unsigned n, const double *__restrict__ b, const double *__restrict__ y,
                                                  double *__restrict__ r, double *__restrict__ rh, double *__restrict__ p,
                                                  double *__restrict__ v, double *__restrict__ part)
 {
-  double bb = 0.0, rr = 0.0;
+  double bb = 0.0, rr = 0.0, hr = 0.0;
   for (unsigned i = gtid(); i < n; i += gstride()) {
     const double ri = b[i] - y[i];
-    r[i] = ri; rh[i] = ri; p[i] = 0.0; v[i] = 0.0;
+    const double h = splitmix_unit(i);
+    r[i] = ri; rh[i] = h; p[i] = 0.0; v[i] = 0.0;
     bb += b[i] * b[i];
     rr += ri * ri;
+    hr += h * ri;
   }
-  const double vv[2] = {bb, rr};
-  write_partials<2>(vv, part);
+  const double vv[3] = {bb, rr, hr};
+  write_partials<3>(vv, part);
 }
 
 // p = r + beta (p - omega v)
@@ -712,20 +726,21 @@ __global__ void __launch_bounds__(TPB) k_bi_s(unsigned n, const double *__restri
   write_partials<1>(vv, part);
 }
 
-// x += alpha p + omega s; r = s - omega t (or only x += alpha p after an early
-// exit on s); partials r.r, rh.r
-__global__ void __launch_bounds__(TPB) k_bi_xr(unsigned n, const double *__restrict__ p, const double *__restrict__ s,
-                                               const double *__restrict__ t, const double *__restrict__ rh,
-                                               double *__restrict__ x, double *__restrict__ r,
-                                               double *__restrict__ part, double *__restrict__ sc)
+// x += alpha ph + omega sh; r = s - omega t (or only x += alpha ph after an
+// early exit on s); partials r.r, rh.r.  ph, sh: preconditioned directions.
+__global__ void __launch_bounds__(TPB) k_bi_xr(unsigned n, const double *__restrict__ ph, const double *__restrict__ sh,
+                                               const double *__restrict__ s, const double *__restrict__ t,
+                                               const double *__restrict__ rh, double *__restrict__ x,
+                                               double *__restrict__ r, double *__restrict__ part,
+                                               double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   const double al = sc[S_ALPHA], om = sc[S_OMEGA];
   const bool half = sc[S_SHALF] != 0.0;
   double rr = 0.0, rhr = 0.0;
   for (unsigned i = gtid(); i < n; i += gstride()) {
-    if (half) { x[i] += al * p[i]; continue; }
-    x[i] += al * p[i] + om * s[i];
+    if (half) { x[i] += al * ph[i]; continue; }
+    x[i] += al * ph[i] + om * sh[i];
     const double ri = s[i] - om * t[i];
     r[i] = ri;
     rr += ri * ri;
@@ -736,7 +751,7 @@ __global__ void __launch_bounds__(TPB) k_bi_xr(unsigned n, const double *__restr
 }
 
 // BiCGStab scalars.
-//  op 0 (init): bn2 = b.b, res2 = r.r, rho = alpha = omega = 1, rz(=rh.r) = r.r; conv test.
+//  op 0 (init): bn2 = b.b, res2 = r.r, rho = rh.r, alpha = omega = 1, beta = 0; conv test.
 //  op 1 (alpha): alpha = rho / rh.v (partial slot 0).
 //  op 2 (s test): s.s <= tol2 -> half step then converge.
 //  op 3 (omega): omega = t.s / t.t (slots 0, 1).
@@ -746,16 +761,17 @@ __global__ void k_bi_scal(int op, const double *__restrict__ part, int nb, doubl
   if (op != 0 && sc[S_CONV] != 0.0) return;
   const double a = sum_partials(part, 0, nb);
   const double b = (op == 0 || op == 3 || op == 4) ? sum_partials(part, 1, nb) : 0.0;
+  const double c3 = (op == 0) ? sum_partials(part, 2, nb) : 0.0;
   if (threadIdx.x != 0) return;
   switch (op) {
     case 0: {
       sc[S_BN2] = a; sc[S_RES2] = b; sc[S_TOL2] = rtol2 * a; sc[S_ITS] = 0.0; sc[S_BAD] = 0.0;
-      sc[S_RHO] = 1.0; sc[S_ALPHA] = 1.0; sc[S_OMEGA] = 1.0; sc[S_SHALF] = 0.0;
+      sc[S_ALPHA] = 1.0; sc[S_OMEGA] = 1.0; sc[S_SHALF] = 0.0;
       sc[S_CONV] = (b <= rtol2 * a || b == 0.0) ? 1.0 : 0.0;
-      // first direction: rho_new = rh.r = r.r
-      const double rho_new = b;
+      // first direction p = r: beta = 0, rho = rh.r
       sc[S_BETA] = 0.0;
-      sc[S_RHO] = rho_new;
+      sc[S_RHO] = c3;
+      if (c3 == 0.0 && sc[S_CONV] == 0.0) { sc[S_BAD] = 1.0; sc[S_CONV] = 1.0; }
       break;
     }
     case 1:

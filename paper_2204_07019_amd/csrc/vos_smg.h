@@ -1,0 +1,258 @@
+// vos_smg.h -- aggregation multigrid on explicit 7-point stencils, used to
+// precondition the momentum (flexible CG) and transport (right-preconditioned
+// BiCGStab) solves.  Templated on the arithmetic of the hierarchy.
+//
+// Level l+1 aggregates 2 cells per active dimension of level l (ceil, so odd
+// sizes keep a one-cell aggregate at the end).  The coarse operator is the
+// Galerkin product P^T A P with piecewise-constant P: couplings between two
+// aggregates add up, couplings inside an aggregate fold into the diagonal.
+// For the upwind transport operator this keeps the flux balance of every
+// aggregate exact.  Restriction sums the children's residuals, prolongation
+// injects.  Smoother: damped Jacobi.  Coarsest level (<= 64 cells): dense
+// inverse built once per solve.
+#pragma once
+#include "vos_device.h"
+#include "vos_kernels.h"
+
+namespace vos {
+
+constexpr int SMG_MAX_LEVELS = 20;
+constexpr int SMG_COARSE_MAX = 64;
+
+template <typename R>
+struct SLevel {
+  int n[3];
+  unsigned nc;
+  R *off;    // 6 * nc: -x, +x, -y, +y, -z, +z
+  R *diag;
+  R *x, *b, *t;
+};
+
+template <typename R>
+__device__ __forceinline__ R smg_apply_cell(const SLevel<R> &L, int nd, const R *x, unsigned id, const int c[3])
+{
+  R v = L.diag[id] * x[id];
+  const unsigned nc = L.nc;
+  if (c[0] > 0) v += L.off[id] * x[id - 1];
+  if (c[0] < L.n[0] - 1) v += L.off[nc + id] * x[id + 1];
+  const unsigned sy = (unsigned)L.n[0];
+  if (c[1] > 0) v += L.off[2 * nc + id] * x[id - sy];
+  if (c[1] < L.n[1] - 1) v += L.off[3 * nc + id] * x[id + sy];
+  if (nd == 3) {
+    const unsigned sz = (unsigned)L.n[0] * L.n[1];
+    if (c[2] > 0) v += L.off[4 * nc + id] * x[id - sz];
+    if (c[2] < L.n[2] - 1) v += L.off[5 * nc + id] * x[id + sz];
+  }
+  return v;
+}
+
+// Level 0 of the transport hierarchy: the row-scaled stencil (unit diagonal).
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_from_scaled(unsigned nc, int nd, const double *__restrict__ off64,
+                                                         SLevel<R> L)
+{
+  for (unsigned id = gtid(); id < nc; id += gstride()) {
+    L.diag[id] = (R)1;
+    for (int k = 0; k < 2 * nd; ++k) L.off[(size_t)k * nc + id] = (R)off64[(size_t)k * nc + id];
+    for (int k = 2 * nd; k < 6; ++k) L.off[(size_t)k * nc + id] = (R)0;
+  }
+}
+
+// Level 0 of the momentum hierarchy of component D on its face grid:
+// diagonal dmom, -mu/dx^2 towards unknown neighbours (fixed rows: identity).
+template <typename R, int D>
+__global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, const double *__restrict__ dmom,
+                                                           SLevel<R> L)
+{
+  const unsigned nc = L.nc;
+  for (unsigned f = gtid(); f < nc; f += gstride()) {
+    int x[3];
+    unflat(g.fd[D], f, x);
+    L.diag[f] = (R)dmom[f];
+    const bool unk = mom_unknown<D>(g, x);
+    double fv;
+    for (int e = 0; e < 3; ++e)
+      for (int s = -1; s <= 1; s += 2) {
+        const int slot = 2 * e + (s > 0);
+        R v = 0;
+        if (unk && e < g.nd && mom_nb<D>(g, x, e, s, 0.0, &fv) == 0) v = (R)(-cvis);
+        L.off[(size_t)slot * nc + f] = v;
+      }
+  }
+}
+
+// Galerkin coarse stencil of aggregate I.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, int nd)
+{
+  for (unsigned I = gtid(); I < C.nc; I += gstride()) {
+    int X[3];
+    unflat(C.n, I, X);
+    R dg = 0, o[6] = {0, 0, 0, 0, 0, 0};
+    const int lim2 = nd == 3 ? 2 : 1;
+    for (int cz = 0; cz < lim2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const int c[3] = {2 * X[0] + cx, 2 * X[1] + cy, nd == 3 ? 2 * X[2] + cz : 0};
+          if (c[0] >= F.n[0] || c[1] >= F.n[1] || c[2] >= F.n[2]) continue;
+          // a dimension of extent 1 is not aggregated
+          if ((F.n[1] == 1 && cy) || (nd == 3 && F.n[2] == 1 && cz) || (F.n[0] == 1 && cx)) continue;
+          const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * c[2]);
+          dg += F.diag[id];
+          for (int d = 0; d < nd; ++d) {
+            const int cd = c[d];
+            const int half = (F.n[d] == 1) ? 0 : 1;  // aggregated in this dimension?
+            for (int s = 0; s < 2; ++s) {
+              const R a = F.off[(size_t)(2 * d + s) * F.nc + id];
+              const int nbc = s ? cd + 1 : cd - 1;
+              if (nbc < 0 || nbc >= F.n[d]) continue;
+              const int aggI = half ? (cd >> 1) : cd;
+              const int aggN = half ? (nbc >> 1) : nbc;
+              if (aggI == aggN) dg += a;
+              else o[2 * d + s] += a;
+            }
+          }
+        }
+    C.diag[I] = dg;
+    for (int k = 0; k < 6; ++k) C.off[(size_t)k * C.nc + I] = o[k];
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_enter(SLevel<R> L, const double *__restrict__ r, R omega,
+                                                   const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+    const R bb = (R)r[id];
+    L.b[id] = bb;
+    L.x[id] = omega * bb / L.diag[id];
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_first(SLevel<R> L, R omega, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) L.x[id] = omega * L.b[id] / L.diag[id];
+}
+
+template <typename R, bool OUT64>
+__global__ void __launch_bounds__(TPB) k_smg_jacobi(SLevel<R> L, int nd, const R *__restrict__ x, R *__restrict__ xo,
+                                                    R omega, double *__restrict__ z, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+    int c[3];
+    unflat(L.n, id, c);
+    const R v = x[id] + omega * (L.b[id] - smg_apply_cell(L, nd, x, id, c)) / L.diag[id];
+    xo[id] = v;
+    if (OUT64) z[id] = (double)v;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_restrict(SLevel<R> F, SLevel<R> C, int nd, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned I = gtid(); I < C.nc; I += gstride()) {
+    int X[3];
+    unflat(C.n, I, X);
+    R s = 0;
+    const int lim2 = nd == 3 ? 2 : 1;
+    for (int cz = 0; cz < lim2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          if ((F.n[1] == 1 && cy) || (nd == 3 && F.n[2] == 1 && cz) || (F.n[0] == 1 && cx)) continue;
+          const int c[3] = {2 * X[0] + cx, 2 * X[1] + cy, nd == 3 ? 2 * X[2] + cz : 0};
+          if (c[0] >= F.n[0] || c[1] >= F.n[1] || c[2] >= F.n[2]) continue;
+          const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * c[2]);
+          s += F.b[id] - smg_apply_cell(F, nd, F.x, id, c);
+        }
+    C.b[I] = s;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_prolong(SLevel<R> F, SLevel<R> C, int nd, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  for (unsigned id = gtid(); id < F.nc; id += gstride()) {
+    int c[3];
+    unflat(F.n, id, c);
+    const int I0 = F.n[0] == 1 ? c[0] : (c[0] >> 1);
+    const int I1 = F.n[1] == 1 ? c[1] : (c[1] >> 1);
+    const int I2 = (nd == 3 && F.n[2] > 1) ? (c[2] >> 1) : c[2];
+    const unsigned I = (unsigned)I0 + (unsigned)C.n[0] * ((unsigned)I1 + (unsigned)C.n[1] * (unsigned)I2);
+    F.x[id] += C.x[I];
+  }
+}
+
+// Dense inverse of the coarsest operator (n <= 64), FP64, one block.  Rows are
+// scaled by the diagonal first (M = D^-1 A); the operators here are
+// diagonally dominant, so Gauss-Jordan needs no pivoting; Ainv = M^-1 D^-1.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_coarse_inverse(SLevel<R> L, int nd, double *__restrict__ Ainv)
+{
+  __shared__ double M[SMG_COARSE_MAX][SMG_COARSE_MAX + 1];
+  __shared__ double rs[SMG_COARSE_MAX];
+  const int n = (int)L.nc;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e / n][e % n] = 0.0;
+  __syncthreads();
+  for (int id = threadIdx.x; id < n; id += blockDim.x) {
+    int c[3];
+    unflat(L.n, (unsigned)id, c);
+    const double dgl = (double)L.diag[id];
+    rs[id] = 1.0 / dgl;
+    M[id][id] = 1.0;
+    const int sy = L.n[0], sz = L.n[0] * L.n[1];
+    if (c[0] > 0) M[id][id - 1] = (double)L.off[id] / dgl;
+    if (c[0] < L.n[0] - 1) M[id][id + 1] = (double)L.off[n + id] / dgl;
+    if (c[1] > 0) M[id][id - sy] = (double)L.off[2 * n + id] / dgl;
+    if (c[1] < L.n[1] - 1) M[id][id + sy] = (double)L.off[3 * n + id] / dgl;
+    if (nd == 3) {
+      if (c[2] > 0) M[id][id - sz] = (double)L.off[4 * n + id] / dgl;
+      if (c[2] < L.n[2] - 1) M[id][id + sz] = (double)L.off[5 * n + id] / dgl;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = 1.0 / M[k][k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+      if (j != k) M[k][j] *= piv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      if (i != k && j != k) M[i][j] -= M[i][k] * M[k][j];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      if (i != k) M[i][k] = -M[i][k] * piv;
+    __syncthreads();
+    if (threadIdx.x == 0) M[k][k] = piv;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    Ainv[e] = M[i][j] * rs[j];
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_smg_coarse_solve(SLevel<R> L, const double *__restrict__ Ainv,
+                                                          const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  __shared__ double bb[SMG_COARSE_MAX];
+  const int n = (int)L.nc;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) bb[i] = (double)L.b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Ainv[i * n + j] * bb[j];
+    L.x[i] = (R)s;
+  }
+}
+
+}  // namespace vos

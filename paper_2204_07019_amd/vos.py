@@ -21,6 +21,7 @@ VOS_OK, VOS_ERR_ARG, VOS_ERR_DEVICE, VOS_ERR_NOCONV, VOS_ERR_OOM, VOS_ERR_STATE 
 IVOS, PSI, PSI_PRIME = 0, 1, 2
 FP64, MIXED = 0, 1
 FREEZE_SOLID = 1
+TIMERS = {"off": -1, "smg_jacobi": 0, "mg_jacobi": 1, "adr_apply": 2, "p_apply": 3, "mom_apply": 4}
 FIELDS = {"eps": 0, "ux": 1, "uy": 2, "uz": 3, "p": 4, "c": 5, "ustar_x": 6, "ustar_y": 7,
           "ustar_z": 8, "rbar": 9, "gmag": 10}
 
@@ -46,7 +47,8 @@ class _Params(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("rtol_u", C.c_double), ("rtol_p", C.c_double), ("rtol_c", C.c_double),
                 ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
-                ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int)]
+                ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int),
+                ("use_graphs", C.c_int)]
 
 
 class _Diag(C.Structure):
@@ -83,9 +85,13 @@ def lib():
         L.vos_field_ptr.argtypes = [vp, C.c_int, C.POINTER(vp)]
         L.vos_step.argtypes = [vp, C.c_double, C.c_int, C.c_int, C.POINTER(_Diag)]
         L.vos_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
+        L.vos_kernel_timer.argtypes = [vp, C.c_int]
+        L.vos_kernel_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
+                                            C.POINTER(C.c_double)]
         L.vos_last_error.restype = C.c_char_p
         for name in ("vos_workspace_bytes", "vos_create", "vos_destroy", "vos_set_solid_fraction",
-                     "vos_set_field", "vos_set_params", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics"):
+                     "vos_set_field", "vos_set_params", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics",
+                     "vos_kernel_timer", "vos_kernel_timer_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -116,6 +122,7 @@ class Opts:
     precision: int = FP64
     mg_nu: int = 2
     check_every: int = 8
+    use_graphs: int = 1
 
 
 class Sim:
@@ -136,7 +143,8 @@ class Sim:
         nbytes = C.c_size_t()
         _check(lib().vos_workspace_bytes(C.byref(self.grid), C.byref(self.opts), C.byref(nbytes)))
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the legacy null stream cannot be graph-captured
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         h = C.c_void_p()
         _check(lib().vos_create(C.byref(self.grid), C.byref(self.params), C.byref(self.opts),
                                 C.c_void_p(self.workspace.data_ptr()), nbytes.value,
@@ -193,6 +201,8 @@ class Sim:
         torch = self.torch
         t = torch.as_tensor(np.asarray(arr) if not isinstance(arr, torch.Tensor) else arr)
         t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        # the library reads it on its own stream: finish torch's copy first
+        torch.cuda.current_stream(self.device).synchronize()
         if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
             raise ValueError(f"expected {shape}, got {tuple(t.shape)}")
         return t
@@ -203,6 +213,15 @@ class Sim:
         rc = lib().vos_step(self._h, dt, nsteps, FREEZE_SOLID if freeze_solid else 0, C.byref(dg))
         _check(rc, diag_to_dict(dg))
         return diag_to_dict(dg)
+
+    def kernel_timer(self, family: str):
+        """Start timing every launch of one kernel family (see TIMERS)."""
+        _check(lib().vos_kernel_timer(self._h, TIMERS[family]))
+
+    def kernel_timer_read(self) -> dict:
+        ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
+        _check(lib().vos_kernel_timer_read(self._h, C.byref(ms), C.byref(n), C.byref(b)))
+        return {"total_ms": ms.value, "launches": n.value, "bytes": b.value}
 
     def diagnostics(self) -> dict:
         dg = _Diag()

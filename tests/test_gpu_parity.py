@@ -152,3 +152,23 @@ def test_noconv_is_reported(orc):
         sim.step(1e-3)
     assert e.value.status == vos.VOS_ERR_NOCONV
     sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_eager(orc, precision):
+    """Captured iteration chunks, replayed many times across steps with host
+    synchronisations in between, give bitwise the same fields as plain launches."""
+    from paper_2204_07019_amd import inputs
+    es = inputs.rsa_discs(128, 64, seed=5, rmin=5, rmax=12, porosity=0.7)
+    prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=5e-6), rtol_u=1e-9, rtol_p=1e-9, rtol_c=1e-9)
+    out = []
+    for graphs in (0, 1):
+        _say(f"graph replay precision {precision} graphs {graphs}")
+        sim = gpu_sim(prob, precision, use_graphs=graphs, check_every=4)
+        sim.set_solid_fraction(es)
+        for _ in range(4):
+            sim.step(1e-3)
+        out.append({k: sim.get_numpy(k) for k in ("ux", "uy", "p", "c", "eps")})
+        sim.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
