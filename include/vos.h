@@ -100,6 +100,8 @@ typedef struct {
                        once and replay it (iteration counts then round up to a multiple of
                        check_every in the worst case; results are identical); 0: plain launches.
                        Ignored (off) when vos_create() is given the null stream. */
+  int coarse_cells; /* multigrid levels with at most this many cells run inside one single-block
+                       kernel (0: the default, 4096); 64..65536 */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */

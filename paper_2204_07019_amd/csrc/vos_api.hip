@@ -223,6 +223,7 @@ struct vos_sim {
   int timer_n;
   bool capturing;
   bool use_graphs;
+  int coarse_cells;         // levels at or below this size run in the single-block kernel
   hipGraphExec_t gexec[8];  // one captured iteration chunk per solve
   hipEvent_t *tev;      // 2 * TIMER_CAP events
   double timer_ms, timer_bytes;
@@ -338,6 +339,8 @@ vos_status check_opts(const vos_opts *o)
   if (o->precision != VOS_FP64 && o->precision != VOS_MIXED) return fail(VOS_ERR_ARG, "unknown precision");
   if (o->mg_nu < 1 || o->mg_nu > 8) return fail(VOS_ERR_ARG, "mg_nu must be in [1, 8]");
   if (o->check_every < 1 || o->check_every > 256) return fail(VOS_ERR_ARG, "check_every must be in [1, 256]");
+  if (o->coarse_cells != 0 && (o->coarse_cells < 64 || o->coarse_cells > 65536))
+    return fail(VOS_ERR_ARG, "coarse_cells must be 0 or in [64, 65536]");
   return VOS_OK;
 }
 
@@ -467,7 +470,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   const R om = (R)omega;
   const int nu = s->opt.mg_nu;
   int lc = 0;
-  while (lc < L - 1 && lv[lc].nc > (unsigned)VC_BLOCK_MAX) ++lc;
+  while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
   for (int l = 0; l < lc; ++l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
@@ -953,6 +956,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, "hipEventCreate failed"); }
   }
   s->capturing = false;
+  s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : VC_BLOCK_MAX;
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
   s->timer_family = VOS_TIMER_OFF;

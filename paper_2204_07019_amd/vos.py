@@ -48,7 +48,7 @@ class _Opts(C.Structure):
     _fields_ = [("rtol_u", C.c_double), ("rtol_p", C.c_double), ("rtol_c", C.c_double),
                 ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
                 ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int),
-                ("use_graphs", C.c_int)]
+                ("use_graphs", C.c_int), ("coarse_cells", C.c_int)]
 
 
 class _Diag(C.Structure):
@@ -123,6 +123,7 @@ class Opts:
     mg_nu: int = 2
     check_every: int = 8
     use_graphs: int = 1
+    coarse_cells: int = 0
 
 
 class Sim:
