@@ -80,8 +80,8 @@ LevelDims level_dims(int nx, int ny, int nz)
   return L;
 }
 
-// Hierarchy: halve every active dimension while all are even, stop once the
-// level has <= MG_COARSE_MAX cells.
+// Pressure hierarchy: ceil-halve every active dimension until the level has
+// <= MG_COARSE_MAX cells (the coarsest is then solved with its dense inverse).
 int mg_hierarchy(const vos_grid &g, LevelDims *out)
 {
   const int nd = g.nz == 1 ? 2 : 3;
@@ -91,10 +91,7 @@ int mg_hierarchy(const vos_grid &g, LevelDims *out)
   while (L < MG_MAX_LEVELS) {
     unsigned nc = (unsigned)n[0] * n[1] * n[2];
     if (nc <= (unsigned)MG_COARSE_MAX) break;
-    bool ok = true;
-    for (int d = 0; d < nd; ++d) ok = ok && (n[d] % 2 == 0) && n[d] >= 2;
-    if (!ok) break;
-    for (int d = 0; d < nd; ++d) n[d] /= 2;
+    for (int d = 0; d < nd; ++d) n[d] = (n[d] + 1) / 2;
     out[L++] = level_dims(n[0], n[1], n[2]);
   }
   return L;
@@ -178,7 +175,7 @@ Layout make_layout(const vos_grid &g, int precision)
   Lo.nlev = mg_hierarchy(g, lv);
   const size_t rs = precision == VOS_MIXED ? sizeof(float) : sizeof(double);
   for (int l = 0; l < Lo.nlev; ++l) {
-    for (int d = 0; d < 3; ++d) Lo.mgT[l][d] = (l == 0 && precision != VOS_MIXED) ? 0 : P.take(lv[l].nf[d] * rs);
+    for (int d = 0; d < 3; ++d) Lo.mgT[l][d] = P.take(lv[l].nf[d] * rs);
     Lo.mgdiag[l] = P.take(lv[l].nc * rs);
     Lo.mgx[l] = P.take(lv[l].nc * rs);
     Lo.mgb[l] = P.take(lv[l].nc * rs);
@@ -223,6 +220,7 @@ struct vos_sim {
   int timer_n;
   bool capturing;
   bool use_graphs;
+  double p_scale;           // global scale of the pressure hierarchy (set per step)
   int coarse_cells;         // levels at or below this size run in the single-block kernel
   hipGraphExec_t gexec[8];  // one captured iteration chunk per solve
   hipEvent_t *tev;      // 2 * TIMER_CAP events
@@ -259,10 +257,7 @@ void fill_levels(vos_sim *s, MgLevel<R> *lv)
       L.n[d] = ld[l].n[d];
       L.nf[d] = ld[l].nf[d];
       for (int e = 0; e < 3; ++e) L.fd[d][e] = ld[l].fd[d][e];
-      if (l == 0 && s->opt.precision != VOS_MIXED)
-        L.T[d] = (R *)s->T[d];
-      else
-        L.T[d] = (R *)(s->ws + s->lo.mgT[l][d]);
+      L.T[d] = (R *)(s->ws + s->lo.mgT[l][d]);
     }
     L.nc = ld[l].nc;
     L.diag = (R *)(s->ws + s->lo.mgdiag[l]);
@@ -463,7 +458,7 @@ void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv)
 // z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
 template <typename Lv, typename R>
 void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, double *z, const double *sc,
-            double omega)
+            double omega, const double *dsc, double rscale = 1.0)
 {
   hipStream_t st = s->stream;
   const int nd = s->g.nd;
@@ -477,25 +472,25 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     {
       TimedLaunch tl(s, VOS_TIMER_SMG_JACOBI, l == 0 ? jacobi_bytes<R>(F.nc, nd, false, l == 0) : 0.0, l == 0);
       if (nu == 1) {
-        if (l == 0) k_v_pre<Lv, R, true, 1><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
-        else k_v_pre<Lv, R, false, 1><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
+        if (l == 0) k_v_pre<Lv, R, true, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
+        else k_v_pre<Lv, R, false, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
       } else {
-        if (l == 0) k_v_pre<Lv, R, true, 2><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
-        else k_v_pre<Lv, R, false, 2><<<nb, TPB, 0, st>>>(F, nd, r, om, sc);
+        if (l == 0) k_v_pre<Lv, R, true, 2><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
+        else k_v_pre<Lv, R, false, 2><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
       }
     }
     for (int k = 2; k < nu; ++k) {
-      k_v_jacobi<Lv, R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
+      k_v_jacobi<Lv, R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, nullptr, sc);
       std::swap(F.x, F.t);
     }
     k_v_restrict<Lv, R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(F, lv[l + 1], nd, sc);
   }
   LevelPack<Lv> pack;
   for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
-  if (lc == 0) k_v_cast_in<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], r, sc);
+  if (lc == 0) k_v_cast_in<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], r, dsc, rscale, sc);
   k_v_coarse_cycle<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, nu, om, Ainv, sc);
   if (lc == 0) {
-    k_v_cast_out<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], z, sc);
+    k_v_cast_out<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], z, dsc, sc);
     return;
   }
   for (int l = lc - 1; l >= 0; --l) {
@@ -503,24 +498,26 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     const int nb = grid_blocks(F.nc);
     {
       const bool out = (l == 0 && nu == 1);
-      if (out) k_v_post<Lv, R, true><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, F.t, om, z, sc);
-      else k_v_post<Lv, R, false><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, F.t, om, nullptr, sc);
+      if (out) k_v_post<Lv, R, true><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, F.t, om, z, dsc, sc);
+      else k_v_post<Lv, R, false><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, F.t, om, nullptr, nullptr, sc);
       std::swap(F.x, F.t);
     }
     for (int k = 1; k < nu; ++k) {
       const bool last = (l == 0 && k == nu - 1);
       TimedLaunch tl(s, VOS_TIMER_SMG_JACOBI, jacobi_bytes<R>(F.nc, nd, last, l == 0), l == 0);
-      if (last) k_v_jacobi<Lv, R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, z, sc);
-      else k_v_jacobi<Lv, R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, sc);
+      if (last) k_v_jacobi<Lv, R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, z, dsc, sc);
+      else k_v_jacobi<Lv, R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, nullptr, sc);
       std::swap(F.x, F.t);
     }
   }
 }
 
+// dsc: diagonal of the symmetrically scaled operator (momentum), nullptr for
+// the row-scaled transport operator.
 template <typename R>
-void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc)
+void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, const double *dsc)
 {
-  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7);
+  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7, dsc);
 }
 
 // ---------------------------------------------------------------- stage S2
@@ -539,12 +536,12 @@ vos_status solve_momentum_t(vos_sim *s, SLevel<R> *lv, double dt, int *its, doub
   const double cvis = s->P.mu / (g.dx * g.dx);
   const double rt2 = s->opt.rtol_u * s->opt.rtol_u;
   k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x);
-  k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);
+  k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);   // Jacobi-scaled
   smg_coarsen_all<R>(s, D, lv);
   k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, s->part, zero_flag);
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 0, s->part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
-  smg_vcycle<R>(s, D, lv, r, z, sc);
+  smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D]);
   k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
   k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
   HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -556,7 +553,7 @@ vos_status solve_momentum_t(vos_sim *s, SLevel<R> *lv, double dt, int *its, doub
     k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 0, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
-    smg_vcycle<R>(s, D, lv, r, z, sc);
+    smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D]);
     k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
     k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
@@ -581,20 +578,26 @@ vos_status solve_momentum(vos_sim *s, double dt, int *its, double *res)
 
 // ---------------------------------------------------------------- stage S3
 
+// Fluid-face transmissibility S dt / (rho dx): the global scale of the pressure hierarchy.
+double pressure_scale(const vos_sim *s, double dt) { return s->g.S * dt / (s->P.rho * s->g.dx); }
+
 template <typename R>
 void mg_setup(vos_sim *s, MgLevel<R> *lv)
 {
   hipStream_t st = s->stream;
-  const int nd = s->g.nd;
-  if (s->opt.precision == VOS_MIXED)
-    for (int d = 0; d < nd; ++d)
-      k_mg_cast_faces<R><<<grid_blocks(lv[0].nf[d]), TPB, 0, st>>>(lv[0].nf[d], s->T[d], lv[0].T[d]);
+  const Dev &g = s->g;
+  const int nd = g.nd;
+  const double inv_s = 1.0 / s->p_scale;
+  k_mg_scaled_faces<R, 0><<<grid_blocks(g.nf[0]), TPB, 0, st>>>(g.nf[0], s->T[0], inv_s, lv[0]);
+  k_mg_scaled_faces<R, 1><<<grid_blocks(g.nf[1]), TPB, 0, st>>>(g.nf[1], s->T[1], inv_s, lv[0]);
+  if (nd == 3) k_mg_scaled_faces<R, 2><<<grid_blocks(g.nf[2]), TPB, 0, st>>>(g.nf[2], s->T[2], inv_s, lv[0]);
+  k_mg_diag<R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], nd);
   for (int l = 0; l + 1 < s->nlev; ++l) {
     k_mg_coarsen<R, 0><<<grid_blocks(lv[l + 1].nf[0]), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
     k_mg_coarsen<R, 1><<<grid_blocks(lv[l + 1].nf[1]), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
     if (nd == 3) k_mg_coarsen<R, 2><<<grid_blocks(lv[l + 1].nf[2]), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
+    k_mg_coarse_diag<R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
   }
-  for (int l = 0; l < s->nlev; ++l) k_mg_diag<R><<<grid_blocks(lv[l].nc), TPB, 0, st>>>(lv[l], nd);
   const MgLevel<R> &C = lv[s->nlev - 1];
   if (C.nc <= (unsigned)MG_COARSE_MAX) k_mg_coarse_inverse<R><<<1, TPB, 0, st>>>(C, nd, s->ainv);
 }
@@ -602,7 +605,9 @@ void mg_setup(vos_sim *s, MgLevel<R> *lv)
 template <typename R>
 void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const double *sc)
 {
-  vcycle<MgLevel<R>, R>(s, lv, s->nlev, s->ainv, r, z, sc, s->g.nd == 3 ? 6.0 / 7.0 : 0.8);
+  // A_R = A / p_scale, so z = A^-1 r is A_R^-1 (r / p_scale)
+  vcycle<MgLevel<R>, R>(s, lv, s->nlev, s->ainv, r, z, sc, s->g.nd == 3 ? 6.0 / 7.0 : 0.8, nullptr,
+                        1.0 / s->p_scale);
 }
 
 template <typename R>
@@ -691,7 +696,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, sc);
-    smg_vcycle<R>(s, H, lv, pv, ph, sc);
+    smg_vcycle<R>(s, H, lv, pv, ph, sc, nullptr);
     {
       TimedLaunch tl(s, VOS_TIMER_ADR_APPLY, (3.0 + 2 * g.nd) * 8.0 * n);
       k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
@@ -699,7 +704,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
-    smg_vcycle<R>(s, H, lv, sv, sh, sc);
+    smg_vcycle<R>(s, H, lv, sv, sh, sc, nullptr);
     {
       TimedLaunch tl(s, VOS_TIMER_ADR_APPLY, (3.0 + 2 * g.nd) * 8.0 * n);
       k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
@@ -793,6 +798,8 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   std::memset(dg, 0, sizeof(*dg));
   vos_status rc = VOS_OK, r2;
   HIP_TRY(hipEventRecord(s->ev[0], st));
+  const double ps = pressure_scale(s, dt);
+  if (ps != s->p_scale) { drop_graphs(s); s->p_scale = ps; }   // captured V-cycles hold 1/p_scale
   launch_coefficients(s, dt);
   HIP_TRY(hipEventRecord(s->ev[1], st));
   r2 = solve_momentum<0>(s, dt, &dg->it_u[0], &dg->res_u[0]);
@@ -956,6 +963,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, "hipEventCreate failed"); }
   }
   s->capturing = false;
+  s->p_scale = 0.0;
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : VC_BLOCK_MAX;
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;

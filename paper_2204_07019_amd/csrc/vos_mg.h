@@ -55,13 +55,7 @@ __device__ __forceinline__ R mg_apply_cell(const MgLevel<R> &L, int nd, const R 
   return v;
 }
 
-// Level-0 transmissibilities in R and the diagonal (sum of face T).
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_mg_cast_faces(unsigned n, const double *__restrict__ src, R *__restrict__ dst)
-{
-  for (unsigned i = gtid(); i < n; i += gstride()) dst[i] = (R)src[i];
-}
-
+// Level-0 diagonal: the sum of the cell's face transmissibilities (outlet included).
 template <typename R>
 __global__ void __launch_bounds__(TPB) k_mg_diag(MgLevel<R> L, int nd)
 {
@@ -79,7 +73,55 @@ __global__ void __launch_bounds__(TPB) k_mg_diag(MgLevel<R> L, int nd)
   }
 }
 
-// Coarse face transmissibilities of direction D from the fine level.
+// Level 0 of the pressure hierarchy: T / s on every face (the outlet's
+// Dirichlet face included), with one global scale s = the transmissibility of a
+// fluid face (S dt / (rho dx)).  Raw coefficients span ~1e-30 (solid) to
+// ~1e-13 (fluid); scaled, FP32 holds them and the residuals comfortably.  The
+// scale is uniform so that piecewise-constant prolongation still acts on the
+// unscaled pressure, which is continuous across the fluid-solid interface.
+template <typename R, int D>
+__global__ void __launch_bounds__(TPB) k_mg_scaled_faces(unsigned nf, const double *__restrict__ T, double inv_s,
+                                                         MgLevel<R> L)
+{
+  for (unsigned f = gtid(); f < nf; f += gstride()) L.T[D][f] = (R)(T[f] * inv_s);
+}
+
+// Coarse diagonal, consistent with the coarse faces: the Galerkin diagonal of
+// the aggregate times the rediscretisation factor 1/2,
+// d_I = 1/2 [ sum_{c in I} d_c - 2 sum_{faces inside I} T ] = sum of the coarse faces' T.
+template <typename R>
+__global__ void __launch_bounds__(TPB) k_mg_coarse_diag(MgLevel<R> F, MgLevel<R> Cc, int nd)
+{
+  for (unsigned I = gtid(); I < Cc.nc; I += gstride()) {
+    int X[3];
+    unflat(Cc.n, I, X);
+    R s = 0;
+    const int lz = nd == 3 ? 2 : 1;
+    for (int cz = 0; cz < lz; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const int c[3] = {2 * X[0] + cx, 2 * X[1] + cy, nd == 3 ? 2 * X[2] + cz : 0};
+          if ((F.n[0] == 1 && cx) || (F.n[1] == 1 && cy) || (cz && !(nd == 3 && F.n[2] > 1))) continue;
+          if (c[0] >= F.n[0] || c[1] >= F.n[1] || c[2] >= F.n[2]) continue;
+          const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * (unsigned)c[2]);
+          s += F.diag[id];
+          // faces between this child and the next child of the same aggregate
+          for (int d = 0; d < nd; ++d) {
+            if (F.n[d] == 1 || (c[d] & 1) || c[d] + 1 >= F.n[d]) continue;
+            int f[3] = {c[0], c[1], c[2]};
+            f[d] += 1;
+            const unsigned fi =
+                (unsigned)f[0] + (unsigned)F.fd[d][0] * ((unsigned)f[1] + (unsigned)F.fd[d][1] * (unsigned)f[2]);
+            s -= (R)2 * F.T[d][fi];
+          }
+        }
+    Cc.diag[I] = (R)0.5 * s;
+  }
+}
+
+// Coarse face transmissibilities of direction D from the fine level
+// (ceil aggregation: the boundary face of an odd-sized level maps to the
+// fine boundary face).
 template <typename R, int D>
 __global__ void __launch_bounds__(TPB) k_mg_coarsen(MgLevel<R> F, MgLevel<R> Cc, int nd)
 {
@@ -87,15 +129,17 @@ __global__ void __launch_bounds__(TPB) k_mg_coarsen(MgLevel<R> F, MgLevel<R> Cc,
     int X[3];
     unflat(Cc.fd[D], f, X);
     int x0[3];
-    for (int e = 0; e < 3; ++e) x0[e] = (e < nd) ? 2 * X[e] : 0;
+    for (int e = 0; e < 3; ++e) x0[e] = (e < nd && F.n[e] > 1) ? 2 * X[e] : X[e];
+    if (x0[D] > F.n[D]) x0[D] = F.n[D];
     R s = 0;
-    const int c1 = (1 < nd && D != 1) ? 2 : 1;
-    const int c2 = (2 < nd && D != 2) ? 2 : 1;
-    const int c0 = (D != 0) ? 2 : 1;
+    const int c1 = (1 < nd && D != 1 && F.n[1] > 1) ? 2 : 1;
+    const int c2 = (2 < nd && D != 2 && F.n[2] > 1) ? 2 : 1;
+    const int c0 = (D != 0 && F.n[0] > 1) ? 2 : 1;
     for (int a = 0; a < c0; ++a)
       for (int bq = 0; bq < c1; ++bq)
         for (int cq = 0; cq < c2; ++cq) {
           const int i = x0[0] + a, j = x0[1] + bq, k = x0[2] + cq;
+          if ((D != 0 && i >= F.n[0]) || (D != 1 && j >= F.n[1]) || (D != 2 && k >= F.n[2])) continue;
           s += F.T[D][(unsigned)i + (unsigned)F.fd[D][0] * ((unsigned)j + (unsigned)F.fd[D][1] * (unsigned)k)];
         }
     Cc.T[D][f] = (R)0.5 * s;

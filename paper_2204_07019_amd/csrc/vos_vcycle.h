@@ -86,15 +86,20 @@ __device__ __forceinline__ R lv_off(const MgLevel<R> &L, unsigned id, const int 
 
 // ------------------------------------------------------------------ fine-level kernels
 
-// Pre-smoothing, sweeps 1 and 2 fused.  FROM64: b = (R) r (level 0 input).
+// Pre-smoothing, sweeps 1 and 2 fused.  FROM64: b = (R)(rscale r / sqrt(dsc)) on
+// level 0 (dsc = diagonal of a symmetrically scaled operator, or nullptr;
+// rscale = 1 / the global scale of an operator scaled by a constant).
 // NSW = 1: only x = w b / d;  NSW = 2: x = x1 + w (b - A x1) / d with x1 = w b / d.
 template <typename Lv, typename R, bool FROM64, int NSW>
-__global__ void __launch_bounds__(TPB) k_v_pre(Lv L, int nd, const double *__restrict__ r64, R omega,
+__global__ void __launch_bounds__(TPB) k_v_pre(Lv L, int nd, const double *__restrict__ r64,
+                                               const double *__restrict__ dsc, double rscale, R omega,
                                                const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   for (unsigned id = gtid(); id < L.nc; id += gstride()) {
-    const R bb = FROM64 ? (R)r64[id] : L.b[id];
+    R bb;
+    if (FROM64) bb = (R)(rscale * (dsc ? r64[id] / sqrt(dsc[id]) : r64[id]));
+    else bb = L.b[id];
     if (FROM64) L.b[id] = bb;
     const R dg = L.diag[id];
     const R x1 = omega * bb / dg;
@@ -103,17 +108,26 @@ __global__ void __launch_bounds__(TPB) k_v_pre(Lv L, int nd, const double *__res
     unflat(L.n, id, c);
     R ax = dg * x1;
     for_neighbours(L.n, nd, id, c, [&](unsigned nid, int k) {
-      const R bn = FROM64 ? (R)r64[nid] : L.b[nid];
+      R bn;
+      if (FROM64) bn = (R)(rscale * (dsc ? r64[nid] / sqrt(dsc[nid]) : r64[nid]));
+      else bn = L.b[nid];
       ax += lv_off(L, id, c, k) * (omega * bn / L.diag[nid]);
     });
     L.x[id] = x1 + omega * (bb - ax) / dg;
   }
 }
 
+// FP64 output of level 0: z = x / sqrt(dsc) (or x when dsc is nullptr).
+__device__ __forceinline__ double unscale(double v, const double *dsc, unsigned id)
+{
+  return dsc ? v / sqrt(dsc[id]) : v;
+}
+
 // One damped-Jacobi sweep xo = x + w (b - A x)/d; OUT64 also writes the FP64 result.
 template <typename Lv, typename R, bool OUT64>
 __global__ void __launch_bounds__(TPB) k_v_jacobi(Lv L, int nd, const R *__restrict__ x, R *__restrict__ xo, R omega,
-                                                  double *__restrict__ z, const double *__restrict__ sc)
+                                                  double *__restrict__ z, const double *__restrict__ dsc,
+                                                  const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   for (unsigned id = gtid(); id < L.nc; id += gstride()) {
@@ -121,7 +135,7 @@ __global__ void __launch_bounds__(TPB) k_v_jacobi(Lv L, int nd, const R *__restr
     unflat(L.n, id, c);
     const R v = x[id] + omega * (L.b[id] - lv_apply(L, nd, x, id, c)) / L.diag[id];
     xo[id] = v;
-    if (OUT64) z[id] = (double)v;
+    if (OUT64) z[id] = unscale((double)v, dsc, id);
   }
 }
 
@@ -159,7 +173,8 @@ __global__ void __launch_bounds__(TPB) k_v_restrict(Lv F, Lv C, int nd, const do
 // xo = y + w (b - A y)/d (neighbour values of y formed on the fly).
 template <typename Lv, typename R, bool OUT64>
 __global__ void __launch_bounds__(TPB) k_v_post(Lv F, Lv C, int nd, R *__restrict__ xo, R omega,
-                                                double *__restrict__ z, const double *__restrict__ sc)
+                                                double *__restrict__ z, const double *__restrict__ dsc,
+                                                const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   for (unsigned id = gtid(); id < F.nc; id += gstride()) {
@@ -177,7 +192,7 @@ __global__ void __launch_bounds__(TPB) k_v_post(Lv F, Lv C, int nd, R *__restric
     });
     const R v = y + omega * (F.b[id] - ay) / dg;
     xo[id] = v;
-    if (OUT64) z[id] = (double)v;
+    if (OUT64) z[id] = unscale((double)v, dsc, id);
   }
 }
 
@@ -274,18 +289,21 @@ __global__ void __launch_bounds__(VC_COARSE_TPB) k_v_coarse_cycle(LevelPack<Lv> 
 
 // b = (R) r (level-0 input when the whole cycle runs in the single block).
 template <typename Lv, typename R>
-__global__ void __launch_bounds__(TPB) k_v_cast_in(Lv L, const double *__restrict__ r, const double *__restrict__ sc)
+__global__ void __launch_bounds__(TPB) k_v_cast_in(Lv L, const double *__restrict__ r, const double *__restrict__ dsc,
+                                                   double rscale, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) L.b[id] = (R)r[id];
+  for (unsigned id = gtid(); id < L.nc; id += gstride())
+    L.b[id] = (R)(rscale * (dsc ? r[id] / sqrt(dsc[id]) : r[id]));
 }
 
 // z = (double) x
 template <typename Lv, typename R>
-__global__ void __launch_bounds__(TPB) k_v_cast_out(Lv L, double *__restrict__ z, const double *__restrict__ sc)
+__global__ void __launch_bounds__(TPB) k_v_cast_out(Lv L, double *__restrict__ z, const double *__restrict__ dsc,
+                                                    const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) z[id] = (double)L.x[id];
+  for (unsigned id = gtid(); id < L.nc; id += gstride()) z[id] = unscale((double)L.x[id], dsc, id);
 }
 
 }  // namespace vos
