@@ -67,12 +67,10 @@ def setup_sim(vos, inputs, scaling, workload, pe, da, precision, model, dt, rela
     return sim, es, dict(params, u_in=u_in, kc=kc), dict(K=K, phi=phi, u_in=u_in, kc=kc, ndim=ndim)
 
 
-def timed_steps(sim, dt, steps, warmup, timer_family=None):
+def timed_steps(sim, dt, steps, warmup):
     import torch
     for _ in range(warmup):
         sim.step(dt)
-    if timer_family:
-        sim.kernel_timer(timer_family)
     diags = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -80,10 +78,44 @@ def timed_steps(sim, dt, steps, warmup, timer_family=None):
         diags.append(sim.step(dt))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    tk = sim.kernel_timer_read() if timer_family else None
-    if timer_family:
-        sim.kernel_timer("off")
-    return el, diags, tk
+    return el, diags
+
+
+def roofline(sim, family, reps=200):
+    """Live roofline of one kernel family: back-to-back launches on the
+    state the timed steps left, between two HIP events on the sim's stream."""
+    t = sim.time_kernel(family, reps)
+    achieved = t["bytes"] / (t["avg_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": family,
+            "avg_launch_us": round(t["avg_ms"] * 1e3, 3), "bytes_per_launch": round(t["bytes"])}
+
+
+def pressure_3d(vos, inputs, n, dt):
+    """The pressure solve on the 256^3 sphere pack (dx = 4 um, seed 33), FP64
+    multigrid, from a flow relaxed by two steps: algorithmic GB/s of the
+    pressure stage and the live roofline of the pressure operator."""
+    import torch
+    es = inputs.sphere_pack(n, seed=33)
+    prm = dict(inputs.BASE_PARAMS, dx=4e-6, model=0)
+    sim = vos.Sim(n, n, n, prm["dx"], dict(prm, kc=0.0),
+                  vos.Opts(precision=vos.FP64, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000))
+    sim.set_solid_fraction(es)
+    for _ in range(2):
+        sim.step(dt, 1, freeze_solid=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = sim.step(dt, 1, freeze_solid=True)
+    el = time.perf_counter() - t0
+    cells = n ** 3
+    t_p = d["t_ms"][2] * 1e-3
+    pb = cells * (P_ITER_BYTES[("fp64", 3)] * d["it_p"] + P_SETUP_BYTES[3])
+    out = {"workload": f"pack {n}^3 dx=4um porosity 0.23 seed 33, FP64 multigrid, rtol 1e-8",
+           "its": d["it_p"], "pressure_ms": round(d["t_ms"][2], 2), "step_ms": round(el * 1e3, 1),
+           "GBs_algorithmic": round(pb / t_p / 1e9, 1), "frac_hbm": round(pb / t_p / 1e9 / HBM_PEAK_GBS, 4),
+           "p_apply_roofline": roofline(sim, "p_apply")}
+    sim.close()
+    return out
 
 
 def cpu_baseline(workload, params, dt, budget_s):
@@ -126,7 +158,9 @@ def main():
     ap.add_argument("--model", type=int, default=0)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--relax", type=int, default=40)
-    ap.add_argument("--timer", default="smg_jacobi", help="kernel family for the live roofline")
+    ap.add_argument("--timer", default="v_restrict", help="kernel family for the live roofline")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D pressure-solve measurement")
+    ap.add_argument("--n3d", type=int, default=256)
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -151,7 +185,7 @@ def main():
     cells = nx * ny * nz
     log(f"K={info['K']:.3e} phi={info['phi']:.3f} u_in={info['u_in']:.3e} kc={info['kc']:.3e}")
 
-    el, diags, tk = timed_steps(sim, args.dt, args.steps, args.warmup, timer_family=args.timer)
+    el, diags = timed_steps(sim, args.dt, args.steps, args.warmup)
     value = cells * args.steps / el
     ms_step = el / args.steps * 1e3
     log(f"mixed: {ms_step:.2f} ms/step, {value:.3e} cell-steps/s")
@@ -169,7 +203,7 @@ def main():
                         vos.Opts(precision=vos.FP64, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=8))
         for k in ("eps", "ux", "uy", "uz", "p", "c"):
             sim64.set(k, sim.get(k))
-        el64, d64, _ = timed_steps(sim64, args.dt, args.steps, args.warmup)
+        el64, d64 = timed_steps(sim64, args.dt, args.steps, args.warmup)
         its64 = sum(d["it_p"] for d in d64)
         t64 = sum(d["t_ms"][2] for d in d64) * 1e-3
         pb64 = cells * (P_ITER_BYTES[("fp64", nd)] * its64 + P_SETUP_BYTES[nd] * len(d64))
@@ -178,15 +212,9 @@ def main():
         log(f"fp64: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} cell-steps/s")
         sim64.close()
 
-    roof = None
-    if tk and tk["launches"] > 0:
-        avg_ms = tk["total_ms"] / tk["launches"]
-        avg_bytes = tk["bytes"] / tk["launches"]
-        achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"{args.timer} (all levels)", "launches": tk["launches"],
-                "avg_launch_us": round(avg_ms * 1e3, 3), "avg_bytes_per_launch": round(avg_bytes)}
+    roof = roofline(sim, args.timer)
+    others = {k: roofline(sim, k) for k in ("v_post", "v_pre", "p_apply", "adr_apply")}
+    p3d = None if args.no_3d else pressure_3d(vos, inputs, args.n3d, args.dt)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -216,6 +244,8 @@ def main():
         "iterations": {"u": last["it_u"], "p": last["it_p"], "c": last["it_c"]},
         "plain_fp64": plain,
         "roofline": roof,
+        "roofline_other_kernels": others,
+        "pressure_solve_3d": p3d,
         "cpu_baseline": cpu,
     }
     sim.close()

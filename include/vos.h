@@ -190,25 +190,23 @@ vos_status vos_step(vos_sim *sim, double dt, int nsteps, int flags, vos_diag *la
  * and balances are those of the last step). */
 vos_status vos_diagnostics(vos_sim *sim, vos_diag *out);
 
-/* Kernel families that vos_kernel_timer can time. */
+/* Kernel families for vos_time_kernel. */
 typedef enum {
-  VOS_TIMER_OFF = -1,
-  VOS_TIMER_SMG_JACOBI = 0,   /* Jacobi sweeps of the momentum / transport multigrid */
-  VOS_TIMER_MG_JACOBI = 1,    /* Jacobi sweeps of the pressure multigrid */
-  VOS_TIMER_ADR_APPLY = 2,    /* transport operator applications */
-  VOS_TIMER_P_APPLY = 3,      /* pressure operator applications */
-  VOS_TIMER_MOM_APPLY = 4     /* momentum operator applications */
-} vos_timer_family;
+  VOS_KERNEL_V_RESTRICT = 0,  /* residual restriction, every fine level of the transport hierarchy */
+  VOS_KERNEL_V_POST = 1,      /* prolongation + first post-smoothing sweep, same levels */
+  VOS_KERNEL_V_PRE = 2,       /* first two pre-smoothing sweeps, same levels */
+  VOS_KERNEL_V_COARSE = 3,    /* the single-block coarse tail of the transport V-cycle */
+  VOS_KERNEL_P_APPLY = 4,     /* pressure operator application (FP64) */
+  VOS_KERNEL_ADR_APPLY = 5    /* transport operator application (FP64) */
+} vos_kernel_family;
 
-/* Time every launch of one kernel family with a HIP event pair on the
- * simulation's stream (VOS_TIMER_OFF stops timing) and reset the totals.
- * Timing adds two event records per launch of that family only. */
-vos_status vos_kernel_timer(vos_sim *sim, int family);
-
-/* Totals since vos_kernel_timer(): summed launch durations [ms], number of
- * timed launches, and the algorithmic bytes those launches move (each array
- * read or written once per launch; neighbour re-reads are not counted). */
-vos_status vos_kernel_timer_read(vos_sim *sim, double *total_ms, long long *launches, double *bytes);
+/* Time `reps` back-to-back launch sequences of one kernel family on the live
+ * state (after at least one vos_step), between two HIP events on the
+ * simulation's stream.  A sequence is one launch per level for the V-cycle
+ * families, else one launch.  Outputs: average duration of one launch [ms]
+ * and its algorithmic bytes (every array read or written once per launch,
+ * neighbour re-reads not counted).  The kernels write only scratch buffers. */
+vos_status vos_time_kernel(vos_sim *sim, int family, int reps, double *avg_launch_ms, double *bytes_per_launch);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *vos_last_error(void);

@@ -53,10 +53,13 @@ struct Plan {
   }
 };
 
+// Blocks of a sweep over n items: one item per thread up to MAXB blocks,
+// rounded up to a multiple of the 8 XCDs (XCD-aware ranges, vos_device.h).
 int grid_blocks(size_t n)
 {
   size_t b = (n + TPB - 1) / TPB;
   if (b < 1) b = 1;
+  if (b >= NXCD) b = (b + NXCD - 1) / NXCD * NXCD;
   if (b > (size_t)MAXB) b = MAXB;
   return (int)b;
 }
@@ -215,32 +218,18 @@ struct vos_sim {
   double *sainv[NSMG];
   double *host;       // pinned scalar read-back buffer
   hipEvent_t ev[7];
-  // kernel-family timer: event pairs around each launch of one family
-  int timer_family;
-  int timer_n;
   bool capturing;
   bool use_graphs;
   double p_scale;           // global scale of the pressure hierarchy (set per step)
   int coarse_cells;         // levels at or below this size run in the single-block kernel
   hipGraphExec_t gexec[8];  // one captured iteration chunk per solve
-  hipEvent_t *tev;      // 2 * TIMER_CAP events
-  double timer_ms, timer_bytes;
-  long long timer_launches;
+
   bool have_geometry;
+  bool stepped;             // a step has run: the hierarchies hold live data
   vos_diag last;
 };
 
 namespace {
-
-constexpr int TIMER_CAP = 8192;
-
-// Wrap a launch of kernel family `fam` moving `bytes` algorithmic bytes.
-struct TimedLaunch {
-  vos_sim *s;
-  bool on;
-  TimedLaunch(vos_sim *s_, int fam, double bytes, bool enabled = true);
-  ~TimedLaunch();
-};
 
 double *sc_block(vos_sim *s, int k) { return s->scal + (size_t)k * S_COUNT * 2; }
 enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6 };
@@ -283,37 +272,6 @@ void fill_smg(vos_sim *s, int h, SLevel<R> *lv)
     L.t = (R *)(s->ws + S.t[l]);
   }
   if (S.nlev) s->sainv[h] = (double *)(s->ws + S.ainv);
-}
-
-TimedLaunch::TimedLaunch(vos_sim *s_, int fam, double bytes, bool enabled) : s(s_), on(false)
-{
-  if (enabled && !s->capturing && s->timer_family == fam && s->timer_n < TIMER_CAP) {
-    on = (hipEventRecord(s->tev[2 * s->timer_n], s->stream) == hipSuccess);
-    if (on) s->timer_bytes += bytes;
-  }
-}
-
-TimedLaunch::~TimedLaunch()
-{
-  if (on) {
-    (void)hipEventRecord(s->tev[2 * s->timer_n + 1], s->stream);
-    ++s->timer_n;
-  }
-}
-
-// Fold the recorded event pairs into the totals (synchronises the stream).
-vos_status timer_flush(vos_sim *s)
-{
-  if (s->timer_n == 0) return VOS_OK;
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  for (int k = 0; k < s->timer_n; ++k) {
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, s->tev[2 * k], s->tev[2 * k + 1]));
-    s->timer_ms += ms;
-  }
-  s->timer_launches += s->timer_n;
-  s->timer_n = 0;
-  return VOS_OK;
 }
 
 vos_status check_grid(const vos_grid *g)
@@ -470,7 +428,6 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
     {
-      TimedLaunch tl(s, VOS_TIMER_SMG_JACOBI, l == 0 ? jacobi_bytes<R>(F.nc, nd, false, l == 0) : 0.0, l == 0);
       if (nu == 1) {
         if (l == 0) k_v_pre<Lv, R, true, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
         else k_v_pre<Lv, R, false, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
@@ -504,7 +461,6 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     }
     for (int k = 1; k < nu; ++k) {
       const bool last = (l == 0 && k == nu - 1);
-      TimedLaunch tl(s, VOS_TIMER_SMG_JACOBI, jacobi_bytes<R>(F.nc, nd, last, l == 0), l == 0);
       if (last) k_v_jacobi<Lv, R, true><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, z, dsc, sc);
       else k_v_jacobi<Lv, R, false><<<nb, TPB, 0, st>>>(F, nd, F.x, F.t, om, nullptr, nullptr, sc);
       std::swap(F.x, F.t);
@@ -546,10 +502,7 @@ vos_status solve_momentum_t(vos_sim *s, SLevel<R> *lv, double dt, int *its, doub
   k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
   HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
-    {
-      TimedLaunch tl(s, VOS_TIMER_MOM_APPLY, 24.0 * n);
-      k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, s->part, sc);
-    }
+    k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 0, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
@@ -632,10 +585,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
   HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
-    {
-      TimedLaunch tl(s, VOS_TIMER_P_APPLY, (2.0 + g.nd) * 8.0 * n);
-      k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], pv, q, s->part, sc);
-    }
+    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], pv, q, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->pdiag, s->p, r, z, 0, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
@@ -697,18 +647,12 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, sc);
     smg_vcycle<R>(s, H, lv, pv, ph, sc, nullptr);
-    {
-      TimedLaunch tl(s, VOS_TIMER_ADR_APPLY, (3.0 + 2 * g.nd) * 8.0 * n);
-      k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
-    }
+    k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
     smg_vcycle<R>(s, H, lv, sv, sh, sc, nullptr);
-    {
-      TimedLaunch tl(s, VOS_TIMER_ADR_APPLY, (3.0 + 2 * g.nd) * 8.0 * n);
-      k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
-    }
+    k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
     k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, rh, s->c, r, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
@@ -829,8 +773,6 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   HIP_TRY(hipGetLastError());
   r2 = fill_diag(s, dt, dg);
   if (r2) return r2;
-  r2 = timer_flush(s);
-  if (r2) return r2;
   for (int k = 0; k < 6; ++k) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
@@ -866,7 +808,7 @@ double *field_ptr(vos_sim *s, int field, size_t *n, bool *writable)
 __global__ void k_set_eps(unsigned n, const double *__restrict__ es, double eps_min, double *__restrict__ eps,
                           int *__restrict__ bad)
 {
-  for (unsigned i = gtid(); i < n; i += gstride()) {
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double v = es[i];
     if (!(v >= 0.0 && v <= 1.0)) bad[0] = 1;
     double e = 1.0 - v;
@@ -877,14 +819,90 @@ __global__ void k_set_eps(unsigned n, const double *__restrict__ es, double eps_
 
 __global__ void k_fill(unsigned n, double v, double *__restrict__ a)
 {
-  for (unsigned i = gtid(); i < n; i += gstride()) a[i] = v;
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) a[i] = v;
 }
 
 // Inlet faces (i = 0) of the x grid get u_in.
 __global__ void k_inlet(Dev g, double u_in, double *__restrict__ ux)
 {
   const unsigned n = (unsigned)g.n[1] * g.n[2];
-  for (unsigned t = gtid(); t < n; t += gstride()) ux[t * (unsigned)g.fd[0][0]] = u_in;
+  for (unsigned t = xbeg(n); t < xend(n); t += xstride()) ux[t * (unsigned)g.fd[0][0]] = u_in;
+}
+
+// Back-to-back launches of one kernel family on the live state, between two
+// events; *ms = average per launch.  The transport hierarchy (h = 3) stands for
+// the V-cycle families; its buffers and the Krylov scratch vectors are only
+// overwritten with values no later step reads.
+template <typename R>
+vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double *ms, double *bytes)
+{
+  hipStream_t st = s->stream;
+  const Dev &g = s->g;
+  const int nd = g.nd;
+  const int L = s->snlev[3];
+  int lc = 0;
+  while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
+  const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
+  const R om = (R)0.7;
+  const double Rs = sizeof(R);
+  double per_seq_bytes = 0.0;
+  int per_seq_launches = 0;
+  auto seq = [&](bool count) {
+    switch (family) {
+      case VOS_KERNEL_V_RESTRICT:
+        for (int l = 0; l < lc; ++l) {
+          k_v_restrict<SLevel<R>, R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd, flag);
+          if (count) { per_seq_bytes += (3.0 + 2 * nd) * Rs * lv[l].nc + Rs * lv[l + 1].nc; ++per_seq_launches; }
+        }
+        break;
+      case VOS_KERNEL_V_POST:
+        for (int l = 0; l < lc; ++l) {
+          k_v_post<SLevel<R>, R, false><<<grid_blocks(lv[l].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd, lv[l].t, om,
+                                                                               nullptr, nullptr, flag);
+          if (count) { per_seq_bytes += (4.0 + 2 * nd) * Rs * lv[l].nc + Rs * lv[l + 1].nc; ++per_seq_launches; }
+        }
+        break;
+      case VOS_KERNEL_V_PRE:
+        for (int l = 1; l < lc; ++l) {
+          k_v_pre<SLevel<R>, R, false, 2><<<grid_blocks(lv[l].nc), TPB, 0, st>>>(lv[l], nd, nullptr, nullptr, 1.0,
+                                                                                 om, flag);
+          if (count) { per_seq_bytes += (3.0 + 2 * nd) * Rs * lv[l].nc; ++per_seq_launches; }
+        }
+        break;
+      case VOS_KERNEL_V_COARSE: {
+        LevelPack<SLevel<R>> pack;
+        for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
+        k_v_coarse_cycle<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, s->opt.mg_nu, om, s->sainv[3],
+                                                                    flag);
+        if (count) {
+          for (int l = lc; l < L; ++l) per_seq_bytes += (5.0 + 2 * nd) * Rs * lv[l].nc;
+          ++per_seq_launches;
+        }
+        break;
+      }
+      case VOS_KERNEL_P_APPLY:
+        k_p_apply<<<grid_blocks(g.nc), TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, s->vec[4], s->part, flag);
+        if (count) { per_seq_bytes += (2.0 + nd) * 8.0 * g.nc; ++per_seq_launches; }
+        break;
+      case VOS_KERNEL_ADR_APPLY:
+        k_adr_apply<1><<<grid_blocks(g.nc), TPB, 0, st>>>(g, s->off, s->c, s->vec[7], s->c, s->part, flag);
+        if (count) { per_seq_bytes += (3.0 + 2 * nd) * 8.0 * g.nc; ++per_seq_launches; }
+        break;
+    }
+  };
+  if (family < VOS_KERNEL_V_RESTRICT || family > VOS_KERNEL_ADR_APPLY) return fail(VOS_ERR_ARG, "unknown kernel family");
+  seq(true);   // warm-up, counts the launches of one sequence
+  if (per_seq_launches == 0) return fail(VOS_ERR_STATE, "the hierarchy has no level of that kind");
+  HIP_TRY(hipEventRecord(s->ev[0], st));
+  for (int k = 0; k < reps; ++k) seq(false);
+  HIP_TRY(hipEventRecord(s->ev[1], st));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventSynchronize(s->ev[1]));
+  float el = 0.f;
+  HIP_TRY(hipEventElapsedTime(&el, s->ev[0], s->ev[1]));
+  *ms = (double)el / ((double)reps * per_seq_launches);
+  *bytes = per_seq_bytes / per_seq_launches;
+  return VOS_OK;
 }
 
 }  // namespace
@@ -955,6 +973,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     fill_smg<double>(s, h, s->smgd[h]);
   }
   s->have_geometry = false;
+  s->stepped = false;
   std::memset(&s->last, 0, sizeof(s->last));
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
@@ -967,11 +986,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : VC_BLOCK_MAX;
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
-  s->timer_family = VOS_TIMER_OFF;
-  s->timer_n = 0;
-  s->timer_ms = s->timer_bytes = 0.0;
-  s->timer_launches = 0;
-  s->tev = nullptr;
+
   // initial state: fluid at rest, p = p_out, c = 0, eps = 1
   hipStream_t stq = s->stream;
   HIP_TRY(hipMemsetAsync(s->ws, 0, lo.total, stq));
@@ -990,10 +1005,7 @@ vos_status vos_destroy(vos_sim *s)
   (void)hipStreamSynchronize(s->stream);
   drop_graphs(s);
   for (int k = 0; k < 7; ++k) (void)hipEventDestroy(s->ev[k]);
-  if (s->tev) {
-    for (int k = 0; k < 2 * TIMER_CAP; ++k) (void)hipEventDestroy(s->tev[k]);
-    delete[] s->tev;
-  }
+
   (void)hipHostFree(s->host);
   delete s;
   return VOS_OK;
@@ -1087,6 +1099,7 @@ vos_status vos_step(vos_sim *s, double dt, int nsteps, int flags, vos_diag *last
   for (int k = 0; k < nsteps; ++k) {
     vos_status st = one_step(s, dt, flags, &dg);
     s->last = dg;
+    s->stepped = true;
     if (st) {
       if (last) *last = dg;
       return st;
@@ -1096,32 +1109,13 @@ vos_status vos_step(vos_sim *s, double dt, int nsteps, int flags, vos_diag *last
   return VOS_OK;
 }
 
-vos_status vos_kernel_timer(vos_sim *s, int family)
+vos_status vos_time_kernel(vos_sim *s, int family, int reps, double *avg_launch_ms, double *bytes_per_launch)
 {
-  if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
-  if (family < VOS_TIMER_OFF || family > VOS_TIMER_MOM_APPLY) return fail(VOS_ERR_ARG, "unknown kernel family");
-  vos_status st = timer_flush(s);
-  if (st) return st;
-  if (family != VOS_TIMER_OFF && !s->tev) {
-    s->tev = new (std::nothrow) hipEvent_t[2 * TIMER_CAP];
-    if (!s->tev) return fail(VOS_ERR_OOM, "host allocation failed");
-    for (int k = 0; k < 2 * TIMER_CAP; ++k) HIP_TRY(hipEventCreate(&s->tev[k]));
-  }
-  s->timer_family = family;
-  s->timer_ms = s->timer_bytes = 0.0;
-  s->timer_launches = 0;
-  return VOS_OK;
-}
-
-vos_status vos_kernel_timer_read(vos_sim *s, double *total_ms, long long *launches, double *bytes)
-{
-  if (!s || !total_ms || !launches || !bytes) return fail(VOS_ERR_ARG, "NULL argument");
-  vos_status st = timer_flush(s);
-  if (st) return st;
-  *total_ms = s->timer_ms;
-  *launches = s->timer_launches;
-  *bytes = s->timer_bytes;
-  return VOS_OK;
+  if (!s || !avg_launch_ms || !bytes_per_launch) return fail(VOS_ERR_ARG, "NULL argument");
+  if (reps < 1 || reps > 100000) return fail(VOS_ERR_ARG, "reps must be in [1, 100000]");
+  if (!s->stepped) return fail(VOS_ERR_STATE, "run vos_step first");
+  if (s->opt.precision == VOS_MIXED) return time_kernel_t<float>(s, s->smgf[3], family, reps, avg_launch_ms, bytes_per_launch);
+  return time_kernel_t<double>(s, s->smgd[3], family, reps, avg_launch_ms, bytes_per_launch);
 }
 
 vos_status vos_diagnostics(vos_sim *s, vos_diag *out)

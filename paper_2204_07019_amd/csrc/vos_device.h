@@ -8,7 +8,7 @@
 namespace vos {
 
 constexpr int TPB = 256;         // threads per block of every sweep (4 wave64s)
-constexpr int MAXB = 1024;       // blocks of a grid-stride sweep == partial-sum slots per quantity
+constexpr int MAXB = 4096;       // blocks of a grid-stride sweep == partial-sum slots per quantity
 constexpr int NSLOT = 16;        // partial-sum quantities one sweep may produce
 
 struct Dev {
@@ -27,6 +27,28 @@ struct Phys {
 
 __device__ __forceinline__ unsigned gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ unsigned gstride() { return gridDim.x * blockDim.x; }
+
+// XCD-aware sweep ranges.  Workgroups are dispatched round-robin over the 8
+// XCDs (block b runs on XCD b % 8), each with its own L2.  With a plain
+// grid-stride loop the y/z neighbours of a block's cells belong to blocks on
+// other XCDs and are fetched again from the Infinity Cache / HBM by every XCD.
+// Instead the blocks of XCD k sweep one contiguous eighth of the array, so
+// neighbour lines stay in that XCD's L2.  Used when the grid is a multiple of
+// 8 blocks (host launches round to that); otherwise plain grid-stride.
+constexpr unsigned NXCD = 8;
+__device__ __forceinline__ bool xcd_on() { return gridDim.x >= NXCD && (gridDim.x % NXCD) == 0; }
+__device__ __forceinline__ unsigned xchunk(unsigned n) { return (n + NXCD - 1) / NXCD; }
+__device__ __forceinline__ unsigned xbeg(unsigned n)
+{
+  return xcd_on() ? (blockIdx.x % NXCD) * xchunk(n) + (blockIdx.x / NXCD) * blockDim.x + threadIdx.x : gtid();
+}
+__device__ __forceinline__ unsigned xend(unsigned n)
+{
+  if (!xcd_on()) return n;
+  const unsigned e = (blockIdx.x % NXCD + 1) * xchunk(n);
+  return e < n ? e : n;
+}
+__device__ __forceinline__ unsigned xstride() { return xcd_on() ? (gridDim.x / NXCD) * blockDim.x : gstride(); }
 
 __device__ __forceinline__ void unflat(const int dims[3], unsigned id, int x[3])
 {

@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(TPB) k_face_coef(Dev g, Phys P, double dt, con
                                                    double *__restrict__ T)
 {
   const double cvis = P.mu / (g.dx * g.dx);
-  for (unsigned f = gtid(); f < g.nf[D]; f += gstride()) {
+  for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     if (!mom_unknown<D>(g, x)) { dmom[f] = 1.0; af[f] = 0.0; T[f] = 0.0; continue; }
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(TPB) k_cell_grad(Dev g, const double *__restri
 {
   const double tau = 1e-10 / g.dx;
   double s_num = 0.0, s_den = 0.0;
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     double gv[3] = {0.0, 0.0, 0.0};
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(TPB) k_cell_grad(Dev g, const double *__restri
 template <int D>
 __global__ void __launch_bounds__(TPB) k_face_w(Dev g, double kc, const double *__restrict__ nD, double *__restrict__ w)
 {
-  for (unsigned f = gtid(); f < g.nf[D]; f += gstride()) {
+  for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     const int q = x[D];
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(TPB) k_face_w(Dev g, double kc, const double *
 __global__ void __launch_bounds__(TPB) k_pdiag(Dev g, const double *__restrict__ T0, const double *__restrict__ T1,
                                                const double *__restrict__ T2, double *__restrict__ pd)
 {
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     double s = T0[fidx(g, 0, x[0], x[1], x[2])] + T0[fidx(g, 0, x[0] + 1, x[1], x[2])] +
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(TPB) k_mom_rhs(Dev g, Phys P, double dt, const
                                                  double *__restrict__ b, double *__restrict__ x0)
 {
   const double cvis = P.mu / (g.dx * g.dx);
-  for (unsigned f = gtid(); f < g.nf[D]; f += gstride()) {
+  for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     if (!mom_unknown<D>(g, x)) { b[f] = 0.0; x0[f] = 0.0; continue; }
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(TPB) k_mom_apply(Dev g, double cvis, const dou
 {
   if (sc[S_CONV] != 0.0) return;
   double acc = 0.0;
-  for (unsigned f = gtid(); f < g.nf[D]; f += gstride()) {
+  for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     const double pf = p[f];
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(TPB) k_mom_apply(Dev g, double cvis, const dou
 template <int D>
 __global__ void __launch_bounds__(TPB) k_mom_fix(Dev g, double u_in, double *__restrict__ u)
 {
-  for (unsigned f = gtid(); f < g.nf[D]; f += gstride()) {
+  for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     if (!mom_unknown<D>(g, x)) u[f] = (D == 0 && x[0] == 0) ? u_in : 0.0;
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(TPB) k_p_apply(Dev g, const double *__restrict
 {
   if (sc[S_CONV] != 0.0) return;
   double acc = 0.0;
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     const double v = papply_cell(g, T0, T1, T2, p, id, x);
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(TPB) k_p_rhs(Dev g, const double *__restrict__
                                                const double *__restrict__ u0, const double *__restrict__ u1,
                                                const double *__restrict__ u2, double *__restrict__ b)
 {
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     const double ap = papply_cell(g, T0, T1, T2, pn, id, x);
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(TPB) k_correct(Dev g, const double *__restrict
                                                  const double *__restrict__ p, const double *__restrict__ pn,
                                                  double *__restrict__ u)
 {
-  for (unsigned f = gtid(); f < g.nf[D]; f += gstride()) {
+  for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     if (!mom_unknown<D>(g, x)) { u[f] = ustar[f]; continue; }
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
   const double *uu[3] = {u0, u1, u2};
   const double *ww[3] = {w0, w1, w2};
   const double lambda = lam[0];
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     const double ep = eps[id];
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(TPB) k_adr_apply(Dev g, const double *__restri
 {
   if (sc[S_CONV] != 0.0) return;
   double d0 = 0.0, d1 = 0.0;
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     double v = xv[id];
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(TPB) k_react(Dev g, Phys P, const double *__re
   const double *ww[3] = {w0, w1, w2};
   const double lambda = lam[0];
   double s_sink = 0.0, s_rate = 0.0;
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     const double ep = eps[id];
@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(TPB) k_eps_update(Dev g, Phys P, double dt, in
 {
   double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   double mx = 0.0;
-  for (unsigned id = gtid(); id < g.nc; id += gstride()) {
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
     const double e0 = eps[id], cc = c[id];
@@ -566,7 +566,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(unsigned n, const double *__res
                                                  double *__restrict__ part)
 {
   double rz = 0.0, bn = 0.0;
-  for (unsigned i = gtid(); i < n; i += gstride()) {
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double d = dg[i];
     const double rr = b[i] - q[i];
     r[i] = rr;
@@ -587,7 +587,7 @@ __global__ void __launch_bounds__(TPB) k_cg_xr(unsigned n, const double *__restr
   if (sc[S_CONV] != 0.0) return;
   const double alpha = sc[S_ALPHA];
   double res = 0.0;
-  for (unsigned i = gtid(); i < n; i += gstride()) {
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     x[i] += alpha * p[i];
     const double rr = r[i] - alpha * q[i];
     r[i] = rr;
@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(TPB) k_cg_zdots(unsigned n, const double *__re
 {
   if (sc[S_CONV] != 0.0) return;
   double zr = 0.0, zq = 0.0;
-  for (unsigned i = gtid(); i < n; i += gstride()) {
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     zr += z[i] * r[i];
     zq += z[i] * q[i];
   }
@@ -620,7 +620,7 @@ __global__ void __launch_bounds__(TPB) k_cg_p(unsigned n, const double *__restri
 {
   if (sc[S_CONV] != 0.0) return;
   const double beta = sc[S_BETA];
-  for (unsigned i = gtid(); i < n; i += gstride()) p[i] = z[i] + beta * p[i];
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = z[i] + beta * p[i];
 }
 
 // One-block scalar updates of the CG recurrences.
@@ -688,7 +688,7 @@ __global__ void __launch_bounds__(TPB) k_bi_init(unsigned n, const double *__res
                                                  double *__restrict__ v, double *__restrict__ part)
 {
   double bb = 0.0, rr = 0.0, hr = 0.0;
-  for (unsigned i = gtid(); i < n; i += gstride()) {
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double ri = b[i] - y[i];
     const double h = splitmix_unit(i);
     r[i] = ri; rh[i] = h; p[i] = 0.0; v[i] = 0.0;
@@ -706,7 +706,7 @@ __global__ void __launch_bounds__(TPB) k_bi_p(unsigned n, const double *__restri
 {
   if (sc[S_CONV] != 0.0) return;
   const double beta = sc[S_BETA], om = sc[S_OMEGA];
-  for (unsigned i = gtid(); i < n; i += gstride()) p[i] = r[i] + beta * (p[i] - om * v[i]);
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = r[i] + beta * (p[i] - om * v[i]);
 }
 
 // s = r - alpha v, partial s.s
@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(TPB) k_bi_s(unsigned n, const double *__restri
   if (sc[S_CONV] != 0.0) return;
   const double al = sc[S_ALPHA];
   double ss = 0.0;
-  for (unsigned i = gtid(); i < n; i += gstride()) {
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double si = r[i] - al * v[i];
     s[i] = si;
     ss += si * si;
@@ -738,7 +738,7 @@ __global__ void __launch_bounds__(TPB) k_bi_xr(unsigned n, const double *__restr
   const double al = sc[S_ALPHA], om = sc[S_OMEGA];
   const bool half = sc[S_SHALF] != 0.0;
   double rr = 0.0, rhr = 0.0;
-  for (unsigned i = gtid(); i < n; i += gstride()) {
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     if (half) { x[i] += al * ph[i]; continue; }
     x[i] += al * ph[i] + om * sh[i];
     const double ri = s[i] - om * t[i];

@@ -59,7 +59,7 @@ __device__ __forceinline__ R mg_apply_cell(const MgLevel<R> &L, int nd, const R 
 template <typename R>
 __global__ void __launch_bounds__(TPB) k_mg_diag(MgLevel<R> L, int nd)
 {
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
     int c[3];
     unflat(L.n, id, c);
     const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
@@ -83,7 +83,7 @@ template <typename R, int D>
 __global__ void __launch_bounds__(TPB) k_mg_scaled_faces(unsigned nf, const double *__restrict__ T, double inv_s,
                                                          MgLevel<R> L)
 {
-  for (unsigned f = gtid(); f < nf; f += gstride()) L.T[D][f] = (R)(T[f] * inv_s);
+  for (unsigned f = xbeg(nf); f < xend(nf); f += xstride()) L.T[D][f] = (R)(T[f] * inv_s);
 }
 
 // Coarse diagonal, consistent with the coarse faces: the Galerkin diagonal of
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(TPB) k_mg_scaled_faces(unsigned nf, const doub
 template <typename R>
 __global__ void __launch_bounds__(TPB) k_mg_coarse_diag(MgLevel<R> F, MgLevel<R> Cc, int nd)
 {
-  for (unsigned I = gtid(); I < Cc.nc; I += gstride()) {
+  for (unsigned I = xbeg(Cc.nc); I < xend(Cc.nc); I += xstride()) {
     int X[3];
     unflat(Cc.n, I, X);
     R s = 0;
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(TPB) k_mg_coarse_diag(MgLevel<R> F, MgLevel<R>
 template <typename R, int D>
 __global__ void __launch_bounds__(TPB) k_mg_coarsen(MgLevel<R> F, MgLevel<R> Cc, int nd)
 {
-  for (unsigned f = gtid(); f < Cc.nf[D]; f += gstride()) {
+  for (unsigned f = xbeg(Cc.nf[D]); f < xend(Cc.nf[D]); f += xstride()) {
     int X[3];
     unflat(Cc.fd[D], f, X);
     int x0[3];
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(TPB) k_mg_enter(MgLevel<R> L, const double *__
                                                   const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
     const R bb = (R)r[id];
     L.b[id] = bb;
     L.x[id] = omega * bb / L.diag[id];
@@ -164,7 +164,7 @@ template <typename R>
 __global__ void __launch_bounds__(TPB) k_mg_first(MgLevel<R> L, R omega, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) L.x[id] = omega * L.b[id] / L.diag[id];
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) L.x[id] = omega * L.b[id] / L.diag[id];
 }
 
 // One damped-Jacobi sweep xo = x + omega (b - A x) / diag; optionally also
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(TPB) k_mg_jacobi(MgLevel<R> L, int nd, const R
                                                    R omega, double *__restrict__ z, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
     int c[3];
     unflat(L.n, id, c);
     const R ax = mg_apply_cell(L, nd, x, id, c);
@@ -189,7 +189,7 @@ template <typename R>
 __global__ void __launch_bounds__(TPB) k_mg_restrict(MgLevel<R> F, MgLevel<R> Cc, int nd, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned I = gtid(); I < Cc.nc; I += gstride()) {
+  for (unsigned I = xbeg(Cc.nc); I < xend(Cc.nc); I += xstride()) {
     int X[3];
     unflat(Cc.n, I, X);
     R s = 0;
@@ -210,7 +210,7 @@ template <typename R>
 __global__ void __launch_bounds__(TPB) k_mg_prolong(MgLevel<R> F, MgLevel<R> Cc, int nd, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < F.nc; id += gstride()) {
+  for (unsigned id = xbeg(F.nc); id < xend(F.nc); id += xstride()) {
     int c[3];
     unflat(F.n, id, c);
     const unsigned I = (unsigned)(c[0] >> 1) + (unsigned)Cc.n[0] *

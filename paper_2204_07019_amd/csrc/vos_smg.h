@@ -51,7 +51,7 @@ template <typename R>
 __global__ void __launch_bounds__(TPB) k_smg_from_scaled(unsigned nc, int nd, const double *__restrict__ off64,
                                                          SLevel<R> L)
 {
-  for (unsigned id = gtid(); id < nc; id += gstride()) {
+  for (unsigned id = xbeg(nc); id < xend(nc); id += xstride()) {
     L.diag[id] = (R)1;
     for (int k = 0; k < 2 * nd; ++k) L.off[(size_t)k * nc + id] = (R)off64[(size_t)k * nc + id];
     for (int k = 2 * nd; k < 6; ++k) L.off[(size_t)k * nc + id] = (R)0;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, c
                                                            SLevel<R> L)
 {
   const unsigned nc = L.nc;
-  for (unsigned f = gtid(); f < nc; f += gstride()) {
+  for (unsigned f = xbeg(nc); f < xend(nc); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     L.diag[f] = (R)1;
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, c
 template <typename R>
 __global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, int nd)
 {
-  for (unsigned I = gtid(); I < C.nc; I += gstride()) {
+  for (unsigned I = xbeg(C.nc); I < xend(C.nc); I += xstride()) {
     int X[3];
     unflat(C.n, I, X);
     R dg = 0, o[6] = {0, 0, 0, 0, 0, 0};
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(TPB) k_smg_enter(SLevel<R> L, const double *__
                                                    const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
     const R bb = (R)r[id];
     L.b[id] = bb;
     L.x[id] = omega * bb / L.diag[id];
@@ -140,7 +140,7 @@ template <typename R>
 __global__ void __launch_bounds__(TPB) k_smg_first(SLevel<R> L, R omega, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) L.x[id] = omega * L.b[id] / L.diag[id];
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) L.x[id] = omega * L.b[id] / L.diag[id];
 }
 
 template <typename R, bool OUT64>
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(TPB) k_smg_jacobi(SLevel<R> L, int nd, const R
                                                     R omega, double *__restrict__ z, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
     int c[3];
     unflat(L.n, id, c);
     const R v = x[id] + omega * (L.b[id] - smg_apply_cell(L, nd, x, id, c)) / L.diag[id];
@@ -161,7 +161,7 @@ template <typename R>
 __global__ void __launch_bounds__(TPB) k_smg_restrict(SLevel<R> F, SLevel<R> C, int nd, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned I = gtid(); I < C.nc; I += gstride()) {
+  for (unsigned I = xbeg(C.nc); I < xend(C.nc); I += xstride()) {
     int X[3];
     unflat(C.n, I, X);
     R s = 0;
@@ -183,7 +183,7 @@ template <typename R>
 __global__ void __launch_bounds__(TPB) k_smg_prolong(SLevel<R> F, SLevel<R> C, int nd, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < F.nc; id += gstride()) {
+  for (unsigned id = xbeg(F.nc); id < xend(F.nc); id += xstride()) {
     int c[3];
     unflat(F.n, id, c);
     const int I0 = F.n[0] == 1 ? c[0] : (c[0] >> 1);

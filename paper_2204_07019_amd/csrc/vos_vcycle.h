@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(TPB) k_v_pre(Lv L, int nd, const double *__res
                                                const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
     R bb;
     if (FROM64) bb = (R)(rscale * (dsc ? r64[id] / sqrt(dsc[id]) : r64[id]));
     else bb = L.b[id];
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(TPB) k_v_jacobi(Lv L, int nd, const R *__restr
                                                   const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) {
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
     int c[3];
     unflat(L.n, id, c);
     const R v = x[id] + omega * (L.b[id] - lv_apply(L, nd, x, id, c)) / L.diag[id];
@@ -162,7 +162,7 @@ template <typename Lv, typename R>
 __global__ void __launch_bounds__(TPB) k_v_restrict(Lv F, Lv C, int nd, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned I = gtid(); I < C.nc; I += gstride()) {
+  for (unsigned I = xbeg(C.nc); I < xend(C.nc); I += xstride()) {
     int X[3];
     unflat(C.n, I, X);
     C.b[I] = lv_restrict_one<Lv, R>(F, nd, X);
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(TPB) k_v_post(Lv F, Lv C, int nd, R *__restric
                                                 const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < F.nc; id += gstride()) {
+  for (unsigned id = xbeg(F.nc); id < xend(F.nc); id += xstride()) {
     int c[3];
     unflat(F.n, id, c);
     const R y = F.x[id] + C.x[parent_of<R>(F.n, C.n, nd, c)];
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(TPB) k_v_cast_in(Lv L, const double *__restric
                                                    double rscale, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride())
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride())
     L.b[id] = (R)(rscale * (dsc ? r[id] / sqrt(dsc[id]) : r[id]));
 }
 
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(TPB) k_v_cast_out(Lv L, double *__restrict__ z
                                                     const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = gtid(); id < L.nc; id += gstride()) z[id] = unscale((double)L.x[id], dsc, id);
+  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) z[id] = unscale((double)L.x[id], dsc, id);
 }
 
 }  // namespace vos

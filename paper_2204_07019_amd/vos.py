@@ -21,7 +21,7 @@ VOS_OK, VOS_ERR_ARG, VOS_ERR_DEVICE, VOS_ERR_NOCONV, VOS_ERR_OOM, VOS_ERR_STATE 
 IVOS, PSI, PSI_PRIME = 0, 1, 2
 FP64, MIXED = 0, 1
 FREEZE_SOLID = 1
-TIMERS = {"off": -1, "smg_jacobi": 0, "mg_jacobi": 1, "adr_apply": 2, "p_apply": 3, "mom_apply": 4}
+KERNELS = {"v_restrict": 0, "v_post": 1, "v_pre": 2, "v_coarse": 3, "p_apply": 4, "adr_apply": 5}
 FIELDS = {"eps": 0, "ux": 1, "uy": 2, "uz": 3, "p": 4, "c": 5, "ustar_x": 6, "ustar_y": 7,
           "ustar_z": 8, "rbar": 9, "gmag": 10}
 
@@ -85,13 +85,11 @@ def lib():
         L.vos_field_ptr.argtypes = [vp, C.c_int, C.POINTER(vp)]
         L.vos_step.argtypes = [vp, C.c_double, C.c_int, C.c_int, C.POINTER(_Diag)]
         L.vos_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
-        L.vos_kernel_timer.argtypes = [vp, C.c_int]
-        L.vos_kernel_timer_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
-                                            C.POINTER(C.c_double)]
+        L.vos_time_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.vos_last_error.restype = C.c_char_p
         for name in ("vos_workspace_bytes", "vos_create", "vos_destroy", "vos_set_solid_fraction",
                      "vos_set_field", "vos_set_params", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics",
-                     "vos_kernel_timer", "vos_kernel_timer_read"):
+                     "vos_time_kernel"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -215,14 +213,12 @@ class Sim:
         _check(rc, diag_to_dict(dg))
         return diag_to_dict(dg)
 
-    def kernel_timer(self, family: str):
-        """Start timing every launch of one kernel family (see TIMERS)."""
-        _check(lib().vos_kernel_timer(self._h, TIMERS[family]))
-
-    def kernel_timer_read(self) -> dict:
-        ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
-        _check(lib().vos_kernel_timer_read(self._h, C.byref(ms), C.byref(n), C.byref(b)))
-        return {"total_ms": ms.value, "launches": n.value, "bytes": b.value}
+    def time_kernel(self, family: str, reps: int = 50) -> dict:
+        """Average duration and algorithmic bytes of one launch of a kernel
+        family, timed back to back on the live state with HIP events."""
+        ms, by = C.c_double(), C.c_double()
+        _check(lib().vos_time_kernel(self._h, KERNELS[family], reps, C.byref(ms), C.byref(by)))
+        return {"avg_ms": ms.value, "bytes": by.value}
 
     def diagnostics(self) -> dict:
         dg = _Diag()
