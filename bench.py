@@ -81,13 +81,39 @@ def timed_steps(sim, dt, steps, warmup):
     return el, diags
 
 
-def roofline(sim, family, reps=200):
+def kernel_sources_sha() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2204_07019_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs (profiles/hbm_traffic.json), or None if the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("csrc_sha") != kernel_sources_sha():
+        return None
+    k = t.get("kernels", {}).get(family)
+    return round(k["traffic_bytes"]) if k and "traffic_bytes" in k else None
+
+
+def roofline(sim, family, reps=200, with_traffic=True):
     """Live roofline of one kernel family: back-to-back launches on the
     state the timed steps left, between two HIP events on the sim's stream."""
     t = sim.time_kernel(family, reps)
     achieved = t["bytes"] / (t["avg_ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": family,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(family) if with_traffic else None, "kernel": family,
             "avg_launch_us": round(t["avg_ms"] * 1e3, 3), "bytes_per_launch": round(t["bytes"])}
 
 
@@ -101,19 +127,27 @@ def pressure_3d(vos, inputs, n, dt):
     sim = vos.Sim(n, n, n, prm["dx"], dict(prm, kc=0.0),
                   vos.Opts(precision=vos.FP64, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000))
     sim.set_solid_fraction(es)
-    for _ in range(2):
-        sim.step(dt, 1, freeze_solid=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    d = sim.step(dt, 1, freeze_solid=True)
+    conv = True
+    try:
+        for _ in range(2):
+            sim.step(dt, 1, freeze_solid=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = sim.step(dt, 1, freeze_solid=True)
+    except vos.VosError as e:
+        # the pressure multigrid is weak on this geometry (thin partial-volume
+        # channels); report the unconverged solve instead of aborting
+        conv, d = False, e.diag
+        t0 = time.perf_counter()
     el = time.perf_counter() - t0
     cells = n ** 3
     t_p = d["t_ms"][2] * 1e-3
     pb = cells * (P_ITER_BYTES[("fp64", 3)] * d["it_p"] + P_SETUP_BYTES[3])
     out = {"workload": f"pack {n}^3 dx=4um porosity 0.23 seed 33, FP64 multigrid, rtol 1e-8",
+           "converged": conv, "res_p": d["res_p"],
            "its": d["it_p"], "pressure_ms": round(d["t_ms"][2], 2), "step_ms": round(el * 1e3, 1),
            "GBs_algorithmic": round(pb / t_p / 1e9, 1), "frac_hbm": round(pb / t_p / 1e9 / HBM_PEAK_GBS, 4),
-           "p_apply_roofline": roofline(sim, "p_apply")}
+           "p_apply_roofline": roofline(sim, "p_apply", with_traffic=False) if conv else None}
     sim.close()
     return out
 
@@ -164,7 +198,19 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 5}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
