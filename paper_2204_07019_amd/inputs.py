@@ -136,3 +136,44 @@ def workload(name: str):
     if name == "pack":
         return sphere_pack(256, seed=33), dict(BASE_PARAMS, dx=4e-6)
     raise KeyError(name)
+
+
+# Layer shapes of the warm-start U-Net (input channels, output channels), in
+# parameter order; the flat parameter vector holds, per layer, W[27][ci][co]
+# then b[co], followed by the 1x1x1 head's w[16] and b[1].
+UNET_LAYERS = ((16, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64),
+               (96, 32), (32, 32), (48, 16), (16, 16))
+
+
+def unet_init(seed: int, cin: int = 4) -> np.ndarray:
+    """He-normal conv weights (fan-in 27 * real input channels), zero biases,
+    small normal head; weights of padded input channels (>= cin) are zero.
+    Returns the flat FP32 parameter vector."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (ci, co) in enumerate(UNET_LAYERS):
+        real = cin if li == 0 else ci
+        w = rng.standard_normal((27, ci, co)) * np.sqrt(2.0 / (27 * real))
+        if li == 0:
+            w[:, cin:, :] = 0.0
+        parts += [w.ravel(), np.zeros(co)]
+    parts += [rng.standard_normal(16) * 0.25, np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unet_batch(n: int, d: int, h: int, w: int, seed: int, cin: int = 4):
+    """Synthetic U-Net inputs (n, d, h, w, cin) in FP32 and a smooth target
+    (n, d, h, w): channel 0 a solid fraction in [0, 1], the others smooth
+    fields; the target is a fixed nonlinear mix of them."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.linspace(0, 1, d), np.linspace(0, 1, h), np.linspace(0, 1, w), indexing="ij")
+    xs = np.zeros((n, d, h, w, cin), np.float32)
+    t = np.zeros((n, d, h, w), np.float32)
+    for b in range(n):
+        f = rng.uniform(1.0, 3.0, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        xs[b, ..., 0] = (rng.random((d, h, w)) < 0.3).astype(np.float32)
+        for c in range(1, cin):
+            xs[b, ..., c] = np.sin(2 * np.pi * f[c % 3] * [x, y, z][c % 3] + ph[c % 3])
+        t[b] = xs[b, ..., 1] * (1.0 - xs[b, ..., 0]) + 0.5 * x
+    return xs, t
