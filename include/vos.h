@@ -124,6 +124,10 @@ typedef struct {
   double alpha;                  /* (1/a) sum c|grad eps|V / sum eps c V (Section 2.5) */
   double t_ms[6];                /* GPU time of coefficients, momentum, pressure,
                                     correction, transport, reaction+update [ms] */
+  int guess;                     /* pressure start: -1 p^n (no network attached),
+                                    0 p^n (network guess rejected or off), 1 network guess */
+  double res0_prev, res0_guess;  /* with a network attached: relative Jacobi-scaled residual
+                                    of p^n and of the network guess (0 when off) */
 } vos_diag;
 
 /* Fields for vos_set_field / vos_get_field / vos_field_ptr. */

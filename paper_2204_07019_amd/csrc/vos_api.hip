@@ -17,6 +17,7 @@
 
 #include "vos.h"
 #include "vos_device.h"
+#include "vos_internal.h"
 #include "vos_kernels.h"
 #include "vos_mg.h"
 #include "vos_smg.h"
@@ -196,6 +197,14 @@ Layout make_layout(const vos_grid &g, int precision)
 
 }  // namespace
 
+namespace vosint {
+vos_status fail(vos_status st, const std::string &msg)
+{
+  g_err = msg;
+  return st;
+}
+}  // namespace vosint
+
 struct vos_sim {
   vos_grid grid;
   vos_params prm;
@@ -227,12 +236,20 @@ struct vos_sim {
   bool have_geometry;
   bool stepped;             // a step has run: the hierarchies hold live data
   vos_diag last;
+
+  vos_unet *net;            // attached warm-start network (or null)
+  double ws_gain;
+  int ws_use;
+  bool ws_sampled;          // the network input of the last pressure solve is in its buffer
+  double ws_s0;             // rms of the Jacobi-scaled initial residual of that solve
+  int ws_used;              // the last solve started from the network's guess
+  double ws_res_prev, ws_res_guess;
 };
 
 namespace {
 
 double *sc_block(vos_sim *s, int k) { return s->scal + (size_t)k * S_COUNT * 2; }
-enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6 };
+enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6, SC_WS = 7 };
 
 template <typename R>
 void fill_levels(vos_sim *s, MgLevel<R> *lv)
@@ -563,6 +580,134 @@ void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const dou
                         1.0 / s->p_scale);
 }
 
+// ---------------------------------------------------------------- warm start
+
+// Initial residual of p^n: r0 = b - A p^n (q = A p^n).  rd = r0 / d; partial
+// sums of rd^2, r0^2 / d and b^2 / d.
+__global__ void __launch_bounds__(TPB) k_ws_r0(unsigned n, const double *__restrict__ b, const double *__restrict__ q,
+                                               const double *__restrict__ dg, double *__restrict__ rd,
+                                               double *__restrict__ part)
+{
+  double a = 0.0, r2 = 0.0, b2 = 0.0;
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
+    const double d = dg[i], r = b[i] - q[i];
+    const double v = r / d;
+    rd[i] = v;
+    a += v * v;
+    r2 += r * r / d;
+    b2 += b[i] * b[i] / d;
+  }
+  const double vv[3] = {a, r2, b2};
+  write_partials<3>(vv, part);
+}
+
+// sc[0] = s0 = rms(rd), sc[1] = r0.D^-1.r0, sc[2] = b.D^-1.b.
+__global__ void k_ws_stats(const double *__restrict__ part, int nb, unsigned n, double *__restrict__ sc)
+{
+  const double a = sum_partials(part, 0, nb);
+  const double r2 = sum_partials(part, 1, nb);
+  const double b2 = sum_partials(part, 2, nb);
+  if (threadIdx.x == 0) {
+    sc[0] = sqrt(a / (double)n);
+    sc[1] = r2;
+    sc[2] = b2;
+  }
+}
+
+// Network input per cell: [eps_s, rd / s0, (i + 1/2) / nx, 1] (FP32, 4 channels).
+__global__ void k_ws_input(Dev g, const double *__restrict__ eps, const double *__restrict__ rd,
+                           const double *__restrict__ sc, float *__restrict__ x)
+{
+  const double s0 = sc[0];
+  const double inv = s0 > 0.0 ? 1.0 / s0 : 0.0;
+  for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
+    const unsigned i = id % (unsigned)g.n[0];
+    float4 v;
+    v.x = (float)(1.0 - eps[id]);
+    v.y = (float)(rd[id] * inv);
+    v.z = (float)((i + 0.5) / g.n[0]);
+    v.w = 1.0f;
+    reinterpret_cast<float4 *>(x)[id] = v;
+  }
+}
+
+// p = p^n + gain s0 y.
+__global__ void k_ws_guess(unsigned n, const double *__restrict__ pn, const float *__restrict__ y, double gain,
+                           const double *__restrict__ sc, double *__restrict__ p)
+{
+  const double s = gain * sc[0];
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = pn[i] + s * (double)y[i];
+}
+
+// Partial sums of (b - q)^2 / d.
+__global__ void __launch_bounds__(TPB) k_ws_res(unsigned n, const double *__restrict__ b, const double *__restrict__ q,
+                                                const double *__restrict__ dg, double *__restrict__ part)
+{
+  double a = 0.0;
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
+    const double r = b[i] - q[i];
+    a += r * r / dg[i];
+  }
+  const double vv[1] = {a};
+  write_partials<1>(vv, part);
+}
+
+__global__ void k_ws_store(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+  const double a = sum_partials(part, 0, nb);
+  if (threadIdx.x == 0) out[0] = a;
+}
+
+// Training target (p - p^n) / (gain s0) as FP32 (0 where s0 = 0).
+__global__ void k_ws_target(unsigned n, const double *__restrict__ p, const double *__restrict__ pn, double scale,
+                            float *__restrict__ t)
+{
+  const double inv = scale > 0.0 ? 1.0 / scale : 0.0;
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) t[i] = (float)((p[i] - pn[i]) * inv);
+}
+
+// Build the network input from the solve's initial residual; with the guess
+// enabled, start from p^n + gain s0 f(input) when its Jacobi-scaled residual is
+// smaller than that of p^n (s->p holds p^n on entry, the start on exit).
+vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, const double *zero_flag)
+{
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  const unsigned n = g.nc;
+  const int nb = grid_blocks(n);
+  double *sc = sc_block(s, SC_WS);
+  float *x = vosint::unet_input(s->net);
+  k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, q, s->part, zero_flag);
+  k_ws_r0<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, rd, s->part);
+  k_ws_stats<<<1, TPB, 0, st>>>(s->part, nb, n, sc);
+  k_ws_input<<<nb, TPB, 0, st>>>(g, s->eps, rd, sc, x);
+  s->ws_used = 0;
+  s->ws_res_guess = 0.0;
+  if (s->ws_use) {
+    if (vos_status e = vosint::unet_forward_on(s->net, st)) return e;
+    k_ws_guess<<<nb, TPB, 0, st>>>(n, s->pn, vosint::unet_output(s->net), s->ws_gain, sc, s->p);
+    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
+    k_ws_res<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, s->part);
+    k_ws_store<<<1, TPB, 0, st>>>(s->part, nb, sc + 3);
+  }
+  HIP_TRY(hipGetLastError());
+  if (vos_status e = read_back(s, sc, 4)) return e;
+  const double *h = s->host;
+  s->ws_s0 = h[0];
+  s->ws_sampled = true;
+  const double bn = h[2] > 0.0 ? h[2] : 1.0;
+  s->ws_res_prev = std::sqrt(h[1] / bn);
+  if (s->ws_use) {
+    s->ws_res_guess = std::sqrt(h[3] / bn);
+    if (h[3] < h[1] && std::isfinite(h[3])) {
+      s->ws_used = 1;
+    } else {
+      HIP_TRY(hipMemcpyAsync(s->p, s->pn, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+  }
+  return VOS_OK;
+}
+
 template <typename R>
 vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
 {
@@ -577,6 +722,8 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   mg_setup<R>(s, lv);
   HIP_TRY(hipMemcpyAsync(s->pn, s->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b);
+  if (s->net)
+    if (vos_status e = warm_start(s, b, q, z, zero_flag)) return e;
   k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, r, z, pv, 0, s->part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
@@ -761,6 +908,9 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   r2 = solve_pressure(s, &dg->it_p, &dg->res_p);
   if (r2 == VOS_ERR_DEVICE) return r2;
   if (r2 && !rc) rc = r2;
+  dg->guess = s->net ? s->ws_used : -1;
+  dg->res0_prev = s->net ? s->ws_res_prev : 0.0;
+  dg->res0_guess = s->net ? s->ws_res_guess : 0.0;
   HIP_TRY(hipEventRecord(s->ev[3], st));
   launch_correct(s);
   HIP_TRY(hipEventRecord(s->ev[4], st));
@@ -974,6 +1124,13 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   }
   s->have_geometry = false;
   s->stepped = false;
+  s->net = nullptr;
+  s->ws_gain = 1.0;
+  s->ws_use = 0;
+  s->ws_sampled = false;
+  s->ws_s0 = 0.0;
+  s->ws_used = 0;
+  s->ws_res_prev = s->ws_res_guess = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
@@ -1122,6 +1279,43 @@ vos_status vos_diagnostics(vos_sim *s, vos_diag *out)
 {
   if (!s || !out) return fail(VOS_ERR_ARG, "NULL argument");
   *out = s->last;
+  return VOS_OK;
+}
+
+
+vos_status vos_attach_unet(vos_sim *s, vos_unet *net, const vos_warm_start *ws)
+{
+  if (!s) return fail(VOS_ERR_ARG, "NULL simulation");
+  if (!net) {
+    s->net = nullptr;
+    s->ws_use = 0;
+    s->ws_sampled = false;
+    return VOS_OK;
+  }
+  if (!ws) return fail(VOS_ERR_ARG, "NULL warm-start options");
+  if (!(ws->gain > 0.0) || !std::isfinite(ws->gain)) return fail(VOS_ERR_ARG, "warm-start gain must be finite and > 0");
+  int b, nz, ny, nx, cin;
+  vosint::unet_dims(net, &b, &nz, &ny, &nx, &cin);
+  if (b != 1 || nz != s->grid.nz || ny != s->grid.ny || nx != s->grid.nx || cin != 4)
+    return fail(VOS_ERR_ARG, "the network must be planned for batch 1, the simulation's grid and 4 input channels");
+  s->net = net;
+  s->ws_gain = ws->gain;
+  s->ws_use = ws->use_guess ? 1 : 0;
+  s->ws_sampled = false;
+  return VOS_OK;
+}
+
+vos_status vos_warm_start_sample(vos_sim *s, float *x_dev, float *target_dev)
+{
+  if (!s || !x_dev || !target_dev) return fail(VOS_ERR_ARG, "NULL argument");
+  if (!s->net || !s->ws_sampled) return fail(VOS_ERR_STATE, "no pressure solve has run with a network attached");
+  const unsigned n = s->g.nc;
+  hipStream_t st = s->stream;
+  HIP_TRY(hipMemcpyAsync(x_dev, vosint::unet_input(s->net), (size_t)n * 4 * sizeof(float), hipMemcpyDeviceToDevice,
+                         st));
+  k_ws_target<<<grid_blocks(n), TPB, 0, st>>>(n, s->p, s->pn, s->ws_gain * s->ws_s0, target_dev);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
   return VOS_OK;
 }
 

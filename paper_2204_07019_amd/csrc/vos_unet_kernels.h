@@ -1,0 +1,369 @@
+// vos_unet_kernels.h -- BF16 MFMA kernels of the pressure warm-start U-Net
+// (3-D, 3x3x3 convolutions, NDHWC activations, FP32 accumulation).
+//
+// The convolutions are dense contractions, so they run on the matrix cores:
+// v_mfma_f32_16x16x16bf16_1k, one wave computing a 16-voxel x 16-channel tile
+// per instruction.  Operand layout of that instruction (wave64), used
+// throughout:
+//   A (16 x 16, M x K): lane l holds A[l % 16][4 (l / 16) + j], j = 0..3
+//   B (16 x 16, K x N): lane l holds B[4 (l / 16) + j][l % 16]
+//   D (16 x 16, M x N): lane l holds D[4 (l / 16) + i][l % 16], i = 0..3
+// Forward: M = 16 consecutive voxels along x, N = output channels, K = input
+// channels of one tap (the 27 taps accumulate into the same tile).  The data
+// gradient is the same kernel on the output gradient with flipped, transposed
+// weights.  The weight gradient contracts over voxels (M = input channels,
+// N = output channels, K = voxels) with a deterministic split-K reduction.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace vosnet {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int CTPB = 256;         // 4 waves per block
+constexpr int WG_CHUNKS = 64;     // split-K chunks of the weight gradient
+
+// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+struct Vol {   // one NDHWC activation tensor (a channel slice of a buffer)
+  unsigned short *p;
+  int ctot;    // channels per voxel in the buffer
+  int coff;    // first channel of the slice
+};
+
+// y[v][co] = sum_tap sum_ci x[v + off(tap)][ci] w[tap][co][ci] (+ bias[co]),
+// zero padding; optional ReLU; optional mask (y = 0 where m[v][co] <= 0);
+// output as BF16 into a channel slice, or as FP32 (y32, dense Cout channels).
+// Grid (ceil(W / 64), H, N * D), block 256: wave w of block bx handles the 16
+// voxels x = 64 bx + 16 w .. + 15 (waves past W return).  NT = Cout / 16 output
+// tiles, kept in registers.  Requires W % 16 == 0 and Cin % 16 == 0.
+template <int NT>
+__global__ void __launch_bounds__(CTPB) k_conv3d_fwd(Vol x, int Cin, const unsigned short *__restrict__ w,
+                                                     const float *__restrict__ bias, Vol y, float *__restrict__ y32,
+                                                     int D, int H, int W, int relu, Vol mask)
+{
+  constexpr int Cout = NT * 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * 64 + wv * 16;
+  if (x0 >= W) return;
+  const int yy = blockIdx.y;
+  const int z = blockIdx.z % D, n = blockIdx.z / D;
+  const int m = lane & 15, kq = lane >> 4;
+  const int nchunk = Cin >> 4;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < 27; ++tap) {
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int zz = z + dz, y1 = yy + dy, xx = x0 + m + dx;
+    const bool ok = zz >= 0 && zz < D && y1 >= 0 && y1 < H && xx >= 0 && xx < W;
+    const size_t vox = ok ? (((size_t)n * D + zz) * H + y1) * W + xx : 0;
+    const unsigned short *xin = x.p + vox * x.ctot + x.coff + kq * 4;
+    const unsigned short *wt = w + (size_t)tap * Cout * Cin + (size_t)m * Cin + kq * 4;
+    for (int cc = 0; cc < nchunk; ++cc) {
+      bf16x4 a = bf16x4{0, 0, 0, 0};
+      if (ok) a = *(const bf16x4 *)(xin + cc * 16);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x4 b = *(const bf16x4 *)(wt + (size_t)t * 16 * Cin + cc * 16);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + m;
+    const float bco = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int xv = x0 + kq * 4 + i;
+      const size_t vox = (((size_t)n * D + z) * H + yy) * W + xv;
+      float v = acc[t][i] + bco;
+      if (relu) v = v > 0.f ? v : 0.f;
+      if (mask.p && !(bf2f(mask.p[vox * mask.ctot + mask.coff + co]) > 0.f)) v = 0.f;
+      if (y32) y32[vox * Cout + co] = v;
+      else y.p[vox * y.ctot + y.coff + co] = f2bf(v);
+    }
+  }
+}
+
+// Weight-gradient partials: part[chunk][tap][ci][co] = sum over the chunk's
+// rows of x[v + off(tap)][ci] dy[v][co].  Grid (27 * tiles, WG_CHUNKS), block
+// 256: the 4 waves split the chunk's rows, LDS combines them.
+__global__ void __launch_bounds__(CTPB) k_conv3d_wgrad(Vol x, int Cin, Vol dy, int Cout, int N, int D, int H, int W,
+                                                       float *__restrict__ part)
+{
+  __shared__ float red[4][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ntc = Cout >> 4;
+  const int tiles = (Cin >> 4) * ntc;
+  const int tap = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const int cit = tile / ntc, cot = tile % ntc;
+  const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const int m = lane & 15, kq = lane >> 4;
+  const int rows = N * D * H;
+  const int r0 = (int)((long long)rows * blockIdx.y / WG_CHUNKS), r1 = (int)((long long)rows * (blockIdx.y + 1) / WG_CHUNKS);
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int r = r0 + wv; r < r1; r += 4) {
+    const int yy = r % H, z = (r / H) % D, n = r / (H * D);
+    const int zz = z + dz, y1 = yy + dyy;
+    const bool rok = zz >= 0 && zz < D && y1 >= 0 && y1 < H;
+    for (int xb = 0; xb < W; xb += 16) {
+      // A[m = ci][k = voxel]: 4 voxels xb + 4 kq + j of input channel cit*16 + m
+      bf16x4 a, b;
+      for (int j = 0; j < 4; ++j) {
+        const int xv = xb + kq * 4 + j;
+        const int xs = xv + dx;
+        unsigned short av = 0;
+        if (rok && xs >= 0 && xs < W) {
+          const size_t vs = (((size_t)n * D + zz) * H + y1) * W + xs;
+          av = x.p[vs * x.ctot + x.coff + cit * 16 + m];
+        }
+        a[j] = (short)av;
+        const size_t vd = (((size_t)n * D + z) * H + yy) * W + xv;
+        b[j] = (short)dy.p[vd * dy.ctot + dy.coff + cot * 16 + m];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+  }
+  // D[ci = 4 kq + i][co = m]
+  for (int i = 0; i < 4; ++i) red[wv][(kq * 4 + i) * 16 + m] = acc[i];
+  __syncthreads();
+  const int e = threadIdx.x;   // 256 entries = 16 ci x 16 co
+  const float s = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+  const int ci = cit * 16 + e / 16, co = cot * 16 + e % 16;
+  part[(((size_t)blockIdx.y * 27 + tap) * Cin + ci) * Cout + co] = s;
+}
+
+// dW[tap][ci][co] = sum over chunks (fixed order).
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int n, float *__restrict__ dw)
+{
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int c = 0; c < WG_CHUNKS; ++c) s += part[(size_t)c * n + i];
+    dw[i] = s;
+  }
+}
+
+// Bias gradient partials: per block, sum of dy over its voxels, per channel.
+// Grid: nblk blocks over V voxels; block 256 = C channels x (256/C) voxel lanes.
+__global__ void k_bias_grad_part(Vol dy, int C, size_t V, float *__restrict__ part)
+{
+  __shared__ float red[256];
+  const int c = threadIdx.x % C, lane = threadIdx.x / C, lanes = CTPB / C;
+  float s = 0.f;
+  if (lane < lanes)
+    for (size_t v = (size_t)blockIdx.x * lanes + lane; v < V; v += (size_t)gridDim.x * lanes)
+      s += bf2f(dy.p[v * dy.ctot + dy.coff + c]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (lane == 0) {
+    float t = 0.f;
+    for (int l = 0; l < lanes; ++l) t += red[l * C + c];
+    part[(size_t)blockIdx.x * C + c] = t;
+  }
+}
+
+__global__ void k_bias_grad_final(const float *__restrict__ part, int C, int nblk, float *__restrict__ db)
+{
+  const int c = threadIdx.x;
+  if (c >= C) return;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * C + c];
+  db[c] = s;
+}
+
+// 2x2x2 average pooling (fine dims D, H, W even).
+__global__ void k_pool_fwd(Vol x, int C, Vol y, int N, int D, int H, int W)
+{
+  const int Dc = D / 2, Hc = H / 2, Wc = W / 2;
+  const size_t total = (size_t)N * Dc * Hc * Wc * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    size_t v = i / C;
+    const int xc = (int)(v % Wc), yc = (int)((v / Wc) % Hc), zc = (int)((v / ((size_t)Wc * Hc)) % Dc);
+    const int n = (int)(v / ((size_t)Wc * Hc * Dc));
+    float s = 0.f;
+    for (int a = 0; a < 8; ++a) {
+      const size_t vf = (((size_t)n * D + 2 * zc + (a >> 2)) * H + 2 * yc + ((a >> 1) & 1)) * W + 2 * xc + (a & 1);
+      s += bf2f(x.p[vf * x.ctot + x.coff + c]);
+    }
+    y.p[v * y.ctot + y.coff + c] = f2bf(0.125f * s);
+  }
+}
+
+// Gradient of the average pool, optionally added to an existing gradient slice
+// and masked by (m > 0): g[f] = (add ? g[f] : 0) + mask(f) * dy[parent] / 8.
+__global__ void k_pool_bwd(Vol dy, int C, Vol g, int N, int D, int H, int W, int add, Vol mask)
+{
+  const size_t total = (size_t)N * D * H * W * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const size_t v = i / C;
+    const int xx = (int)(v % W), yy = (int)((v / W) % H), zz = (int)((v / ((size_t)W * H)) % D);
+    const int n = (int)(v / ((size_t)W * H * D));
+    const size_t vc = (((size_t)n * (D / 2) + zz / 2) * (H / 2) + yy / 2) * (W / 2) + xx / 2;
+    float d = 0.125f * bf2f(dy.p[vc * dy.ctot + dy.coff + c]);
+    if (mask.p && !(bf2f(mask.p[v * mask.ctot + mask.coff + c]) > 0.f)) d = 0.f;
+    const size_t gi = v * g.ctot + g.coff + c;
+    g.p[gi] = f2bf(add ? bf2f(g.p[gi]) + d : d);
+  }
+}
+
+// Nearest-neighbour 2x upsampling into a channel slice: y[f] = x[parent(f)].
+__global__ void k_up_fwd(Vol x, int C, Vol y, int N, int D, int H, int W)
+{
+  const size_t total = (size_t)N * D * H * W * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const size_t v = i / C;
+    const int xx = (int)(v % W), yy = (int)((v / W) % H), zz = (int)((v / ((size_t)W * H)) % D);
+    const int n = (int)(v / ((size_t)W * H * D));
+    const size_t vc = (((size_t)n * (D / 2) + zz / 2) * (H / 2) + yy / 2) * (W / 2) + xx / 2;
+    y.p[v * y.ctot + y.coff + c] = x.p[vc * x.ctot + x.coff + c];
+  }
+}
+
+// Gradient of the upsampling: g[parent] = sum of the 8 children's gradients.
+__global__ void k_up_bwd(Vol dy, int C, Vol g, int N, int D, int H, int W)
+{
+  const int Dc = D / 2, Hc = H / 2, Wc = W / 2;
+  const size_t total = (size_t)N * Dc * Hc * Wc * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const size_t v = i / C;
+    const int xc = (int)(v % Wc), yc = (int)((v / Wc) % Hc), zc = (int)((v / ((size_t)Wc * Hc)) % Dc);
+    const int n = (int)(v / ((size_t)Wc * Hc * Dc));
+    float s = 0.f;
+    for (int a = 0; a < 8; ++a) {
+      const size_t vf = (((size_t)n * D + 2 * zc + (a >> 2)) * H + 2 * yc + ((a >> 1) & 1)) * W + 2 * xc + (a & 1);
+      s += bf2f(dy.p[vf * dy.ctot + dy.coff + c]);
+    }
+    g.p[v * g.ctot + g.coff + c] = f2bf(s);
+  }
+}
+
+// FP32 NDHWC input with cin real channels -> BF16 with 16 channels (zero padded).
+__global__ void k_pack_input(const float *__restrict__ xin, int cin, size_t V, Vol y)
+{
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < V * 16; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % 16);
+    const size_t v = i / 16;
+    y.p[v * y.ctot + y.coff + c] = c < cin ? f2bf(xin[v * cin + c]) : (unsigned short)0;
+  }
+}
+
+// Head (1x1x1, 16 -> 1, FP32): out[v] = sum_c w[c] x[v][c] + b.
+__global__ void k_head_fwd(Vol x, const float *__restrict__ w, const float *__restrict__ b, size_t V,
+                           float *__restrict__ out)
+{
+  for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x) {
+    float s = b[0];
+    for (int c = 0; c < 16; ++c) s += w[c] * bf2f(x.p[v * x.ctot + x.coff + c]);
+    out[v] = s;
+  }
+}
+
+// MSE: dy = 2 (y - t) / V (FP32), and per-block partial sums of (y - t)^2.
+__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, size_t V, float *__restrict__ dy,
+                      double *__restrict__ part)
+{
+  __shared__ double red[CTPB];
+  double s = 0.0;
+  for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x) {
+    const float d = y[v] - t[v];
+    dy[v] = 2.f * d / (float)V;
+    s += (double)d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = CTPB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Head backward: gx[v][c] = mask(v,c) * w[c] dy[v] (BF16); partials of
+// dw[c] = sum_v x[v][c] dy[v] and db = sum_v dy[v] per block (17 values).
+__global__ void k_head_bwd(Vol x, const float *__restrict__ w, const float *__restrict__ dy, size_t V, Vol gx,
+                           float *__restrict__ part)
+{
+  __shared__ float red[17][CTPB];
+  float s[17];
+  for (int k = 0; k < 17; ++k) s[k] = 0.f;
+  for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x) {
+    const float d = dy[v];
+    for (int c = 0; c < 16; ++c) {
+      const float xv = bf2f(x.p[v * x.ctot + x.coff + c]);
+      s[c] += xv * d;
+      gx.p[v * gx.ctot + gx.coff + c] = f2bf(xv > 0.f ? w[c] * d : 0.f);
+    }
+    s[16] += d;
+  }
+  for (int k = 0; k < 17; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  if (threadIdx.x < 17) {
+    float t = 0.f;
+    for (int i = 0; i < CTPB; ++i) t += red[threadIdx.x][i];
+    part[(size_t)blockIdx.x * 17 + threadIdx.x] = t;
+  }
+}
+
+// Master FP32 weights [tap][ci][co] -> forward layout [tap][co][ci] and
+// data-gradient layout [26 - tap][ci][co] as BF16 (the latter is the forward
+// layout of the transposed, flipped convolution; skipped when wd is null).
+__global__ void k_weights_to_bf16(const float *__restrict__ wm, int Cin, int Cout, unsigned short *__restrict__ wf,
+                                  unsigned short *__restrict__ wd)
+{
+  const int n = 27 * Cin * Cout;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int co = i % Cout, ci = (i / Cout) % Cin, tap = i / (Cout * Cin);
+    const unsigned short h = f2bf(wm[i]);
+    wf[((size_t)tap * Cout + co) * Cin + ci] = h;
+    if (wd) wd[((size_t)(26 - tap) * Cin + ci) * Cout + co] = h;
+  }
+}
+
+// Adam (Kingma & Ba 2015) on FP32 master parameters.
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+}  // namespace vosnet
+
+namespace vosnet {
+// Fixed-order sum of n double partials by one block of CTPB threads.
+__global__ void k_sum_double(const double *__restrict__ part, int n, double *__restrict__ out)
+{
+  __shared__ double red[CTPB];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += CTPB) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = CTPB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+}  // namespace vosnet

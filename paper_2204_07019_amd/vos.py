@@ -59,7 +59,8 @@ class _Diag(C.Structure):
                 ("acid_in", C.c_double), ("acid_out", C.c_double), ("acid_consumed", C.c_double),
                 ("solid_rate", C.c_double), ("acid_balance_rel", C.c_double),
                 ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
-                ("max_deps", C.c_double), ("alpha", C.c_double), ("t_ms", C.c_double * 6)]
+                ("max_deps", C.c_double), ("alpha", C.c_double), ("t_ms", C.c_double * 6),
+                ("guess", C.c_int), ("res0_prev", C.c_double), ("res0_guess", C.c_double)]
 
 
 _lib = None

@@ -1,5 +1,5 @@
 """The C-ABI library builds for gfx950, loads, and exports every entry point
-include/vos.h declares (no compute calls: this runs without a GPU)."""
+the headers under include/ declare (no compute calls: this runs without a GPU)."""
 import ctypes
 import os
 import re
@@ -8,9 +8,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "vos.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(vos_[a-z_]+)\s*\(", src)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(vos_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -47,3 +51,22 @@ def test_argument_errors_without_a_device():
     mixed = vos._Opts(**dict(vos.asdict(vos.Opts()), precision=vos.MIXED))
     m = ctypes.c_size_t()
     assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(mixed), ctypes.byref(m)) == vos.VOS_OK
+
+
+def test_unet_host_validation_without_a_device():
+    from paper_2204_07019_amd import unet
+    assert unet.param_count() == 359761
+    L = unet.lib()
+    n = ctypes.c_size_t()
+    for bad in [(1, 8, 8, 48, 4, 1), (1, 6, 8, 64, 4, 1), (1, 8, 8, 64, 0, 1), (1, 8, 8, 64, 17, 1),
+                (0, 8, 8, 64, 4, 1)]:
+        s = unet._Shape(*bad)
+        assert L.vos_unet_workspace_bytes(ctypes.byref(s), ctypes.byref(n)) == 1, bad
+    s = unet._Shape(2, 8, 8, 64, 4, 1)
+    assert L.vos_unet_workspace_bytes(ctypes.byref(s), ctypes.byref(n)) == 0
+    train = n.value
+    s = unet._Shape(2, 8, 8, 64, 4, 0)
+    assert L.vos_unet_workspace_bytes(ctypes.byref(s), ctypes.byref(n)) == 0
+    assert 0 < n.value < train
+    # activations: >= 224 bytes per full-resolution voxel for inference
+    assert n.value >= 2 * 8 * 8 * 64 * 224

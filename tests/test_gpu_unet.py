@@ -1,0 +1,160 @@
+"""GPU parity of the warm-start U-Net kernels against the FP64 oracle.
+
+The oracle runs with bfloat16 rounding at the points where the GPU stores
+bfloat16 (inputs, weights, activations, activation gradients), so the two
+differ only by FP32-versus-FP64 accumulation and the bfloat16 rounding flips
+(one ulp = 2^-8 relative) that this causes, which then propagate.  Measured on
+the CPU with the oracle's own contractions accumulated in FP32 (one other
+summation order), that noise reaches 1.9e-3 on the output and 6.4e-3 on the
+gradients of the 64-channel level (whose 192 voxels make the relative error
+heavy-tailed) over five seeds at these shapes.  Tolerances (relative L2):
+5e-3 for the output, 2e-2 for each layer's gradient.  A wrong tap, transposed
+weight, missing mask or wrong scale gives errors of order 1e-1 to 1.
+"""
+import numpy as np
+import pytest
+
+from oracle import unet as orc
+from paper_2204_07019_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 5e-3
+TOL_GRAD = 2e-2
+
+
+def rel(a, b):
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def params(seed):
+    th = inputs.unet_init(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    # nonzero biases so that bias paths are exercised
+    o = 0
+    for ci, co in inputs.UNET_LAYERS:
+        o += 27 * ci * co
+        th[o:o + co] = 0.05 * rng.standard_normal(co)
+        o += co
+    th[-1] = 0.1
+    return th.astype(np.float32)
+
+
+def layer_slices():
+    out, o = {}, 0
+    for (name, ci, co) in orc.LAYERS:
+        out[name + ".w"] = slice(o, o + 27 * ci * co)
+        o += 27 * ci * co
+        out[name + ".b"] = slice(o, o + co)
+        o += co
+    out["head.w"] = slice(o, o + 16)
+    out["head.b"] = slice(o + 16, o + 17)
+    return out
+
+
+SHAPES = [(2, 8, 12, 64), (1, 4, 8, 192)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_matches_oracle(shape):
+    import torch
+    from paper_2204_07019_amd.unet import UNet
+    print("unet forward", shape, flush=True)
+    n, d, h, w = shape
+    x, _ = inputs.unet_batch(n, d, h, w, seed=21)
+    th = params(3)
+    net = UNet(n, d, h, w, cin=4, train=False)
+    net.set_params(th)
+    y = net.forward(torch.from_numpy(x)).cpu().numpy()
+    yo, _ = orc.forward(th.astype(np.float64), x, bf16_round=True)
+    e = rel(y, yo)
+    print("rel L2", e)
+    assert e < TOL
+    net.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gradients_match_oracle(shape):
+    import torch
+    from paper_2204_07019_amd.unet import UNet
+    print("unet gradients", shape, flush=True)
+    n, d, h, w = shape
+    x, t = inputs.unet_batch(n, d, h, w, seed=22)
+    th = params(4)
+    net = UNet(n, d, h, w, cin=4, train=True)
+    net.set_params(th)
+    loss = net.loss_grad(torch.from_numpy(x), torch.from_numpy(t))
+    g = net.get_grads()
+    lo, go, _ = orc.loss_and_grad(th.astype(np.float64), x, t, bf16_round=True)
+    assert abs(loss - lo) <= 1e-3 * lo
+    worst = {}
+    for name, sl in layer_slices().items():
+        if name == "e0a.w":
+            # padded input channels carry zero input, hence zero gradient
+            gw = g[sl].reshape(27, 16, 16)
+            assert np.all(gw[:, 4:, :] == 0.0)
+        worst[name] = rel(g[sl], go[sl])
+    print(sorted(worst.items(), key=lambda kv: -kv[1])[:4])
+    assert max(worst.values()) < TOL_GRAD, worst
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    import torch
+    from paper_2204_07019_amd.unet import UNet
+    print("unet adam", flush=True)
+    x, t = inputs.unet_batch(1, 4, 4, 64, seed=23)
+    th = params(5)
+    net = UNet(1, 4, 4, 64, cin=4, train=True)
+    net.set_params(th)
+    m = np.zeros(th.size)
+    v = np.zeros(th.size)
+    ref = th.astype(np.float64)
+    for it in range(1, 4):
+        net.loss_grad(torch.from_numpy(x), torch.from_numpy(t))
+        g = net.get_grads().astype(np.float64)
+        net.adam(1e-3, 0.9, 0.999, 1e-8)
+        ref, m, v = orc.adam(ref, g, m, v, it, 1e-3)
+        got = net.get_params().astype(np.float64)
+        assert np.max(np.abs(got - ref)) < 1e-6, it
+        ref = got          # continue from the GPU's parameters (FP32 state)
+    net.close()
+
+
+def test_training_reduces_loss_and_params_roundtrip(tmp_path):
+    import torch
+    from paper_2204_07019_amd.unet import UNet
+    print("unet training", flush=True)
+    x, t = inputs.unet_batch(2, 8, 8, 64, seed=24)
+    net = UNet(2, 8, 8, 64, cin=4, train=True)
+    net.set_params(inputs.unet_init(6))
+    xt = torch.from_numpy(x).cuda()
+    tt = torch.from_numpy(t).cuda()
+    torch.cuda.synchronize()
+    losses = [net.train_step(xt, tt, 3e-3) for _ in range(40)]
+    print(losses[0], losses[-1])
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.3 * losses[0]
+    p = tmp_path / "w.npy"
+    net.save(str(p))
+    inf = UNet(2, 8, 8, 64, cin=4, train=False)
+    inf.load(str(p))
+    y1 = net.forward(xt).cpu().numpy()
+    y2 = inf.forward(xt).cpu().numpy()
+    np.testing.assert_array_equal(y1, y2)
+    net.close()
+    inf.close()
+
+
+def test_bad_parameters_rejected():
+    from paper_2204_07019_amd.unet import UNet
+    from paper_2204_07019_amd.vos import VosError
+    net = UNet(1, 4, 4, 64, cin=4, train=False)
+    th = inputs.unet_init(1)
+    th[7] = np.nan
+    with pytest.raises(VosError):
+        net.set_params(th)
+    with pytest.raises(VosError):
+        net.adam(1e-3)            # inference-only network has no optimiser state
+    net.close()

@@ -1,0 +1,129 @@
+"""GPU tests of the learned warm start inside the pressure solve.
+
+The network only changes where CG starts: with the guess off the step must be
+bit-identical to a run without a network, with it on the fields must agree
+to the solve tolerance, and the training sample must hold the input the
+network was given and the increment the solve produced.
+"""
+import numpy as np
+import pytest
+
+from paper_2204_07019_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (16, 16, 64)      # nz, ny, nx: nx % 64 == 0, ny and nz % 4 == 0
+DT = 1e-3
+
+
+def geometry():
+    return inputs.sphere_pack(64, seed=5, median_r=5.0, porosity=0.4, ny=16, nz=16)
+
+
+def new_sim():
+    from paper_2204_07019_amd import vos
+    prm = dict(inputs.BASE_PARAMS)
+    prm["model"] = vos.IVOS
+    opts = vos.Opts(rtol_u=1e-10, rtol_p=1e-10, rtol_c=1e-10, precision=vos.MIXED, maxit_p=5000)
+    nz, ny, nx = SHAPE
+    sim = vos.Sim(nx, ny, nz, 4e-6, prm, opts)
+    sim.set_solid_fraction(geometry())
+    sim.step(DT, 2, freeze_solid=True)
+    return sim
+
+
+def new_net(seed=3):
+    from paper_2204_07019_amd.unet import UNet
+    nz, ny, nx = SHAPE
+    net = UNet(1, nz, ny, nx, cin=4, train=False)
+    net.set_params(inputs.unet_init(seed))
+    return net
+
+
+def fields(sim):
+    return {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
+
+
+def test_attached_without_guess_is_bit_identical():
+    from paper_2204_07019_amd import unet
+    print("warm start: guess off vs no network", flush=True)
+    a = new_sim()
+    b = new_sim()
+    net = new_net()
+    unet.attach(b, net, gain=1.0, use_guess=False)
+    for _ in range(3):
+        da = a.step(DT)
+        db = b.step(DT)
+        assert da["guess"] == -1 and db["guess"] == 0
+        assert db["res0_prev"] > 0 and db["res0_guess"] == 0
+        assert da["it_p"] == db["it_p"]
+    fa, fb = fields(a), fields(b)
+    for k in fa:
+        np.testing.assert_array_equal(fa[k], fb[k], err_msg=k)
+    a.close(), b.close(), net.close()
+
+
+def test_guess_changes_start_not_solution():
+    from paper_2204_07019_amd import unet
+    print("warm start: guess on vs no network", flush=True)
+    a = new_sim()
+    b = new_sim()
+    net = new_net()
+    unet.attach(b, net, gain=1.0, use_guess=True)
+    for _ in range(3):
+        a.step(DT)
+        db = b.step(DT)
+        assert db["guess"] in (0, 1)
+        # the start kept is never worse than p^n
+        if db["guess"] == 1:
+            assert db["res0_guess"] < db["res0_prev"]
+    fa, fb = fields(a), fields(b)
+    live = fa["eps"] > 0.5
+    dp = np.linalg.norm((fb["p"] - fa["p"])[live]) / np.linalg.norm(fa["p"][live])
+    print("p rel diff", dp)
+    assert dp < 1e-6
+    for k in ("ux", "uy", "uz", "c"):
+        assert np.linalg.norm(fb[k] - fa[k]) <= 1e-6 * np.linalg.norm(fa[k]) + 1e-300, k
+    unet.attach(b, None)
+    assert b.step(DT)["guess"] == -1
+    a.close(), b.close(), net.close()
+
+
+def test_sample_holds_input_and_increment():
+    from paper_2204_07019_amd import unet
+    print("warm start: training sample", flush=True)
+    sim = new_sim()
+    net = new_net()
+    unet.attach(sim, net, gain=2.0, use_guess=False)
+    eps0 = sim.get_numpy("eps")
+    p0 = sim.get_numpy("p")
+    sim.step(DT)
+    p1 = sim.get_numpy("p")
+    x, t = unet.warm_start_sample(sim)
+    x = x.cpu().numpy()
+    t = t.cpu().numpy().astype(np.float64)
+    nz, ny, nx = SHAPE
+    np.testing.assert_allclose(x[..., 0], (1.0 - eps0).astype(np.float32), rtol=0, atol=0)
+    assert abs(np.sqrt(np.mean(x[..., 1].astype(np.float64) ** 2)) - 1.0) < 1e-5
+    np.testing.assert_array_equal(x[..., 2], np.broadcast_to(((np.arange(nx) + 0.5) / nx).astype(np.float32),
+                                                             (nz, ny, nx)))
+    assert np.all(x[..., 3] == 1.0)
+    # target = (p^{n+1} - p^n) / (gain s0): proportional to the increment
+    dp = p1 - p0
+    k = np.dot(t.ravel(), dp.ravel()) / np.dot(dp.ravel(), dp.ravel())
+    assert k > 0
+    assert np.linalg.norm(t - k * dp) <= 1e-6 * np.linalg.norm(t)
+    sim.close(), net.close()
+
+
+def test_attach_rejects_wrong_shape():
+    from paper_2204_07019_amd import unet
+    from paper_2204_07019_amd.unet import UNet
+    from paper_2204_07019_amd.vos import VosError
+    sim = new_sim()
+    net = UNet(1, 16, 16, 128, cin=4, train=False)
+    with pytest.raises(VosError):
+        unet.attach(sim, net)
+    with pytest.raises(VosError):
+        unet.warm_start_sample(sim)
+    sim.close(), net.close()
