@@ -89,10 +89,13 @@ vos_status vos_unet_train_step(vos_unet *net, const float *x, const float *targe
  * cin = 4), every pressure solve first builds the network input, per cell
  *   [eps_s, (r0 / d) / s0, (i + 1/2) / nx, 1]
  * with r0 = b - A p^n the initial residual, d = diag(A) and
- * s0 = rms(r0 / d) (FP64 reduction).  With use_guess = 1 it then starts CG
- * from p^n + gain * s0 * network(input) if that guess has a smaller
- * Jacobi-scaled residual than p^n, else from p^n (vos_diag reports which,
- * and both residuals).  gain > 0 [Pa per unit of the scaled residual's rms]. */
+ * s0 = rms(r0 / d) (FP64 reduction).  With use_guess = 1 the network output v
+ * is a search direction: the solve starts from p^n + alpha v with
+ * alpha = (v . r0) / (v . A v), the step that minimises the A-norm error
+ * along v (which then drops by (v . r0)^2 / (v . A v)), unless v . A v <= 0
+ * or v . r0 == 0, when it starts from p^n.  vos_diag reports which, and the
+ * Jacobi-scaled residuals of both starts.  gain > 0 only scales the training
+ * target (vos_warm_start_sample). */
 typedef struct { double gain; int use_guess; } vos_warm_start;
 
 /* Attach (net != NULL) or detach (net == NULL).  The network must outlive the
@@ -101,8 +104,9 @@ vos_status vos_attach_unet(vos_sim *sim, vos_unet *net, const vos_warm_start *ws
 
 /* Training sample of the last step's pressure solve (attached network
  * required): x_dev receives the network input it was given (nz*ny*nx*4 FP32),
- * target_dev the increment it should have predicted, (p^{n+1} - p^n) / (gain
- * s0) (nz*ny*nx FP32).  Device pointers. */
+ * target_dev the increment the solve produced, (p^{n+1} - p^n) / (gain s0)
+ * (nz*ny*nx FP32; 0 where s0 = 0).  Device pointers; valid until the next
+ * step. */
 vos_status vos_warm_start_sample(vos_sim *sim, float *x_dev, float *target_dev);
 
 #ifdef __cplusplus

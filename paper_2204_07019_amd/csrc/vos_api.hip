@@ -582,16 +582,17 @@ void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const dou
 
 // ---------------------------------------------------------------- warm start
 
-// Initial residual of p^n: r0 = b - A p^n (q = A p^n).  rd = r0 / d; partial
-// sums of rd^2, r0^2 / d and b^2 / d.
+// Initial residual of p^n: r0 = b - A p^n (q = A p^n), kept in r0.  rd = r0 / d;
+// partial sums of rd^2, r0^2 / d and b^2 / d.
 __global__ void __launch_bounds__(TPB) k_ws_r0(unsigned n, const double *__restrict__ b, const double *__restrict__ q,
-                                               const double *__restrict__ dg, double *__restrict__ rd,
-                                               double *__restrict__ part)
+                                               const double *__restrict__ dg, double *__restrict__ r0,
+                                               double *__restrict__ rd, double *__restrict__ part)
 {
   double a = 0.0, r2 = 0.0, b2 = 0.0;
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double d = dg[i], r = b[i] - q[i];
     const double v = r / d;
+    r0[i] = r;
     rd[i] = v;
     a += v * v;
     r2 += r * r / d;
@@ -631,12 +632,46 @@ __global__ void k_ws_input(Dev g, const double *__restrict__ eps, const double *
   }
 }
 
-// p = p^n + gain s0 y.
-__global__ void k_ws_guess(unsigned n, const double *__restrict__ pn, const float *__restrict__ y, double gain,
+// Search direction from the network output: v = y (FP64).
+__global__ void k_ws_dir(unsigned n, const float *__restrict__ y, double *__restrict__ v)
+{
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) v[i] = (double)y[i];
+}
+
+// Partial sums of v.r0 and v.(A v) (q = A v).
+__global__ void __launch_bounds__(TPB) k_ws_dots(unsigned n, const double *__restrict__ v,
+                                                 const double *__restrict__ r0, const double *__restrict__ q,
+                                                 double *__restrict__ part)
+{
+  double a = 0.0, c = 0.0;
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
+    a += v[i] * r0[i];
+    c += v[i] * q[i];
+  }
+  const double vv[2] = {a, c};
+  write_partials<2>(vv, part);
+}
+
+// Step along v minimising the A-norm error of p^n + alpha v:
+// alpha = v.r0 / v.Av (0 if v.Av is not positive); sc[4] = alpha, sc[5] = the
+// decrease of the squared A-norm error, (v.r0)^2 / v.Av.
+__global__ void k_ws_alpha(const double *__restrict__ part, int nb, double *__restrict__ sc)
+{
+  const double a = sum_partials(part, 0, nb);
+  const double c = sum_partials(part, 1, nb);
+  if (threadIdx.x == 0) {
+    const bool ok = c > 0.0 && isfinite(a / c);
+    sc[4] = ok ? a / c : 0.0;
+    sc[5] = ok ? a * a / c : 0.0;
+  }
+}
+
+// p = p^n + alpha v.
+__global__ void k_ws_guess(unsigned n, const double *__restrict__ pn, const double *__restrict__ v,
                            const double *__restrict__ sc, double *__restrict__ p)
 {
-  const double s = gain * sc[0];
-  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = pn[i] + s * (double)y[i];
+  const double al = sc[4];
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = pn[i] + al * v[i];
 }
 
 // Partial sums of (b - q)^2 / d.
@@ -666,10 +701,14 @@ __global__ void k_ws_target(unsigned n, const double *__restrict__ p, const doub
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) t[i] = (float)((p[i] - pn[i]) * inv);
 }
 
-// Build the network input from the solve's initial residual; with the guess
-// enabled, start from p^n + gain s0 f(input) when its Jacobi-scaled residual is
-// smaller than that of p^n (s->p holds p^n on entry, the start on exit).
-vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, const double *zero_flag)
+// Build the network input from the solve's initial residual.  With the guess
+// enabled, take the network output v as a search direction from p^n with the
+// step alpha that minimises the A-norm error, and start from p^n + alpha v
+// whenever that error decreases (v.Av > 0 and v.r0 != 0); the Jacobi-scaled
+// residual of both starts is reported, not used to choose: a smooth error mode
+// carries a large error and a tiny residual.  s->p holds p^n on entry, the
+// start on exit.  Scratch: q, rd, r0 (CG overwrites them).
+vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double *r0, const double *zero_flag)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
@@ -678,20 +717,25 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, const 
   double *sc = sc_block(s, SC_WS);
   float *x = vosint::unet_input(s->net);
   k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, q, s->part, zero_flag);
-  k_ws_r0<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, rd, s->part);
+  k_ws_r0<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, r0, rd, s->part);
   k_ws_stats<<<1, TPB, 0, st>>>(s->part, nb, n, sc);
   k_ws_input<<<nb, TPB, 0, st>>>(g, s->eps, rd, sc, x);
   s->ws_used = 0;
   s->ws_res_guess = 0.0;
   if (s->ws_use) {
     if (vos_status e = vosint::unet_forward_on(s->net, st)) return e;
-    k_ws_guess<<<nb, TPB, 0, st>>>(n, s->pn, vosint::unet_output(s->net), s->ws_gain, sc, s->p);
+    double *v = rd;   // the scaled residual is no longer needed
+    k_ws_dir<<<nb, TPB, 0, st>>>(n, vosint::unet_output(s->net), v);
+    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], v, q, s->part, zero_flag);
+    k_ws_dots<<<nb, TPB, 0, st>>>(n, v, r0, q, s->part);
+    k_ws_alpha<<<1, TPB, 0, st>>>(s->part, nb, sc);
+    k_ws_guess<<<nb, TPB, 0, st>>>(n, s->pn, v, sc, s->p);
     k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
     k_ws_res<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, s->part);
     k_ws_store<<<1, TPB, 0, st>>>(s->part, nb, sc + 3);
   }
   HIP_TRY(hipGetLastError());
-  if (vos_status e = read_back(s, sc, 4)) return e;
+  if (vos_status e = read_back(s, sc, 6)) return e;
   const double *h = s->host;
   s->ws_s0 = h[0];
   s->ws_sampled = true;
@@ -699,7 +743,7 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, const 
   s->ws_res_prev = std::sqrt(h[1] / bn);
   if (s->ws_use) {
     s->ws_res_guess = std::sqrt(h[3] / bn);
-    if (h[3] < h[1] && std::isfinite(h[3])) {
+    if (h[5] > 0.0 && std::isfinite(h[3])) {
       s->ws_used = 1;
     } else {
       HIP_TRY(hipMemcpyAsync(s->p, s->pn, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -723,7 +767,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   HIP_TRY(hipMemcpyAsync(s->pn, s->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b);
   if (s->net)
-    if (vos_status e = warm_start(s, b, q, z, zero_flag)) return e;
+    if (vos_status e = warm_start(s, b, q, z, pv, zero_flag)) return e;
   k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, r, z, pv, 0, s->part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
