@@ -1364,3 +1364,26 @@ vos_status vos_warm_start_sample(vos_sim *s, float *x_dev, float *target_dev)
 }
 
 }  // extern "C"
+
+namespace vosint {
+
+vos_status set_tuning(vos_sim *s, int check_every, int coarse_cells)
+{
+  if (!s) return fail(VOS_ERR_ARG, "NULL simulation");
+  if (check_every < 1 || check_every > 256) return fail(VOS_ERR_ARG, "check_every must be in [1, 256]");
+  if (coarse_cells != 0 && (coarse_cells < 64 || coarse_cells > 65536))
+    return fail(VOS_ERR_ARG, "coarse_cells must be 0 or in [64, 65536]");
+  drop_graphs(s);   // captured chunks hold the old chunk length and coarse split
+  s->opt.check_every = check_every;
+  s->opt.coarse_cells = coarse_cells;
+  s->coarse_cells = coarse_cells > 0 ? coarse_cells : VC_BLOCK_MAX;
+  return VOS_OK;
+}
+
+void get_tuning(const vos_sim *s, int *check_every, int *coarse_cells)
+{
+  *check_every = s->opt.check_every;
+  *coarse_cells = s->opt.coarse_cells;
+}
+
+}  // namespace vosint

@@ -24,4 +24,9 @@ float *unet_output(vos_unet *net);
 // enqueued on `stream`.
 vos_status unet_forward_on(vos_unet *net, hipStream_t stream);
 
+// Launch tuning of a simulation (same ranges as vos_opts); drops its
+// captured graphs.  Neither value changes the workspace layout.
+vos_status set_tuning(vos_sim *s, int check_every, int coarse_cells);
+void get_tuning(const vos_sim *s, int *check_every, int *coarse_cells);
+
 }  // namespace vosint

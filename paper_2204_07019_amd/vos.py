@@ -151,7 +151,27 @@ class Sim:
                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
 
+    @classmethod
+    def borrowed(cls, handle, nx: int, ny: int, nz: int, dx: float, params: dict, device: str = "cuda:0"):
+        """Wrap a handle owned elsewhere (a batch instance): same methods,
+        close() does not destroy it."""
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shape = (nz, ny, nx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.grid = _Grid(nx, ny, nz, dx)
+        keys = [k for k, _ in _Params._fields_]
+        self.params = _Params(**{k: params[k] for k in keys})
+        self._h = handle
+        self._borrowed = True
+        return self
+
     def close(self):
+        if getattr(self, "_borrowed", False):
+            self._h = None
+            return
         if getattr(self, "_h", None):
             lib().vos_destroy(self._h)
             self._h = None
