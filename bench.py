@@ -152,6 +152,110 @@ def pressure_3d(vos, inputs, n, dt):
     return out
 
 
+BATCH_SIZES = ((256, 128), (512, 256), (768, 384), (1024, 512))
+
+
+def batch_bench(vos, inputs, scaling, n, steps, dt, seed=2, relax=5):
+    """Many micromodels at once: n RSA-disc micromodels with sizes drawn from
+    BATCH_SIZES, Pe ~ logU[0.1, 100], Da ~ logU[1e-3, 1], iVoS, mixed
+    precision, advanced together by the batch API after autotuning."""
+    import numpy as np
+    import torch
+    from paper_2204_07019_amd.batch import Batch
+    rng = np.random.default_rng(seed)
+    picks = rng.integers(0, len(BATCH_SIZES), n)
+    pe = 10 ** rng.uniform(-1, 2, n)
+    da = 10 ** rng.uniform(-3, 0, n)
+    base = dict(inputs.BASE_PARAMS, model=0)
+    specs = [(BATCH_SIZES[k][0], BATCH_SIZES[k][1], 1, 5e-6, dict(base, kc=0.0)) for k in picks]
+    opts = vos.Opts(precision=vos.MIXED, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=8)
+    b = Batch(specs, opts)
+    for i, (nx, ny, *_rest) in enumerate(specs):
+        b.sims[i].set_solid_fraction(inputs.rsa_discs(nx, ny, seed=100 + i))
+    d = b.step(dt, relax, freeze_solid=True)
+    for i, s in enumerate(b.sims):
+        phi = float(s.get("eps").mean())
+        u_in, kc = scaling.inlet_for(pe[i], da[i], d[i]["K"], phi, base["D"], 2)
+        r = u_in / base["u_in"]
+        for f in ("ux", "uy"):
+            s.set(f, s.get(f) * r)
+        s.set("p", (s.get("p") - base["p_out"]) * r + base["p_out"])
+        s.set_params(dict(base, u_in=u_in, kc=kc))
+    b.step(dt, 2, freeze_solid=True)
+    tuned = b.tune(dt, probe_steps=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diags = b.step(dt, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = sum(nx * ny for (nx, ny, *_r) in specs)
+    out = {"workload": f"{n} RSA micromodels, sizes from {['%dx%d' % s for s in BATCH_SIZES]}, "
+                       f"Pe logU[0.1,100], Da logU[1e-3,1], iVoS, mixed, dt={dt:g}s, rtol 1e-8",
+           "instances": n, "cells": cells, "steps": steps,
+           "value": cells * steps / el, "unit": "cell-steps/s", "ms_per_batch_step": el / steps * 1e3,
+           "tuned": tuned,
+           "max_its_p": max(dg["it_p"] for dg in diags), "max_its_c": max(dg["it_c"] for dg in diags)}
+    b.close()
+    return out
+
+
+# U-Net layer shapes (input, output channels) and levels, for the FLOP count.
+UNET_LAYERS = ((16, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2), (64, 64, 2),
+               (96, 32, 1), (32, 32, 1), (48, 16, 0), (16, 16, 0))
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def unet_flops(voxels, train):
+    """Convolution FLOPs (2 per multiply-add) of one forward pass, or of one
+    training step (forward + data gradient of every layer but the first +
+    weight gradient)."""
+    fwd = sum(2 * 27 * ci * co * voxels / 8 ** lv for ci, co, lv in UNET_LAYERS)
+    if not train:
+        return fwd
+    dg = sum(2 * 27 * ci * co * voxels / 8 ** lv for ci, co, lv in UNET_LAYERS[1:])
+    return 2 * fwd + dg
+
+
+def unet_bench(inputs, n, batch_train, reps=5):
+    """Forward (batch 1) and training step (batch_train) of the warm-start
+    U-Net on n^3 voxels, timed with HIP events on the network's stream."""
+    import ctypes as C
+    import torch
+    from paper_2204_07019_amd import unet as U
+    out = {}
+    for name, b, train in (("forward", 1, False), ("train_step", batch_train, True)):
+        net = U.UNet(b, n, n, n, cin=4, train=train)
+        net.set_params(inputs.unet_init(0))
+        x = torch.randn(b, n, n, n, 4, device="cuda")
+        t = torch.randn(b, n, n, n, device="cuda")
+        y = torch.empty(b, n, n, n, device="cuda")
+        torch.cuda.synchronize()
+        L = U.lib()
+
+        def run():
+            if train:
+                vos_rc = L.vos_unet_train_step(net._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                               C.c_float(1e-5), None)
+            else:
+                vos_rc = L.vos_unet_forward(net._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()))
+            assert vos_rc == 0, L.vos_last_error()
+        run()
+        net.stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(reps):
+            run()
+        e1.record(net.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = unet_flops(b * n ** 3, train) / ms / 1e9
+        out[name] = {"batch": b, "voxels": b * n ** 3, "ms": round(ms, 3), "TFLOPs": round(tf, 1),
+                     "frac_bf16_peak": round(tf / BF16_PEAK_TFLOPS, 4)}
+        net.close()
+    return out
+
+
 def cpu_baseline(workload, params, dt, budget_s):
     """The oracle (plain C, one thread) on a bounded sample of the workload:
     a crop of the same geometry, one step at a time until the budget is used."""
@@ -198,6 +302,11 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-micromodel batch")
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-unet", action="store_true", help="skip the U-Net timing")
+    ap.add_argument("--unet-n", type=int, default=128)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -261,6 +370,15 @@ def main():
     roof = roofline(sim, args.timer)
     others = {k: roofline(sim, k) for k in ("v_post", "v_pre", "p_apply", "adr_apply")}
     p3d = None if args.no_3d else pressure_3d(vos, inputs, args.n3d, args.dt)
+    bat = None
+    if not args.no_batch:
+        log(f"batch of {args.batch_n} micromodels")
+        bat = batch_bench(vos, inputs, scaling, args.batch_n, args.batch_steps, args.dt)
+        log(f"batch: {bat['value']:.3e} cell-steps/s, {bat['ms_per_batch_step']:.1f} ms per batch step")
+    net = None
+    if not args.no_unet:
+        log(f"U-Net {args.unet_n}^3")
+        net = unet_bench(inputs, args.unet_n, 2)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -292,6 +410,8 @@ def main():
         "roofline": roof,
         "roofline_other_kernels": others,
         "pressure_solve_3d": p3d,
+        "batch_micromodels": bat,
+        "unet": net,
         "cpu_baseline": cpu,
     }
     sim.close()

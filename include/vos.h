@@ -63,12 +63,15 @@ typedef enum {
   VOS_PSI_PRIME = 2    /* psi = lambda(eps) eps (1 - eps), lambda refitted every step */
 } vos_model;
 
-/* Arithmetic of the pressure multigrid preconditioner. */
+/* Arithmetic of the multigrid preconditioners. */
 typedef enum {
   VOS_FP64 = 0,        /* everything FP64 */
   VOS_MIXED = 1        /* FP32 multigrid (smoothing, restriction, prolongation)
-                          inside FP64 CG: residuals, dot products, right-hand
-                          side and every global balance stay FP64 */
+                          for the pressure and momentum systems inside FP64 CG:
+                          residuals, dot products, right-hand sides and every
+                          global balance stay FP64.  The transport hierarchy is
+                          FP64 in both modes (its coarse operators of
+                          upwind-dominated rows lose their diagonal in FP32) */
 } vos_precision;
 
 /* Physical parameters (Tables 1-3 of the paper give realistic values). */

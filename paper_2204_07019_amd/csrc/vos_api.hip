@@ -190,7 +190,9 @@ Layout make_layout(const vos_grid &g, int precision)
     if (d < nd) plan_smg(P, Lo.smg[d], D0.fd[d][0], D0.fd[d][1], D0.fd[d][2], nd, rs);
     else Lo.smg[d].nlev = 0;
   }
-  plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, rs);
+  // the transport hierarchy is FP64 in both precisions: its Galerkin coarse
+  // diagonals of upwind-dominated rows cancel to near zero and break down in FP32
+  plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, sizeof(double));
   Lo.total = P.off;
   return Lo;
 }
@@ -860,8 +862,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
 
 vos_status solve_transport(vos_sim *s, int *its, double *res)
 {
-  if (s->opt.precision == VOS_MIXED) return solve_transport_t<float>(s, s->smgf[3], its, res);
-  return solve_transport_t<double>(s, s->smgd[3], its, res);
+  return solve_transport_t<double>(s, s->smgd[3], its, res);   // FP64 hierarchy in both precisions
 }
 
 // ---------------------------------------------------------------- stages S6-S7
@@ -1315,7 +1316,6 @@ vos_status vos_time_kernel(vos_sim *s, int family, int reps, double *avg_launch_
   if (!s || !avg_launch_ms || !bytes_per_launch) return fail(VOS_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 100000) return fail(VOS_ERR_ARG, "reps must be in [1, 100000]");
   if (!s->stepped) return fail(VOS_ERR_STATE, "run vos_step first");
-  if (s->opt.precision == VOS_MIXED) return time_kernel_t<float>(s, s->smgf[3], family, reps, avg_launch_ms, bytes_per_launch);
   return time_kernel_t<double>(s, s->smgd[3], family, reps, avg_launch_ms, bytes_per_launch);
 }
 
