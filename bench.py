@@ -27,11 +27,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per cell of one pressure PCG iteration in 2-D with the FP32
-# hierarchy (each array read or written once): outer FP64 CG 136 B (apply
-# 32, x/r update 56, z.r/z.q 24, direction 24) + V-cycle 173 B (finest level
-# 130 B x 4/3 for the coarser levels).  FP64 hierarchy: 136 + 292.
-P_ITER_BYTES = {("mixed", 2): 136 + 173, ("fp64", 2): 136 + 292,
+# Algorithmic bytes per cell of one pressure PCG iteration (each array read or
+# written once per launch): outer FP64 CG 136 B in 2-D (apply 32, x/r update
+# 56, z.r/z.q 24, direction 24), 152 B in 3-D, plus one V-cycle.  2-D V-cycle
+# (tiled kernels): finest level down leg r 8 + diag + 2 face T + b + x + coarse
+# b/4, up leg x + coarse x/4 + b + diag + 2 face T + result + z 8, times 4/3
+# for the coarser levels: FP32 hierarchy 83 B, FP64 144 B.  3-D V-cycle
+# (per-sweep kernels, two sweeps): FP32 187 B, FP64 318 B.
+P_ITER_BYTES = {("mixed", 2): 136 + 83, ("fp64", 2): 136 + 144,
                 ("mixed", 3): 152 + 187, ("fp64", 3): 152 + 318}
 # Per-step pressure setup (hierarchy build, right-hand side, initial residual):
 P_SETUP_BYTES = {2: 150, 3: 200}
@@ -296,7 +299,7 @@ def main():
     ap.add_argument("--model", type=int, default=0)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--relax", type=int, default=40)
-    ap.add_argument("--timer", default="v_restrict", help="kernel family for the live roofline")
+    ap.add_argument("--timer", default="v_down", help="kernel family for the live roofline")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D pressure-solve measurement")
     ap.add_argument("--n3d", type=int, default=256)
     ap.add_argument("--skip-plain", action="store_true")
@@ -368,7 +371,7 @@ def main():
         sim64.close()
 
     roof = roofline(sim, args.timer)
-    others = {k: roofline(sim, k) for k in ("v_post", "v_pre", "p_apply", "adr_apply")}
+    others = {k: roofline(sim, k) for k in ("v_up", "v_coarse", "p_apply", "adr_apply")}
     p3d = None if args.no_3d else pressure_3d(vos, inputs, args.n3d, args.dt)
     bat = None
     if not args.no_batch:

@@ -97,14 +97,15 @@ typedef struct {
   double rtol_u, rtol_p, rtol_c;
   int maxit_u, maxit_p, maxit_c;
   int precision;    /* vos_precision (pressure multigrid) */
-  int mg_nu;        /* Jacobi sweeps before and after each coarse correction (>= 1) */
+  int mg_nu;        /* Jacobi sweeps before and after each coarse correction, 1..8;
+                       0: 4 in 2-D, 2 in 3-D */
   int check_every;  /* Krylov iterations launched between host convergence checks, 1..256 */
   int use_graphs;   /* 1: capture each solve's chunk of check_every iterations in a HIP graph
                        once and replay it (iteration counts then round up to a multiple of
                        check_every in the worst case; results are identical); 0: plain launches.
                        Ignored (off) when vos_create() is given the null stream. */
   int coarse_cells; /* multigrid levels with at most this many cells run inside one single-block
-                       kernel (0: the default, 4096); 64..65536 */
+                       kernel, 64..65536 (0: 1024 in 2-D, 4096 in 3-D) */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */
@@ -204,7 +205,9 @@ typedef enum {
   VOS_KERNEL_V_PRE = 2,       /* first two pre-smoothing sweeps, same levels */
   VOS_KERNEL_V_COARSE = 3,    /* the single-block coarse tail of the transport V-cycle */
   VOS_KERNEL_P_APPLY = 4,     /* pressure operator application (FP64) */
-  VOS_KERNEL_ADR_APPLY = 5    /* transport operator application (FP64) */
+  VOS_KERNEL_ADR_APPLY = 5,   /* transport operator application (FP64) */
+  VOS_KERNEL_V_DOWN = 6,      /* 2-D tiled down leg (pre-sweeps + restriction), finest transport level */
+  VOS_KERNEL_V_UP = 7         /* 2-D tiled up leg (prolongation + post-sweeps), finest transport level */
 } vos_kernel_family;
 
 /* Time `reps` back-to-back launch sequences of one kernel family on the live

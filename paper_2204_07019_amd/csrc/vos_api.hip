@@ -309,7 +309,7 @@ vos_status check_opts(const vos_opts *o)
   if (!(o->rtol_u > 0) || !(o->rtol_p > 0) || !(o->rtol_c > 0)) return fail(VOS_ERR_ARG, "tolerances must be > 0");
   if (o->maxit_u < 1 || o->maxit_p < 1 || o->maxit_c < 1) return fail(VOS_ERR_ARG, "maxit must be >= 1");
   if (o->precision != VOS_FP64 && o->precision != VOS_MIXED) return fail(VOS_ERR_ARG, "unknown precision");
-  if (o->mg_nu < 1 || o->mg_nu > 8) return fail(VOS_ERR_ARG, "mg_nu must be in [1, 8]");
+  if (o->mg_nu < 0 || o->mg_nu > 8) return fail(VOS_ERR_ARG, "mg_nu must be in [0, 8]");
   if (o->check_every < 1 || o->check_every > 256) return fail(VOS_ERR_ARG, "check_every must be in [1, 256]");
   if (o->coarse_cells != 0 && (o->coarse_cells < 64 || o->coarse_cells > 65536))
     return fail(VOS_ERR_ARG, "coarse_cells must be 0 or in [64, 65536]");
@@ -443,9 +443,21 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   const int nu = s->opt.mg_nu;
   int lc = 0;
   while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
+  // 2-D levels with 2..4 sweeps each way: one tiled kernel per leg (vos_vcycle.h)
+  auto tiled = [&](const Lv &F) { return nd == 2 && nu >= 2 && nu <= 4 && F.n[0] >= 2 && F.n[1] >= 2; };
+  auto tgrid = [](const Lv &F) { return dim3((F.n[0] + VT_X - 1) / VT_X, (F.n[1] + VT_Y - 1) / VT_Y); };
   for (int l = 0; l < lc; ++l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
+    if (tiled(F)) {
+      const dim3 gr = tgrid(F);
+#define VDOWN(NU_)                                                                                   \
+  if (l == 0) k_v_down2d<Lv, R, true, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc); \
+  else k_v_down2d<Lv, R, false, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc);
+      if (nu == 2) { VDOWN(2) } else if (nu == 3) { VDOWN(3) } else { VDOWN(4) }
+#undef VDOWN
+      continue;
+    }
     {
       if (nu == 1) {
         if (l == 0) k_v_pre<Lv, R, true, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
@@ -472,6 +484,16 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   for (int l = lc - 1; l >= 0; --l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
+    if (tiled(F)) {
+      const dim3 gr = tgrid(F);
+#define VUP(NU_)                                                                                      \
+  if (l == 0) k_v_up2d<Lv, R, true, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, sc);       \
+  else k_v_up2d<Lv, R, false, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, sc);
+      if (nu == 2) { VUP(2) } else if (nu == 3) { VUP(3) } else { VUP(4) }
+#undef VUP
+      std::swap(F.x, F.t);
+      continue;
+    }
     {
       const bool out = (l == 0 && nu == 1);
       if (out) k_v_post<Lv, R, true><<<nb, TPB, 0, st>>>(F, lv[l + 1], nd, F.t, om, z, dsc, sc);
@@ -1075,6 +1097,24 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
         }
         break;
       }
+      case VOS_KERNEL_V_DOWN:
+      case VOS_KERNEL_V_UP: {
+        // the tiled 2-D kernels of the finest level
+        const dim3 gr((lv[0].n[0] + VT_X - 1) / VT_X, (lv[0].n[1] + VT_Y - 1) / VT_Y);
+        const int nu = s->opt.mg_nu;
+        if (family == VOS_KERNEL_V_DOWN) {
+          if (nu == 2) k_v_down2d<SLevel<R>, R, false, 2><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
+          else if (nu == 3) k_v_down2d<SLevel<R>, R, false, 3><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
+          else k_v_down2d<SLevel<R>, R, false, 4><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
+          if (count) { per_seq_bytes += (3.0 + 2 * nd) * Rs * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
+        } else {
+          if (nu == 2) k_v_up2d<SLevel<R>, R, false, 2><<<gr, TPB, 0, st>>>(lv[0], lv[1], lv[0].t, om, nullptr, nullptr, flag);
+          else if (nu == 3) k_v_up2d<SLevel<R>, R, false, 3><<<gr, TPB, 0, st>>>(lv[0], lv[1], lv[0].t, om, nullptr, nullptr, flag);
+          else k_v_up2d<SLevel<R>, R, false, 4><<<gr, TPB, 0, st>>>(lv[0], lv[1], lv[0].t, om, nullptr, nullptr, flag);
+          if (count) { per_seq_bytes += (4.0 + 2 * nd) * Rs * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
+        }
+        break;
+      }
       case VOS_KERNEL_P_APPLY:
         k_p_apply<<<grid_blocks(g.nc), TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, s->vec[4], s->part, flag);
         if (count) { per_seq_bytes += (2.0 + nd) * 8.0 * g.nc; ++per_seq_launches; }
@@ -1085,7 +1125,10 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
         break;
     }
   };
-  if (family < VOS_KERNEL_V_RESTRICT || family > VOS_KERNEL_ADR_APPLY) return fail(VOS_ERR_ARG, "unknown kernel family");
+  if (family < VOS_KERNEL_V_RESTRICT || family > VOS_KERNEL_V_UP) return fail(VOS_ERR_ARG, "unknown kernel family");
+  if ((family == VOS_KERNEL_V_DOWN || family == VOS_KERNEL_V_UP) &&
+      !(nd == 2 && s->opt.mg_nu >= 2 && s->opt.mg_nu <= 4 && lc >= 1 && lv[0].n[0] >= 2 && lv[0].n[1] >= 2))
+    return fail(VOS_ERR_ARG, "the tiled V-cycle kernels run on 2-D levels with 2..4 sweeps only");
   seq(true);   // warm-up, counts the launches of one sequence
   if (per_seq_launches == 0) return fail(VOS_ERR_STATE, "the hierarchy has no level of that kind");
   HIP_TRY(hipEventRecord(s->ev[0], st));
@@ -1185,7 +1228,10 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   }
   s->capturing = false;
   s->p_scale = 0.0;
-  s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : VC_BLOCK_MAX;
+  // defaults (0): in 2-D four sweeps with the tiled fine-level kernels and a
+  // 1024-cell single-block tail; in 3-D two sweeps and a 4096-cell tail
+  if (s->opt.mg_nu == 0) s->opt.mg_nu = grid->nz == 1 ? 4 : 2;
+  s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? 1024 : VC_BLOCK_MAX);
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
 
@@ -1376,7 +1422,7 @@ vos_status set_tuning(vos_sim *s, int check_every, int coarse_cells)
   drop_graphs(s);   // captured chunks hold the old chunk length and coarse split
   s->opt.check_every = check_every;
   s->opt.coarse_cells = coarse_cells;
-  s->coarse_cells = coarse_cells > 0 ? coarse_cells : VC_BLOCK_MAX;
+  s->coarse_cells = coarse_cells > 0 ? coarse_cells : (s->g.nd == 2 ? 1024 : VC_BLOCK_MAX);
   return VOS_OK;
 }
 

@@ -196,6 +196,209 @@ __global__ void __launch_bounds__(TPB) k_v_post(Lv F, Lv C, int nd, R *__restric
   }
 }
 
+// ------------------------------------------------------------------ 2-D tiled fine-level kernels
+//
+// On a 2-D level the launches of a fine level (pre-smoothing sweeps,
+// restriction, prolongation + post-smoothing sweeps) become two: each block
+// owns a VT_X x VT_Y tile and recomputes the NU sweeps on a halo that shrinks
+// by one cell per sweep (tile + NU, ..., tile + 1, tile), so no grid-wide
+// synchronisation is needed between the sweeps.  Every cell value is formed by
+// the same expression, in the same order, as in the unfused kernels above
+// (sweeps 1-2 as k_v_pre, later pre-sweeps and the residual as k_v_jacobi /
+// k_v_restrict, the first post-sweep as k_v_post, later ones as k_v_jacobi).
+
+constexpr int VT_X = 32, VT_Y = 16;   // tile (both even: aggregates stay inside)
+
+template <int NU>
+struct VHalo {
+  static constexpr int W = VT_X + 2 * NU, H = VT_Y + 2 * NU;
+};
+
+// Neighbour term from an LDS coefficient: SLevel adds off * x, MgLevel
+// subtracts T * x (o = -T), matching lv_term.
+template <typename R>
+__device__ __forceinline__ R lds_term(const SLevel<R> &, R v, R o, R xn) { return v + o * xn; }
+template <typename R>
+__device__ __forceinline__ R lds_term(const MgLevel<R> &, R v, R o, R xn) { return v - (-o) * xn; }
+
+// A x at a tile cell from LDS arrays (lv_apply order); os[k] holds the
+// coefficient towards neighbour slot k (0 where there is no neighbour).
+template <typename Lv, typename R, int W, int H>
+__device__ __forceinline__ R tile_apply(const Lv &L, const R (*os)[H][W], R dg, const R (*x)[W], int lx, int ly,
+                                        const int c[3])
+{
+  R v = dg * x[ly][lx];
+  if (c[0] > 0) v = lds_term(L, v, os[0][ly][lx], x[ly][lx - 1]);
+  if (c[0] < L.n[0] - 1) v = lds_term(L, v, os[1][ly][lx], x[ly][lx + 1]);
+  if (c[1] > 0) v = lds_term(L, v, os[2][ly][lx], x[ly - 1][lx]);
+  if (c[1] < L.n[1] - 1) v = lds_term(L, v, os[3][ly][lx], x[ly + 1][lx]);
+  return v;
+}
+
+// A x in the k_v_pre / k_v_post order: d x + sum of off * x.
+template <typename Lv, typename R, int W, int H>
+__device__ __forceinline__ R tile_apply_off(const Lv &L, const R (*os)[H][W], R dg, const R (*x)[W], int lx, int ly,
+                                            const int c[3])
+{
+  R v = dg * x[ly][lx];
+  if (c[0] > 0) v += os[0][ly][lx] * x[ly][lx - 1];
+  if (c[0] < L.n[0] - 1) v += os[1][ly][lx] * x[ly][lx + 1];
+  if (c[1] > 0) v += os[2][ly][lx] * x[ly - 1][lx];
+  if (c[1] < L.n[1] - 1) v += os[3][ly][lx] * x[ly + 1][lx];
+  return v;
+}
+
+// The four neighbour coefficients of an in-domain cell into LDS.
+template <typename Lv, typename R, int W, int H>
+__device__ __forceinline__ void load_coef(const Lv &L, R (*os)[H][W], int lx, int ly, unsigned id, const int c[3])
+{
+  os[0][ly][lx] = c[0] > 0 ? lv_off(L, id, c, 0) : (R)0;
+  os[1][ly][lx] = c[0] < L.n[0] - 1 ? lv_off(L, id, c, 1) : (R)0;
+  os[2][ly][lx] = c[1] > 0 ? lv_off(L, id, c, 2) : (R)0;
+  os[3][ly][lx] = c[1] < L.n[1] - 1 ? lv_off(L, id, c, 3) : (R)0;
+}
+
+// Down leg of a 2-D fine level: NU damped-Jacobi sweeps from zero, then the
+// residual restricted to the coarse right-hand side.  F.x receives the
+// smoothed iterate (tile cells); with FROM64, F.b the scaled right-hand side.
+// Grid (ceil(nx / VT_X), ceil(ny / VT_Y)), block TPB.
+template <typename Lv, typename R, bool FROM64, int NU>
+__global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__restrict__ r64,
+                                                  const double *__restrict__ dsc, double rscale, R omega,
+                                                  const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
+  __shared__ R bs[H][W], ds[H][W], xa[H][W], xb[H][W], os[4][H][W];
+  const int nx = F.n[0], ny = F.n[1];
+  const int X0 = blockIdx.x * VT_X - NU, Y0 = blockIdx.y * VT_Y - NU;   // global coords of LDS cell (0, 0)
+  for (int t = threadIdx.x; t < W * H; t += TPB) {
+    const int lx = t % W, ly = t / W;
+    const int gx = X0 + lx, gy = Y0 + ly;
+    R bb = 0, dg = 1, v = 0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
+      const int c[3] = {gx, gy, 0};
+      if (FROM64) bb = (R)(rscale * (dsc ? r64[id] / sqrt(dsc[id]) : r64[id]));
+      else bb = F.b[id];
+      if (FROM64 && lx >= NU && lx < VT_X + NU && ly >= NU && ly < VT_Y + NU) F.b[id] = bb;
+      dg = F.diag[id];
+      v = omega * bb / dg;
+      load_coef<Lv, R, W, H>(F, os, lx, ly, id, c);
+    }
+    bs[ly][lx] = bb;
+    ds[ly][lx] = dg;
+    xa[ly][lx] = v;
+  }
+  __syncthreads();
+  // sweeps 2..NU on a halo shrinking from NU - 1 to 1 (ping-pong xa -> xb -> xa ...)
+#pragma unroll
+  for (int k = 2; k <= NU; ++k) {
+    const int h = NU - k + 1;
+    R(*src)[W] = (k % 2 == 0) ? xa : xb;
+    R(*dst)[W] = (k % 2 == 0) ? xb : xa;
+    for (int t = threadIdx.x; t < (VT_X + 2 * h) * (VT_Y + 2 * h); t += TPB) {
+      const int lx = NU - h + t % (VT_X + 2 * h), ly = NU - h + t / (VT_X + 2 * h);
+      const int gx = X0 + lx, gy = Y0 + ly;
+      if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
+      const int c[3] = {gx, gy, 0};
+      const R dg = ds[ly][lx];
+      const R ax = (k == 2) ? tile_apply_off<Lv, R, W, H>(F, os, dg, src, lx, ly, c)
+                            : tile_apply<Lv, R, W, H>(F, os, dg, src, lx, ly, c);
+      dst[ly][lx] = src[ly][lx] + omega * (bs[ly][lx] - ax) / dg;
+    }
+    __syncthreads();
+  }
+  R(*xf)[W] = (NU % 2 == 0) ? xb : xa;   // the last sweep's output
+  // residual on the tile, x to F.x
+  constexpr int PER = (VT_X * VT_Y + TPB - 1) / TPB;
+  R res[PER];
+  int q = 0;
+  for (int t = threadIdx.x; t < VT_X * VT_Y; t += TPB, ++q) {
+    const int lx = NU + t % VT_X, ly = NU + t / VT_X;
+    const int gx = X0 + lx, gy = Y0 + ly;
+    res[q] = 0;
+    if (gx >= nx || gy >= ny) continue;
+    const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
+    const int c[3] = {gx, gy, 0};
+    F.x[id] = xf[ly][lx];
+    res[q] = bs[ly][lx] - tile_apply<Lv, R, W, H>(F, os, ds[ly][lx], xf, lx, ly, c);
+  }
+  __syncthreads();
+  q = 0;
+  for (int t = threadIdx.x; t < VT_X * VT_Y; t += TPB, ++q) bs[NU + t / VT_X][NU + t % VT_X] = res[q];
+  __syncthreads();
+  // restriction: sum over each 2 x 2 aggregate (cy outer, cx inner)
+  for (int t = threadIdx.x; t < (VT_X / 2) * (VT_Y / 2); t += TPB) {
+    const int ix = t % (VT_X / 2), iy = t / (VT_X / 2);
+    const int IX = blockIdx.x * (VT_X / 2) + ix, IY = blockIdx.y * (VT_Y / 2) + iy;
+    if (IX >= C.n[0] || IY >= C.n[1]) continue;
+    R sum = 0;
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        if (2 * IX + cx >= nx || 2 * IY + cy >= ny) continue;
+        sum += bs[NU + 2 * iy + cy][NU + 2 * ix + cx];
+      }
+    C.b[(unsigned)IX + (unsigned)C.n[0] * (unsigned)IY] = sum;
+  }
+}
+
+// Up leg of a 2-D fine level: prolongation of the coarse correction and NU
+// post-smoothing sweeps.  Reads F.x, F.b, C.x; writes the result to xo (a
+// buffer other than F.x: neighbouring tiles still read F.x) and, with OUT64,
+// z = unscale(result).
+template <typename Lv, typename R, bool OUT64, int NU>
+__global__ void __launch_bounds__(TPB) k_v_up2d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z,
+                                                const double *__restrict__ dsc, const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
+  __shared__ R ya[H][W], yb[H][W], bs[H][W], ds[H][W], os[4][H][W];
+  const int nx = F.n[0], ny = F.n[1];
+  const int X0 = blockIdx.x * VT_X - NU, Y0 = blockIdx.y * VT_Y - NU;
+  for (int t = threadIdx.x; t < W * H; t += TPB) {
+    const int lx = t % W, ly = t / W;
+    const int gx = X0 + lx, gy = Y0 + ly;
+    R v = 0, bb = 0, dg = 1;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
+      const int c[3] = {gx, gy, 0};
+      v = F.x[id] + C.x[parent_of<R>(F.n, C.n, 2, c)];
+      bb = F.b[id];
+      dg = F.diag[id];
+      load_coef<Lv, R, W, H>(F, os, lx, ly, id, c);
+    }
+    ya[ly][lx] = v;
+    bs[ly][lx] = bb;
+    ds[ly][lx] = dg;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 1; k <= NU; ++k) {
+    const int h = NU - k;
+    R(*src)[W] = (k % 2 == 1) ? ya : yb;
+    R(*dst)[W] = (k % 2 == 1) ? yb : ya;
+    for (int t = threadIdx.x; t < (VT_X + 2 * h) * (VT_Y + 2 * h); t += TPB) {
+      const int lx = NU - h + t % (VT_X + 2 * h), ly = NU - h + t / (VT_X + 2 * h);
+      const int gx = X0 + lx, gy = Y0 + ly;
+      if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
+      const int c[3] = {gx, gy, 0};
+      const R dg = ds[ly][lx];
+      const R ay = (k == 1) ? tile_apply_off<Lv, R, W, H>(F, os, dg, src, lx, ly, c)
+                            : tile_apply<Lv, R, W, H>(F, os, dg, src, lx, ly, c);
+      const R o = src[ly][lx] + omega * (bs[ly][lx] - ay) / dg;
+      if (k < NU) {
+        dst[ly][lx] = o;
+      } else {
+        const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
+        xo[id] = o;
+        if (OUT64) z[id] = unscale((double)o, dsc, id);
+      }
+    }
+    if (k < NU) __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ single-block coarse tail
 
 template <typename Lv>

@@ -21,7 +21,8 @@ VOS_OK, VOS_ERR_ARG, VOS_ERR_DEVICE, VOS_ERR_NOCONV, VOS_ERR_OOM, VOS_ERR_STATE 
 IVOS, PSI, PSI_PRIME = 0, 1, 2
 FP64, MIXED = 0, 1
 FREEZE_SOLID = 1
-KERNELS = {"v_restrict": 0, "v_post": 1, "v_pre": 2, "v_coarse": 3, "p_apply": 4, "adr_apply": 5}
+KERNELS = {"v_restrict": 0, "v_post": 1, "v_pre": 2, "v_coarse": 3, "p_apply": 4, "adr_apply": 5,
+           "v_down": 6, "v_up": 7}
 FIELDS = {"eps": 0, "ux": 1, "uy": 2, "uz": 3, "p": 4, "c": 5, "ustar_x": 6, "ustar_y": 7,
           "ustar_z": 8, "rbar": 9, "gmag": 10}
 
@@ -119,7 +120,7 @@ class Opts:
     maxit_p: int = 2000
     maxit_c: int = 20000
     precision: int = FP64
-    mg_nu: int = 2
+    mg_nu: int = 0          # 0: library default (4 in 2-D, 2 in 3-D)
     check_every: int = 8
     use_graphs: int = 1
     coarse_cells: int = 0

@@ -46,7 +46,7 @@ def test_argument_errors_without_a_device():
     g = vos._Grid(64, 32, 1, 5e-6)
     assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) == vos.VOS_OK
     assert n.value > 64 * 32 * 8 * 20
-    bad = vos._Opts(**dict(vos.asdict(vos.Opts()), mg_nu=0))
+    bad = vos._Opts(**dict(vos.asdict(vos.Opts()), mg_nu=9))
     assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(n)) == vos.VOS_ERR_ARG
     mixed = vos._Opts(**dict(vos.asdict(vos.Opts()), precision=vos.MIXED))
     m = ctypes.c_size_t()
