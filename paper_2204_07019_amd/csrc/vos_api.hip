@@ -54,6 +54,14 @@ struct Plan {
   }
 };
 
+// Blocks of a tiled 2-D V-cycle kernel (vos_vcycle.h, tile_of): the tile
+// count rounded up to a multiple of the 8 XCDs.
+unsigned tile_blocks(int nx, int ny)
+{
+  const unsigned nt = (unsigned)((nx + VT_X - 1) / VT_X) * (unsigned)((ny + VT_Y - 1) / VT_Y);
+  return (nt + NXCD - 1) / NXCD * NXCD;
+}
+
 // Blocks of a sweep over n items: one item per thread up to MAXB blocks,
 // rounded up to a multiple of the 8 XCDs (XCD-aware ranges, vos_device.h).
 int grid_blocks(size_t n)
@@ -445,7 +453,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
   // 2-D levels with 2..4 sweeps each way: one tiled kernel per leg (vos_vcycle.h)
   auto tiled = [&](const Lv &F) { return nd == 2 && nu >= 2 && nu <= 4 && F.n[0] >= 2 && F.n[1] >= 2; };
-  auto tgrid = [](const Lv &F) { return dim3((F.n[0] + VT_X - 1) / VT_X, (F.n[1] + VT_Y - 1) / VT_Y); };
+  auto tgrid = [](const Lv &F) { return dim3(tile_blocks(F.n[0], F.n[1])); };
   for (int l = 0; l < lc; ++l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
@@ -1100,7 +1108,7 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_DOWN:
       case VOS_KERNEL_V_UP: {
         // the tiled 2-D kernels of the finest level
-        const dim3 gr((lv[0].n[0] + VT_X - 1) / VT_X, (lv[0].n[1] + VT_Y - 1) / VT_Y);
+        const dim3 gr(tile_blocks(lv[0].n[0], lv[0].n[1]));
         const int nu = s->opt.mg_nu;
         if (family == VOS_KERNEL_V_DOWN) {
           if (nu == 2) k_v_down2d<SLevel<R>, R, false, 2><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);

@@ -202,12 +202,28 @@ __global__ void __launch_bounds__(TPB) k_v_post(Lv F, Lv C, int nd, R *__restric
 // restriction, prolongation + post-smoothing sweeps) become two: each block
 // owns a VT_X x VT_Y tile and recomputes the NU sweeps on a halo that shrinks
 // by one cell per sweep (tile + NU, ..., tile + 1, tile), so no grid-wide
-// synchronisation is needed between the sweeps.  Every cell value is formed by
+// synchronisation is needed between the sweeps.  Grid: tile_of().  Every cell value is formed by
 // the same expression, in the same order, as in the unfused kernels above
 // (sweeps 1-2 as k_v_pre, later pre-sweeps and the residual as k_v_jacobi /
 // k_v_restrict, the first post-sweep as k_v_post, later ones as k_v_jacobi).
 
 constexpr int VT_X = 32, VT_Y = 16;   // tile (both even: aggregates stay inside)
+
+// XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs
+// (block b on XCD b % 8), so block b takes tile (b % 8) * per + b / 8 -- each
+// XCD sweeps one contiguous band of tiles, and a tile's halo neighbours are
+// mostly in the same XCD's L2.  Launch per * 8 blocks, per = ceil(tiles / 8).
+__device__ __forceinline__ bool tile_of(int nx, int ny, int &tx, int &ty)
+{
+  const int gx = (nx + VT_X - 1) / VT_X, gy = (ny + VT_Y - 1) / VT_Y;
+  const unsigned ntiles = (unsigned)gx * (unsigned)gy;
+  const unsigned per = (ntiles + NXCD - 1) / NXCD;
+  const unsigned t = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  if (t >= ntiles) return false;
+  tx = (int)(t % (unsigned)gx);
+  ty = (int)(t / (unsigned)gx);
+  return true;
+}
 
 template <int NU>
 struct VHalo {
@@ -261,7 +277,7 @@ __device__ __forceinline__ void load_coef(const Lv &L, R (*os)[H][W], int lx, in
 // Down leg of a 2-D fine level: NU damped-Jacobi sweeps from zero, then the
 // residual restricted to the coarse right-hand side.  F.x receives the
 // smoothed iterate (tile cells); with FROM64, F.b the scaled right-hand side.
-// Grid (ceil(nx / VT_X), ceil(ny / VT_Y)), block TPB.
+// Grid: tile_of(), block TPB.
 template <typename Lv, typename R, bool FROM64, int NU>
 __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__restrict__ r64,
                                                   const double *__restrict__ dsc, double rscale, R omega,
@@ -271,7 +287,9 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
   constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
   __shared__ R bs[H][W], ds[H][W], xa[H][W], xb[H][W], os[4][H][W];
   const int nx = F.n[0], ny = F.n[1];
-  const int X0 = blockIdx.x * VT_X - NU, Y0 = blockIdx.y * VT_Y - NU;   // global coords of LDS cell (0, 0)
+  int tx, ty;
+  if (!tile_of(nx, ny, tx, ty)) return;
+  const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;   // global coords of LDS cell (0, 0)
   for (int t = threadIdx.x; t < W * H; t += TPB) {
     const int lx = t % W, ly = t / W;
     const int gx = X0 + lx, gy = Y0 + ly;
@@ -331,7 +349,7 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
   // restriction: sum over each 2 x 2 aggregate (cy outer, cx inner)
   for (int t = threadIdx.x; t < (VT_X / 2) * (VT_Y / 2); t += TPB) {
     const int ix = t % (VT_X / 2), iy = t / (VT_X / 2);
-    const int IX = blockIdx.x * (VT_X / 2) + ix, IY = blockIdx.y * (VT_Y / 2) + iy;
+    const int IX = tx * (VT_X / 2) + ix, IY = ty * (VT_Y / 2) + iy;
     if (IX >= C.n[0] || IY >= C.n[1]) continue;
     R sum = 0;
     for (int cy = 0; cy < 2; ++cy)
@@ -355,7 +373,9 @@ __global__ void __launch_bounds__(TPB) k_v_up2d(Lv F, Lv C, R *__restrict__ xo, 
   constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
   __shared__ R ya[H][W], yb[H][W], bs[H][W], ds[H][W], os[4][H][W];
   const int nx = F.n[0], ny = F.n[1];
-  const int X0 = blockIdx.x * VT_X - NU, Y0 = blockIdx.y * VT_Y - NU;
+  int tx, ty;
+  if (!tile_of(nx, ny, tx, ty)) return;
+  const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;
   for (int t = threadIdx.x; t < W * H; t += TPB) {
     const int lx = t % W, ly = t / W;
     const int gx = X0 + lx, gy = Y0 + ly;
