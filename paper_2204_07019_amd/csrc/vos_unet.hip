@@ -3,6 +3,7 @@
 // the kernels of vos_unet_kernels.h on the network's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -179,13 +180,13 @@ const Vol NOMASK = {nullptr, 0, 0};
 void conv(hipStream_t st, Vol x, int Cin, const unsigned short *w, const float *bias, Vol y, float *y32, int Cout,
           int N, const int *d, int relu, Vol mask)
 {
-  const dim3 grid((d[2] + 63) / 64, d[1], N * d[0]);
+  const dim3 grid((d[2] + KT_X - 1) / KT_X, (d[1] + KT_Y - 1) / KT_Y, N * d[0]);
   switch (Cout / 16) {
-    case 1: k_conv3d_fwd<1><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
-    case 2: k_conv3d_fwd<2><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
-    case 3: k_conv3d_fwd<3><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
-    case 4: k_conv3d_fwd<4><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
-    case 6: k_conv3d_fwd<6><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
+    case 1: k_conv3d_tile<1><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
+    case 2: k_conv3d_tile<2><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
+    case 3: k_conv3d_tile<3><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
+    case 4: k_conv3d_tile<4><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
+    case 6: k_conv3d_tile<6><<<grid, CTPB, 0, st>>>(x, Cin, w, bias, y, y32, d[0], d[1], d[2], relu, mask); break;
     default: break;   // unreachable: the layer table holds 16, 32, 48, 64 and 96
   }
 }
@@ -205,12 +206,15 @@ void layer_bwd(vos_unet *u, hipStream_t st, int l, Vol in, Vol gout, Vol gin, Vo
   const int lv = LAY[l].level, ci = LAY[l].ci, co = LAY[l].co;
   const int *d = u->dd[lv];
   const int tiles = (ci / 16) * (co / 16);
-  k_conv3d_wgrad<<<dim3(27 * tiles, WG_CHUNKS), CTPB, 0, st>>>(in, ci, gout, co, u->N, d[0], d[1], d[2], u->wpart);
+  // split-K groups: as many as the partial buffer holds for this layer, at most 1024
   const size_t nw = wsize(l);
+  const int groups = (int)std::min<size_t>(1024, WPART_FLOATS / nw);
+  k_conv3d_wgrad_tile<<<dim3(groups, tiles), CTPB, 0, st>>>(in, ci, gout, co, u->N, d[0], d[1], d[2], groups,
+                                                             u->wpart);
   float *g = u->grad + layer_off(l);
-  k_wgrad_reduce<<<eblocks(nw), CTPB, 0, st>>>(u->wpart, (int)nw, g);
+  k_wgrad_reduce<<<eblocks(nw), CTPB, 0, st>>>(u->wpart, (int)nw, groups, g);
   k_bias_grad_part<<<NB_BIAS, CTPB, 0, st>>>(gout, co, u->V[lv], u->bpart);
-  k_bias_grad_final<<<1, 64, 0, st>>>(u->bpart, co, NB_BIAS, g + nw);
+  k_bias_grad_final<<<1, CTPB, 0, st>>>(u->bpart, co, NB_BIAS, g + nw);
   if (gin.p) conv(st, gout, co, u->wd[l], nullptr, gin, nullptr, ci, u->N, d, 0, mask);
 }
 
@@ -227,10 +231,10 @@ void forward(vos_unet *u, hipStream_t st, const float *x, float *y)
   k_pool_fwd<<<eblocks(u->V[2] * 32), CTPB, 0, st>>>(vol(u->C1, 96, 64), 32, vol(u->P1, 32), N, d1[0], d1[1], d1[2]);
   layer_fwd(u, st, BA, vol(u->P1, 32), vol(u->A2, 64));
   layer_fwd(u, st, BB, vol(u->A2, 64), vol(u->B2, 64));
-  k_up_fwd<<<eblocks(u->V[1] * 64), CTPB, 0, st>>>(vol(u->B2, 64), 64, vol(u->C1, 96, 0), N, d1[0], d1[1], d1[2]);
+  k_up_fwd<<<eblocks(u->V[1] * 8), CTPB, 0, st>>>(vol(u->B2, 64), 64, vol(u->C1, 96, 0), N, d1[0], d1[1], d1[2]);
   layer_fwd(u, st, D1A, vol(u->C1, 96), vol(u->D1, 32));
   layer_fwd(u, st, D1B, vol(u->D1, 32), vol(u->E1, 32));
-  k_up_fwd<<<eblocks(u->V[0] * 32), CTPB, 0, st>>>(vol(u->E1, 32), 32, vol(u->C0, 48, 0), N, d0[0], d0[1], d0[2]);
+  k_up_fwd<<<eblocks(u->V[0] * 4), CTPB, 0, st>>>(vol(u->E1, 32), 32, vol(u->C0, 48, 0), N, d0[0], d0[1], d0[2]);
   layer_fwd(u, st, D0A, vol(u->C0, 48), vol(u->D0, 16));
   layer_fwd(u, st, D0B, vol(u->D0, 16), vol(u->E0, 16));
   const float *hw = u->theta + head_off();
@@ -246,7 +250,7 @@ void backward(vos_unet *u, hipStream_t st, const float *target)
   k_sum_double<<<1, CTPB, 0, st>>>(u->lpart, NB_BIAS, u->lsum);
   const float *hw = u->theta + head_off();
   k_head_bwd<<<NB_BIAS, CTPB, 0, st>>>(vol(u->E0, 16), hw, u->dy, V0, vol(u->gE0, 16), u->hpart);
-  k_bias_grad_final<<<1, 64, 0, st>>>(u->hpart, 17, NB_BIAS, u->grad + head_off());
+  k_bias_grad_final<<<1, CTPB, 0, st>>>(u->hpart, 17, NB_BIAS, u->grad + head_off());
   layer_bwd(u, st, D0B, vol(u->D0, 16), vol(u->gE0, 16), vol(u->gD0, 16), vol(u->D0, 16));
   layer_bwd(u, st, D0A, vol(u->C0, 48), vol(u->gD0, 16), vol(u->gC0, 48), vol(u->C0, 48));
   k_up_bwd<<<eblocks(u->V[1] * 32), CTPB, 0, st>>>(vol(u->gC0, 48, 0), 32, vol(u->gE1, 32), N, d0[0], d0[1], d0[2]);

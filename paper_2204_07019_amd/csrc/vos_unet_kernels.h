@@ -97,6 +97,85 @@ __global__ void __launch_bounds__(CTPB) k_conv3d_fwd(Vol x, int Cin, const unsig
   }
 }
 
+// Tiled version of k_conv3d_fwd (same arithmetic per output: the 27 taps in
+// order, chunks of 16 input channels in order, FP32 accumulation).  A block of
+// 4 waves owns 64 x-voxels (4 matrix tiles of 16) x 4 rows (wave w: row
+// 4 by + w) at one z; per chunk of 16 input channels the 3 x 6 x 66 halo of
+// the input is staged in LDS once, as [z][y][channel quad][x] of 4 BF16 each,
+// so a wave reads its A fragments from LDS for all 27 taps, and each weight
+// fragment is reused for the 4 matrix tiles.  Grid (ceil(W / 64), ceil(H / 4),
+// N * D).  Requires Cin % 16 == 0.
+constexpr int KT_X = 64, KT_Y = 4, KH_X = KT_X + 2, KH_Y = KT_Y + 2;
+
+template <int NT>
+__global__ void __launch_bounds__(CTPB) k_conv3d_tile(Vol x, int Cin, const unsigned short *__restrict__ w,
+                                                      const float *__restrict__ bias, Vol y, float *__restrict__ y32,
+                                                      int D, int H, int W, int relu, Vol mask)
+{
+  constexpr int Cout = NT * 16;
+  __shared__ __align__(16) bf16x4 tile[3][KH_Y][4][KH_X];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int x0 = blockIdx.x * KT_X, y0 = blockIdx.y * KT_Y;
+  const int z = blockIdx.z % D, n = blockIdx.z / D;
+  const int yy = y0 + wv;
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nchunk = Cin >> 4;
+  for (int cc = 0; cc < nchunk; ++cc) {
+    __syncthreads();   // the previous chunk's tile has been consumed
+    for (int e = threadIdx.x; e < 3 * KH_Y * KH_X * 4; e += CTPB) {
+      const int q = e & 3, vox = e >> 2;
+      const int hx = vox % KH_X, hy = (vox / KH_X) % KH_Y, hz = vox / (KH_X * KH_Y);
+      const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z + hz - 1;
+      bf16x4 v = bf16x4{0, 0, 0, 0};
+      if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
+        const size_t gv = (((size_t)n * D + gz) * H + gy) * W + gx;
+        v = *(const bf16x4 *)(x.p + gv * x.ctot + x.coff + cc * 16 + q * 4);
+      }
+      tile[hz][hy][q][hx] = v;
+    }
+    __syncthreads();
+    if (yy < H) {
+      const unsigned short *wc = w + (size_t)m * Cin + cc * 16 + kq * 4;
+      for (int tap = 0; tap < 27; ++tap) {
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+        bf16x4 b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = *(const bf16x4 *)(wc + (size_t)tap * Cout * Cin + (size_t)t * 16 * Cin);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const bf16x4 a = tile[dz][wv + dy][kq][mt * 16 + m + dx];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[mt][t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if (yy >= H) return;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + m;
+      const float bco = bias ? bias[co] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int xv = x0 + mt * 16 + kq * 4 + i;
+        if (xv >= W) continue;
+        const size_t vox = (((size_t)n * D + z) * H + yy) * W + xv;
+        float v = acc[mt][t][i] + bco;
+        if (relu) v = v > 0.f ? v : 0.f;
+        if (mask.p && !(bf2f(mask.p[vox * mask.ctot + mask.coff + co]) > 0.f)) v = 0.f;
+        if (y32) y32[vox * Cout + co] = v;
+        else y.p[vox * y.ctot + y.coff + co] = f2bf(v);
+      }
+    }
+}
+
 // Weight-gradient partials: part[chunk][tap][ci][co] = sum over the chunk's
 // rows of x[v + off(tap)][ci] dy[v][co].  Grid (27 * tiles, WG_CHUNKS), block
 // 256: the 4 waves split the chunk's rows, LDS combines them.
@@ -145,12 +224,103 @@ __global__ void __launch_bounds__(CTPB) k_conv3d_wgrad(Vol x, int Cin, Vol dy, i
   part[(((size_t)blockIdx.y * 27 + tap) * Cin + ci) * Cout + co] = s;
 }
 
-// dW[tap][ci][co] = sum over chunks (fixed order).
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int n, float *__restrict__ dw)
+// Tiled weight gradient.  Block (group g, channel-tile pair) loops over the
+// spatial tiles g, g + groups, ... (64 x-voxels x 4 rows at one z; wave w owns
+// row w) and accumulates, for all 27 taps, dW[tap][ci][co] += x[v + off][ci]
+// dy[v][co] over the tile's voxels (K = voxels, 16 per matrix step).  Per
+// tile the input halo (16 channels, 3 x 6 x 66) is staged channel-major in
+// LDS with x contiguous, so one aligned 8-byte read gives 4 consecutive
+// voxels; the x-shifted operands of the three dx taps are formed from it and
+// the two edge voxels by 64-bit shifts.  The 4 waves' sums are added in fixed
+// order and written as partial g: part[((g * 27 + tap) * Cin + ci) * Cout + co].
+constexpr int WX_P = 72;   // LDS row: halo x index hx stored at hx + 3 (interior quads 8-byte aligned)
+
+__global__ void __launch_bounds__(CTPB) k_conv3d_wgrad_tile(Vol x, int Cin, Vol dy, int Cout, int N, int D, int H,
+                                                           int W, int groups, float *__restrict__ part)
+{
+  __shared__ __align__(16) unsigned short xt[16][3][KH_Y][WX_P];   // 41472 B; rows of 144 B
+  __shared__ __align__(16) unsigned short dt[16][KT_Y][KT_X];      // 8192 B; rows of 128 B
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int ntc = Cout >> 4;
+  const int cit = blockIdx.y / ntc, cot = blockIdx.y % ntc;
+  const int gx = (W + KT_X - 1) / KT_X, gy = (H + KT_Y - 1) / KT_Y;
+  const long long ntiles = (long long)gx * gy * D * N;
+  f32x4 acc[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (long long tile = blockIdx.x; tile < ntiles; tile += groups) {
+    const int tx = (int)(tile % gx), ty = (int)((tile / gx) % gy);
+    const int z = (int)((tile / ((long long)gx * gy)) % D), n = (int)(tile / ((long long)gx * gy * D));
+    const int x0 = tx * KT_X, y0 = ty * KT_Y;
+    __syncthreads();   // previous tile consumed
+    for (int e = threadIdx.x; e < 3 * KH_Y * KH_X * 4; e += CTPB) {
+      const int q = e & 3, vox = e >> 2;
+      const int hx = vox % KH_X, hy = (vox / KH_X) % KH_Y, hz = vox / (KH_X * KH_Y);
+      const int ix = x0 + hx - 1, iy = y0 + hy - 1, iz = z + hz - 1;
+      bf16x4 v = bf16x4{0, 0, 0, 0};
+      if (ix >= 0 && ix < W && iy >= 0 && iy < H && iz >= 0 && iz < D) {
+        const size_t gv = (((size_t)n * D + iz) * H + iy) * W + ix;
+        v = *(const bf16x4 *)(x.p + gv * x.ctot + x.coff + cit * 16 + q * 4);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xt[q * 4 + j][hz][hy][hx + 3] = (unsigned short)v[j];
+    }
+    for (int e = threadIdx.x; e < KT_Y * KT_X * 4; e += CTPB) {
+      const int q = e & 3, vox = e >> 2;
+      const int xl = vox % KT_X, r = vox / KT_X;
+      const int ix = x0 + xl, iy = y0 + r;
+      bf16x4 v = bf16x4{0, 0, 0, 0};
+      if (ix < W && iy < H) {
+        const size_t gv = (((size_t)n * D + z) * H + iy) * W + ix;
+        v = *(const bf16x4 *)(dy.p + gv * dy.ctot + dy.coff + cot * 16 + q * 4);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dt[q * 4 + j][r][xl] = (unsigned short)v[j];
+    }
+    __syncthreads();
+    for (int g16 = 0; g16 < KT_X / 16; ++g16) {
+      const int xq = g16 * 16 + kq * 4;   // first voxel of this lane's quad (interior x index)
+      const bf16x4 b = *(const bf16x4 *)&dt[m][wv][xq];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const int dz = c / 3, dyy = c % 3;
+        const unsigned short *row = &xt[m][dz][wv + dyy][0];
+        const unsigned long long Q = *(const unsigned long long *)(row + xq + 4);
+        const unsigned long long eL = row[xq + 3], eR = row[xq + 8];
+        const unsigned long long A0 = (Q << 16) | eL, A2 = (Q >> 16) | (eR << 48);
+        bf16x4 a0, a1, a2;
+        __builtin_memcpy(&a0, &A0, 8);
+        __builtin_memcpy(&a1, &Q, 8);
+        __builtin_memcpy(&a2, &A2, 8);
+        acc[c * 3 + 0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc[c * 3 + 0], 0, 0, 0);
+        acc[c * 3 + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b, acc[c * 3 + 1], 0, 0, 0);
+        acc[c * 3 + 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b, acc[c * 3 + 2], 0, 0, 0);
+      }
+    }
+  }
+  // add the 4 waves (fixed order) and write this group's partial
+  __syncthreads();
+  float *red = reinterpret_cast<float *>(&xt[0][0][0][0]);   // 4 x 256 floats
+#pragma unroll
+  for (int tap = 0; tap < 27; ++tap) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wv * 256 + (kq * 4 + i) * 16 + m] = acc[tap][i];
+    __syncthreads();
+    const int e = threadIdx.x;   // 16 ci x 16 co
+    const float sum = red[e] + red[256 + e] + red[512 + e] + red[768 + e];
+    const int ci = cit * 16 + e / 16, co = cot * 16 + e % 16;
+    part[(((size_t)blockIdx.x * 27 + tap) * Cin + ci) * Cout + co] = sum;
+    __syncthreads();
+  }
+}
+
+// dW[tap][ci][co] = sum over the `chunks` partials (fixed order).
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int n, int chunks, float *__restrict__ dw)
 {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     float s = 0.f;
-    for (int c = 0; c < WG_CHUNKS; ++c) s += part[(size_t)c * n + i];
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + i];
     dw[i] = s;
   }
 }
@@ -174,13 +344,33 @@ __global__ void k_bias_grad_part(Vol dy, int C, size_t V, float *__restrict__ pa
   }
 }
 
-__global__ void k_bias_grad_final(const float *__restrict__ part, int C, int nblk, float *__restrict__ db)
+// db[c] = sum over the nblk partials (fixed order): one block of CTPB threads,
+// each thread sums a strided subset of the partials of every channel, then a
+// tree over the threads.  C <= 64.
+__global__ void __launch_bounds__(CTPB) k_bias_grad_final(const float *__restrict__ part, int C, int nblk,
+                                                          float *__restrict__ db)
 {
-  const int c = threadIdx.x;
-  if (c >= C) return;
-  float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * C + c];
-  db[c] = s;
+  __shared__ float red[CTPB][17];
+  for (int c0 = 0; c0 < C; c0 += 16) {
+    const int cn = C - c0 < 16 ? C - c0 : 16;
+    float acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    for (int b = threadIdx.x; b < nblk; b += CTPB)
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < cn) acc[k] += part[(size_t)b * C + c0 + k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int o = CTPB / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o)
+        for (int k = 0; k < cn; ++k) red[threadIdx.x][k] += red[threadIdx.x + o][k];
+      __syncthreads();
+    }
+    if (threadIdx.x < cn) db[c0 + threadIdx.x] = red[0][threadIdx.x];
+    __syncthreads();
+  }
 }
 
 // 2x2x2 average pooling (fine dims D, H, W even).
@@ -221,16 +411,18 @@ __global__ void k_pool_bwd(Vol dy, int C, Vol g, int N, int D, int H, int W, int
 }
 
 // Nearest-neighbour 2x upsampling into a channel slice: y[f] = x[parent(f)].
+// One thread moves 8 channels (16 bytes): C, ctot and coff are multiples of 8.
 __global__ void k_up_fwd(Vol x, int C, Vol y, int N, int D, int H, int W)
 {
-  const size_t total = (size_t)N * D * H * W * C;
+  const int C8 = C / 8;
+  const size_t total = (size_t)N * D * H * W * C8;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const size_t v = i / C;
+    const int c = (int)(i % C8) * 8;
+    const size_t v = i / C8;
     const int xx = (int)(v % W), yy = (int)((v / W) % H), zz = (int)((v / ((size_t)W * H)) % D);
     const int n = (int)(v / ((size_t)W * H * D));
     const size_t vc = (((size_t)n * (D / 2) + zz / 2) * (H / 2) + yy / 2) * (W / 2) + xx / 2;
-    y.p[v * y.ctot + y.coff + c] = x.p[vc * x.ctot + x.coff + c];
+    *(uint4 *)(y.p + v * y.ctot + y.coff + c) = *(const uint4 *)(x.p + vc * x.ctot + x.coff + c);
   }
 }
 
