@@ -206,13 +206,13 @@ void layer_bwd(vos_unet *u, hipStream_t st, int l, Vol in, Vol gout, Vol gin, Vo
   const int lv = LAY[l].level, ci = LAY[l].ci, co = LAY[l].co;
   const int *d = u->dd[lv];
   const int tiles = (ci / 16) * (co / 16);
-  // split-K groups: as many as the partial buffer holds for this layer, at most 1024
+  // split-K groups: at most 256 (and what the partial buffer holds for this layer)
   const size_t nw = wsize(l);
-  const int groups = (int)std::min<size_t>(1024, WPART_FLOATS / nw);
+  const int groups = (int)std::min<size_t>(256, WPART_FLOATS / nw);
   k_conv3d_wgrad_tile<<<dim3(groups, tiles), CTPB, 0, st>>>(in, ci, gout, co, u->N, d[0], d[1], d[2], groups,
                                                              u->wpart);
   float *g = u->grad + layer_off(l);
-  k_wgrad_reduce<<<eblocks(nw), CTPB, 0, st>>>(u->wpart, (int)nw, groups, g);
+  k_wgrad_reduce<<<(unsigned)((nw + 31) / 32), CTPB, 0, st>>>(u->wpart, (int)nw, groups, g);
   k_bias_grad_part<<<NB_BIAS, CTPB, 0, st>>>(gout, co, u->V[lv], u->bpart);
   k_bias_grad_final<<<1, CTPB, 0, st>>>(u->bpart, co, NB_BIAS, g + nw);
   if (gin.p) conv(st, gout, co, u->wd[l], nullptr, gin, nullptr, ci, u->N, d, 0, mask);
@@ -259,11 +259,11 @@ void backward(vos_unet *u, hipStream_t st, const float *target)
   k_up_bwd<<<eblocks(u->V[2] * 64), CTPB, 0, st>>>(vol(u->gC1, 96, 0), 64, vol(u->gB2, 64), N, d1[0], d1[1], d1[2]);
   layer_bwd(u, st, BB, vol(u->A2, 64), vol(u->gB2, 64), vol(u->gA2, 64), vol(u->A2, 64));
   layer_bwd(u, st, BA, vol(u->P1, 32), vol(u->gA2, 64), vol(u->gP1, 32), NOMASK);
-  k_pool_bwd<<<eblocks(u->V[1] * 32), CTPB, 0, st>>>(vol(u->gP1, 32), 32, vol(u->gC1, 96, 64), N, d1[0], d1[1], d1[2],
+  k_pool_bwd<<<eblocks(u->V[1] * 4), CTPB, 0, st>>>(vol(u->gP1, 32), 32, vol(u->gC1, 96, 64), N, d1[0], d1[1], d1[2],
                                                      1, vol(u->C1, 96, 64));
   layer_bwd(u, st, E1B, vol(u->A1, 32), vol(u->gC1, 96, 64), vol(u->gA1, 32), vol(u->A1, 32));
   layer_bwd(u, st, E1A, vol(u->P0, 16), vol(u->gA1, 32), vol(u->gP0, 16), NOMASK);
-  k_pool_bwd<<<eblocks(u->V[0] * 16), CTPB, 0, st>>>(vol(u->gP0, 16), 16, vol(u->gC0, 48, 32), N, d0[0], d0[1], d0[2],
+  k_pool_bwd<<<eblocks(u->V[0] * 2), CTPB, 0, st>>>(vol(u->gP0, 16), 16, vol(u->gC0, 48, 32), N, d0[0], d0[1], d0[2],
                                                      1, vol(u->C0, 48, 32));
   layer_bwd(u, st, E0B, vol(u->A0, 16), vol(u->gC0, 48, 32), vol(u->gA0, 16), vol(u->A0, 16));
   layer_bwd(u, st, E0A, vol(u->X0, 16), vol(u->gA0, 16), NOMASK, NOMASK);

@@ -315,13 +315,24 @@ __global__ void __launch_bounds__(CTPB) k_conv3d_wgrad_tile(Vol x, int Cin, Vol 
   }
 }
 
-// dW[tap][ci][co] = sum over the `chunks` partials (fixed order).
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int n, int chunks, float *__restrict__ dw)
+// dW[tap][ci][co] = sum over the `chunks` partials (fixed order: lane l of 8
+// sums chunks l, l + 8, ... in turn, then the 8 lane sums are added in lane
+// order).  Block CTPB = 32 weights x 8 lanes.
+__global__ void __launch_bounds__(CTPB) k_wgrad_reduce(const float *__restrict__ part, int n, int chunks,
+                                                       float *__restrict__ dw)
 {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + i];
-    dw[i] = s;
+  __shared__ float red[8][32];
+  const int wl = threadIdx.x & 31, l = threadIdx.x >> 5;
+  const int i = blockIdx.x * 32 + wl;
+  float s = 0.f;
+  if (i < n)
+    for (int c = l; c < chunks; c += 8) s += part[(size_t)c * n + i];
+  red[l][wl] = s;
+  __syncthreads();
+  if (l == 0 && i < n) {
+    float t = 0.f;
+    for (int k = 0; k < 8; ++k) t += red[k][wl];
+    dw[i] = t;
   }
 }
 
@@ -394,19 +405,34 @@ __global__ void k_pool_fwd(Vol x, int C, Vol y, int N, int D, int H, int W)
 
 // Gradient of the average pool, optionally added to an existing gradient slice
 // and masked by (m > 0): g[f] = (add ? g[f] : 0) + mask(f) * dy[parent] / 8.
+// One thread handles 8 channels (C, ctot and coff are multiples of 8).
 __global__ void k_pool_bwd(Vol dy, int C, Vol g, int N, int D, int H, int W, int add, Vol mask)
 {
-  const size_t total = (size_t)N * D * H * W * C;
+  const int C8 = C / 8;
+  const size_t total = (size_t)N * D * H * W * C8;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % C);
-    const size_t v = i / C;
+    const int c = (int)(i % C8) * 8;
+    const size_t v = i / C8;
     const int xx = (int)(v % W), yy = (int)((v / W) % H), zz = (int)((v / ((size_t)W * H)) % D);
     const int n = (int)(v / ((size_t)W * H * D));
     const size_t vc = (((size_t)n * (D / 2) + zz / 2) * (H / 2) + yy / 2) * (W / 2) + xx / 2;
-    float d = 0.125f * bf2f(dy.p[vc * dy.ctot + dy.coff + c]);
-    if (mask.p && !(bf2f(mask.p[v * mask.ctot + mask.coff + c]) > 0.f)) d = 0.f;
-    const size_t gi = v * g.ctot + g.coff + c;
-    g.p[gi] = f2bf(add ? bf2f(g.p[gi]) + d : d);
+    const uint4 dv = *(const uint4 *)(dy.p + vc * dy.ctot + dy.coff + c);
+    const unsigned short *d8 = reinterpret_cast<const unsigned short *>(&dv);
+    uint4 mv = uint4{0, 0, 0, 0}, gv = uint4{0, 0, 0, 0};
+    if (mask.p) mv = *(const uint4 *)(mask.p + v * mask.ctot + mask.coff + c);
+    unsigned short *gp = g.p + v * g.ctot + g.coff + c;
+    if (add) gv = *(const uint4 *)gp;
+    const unsigned short *m8 = reinterpret_cast<const unsigned short *>(&mv);
+    const unsigned short *g8 = reinterpret_cast<const unsigned short *>(&gv);
+    uint4 ov;
+    unsigned short *o8 = reinterpret_cast<unsigned short *>(&ov);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float d = 0.125f * bf2f(d8[k]);
+      if (mask.p && !(bf2f(m8[k]) > 0.f)) d = 0.f;
+      o8[k] = f2bf(add ? bf2f(g8[k]) + d : d);
+    }
+    *(uint4 *)gp = ov;
   }
 }
 
