@@ -132,6 +132,9 @@ typedef struct {
                                     0 p^n (network guess rejected or off), 1 network guess */
   double res0_prev, res0_guess;  /* with a network attached: relative Jacobi-scaled residual
                                     of p^n and of the network guess (0 when off) */
+  double guess_error_drop;       /* with the guess on: the fraction of the squared A-norm error
+                                    of starting from p^n that the guess removed, in [0, 1],
+                                    measured against the converged solution */
 } vos_diag;
 
 /* Fields for vos_set_field / vos_get_field / vos_field_ptr. */
@@ -146,7 +149,8 @@ typedef enum {
   VOS_FIELD_USTAR_Y = 7,
   VOS_FIELD_USTAR_Z = 8,
   VOS_FIELD_RBAR = 9,    /* last reaction rate Rbar [mol/m3/s] (cells; read only) */
-  VOS_FIELD_GMAG = 10    /* |grad eps| of the last step's start (cells; read only) */
+  VOS_FIELD_GMAG = 10,   /* |grad eps| of the last step's start (cells; read only) */
+  VOS_FIELD_PDIAG = 11   /* diagonal of the last step's pressure matrix (cells; read only) */
 } vos_field;
 
 typedef struct vos_sim vos_sim;

@@ -87,15 +87,17 @@ vos_status vos_unet_train_step(vos_unet *net, const float *x, const float *targe
 /* ---------------------------------------------------------------- warm start
  * With a network attached (planned for batch 1, nz, ny, nx of the simulation,
  * cin = 4), every pressure solve first builds the network input, per cell
- *   [eps_s, (r0 / d) / s0, (i + 1/2) / nx, 1]
+ *   [eps_s, (r0 / sqrt(d)) / s0, (i + 1/2) / nx, 1]
  * with r0 = b - A p^n the initial residual, d = diag(A) and
- * s0 = rms(r0 / d) (FP64 reduction).  With use_guess = 1 the network output v
- * is a search direction: the solve starts from p^n + alpha v with
- * alpha = (v . r0) / (v . A v), the step that minimises the A-norm error
- * along v (which then drops by (v . r0)^2 / (v . A v)), unless v . A v <= 0
- * or v . r0 == 0, when it starts from p^n.  vos_diag reports which, and the
- * Jacobi-scaled residuals of both starts.  gain > 0 only scales the training
- * target (vos_warm_start_sample). */
+ * s0 = rms(r0 / sqrt(d)) (FP64 reduction): the network works in the space
+ * scaled by D^1/2, where the operator has a unit diagonal.  With use_guess = 1
+ * its output y gives the search direction v = y / sqrt(d) in cells that carry
+ * flow (eps > 2 eps_min; 0 in intact solid), and the solve starts from
+ * p^n + alpha v with alpha = (Av . D^-1 r0) / (Av . D^-1 Av), the step that
+ * minimises the Jacobi-scaled residual the stopping rule measures, if that
+ * residual is then smaller than p^n's; else from p^n.  vos_diag reports
+ * which, both residuals and the A-norm error removed.  gain > 0 only scales
+ * the training target (vos_warm_start_sample). */
 typedef struct { double gain; int use_guess; } vos_warm_start;
 
 /* Attach (net != NULL) or detach (net == NULL).  The network must outlive the
@@ -104,9 +106,9 @@ vos_status vos_attach_unet(vos_sim *sim, vos_unet *net, const vos_warm_start *ws
 
 /* Training sample of the last step's pressure solve (attached network
  * required): x_dev receives the network input it was given (nz*ny*nx*4 FP32),
- * target_dev the increment the solve produced, (p^{n+1} - p^n) / (gain s0)
- * (nz*ny*nx FP32; 0 where s0 = 0).  Device pointers; valid until the next
- * step. */
+ * target_dev the increment the solve produced in the scaled space,
+ * sqrt(d) (p^{n+1} - p^n) / (gain s0) (nz*ny*nx FP32; 0 where s0 = 0).
+ * Device pointers; valid until the next step. */
 vos_status vos_warm_start_sample(vos_sim *sim, float *x_dev, float *target_dev);
 
 #ifdef __cplusplus

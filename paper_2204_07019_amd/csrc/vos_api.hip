@@ -254,6 +254,8 @@ struct vos_sim {
   double ws_s0;             // rms of the Jacobi-scaled initial residual of that solve
   int ws_used;              // the last solve started from the network's guess
   double ws_res_prev, ws_res_guess;
+  double ws_drop;           // decrease of the squared A-norm error the guess achieved
+  double ws_frac;           // ws_drop / squared A-norm error of starting from p^n
 };
 
 namespace {
@@ -614,8 +616,9 @@ void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const dou
 
 // ---------------------------------------------------------------- warm start
 
-// Initial residual of p^n: r0 = b - A p^n (q = A p^n), kept in r0.  rd = r0 / d;
-// partial sums of rd^2, r0^2 / d and b^2 / d.
+
+// Initial residual of p^n: r0 = b - A p^n (q = A p^n), kept in r0.  rd = r0 / sqrt(d)
+// (the symmetrically scaled residual); partial sums of rd^2, r0^2 / d and b^2 / d.
 __global__ void __launch_bounds__(TPB) k_ws_r0(unsigned n, const double *__restrict__ b, const double *__restrict__ q,
                                                const double *__restrict__ dg, double *__restrict__ r0,
                                                double *__restrict__ rd, double *__restrict__ part)
@@ -623,7 +626,7 @@ __global__ void __launch_bounds__(TPB) k_ws_r0(unsigned n, const double *__restr
   double a = 0.0, r2 = 0.0, b2 = 0.0;
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double d = dg[i], r = b[i] - q[i];
-    const double v = r / d;
+    const double v = r / sqrt(d);
     r0[i] = r;
     rd[i] = v;
     a += v * v;
@@ -647,7 +650,8 @@ __global__ void k_ws_stats(const double *__restrict__ part, int nb, unsigned n, 
   }
 }
 
-// Network input per cell: [eps_s, rd / s0, (i + 1/2) / nx, 1] (FP32, 4 channels).
+// Network input per cell: [eps_s, rd / s0, (i + 1/2) / nx, 1] (FP32, 4 channels),
+// rd = r0 / sqrt(d).
 __global__ void k_ws_input(Dev g, const double *__restrict__ eps, const double *__restrict__ rd,
                            const double *__restrict__ sc, float *__restrict__ x)
 {
@@ -664,37 +668,49 @@ __global__ void k_ws_input(Dev g, const double *__restrict__ eps, const double *
   }
 }
 
-// Search direction from the network output: v = y (FP64).
-__global__ void k_ws_dir(unsigned n, const float *__restrict__ y, double *__restrict__ v)
+// Search direction from the network output, back from the scaled space:
+// v = y / sqrt(d) (FP64) where the cell carries flow (eps > 2 eps_min), 0 in
+// intact solid: there d ~ 1e-30 would turn output noise into huge pressure
+// changes that the flow does not see but the Jacobi-scaled residual does.
+__global__ void k_ws_dir(unsigned n, const float *__restrict__ y, const double *__restrict__ dg,
+                         const double *__restrict__ eps, double eps_live, double *__restrict__ v)
 {
-  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) v[i] = (double)y[i];
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride())
+    v[i] = eps[i] > eps_live ? (double)y[i] / sqrt(dg[i]) : 0.0;
 }
 
-// Partial sums of v.r0 and v.(A v) (q = A v).
+// Partial sums of v.r0, v.(A v), (A v).D^-1.r0 and (A v).D^-1.(A v) (q = A v).
 __global__ void __launch_bounds__(TPB) k_ws_dots(unsigned n, const double *__restrict__ v,
                                                  const double *__restrict__ r0, const double *__restrict__ q,
-                                                 double *__restrict__ part)
+                                                 const double *__restrict__ dg, double *__restrict__ part)
 {
-  double a = 0.0, c = 0.0;
+  double a = 0.0, c = 0.0, e = 0.0, f = 0.0;
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     a += v[i] * r0[i];
     c += v[i] * q[i];
+    e += q[i] * r0[i] / dg[i];
+    f += q[i] * q[i] / dg[i];
   }
-  const double vv[2] = {a, c};
-  write_partials<2>(vv, part);
+  const double vv[4] = {a, c, e, f};
+  write_partials<4>(vv, part);
 }
 
-// Step along v minimising the A-norm error of p^n + alpha v:
-// alpha = v.r0 / v.Av (0 if v.Av is not positive); sc[4] = alpha, sc[5] = the
-// decrease of the squared A-norm error, (v.r0)^2 / v.Av.
+// Step along v minimising the Jacobi-scaled residual of p^n + alpha v (the
+// norm the solve's stopping rule measures): alpha = (Av).D^-1.r0 /
+// (Av).D^-1.(Av), 0 if that is not defined.  sc[4] = alpha, sc[5] = the
+// decrease of the squared A-norm error this step gives, 2 alpha v.r0 -
+// alpha^2 v.Av (may be negative).
 __global__ void k_ws_alpha(const double *__restrict__ part, int nb, double *__restrict__ sc)
 {
   const double a = sum_partials(part, 0, nb);
   const double c = sum_partials(part, 1, nb);
+  const double e = sum_partials(part, 2, nb);
+  const double f = sum_partials(part, 3, nb);
   if (threadIdx.x == 0) {
-    const bool ok = c > 0.0 && isfinite(a / c);
-    sc[4] = ok ? a / c : 0.0;
-    sc[5] = ok ? a * a / c : 0.0;
+    const bool ok = f > 0.0 && isfinite(e / f);
+    const double al = ok ? e / f : 0.0;
+    sc[4] = al;
+    sc[5] = 2.0 * al * a - al * al * c;
   }
 }
 
@@ -704,6 +720,12 @@ __global__ void k_ws_guess(unsigned n, const double *__restrict__ pn, const doub
 {
   const double al = sc[4];
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = pn[i] + al * v[i];
+}
+
+// v = p - pn.
+__global__ void k_ws_diff(unsigned n, const double *__restrict__ p, const double *__restrict__ pn, double *__restrict__ v)
+{
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) v[i] = p[i] - pn[i];
 }
 
 // Partial sums of (b - q)^2 / d.
@@ -725,21 +747,22 @@ __global__ void k_ws_store(const double *__restrict__ part, int nb, double *__re
   if (threadIdx.x == 0) out[0] = a;
 }
 
-// Training target (p - p^n) / (gain s0) as FP32 (0 where s0 = 0).
-__global__ void k_ws_target(unsigned n, const double *__restrict__ p, const double *__restrict__ pn, double scale,
-                            float *__restrict__ t)
+// Training target sqrt(d) (p - p^n) / (gain s0) as FP32 (0 where s0 = 0): the
+// increment in the symmetrically scaled space, whose squared norm weights each
+// cell by its diagonal as the A-norm does.
+__global__ void k_ws_target(unsigned n, const double *__restrict__ p, const double *__restrict__ pn,
+                            const double *__restrict__ dg, double scale, float *__restrict__ t)
 {
   const double inv = scale > 0.0 ? 1.0 / scale : 0.0;
-  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) t[i] = (float)((p[i] - pn[i]) * inv);
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) t[i] = (float)(sqrt(dg[i]) * (p[i] - pn[i]) * inv);
 }
 
 // Build the network input from the solve's initial residual.  With the guess
-// enabled, take the network output v as a search direction from p^n with the
-// step alpha that minimises the A-norm error, and start from p^n + alpha v
-// whenever that error decreases (v.Av > 0 and v.r0 != 0); the Jacobi-scaled
-// residual of both starts is reported, not used to choose: a smooth error mode
-// carries a large error and a tiny residual.  s->p holds p^n on entry, the
-// start on exit.  Scratch: q, rd, r0 (CG overwrites them).
+// enabled, take the network output as a search direction v from p^n with the
+// step alpha that minimises the Jacobi-scaled residual (the stopping rule's
+// norm), and start from p^n + alpha v if that residual is smaller than p^n's.
+// s->p holds p^n on entry, the start on exit.  Scratch: q, rd, r0 (CG
+// overwrites them).
 vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double *r0, const double *zero_flag)
 {
   const Dev &g = s->g;
@@ -757,9 +780,9 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double
   if (s->ws_use) {
     if (vos_status e = vosint::unet_forward_on(s->net, st)) return e;
     double *v = rd;   // the scaled residual is no longer needed
-    k_ws_dir<<<nb, TPB, 0, st>>>(n, vosint::unet_output(s->net), v);
+    k_ws_dir<<<nb, TPB, 0, st>>>(n, vosint::unet_output(s->net), s->pdiag, s->eps, 2.0 * s->P.eps_min, v);
     k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], v, q, s->part, zero_flag);
-    k_ws_dots<<<nb, TPB, 0, st>>>(n, v, r0, q, s->part);
+    k_ws_dots<<<nb, TPB, 0, st>>>(n, v, r0, q, s->pdiag, s->part);
     k_ws_alpha<<<1, TPB, 0, st>>>(s->part, nb, sc);
     k_ws_guess<<<nb, TPB, 0, st>>>(n, s->pn, v, sc, s->p);
     k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
@@ -775,7 +798,8 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double
   s->ws_res_prev = std::sqrt(h[1] / bn);
   if (s->ws_use) {
     s->ws_res_guess = std::sqrt(h[3] / bn);
-    if (h[5] > 0.0 && std::isfinite(h[3])) {
+    s->ws_drop = h[5];
+    if (h[3] < h[1] && std::isfinite(h[3])) {
       s->ws_used = 1;
     } else {
       HIP_TRY(hipMemcpyAsync(s->p, s->pn, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -821,6 +845,17 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   bool conv;
   vos_status stt = krylov_loop(s, 3, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
+  s->ws_frac = 0.0;
+  if (s->net && s->ws_use) {
+    // squared A-norm of the increment dp = p^{n+1} - p^n: the initial error of a start at p^n
+    k_ws_diff<<<nb, TPB, 0, st>>>(n, s->p, s->pn, z);
+    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], z, q, s->part, zero_flag);
+    k_ws_store<<<1, TPB, 0, st>>>(s->part, nb, sc_block(s, SC_WS) + 6);
+    HIP_TRY(hipGetLastError());
+    if (vos_status e = read_back(s, sc_block(s, SC_WS) + 6, 1)) return e;
+    const double e2 = s->host[0];
+    s->ws_frac = (e2 > 0.0 && s->ws_used) ? std::min(1.0, s->ws_drop / e2) : 0.0;
+  }
   const double bn2 = s->host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "pressure solve did not converge");
@@ -986,6 +1021,7 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   dg->guess = s->net ? s->ws_used : -1;
   dg->res0_prev = s->net ? s->ws_res_prev : 0.0;
   dg->res0_guess = s->net ? s->ws_res_guess : 0.0;
+  dg->guess_error_drop = s->net ? s->ws_frac : 0.0;
   HIP_TRY(hipEventRecord(s->ev[3], st));
   launch_correct(s);
   HIP_TRY(hipEventRecord(s->ev[4], st));
@@ -1026,6 +1062,7 @@ double *field_ptr(vos_sim *s, int field, size_t *n, bool *writable)
     case VOS_FIELD_USTAR_Z: *writable = false; *n = g.nf[2]; return s->ustar[2];
     case VOS_FIELD_RBAR: *writable = false; *n = g.nc; return s->rbar;
     case VOS_FIELD_GMAG: *writable = false; *n = g.nc; return s->gmag;
+    case VOS_FIELD_PDIAG: *writable = false; *n = g.nc; return s->pdiag;
     default: return nullptr;
   }
 }
@@ -1227,6 +1264,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->ws_s0 = 0.0;
   s->ws_used = 0;
   s->ws_res_prev = s->ws_res_guess = 0.0;
+  s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
@@ -1411,7 +1449,7 @@ vos_status vos_warm_start_sample(vos_sim *s, float *x_dev, float *target_dev)
   hipStream_t st = s->stream;
   HIP_TRY(hipMemcpyAsync(x_dev, vosint::unet_input(s->net), (size_t)n * 4 * sizeof(float), hipMemcpyDeviceToDevice,
                          st));
-  k_ws_target<<<grid_blocks(n), TPB, 0, st>>>(n, s->p, s->pn, s->ws_gain * s->ws_s0, target_dev);
+  k_ws_target<<<grid_blocks(n), TPB, 0, st>>>(n, s->p, s->pn, s->pdiag, s->ws_gain * s->ws_s0, target_dev);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return VOS_OK;

@@ -24,7 +24,7 @@ FREEZE_SOLID = 1
 KERNELS = {"v_restrict": 0, "v_post": 1, "v_pre": 2, "v_coarse": 3, "p_apply": 4, "adr_apply": 5,
            "v_down": 6, "v_up": 7}
 FIELDS = {"eps": 0, "ux": 1, "uy": 2, "uz": 3, "p": 4, "c": 5, "ustar_x": 6, "ustar_y": 7,
-          "ustar_z": 8, "rbar": 9, "gmag": 10}
+          "ustar_z": 8, "rbar": 9, "gmag": 10, "pdiag": 11}
 
 
 class VosError(RuntimeError):
@@ -61,7 +61,8 @@ class _Diag(C.Structure):
                 ("solid_rate", C.c_double), ("acid_balance_rel", C.c_double),
                 ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
                 ("max_deps", C.c_double), ("alpha", C.c_double), ("t_ms", C.c_double * 6),
-                ("guess", C.c_int), ("res0_prev", C.c_double), ("res0_guess", C.c_double)]
+                ("guess", C.c_int), ("res0_prev", C.c_double), ("res0_guess", C.c_double),
+                ("guess_error_drop", C.c_double)]
 
 
 _lib = None
