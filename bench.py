@@ -259,6 +259,65 @@ def unet_bench(inputs, n, batch_train, reps=5):
     return out
 
 
+def learned_3d(vos, inputs, n, dt, snapshots=60, iters=400, steps=10):
+    """Learned warm start beside plain FP64 and mixed precision on an n^3 grain
+    pack (median radius n/10, porosity 0.3, seed 34, dx = 4 um, iVoS): the
+    network is trained by the library's own kernels on snapshots the solver
+    produced, then three copies of the same state take `steps` steps each at
+    an equal 1e-8 pressure residual."""
+    import torch
+    from paper_2204_07019_amd import unet as U
+    from paper_2204_07019_amd import warmstart as W
+    es = inputs.sphere_pack(n, seed=34, median_r=n / 10.0, porosity=0.3)
+    prm = dict(inputs.BASE_PARAMS, dx=4e-6, model=0)
+
+    def make(prec):
+        return vos.Sim(n, n, n, prm["dx"], prm, vos.Opts(precision=prec, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8,
+                                                          maxit_p=6000))
+    base = make(vos.MIXED)
+    base.set_solid_fraction(es)
+    base.step(dt, 3, freeze_solid=True)
+    t0 = time.perf_counter()
+    data = W.collect(base, snapshots, dt, U.UNet(1, n, n, n, cin=4, train=False))
+    t_collect = time.perf_counter() - t0
+    net = U.UNet(2, n, n, n, cin=4, train=True)
+    net.set_params(inputs.unet_init(1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = W.train(net, data, iters, lr=1e-3, log_every=iters // 4)
+    t_train = time.perf_counter() - t0
+    state = {k: base.get(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
+    base.close()
+    inf = U.UNet(1, n, n, n, cin=4, train=False)
+    inf.set_params(net.get_params())
+    net.close()
+    out = {"workload": f"pack {n}^3 median radius {n / 10:g} porosity 0.3 seed 34, iVoS, dt={dt:g}s, rtol 1e-8",
+           "snapshots": snapshots, "train_iters": iters, "train_loss": [round(l, 4) for _, l in hist],
+           "collect_s": round(t_collect, 2), "train_s": round(t_train, 2)}
+    for name, prec, learned in (("plain_fp64", vos.FP64, False), ("mixed", vos.MIXED, False),
+                                ("mixed_learned", vos.MIXED, True)):
+        s = make(prec)
+        for k, v in state.items():
+            s.set(k, v)
+        if learned:
+            U.attach(s, inf, gain=data.gain, use_guess=True)
+        s.step(dt)   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ds = [s.step(dt) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"cell_steps_per_s": n ** 3 * steps / el, "ms_per_step": el / steps * 1e3,
+                     "pressure_its_per_step": sum(d["it_p"] for d in ds) / steps,
+                     "pressure_ms_per_step": sum(d["t_ms"][2] for d in ds) / steps}
+        if learned:
+            out[name]["guess_accepted"] = sum(1 for d in ds if d["guess"] == 1)
+            out[name]["error_drop_mean"] = sum(d["guess_error_drop"] for d in ds) / steps
+        s.close()
+    inf.close()
+    return out
+
+
 def cpu_baseline(workload, params, dt, budget_s):
     """The oracle (plain C, one thread) on a bounded sample of the workload:
     a crop of the same geometry, one step at a time until the budget is used."""
@@ -309,6 +368,8 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net timing")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
+    ap.add_argument("--n-learned", type=int, default=128)
     ap.add_argument("--unet-n", type=int, default=128)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
@@ -382,6 +443,12 @@ def main():
     if not args.no_unet:
         log(f"U-Net {args.unet_n}^3")
         net = unet_bench(inputs, args.unet_n, 2)
+    learned = None
+    if not args.no_learned:
+        log(f"learned warm start {args.n_learned}^3")
+        learned = learned_3d(vos, inputs, args.n_learned, 2e-3)
+        log("learned: " + ", ".join(f"{k} {learned[k]['ms_per_step']:.1f} ms/step"
+                                     for k in ("plain_fp64", "mixed", "mixed_learned")))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -415,6 +482,7 @@ def main():
         "pressure_solve_3d": p3d,
         "batch_micromodels": bat,
         "unet": net,
+        "learned_3d": learned,
         "cpu_baseline": cpu,
     }
     sim.close()
