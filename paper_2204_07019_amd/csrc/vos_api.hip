@@ -445,12 +445,11 @@ void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv)
 // z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
 template <typename Lv, typename R>
 void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, double *z, const double *sc,
-            double omega, const double *dsc, double rscale = 1.0)
+            double omega, const double *dsc, double rscale, int nu)
 {
   hipStream_t st = s->stream;
   const int nd = s->g.nd;
   const R om = (R)omega;
-  const int nu = s->opt.mg_nu;
   int lc = 0;
   while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
   // 2-D levels with 2..4 sweeps each way: one tiled kernel per leg (vos_vcycle.h)
@@ -519,12 +518,18 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   }
 }
 
+// Sweeps per leg of hierarchy h: the option for momentum and pressure; at most
+// 2 for transport, whose rows on reactive bands are not diagonally dominant
+// (more damped-Jacobi sweeps amplify error modes there: measured 300-600
+// iterations with 2, 1000-2300 with 4 on a Pe 47, Da 0.54 micromodel).
+int sweeps(const vos_sim *s, int h) { return h == 3 ? std::min(2, s->opt.mg_nu) : s->opt.mg_nu; }
+
 // dsc: diagonal of the symmetrically scaled operator (momentum), nullptr for
 // the row-scaled transport operator.
 template <typename R>
 void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, const double *dsc)
 {
-  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7, dsc);
+  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7, dsc, 1.0, sweeps(s, h));
 }
 
 // ---------------------------------------------------------------- stage S2
@@ -611,7 +616,7 @@ void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const dou
 {
   // A_R = A / p_scale, so z = A^-1 r is A_R^-1 (r / p_scale)
   vcycle<MgLevel<R>, R>(s, lv, s->nlev, s->ainv, r, z, sc, s->g.nd == 3 ? 6.0 / 7.0 : 0.8, nullptr,
-                        1.0 / s->p_scale);
+                        1.0 / s->p_scale, s->opt.mg_nu);
 }
 
 // ---------------------------------------------------------------- warm start
@@ -1134,7 +1139,7 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_COARSE: {
         LevelPack<SLevel<R>> pack;
         for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
-        k_v_coarse_cycle<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, s->opt.mg_nu, om, s->sainv[3],
+        k_v_coarse_cycle<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, sweeps(s, 3), om, s->sainv[3],
                                                                     flag);
         if (count) {
           for (int l = lc; l < L; ++l) per_seq_bytes += (5.0 + 2 * nd) * Rs * lv[l].nc;
@@ -1146,7 +1151,7 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_UP: {
         // the tiled 2-D kernels of the finest level
         const dim3 gr(tile_blocks(lv[0].n[0], lv[0].n[1]));
-        const int nu = s->opt.mg_nu;
+        const int nu = sweeps(s, 3);
         if (family == VOS_KERNEL_V_DOWN) {
           if (nu == 2) k_v_down2d<SLevel<R>, R, false, 2><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
           else if (nu == 3) k_v_down2d<SLevel<R>, R, false, 3><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
@@ -1172,7 +1177,7 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
   };
   if (family < VOS_KERNEL_V_RESTRICT || family > VOS_KERNEL_V_UP) return fail(VOS_ERR_ARG, "unknown kernel family");
   if ((family == VOS_KERNEL_V_DOWN || family == VOS_KERNEL_V_UP) &&
-      !(nd == 2 && s->opt.mg_nu >= 2 && s->opt.mg_nu <= 4 && lc >= 1 && lv[0].n[0] >= 2 && lv[0].n[1] >= 2))
+      !(nd == 2 && sweeps(s, 3) >= 2 && sweeps(s, 3) <= 4 && lc >= 1 && lv[0].n[0] >= 2 && lv[0].n[1] >= 2))
     return fail(VOS_ERR_ARG, "the tiled V-cycle kernels run on 2-D levels with 2..4 sweeps only");
   seq(true);   // warm-up, counts the launches of one sequence
   if (per_seq_launches == 0) return fail(VOS_ERR_STATE, "the hierarchy has no level of that kind");
