@@ -146,79 +146,6 @@ __global__ void __launch_bounds__(TPB) k_mg_coarsen(MgLevel<R> F, MgLevel<R> Cc,
   }
 }
 
-// Level-0 entry: b = (R) r and the first Jacobi sweep from zero, x = omega b / diag.
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_mg_enter(MgLevel<R> L, const double *__restrict__ r, R omega,
-                                                  const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
-    const R bb = (R)r[id];
-    L.b[id] = bb;
-    L.x[id] = omega * bb / L.diag[id];
-  }
-}
-
-// First sweep from zero on a coarse level: x = omega b / diag.
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_mg_first(MgLevel<R> L, R omega, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) L.x[id] = omega * L.b[id] / L.diag[id];
-}
-
-// One damped-Jacobi sweep xo = x + omega (b - A x) / diag; optionally also
-// writes the FP64 result (the preconditioned residual z).
-template <typename R, bool OUT64>
-__global__ void __launch_bounds__(TPB) k_mg_jacobi(MgLevel<R> L, int nd, const R *__restrict__ x, R *__restrict__ xo,
-                                                   R omega, double *__restrict__ z, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
-    int c[3];
-    unflat(L.n, id, c);
-    const R ax = mg_apply_cell(L, nd, x, id, c);
-    const R v = x[id] + omega * (L.b[id] - ax) / L.diag[id];
-    xo[id] = v;
-    if (OUT64) z[id] = (double)v;
-  }
-}
-
-// Residual of the fine level, summed over the children of each coarse cell.
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_mg_restrict(MgLevel<R> F, MgLevel<R> Cc, int nd, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned I = xbeg(Cc.nc); I < xend(Cc.nc); I += xstride()) {
-    int X[3];
-    unflat(Cc.n, I, X);
-    R s = 0;
-    const int c1 = nd >= 2 ? 2 : 1, c2 = nd >= 3 ? 2 : 1;
-    for (int cq = 0; cq < c2; ++cq)
-      for (int bq = 0; bq < c1; ++bq)
-        for (int a = 0; a < 2; ++a) {
-          const int c[3] = {2 * X[0] + a, 2 * X[1] + bq, nd == 3 ? 2 * X[2] + cq : 0};
-          const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * (unsigned)c[2]);
-          s += F.b[id] - mg_apply_cell(F, nd, F.x, id, c);
-        }
-    Cc.b[I] = s;
-  }
-}
-
-// x_fine += x_coarse(parent)
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_mg_prolong(MgLevel<R> F, MgLevel<R> Cc, int nd, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(F.nc); id < xend(F.nc); id += xstride()) {
-    int c[3];
-    unflat(F.n, id, c);
-    const unsigned I = (unsigned)(c[0] >> 1) + (unsigned)Cc.n[0] *
-                       ((unsigned)(c[1] >> 1) + (unsigned)Cc.n[1] * (unsigned)(nd == 3 ? (c[2] >> 1) : 0));
-    F.x[id] += Cc.x[I];
-  }
-}
-
 // Dense inverse of the coarsest operator (n <= 64), FP64, one block: build
 // A, scale to unit diagonal, Gauss-Jordan in place (SPD: no pivoting), unscale.
 template <typename R>
@@ -273,23 +200,6 @@ __global__ void __launch_bounds__(TPB) k_mg_coarse_inverse(MgLevel<R> L, int nd,
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
     Ainv[e] = M[i][j] * sc[i] * sc[j];
-  }
-}
-
-// x = Ainv b on the coarsest level.
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_mg_coarse_solve(MgLevel<R> L, const double *__restrict__ Ainv,
-                                                         const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  __shared__ double bb[MG_COARSE_MAX];
-  const int n = (int)L.nc;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) bb[i] = (double)L.b[i];
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Ainv[i * n + j] * bb[j];
-    L.x[i] = (R)s;
   }
 }
 

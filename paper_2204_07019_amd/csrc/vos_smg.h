@@ -124,76 +124,6 @@ __global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, i
   }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_enter(SLevel<R> L, const double *__restrict__ r, R omega,
-                                                   const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
-    const R bb = (R)r[id];
-    L.b[id] = bb;
-    L.x[id] = omega * bb / L.diag[id];
-  }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_first(SLevel<R> L, R omega, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) L.x[id] = omega * L.b[id] / L.diag[id];
-}
-
-template <typename R, bool OUT64>
-__global__ void __launch_bounds__(TPB) k_smg_jacobi(SLevel<R> L, int nd, const R *__restrict__ x, R *__restrict__ xo,
-                                                    R omega, double *__restrict__ z, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(L.nc); id < xend(L.nc); id += xstride()) {
-    int c[3];
-    unflat(L.n, id, c);
-    const R v = x[id] + omega * (L.b[id] - smg_apply_cell(L, nd, x, id, c)) / L.diag[id];
-    xo[id] = v;
-    if (OUT64) z[id] = (double)v;
-  }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_restrict(SLevel<R> F, SLevel<R> C, int nd, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned I = xbeg(C.nc); I < xend(C.nc); I += xstride()) {
-    int X[3];
-    unflat(C.n, I, X);
-    R s = 0;
-    const int lim2 = nd == 3 ? 2 : 1;
-    for (int cz = 0; cz < lim2; ++cz)
-      for (int cy = 0; cy < 2; ++cy)
-        for (int cx = 0; cx < 2; ++cx) {
-          if ((F.n[1] == 1 && cy) || (nd == 3 && F.n[2] == 1 && cz) || (F.n[0] == 1 && cx)) continue;
-          const int c[3] = {2 * X[0] + cx, 2 * X[1] + cy, nd == 3 ? 2 * X[2] + cz : 0};
-          if (c[0] >= F.n[0] || c[1] >= F.n[1] || c[2] >= F.n[2]) continue;
-          const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * c[2]);
-          s += F.b[id] - smg_apply_cell(F, nd, F.x, id, c);
-        }
-    C.b[I] = s;
-  }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_prolong(SLevel<R> F, SLevel<R> C, int nd, const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  for (unsigned id = xbeg(F.nc); id < xend(F.nc); id += xstride()) {
-    int c[3];
-    unflat(F.n, id, c);
-    const int I0 = F.n[0] == 1 ? c[0] : (c[0] >> 1);
-    const int I1 = F.n[1] == 1 ? c[1] : (c[1] >> 1);
-    const int I2 = (nd == 3 && F.n[2] > 1) ? (c[2] >> 1) : c[2];
-    const unsigned I = (unsigned)I0 + (unsigned)C.n[0] * ((unsigned)I1 + (unsigned)C.n[1] * (unsigned)I2);
-    F.x[id] += C.x[I];
-  }
-}
-
 // Dense inverse of the coarsest operator (n <= 64), FP64, one block.  Rows are
 // scaled by the diagonal first (M = D^-1 A); the operators here are
 // diagonally dominant, so Gauss-Jordan needs no pivoting; Ainv = M^-1 D^-1.
@@ -242,22 +172,6 @@ __global__ void __launch_bounds__(TPB) k_smg_coarse_inverse(SLevel<R> L, int nd,
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
     Ainv[e] = M[i][j] * rs[j];
-  }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_coarse_solve(SLevel<R> L, const double *__restrict__ Ainv,
-                                                          const double *__restrict__ sc)
-{
-  if (sc[S_CONV] != 0.0) return;
-  __shared__ double bb[SMG_COARSE_MAX];
-  const int n = (int)L.nc;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) bb[i] = (double)L.b[i];
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Ainv[i * n + j] * bb[j];
-    L.x[i] = (R)s;
   }
 }
 

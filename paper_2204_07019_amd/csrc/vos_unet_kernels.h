@@ -22,7 +22,7 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int CTPB = 256;         // 4 waves per block
-constexpr int WG_CHUNKS = 64;     // split-K chunks of the weight gradient
+constexpr int WG_CHUNKS = 64;     // weight-gradient partial buffer: WG_CHUNKS x 27 x max(ci co) floats
 
 // Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
 __device__ __forceinline__ unsigned short f2bf(float f)
@@ -41,65 +41,13 @@ struct Vol {   // one NDHWC activation tensor (a channel slice of a buffer)
   int coff;    // first channel of the slice
 };
 
-// y[v][co] = sum_tap sum_ci x[v + off(tap)][ci] w[tap][co][ci] (+ bias[co]),
-// zero padding; optional ReLU; optional mask (y = 0 where m[v][co] <= 0);
+// Convolution, forward and data gradient: y[v][co] = sum over the 27 taps
+// (in order) and the input channels (chunks of 16, in order) of
+// x[v + off(tap)][ci] w[tap][co][ci] (+ bias[co]), zero padding, FP32
+// accumulation; optional ReLU; optional mask (y = 0 where m[v][co] <= 0);
 // output as BF16 into a channel slice, or as FP32 (y32, dense Cout channels).
-// Grid (ceil(W / 64), H, N * D), block 256: wave w of block bx handles the 16
-// voxels x = 64 bx + 16 w .. + 15 (waves past W return).  NT = Cout / 16 output
-// tiles, kept in registers.  Requires W % 16 == 0 and Cin % 16 == 0.
-template <int NT>
-__global__ void __launch_bounds__(CTPB) k_conv3d_fwd(Vol x, int Cin, const unsigned short *__restrict__ w,
-                                                     const float *__restrict__ bias, Vol y, float *__restrict__ y32,
-                                                     int D, int H, int W, int relu, Vol mask)
-{
-  constexpr int Cout = NT * 16;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int x0 = blockIdx.x * 64 + wv * 16;
-  if (x0 >= W) return;
-  const int yy = blockIdx.y;
-  const int z = blockIdx.z % D, n = blockIdx.z / D;
-  const int m = lane & 15, kq = lane >> 4;
-  const int nchunk = Cin >> 4;
-  f32x4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int tap = 0; tap < 27; ++tap) {
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const int zz = z + dz, y1 = yy + dy, xx = x0 + m + dx;
-    const bool ok = zz >= 0 && zz < D && y1 >= 0 && y1 < H && xx >= 0 && xx < W;
-    const size_t vox = ok ? (((size_t)n * D + zz) * H + y1) * W + xx : 0;
-    const unsigned short *xin = x.p + vox * x.ctot + x.coff + kq * 4;
-    const unsigned short *wt = w + (size_t)tap * Cout * Cin + (size_t)m * Cin + kq * 4;
-    for (int cc = 0; cc < nchunk; ++cc) {
-      bf16x4 a = bf16x4{0, 0, 0, 0};
-      if (ok) a = *(const bf16x4 *)(xin + cc * 16);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bf16x4 b = *(const bf16x4 *)(wt + (size_t)t * 16 * Cin + cc * 16);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + m;
-    const float bco = bias ? bias[co] : 0.f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int xv = x0 + kq * 4 + i;
-      const size_t vox = (((size_t)n * D + z) * H + yy) * W + xv;
-      float v = acc[t][i] + bco;
-      if (relu) v = v > 0.f ? v : 0.f;
-      if (mask.p && !(bf2f(mask.p[vox * mask.ctot + mask.coff + co]) > 0.f)) v = 0.f;
-      if (y32) y32[vox * Cout + co] = v;
-      else y.p[vox * y.ctot + y.coff + co] = f2bf(v);
-    }
-  }
-}
-
-// Tiled version of k_conv3d_fwd (same arithmetic per output: the 27 taps in
-// order, chunks of 16 input channels in order, FP32 accumulation).  A block of
-// 4 waves owns 64 x-voxels (4 matrix tiles of 16) x 4 rows (wave w: row
+// The data gradient is this kernel on the output gradient with the flipped,
+// transposed weights.  A block of 4 waves owns 64 x-voxels (4 matrix tiles of 16) x 4 rows (wave w: row
 // 4 by + w) at one z; per chunk of 16 input channels the 3 x 6 x 66 halo of
 // the input is staged in LDS once, as [z][y][channel quad][x] of 4 BF16 each,
 // so a wave reads its A fragments from LDS for all 27 taps, and each weight
@@ -174,54 +122,6 @@ __global__ void __launch_bounds__(CTPB) k_conv3d_tile(Vol x, int Cin, const unsi
         else y.p[vox * y.ctot + y.coff + co] = f2bf(v);
       }
     }
-}
-
-// Weight-gradient partials: part[chunk][tap][ci][co] = sum over the chunk's
-// rows of x[v + off(tap)][ci] dy[v][co].  Grid (27 * tiles, WG_CHUNKS), block
-// 256: the 4 waves split the chunk's rows, LDS combines them.
-__global__ void __launch_bounds__(CTPB) k_conv3d_wgrad(Vol x, int Cin, Vol dy, int Cout, int N, int D, int H, int W,
-                                                       float *__restrict__ part)
-{
-  __shared__ float red[4][256];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int ntc = Cout >> 4;
-  const int tiles = (Cin >> 4) * ntc;
-  const int tap = blockIdx.x / tiles, tile = blockIdx.x % tiles;
-  const int cit = tile / ntc, cot = tile % ntc;
-  const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-  const int m = lane & 15, kq = lane >> 4;
-  const int rows = N * D * H;
-  const int r0 = (int)((long long)rows * blockIdx.y / WG_CHUNKS), r1 = (int)((long long)rows * (blockIdx.y + 1) / WG_CHUNKS);
-  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int r = r0 + wv; r < r1; r += 4) {
-    const int yy = r % H, z = (r / H) % D, n = r / (H * D);
-    const int zz = z + dz, y1 = yy + dyy;
-    const bool rok = zz >= 0 && zz < D && y1 >= 0 && y1 < H;
-    for (int xb = 0; xb < W; xb += 16) {
-      // A[m = ci][k = voxel]: 4 voxels xb + 4 kq + j of input channel cit*16 + m
-      bf16x4 a, b;
-      for (int j = 0; j < 4; ++j) {
-        const int xv = xb + kq * 4 + j;
-        const int xs = xv + dx;
-        unsigned short av = 0;
-        if (rok && xs >= 0 && xs < W) {
-          const size_t vs = (((size_t)n * D + zz) * H + y1) * W + xs;
-          av = x.p[vs * x.ctot + x.coff + cit * 16 + m];
-        }
-        a[j] = (short)av;
-        const size_t vd = (((size_t)n * D + z) * H + yy) * W + xv;
-        b[j] = (short)dy.p[vd * dy.ctot + dy.coff + cot * 16 + m];
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-  }
-  // D[ci = 4 kq + i][co = m]
-  for (int i = 0; i < 4; ++i) red[wv][(kq * 4 + i) * 16 + m] = acc[i];
-  __syncthreads();
-  const int e = threadIdx.x;   // 256 entries = 16 ci x 16 co
-  const float s = red[0][e] + red[1][e] + red[2][e] + red[3][e];
-  const int ci = cit * 16 + e / 16, co = cot * 16 + e % 16;
-  part[(((size_t)blockIdx.y * 27 + tap) * Cin + ci) * Cout + co] = s;
 }
 
 // Tiled weight gradient.  Block (group g, channel-tile pair) loops over the
