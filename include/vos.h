@@ -106,6 +106,10 @@ typedef struct {
                        Ignored (off) when vos_create() is given the null stream. */
   int coarse_cells; /* multigrid levels with at most this many cells run inside one single-block
                        kernel, 64..65536 (0: 1024 in 2-D, 4096 in 3-D) */
+  int level_kernels;/* kernels of the fine multigrid levels: 0 fused (2-D: one tiled kernel per
+                       leg of a level; 3-D: sweeps that march through z with the neighbours in
+                       LDS and registers); 1 one plain kernel per sweep.  Both form every value
+                       by the same expression: results are bitwise identical. */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */

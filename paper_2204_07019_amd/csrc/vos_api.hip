@@ -22,6 +22,7 @@
 #include "vos_mg.h"
 #include "vos_smg.h"
 #include "vos_vcycle.h"
+#include "vos_march3d.h"
 
 using namespace vos;
 
@@ -60,6 +61,41 @@ unsigned tile_blocks(int nx, int ny)
 {
   const unsigned nt = (unsigned)((nx + VT_X - 1) / VT_X) * (unsigned)((ny + VT_Y - 1) / VT_Y);
   return (nt + NXCD - 1) / NXCD * NXCD;
+}
+
+// z-run length of the 3-D marching kernels (vos_march3d.h): about 2048 work
+// items per level, even (restriction aggregates pairs of planes), 2..64.
+int zrun_len(const int n[3])
+{
+  const long tiles = (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + ZT_Y - 1) / ZT_Y);
+  long zl = (long)n[2] * tiles / 2048;
+  zl = std::max(2L, std::min(64L, zl));
+  return (int)(zl & ~1L);
+}
+
+// Blocks of a 3-D marching kernel: its work items rounded up to a multiple of the 8 XCDs.
+unsigned zrun_blocks(const int n[3], int zlen)
+{
+  const unsigned nw = (unsigned)((n[0] + ZT_X - 1) / ZT_X) * (unsigned)((n[1] + ZT_Y - 1) / ZT_Y) *
+                      (unsigned)((n[2] + zlen - 1) / zlen);
+  return (nw + NXCD - 1) / NXCD * NXCD;
+}
+
+// The pressure operator marches through z on 3-D grids at least half a tile
+// wide whose tiles fit the MAXB partial slots; the z-run is lengthened until
+// the work items do.
+bool papply_marching(const Dev &g)
+{
+  const long tiles = (long)((g.n[0] + ZT_X - 1) / ZT_X) * ((g.n[1] + ZT_Y - 1) / ZT_Y);
+  return g.nd == 3 && g.n[0] >= ZT_X / 2 && g.n[1] >= 2 && g.n[2] >= 2 && tiles <= MAXB;
+}
+
+int papply_zlen(const Dev &g)
+{
+  const long tiles = (long)((g.n[0] + ZT_X - 1) / ZT_X) * ((g.n[1] + ZT_Y - 1) / ZT_Y);
+  int zl = zrun_len(g.n);
+  while (tiles * ((g.n[2] + zl - 1) / zl) > MAXB) zl += 2;
+  return zl;
 }
 
 // Blocks of a sweep over n items: one item per thread up to MAXB blocks,
@@ -323,6 +359,7 @@ vos_status check_opts(const vos_opts *o)
   if (o->check_every < 1 || o->check_every > 256) return fail(VOS_ERR_ARG, "check_every must be in [1, 256]");
   if (o->coarse_cells != 0 && (o->coarse_cells < 64 || o->coarse_cells > 65536))
     return fail(VOS_ERR_ARG, "coarse_cells must be 0 or in [64, 65536]");
+  if (o->level_kernels != 0 && o->level_kernels != 1) return fail(VOS_ERR_ARG, "level_kernels must be 0 or 1");
   return VOS_OK;
 }
 
@@ -397,6 +434,22 @@ void drop_graphs(vos_sim *s)
     if (s->gexec[k]) { (void)hipGraphExecDestroy(s->gexec[k]); s->gexec[k] = nullptr; }
 }
 
+// q = A x (pressure operator) with the partials of x.q in s->part; returns
+// the number of partial blocks.
+int p_apply(vos_sim *s, const double *x, double *q, const double *flag)
+{
+  const Dev &g = s->g;
+  if (papply_marching(g)) {
+    const int zl = papply_zlen(g);
+    const unsigned nb = zrun_blocks(g.n, zl);
+    k_p_apply3d<<<nb, TPB, 0, s->stream>>>(g, s->T[0], s->T[1], s->T[2], x, q, s->part, zl, flag);
+    return (int)nb;
+  }
+  const int nb = grid_blocks(g.nc);
+  k_p_apply<<<nb, TPB, 0, s->stream>>>(g, s->T[0], s->T[1], s->T[2], x, q, s->part, flag);
+  return nb;
+}
+
 // ---------------------------------------------------------------- stage S1
 
 void launch_coefficients(vos_sim *s, double dt)
@@ -452,12 +505,32 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   const R om = (R)omega;
   int lc = 0;
   while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
+  const bool fused = s->opt.level_kernels == 0;
   // 2-D levels with 2..4 sweeps each way: one tiled kernel per leg (vos_vcycle.h)
-  auto tiled = [&](const Lv &F) { return nd == 2 && nu >= 2 && nu <= 4 && F.n[0] >= 2 && F.n[1] >= 2; };
+  auto tiled = [&](const Lv &F) { return fused && nd == 2 && nu >= 2 && nu <= 4 && F.n[0] >= 2 && F.n[1] >= 2; };
   auto tgrid = [](const Lv &F) { return dim3(tile_blocks(F.n[0], F.n[1])); };
+  // 3-D levels at least half a tile wide: z-marching kernels (vos_march3d.h)
+  auto zmarch = [&](const Lv &F) { return fused && nd == 3 && F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2; };
   for (int l = 0; l < lc; ++l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
+    if (zmarch(F)) {
+      const int zl = zrun_len(F.n);
+      const dim3 gr(zrun_blocks(F.n, zl));
+      if (nu == 1) {
+        if (l == 0) k_v_pre<Lv, R, true, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
+        else k_v_pre<Lv, R, false, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
+      } else {
+        if (l == 0) k_v_pre3d<Lv, R, true><<<gr, TPB, 0, st>>>(F, r, dsc, rscale, om, zl, sc);
+        else k_v_pre3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, r, dsc, rscale, om, zl, sc);
+      }
+      for (int k = 2; k < nu; ++k) {
+        k_v_jacobi3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, nullptr, nullptr, zl, sc);
+        std::swap(F.x, F.t);
+      }
+      k_v_restrict3d<Lv, R><<<gr, TPB, 0, st>>>(F, lv[l + 1], zl, sc);
+      continue;
+    }
     if (tiled(F)) {
       const dim3 gr = tgrid(F);
 #define VDOWN(NU_)                                                                                   \
@@ -493,6 +566,19 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   for (int l = lc - 1; l >= 0; --l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
+    if (zmarch(F)) {
+      const int zl = zrun_len(F.n);
+      const dim3 gr(zrun_blocks(F.n, zl));
+      if (l == 0 && nu == 1) k_v_post3d<Lv, R, true><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, zl, sc);
+      else k_v_post3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, zl, sc);
+      std::swap(F.x, F.t);
+      for (int k = 1; k < nu; ++k) {
+        if (l == 0 && k == nu - 1) k_v_jacobi3d<Lv, R, true><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, z, dsc, zl, sc);
+        else k_v_jacobi3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, nullptr, nullptr, zl, sc);
+        std::swap(F.x, F.t);
+      }
+      continue;
+    }
     if (tiled(F)) {
       const dim3 gr = tgrid(F);
 #define VUP(NU_)                                                                                      \
@@ -776,7 +862,7 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double
   const int nb = grid_blocks(n);
   double *sc = sc_block(s, SC_WS);
   float *x = vosint::unet_input(s->net);
-  k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, q, s->part, zero_flag);
+  p_apply(s, s->pn, q, zero_flag);
   k_ws_r0<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, r0, rd, s->part);
   k_ws_stats<<<1, TPB, 0, st>>>(s->part, nb, n, sc);
   k_ws_input<<<nb, TPB, 0, st>>>(g, s->eps, rd, sc, x);
@@ -786,11 +872,11 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double
     if (vos_status e = vosint::unet_forward_on(s->net, st)) return e;
     double *v = rd;   // the scaled residual is no longer needed
     k_ws_dir<<<nb, TPB, 0, st>>>(n, vosint::unet_output(s->net), s->pdiag, s->eps, 2.0 * s->P.eps_min, v);
-    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], v, q, s->part, zero_flag);
+    p_apply(s, v, q, zero_flag);
     k_ws_dots<<<nb, TPB, 0, st>>>(n, v, r0, q, s->pdiag, s->part);
     k_ws_alpha<<<1, TPB, 0, st>>>(s->part, nb, sc);
     k_ws_guess<<<nb, TPB, 0, st>>>(n, s->pn, v, sc, s->p);
-    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
+    p_apply(s, s->p, q, zero_flag);
     k_ws_res<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, s->part);
     k_ws_store<<<1, TPB, 0, st>>>(s->part, nb, sc + 3);
   }
@@ -829,7 +915,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b);
   if (s->net)
     if (vos_status e = warm_start(s, b, q, z, pv, zero_flag)) return e;
-  k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, q, s->part, zero_flag);
+  p_apply(s, s->p, q, zero_flag);
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, r, z, pv, 0, s->part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
   mg_vcycle<R>(s, lv, r, z, sc);
@@ -837,8 +923,8 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
   HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
-    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], pv, q, s->part, sc);
-    k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
+    const int nbq = p_apply(s, pv, q, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nbq, rt2, sc);
     k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->pdiag, s->p, r, z, 0, s->part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
     mg_vcycle<R>(s, lv, r, z, sc);
@@ -854,8 +940,8 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   if (s->net && s->ws_use) {
     // squared A-norm of the increment dp = p^{n+1} - p^n: the initial error of a start at p^n
     k_ws_diff<<<nb, TPB, 0, st>>>(n, s->p, s->pn, z);
-    k_p_apply<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], z, q, s->part, zero_flag);
-    k_ws_store<<<1, TPB, 0, st>>>(s->part, nb, sc_block(s, SC_WS) + 6);
+    const int nbq = p_apply(s, z, q, zero_flag);
+    k_ws_store<<<1, TPB, 0, st>>>(s->part, nbq, sc_block(s, SC_WS) + 6);
     HIP_TRY(hipGetLastError());
     if (vos_status e = read_back(s, sc_block(s, SC_WS) + 6, 1)) return e;
     const double e2 = s->host[0];
@@ -1166,7 +1252,7 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
         break;
       }
       case VOS_KERNEL_P_APPLY:
-        k_p_apply<<<grid_blocks(g.nc), TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->p, s->vec[4], s->part, flag);
+        p_apply(s, s->p, s->vec[4], flag);
         if (count) { per_seq_bytes += (2.0 + nd) * 8.0 * g.nc; ++per_seq_launches; }
         break;
       case VOS_KERNEL_ADR_APPLY:

@@ -49,7 +49,7 @@ class _Opts(C.Structure):
     _fields_ = [("rtol_u", C.c_double), ("rtol_p", C.c_double), ("rtol_c", C.c_double),
                 ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
                 ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int),
-                ("use_graphs", C.c_int), ("coarse_cells", C.c_int)]
+                ("use_graphs", C.c_int), ("coarse_cells", C.c_int), ("level_kernels", C.c_int)]
 
 
 class _Diag(C.Structure):
@@ -125,6 +125,7 @@ class Opts:
     check_every: int = 8
     use_graphs: int = 1
     coarse_cells: int = 0
+    level_kernels: int = 0  # 0: fused fine-level multigrid kernels, 1: one plain kernel per sweep
 
 
 class Sim:

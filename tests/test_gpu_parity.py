@@ -127,6 +127,63 @@ def test_ragged_and_3d(orc, shape):
     _compare(st, g, eps0)
 
 
+@pytest.mark.parametrize("shape,precision", [((70, 12, 9), 0), ((70, 12, 9), 1), ((96, 10, 6), 1)])
+def test_3d_marching_levels_vs_oracle(orc, shape, precision):
+    """3-D levels wide enough for the z-marching multigrid kernels (ragged in
+    x, y and z; coarse levels down to 64 cells, so marching and plain levels
+    alternate in one hierarchy) against the oracle."""
+    from paper_2204_07019_amd import inputs
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx + 7 * nz)
+    es = np.zeros((nz, ny, nx))
+    es[1:nz - 1, ny // 4: 3 * ny // 4, nx // 3: nx // 3 + 9] = 1.0
+    es[:, 1: ny // 4, nx // 2 + 3] = rng.uniform(0.3, 0.7)
+    prm = dict(inputs.BASE_PARAMS, dx=5e-6)
+    prob = make_problem(es, prm, model=0, **TIGHT)
+    _say(f"3-D marching levels {shape} precision {precision}")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 3, precision=precision, coarse_cells=64)
+    _compare(st, g, eps0)
+
+
+LEVEL_CASES = [  # (shape, precision, extra options): 2-D tiled and 3-D marching levels
+    ((96, 40, 1), 0, {}),
+    ((96, 40, 1), 1, {"mg_nu": 3}),
+    ((70, 12, 9), 0, {"coarse_cells": 64}),
+    ((70, 12, 9), 1, {"coarse_cells": 64, "mg_nu": 3}),
+    ((64, 32, 16), 1, {"mg_nu": 1}),
+    ((130, 20, 11), 0, {"coarse_cells": 64, "mg_nu": 2}),
+]
+
+
+@pytest.mark.parametrize("shape,precision,extra", LEVEL_CASES)
+def test_level_kernels_bitwise(orc, shape, precision, extra):
+    """The fused fine-level multigrid kernels (2-D tiles, 3-D z-marching) and
+    the plain one-kernel-per-sweep path form every value by the same
+    expression: fields and iteration counts are bitwise equal."""
+    from paper_2204_07019_amd import inputs
+    nx, ny, nz = shape
+    if nz == 1:
+        es = inputs.rsa_discs(nx, ny, seed=9, rmin=3, rmax=7, porosity=0.7)
+    else:
+        rng = np.random.default_rng(nx * nz)
+        es = np.clip(rng.uniform(-3.0, 1.5, (nz, ny, nx)), 0.0, 1.0)
+        es[:, :, :2] = 0.0
+        es[:, :, -2:] = 0.0
+    prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=5e-6), rtol_u=1e-9, rtol_p=1e-9, rtol_c=1e-9)
+    out, its = [], []
+    for lk in (0, 1):
+        _say(f"level kernels {lk} {shape} precision {precision} {extra}")
+        sim = gpu_sim(prob, precision, level_kernels=lk, **extra)
+        sim.set_solid_fraction(es)
+        d = [sim.step(1e-3) for _ in range(3)]
+        its.append([(x["it_u"], x["it_p"], x["it_c"]) for x in d])
+        out.append({k: sim.get_numpy(k) for k in ("ux", "uy", "uz", "p", "c", "eps")})
+        sim.close()
+    assert its[0] == its[1], its
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), (k, rel_l2(out[0][k], out[1][k]))
+
+
 def test_empty_solid_and_fully_fluid(orc):
     """Degenerate geometries: no solid at all (no reaction, c -> c_in)."""
     from paper_2204_07019_amd import inputs
