@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # (tiled kernels): finest level down leg r 8 + diag + 2 face T + b + x + coarse
 # b/4, up leg x + coarse x/4 + b + diag + 2 face T + result + z 8, times 4/3
 # for the coarser levels: FP32 hierarchy 83 B, FP64 144 B.  3-D V-cycle
-# (per-sweep kernels, two sweeps): FP32 187 B, FP64 318 B.
+# (one launch per sweep, the first two sweeps fused): FP32 187 B, FP64 318 B.
 P_ITER_BYTES = {("mixed", 2): 136 + 83, ("fp64", 2): 136 + 144,
                 ("mixed", 3): 152 + 187, ("fp64", 3): 152 + 318}
 # Per-step pressure setup (hierarchy build, right-hand side, initial residual):
@@ -120,15 +120,18 @@ def roofline(sim, family, reps=200, with_traffic=True):
             "avg_launch_us": round(t["avg_ms"] * 1e3, 3), "bytes_per_launch": round(t["bytes"])}
 
 
-def pressure_3d(vos, inputs, n, dt):
+def pressure_3d(vos, inputs, n, dt, precision=None):
     """The pressure solve on the 256^3 sphere pack (dx = 4 um, seed 33), FP64
-    multigrid, from a flow relaxed by two steps: algorithmic GB/s of the
-    pressure stage and the live roofline of the pressure operator."""
+    (or mixed-precision) multigrid, from a flow relaxed by two steps:
+    algorithmic GB/s of the pressure stage and the live roofline of the
+    pressure operator."""
     import torch
+    precision = vos.FP64 if precision is None else precision
+    tag = "fp64" if precision == vos.FP64 else "mixed"
     es = inputs.sphere_pack(n, seed=33)
     prm = dict(inputs.BASE_PARAMS, dx=4e-6, model=0)
     sim = vos.Sim(n, n, n, prm["dx"], dict(prm, kc=0.0),
-                  vos.Opts(precision=vos.FP64, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000))
+                  vos.Opts(precision=precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000))
     sim.set_solid_fraction(es)
     conv = True
     try:
@@ -145,8 +148,9 @@ def pressure_3d(vos, inputs, n, dt):
     el = time.perf_counter() - t0
     cells = n ** 3
     t_p = d["t_ms"][2] * 1e-3
-    pb = cells * (P_ITER_BYTES[("fp64", 3)] * d["it_p"] + P_SETUP_BYTES[3])
-    out = {"workload": f"pack {n}^3 dx=4um porosity 0.23 seed 33, FP64 multigrid, rtol 1e-8",
+    pb = cells * (P_ITER_BYTES[(tag, 3)] * d["it_p"] + P_SETUP_BYTES[3])
+    hier = "FP64" if precision == vos.FP64 else "FP32"
+    out = {"workload": f"pack {n}^3 dx=4um porosity 0.23 seed 33, {hier} multigrid, rtol 1e-8",
            "converged": conv, "res_p": d["res_p"],
            "its": d["it_p"], "pressure_ms": round(d["t_ms"][2], 2), "step_ms": round(el * 1e3, 1),
            "GBs_algorithmic": round(pb / t_p / 1e9, 1), "frac_hbm": round(pb / t_p / 1e9 / HBM_PEAK_GBS, 4),
@@ -361,6 +365,7 @@ def main():
     ap.add_argument("--timer", default="v_down", help="kernel family for the live roofline")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D pressure-solve measurement")
     ap.add_argument("--n3d", type=int, default=256)
+    ap.add_argument("--only-3d", action="store_true", help="measure only the 3-D pressure solve and print it")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -396,6 +401,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     vos.lib()
+    if args.only_3d:
+        print(json.dumps({"pressure_3d": pressure_3d(vos, inputs, args.n3d, args.dt),
+                          "pressure_3d_mixed": pressure_3d(vos, inputs, args.n3d, args.dt, vos.MIXED)}),
+              flush=True)
+        return
 
     log(f"setup {args.workload} Pe={args.pe} Da={args.da}")
     sim, es, params, info = setup_sim(vos, inputs, scaling, args.workload, args.pe, args.da,
@@ -434,6 +444,7 @@ def main():
     roof = roofline(sim, args.timer)
     others = {k: roofline(sim, k) for k in ("v_up", "v_coarse", "p_apply", "adr_apply")}
     p3d = None if args.no_3d else pressure_3d(vos, inputs, args.n3d, args.dt)
+    p3d_mixed = None if args.no_3d else pressure_3d(vos, inputs, args.n3d, args.dt, vos.MIXED)
     bat = None
     if not args.no_batch:
         log(f"batch of {args.batch_n} micromodels")
@@ -480,6 +491,7 @@ def main():
         "roofline": roof,
         "roofline_other_kernels": others,
         "pressure_solve_3d": p3d,
+        "pressure_solve_3d_mixed": p3d_mixed,
         "batch_micromodels": bat,
         "unet": net,
         "learned_3d": learned,

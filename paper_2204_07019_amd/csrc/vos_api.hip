@@ -521,8 +521,9 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
         if (l == 0) k_v_pre<Lv, R, true, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
         else k_v_pre<Lv, R, false, 1><<<nb, TPB, 0, st>>>(F, nd, r, dsc, rscale, om, sc);
       } else {
-        if (l == 0) k_v_pre3d<Lv, R, true><<<gr, TPB, 0, st>>>(F, r, dsc, rscale, om, zl, sc);
-        else k_v_pre3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, r, dsc, rscale, om, zl, sc);
+        if (l > 0) k_v_pre3d<Lv, R, RHS_B><<<gr, TPB, 0, st>>>(F, r, dsc, rscale, om, zl, sc);
+        else if (dsc) k_v_pre3d<Lv, R, RHS_RD><<<gr, TPB, 0, st>>>(F, r, dsc, rscale, om, zl, sc);
+        else k_v_pre3d<Lv, R, RHS_R><<<gr, TPB, 0, st>>>(F, r, dsc, rscale, om, zl, sc);
       }
       for (int k = 2; k < nu; ++k) {
         k_v_jacobi3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, nullptr, nullptr, zl, sc);

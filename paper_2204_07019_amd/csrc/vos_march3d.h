@@ -57,71 +57,114 @@ struct ZNb {
   R w, e, s, n, b, t;
 };
 
-// A x in the lv_apply order (mg_apply_cell / smg_apply_cell) from explicit neighbour values.
+// Diagonal and the six neighbour coefficients of a cell as stored (MgLevel:
+// face transmissibilities T, subtracted; SLevel: off-diagonals, added), in
+// the neighbour slot order -x, +x, -y, +y, -z, +z.  Loaded unconditionally
+// (every index is inside its array) so that all loads of a plane are in
+// flight together; a missing neighbour's term is skipped by a select.
 template <typename R>
-__device__ __forceinline__ R zapply(const MgLevel<R> &L, unsigned id, const int c[3], R xc, const ZNb<R> &x)
+struct ZCoef {
+  R d, o[6];
+};
+
+template <typename R>
+__device__ __forceinline__ ZCoef<R> zcoef(const MgLevel<R> &L, unsigned id, const int c[3])
 {
+  ZCoef<R> k;
   const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
-  const R tw = L.T[0][f0], te = L.T[0][f0 + 1];
-  R v = L.diag[id] * xc;
-  if (c[0] > 0) v -= tw * x.w;
-  if (c[0] < L.n[0] - 1) v -= te * x.e;
   const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
-  const R ts = L.T[1][f1], tn = L.T[1][f1 + L.fd[1][0]];
-  if (c[1] > 0) v -= ts * x.s;
-  if (c[1] < L.n[1] - 1) v -= tn * x.n;
-  const unsigned sz = (unsigned)L.n[0] * L.n[1];
   const unsigned f2 = (unsigned)c[0] + (unsigned)L.fd[2][0] * ((unsigned)c[1] + (unsigned)L.fd[2][1] * c[2]);
-  const R tb = L.T[2][f2], tt = L.T[2][f2 + sz];
-  if (c[2] > 0) v -= tb * x.b;
-  if (c[2] < L.n[2] - 1) v -= tt * x.t;
-  return v;
+  const unsigned sz = (unsigned)L.n[0] * L.n[1];
+  k.d = L.diag[id];
+  k.o[0] = L.T[0][f0];
+  k.o[1] = L.T[0][f0 + 1];
+  k.o[2] = L.T[1][f1];
+  k.o[3] = L.T[1][f1 + L.fd[1][0]];
+  k.o[4] = L.T[2][f2];
+  k.o[5] = L.T[2][f2 + sz];
+  return k;
 }
 
 template <typename R>
-__device__ __forceinline__ R zapply(const SLevel<R> &L, unsigned id, const int c[3], R xc, const ZNb<R> &x)
+__device__ __forceinline__ ZCoef<R> zcoef(const SLevel<R> &L, unsigned id, const int *)
 {
-  R v = L.diag[id] * xc;
-  const unsigned nc = L.nc;
-  if (c[0] > 0) v += L.off[id] * x.w;
-  if (c[0] < L.n[0] - 1) v += L.off[nc + id] * x.e;
-  if (c[1] > 0) v += L.off[2 * nc + id] * x.s;
-  if (c[1] < L.n[1] - 1) v += L.off[3 * nc + id] * x.n;
-  if (c[2] > 0) v += L.off[4 * nc + id] * x.b;
-  if (c[2] < L.n[2] - 1) v += L.off[5 * nc + id] * x.t;
+  ZCoef<R> k;
+  k.d = L.diag[id];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) k.o[q] = L.off[(size_t)q * L.nc + id];
+  return k;
+}
+
+// Which neighbour slots exist.
+struct ZHas {
+  bool h[6];
+};
+__device__ __forceinline__ ZHas zhas(const int n[3], const int c[3])
+{
+  return ZHas{{c[0] > 0, c[0] < n[0] - 1, c[1] > 0, c[1] < n[1] - 1, c[2] > 0, c[2] < n[2] - 1}};
+}
+
+template <typename R>
+__device__ __forceinline__ R zterm(const MgLevel<R> &, R v, R o, R x) { return v - o * x; }
+template <typename R>
+__device__ __forceinline__ R zterm(const SLevel<R> &, R v, R o, R x) { return v + o * x; }
+
+// A x in the lv_apply order (mg_apply_cell / smg_apply_cell).
+template <typename Lv, typename R>
+__device__ __forceinline__ R zapply(const Lv &L, const ZHas &h, const ZCoef<R> &k, R xc, const ZNb<R> &x)
+{
+  R v = k.d * xc;
+  v = h.h[0] ? zterm(L, v, k.o[0], x.w) : v;
+  v = h.h[1] ? zterm(L, v, k.o[1], x.e) : v;
+  v = h.h[2] ? zterm(L, v, k.o[2], x.s) : v;
+  v = h.h[3] ? zterm(L, v, k.o[3], x.n) : v;
+  v = h.h[4] ? zterm(L, v, k.o[4], x.b) : v;
+  v = h.h[5] ? zterm(L, v, k.o[5], x.t) : v;
   return v;
 }
+
+// Neighbour coefficient as lv_off gives it: -T (MgLevel) or off (SLevel).
+template <typename R>
+__device__ __forceinline__ R zoff(const MgLevel<R> &, R o) { return -o; }
+template <typename R>
+__device__ __forceinline__ R zoff(const SLevel<R> &, R o) { return o; }
 
 // A x in the k_v_pre / k_v_post order: d x + lv_off * x over the neighbour slots.
 template <typename Lv, typename R>
-__device__ __forceinline__ R zapply_off(const Lv &L, unsigned id, const int c[3], R dg, R xc, const ZNb<R> &x)
+__device__ __forceinline__ R zapply_off(const Lv &L, const ZHas &h, const ZCoef<R> &k, R dg, R xc, const ZNb<R> &x)
 {
   R v = dg * xc;
-  if (c[0] > 0) v += lv_off(L, id, c, 0) * x.w;
-  if (c[0] < L.n[0] - 1) v += lv_off(L, id, c, 1) * x.e;
-  if (c[1] > 0) v += lv_off(L, id, c, 2) * x.s;
-  if (c[1] < L.n[1] - 1) v += lv_off(L, id, c, 3) * x.n;
-  if (c[2] > 0) v += lv_off(L, id, c, 4) * x.b;
-  if (c[2] < L.n[2] - 1) v += lv_off(L, id, c, 5) * x.t;
+  v = h.h[0] ? v + zoff(L, k.o[0]) * x.w : v;
+  v = h.h[1] ? v + zoff(L, k.o[1]) * x.e : v;
+  v = h.h[2] ? v + zoff(L, k.o[2]) * x.s : v;
+  v = h.h[3] ? v + zoff(L, k.o[3]) * x.n : v;
+  v = h.h[4] ? v + zoff(L, k.o[4]) * x.b : v;
+  v = h.h[5] ? v + zoff(L, k.o[5]) * x.t : v;
   return v;
 }
 
-// The march.  O: per-cell record whose member s is the staged value.
-//   own(id, c)  -> O   the thread's own cell (reads only)
+// The march.  O: per-cell record whose member s is the staged value; K: the
+// per-cell data the body reads (coefficients, right-hand side).
+//   own(id, c)  -> O   the thread's own cell
 //   halo(id, c) -> R   the staged value of a halo cell
-//   body(in, id, c, cur, nb)  plane z of the own cell (called by every thread
-//                     of the block, in == false outside the level, so that
-//                     body may hold block-uniform barriers)
-template <typename R, typename O, typename OwnF, typename HaloF, typename BodyF>
+//   coef(id, c) -> K   loaded before the plane's barrier
+//   body(in, id, c, cur, nb, k)  plane z of the own cell, called by every
+//                     thread of the block (in == false outside the level) so
+//                     that body may hold block-uniform barriers
+// own and halo are called for every thread with an in-range cell (the level's
+// cell 0 when the thread has none) and their result is discarded there, so
+// that their loads are not split into branches.
+template <typename R, typename O, typename K, typename OwnF, typename HaloF, typename CoefF, typename BodyF>
 __device__ __forceinline__ void zmarch(const int n[3], const ZTile &t, ZPlane<R> *pl, OwnF own, HaloF halo,
-                                       BodyF body)
+                                       CoefF coef, BodyF body)
 {
+  __shared__ R dump[TPB];   // halo stores of threads without a halo cell (never read)
   const int nx = n[0], ny = n[1], nz = n[2];
   const unsigned sz = (unsigned)nx * (unsigned)ny;
   const int lx = threadIdx.x % ZT_X, ly = threadIdx.x / ZT_X;
   const int gx = t.x0 + lx, gy = t.y0 + ly;
   const bool in = gx < nx && gy < ny;
-  const unsigned col = in ? (unsigned)gx + (unsigned)nx * (unsigned)gy : 0u;
+  const unsigned col = in ? (unsigned)gx + (unsigned)nx * (unsigned)gy : 0u;   // column of cell (0, 0) outside
   // this thread's halo cell (136 of them: rows above and below, columns left and right)
   int hx = -1, hy = -1;
   {
@@ -135,34 +178,42 @@ __device__ __forceinline__ void zmarch(const int n[3], const ZTile &t, ZPlane<R>
   const bool hin = hx >= 0 && hgx >= 0 && hgx < nx && hgy >= 0 && hgy < ny;
   const unsigned hcol = hin ? (unsigned)hgx + (unsigned)nx * (unsigned)hgy : 0u;
 
-  auto stage = [&](int z, int slot, bool with_halo, O &o) {
-    o = O{};
-    if (in && z < nz) {
-      const int c[3] = {gx, gy, z};
-      o = own(col + sz * (unsigned)z, c);
-    }
-    pl[slot][ly + 1][lx + 1] = o.s;
-    if (with_halo && hx >= 0) {
-      R v = (R)0;
-      if (hin && z < nz) {
-        const int c[3] = {hgx, hgy, z};
-        v = halo(hcol + sz * (unsigned)z, c);
-      }
-      pl[slot][hy][hx] = v;
-    }
+  auto own_at = [&](int z) -> O {
+    const bool ok = in && z >= 0 && z < nz;
+    const int c[3] = {ok ? gx : 0, ok ? gy : 0, ok ? z : 0};
+    const O o = own(ok ? col + sz * (unsigned)z : 0u, c);
+    return ok ? o : O{};
+  };
+  auto halo_at = [&](int z, bool want) -> R {
+    const bool ok = want && hin && z < nz;
+    const int c[3] = {ok ? hgx : 0, ok ? hgy : 0, ok ? z : 0};
+    const R v = halo(ok ? hcol + sz * (unsigned)z : 0u, c);
+    return ok ? v : (R)0;
   };
 
-  R sm = (R)0;   // own staged value of plane z - 1
-  if (t.z0 > 0 && in) {
-    const int c[3] = {gx, gy, t.z0 - 1};
-    sm = own(col + sz * (unsigned)(t.z0 - 1), c).s;
+  // LDS slot of this thread's halo value in each plane (a private dump slot without one)
+  auto hslot = [&](int slot) -> R * { return hx >= 0 ? &pl[slot][hy][hx] : &dump[threadIdx.x]; };
+
+  R sm = t.z0 > 0 ? own_at(t.z0 - 1).s : (R)0;   // own staged value of plane z - 1
+  O cur = own_at(t.z0);
+  {
+    const R hv = halo_at(t.z0, true);
+    pl[0][ly + 1][lx + 1] = cur.s;
+    *hslot(0) = hv;
   }
-  O cur, nxt;
-  stage(t.z0, 0, true, cur);
   int s = 0;
   for (int z = t.z0; z < t.z1; ++z) {
     const int s1 = s == 2 ? 0 : s + 1;
-    stage(z + 1, s1, z + 1 < t.z1, nxt);
+    const int c[3] = {gx, gy, z};
+    const unsigned id = col + sz * (unsigned)z;
+    // loads of plane z + 1's staged values and of plane z's coefficients, all
+    // unconditional (outside the level: cell (0, 0, z), result unused)
+    const O nxt = own_at(z + 1);
+    const R hv = halo_at(z + 1, z + 1 < t.z1);
+    const int cs[3] = {in ? gx : 0, in ? gy : 0, z};
+    const K k = coef(id, cs);
+    pl[s1][ly + 1][lx + 1] = nxt.s;
+    *hslot(s1) = hv;
     __syncthreads();
     const ZPlane<R> &p = pl[s];
     ZNb<R> nb;
@@ -172,13 +223,19 @@ __device__ __forceinline__ void zmarch(const int n[3], const ZTile &t, ZPlane<R>
     nb.n = p[ly + 2][lx + 1];
     nb.b = sm;
     nb.t = nxt.s;
-    const int c[3] = {gx, gy, z};
-    body(in, col + sz * (unsigned)z, c, cur, nb);
+    body(in, id, c, cur, nb, k);
     sm = cur.s;
     cur = nxt;
     s = s1;
   }
 }
+
+// Coefficients and right-hand side of a cell.
+template <typename R>
+struct ZCoefB {
+  ZCoef<R> a;
+  R b;
+};
 
 // One damped-Jacobi sweep (k_v_jacobi).
 template <typename Lv, typename R, bool OUT64>
@@ -191,18 +248,24 @@ __global__ void __launch_bounds__(TPB) k_v_jacobi3d(Lv L, const R *__restrict__ 
   if (!ztile_of(L.n, zlen, t)) return;
   __shared__ ZPlane<R> pl[3];
   struct O { R s; };
-  zmarch<R, O>(
+  zmarch<R, O, ZCoefB<R>>(
       L.n, t, pl, [&](unsigned id, const int *) { return O{x[id]}; }, [&](unsigned id, const int *) { return x[id]; },
-      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb) {
+      [&](unsigned id, const int *c) { return ZCoefB<R>{zcoef(L, id, c), L.b[id]}; },
+      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb, const ZCoefB<R> &k) {
         if (!in) return;
-        const R v = cur.s + omega * (L.b[id] - zapply(L, id, c, cur.s, nb)) / L.diag[id];
+        const R v = cur.s + omega * (k.b - zapply(L, zhas(L.n, c), k.a, cur.s, nb)) / k.a.d;
         xo[id] = v;
         if (OUT64) z[id] = unscale((double)v, dsc, id);
       });
 }
 
+// Right-hand side of a pre-smoothing kernel: the level's b (RHS_B), or on
+// level 0 the FP64 residual (R)(rscale r) (RHS_R) or (R)(rscale r / sqrt(dsc))
+// (RHS_RD) -- k_v_pre's FROM64 expression with the dsc test taken on the host.
+enum { RHS_B = 0, RHS_R = 1, RHS_RD = 2 };
+
 // Pre-smoothing sweeps 1 and 2 (k_v_pre with two sweeps).
-template <typename Lv, typename R, bool FROM64>
+template <typename Lv, typename R, int RHS>
 __global__ void __launch_bounds__(TPB) k_v_pre3d(Lv L, const double *__restrict__ r64,
                                                  const double *__restrict__ dsc, double rscale, R omega, int zlen,
                                                  const double *__restrict__ sc)
@@ -212,11 +275,13 @@ __global__ void __launch_bounds__(TPB) k_v_pre3d(Lv L, const double *__restrict_
   if (!ztile_of(L.n, zlen, t)) return;
   __shared__ ZPlane<R> pl[3];
   struct O { R s, bb, dg; };
+  constexpr bool FROM64 = RHS != RHS_B;
   auto rhs = [&](unsigned id) -> R {
-    if (FROM64) return (R)(rscale * (dsc ? r64[id] / sqrt(dsc[id]) : r64[id]));
+    if (RHS == RHS_RD) return (R)(rscale * (r64[id] / sqrt(dsc[id])));
+    if (RHS == RHS_R) return (R)(rscale * r64[id]);
     return L.b[id];
   };
-  zmarch<R, O>(
+  zmarch<R, O, ZCoef<R>>(
       L.n, t, pl,
       [&](unsigned id, const int *) {
         O o;
@@ -226,10 +291,11 @@ __global__ void __launch_bounds__(TPB) k_v_pre3d(Lv L, const double *__restrict_
         return o;
       },
       [&](unsigned id, const int *) { return omega * rhs(id) / L.diag[id]; },
-      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb) {
+      [&](unsigned id, const int *c) { return zcoef(L, id, c); },
+      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb, const ZCoef<R> &k) {
         if (!in) return;
         if (FROM64) L.b[id] = cur.bb;
-        const R ax = zapply_off<Lv, R>(L, id, c, cur.dg, cur.s, nb);
+        const R ax = zapply_off<Lv, R>(L, zhas(L.n, c), k, cur.dg, cur.s, nb);
         L.x[id] = cur.s + omega * (cur.bb - ax) / cur.dg;
       });
 }
@@ -246,11 +312,12 @@ __global__ void __launch_bounds__(TPB) k_v_restrict3d(Lv F, Lv C, int zlen, cons
   struct O { R s; };
   const R *x = F.x;
   const int lx = threadIdx.x % ZT_X, ly = threadIdx.x / ZT_X;
-  zmarch<R, O>(
+  zmarch<R, O, ZCoefB<R>>(
       F.n, t, pl, [&](unsigned id, const int *) { return O{x[id]}; }, [&](unsigned id, const int *) { return x[id]; },
-      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb) {
+      [&](unsigned id, const int *c) { return ZCoefB<R>{zcoef(F, id, c), F.b[id]}; },
+      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb, const ZCoefB<R> &k) {
         const int z = c[2];
-        rs[z & 1][ly][lx] = in ? F.b[id] - zapply(F, id, c, cur.s, nb) : (R)0;
+        rs[z & 1][ly][lx] = in ? k.b - zapply(F, zhas(F.n, c), k.a, cur.s, nb) : (R)0;
         if ((z & 1) == 0 && z + 1 < F.n[2]) return;   // block-uniform
         __syncthreads();
         // sum over each 2 x 2 x 2 aggregate (cz, cy, cx from outer to inner)
@@ -283,13 +350,14 @@ __global__ void __launch_bounds__(TPB) k_v_post3d(Lv F, Lv C, R *__restrict__ xo
   __shared__ ZPlane<R> pl[3];
   struct O { R s; };
   auto yv = [&](unsigned id, const int *c) -> R { return F.x[id] + C.x[parent_of<R>(F.n, C.n, 3, c)]; };
-  zmarch<R, O>(
+  zmarch<R, O, ZCoefB<R>>(
       F.n, t, pl, [&](unsigned id, const int *c) { return O{yv(id, c)}; }, yv,
-      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb) {
+      [&](unsigned id, const int *c) { return ZCoefB<R>{zcoef(F, id, c), F.b[id]}; },
+      [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb, const ZCoefB<R> &k) {
         if (!in) return;
-        const R dg = F.diag[id];
-        const R ay = zapply_off<Lv, R>(F, id, c, dg, cur.s, nb);
-        const R v = cur.s + omega * (F.b[id] - ay) / dg;
+        const R dg = k.a.d;
+        const R ay = zapply_off<Lv, R>(F, zhas(F.n, c), k.a, dg, cur.s, nb);
+        const R v = cur.s + omega * (k.b - ay) / dg;
         xo[id] = v;
         if (OUT64) z[id] = unscale((double)v, dsc, id);
       });
@@ -309,29 +377,33 @@ __global__ void __launch_bounds__(TPB) k_p_apply3d(Dev g, const double *__restri
   ZTile t;
   if (ztile_of(g.n, zlen, t)) {
     struct O { double s; };
-    zmarch<double, O>(
+    struct K { double tw, te, ts, tn, tb, tt; };
+    zmarch<double, O, K>(
         g.n, t, pl, [&](unsigned id, const int *) { return O{p[id]}; },
         [&](unsigned id, const int *) { return p[id]; },
-        [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<double> &nb) {
-          if (!in) return;
-          const double pc = cur.s;
+        [&](unsigned, const int *c) {
           const unsigned f0 = fidx(g, 0, c[0], c[1], c[2]);
-          const double tw = T0[f0], te = T0[f0 + 1];
-          double v = (tw + te) * pc;
-          if (c[0] > 0) v -= tw * nb.w;
-          if (c[0] < g.n[0] - 1) v -= te * nb.e;
           const unsigned f1 = fidx(g, 1, c[0], c[1], c[2]);
-          const unsigned sy = (unsigned)g.fd[1][0];
-          const double ts = T1[f1], tn = T1[f1 + sy];
-          v += (ts + tn) * pc;
-          if (c[1] > 0) v -= ts * nb.s;
-          if (c[1] < g.n[1] - 1) v -= tn * nb.n;
           const unsigned f2 = fidx(g, 2, c[0], c[1], c[2]);
-          const unsigned sz = (unsigned)g.n[0] * g.n[1];
-          const double tb = T2[f2], tt = T2[f2 + sz];
-          v += (tb + tt) * pc;
-          if (c[2] > 0) v -= tb * nb.b;
-          if (c[2] < g.n[2] - 1) v -= tt * nb.t;
+          const unsigned sy = (unsigned)g.fd[1][0], sz = (unsigned)g.n[0] * g.n[1];
+          const K k{T0[f0], T0[f0 + 1], T1[f1], T1[f1 + sy], T2[f2], T2[f2 + sz]};
+          // keep the loads ahead of the plane's barrier (one memory round trip per plane)
+          asm volatile("" ::"v"(k.tw), "v"(k.te), "v"(k.ts), "v"(k.tn), "v"(k.tb), "v"(k.tt));
+          return k;
+        },
+        [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<double> &nb, const K &k) {
+          if (!in) return;
+          const ZHas h = zhas(g.n, c);
+          const double pc = cur.s;
+          double v = (k.tw + k.te) * pc;
+          v = h.h[0] ? v - k.tw * nb.w : v;
+          v = h.h[1] ? v - k.te * nb.e : v;
+          v += (k.ts + k.tn) * pc;
+          v = h.h[2] ? v - k.ts * nb.s : v;
+          v = h.h[3] ? v - k.tn * nb.n : v;
+          v += (k.tb + k.tt) * pc;
+          v = h.h[4] ? v - k.tb * nb.b : v;
+          v = h.h[5] ? v - k.tt * nb.t : v;
           q[id] = v;
           acc += pc * v;
         });
