@@ -152,7 +152,8 @@ def pressure_3d(vos, inputs, n, dt, precision=None):
     hier = "FP64" if precision == vos.FP64 else "FP32"
     out = {"workload": f"pack {n}^3 dx=4um porosity 0.23 seed 33, {hier} multigrid, rtol 1e-8",
            "converged": conv, "res_p": d["res_p"],
-           "its": d["it_p"], "pressure_ms": round(d["t_ms"][2], 2), "step_ms": round(el * 1e3, 1),
+           "its": d["it_p"], "its_fp64_hierarchy": d["it_p_fp64"] if precision != vos.FP64 else d["it_p"],
+           "pressure_ms": round(d["t_ms"][2], 2), "step_ms": round(el * 1e3, 1),
            "GBs_algorithmic": round(pb / t_p / 1e9, 1), "frac_hbm": round(pb / t_p / 1e9 / HBM_PEAK_GBS, 4),
            "p_apply_roofline": roofline(sim, "p_apply", with_traffic=False) if conv else None}
     sim.close()

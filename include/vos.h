@@ -110,6 +110,13 @@ typedef struct {
                        leg of a level; 3-D: sweeps that march through z with the neighbours in
                        LDS and registers); 1 one plain kernel per sweep.  Both form every value
                        by the same expression: results are bitwise identical. */
+  int p_fp32_its;   /* VOS_MIXED: at most this many pressure iterations per solve with the FP32
+                       hierarchy before the solve continues with an FP64 one (0: no limit).
+                       Independently, a solve switches once its residual has not halved within
+                       400 iterations (FP32 rounding can stall the outer CG above 1e-8 when the
+                       diagonal spans many orders of magnitude), and the later solves then use
+                       the FP64 hierarchy from the start until the next
+                       vos_set_solid_fraction.  >= 0. */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */
@@ -139,6 +146,8 @@ typedef struct {
   double guess_error_drop;       /* with the guess on: the fraction of the squared A-norm error
                                     of starting from p^n that the guess removed, in [0, 1],
                                     measured against the converged solution */
+  int it_p_fp64;                 /* VOS_MIXED: pressure iterations run with the FP64 hierarchy
+                                    after the FP32 one stalled or reached p_fp32_its (0: none) */
 } vos_diag;
 
 /* Fields for vos_set_field / vos_get_field / vos_field_ptr. */

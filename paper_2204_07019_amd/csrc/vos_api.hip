@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "vos.h"
 #include "vos_device.h"
@@ -166,6 +167,9 @@ struct Layout {
 };
 
 constexpr int NSC = 8;  // scalar blocks: mom x/y/z, pressure, transport, misc, diag, spare
+// Iterations without the residual halving after which a mixed-precision
+// pressure solve continues with the FP64 hierarchy.
+constexpr int P_STALL_WINDOW = 400;
 
 // Aggregation hierarchy: ceil-halve every active dimension until <= SMG_COARSE_MAX cells.
 void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs)
@@ -222,12 +226,15 @@ Layout make_layout(const vos_grid &g, int precision)
   LevelDims lv[MG_MAX_LEVELS];
   Lo.nlev = mg_hierarchy(g, lv);
   const size_t rs = precision == VOS_MIXED ? sizeof(float) : sizeof(double);
+  // the pressure hierarchy is sized for FP64 in both modes: a mixed-precision
+  // solve whose FP32 hierarchy stalls continues with an FP64 one built over it
+  const size_t rsp = sizeof(double);
   for (int l = 0; l < Lo.nlev; ++l) {
-    for (int d = 0; d < 3; ++d) Lo.mgT[l][d] = P.take(lv[l].nf[d] * rs);
-    Lo.mgdiag[l] = P.take(lv[l].nc * rs);
-    Lo.mgx[l] = P.take(lv[l].nc * rs);
-    Lo.mgb[l] = P.take(lv[l].nc * rs);
-    Lo.mgt[l] = P.take(lv[l].nc * rs);
+    for (int d = 0; d < 3; ++d) Lo.mgT[l][d] = P.take(lv[l].nf[d] * rsp);
+    Lo.mgdiag[l] = P.take(lv[l].nc * rsp);
+    Lo.mgx[l] = P.take(lv[l].nc * rsp);
+    Lo.mgb[l] = P.take(lv[l].nc * rsp);
+    Lo.mgt[l] = P.take(lv[l].nc * rsp);
   }
   const int nd = g.nz == 1 ? 2 : 3;
   for (int d = 0; d < 3; ++d) {
@@ -292,6 +299,8 @@ struct vos_sim {
   double ws_res_prev, ws_res_guess;
   double ws_drop;           // decrease of the squared A-norm error the guess achieved
   double ws_frac;           // ws_drop / squared A-norm error of starting from p^n
+  int it_p_fp64;            // iterations of the last pressure solve run with the FP64 hierarchy (mixed)
+  bool p_fp64_sticky;       // an FP32 pressure solve stalled on the current geometry (mixed)
 };
 
 namespace {
@@ -360,6 +369,7 @@ vos_status check_opts(const vos_opts *o)
   if (o->coarse_cells != 0 && (o->coarse_cells < 64 || o->coarse_cells > 65536))
     return fail(VOS_ERR_ARG, "coarse_cells must be 0 or in [64, 65536]");
   if (o->level_kernels != 0 && o->level_kernels != 1) return fail(VOS_ERR_ARG, "level_kernels must be 0 or 1");
+  if (o->p_fp32_its < 0) return fail(VOS_ERR_ARG, "p_fp32_its must be >= 0");
   return VOS_OK;
 }
 
@@ -385,9 +395,17 @@ vos_status read_back(vos_sim *s, const double *dev, size_t n)
 // With graphs on, a chunk of check_every iterations is captured once per
 // solve (gid) and replayed; every kernel in it returns at once after the flag
 // is set, so replaying a whole chunk past convergence changes nothing.
+// Stall rule of a solve that may switch preconditioners: give up once the
+// residual has not halved within `window` iterations, or after `cap`
+// iterations (0: no cap).  window 0: never.
+struct Stall {
+  int window = 0, cap = 0;
+  bool hit = false, by_cap = false;
+};
+
 template <typename F>
 vos_status krylov_loop(vos_sim *s, int gid, double *sc, int maxit, F &&iter, int *its, double *res2, double *tol2,
-                       bool *conv)
+                       bool *conv, Stall *stall = nullptr)
 {
   HIP_TRY(hipGetLastError());
   int launched = 0;
@@ -395,6 +413,8 @@ vos_status krylov_loop(vos_sim *s, int gid, double *sc, int maxit, F &&iter, int
   if (st) return st;
   bool done = s->host[S_CONV] != 0.0;
   const int chunk = s->opt.check_every;
+  double mark = s->host[S_RES2];
+  int mark_its = (int)s->host[S_ITS];
   while (!done && launched < maxit) {
     if (s->use_graphs) {
       if (!s->gexec[gid]) {
@@ -420,6 +440,19 @@ vos_status krylov_loop(vos_sim *s, int gid, double *sc, int maxit, F &&iter, int
     st = read_back(s, sc, S_COUNT);
     if (st) return st;
     done = s->host[S_CONV] != 0.0;
+    if (stall && !done) {
+      const int it = (int)s->host[S_ITS];
+      if (s->host[S_RES2] <= 0.25 * mark) {
+        mark = s->host[S_RES2];
+        mark_its = it;
+      }
+      const bool capped = stall->cap > 0 && it >= stall->cap;
+      if (capped || (stall->window > 0 && it - mark_its >= stall->window)) {
+        stall->hit = true;
+        stall->by_cap = capped;
+        break;
+      }
+    }
   }
   *its = (int)s->host[S_ITS];
   *res2 = s->host[S_RES2];
@@ -901,7 +934,7 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double
 }
 
 template <typename R>
-vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
+vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, double *res)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
@@ -935,8 +968,36 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
   };
   double res2, tol2;
   bool conv;
-  vos_status stt = krylov_loop(s, 3, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv);
+  Stall stall;
+  const bool mixed = std::is_same<R, float>::value;
+  if (mixed) {
+    stall.window = P_STALL_WINDOW;
+    stall.cap = s->opt.p_fp32_its;
+  }
+  s->it_p_fp64 = 0;
+  vos_status stt = krylov_loop(s, gid, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv, mixed ? &stall : nullptr);
   if (stt) return stt;
+  if (!mixed && s->opt.precision == VOS_MIXED) s->it_p_fp64 = *its;   // a solve after an FP32 stall
+  if (stall.hit && !conv) {
+    if (!stall.by_cap) s->p_fp64_sticky = true;   // later solves of this geometry start in FP64
+    // continue the same flexible CG with an FP64 hierarchy built over the FP32 one's memory
+    // (the next solve rebuilds the FP32 hierarchy)
+    mg_setup<double>(s, s->mgd);
+    auto iter64 = [&]() {
+      const int nbq = p_apply(s, pv, q, sc);
+      k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nbq, rt2, sc);
+      k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->pdiag, s->p, r, z, 0, s->part, sc);
+      k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
+      mg_vcycle<double>(s, s->mgd, r, z, sc);
+      k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
+      k_cg_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
+      k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
+    };
+    const int its32 = *its;
+    stt = krylov_loop(s, 5, sc, std::max(1, s->opt.maxit_p - its32), iter64, its, &res2, &tol2, &conv);
+    if (stt) return stt;
+    s->it_p_fp64 = *its - its32;
+  }
   s->ws_frac = 0.0;
   if (s->net && s->ws_use) {
     // squared A-norm of the increment dp = p^{n+1} - p^n: the initial error of a start at p^n
@@ -956,8 +1017,10 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int *its, double *res)
 
 vos_status solve_pressure(vos_sim *s, int *its, double *res)
 {
-  if (s->opt.precision == VOS_MIXED) return solve_pressure_t<float>(s, s->mgf, its, res);
-  return solve_pressure_t<double>(s, s->mgd, its, res);
+  // mixed precision: the FP32 hierarchy until one of its solves stalls on this geometry, then
+  // FP64 (its iteration chunk captured under its own graph slot)
+  if (s->opt.precision == VOS_MIXED && !s->p_fp64_sticky) return solve_pressure_t<float>(s, s->mgf, 3, its, res);
+  return solve_pressure_t<double>(s, s->mgd, s->opt.precision == VOS_MIXED ? 5 : 3, its, res);
 }
 
 // ---------------------------------------------------------------- stage S4
@@ -1114,6 +1177,7 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   dg->res0_prev = s->net ? s->ws_res_prev : 0.0;
   dg->res0_guess = s->net ? s->ws_res_guess : 0.0;
   dg->guess_error_drop = s->net ? s->ws_frac : 0.0;
+  dg->it_p_fp64 = s->it_p_fp64;
   HIP_TRY(hipEventRecord(s->ev[3], st));
   launch_correct(s);
   HIP_TRY(hipEventRecord(s->ev[4], st));
@@ -1356,6 +1420,8 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->ws_s0 = 0.0;
   s->ws_used = 0;
   s->ws_res_prev = s->ws_res_guess = 0.0;
+  s->it_p_fp64 = 0;
+  s->p_fp64_sticky = false;
   s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
@@ -1408,6 +1474,7 @@ vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device
   int *bad = (int *)(s->vec[1]);
   HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), st));
   k_set_eps<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, src, s->P.eps_min, s->eps, bad);
+  s->p_fp64_sticky = false;   // a new geometry: mixed precision tries the FP32 hierarchy again
   k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, s->P.u_in, s->u[0]);
   HIP_TRY(hipGetLastError());
   int hbad = 0;

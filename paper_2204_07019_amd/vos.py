@@ -49,7 +49,8 @@ class _Opts(C.Structure):
     _fields_ = [("rtol_u", C.c_double), ("rtol_p", C.c_double), ("rtol_c", C.c_double),
                 ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
                 ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int),
-                ("use_graphs", C.c_int), ("coarse_cells", C.c_int), ("level_kernels", C.c_int)]
+                ("use_graphs", C.c_int), ("coarse_cells", C.c_int), ("level_kernels", C.c_int),
+                ("p_fp32_its", C.c_int)]
 
 
 class _Diag(C.Structure):
@@ -62,7 +63,7 @@ class _Diag(C.Structure):
                 ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
                 ("max_deps", C.c_double), ("alpha", C.c_double), ("t_ms", C.c_double * 6),
                 ("guess", C.c_int), ("res0_prev", C.c_double), ("res0_guess", C.c_double),
-                ("guess_error_drop", C.c_double)]
+                ("guess_error_drop", C.c_double), ("it_p_fp64", C.c_int)]
 
 
 _lib = None
@@ -126,6 +127,7 @@ class Opts:
     use_graphs: int = 1
     coarse_cells: int = 0
     level_kernels: int = 0  # 0: fused fine-level multigrid kernels, 1: one plain kernel per sweep
+    p_fp32_its: int = 0     # mixed: cap on FP32-preconditioned pressure iterations (0: stall detection only)
 
 
 class Sim:

@@ -145,6 +145,24 @@ def test_3d_marching_levels_vs_oracle(orc, shape, precision):
     _compare(st, g, eps0)
 
 
+def test_mixed_pressure_fp64_fallback(orc):
+    """Mixed precision whose pressure solves are sent to the FP64 hierarchy
+    after 8 FP32-preconditioned iterations (the path a stalled FP32 multigrid
+    takes) still matches the oracle, and reports the FP64 iterations."""
+    from paper_2204_07019_amd import inputs
+    nx, ny, nz = 70, 12, 9
+    rng = np.random.default_rng(11)
+    es = np.zeros((nz, ny, nx))
+    es[1:nz - 1, ny // 4: 3 * ny // 4, nx // 3: nx // 3 + 9] = 1.0
+    es[:, 1: ny // 4, nx // 2 + 3] = rng.uniform(0.3, 0.7)
+    prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=5e-6), model=0, **TIGHT)
+    _say("mixed precision, pressure forced to the FP64 hierarchy after 8 iterations")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 3, precision=1, p_fp32_its=8, coarse_cells=64)
+    for _, dg in diags:
+        assert dg["it_p"] > 8 and dg["it_p_fp64"] == dg["it_p"] - 8, dg
+    _compare(st, g, eps0)
+
+
 LEVEL_CASES = [  # (shape, precision, extra options): 2-D tiled and 3-D marching levels
     ((96, 40, 1), 0, {}),
     ((96, 40, 1), 1, {"mg_nu": 3}),
