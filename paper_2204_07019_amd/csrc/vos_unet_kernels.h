@@ -50,9 +50,10 @@ struct Vol {   // one NDHWC activation tensor (a channel slice of a buffer)
 // transposed weights.  A block of 4 waves owns 64 x-voxels (4 matrix tiles of 16) x 4 rows (wave w: row
 // 4 by + w) at one z; per chunk of 16 input channels the 3 x 6 x 66 halo of
 // the input is staged in LDS once, as [z][y][channel quad][x] of 4 BF16 each,
-// so a wave reads its A fragments from LDS for all 27 taps, and each weight
-// fragment is reused for the 4 matrix tiles.  Grid (ceil(W / 64), ceil(H / 4),
-// N * D).  Requires Cin % 16 == 0.
+// together with the chunk's weight fragments of all 27 taps ([tap][tile][lane],
+// so no global load sits inside the tap loop); a wave reads its A and B
+// fragments from LDS, and each weight fragment is reused for the 4 matrix
+// tiles.  Grid (ceil(W / 64), ceil(H / 4), N * D).  Requires Cin % 16 == 0.
 constexpr int KT_X = 64, KT_Y = 4, KH_X = KT_X + 2, KH_Y = KT_Y + 2;
 
 template <int NT>
@@ -62,6 +63,7 @@ __global__ void __launch_bounds__(CTPB) k_conv3d_tile(Vol x, int Cin, const unsi
 {
   constexpr int Cout = NT * 16;
   __shared__ __align__(16) bf16x4 tile[3][KH_Y][4][KH_X];
+  __shared__ __align__(16) bf16x4 wl[27][NT][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
   const int x0 = blockIdx.x * KT_X, y0 = blockIdx.y * KT_Y;
@@ -73,27 +75,53 @@ __global__ void __launch_bounds__(CTPB) k_conv3d_tile(Vol x, int Cin, const unsi
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int nchunk = Cin >> 4;
+  // staging: every load of a thread is issued before any is waited for (addresses
+  // clamped into the tensor, zero padding selected afterwards)
+  constexpr int NX = 3 * KH_Y * KH_X * 4, PX = (NX + CTPB - 1) / CTPB;
+  constexpr int NWF = 27 * NT * 64, PW = (NWF + CTPB - 1) / CTPB;
   for (int cc = 0; cc < nchunk; ++cc) {
-    __syncthreads();   // the previous chunk's tile has been consumed
-    for (int e = threadIdx.x; e < 3 * KH_Y * KH_X * 4; e += CTPB) {
+    bf16x4 xv[PX], wv4[PW];
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+      const int e = min((int)threadIdx.x + i * CTPB, NX - 1);
       const int q = e & 3, vox = e >> 2;
       const int hx = vox % KH_X, hy = (vox / KH_X) % KH_Y, hz = vox / (KH_X * KH_Y);
       const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z + hz - 1;
-      bf16x4 v = bf16x4{0, 0, 0, 0};
-      if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
-        const size_t gv = (((size_t)n * D + gz) * H + gy) * W + gx;
-        v = *(const bf16x4 *)(x.p + gv * x.ctot + x.coff + cc * 16 + q * 4);
-      }
-      tile[hz][hy][q][hx] = v;
+      const int cx = min(max(gx, 0), W - 1), cy = min(max(gy, 0), H - 1), cz = min(max(gz, 0), D - 1);
+      const size_t gv = (((size_t)n * D + cz) * H + cy) * W + cx;
+      const bf16x4 v = *(const bf16x4 *)(x.p + gv * x.ctot + x.coff + cc * 16 + q * 4);
+      const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D;
+      xv[i] = in ? v : bf16x4{0, 0, 0, 0};
+    }
+    // B fragment of lane l for tap and output tile t: w[tap][t 16 + l % 16][16 cc + 4 (l / 16) .. + 3]
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+      const int e = min((int)threadIdx.x + i * CTPB, NWF - 1);
+      const int ln = e & 63, t = (e >> 6) % NT, tap = (e >> 6) / NT;
+      wv4[i] = *(const bf16x4 *)(w + (size_t)tap * Cout * Cin + (size_t)(t * 16 + (ln & 15)) * Cin + cc * 16 +
+                                 (ln >> 4) * 4);
+    }
+    __syncthreads();   // the previous chunk's tile has been consumed
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+      const int e = (int)threadIdx.x + i * CTPB;
+      if (e >= NX) break;
+      const int q = e & 3, vox = e >> 2;
+      tile[vox / (KH_X * KH_Y)][(vox / KH_X) % KH_Y][q][vox % KH_X] = xv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+      const int e = (int)threadIdx.x + i * CTPB;
+      if (e >= NWF) break;
+      wl[(e >> 6) / NT][(e >> 6) % NT][e & 63] = wv4[i];
     }
     __syncthreads();
     if (yy < H) {
-      const unsigned short *wc = w + (size_t)m * Cin + cc * 16 + kq * 4;
       for (int tap = 0; tap < 27; ++tap) {
         const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
         bf16x4 b[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) b[t] = *(const bf16x4 *)(wc + (size_t)tap * Cout * Cin + (size_t)t * 16 * Cin);
+        for (int t = 0; t < NT; ++t) b[t] = wl[tap][t][lane];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
           const bf16x4 a = tile[dz][wv + dy][kq][mt * 16 + m + dx];
@@ -149,36 +177,59 @@ __global__ void __launch_bounds__(CTPB) k_conv3d_wgrad_tile(Vol x, int Cin, Vol 
   f32x4 acc[27];
 #pragma unroll
   for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (long long tile = blockIdx.x; tile < ntiles; tile += groups) {
+  // staging of a tile: every load is issued before any is waited for (addresses clamped
+  // into the tensors, zero padding selected afterwards); the next tile's loads are in
+  // flight while the current tile is contracted
+  constexpr int NX = 3 * KH_Y * KH_X * 4, PX = (NX + CTPB - 1) / CTPB;
+  constexpr int ND = KT_Y * KT_X * 4, PD = (ND + CTPB - 1) / CTPB;
+  bf16x4 xv[PX], dv[PD];
+  auto load = [&](long long tile) {
     const int tx = (int)(tile % gx), ty = (int)((tile / gx) % gy);
     const int z = (int)((tile / ((long long)gx * gy)) % D), n = (int)(tile / ((long long)gx * gy * D));
     const int x0 = tx * KT_X, y0 = ty * KT_Y;
-    __syncthreads();   // previous tile consumed
-    for (int e = threadIdx.x; e < 3 * KH_Y * KH_X * 4; e += CTPB) {
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+      const int e = min((int)threadIdx.x + i * CTPB, NX - 1);
       const int q = e & 3, vox = e >> 2;
       const int hx = vox % KH_X, hy = (vox / KH_X) % KH_Y, hz = vox / (KH_X * KH_Y);
       const int ix = x0 + hx - 1, iy = y0 + hy - 1, iz = z + hz - 1;
-      bf16x4 v = bf16x4{0, 0, 0, 0};
-      if (ix >= 0 && ix < W && iy >= 0 && iy < H && iz >= 0 && iz < D) {
-        const size_t gv = (((size_t)n * D + iz) * H + iy) * W + ix;
-        v = *(const bf16x4 *)(x.p + gv * x.ctot + x.coff + cit * 16 + q * 4);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xt[q * 4 + j][hz][hy][hx + 3] = (unsigned short)v[j];
+      const int cx = min(max(ix, 0), W - 1), cy = min(max(iy, 0), H - 1), cz = min(max(iz, 0), D - 1);
+      const size_t gv = (((size_t)n * D + cz) * H + cy) * W + cx;
+      const bf16x4 v = *(const bf16x4 *)(x.p + gv * x.ctot + x.coff + cit * 16 + q * 4);
+      xv[i] = (ix >= 0 && ix < W && iy >= 0 && iy < H && iz >= 0 && iz < D) ? v : bf16x4{0, 0, 0, 0};
     }
-    for (int e = threadIdx.x; e < KT_Y * KT_X * 4; e += CTPB) {
-      const int q = e & 3, vox = e >> 2;
-      const int xl = vox % KT_X, r = vox / KT_X;
-      const int ix = x0 + xl, iy = y0 + r;
-      bf16x4 v = bf16x4{0, 0, 0, 0};
-      if (ix < W && iy < H) {
-        const size_t gv = (((size_t)n * D + z) * H + iy) * W + ix;
-        v = *(const bf16x4 *)(dy.p + gv * dy.ctot + dy.coff + cot * 16 + q * 4);
-      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dt[q * 4 + j][r][xl] = (unsigned short)v[j];
+    for (int i = 0; i < PD; ++i) {
+      const int e = min((int)threadIdx.x + i * CTPB, ND - 1);
+      const int q = e & 3, vox = e >> 2;
+      const int ix = x0 + vox % KT_X, iy = y0 + vox / KT_X;
+      const size_t gv = (((size_t)n * D + z) * H + min(iy, H - 1)) * W + min(ix, W - 1);
+      const bf16x4 v = *(const bf16x4 *)(dy.p + gv * dy.ctot + dy.coff + cot * 16 + q * 4);
+      dv[i] = (ix < W && iy < H) ? v : bf16x4{0, 0, 0, 0};
+    }
+  };
+  if (blockIdx.x < ntiles) load(blockIdx.x);
+  for (long long tile = blockIdx.x; tile < ntiles; tile += groups) {
+    __syncthreads();   // previous tile consumed
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+      const int e = (int)threadIdx.x + i * CTPB;
+      if (e >= NX) break;
+      const int q = e & 3, vox = e >> 2;
+      const int hx = vox % KH_X, hy = (vox / KH_X) % KH_Y, hz = vox / (KH_X * KH_Y);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xt[q * 4 + j][hz][hy][hx + 3] = (unsigned short)xv[i][j];
+    }
+#pragma unroll
+    for (int i = 0; i < PD; ++i) {
+      const int e = (int)threadIdx.x + i * CTPB;
+      if (e >= ND) break;
+      const int q = e & 3, vox = e >> 2;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dt[q * 4 + j][vox / KT_X][vox % KT_X] = (unsigned short)dv[i][j];
     }
     __syncthreads();
+    if (tile + groups < ntiles) load(tile + groups);
     for (int g16 = 0; g16 < KT_X / 16; ++g16) {
       const int xq = g16 * 16 + kq * 4;   // first voxel of this lane's quad (interior x index)
       const bf16x4 b = *(const bf16x4 *)&dt[m][wv][xq];
