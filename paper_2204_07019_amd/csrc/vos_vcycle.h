@@ -264,16 +264,6 @@ __device__ __forceinline__ R tile_apply_off(const Lv &L, const R (*os)[H][W], R 
   return v;
 }
 
-// The four neighbour coefficients of an in-domain cell into LDS.
-template <typename Lv, typename R, int W, int H>
-__device__ __forceinline__ void load_coef(const Lv &L, R (*os)[H][W], int lx, int ly, unsigned id, const int c[3])
-{
-  os[0][ly][lx] = c[0] > 0 ? lv_off(L, id, c, 0) : (R)0;
-  os[1][ly][lx] = c[0] < L.n[0] - 1 ? lv_off(L, id, c, 1) : (R)0;
-  os[2][ly][lx] = c[1] > 0 ? lv_off(L, id, c, 2) : (R)0;
-  os[3][ly][lx] = c[1] < L.n[1] - 1 ? lv_off(L, id, c, 3) : (R)0;
-}
-
 // Down leg of a 2-D fine level: NU damped-Jacobi sweeps from zero, then the
 // residual restricted to the coarse right-hand side.  F.x receives the
 // smoothed iterate (tile cells); with FROM64, F.b the scaled right-hand side.
@@ -290,23 +280,39 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
   int tx, ty;
   if (!tile_of(nx, ny, tx, ty)) return;
   const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;   // global coords of LDS cell (0, 0)
-  for (int t = threadIdx.x; t < W * H; t += TPB) {
+  // staging in two phases: every load of a thread first (coordinates clamped into the
+  // level, so no load sits in a branch), then the values (defaults outside the level)
+  constexpr int PER = (W * H + TPB - 1) / TPB;
+  R rb[PER], rd[PER], ro[PER][4];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = min((int)threadIdx.x + i * TPB, W * H - 1);
+    const int gx = min(max(X0 + t % W, 0), nx - 1), gy = min(max(Y0 + t / W, 0), ny - 1);
+    const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
+    const int c[3] = {gx, gy, 0};
+    if (FROM64) rb[i] = (R)(rscale * (dsc ? r64[id] / sqrt(dsc[id]) : r64[id]));
+    else rb[i] = F.b[id];
+    rd[i] = F.diag[id];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ro[i][k] = lv_off(F, id, c, k);
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = (int)threadIdx.x + i * TPB;
+    if (t >= W * H) break;
     const int lx = t % W, ly = t / W;
     const int gx = X0 + lx, gy = Y0 + ly;
-    R bb = 0, dg = 1, v = 0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
-      const int c[3] = {gx, gy, 0};
-      if (FROM64) bb = (R)(rscale * (dsc ? r64[id] / sqrt(dsc[id]) : r64[id]));
-      else bb = F.b[id];
-      if (FROM64 && lx >= NU && lx < VT_X + NU && ly >= NU && ly < VT_Y + NU) F.b[id] = bb;
-      dg = F.diag[id];
-      v = omega * bb / dg;
-      load_coef<Lv, R, W, H>(F, os, lx, ly, id, c);
-    }
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const R bb = in ? rb[i] : (R)0, dg = in ? rd[i] : (R)1;
+    if (FROM64 && in && lx >= NU && lx < VT_X + NU && ly >= NU && ly < VT_Y + NU)
+      F.b[(unsigned)gx + (unsigned)nx * (unsigned)gy] = bb;
     bs[ly][lx] = bb;
     ds[ly][lx] = dg;
-    xa[ly][lx] = v;
+    xa[ly][lx] = in ? omega * bb / dg : (R)0;
+    os[0][ly][lx] = in && gx > 0 ? ro[i][0] : (R)0;
+    os[1][ly][lx] = in && gx < nx - 1 ? ro[i][1] : (R)0;
+    os[2][ly][lx] = in && gy > 0 ? ro[i][2] : (R)0;
+    os[3][ly][lx] = in && gy < ny - 1 ? ro[i][3] : (R)0;
   }
   __syncthreads();
   // sweeps 2..NU on a halo shrinking from NU - 1 to 1 (ping-pong xa -> xb -> xa ...)
@@ -329,8 +335,8 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
   }
   R(*xf)[W] = (NU % 2 == 0) ? xb : xa;   // the last sweep's output
   // residual on the tile, x to F.x
-  constexpr int PER = (VT_X * VT_Y + TPB - 1) / TPB;
-  R res[PER];
+  constexpr int PT = (VT_X * VT_Y + TPB - 1) / TPB;
+  R res[PT];
   int q = 0;
   for (int t = threadIdx.x; t < VT_X * VT_Y; t += TPB, ++q) {
     const int lx = NU + t % VT_X, ly = NU + t / VT_X;
@@ -376,21 +382,35 @@ __global__ void __launch_bounds__(TPB) k_v_up2d(Lv F, Lv C, R *__restrict__ xo, 
   int tx, ty;
   if (!tile_of(nx, ny, tx, ty)) return;
   const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;
-  for (int t = threadIdx.x; t < W * H; t += TPB) {
+  // two-phase staging as in the down leg
+  constexpr int PER = (W * H + TPB - 1) / TPB;
+  R rv[PER], rb[PER], rd[PER], ro[PER][4];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = min((int)threadIdx.x + i * TPB, W * H - 1);
+    const int gx = min(max(X0 + t % W, 0), nx - 1), gy = min(max(Y0 + t / W, 0), ny - 1);
+    const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
+    const int c[3] = {gx, gy, 0};
+    rv[i] = F.x[id] + C.x[parent_of<R>(F.n, C.n, 2, c)];
+    rb[i] = F.b[id];
+    rd[i] = F.diag[id];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ro[i][k] = lv_off(F, id, c, k);
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = (int)threadIdx.x + i * TPB;
+    if (t >= W * H) break;
     const int lx = t % W, ly = t / W;
     const int gx = X0 + lx, gy = Y0 + ly;
-    R v = 0, bb = 0, dg = 1;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
-      const int c[3] = {gx, gy, 0};
-      v = F.x[id] + C.x[parent_of<R>(F.n, C.n, 2, c)];
-      bb = F.b[id];
-      dg = F.diag[id];
-      load_coef<Lv, R, W, H>(F, os, lx, ly, id, c);
-    }
-    ya[ly][lx] = v;
-    bs[ly][lx] = bb;
-    ds[ly][lx] = dg;
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    ya[ly][lx] = in ? rv[i] : (R)0;
+    bs[ly][lx] = in ? rb[i] : (R)0;
+    ds[ly][lx] = in ? rd[i] : (R)1;
+    os[0][ly][lx] = in && gx > 0 ? ro[i][0] : (R)0;
+    os[1][ly][lx] = in && gx < nx - 1 ? ro[i][1] : (R)0;
+    os[2][ly][lx] = in && gy > 0 ? ro[i][2] : (R)0;
+    os[3][ly][lx] = in && gy < ny - 1 ? ro[i][3] : (R)0;
   }
   __syncthreads();
 #pragma unroll
