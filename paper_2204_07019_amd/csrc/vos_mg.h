@@ -31,27 +31,36 @@ struct MgLevel {
   R *x, *b, *t;
 };
 
+// A x at cell id.  Every load is issued unconditionally (a missing
+// neighbour's index is clamped to the cell itself and its term skipped by a
+// select), so all loads of a cell are in flight together; the arithmetic is
+// the branchy form's: d x, then - T x per existing neighbour in slot order.
 template <typename R>
 __device__ __forceinline__ R mg_apply_cell(const MgLevel<R> &L, int nd, const R *x, unsigned id, const int c[3])
 {
+  const unsigned sy = (unsigned)L.n[0];
+  const bool hw = c[0] > 0, he = c[0] < L.n[0] - 1, hs = c[1] > 0, hn = c[1] < L.n[1] - 1;
   const R xc = x[id];
+  const R xw = x[hw ? id - 1 : id], xe = x[he ? id + 1 : id];
+  const R xs = x[hs ? id - sy : id], xn = x[hn ? id + sy : id];
   const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
   const R tw = L.T[0][f0], te = L.T[0][f0 + 1];
-  R v = L.diag[id] * xc;
-  if (c[0] > 0) v -= tw * x[id - 1];
-  if (c[0] < L.n[0] - 1) v -= te * x[id + 1];
   const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
   const R ts = L.T[1][f1], tn = L.T[1][f1 + L.fd[1][0]];
-  if (c[1] > 0) v -= ts * x[id - L.n[0]];
-  if (c[1] < L.n[1] - 1) v -= tn * x[id + L.n[0]];
+  R v = L.diag[id] * xc;
+  v = hw ? v - tw * xw : v;
+  v = he ? v - te * xe : v;
+  v = hs ? v - ts * xs : v;
+  v = hn ? v - tn * xn : v;
   if (nd == 3) {
     const unsigned sz = (unsigned)L.n[0] * L.n[1];
+    const bool hb = c[2] > 0, ht = c[2] < L.n[2] - 1;
+    const R xb = x[hb ? id - sz : id], xt = x[ht ? id + sz : id];
     const unsigned f2 = (unsigned)c[0] + (unsigned)L.fd[2][0] * ((unsigned)c[1] + (unsigned)L.fd[2][1] * c[2]);
     const R tb = L.T[2][f2], tt = L.T[2][f2 + sz];
-    if (c[2] > 0) v -= tb * x[id - sz];
-    if (c[2] < L.n[2] - 1) v -= tt * x[id + sz];
+    v = hb ? v - tb * xb : v;
+    v = ht ? v - tt * xt : v;
   }
-  (void)tw; (void)te; (void)ts; (void)tn;
   return v;
 }
 

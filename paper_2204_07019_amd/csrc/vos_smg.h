@@ -28,20 +28,29 @@ struct SLevel {
   R *x, *b, *t;
 };
 
+// A x at cell id, every load issued unconditionally (as mg_apply_cell):
+// d x, then + off x per existing neighbour in slot order.
 template <typename R>
 __device__ __forceinline__ R smg_apply_cell(const SLevel<R> &L, int nd, const R *x, unsigned id, const int c[3])
 {
-  R v = L.diag[id] * x[id];
-  const unsigned nc = L.nc;
-  if (c[0] > 0) v += L.off[id] * x[id - 1];
-  if (c[0] < L.n[0] - 1) v += L.off[nc + id] * x[id + 1];
-  const unsigned sy = (unsigned)L.n[0];
-  if (c[1] > 0) v += L.off[2 * nc + id] * x[id - sy];
-  if (c[1] < L.n[1] - 1) v += L.off[3 * nc + id] * x[id + sy];
+  const unsigned nc = L.nc, sy = (unsigned)L.n[0];
+  const bool hw = c[0] > 0, he = c[0] < L.n[0] - 1, hs = c[1] > 0, hn = c[1] < L.n[1] - 1;
+  const R xc = x[id];
+  const R xw = x[hw ? id - 1 : id], xe = x[he ? id + 1 : id];
+  const R xs = x[hs ? id - sy : id], xn = x[hn ? id + sy : id];
+  const R ow = L.off[id], oe = L.off[nc + id], os = L.off[2 * nc + id], on = L.off[3 * nc + id];
+  R v = L.diag[id] * xc;
+  v = hw ? v + ow * xw : v;
+  v = he ? v + oe * xe : v;
+  v = hs ? v + os * xs : v;
+  v = hn ? v + on * xn : v;
   if (nd == 3) {
     const unsigned sz = (unsigned)L.n[0] * L.n[1];
-    if (c[2] > 0) v += L.off[4 * nc + id] * x[id - sz];
-    if (c[2] < L.n[2] - 1) v += L.off[5 * nc + id] * x[id + sz];
+    const bool hb = c[2] > 0, ht = c[2] < L.n[2] - 1;
+    const R xb = x[hb ? id - sz : id], xt = x[ht ? id + sz : id];
+    const R ob = L.off[4 * nc + id], ot = L.off[5 * nc + id];
+    v = hb ? v + ob * xb : v;
+    v = ht ? v + ot * xt : v;
   }
   return v;
 }

@@ -139,21 +139,29 @@ __global__ void __launch_bounds__(TPB) k_v_jacobi(Lv L, int nd, const R *__restr
   }
 }
 
-// Coarse right-hand side: the fine residual summed over each aggregate.
+// Coarse right-hand side: the fine residual summed over each aggregate
+// (children in cz, cy, cx order; a missing child -- ceil aggregation or an
+// extent-1 dimension -- is evaluated at a clamped cell and skipped by a
+// select, so no load sits in a branch).
 template <typename Lv, typename R>
 __device__ __forceinline__ R lv_restrict_one(const Lv &F, int nd, const int X[3])
 {
   R s = 0;
   const int lz = nd == 3 ? 2 : 1;
+#pragma unroll
   for (int cz = 0; cz < lz; ++cz)
+#pragma unroll
     for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
-        const int c[3] = {F.n[0] == 1 ? 0 : 2 * X[0] + cx, F.n[1] == 1 ? 0 : 2 * X[1] + cy,
-                          (nd == 3 && F.n[2] > 1) ? 2 * X[2] + cz : 0};
-        if ((F.n[0] == 1 && cx) || (F.n[1] == 1 && cy) || (cz && !(nd == 3 && F.n[2] > 1))) continue;
-        if (c[0] >= F.n[0] || c[1] >= F.n[1] || c[2] >= F.n[2]) continue;
+        const int c0 = F.n[0] == 1 ? 0 : 2 * X[0] + cx, c1 = F.n[1] == 1 ? 0 : 2 * X[1] + cy;
+        const int c2 = (nd == 3 && F.n[2] > 1) ? 2 * X[2] + cz : 0;
+        const bool ok = !((F.n[0] == 1 && cx) || (F.n[1] == 1 && cy) || (cz && !(nd == 3 && F.n[2] > 1))) &&
+                        c0 < F.n[0] && c1 < F.n[1] && c2 < F.n[2];
+        const int c[3] = {min(c0, F.n[0] - 1), min(c1, F.n[1] - 1), min(c2, F.n[2] - 1)};
         const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * (unsigned)c[2]);
-        s += F.b[id] - lv_apply(F, nd, F.x, id, c);
+        const R r = F.b[id] - lv_apply(F, nd, F.x, id, c);
+        s = ok ? s + r : s;
       }
   return s;
 }
