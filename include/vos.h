@@ -220,7 +220,7 @@ typedef enum {
   VOS_KERNEL_V_RESTRICT = 0,  /* residual restriction, every fine level of the transport hierarchy */
   VOS_KERNEL_V_POST = 1,      /* prolongation + first post-smoothing sweep, same levels */
   VOS_KERNEL_V_PRE = 2,       /* first two pre-smoothing sweeps, same levels */
-  VOS_KERNEL_V_COARSE = 3,    /* the single-block coarse tail of the transport V-cycle */
+  VOS_KERNEL_V_COARSE = 3,    /* the single-block coarse tail of the transport V-cycle (in LDS in 2-D) */
   VOS_KERNEL_P_APPLY = 4,     /* pressure operator application (FP64) */
   VOS_KERNEL_ADR_APPLY = 5,   /* transport operator application (FP64) */
   VOS_KERNEL_V_DOWN = 6,      /* 2-D tiled down leg (pre-sweeps + restriction), finest transport level */

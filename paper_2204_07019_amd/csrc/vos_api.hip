@@ -528,6 +528,20 @@ void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv)
   k_smg_coarse_inverse<R><<<1, TPB, 0, st>>>(lv[L - 1], nd, s->sainv[h]);
 }
 
+// The coarse tail (levels lc..L-1) runs in LDS (k_v_coarse_lds) when it is
+// 2-D, every level fits one cell per thread and the tail fits VCL_CELLS.
+template <typename Lv>
+bool coarse_in_lds(const Lv *lv, int lc, int L, int nd, bool fused)
+{
+  if (!fused || nd != 2 || L - lc > VCL_MAXLV) return false;
+  unsigned tot = 0;
+  for (int l = lc; l < L; ++l) {
+    if (lv[l].nc > (unsigned)VC_COARSE_TPB) return false;
+    tot += lv[l].nc;
+  }
+  return tot <= (unsigned)VCL_CELLS;
+}
+
 // z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
 template <typename Lv, typename R>
 void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, double *z, const double *sc,
@@ -592,7 +606,10 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   LevelPack<Lv> pack;
   for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
   if (lc == 0) k_v_cast_in<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], r, dsc, rscale, sc);
-  k_v_coarse_cycle<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, nu, om, Ainv, sc);
+  if (coarse_in_lds(lv, lc, L, nd, fused))
+    k_v_coarse_lds<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nu, om, Ainv, sc);
+  else
+    k_v_coarse_cycle<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, nu, om, Ainv, sc);
   if (lc == 0) {
     k_v_cast_out<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], z, dsc, sc);
     return;
@@ -1290,8 +1307,11 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_COARSE: {
         LevelPack<SLevel<R>> pack;
         for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
-        k_v_coarse_cycle<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, sweeps(s, 3), om, s->sainv[3],
-                                                                    flag);
+        if (coarse_in_lds(lv, lc, L, nd, s->opt.level_kernels == 0))
+          k_v_coarse_lds<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, sweeps(s, 3), om, s->sainv[3], flag);
+        else
+          k_v_coarse_cycle<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, sweeps(s, 3), om,
+                                                                      s->sainv[3], flag);
         if (count) {
           for (int l = lc; l < L; ++l) per_seq_bytes += (5.0 + 2 * nd) * Rs * lv[l].nc;
           ++per_seq_launches;

@@ -538,6 +538,186 @@ __global__ void __launch_bounds__(VC_COARSE_TPB) k_v_coarse_cycle(LevelPack<Lv> 
 #undef VC_T
 }
 
+// ------------------------------------------------------------------ 2-D coarse tail in LDS
+//
+// The same cycle as k_v_coarse_cycle when every level of the tail has at most
+// VC_COARSE_TPB cells (2-D): thread i owns cell i of each level, keeps that
+// cell's diagonal, four neighbour coefficients and right-hand side in
+// registers, and the iterates live in LDS, so a sweep costs one barrier
+// instead of a store and reload through L2.  Every value is formed by the
+// expression k_v_coarse_cycle uses (bitwise equal results).
+constexpr int VCL_MAXLV = 6;      // levels of the tail
+constexpr int VCL_CELLS = 1536;   // LDS cells over all levels of the tail
+
+template <typename R>
+struct CCoef {
+  R d, o[4];   // diagonal; -x, +x, -y, +y coefficients as stored (MgLevel T, SLevel off)
+};
+
+template <typename R>
+__device__ __forceinline__ CCoef<R> ccoef(const MgLevel<R> &L, unsigned id, const int c[3])
+{
+  const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
+  const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
+  return CCoef<R>{L.diag[id], {L.T[0][f0], L.T[0][f0 + 1], L.T[1][f1], L.T[1][f1 + L.fd[1][0]]}};
+}
+
+template <typename R>
+__device__ __forceinline__ CCoef<R> ccoef(const SLevel<R> &L, unsigned id, const int *)
+{
+  return CCoef<R>{L.diag[id], {L.off[id], L.off[L.nc + id], L.off[2 * L.nc + id], L.off[3 * L.nc + id]}};
+}
+
+template <typename R>
+__device__ __forceinline__ R cterm(const MgLevel<R> &, R v, R o, R x) { return v - o * x; }
+template <typename R>
+__device__ __forceinline__ R cterm(const SLevel<R> &, R v, R o, R x) { return v + o * x; }
+
+// A x at cell id of a 2-D level from the LDS iterate x (mg_apply_cell / smg_apply_cell order).
+template <typename Lv, typename R>
+__device__ __forceinline__ R capply(const Lv &L, const CCoef<R> &k, const R *x, unsigned id, const int c[3])
+{
+  const unsigned sy = (unsigned)L.n[0];
+  const bool hw = c[0] > 0, he = c[0] < L.n[0] - 1, hs = c[1] > 0, hn = c[1] < L.n[1] - 1;
+  const R xc = x[id], xw = x[hw ? id - 1 : id], xe = x[he ? id + 1 : id];
+  const R xs = x[hs ? id - sy : id], xn = x[hn ? id + sy : id];
+  R v = k.d * xc;
+  v = hw ? cterm(L, v, k.o[0], xw) : v;
+  v = he ? cterm(L, v, k.o[1], xe) : v;
+  v = hs ? cterm(L, v, k.o[2], xs) : v;
+  v = hn ? cterm(L, v, k.o[3], xn) : v;
+  return v;
+}
+
+template <typename Lv, typename R>
+__global__ void __launch_bounds__(VC_COARSE_TPB) k_v_coarse_lds(LevelPack<Lv> P, int l0, int L, int nu, R omega,
+                                                                const double *__restrict__ Ainv,
+                                                                const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  __shared__ R xs[2][VCL_CELLS];     // iterates (ping-pong), level q at offset off[q]
+  __shared__ R rs[VC_COARSE_TPB];    // residuals being restricted; the coarsest right-hand side
+  const int nl = L - l0;
+  const unsigned i = threadIdx.x;
+  unsigned off[VCL_MAXLV];
+  CCoef<R> k[VCL_MAXLV];
+  R rb[VCL_MAXLV];
+  int sel[VCL_MAXLV];
+  {
+    unsigned o = 0;
+#pragma unroll
+    for (int q = 0; q < VCL_MAXLV; ++q) {
+      off[q] = o;
+      sel[q] = 0;
+      rb[q] = (R)0;
+      k[q] = CCoef<R>{};
+      if (q < nl) {
+        const Lv &F = P.lv[l0 + q];
+        o += F.nc;
+        if (i < F.nc) {
+          int c[3];
+          unflat(F.n, i, c);
+          k[q] = ccoef(F, i, c);
+        }
+      }
+    }
+  }
+  if (i < P.lv[l0].nc) rb[0] = P.lv[l0].b[i];
+  // Jacobi sweeps 2..count of level q (sweep 1 from zero done by the caller)
+  auto sweeps = [&](int q, const Lv &F, int count, const int c[3], bool own) {
+    for (int s = 1; s < count; ++s) {
+      const R *xa = xs[sel[q]] + off[q];
+      R *xb = xs[sel[q] ^ 1] + off[q];
+      if (own) xb[i] = xa[i] + omega * (rb[q] - capply(F, k[q], xa, i, c)) / k[q].d;
+      sel[q] ^= 1;
+      __syncthreads();
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < VCL_MAXLV - 1; ++q) {
+    if (q < nl - 1) {
+      const Lv &F = P.lv[l0 + q];
+      const bool own = i < F.nc;
+      int c[3];
+      unflat(F.n, own ? i : 0u, c);
+      if (own) xs[sel[q]][off[q] + i] = omega * rb[q] / k[q].d;
+      __syncthreads();
+      sweeps(q, F, nu, c, own);
+      if (own) rs[i] = rb[q] - capply(F, k[q], xs[sel[q]] + off[q], i, c);
+      __syncthreads();
+      // coarse right-hand side: the children's residuals in cy, cx order (lv_restrict_one)
+      const Lv &C = P.lv[l0 + q + 1];
+      if (i < C.nc) {
+        int X[3];
+        unflat(C.n, i, X);
+        R sum = 0;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) {
+            const int c0 = F.n[0] == 1 ? 0 : 2 * X[0] + cx, c1 = F.n[1] == 1 ? 0 : 2 * X[1] + cy;
+            const bool ok = !((F.n[0] == 1 && cx) || (F.n[1] == 1 && cy)) && c0 < F.n[0] && c1 < F.n[1];
+            const R r = rs[(unsigned)min(c0, F.n[0] - 1) + (unsigned)F.n[0] * (unsigned)min(c1, F.n[1] - 1)];
+            sum = ok ? sum + r : sum;
+          }
+        rb[q + 1] = sum;
+      }
+      __syncthreads();
+    }
+  }
+  // coarsest level
+  {
+    const int q = nl - 1;
+    const Lv &C = P.lv[L - 1];
+    const bool own = i < C.nc;
+    R bq = (R)0;
+    unsigned offq = 0;
+#pragma unroll
+    for (int qq = 0; qq < VCL_MAXLV; ++qq)
+      if (qq == q) {
+        bq = rb[qq];
+        offq = off[qq];
+      }
+    if (C.nc <= 64u) {
+      if (own) rs[i] = bq;
+      __syncthreads();
+      if (own) {
+        double acc = 0.0;
+        for (unsigned j = 0; j < C.nc; ++j) acc += Ainv[i * C.nc + j] * (double)rs[j];
+        xs[0][offq + i] = (R)acc;
+      }
+#pragma unroll
+      for (int qq = 0; qq < VCL_MAXLV; ++qq)
+        if (qq == q) sel[qq] = 0;
+      __syncthreads();
+    } else {
+      int c[3];
+      unflat(C.n, own ? i : 0u, c);
+#pragma unroll
+      for (int qq = 0; qq < VCL_MAXLV; ++qq)
+        if (qq == q) {
+          if (own) xs[sel[qq]][off[qq] + i] = omega * rb[qq] / k[qq].d;
+          __syncthreads();
+          sweeps(qq, C, 64, c, own);
+        }
+    }
+  }
+#pragma unroll
+  for (int q = VCL_MAXLV - 2; q >= 0; --q) {
+    if (q < nl - 1) {
+      const Lv &F = P.lv[l0 + q];
+      const Lv &C = P.lv[l0 + q + 1];
+      const bool own = i < F.nc;
+      int c[3];
+      unflat(F.n, own ? i : 0u, c);
+      if (own) xs[sel[q]][off[q] + i] += xs[sel[q + 1]][off[q + 1] + parent_of<R>(F.n, C.n, 2, c)];
+      __syncthreads();
+      sweeps(q, F, nu + 1, c, own);
+    }
+  }
+  if (i < P.lv[l0].nc) P.lv[l0].x[i] = xs[sel[0]][off[0] + i];
+}
+
 // b = (R) r (level-0 input when the whole cycle runs in the single block).
 template <typename Lv, typename R>
 __global__ void __launch_bounds__(TPB) k_v_cast_in(Lv L, const double *__restrict__ r, const double *__restrict__ dsc,
