@@ -116,12 +116,24 @@ __device__ __forceinline__ void write_partials(const double (&v)[NQ], double *pa
   }
 }
 
-// Fixed-order sum of nb partials of quantity q by one block; valid in thread 0.
+// Fixed-order sum of nb partials of quantity q by one block: thread t adds
+// partials t, t + blockDim, ... in that order, then the block sum; valid in
+// thread 0.  The loads of a chunk of 16 are all issued before the first add
+// (indices clamped into the quantity's slots, the ones past nb dropped by a
+// select), so a thread waits for memory once per chunk, not once per partial.
+constexpr int PCHUNK = 16;
 __device__ __forceinline__ double sum_partials(const double *part, int q, int nb)
 {
   __shared__ double lds[TPB / 64];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[q * MAXB + b];
+  const int st = (int)blockDim.x;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += PCHUNK * st) {
+    double v[PCHUNK];
+#pragma unroll
+    for (int k = 0; k < PCHUNK; ++k) v[k] = part[q * MAXB + min(b0 + k * st, MAXB - 1)];
+#pragma unroll
+    for (int k = 0; k < PCHUNK; ++k) s = b0 + k * st < nb ? s + v[k] : s;
+  }
   return block_sum(s, lds);
 }
 
@@ -129,7 +141,14 @@ __device__ __forceinline__ double max_partials(const double *part, int q, int nb
 {
   __shared__ double lds[TPB / 64];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) s = fmax(s, part[q * MAXB + b]);
+  const int st = (int)blockDim.x;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += PCHUNK * st) {
+    double v[PCHUNK];
+#pragma unroll
+    for (int k = 0; k < PCHUNK; ++k) v[k] = part[q * MAXB + min(b0 + k * st, MAXB - 1)];
+#pragma unroll
+    for (int k = 0; k < PCHUNK; ++k) s = b0 + k * st < nb ? fmax(s, v[k]) : s;
+  }
   return block_max(s, lds);
 }
 
