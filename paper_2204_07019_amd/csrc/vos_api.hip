@@ -528,18 +528,36 @@ void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv)
   k_smg_coarse_inverse<R><<<1, TPB, 0, st>>>(lv[L - 1], nd, s->sainv[h]);
 }
 
-// The coarse tail (levels lc..L-1) runs in LDS (k_v_coarse_lds) when it is
-// 2-D, every level fits one cell per thread and the tail fits VCL_CELLS.
+// Cells per thread on the first level of a coarse tail (levels lc..L-1) that
+// runs in LDS (k_v_coarse_lds): 1, 2 or (FP32) 4 -- an FP64 tail with 4 would
+// spill registers; 0 when the tail does not qualify (not 2-D, first level
+// above that many cells per thread, a later level above one cell per thread,
+// or more than VCL_CELLS cells in all).
 template <typename Lv>
-bool coarse_in_lds(const Lv *lv, int lc, int L, int nd, bool fused)
+int coarse_in_lds(const Lv *lv, int lc, int L, int nd, bool fused)
 {
-  if (!fused || nd != 2 || L - lc > VCL_MAXLV) return false;
+  if (!fused || nd != 2 || L - lc > VCL_MAXLV) return 0;
+  const unsigned c0max = sizeof(*lv[0].x) == 8 ? 2u : (unsigned)VCL_C0;
   unsigned tot = 0;
   for (int l = lc; l < L; ++l) {
-    if (lv[l].nc > (unsigned)VC_COARSE_TPB) return false;
+    const unsigned cap = (unsigned)VC_COARSE_TPB * (l == lc ? c0max : 1u);
+    if (lv[l].nc > cap) return 0;
     tot += lv[l].nc;
   }
-  return tot <= (unsigned)VCL_CELLS;
+  if (tot > (unsigned)VCL_CELLS) return 0;
+  const unsigned c0 = (lv[lc].nc + VC_COARSE_TPB - 1) / VC_COARSE_TPB;
+  return c0 <= 1 ? 1 : (c0 <= 2 ? 2 : 4);
+}
+
+template <typename Lv, typename R>
+void launch_coarse(int c0, const LevelPack<Lv> &pack, int lc, int L, int nd, int nu, R om, const double *Ainv,
+                   const double *sc, hipStream_t st)
+{
+  if (c0 == 1) k_v_coarse_lds<Lv, R, 1><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nu, om, Ainv, sc);
+  else if (c0 == 2) k_v_coarse_lds<Lv, R, 2><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nu, om, Ainv, sc);
+  else if (sizeof(R) == 4 && c0 == 4) k_v_coarse_lds<Lv, R, sizeof(R) == 4 ? 4 : 2><<<1, VC_COARSE_TPB, 0, st>>>(
+      pack, lc, L, nu, om, Ainv, sc);
+  else k_v_coarse_cycle<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, nu, om, Ainv, sc);
 }
 
 // z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
@@ -606,10 +624,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   LevelPack<Lv> pack;
   for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
   if (lc == 0) k_v_cast_in<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], r, dsc, rscale, sc);
-  if (coarse_in_lds(lv, lc, L, nd, fused))
-    k_v_coarse_lds<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nu, om, Ainv, sc);
-  else
-    k_v_coarse_cycle<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, nu, om, Ainv, sc);
+  launch_coarse<Lv, R>(coarse_in_lds(lv, lc, L, nd, fused), pack, lc, L, nd, nu, om, Ainv, sc, st);
   if (lc == 0) {
     k_v_cast_out<Lv, R><<<grid_blocks(lv[0].nc), TPB, 0, st>>>(lv[0], z, dsc, sc);
     return;
@@ -1307,11 +1322,8 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_COARSE: {
         LevelPack<SLevel<R>> pack;
         for (int l = 0; l < L && l < VC_MAX_LEVELS; ++l) pack.lv[l] = lv[l];
-        if (coarse_in_lds(lv, lc, L, nd, s->opt.level_kernels == 0))
-          k_v_coarse_lds<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, sweeps(s, 3), om, s->sainv[3], flag);
-        else
-          k_v_coarse_cycle<SLevel<R>, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, sweeps(s, 3), om,
-                                                                      s->sainv[3], flag);
+        launch_coarse<SLevel<R>, R>(coarse_in_lds(lv, lc, L, nd, s->opt.level_kernels == 0), pack, lc, L, nd,
+                                    sweeps(s, 3), om, s->sainv[3], flag, st);
         if (count) {
           for (int l = lc; l < L; ++l) per_seq_bytes += (5.0 + 2 * nd) * Rs * lv[l].nc;
           ++per_seq_launches;
@@ -1455,7 +1467,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   // defaults (0): in 2-D four sweeps with the tiled fine-level kernels and a
   // 1024-cell single-block tail; in 3-D two sweeps and a 4096-cell tail
   if (s->opt.mg_nu == 0) s->opt.mg_nu = grid->nz == 1 ? 4 : 2;
-  s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? 1024 : VC_BLOCK_MAX);
+  s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? VC_TAIL_2D : VC_BLOCK_MAX);
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
 
@@ -1647,7 +1659,7 @@ vos_status set_tuning(vos_sim *s, int check_every, int coarse_cells)
   drop_graphs(s);   // captured chunks hold the old chunk length and coarse split
   s->opt.check_every = check_every;
   s->opt.coarse_cells = coarse_cells;
-  s->coarse_cells = coarse_cells > 0 ? coarse_cells : (s->g.nd == 2 ? 1024 : VC_BLOCK_MAX);
+  s->coarse_cells = coarse_cells > 0 ? coarse_cells : (s->g.nd == 2 ? VC_TAIL_2D : VC_BLOCK_MAX);
   return VOS_OK;
 }
 

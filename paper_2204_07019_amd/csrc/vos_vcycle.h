@@ -23,7 +23,8 @@
 
 namespace vos {
 
-constexpr int VC_BLOCK_MAX = 4096;   // levels at or below this size run in the single-block kernel
+constexpr int VC_BLOCK_MAX = 4096;   // levels at or below this size run in the single-block kernel (3-D)
+constexpr int VC_TAIL_2D = 2048;     // the same in 2-D (the tail runs in LDS, k_v_coarse_lds)
 constexpr int VC_MAX_LEVELS = 20;
 constexpr int VC_COARSE_TPB = 1024;
 
@@ -454,6 +455,7 @@ struct LevelPack {
   Lv lv[VC_MAX_LEVELS];
 };
 
+
 template <typename Lv, typename R>
 __device__ void blk_jacobi(const Lv &L, int nd, const R *x, R *xo, R omega, bool zero_x)
 {
@@ -540,14 +542,16 @@ __global__ void __launch_bounds__(VC_COARSE_TPB) k_v_coarse_cycle(LevelPack<Lv> 
 
 // ------------------------------------------------------------------ 2-D coarse tail in LDS
 //
-// The same cycle as k_v_coarse_cycle when every level of the tail has at most
-// VC_COARSE_TPB cells (2-D): thread i owns cell i of each level, keeps that
-// cell's diagonal, four neighbour coefficients and right-hand side in
-// registers, and the iterates live in LDS, so a sweep costs one barrier
-// instead of a store and reload through L2.  Every value is formed by the
-// expression k_v_coarse_cycle uses (bitwise equal results).
+// The same cycle as k_v_coarse_cycle for a 2-D tail whose first level has at
+// most C0 x VC_COARSE_TPB cells and every later level at most VC_COARSE_TPB:
+// thread i owns cells i + j VC_COARSE_TPB (j < C0) of the first level and cell
+// i of the others, keeps their diagonals, neighbour coefficients and
+// right-hand sides in registers, and the iterates live in LDS, so a sweep
+// costs a barrier instead of a store and reload through L2.  Every value is
+// formed by the expression k_v_coarse_cycle uses (bitwise equal results).
 constexpr int VCL_MAXLV = 6;      // levels of the tail
-constexpr int VCL_CELLS = 1536;   // LDS cells over all levels of the tail
+constexpr int VCL_C0 = 4;         // most cells per thread on the first level
+constexpr int VCL_CELLS = 5632;   // LDS cells over all levels of the tail
 
 template <typename R>
 struct CCoef {
@@ -589,61 +593,91 @@ __device__ __forceinline__ R capply(const Lv &L, const CCoef<R> &k, const R *x, 
   return v;
 }
 
-template <typename Lv, typename R>
+template <typename Lv, typename R, int C0>
 __global__ void __launch_bounds__(VC_COARSE_TPB) k_v_coarse_lds(LevelPack<Lv> P, int l0, int L, int nu, R omega,
                                                                 const double *__restrict__ Ainv,
                                                                 const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
+  constexpr unsigned T = VC_COARSE_TPB;
   __shared__ R xs[2][VCL_CELLS];     // iterates (ping-pong), level q at offset off[q]
-  __shared__ R rs[VC_COARSE_TPB];    // residuals being restricted; the coarsest right-hand side
+  __shared__ R rs[C0 * T];           // residuals being restricted; the coarsest right-hand side
   const int nl = L - l0;
   const unsigned i = threadIdx.x;
   unsigned off[VCL_MAXLV];
-  CCoef<R> k[VCL_MAXLV];
-  R rb[VCL_MAXLV];
+  CCoef<R> k[VCL_MAXLV][C0];
+  R rb[VCL_MAXLV][C0];
   int sel[VCL_MAXLV];
+  // slots of level q: C0 on the first level, 1 on the others
+#define VCL_S(q) ((q) == 0 ? C0 : 1)
   {
     unsigned o = 0;
 #pragma unroll
     for (int q = 0; q < VCL_MAXLV; ++q) {
       off[q] = o;
       sel[q] = 0;
-      rb[q] = (R)0;
-      k[q] = CCoef<R>{};
+#pragma unroll
+      for (int j = 0; j < C0; ++j) {
+        rb[q][j] = (R)0;
+        k[q][j] = CCoef<R>{};
+      }
       if (q < nl) {
         const Lv &F = P.lv[l0 + q];
         o += F.nc;
-        if (i < F.nc) {
-          int c[3];
-          unflat(F.n, i, c);
-          k[q] = ccoef(F, i, c);
+#pragma unroll
+        for (int j = 0; j < VCL_S(q); ++j) {
+          const unsigned id = i + j * T;
+          if (id < F.nc) {
+            int c[3];
+            unflat(F.n, id, c);
+            k[q][j] = ccoef(F, id, c);
+            if (q == 0) rb[0][j] = F.b[id];
+          }
         }
       }
     }
   }
-  if (i < P.lv[l0].nc) rb[0] = P.lv[l0].b[i];
-  // Jacobi sweeps 2..count of level q (sweep 1 from zero done by the caller)
-  auto sweeps = [&](int q, const Lv &F, int count, const int c[3], bool own) {
+  // Jacobi sweeps 2..count of level q (sweep 1, from zero, done before)
+  auto sweeps = [&](int q, const Lv &F, int count) {
     for (int s = 1; s < count; ++s) {
       const R *xa = xs[sel[q]] + off[q];
       R *xb = xs[sel[q] ^ 1] + off[q];
-      if (own) xb[i] = xa[i] + omega * (rb[q] - capply(F, k[q], xa, i, c)) / k[q].d;
+#pragma unroll
+      for (int j = 0; j < VCL_S(q); ++j) {
+        const unsigned id = i + j * T;
+        if (id < F.nc) {
+          int c[3];
+          unflat(F.n, id, c);
+          xb[id] = xa[id] + omega * (rb[q][j] - capply(F, k[q][j], xa, id, c)) / k[q][j].d;
+        }
+      }
       sel[q] ^= 1;
       __syncthreads();
     }
+  };
+  auto zero_sweep = [&](int q, const Lv &F) {
+#pragma unroll
+    for (int j = 0; j < VCL_S(q); ++j) {
+      const unsigned id = i + j * T;
+      if (id < F.nc) xs[sel[q]][off[q] + id] = omega * rb[q][j] / k[q][j].d;
+    }
+    __syncthreads();
   };
 #pragma unroll
   for (int q = 0; q < VCL_MAXLV - 1; ++q) {
     if (q < nl - 1) {
       const Lv &F = P.lv[l0 + q];
-      const bool own = i < F.nc;
-      int c[3];
-      unflat(F.n, own ? i : 0u, c);
-      if (own) xs[sel[q]][off[q] + i] = omega * rb[q] / k[q].d;
-      __syncthreads();
-      sweeps(q, F, nu, c, own);
-      if (own) rs[i] = rb[q] - capply(F, k[q], xs[sel[q]] + off[q], i, c);
+      zero_sweep(q, F);
+      sweeps(q, F, nu);
+#pragma unroll
+      for (int j = 0; j < VCL_S(q); ++j) {
+        const unsigned id = i + j * T;
+        if (id < F.nc) {
+          int c[3];
+          unflat(F.n, id, c);
+          rs[id] = rb[q][j] - capply(F, k[q][j], xs[sel[q]] + off[q], id, c);
+        }
+      }
       __syncthreads();
       // coarse right-hand side: the children's residuals in cy, cx order (lv_restrict_one)
       const Lv &C = P.lv[l0 + q + 1];
@@ -660,46 +694,30 @@ __global__ void __launch_bounds__(VC_COARSE_TPB) k_v_coarse_lds(LevelPack<Lv> P,
             const R r = rs[(unsigned)min(c0, F.n[0] - 1) + (unsigned)F.n[0] * (unsigned)min(c1, F.n[1] - 1)];
             sum = ok ? sum + r : sum;
           }
-        rb[q + 1] = sum;
+        rb[q + 1][0] = sum;
       }
       __syncthreads();
     }
   }
-  // coarsest level
-  {
-    const int q = nl - 1;
-    const Lv &C = P.lv[L - 1];
-    const bool own = i < C.nc;
-    R bq = (R)0;
-    unsigned offq = 0;
+  // coarsest level (the first level too when the tail has one level)
 #pragma unroll
-    for (int qq = 0; qq < VCL_MAXLV; ++qq)
-      if (qq == q) {
-        bq = rb[qq];
-        offq = off[qq];
-      }
-    if (C.nc <= 64u) {
-      if (own) rs[i] = bq;
-      __syncthreads();
-      if (own) {
-        double acc = 0.0;
-        for (unsigned j = 0; j < C.nc; ++j) acc += Ainv[i * C.nc + j] * (double)rs[j];
-        xs[0][offq + i] = (R)acc;
-      }
-#pragma unroll
-      for (int qq = 0; qq < VCL_MAXLV; ++qq)
-        if (qq == q) sel[qq] = 0;
-      __syncthreads();
-    } else {
-      int c[3];
-      unflat(C.n, own ? i : 0u, c);
-#pragma unroll
-      for (int qq = 0; qq < VCL_MAXLV; ++qq)
-        if (qq == q) {
-          if (own) xs[sel[qq]][off[qq] + i] = omega * rb[qq] / k[qq].d;
-          __syncthreads();
-          sweeps(qq, C, 64, c, own);
+  for (int q = 0; q < VCL_MAXLV; ++q) {
+    if (q == nl - 1) {
+      const Lv &C = P.lv[L - 1];
+      if (C.nc <= 64u) {
+        if (i < C.nc) rs[i] = rb[q][0];
+        __syncthreads();
+        if (i < C.nc) {
+          double acc = 0.0;
+          for (unsigned j = 0; j < C.nc; ++j) acc += Ainv[i * C.nc + j] * (double)rs[j];
+          xs[0][off[q] + i] = (R)acc;
         }
+        sel[q] = 0;
+        __syncthreads();
+      } else {
+        zero_sweep(q, C);
+        sweeps(q, C, 64);
+      }
     }
   }
 #pragma unroll
@@ -707,15 +725,25 @@ __global__ void __launch_bounds__(VC_COARSE_TPB) k_v_coarse_lds(LevelPack<Lv> P,
     if (q < nl - 1) {
       const Lv &F = P.lv[l0 + q];
       const Lv &C = P.lv[l0 + q + 1];
-      const bool own = i < F.nc;
-      int c[3];
-      unflat(F.n, own ? i : 0u, c);
-      if (own) xs[sel[q]][off[q] + i] += xs[sel[q + 1]][off[q + 1] + parent_of<R>(F.n, C.n, 2, c)];
+#pragma unroll
+      for (int j = 0; j < VCL_S(q); ++j) {
+        const unsigned id = i + j * T;
+        if (id < F.nc) {
+          int c[3];
+          unflat(F.n, id, c);
+          xs[sel[q]][off[q] + id] += xs[sel[q + 1]][off[q + 1] + parent_of<R>(F.n, C.n, 2, c)];
+        }
+      }
       __syncthreads();
-      sweeps(q, F, nu + 1, c, own);
+      sweeps(q, F, nu + 1);
     }
   }
-  if (i < P.lv[l0].nc) P.lv[l0].x[i] = xs[sel[0]][off[0] + i];
+#pragma unroll
+  for (int j = 0; j < C0; ++j) {
+    const unsigned id = i + j * T;
+    if (id < P.lv[l0].nc) P.lv[l0].x[id] = xs[sel[0]][off[0] + id];
+  }
+#undef VCL_S
 }
 
 // b = (R) r (level-0 input when the whole cycle runs in the single block).
