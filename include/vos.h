@@ -97,8 +97,9 @@ typedef struct {
   double rtol_u, rtol_p, rtol_c;
   int maxit_u, maxit_p, maxit_c;
   int precision;    /* vos_precision (pressure multigrid) */
-  int mg_nu;        /* Jacobi sweeps before and after each coarse correction, 1..8;
-                       0: 4 in 2-D, 2 in 3-D */
+  int mg_nu;        /* Jacobi sweeps before and after each coarse correction of the pressure
+                       and momentum hierarchies, 1..8; 0: pressure 4 and momentum 2 in 2-D,
+                       2 in 3-D.  The transport hierarchy uses at most 2. */
   int check_every;  /* Krylov iterations launched between host convergence checks, 1..256 */
   int use_graphs;   /* 1: capture each solve's chunk of check_every iterations in a HIP graph
                        once and replay it (iteration counts then round up to a multiple of

@@ -301,6 +301,7 @@ struct vos_sim {
   double ws_frac;           // ws_drop / squared A-norm error of starting from p^n
   int it_p_fp64;            // iterations of the last pressure solve run with the FP64 hierarchy (mixed)
   bool p_fp64_sticky;       // an FP32 pressure solve stalled on the current geometry (mixed)
+  int nu_mom;               // sweeps per leg of the momentum hierarchies
 };
 
 namespace {
@@ -674,7 +675,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
 // 2 for transport, whose rows on reactive bands are not diagonally dominant
 // (more damped-Jacobi sweeps amplify error modes there: measured 300-600
 // iterations with 2, 1000-2300 with 4 on a Pe 47, Da 0.54 micromodel).
-int sweeps(const vos_sim *s, int h) { return h == 3 ? std::min(2, s->opt.mg_nu) : s->opt.mg_nu; }
+int sweeps(const vos_sim *s, int h) { return h == 3 ? std::min(2, s->opt.mg_nu) : s->nu_mom; }
 
 // dsc: diagonal of the symmetrically scaled operator (momentum), nullptr for
 // the row-scaled transport operator.
@@ -1466,7 +1467,10 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->p_scale = 0.0;
   // defaults (0): in 2-D four sweeps with the tiled fine-level kernels and a
   // 1024-cell single-block tail; in 3-D two sweeps and a 4096-cell tail
+  // automatic sweeps: 2-D pressure 4 (fewer iterations at the same launch count), 2-D momentum 2
+  // (measured faster per step than 3 or 4 on the micromodel), 3-D 2; transport at most 2
   if (s->opt.mg_nu == 0) s->opt.mg_nu = grid->nz == 1 ? 4 : 2;
+  s->nu_mom = opts->mg_nu == 0 ? 2 : opts->mg_nu;
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? VC_TAIL_2D : VC_BLOCK_MAX);
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
