@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <type_traits>
 
 #include "vos.h"
@@ -159,7 +160,7 @@ struct SmgPlan {
 struct Layout {
   size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
   size_t vec[NVEC];
-  size_t part, part_max, scal, ainv;
+  size_t part, part2, part_max, scal, ainv;
   size_t mgT[MG_MAX_LEVELS][3], mgdiag[MG_MAX_LEVELS], mgx[MG_MAX_LEVELS], mgb[MG_MAX_LEVELS], mgt[MG_MAX_LEVELS];
   int nlev;
   SmgPlan smg[NSMG];
@@ -220,6 +221,7 @@ Layout make_layout(const vos_grid &g, int precision)
   }
   for (int k = 0; k < NVEC; ++k) Lo.vec[k] = P.take(nmax * dbl);
   Lo.part = P.take((size_t)NSLOT * MAXB * dbl);
+  Lo.part2 = P.take((size_t)NSLOT * MAXB * dbl);   // partials of the momentum solve on the second lane
   Lo.part_max = P.take((size_t)MAXB * dbl);
   Lo.scal = P.take((size_t)NSC * S_COUNT * 2 * dbl);
   Lo.ainv = P.take((size_t)MG_COARSE_MAX * MG_COARSE_MAX * dbl);
@@ -280,7 +282,6 @@ struct vos_sim {
   double *sainv[NSMG];
   double *host;       // pinned scalar read-back buffer
   hipEvent_t ev[7];
-  bool capturing;
   bool use_graphs;
   double p_scale;           // global scale of the pressure hierarchy (set per step)
   int coarse_cells;         // levels at or below this size run in the single-block kernel
@@ -302,6 +303,11 @@ struct vos_sim {
   int it_p_fp64;            // iterations of the last pressure solve run with the FP64 hierarchy (mixed)
   bool p_fp64_sticky;       // an FP32 pressure solve stalled on the current geometry (mixed)
   int nu_mom;               // sweeps per leg of the momentum hierarchies
+  // second lane: momentum component 1 runs on its own stream from a second host thread
+  hipStream_t lane_stream;
+  double *part2;            // its block partials
+  double *host2;            // its pinned read-back buffer
+  hipEvent_t fork, join;
 };
 
 namespace {
@@ -385,12 +391,27 @@ vos_status check_params(const vos_params *p)
 }
 
 // Host read of n doubles from device memory (synchronises the stream).
-vos_status read_back(vos_sim *s, const double *dev, size_t n)
+// Where a solve runs: its stream, Krylov vectors, block partials and pinned
+// read-back buffer.  The main lane is the sim's own; the second lane lets a
+// momentum component run concurrently with another.
+struct Lane {
+  hipStream_t st;
+  double *const *vec;
+  double *part;
+  double *host;
+};
+
+Lane main_lane(vos_sim *s) { return Lane{s->stream, s->vec, s->part, s->host}; }
+Lane second_lane(vos_sim *s) { return Lane{s->lane_stream, s->vec + 5, s->part2, s->host2}; }
+
+vos_status read_back(const Lane &ln, const double *dev, size_t n)
 {
-  HIP_TRY(hipMemcpyAsync(s->host, dev, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpyAsync(ln.host, dev, n * sizeof(double), hipMemcpyDeviceToHost, ln.st));
+  HIP_TRY(hipStreamSynchronize(ln.st));
   return VOS_OK;
 }
+
+vos_status read_back(vos_sim *s, const double *dev, size_t n) { return read_back(main_lane(s), dev, n); }
 
 // Run iterations until the device flag says converged or maxit is reached.
 // With graphs on, a chunk of check_every iterations is captured once per
@@ -405,32 +426,31 @@ struct Stall {
 };
 
 template <typename F>
-vos_status krylov_loop(vos_sim *s, int gid, double *sc, int maxit, F &&iter, int *its, double *res2, double *tol2,
-                       bool *conv, Stall *stall = nullptr)
+vos_status krylov_loop(vos_sim *s, const Lane &ln, int gid, double *sc, int maxit, F &&iter, int *its, double *res2,
+                       double *tol2, bool *conv, Stall *stall = nullptr)
 {
   HIP_TRY(hipGetLastError());
   int launched = 0;
-  vos_status st = read_back(s, sc, S_COUNT);
+  const double *host = ln.host;
+  vos_status st = read_back(ln, sc, S_COUNT);
   if (st) return st;
-  bool done = s->host[S_CONV] != 0.0;
+  bool done = host[S_CONV] != 0.0;
   const int chunk = s->opt.check_every;
-  double mark = s->host[S_RES2];
-  int mark_its = (int)s->host[S_ITS];
+  double mark = host[S_RES2];
+  int mark_its = (int)host[S_ITS];
   while (!done && launched < maxit) {
     if (s->use_graphs) {
       if (!s->gexec[gid]) {
         hipGraph_t graph;
-        s->capturing = true;
-        HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        HIP_TRY(hipStreamBeginCapture(ln.st, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < chunk; ++i) iter();
-        hipError_t e = hipStreamEndCapture(s->stream, &graph);
-        s->capturing = false;
+        hipError_t e = hipStreamEndCapture(ln.st, &graph);
         if (e != hipSuccess) return fail(VOS_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
         e = hipGraphInstantiate(&s->gexec[gid], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) { s->gexec[gid] = nullptr; return fail(VOS_ERR_DEVICE, "hipGraphInstantiate failed"); }
       }
-      HIP_TRY(hipGraphLaunch(s->gexec[gid], s->stream));
+      HIP_TRY(hipGraphLaunch(s->gexec[gid], ln.st));
       launched += chunk;
     } else {
       const int k = std::min(chunk, maxit - launched);
@@ -438,13 +458,13 @@ vos_status krylov_loop(vos_sim *s, int gid, double *sc, int maxit, F &&iter, int
       launched += k;
     }
     HIP_TRY(hipGetLastError());
-    st = read_back(s, sc, S_COUNT);
+    st = read_back(ln, sc, S_COUNT);
     if (st) return st;
-    done = s->host[S_CONV] != 0.0;
+    done = host[S_CONV] != 0.0;
     if (stall && !done) {
-      const int it = (int)s->host[S_ITS];
-      if (s->host[S_RES2] <= 0.25 * mark) {
-        mark = s->host[S_RES2];
+      const int it = (int)host[S_ITS];
+      if (host[S_RES2] <= 0.25 * mark) {
+        mark = host[S_RES2];
         mark_its = it;
       }
       const bool capped = stall->cap > 0 && it >= stall->cap;
@@ -455,10 +475,10 @@ vos_status krylov_loop(vos_sim *s, int gid, double *sc, int maxit, F &&iter, int
       }
     }
   }
-  *its = (int)s->host[S_ITS];
-  *res2 = s->host[S_RES2];
-  *tol2 = s->host[S_TOL2];
-  *conv = (s->host[S_RES2] <= s->host[S_TOL2]) || (s->host[S_RES2] == 0.0);
+  *its = (int)host[S_ITS];
+  *res2 = host[S_RES2];
+  *tol2 = host[S_TOL2];
+  *conv = (host[S_RES2] <= host[S_TOL2]) || (host[S_RES2] == 0.0);
   return VOS_OK;
 }
 
@@ -519,9 +539,8 @@ double jacobi_bytes(unsigned nc, int nd, bool out64, bool finest)
 
 // Coarse levels and coarsest inverse of hierarchy h (level 0 already filled).
 template <typename R>
-void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv)
+void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv, hipStream_t st)
 {
-  hipStream_t st = s->stream;
   const int nd = s->g.nd;
   const int L = s->snlev[h];
   for (int l = 0; l + 1 < L; ++l)
@@ -564,9 +583,8 @@ void launch_coarse(int c0, const LevelPack<Lv> &pack, int lc, int L, int nd, int
 // z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
 template <typename Lv, typename R>
 void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, double *z, const double *sc,
-            double omega, const double *dsc, double rscale, int nu)
+            double omega, const double *dsc, double rscale, int nu, hipStream_t st)
 {
-  hipStream_t st = s->stream;
   const int nd = s->g.nd;
   const R om = (R)omega;
   int lc = 0;
@@ -680,21 +698,23 @@ int sweeps(const vos_sim *s, int h) { return h == 3 ? std::min(2, s->opt.mg_nu) 
 // dsc: diagonal of the symmetrically scaled operator (momentum), nullptr for
 // the row-scaled transport operator.
 template <typename R>
-void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, const double *dsc)
+void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, const double *dsc,
+                hipStream_t st)
 {
-  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7, dsc, 1.0, sweeps(s, h));
+  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7, dsc, 1.0, sweeps(s, h), st);
 }
 
 // ---------------------------------------------------------------- stage S2
 
 template <int D, typename R>
-vos_status solve_momentum_t(vos_sim *s, SLevel<R> *lv, double dt, int *its, double *res)
+vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt, int *its, double *res)
 {
   const Dev &g = s->g;
-  hipStream_t st = s->stream;
+  hipStream_t st = ln.st;
+  double *part = ln.part;
   const unsigned n = g.nf[D];
   const int nb = grid_blocks(n);
-  double *b = s->vec[0], *r = s->vec[1], *z = s->vec[2], *pv = s->vec[3], *q = s->vec[4];
+  double *b = ln.vec[0], *r = ln.vec[1], *z = ln.vec[2], *pv = ln.vec[3], *q = ln.vec[4];
   double *x = s->ustar[D];
   double *sc = sc_block(s, SC_MOM + D);
   double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
@@ -702,40 +722,40 @@ vos_status solve_momentum_t(vos_sim *s, SLevel<R> *lv, double dt, int *its, doub
   const double rt2 = s->opt.rtol_u * s->opt.rtol_u;
   k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x);
   k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);   // Jacobi-scaled
-  smg_coarsen_all<R>(s, D, lv);
-  k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, s->part, zero_flag);
-  k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 0, s->part);
-  k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
-  smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D]);
-  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
-  k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
+  smg_coarsen_all<R>(s, D, lv, st);
+  k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, part, zero_flag);
+  k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 0, part);
+  k_cg_scal<<<1, TPB, 0, st>>>(0, part, nb, rt2, sc);
+  smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D], st);
+  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, part, sc);
+  k_cg_scal<<<1, TPB, 0, st>>>(5, part, nb, rt2, sc);
   HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
-    k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, s->part, sc);
-    k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
-    k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 0, s->part, sc);
-    k_cg_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
-    smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D]);
-    k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
-    k_cg_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
+    k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(1, part, nb, rt2, sc);
+    k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 0, part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(3, part, nb, rt2, sc);
+    smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D], st);
+    k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, part, sc);
+    k_cg_scal<<<1, TPB, 0, st>>>(4, part, nb, rt2, sc);
     k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
   };
   double res2, tol2;
   bool conv;
-  vos_status stt = krylov_loop(s, D, sc, s->opt.maxit_u, iter, its, &res2, &tol2, &conv);
+  vos_status stt = krylov_loop(s, ln, D, sc, s->opt.maxit_u, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
   k_mom_fix<D><<<nb, TPB, 0, st>>>(g, s->P.u_in, x);
-  const double bn2 = s->host[S_BN2];
+  const double bn2 = ln.host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "momentum predictor did not converge");
   return VOS_OK;
 }
 
 template <int D>
-vos_status solve_momentum(vos_sim *s, double dt, int *its, double *res)
+vos_status solve_momentum(vos_sim *s, const Lane &ln, double dt, int *its, double *res)
 {
-  if (s->opt.precision == VOS_MIXED) return solve_momentum_t<D, float>(s, s->smgf[D], dt, its, res);
-  return solve_momentum_t<D, double>(s, s->smgd[D], dt, its, res);
+  if (s->opt.precision == VOS_MIXED) return solve_momentum_t<D, float>(s, ln, s->smgf[D], dt, its, res);
+  return solve_momentum_t<D, double>(s, ln, s->smgd[D], dt, its, res);
 }
 
 // ---------------------------------------------------------------- stage S3
@@ -769,7 +789,7 @@ void mg_vcycle(vos_sim *s, MgLevel<R> *lv, const double *r, double *z, const dou
 {
   // A_R = A / p_scale, so z = A^-1 r is A_R^-1 (r / p_scale)
   vcycle<MgLevel<R>, R>(s, lv, s->nlev, s->ainv, r, z, sc, s->g.nd == 3 ? 6.0 / 7.0 : 0.8, nullptr,
-                        1.0 / s->p_scale, s->opt.mg_nu);
+                        1.0 / s->p_scale, s->opt.mg_nu, s->stream);
 }
 
 // ---------------------------------------------------------------- warm start
@@ -1008,7 +1028,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, doubl
     stall.cap = s->opt.p_fp32_its;
   }
   s->it_p_fp64 = 0;
-  vos_status stt = krylov_loop(s, gid, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv, mixed ? &stall : nullptr);
+  vos_status stt = krylov_loop(s, main_lane(s), gid, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv, mixed ? &stall : nullptr);
   if (stt) return stt;
   if (!mixed && s->opt.precision == VOS_MIXED) s->it_p_fp64 = *its;   // a solve after an FP32 stall
   if (stall.hit && !conv) {
@@ -1027,7 +1047,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, doubl
       k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
     };
     const int its32 = *its;
-    stt = krylov_loop(s, 5, sc, std::max(1, s->opt.maxit_p - its32), iter64, its, &res2, &tol2, &conv);
+    stt = krylov_loop(s, main_lane(s), 5, sc, std::max(1, s->opt.maxit_p - its32), iter64, its, &res2, &tol2, &conv);
     if (stt) return stt;
     s->it_p_fp64 = *its - its32;
   }
@@ -1086,18 +1106,18 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
                                      s->gmag, sc_block(s, SC_MISC), s->off, b, y);
   k_smg_from_scaled<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, lv[0]);
-  smg_coarsen_all<R>(s, H, lv);
+  smg_coarsen_all<R>(s, H, lv, st);
   k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
   k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
   k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, sc);
-    smg_vcycle<R>(s, H, lv, pv, ph, sc, nullptr);
+    smg_vcycle<R>(s, H, lv, pv, ph, sc, nullptr, st);
     k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
-    smg_vcycle<R>(s, H, lv, sv, sh, sc, nullptr);
+    smg_vcycle<R>(s, H, lv, sv, sh, sc, nullptr, st);
     k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
     k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, rh, s->c, r, s->part, sc);
@@ -1105,7 +1125,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   };
   double res2, tol2;
   bool conv;
-  vos_status stt = krylov_loop(s, 4, sc, s->opt.maxit_c, iter, its, &res2, &tol2, &conv);
+  vos_status stt = krylov_loop(s, main_lane(s), 4, sc, s->opt.maxit_c, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
   const double bn2 = s->host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
@@ -1191,16 +1211,34 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   if (ps != s->p_scale) { drop_graphs(s); s->p_scale = ps; }   // captured V-cycles hold 1/p_scale
   launch_coefficients(s, dt);
   HIP_TRY(hipEventRecord(s->ev[1], st));
-  r2 = solve_momentum<0>(s, dt, &dg->it_u[0], &dg->res_u[0]);
-  if (r2 == VOS_ERR_DEVICE) return r2;
-  if (r2 && !rc) rc = r2;
-  r2 = solve_momentum<1>(s, dt, &dg->it_u[1], &dg->res_u[1]);
-  if (r2 == VOS_ERR_DEVICE) return r2;
-  if (r2 && !rc) rc = r2;
-  if (s->g.nd == 3) {
-    r2 = solve_momentum<2>(s, dt, &dg->it_u[2], &dg->res_u[2]);
-    if (r2 == VOS_ERR_DEVICE) return r2;
-    if (r2 && !rc) rc = r2;
+  // The momentum components are independent systems: component 1 runs on the
+  // second lane (its own stream, Krylov vectors, partials and read-back
+  // buffer) from a second host thread while the main lane solves 0 (and 2).
+  {
+    HIP_TRY(hipEventRecord(s->fork, st));
+    HIP_TRY(hipStreamWaitEvent(s->lane_stream, s->fork, 0));
+    vos_status r1 = VOS_OK;
+    std::string m1;
+    std::thread t1([&]() {
+      r1 = solve_momentum<1>(s, second_lane(s), dt, &dg->it_u[1], &dg->res_u[1]);
+      if (r1) m1 = vos_last_error();
+    });
+    const Lane ml = main_lane(s);
+    vos_status r0 = solve_momentum<0>(s, ml, dt, &dg->it_u[0], &dg->res_u[0]);
+    std::string m0 = r0 ? std::string(vos_last_error()) : std::string();
+    vos_status r3 = VOS_OK;
+    if (s->g.nd == 3 && r0 != VOS_ERR_DEVICE) r3 = solve_momentum<2>(s, ml, dt, &dg->it_u[2], &dg->res_u[2]);
+    std::string m3 = r3 ? std::string(vos_last_error()) : std::string();
+    t1.join();
+    HIP_TRY(hipEventRecord(s->join, s->lane_stream));
+    HIP_TRY(hipStreamWaitEvent(st, s->join, 0));
+    // component order for the reported status: 0, 1, 2 (device errors end the step)
+    const vos_status rr[3] = {r0, r1, r3};
+    const std::string *mm[3] = {&m0, &m1, &m3};
+    for (int k = 0; k < 3; ++k)
+      if (rr[k] == VOS_ERR_DEVICE) return fail(rr[k], *mm[k]);
+    for (int k = 0; k < 3; ++k)
+      if (rr[k] && !rc) rc = fail(rr[k], *mm[k]);
   }
   HIP_TRY(hipEventRecord(s->ev[2], st));
   r2 = solve_pressure(s, &dg->it_p, &dg->res_p);
@@ -1379,6 +1417,22 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
 
 }  // namespace
 
+// Frees what vos_create made besides the workspace (the caller's); used on
+// creation failure and by vos_destroy.
+void release(vos_sim *s)
+{
+  if (s->lane_stream) (void)hipStreamSynchronize(s->lane_stream);
+  drop_graphs(s);
+  for (int k = 0; k < 7; ++k)
+    if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+  if (s->fork) (void)hipEventDestroy(s->fork);
+  if (s->join) (void)hipEventDestroy(s->join);
+  if (s->lane_stream) (void)hipStreamDestroy(s->lane_stream);
+  if (s->host) (void)hipHostFree(s->host);
+  if (s->host2) (void)hipHostFree(s->host2);
+  delete s;
+}
+
 // ====================================================================== C ABI
 
 extern "C" {
@@ -1457,13 +1511,25 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->p_fp64_sticky = false;
   s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
+  s->part2 = D(lo.part2);
+  s->host = s->host2 = nullptr;
+  s->lane_stream = nullptr;
+  s->fork = s->join = nullptr;
+  for (int k = 0; k < 7; ++k) s->ev[k] = nullptr;
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
-  if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
-  for (int k = 0; k < 7; ++k) {
-    e = hipEventCreate(&s->ev[k]);
-    if (e != hipSuccess) { delete s; return fail(VOS_ERR_DEVICE, "hipEventCreate failed"); }
+  if (e == hipSuccess) e = hipHostMalloc((void **)&s->host2, 64 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    release(s);
+    return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
-  s->capturing = false;
+  e = hipStreamCreateWithFlags(&s->lane_stream, hipStreamNonBlocking);   // default priority
+  for (int k = 0; k < 7 && e == hipSuccess; ++k) e = hipEventCreate(&s->ev[k]);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    release(s);
+    return fail(VOS_ERR_DEVICE, std::string("stream / event creation: ") + hipGetErrorString(e));
+  }
   s->p_scale = 0.0;
   // defaults (0): in 2-D four sweeps with the tiled fine-level kernels and a
   // 1024-cell single-block tail; in 3-D two sweeps and a 4096-cell tail
@@ -1491,11 +1557,7 @@ vos_status vos_destroy(vos_sim *s)
 {
   if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
   (void)hipStreamSynchronize(s->stream);
-  drop_graphs(s);
-  for (int k = 0; k < 7; ++k) (void)hipEventDestroy(s->ev[k]);
-
-  (void)hipHostFree(s->host);
-  delete s;
+  release(s);
   return VOS_OK;
 }
 
