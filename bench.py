@@ -39,6 +39,10 @@ P_ITER_BYTES = {("mixed", 2): 136 + 83, ("fp64", 2): 136 + 144,
 # Krylov iterations per captured chunk on the micromodel (its solves take 7-27
 # iterations; longer chunks launch more kernels that only find the flag set).
 CHECK_EVERY = 4
+# Pressure and transport solves start from the linear extrapolation 2 x^n - x^(n-1)
+# of the last two steps (vos_opts.extrapolate); the start-from-x^n rate is reported
+# beside it.
+EXTRAPOLATE = 1
 # Per-step pressure setup (hierarchy build, right-hand side, initial residual):
 P_SETUP_BYTES = {2: 150, 3: 200}
 
@@ -47,12 +51,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def setup_sim(vos, inputs, scaling, workload, pe, da, precision, model, dt, relax_steps):
+def setup_sim(vos, inputs, scaling, workload, pe, da, precision, model, dt, relax_steps, extrapolate=EXTRAPOLATE):
     import torch
     es, prm = inputs.workload(workload)
     nz, ny, nx = es.shape
     params = dict(prm, model=model)
-    opts = vos.Opts(precision=precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=CHECK_EVERY)
+    opts = vos.Opts(precision=precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=CHECK_EVERY,
+                    extrapolate=extrapolate)
     sim = vos.Sim(nx, ny, nz, prm["dx"], dict(params, kc=0.0), opts)
     sim.set_solid_fraction(es)
     d = None
@@ -179,7 +184,8 @@ def batch_bench(vos, inputs, scaling, n, steps, dt, seed=2, relax=5):
     da = 10 ** rng.uniform(-3, 0, n)
     base = dict(inputs.BASE_PARAMS, model=0)
     specs = [(BATCH_SIZES[k][0], BATCH_SIZES[k][1], 1, 5e-6, dict(base, kc=0.0)) for k in picks]
-    opts = vos.Opts(precision=vos.MIXED, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=8)
+    opts = vos.Opts(precision=vos.MIXED, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=8,
+                    extrapolate=EXTRAPOLATE)
     b = Batch(specs, opts)
     for i, (nx, ny, *_rest) in enumerate(specs):
         b.sims[i].set_solid_fraction(inputs.rsa_discs(nx, ny, seed=100 + i))
@@ -279,9 +285,9 @@ def learned_3d(vos, inputs, n, dt, snapshots=60, iters=400, steps=10):
     es = inputs.sphere_pack(n, seed=34, median_r=n / 10.0, porosity=0.3)
     prm = dict(inputs.BASE_PARAMS, dx=4e-6, model=0)
 
-    def make(prec):
+    def make(prec, extrapolate=0):
         return vos.Sim(n, n, n, prm["dx"], prm, vos.Opts(precision=prec, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8,
-                                                          maxit_p=6000))
+                                                          maxit_p=6000, extrapolate=extrapolate))
     base = make(vos.MIXED)
     base.set_solid_fraction(es)
     base.step(dt, 3, freeze_solid=True)
@@ -302,14 +308,15 @@ def learned_3d(vos, inputs, n, dt, snapshots=60, iters=400, steps=10):
     out = {"workload": f"pack {n}^3 median radius {n / 10:g} porosity 0.3 seed 34, iVoS, dt={dt:g}s, rtol 1e-8",
            "snapshots": snapshots, "train_iters": iters, "train_loss": [round(l, 4) for _, l in hist],
            "collect_s": round(t_collect, 2), "train_s": round(t_train, 2)}
-    for name, prec, learned in (("plain_fp64", vos.FP64, False), ("mixed", vos.MIXED, False),
-                                ("mixed_learned", vos.MIXED, True)):
-        s = make(prec)
+    for name, prec, learned, ex in (("plain_fp64", vos.FP64, False, 0), ("mixed", vos.MIXED, False, 0),
+                                    ("mixed_learned", vos.MIXED, True, 0),
+                                    ("mixed_extrapolated", vos.MIXED, False, 1)):
+        s = make(prec, ex)
         for k, v in state.items():
             s.set(k, v)
         if learned:
             U.attach(s, inf, gain=data.gain, use_guess=True)
-        s.step(dt)   # warm-up (graph capture)
+        s.step(dt)   # warm-up (graph capture; the extrapolation's first history point)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ds = [s.step(dt) for _ in range(steps)]
@@ -430,21 +437,31 @@ def main():
     p_gbs = p_bytes / t_p / 1e9
 
     plain = None
+    from_xn = None
     if not args.skip_plain:
-        # same relaxed state, plain FP64 multigrid
-        sim64 = vos.Sim(nx, ny, nz, inputs.workload(args.workload)[1]["dx"], params,
-                        vos.Opts(precision=vos.FP64, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8,
-                                 check_every=CHECK_EVERY))
-        for k in ("eps", "ux", "uy", "uz", "p", "c"):
-            sim64.set(k, sim.get(k))
-        el64, d64 = timed_steps(sim64, args.dt, args.steps, args.warmup)
-        its64 = sum(d["it_p"] for d in d64)
-        t64 = sum(d["t_ms"][2] for d in d64) * 1e-3
-        pb64 = cells * (P_ITER_BYTES[("fp64", nd)] * its64 + P_SETUP_BYTES[nd] * len(d64))
-        plain = {"value": cells * args.steps / el64, "ms_per_step": el64 / args.steps * 1e3,
-                 "pressure_its_per_step": its64 / len(d64), "pressure_GBs": pb64 / t64 / 1e9}
-        log(f"fp64: {plain['ms_per_step']:.2f} ms/step, {plain['value']:.3e} cell-steps/s")
-        sim64.close()
+        # the same relaxed state, (a) plain FP64 multigrid with the same options,
+        # (b) mixed precision with every solve started from x^n
+        for prec, ex in ((vos.FP64, EXTRAPOLATE), (vos.MIXED, 0)):
+            sim2 = vos.Sim(nx, ny, nz, inputs.workload(args.workload)[1]["dx"], params,
+                           vos.Opts(precision=prec, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8,
+                                    check_every=CHECK_EVERY, extrapolate=ex))
+            for k in ("eps", "ux", "uy", "uz", "p", "c"):
+                sim2.set(k, sim.get(k))
+            el2, d2 = timed_steps(sim2, args.dt, args.steps, args.warmup)
+            its2 = sum(d["it_p"] for d in d2)
+            t2 = sum(d["t_ms"][2] for d in d2) * 1e-3
+            tag = "fp64" if prec == vos.FP64 else "mixed"
+            pb2 = cells * (P_ITER_BYTES[(tag, nd)] * its2 + P_SETUP_BYTES[nd] * len(d2))
+            res = {"value": cells * args.steps / el2, "ms_per_step": el2 / args.steps * 1e3,
+                   "pressure_its_per_step": its2 / len(d2), "pressure_GBs": pb2 / t2 / 1e9,
+                   "transport_its_per_step": sum(d["it_c"] for d in d2) / len(d2)}
+            if prec == vos.FP64:
+                plain = res
+                log(f"fp64: {res['ms_per_step']:.2f} ms/step, {res['value']:.3e} cell-steps/s")
+            else:
+                from_xn = res
+                log(f"mixed, solves started from x^n: {res['ms_per_step']:.2f} ms/step")
+            sim2.close()
 
     roof = roofline(sim, args.timer)
     others = {k: roofline(sim, k) for k in ("v_up", "v_coarse", "p_apply", "adr_apply")}
@@ -487,12 +504,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {nx}x{ny}x{nz} dx=5um RSA discs seed 11, iVoS, "
                                f"Pe={args.pe:g} Da={args.da:g}, dt={args.dt:g}s, rtol 1e-8",
-                   "precision": "mixed", "cells": cells},
+                   "precision": "mixed", "cells": cells,
+                   "solver_starts": "extrapolated 2x^n - x^(n-1)" if EXTRAPOLATE else "x^n"},
         "pressure_solve": {"GBs_algorithmic": round(p_gbs, 1), "frac_hbm": round(p_gbs / HBM_PEAK_GBS, 4),
                            "its_per_step": its_p / len(diags), "ms_per_step": t_p / len(diags) * 1e3},
         "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)],
         "iterations": {"u": last["it_u"], "p": last["it_p"], "c": last["it_c"]},
         "plain_fp64": plain,
+        "mixed_started_from_xn": from_xn,
         "roofline": roof,
         "roofline_other_kernels": others,
         "pressure_solve_3d": p3d,

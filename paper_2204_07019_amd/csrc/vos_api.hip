@@ -158,7 +158,7 @@ struct SmgPlan {
 };
 
 struct Layout {
-  size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
+  size_t eps, p, c, pn, cold, cprev, pprev, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
   size_t vec[NVEC];
   size_t part, part2, part_max, scal, ainv;
   size_t mgT[MG_MAX_LEVELS][3], mgdiag[MG_MAX_LEVELS], mgx[MG_MAX_LEVELS], mgb[MG_MAX_LEVELS], mgt[MG_MAX_LEVELS];
@@ -204,6 +204,8 @@ Layout make_layout(const vos_grid &g, int precision)
   Lo.c = P.take(nc * dbl);
   Lo.pn = P.take(nc * dbl);
   Lo.cold = P.take(nc * dbl);
+  Lo.cprev = P.take(nc * dbl);   // last step's solutions, for extrapolated starts
+  Lo.pprev = P.take(nc * dbl);
   Lo.rbar = P.take(nc * dbl);
   Lo.gmag = P.take(nc * dbl);
   for (int d = 0; d < 3; ++d) Lo.nrm[d] = P.take(nc * dbl);
@@ -303,11 +305,15 @@ struct vos_sim {
   int it_p_fp64;            // iterations of the last pressure solve run with the FP64 hierarchy (mixed)
   bool p_fp64_sticky;       // an FP32 pressure solve stalled on the current geometry (mixed)
   int nu_mom;               // sweeps per leg of the momentum hierarchies
-  // second lane: momentum component 1 runs on its own stream from a second host thread
-  hipStream_t lane_stream;
-  double *part2;            // its block partials
-  double *host2;            // its pinned read-back buffer
-  hipEvent_t fork, join;
+  double *cprev, *pprev;    // c and p of the previous step (extrapolated starts)
+  bool hist_c, hist_p;      // they hold a solution of this state's history
+  // two lanes for the momentum components, each with its own stream (created back to
+  // back, so they land on different hardware queues), Krylov vectors, partials and
+  // pinned read-back buffer; component 1 is driven from a second host thread
+  hipStream_t lane_stream[2];
+  double *part2;            // block partials of lane 1
+  double *host2;            // pinned read-back buffer of lane 1
+  hipEvent_t fork, join[2];
 };
 
 namespace {
@@ -377,6 +383,7 @@ vos_status check_opts(const vos_opts *o)
     return fail(VOS_ERR_ARG, "coarse_cells must be 0 or in [64, 65536]");
   if (o->level_kernels != 0 && o->level_kernels != 1) return fail(VOS_ERR_ARG, "level_kernels must be 0 or 1");
   if (o->p_fp32_its < 0) return fail(VOS_ERR_ARG, "p_fp32_its must be >= 0");
+  if (o->extrapolate != 0 && o->extrapolate != 1) return fail(VOS_ERR_ARG, "extrapolate must be 0 or 1");
   return VOS_OK;
 }
 
@@ -402,7 +409,10 @@ struct Lane {
 };
 
 Lane main_lane(vos_sim *s) { return Lane{s->stream, s->vec, s->part, s->host}; }
-Lane second_lane(vos_sim *s) { return Lane{s->lane_stream, s->vec + 5, s->part2, s->host2}; }
+Lane momentum_lane(vos_sim *s, int k)
+{
+  return k == 0 ? Lane{s->lane_stream[0], s->vec, s->part, s->host} : Lane{s->lane_stream[1], s->vec + 5, s->part2, s->host2};
+}
 
 vos_status read_back(const Lane &ln, const double *dev, size_t n)
 {
@@ -486,6 +496,18 @@ void drop_graphs(vos_sim *s)
 {
   for (int k = 0; k < 8; ++k)
     if (s->gexec[k]) { (void)hipGraphExecDestroy(s->gexec[k]); s->gexec[k] = nullptr; }
+}
+
+// Start of a solve from the linear extrapolation in time of the last two
+// solutions: x = 2 x^n - x^(n-1) when have_prev, and prev = x^n either way.
+__global__ void __launch_bounds__(TPB) k_extrap(unsigned n, int have_prev, double *__restrict__ x,
+                                                double *__restrict__ prev)
+{
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
+    const double xn = x[i];
+    if (have_prev) x[i] = 2.0 * xn - prev[i];
+    prev[i] = xn;
+  }
 }
 
 // q = A x (pressure operator) with the partials of x.q in s->part; returns
@@ -999,6 +1021,10 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, doubl
   const double rt2 = s->opt.rtol_p * s->opt.rtol_p;
   mg_setup<R>(s, lv);
   HIP_TRY(hipMemcpyAsync(s->pn, s->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (s->opt.extrapolate && !s->net) {   // the start only; the right-hand side keeps p^n (pn)
+    k_extrap<<<nb, TPB, 0, st>>>(n, s->hist_p ? 1 : 0, s->p, s->pprev);
+    s->hist_p = true;
+  }
   k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b);
   if (s->net)
     if (vos_status e = warm_start(s, b, q, z, pv, zero_flag)) return e;
@@ -1103,6 +1129,10 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   const int H = 3;
   const double rt2 = s->opt.rtol_c * s->opt.rtol_c;
   HIP_TRY(hipMemcpyAsync(s->cold, s->c, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (s->opt.extrapolate) {   // the start only; the deferred correction keeps c^n (cold)
+    k_extrap<<<nb, TPB, 0, st>>>(n, s->hist_c ? 1 : 0, s->c, s->cprev);
+    s->hist_c = true;
+  }
   k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
                                      s->gmag, sc_block(s, SC_MISC), s->off, b, y);
   k_smg_from_scaled<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, lv[0]);
@@ -1211,27 +1241,29 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   if (ps != s->p_scale) { drop_graphs(s); s->p_scale = ps; }   // captured V-cycles hold 1/p_scale
   launch_coefficients(s, dt);
   HIP_TRY(hipEventRecord(s->ev[1], st));
-  // The momentum components are independent systems: component 1 runs on the
-  // second lane (its own stream, Krylov vectors, partials and read-back
-  // buffer) from a second host thread while the main lane solves 0 (and 2).
+  // The momentum components are independent systems: components 0 (then 2)
+  // and 1 run on the two momentum lanes, 1 driven from a second host thread.
   {
     HIP_TRY(hipEventRecord(s->fork, st));
-    HIP_TRY(hipStreamWaitEvent(s->lane_stream, s->fork, 0));
+    HIP_TRY(hipStreamWaitEvent(s->lane_stream[0], s->fork, 0));
+    HIP_TRY(hipStreamWaitEvent(s->lane_stream[1], s->fork, 0));
     vos_status r1 = VOS_OK;
     std::string m1;
     std::thread t1([&]() {
-      r1 = solve_momentum<1>(s, second_lane(s), dt, &dg->it_u[1], &dg->res_u[1]);
+      r1 = solve_momentum<1>(s, momentum_lane(s, 1), dt, &dg->it_u[1], &dg->res_u[1]);
       if (r1) m1 = vos_last_error();
     });
-    const Lane ml = main_lane(s);
-    vos_status r0 = solve_momentum<0>(s, ml, dt, &dg->it_u[0], &dg->res_u[0]);
+    const Lane l0 = momentum_lane(s, 0);
+    vos_status r0 = solve_momentum<0>(s, l0, dt, &dg->it_u[0], &dg->res_u[0]);
     std::string m0 = r0 ? std::string(vos_last_error()) : std::string();
     vos_status r3 = VOS_OK;
-    if (s->g.nd == 3 && r0 != VOS_ERR_DEVICE) r3 = solve_momentum<2>(s, ml, dt, &dg->it_u[2], &dg->res_u[2]);
+    if (s->g.nd == 3 && r0 != VOS_ERR_DEVICE) r3 = solve_momentum<2>(s, l0, dt, &dg->it_u[2], &dg->res_u[2]);
     std::string m3 = r3 ? std::string(vos_last_error()) : std::string();
     t1.join();
-    HIP_TRY(hipEventRecord(s->join, s->lane_stream));
-    HIP_TRY(hipStreamWaitEvent(st, s->join, 0));
+    for (int k = 0; k < 2; ++k) {
+      HIP_TRY(hipEventRecord(s->join[k], s->lane_stream[k]));
+      HIP_TRY(hipStreamWaitEvent(st, s->join[k], 0));
+    }
     // component order for the reported status: 0, 1, 2 (device errors end the step)
     const vos_status rr[3] = {r0, r1, r3};
     const std::string *mm[3] = {&m0, &m1, &m3};
@@ -1421,13 +1453,16 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
 // creation failure and by vos_destroy.
 void release(vos_sim *s)
 {
-  if (s->lane_stream) (void)hipStreamSynchronize(s->lane_stream);
+  for (int k = 0; k < 2; ++k)
+    if (s->lane_stream[k]) (void)hipStreamSynchronize(s->lane_stream[k]);
   drop_graphs(s);
   for (int k = 0; k < 7; ++k)
     if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
   if (s->fork) (void)hipEventDestroy(s->fork);
-  if (s->join) (void)hipEventDestroy(s->join);
-  if (s->lane_stream) (void)hipStreamDestroy(s->lane_stream);
+  for (int k = 0; k < 2; ++k) {
+    if (s->join[k]) (void)hipEventDestroy(s->join[k]);
+    if (s->lane_stream[k]) (void)hipStreamDestroy(s->lane_stream[k]);
+  }
   if (s->host) (void)hipHostFree(s->host);
   if (s->host2) (void)hipHostFree(s->host2);
   delete s;
@@ -1484,6 +1519,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   char *w = s->ws;
   auto D = [&](size_t o) { return (double *)(w + o); };
   s->eps = D(lo.eps); s->p = D(lo.p); s->c = D(lo.c); s->pn = D(lo.pn); s->cold = D(lo.cold);
+  s->cprev = D(lo.cprev); s->pprev = D(lo.pprev);
   s->rbar = D(lo.rbar); s->gmag = D(lo.gmag); s->pdiag = D(lo.pdiag); s->off = D(lo.off);
   for (int d = 0; d < 3; ++d) {
     s->nrm[d] = D(lo.nrm[d]); s->u[d] = D(lo.u[d]); s->ustar[d] = D(lo.ustar[d]); s->dmom[d] = D(lo.dmom[d]);
@@ -1509,12 +1545,13 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->ws_res_prev = s->ws_res_guess = 0.0;
   s->it_p_fp64 = 0;
   s->p_fp64_sticky = false;
+  s->hist_c = s->hist_p = false;
   s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
   s->part2 = D(lo.part2);
   s->host = s->host2 = nullptr;
-  s->lane_stream = nullptr;
-  s->fork = s->join = nullptr;
+  s->lane_stream[0] = s->lane_stream[1] = nullptr;
+  s->fork = s->join[0] = s->join[1] = nullptr;
   for (int k = 0; k < 7; ++k) s->ev[k] = nullptr;
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&s->host2, 64 * sizeof(double), hipHostMallocDefault);
@@ -1522,10 +1559,12 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     release(s);
     return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
-  e = hipStreamCreateWithFlags(&s->lane_stream, hipStreamNonBlocking);   // default priority
+  // default priority; created back to back so they land on different hardware queues
+  e = hipStreamCreateWithFlags(&s->lane_stream[0], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->lane_stream[1], hipStreamNonBlocking);
   for (int k = 0; k < 7 && e == hipSuccess; ++k) e = hipEventCreate(&s->ev[k]);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming);
   if (e != hipSuccess) {
     release(s);
     return fail(VOS_ERR_DEVICE, std::string("stream / event creation: ") + hipGetErrorString(e));
@@ -1573,6 +1612,7 @@ vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device
   HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), st));
   k_set_eps<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, src, s->P.eps_min, s->eps, bad);
   s->p_fp64_sticky = false;   // a new geometry: mixed precision tries the FP32 hierarchy again
+  s->hist_c = s->hist_p = false;
   k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, s->P.u_in, s->u[0]);
   HIP_TRY(hipGetLastError());
   int hbad = 0;
@@ -1591,6 +1631,7 @@ vos_status vos_set_params(vos_sim *s, const vos_params *params)
   if (st) return st;
   s->prm = *params;
   drop_graphs(s);   // captured iterations hold mu / dx^2 by value
+  s->hist_c = s->hist_p = false;
   Phys &P = s->P;
   P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
   P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
@@ -1609,6 +1650,7 @@ vos_status vos_set_field(vos_sim *s, int field, const double *src, int on_device
   double *d = field_ptr(s, field, &n, &wr);
   if (!d) return fail(VOS_ERR_ARG, "unknown field");
   if (!wr) return fail(VOS_ERR_ARG, "field is read-only");
+  s->hist_c = s->hist_p = false;
   HIP_TRY(hipMemcpyAsync(d, src, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                          s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));

@@ -75,6 +75,21 @@ def test_post_20_steps(orc, precision):
     assert dg["solid_rate"] == pytest.approx(do["solid_rate"], rel=1e-6)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_extrapolated_starts_match_oracle(orc, precision):
+    """Pressure and transport solves started from 2 x^n - x^(n-1): 12 post
+    steps within 1e-6 of the oracle, and the extrapolated starts do not skip
+    the solves (every step still iterates)."""
+    from paper_2204_07019_amd import inputs
+    es, prm = inputs.workload("post")
+    prob = make_problem(es, prm, model=0, **TIGHT)
+    _say(f"post 256x64 extrapolated starts precision {precision} 12 steps")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 12, precision=precision, extrapolate=1)
+    _compare(st, g, eps0)
+    for _, dg in diags:
+        assert dg["it_p"] >= 1 and dg["it_c"] >= 1, dg
+
+
 def test_post_stagewise_one_step(orc):
     """Intermediate outputs of one step: momentum predictor, reaction rate, |grad eps|."""
     import oracle
