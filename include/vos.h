@@ -119,10 +119,12 @@ typedef struct {
                        the FP64 hierarchy from the start until the next
                        vos_set_solid_fraction.  >= 0. */
   int extrapolate;  /* 1: the pressure and transport solves start from the linear extrapolation
-                       2 x^n - x^(n-1) of the last two steps' solutions (x^n on the first step
-                       after vos_create, vos_set_field, vos_set_solid_fraction or vos_set_params;
-                       the pressure keeps x^n while a warm-start network is attached); the
-                       right-hand sides are unchanged.  0: start from x^n. */
+                       2 x^n - x^(n-1) of the last two steps' solutions, the momentum predictor
+                       from 2 u*^n - u*^(n-1) of the last two predictors (x^n, or u^n, until
+                       that history exists again after vos_create, vos_set_field,
+                       vos_set_solid_fraction or vos_set_params; the pressure keeps p^n while
+                       a warm-start network is attached); right-hand sides are unchanged.
+                       0: start from x^n (u^n). */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */

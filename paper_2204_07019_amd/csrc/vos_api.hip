@@ -158,6 +158,7 @@ struct SmgPlan {
 };
 
 struct Layout {
+  size_t uprev[3];
   size_t eps, p, c, pn, cold, cprev, pprev, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
   size_t vec[NVEC];
   size_t part, part2, part_max, scal, ainv;
@@ -220,6 +221,7 @@ Layout make_layout(const vos_grid &g, int precision)
     Lo.af[d] = P.take(D0.nf[d] * dbl);
     Lo.T[d] = P.take(D0.nf[d] * dbl);
     Lo.w[d] = P.take(D0.nf[d] * dbl);
+    Lo.uprev[d] = P.take(D0.nf[d] * dbl);   // the predictor of the step before (extrapolated starts)
   }
   for (int k = 0; k < NVEC; ++k) Lo.vec[k] = P.take(nmax * dbl);
   Lo.part = P.take((size_t)NSLOT * MAXB * dbl);
@@ -307,6 +309,8 @@ struct vos_sim {
   int nu_mom;               // sweeps per leg of the momentum hierarchies
   double *cprev, *pprev;    // c and p of the previous step (extrapolated starts)
   bool hist_c, hist_p;      // they hold a solution of this state's history
+  double *uprev[3];         // momentum predictors of the step before
+  int hist_u[3];            // 0: no predictor of this history, 1: ustar holds one, 2: uprev too
   // two lanes for the momentum components, each with its own stream (created back to
   // back, so they land on different hardware queues), Krylov vectors, partials and
   // pinned read-back buffer; component 1 is driven from a second host thread
@@ -742,7 +746,10 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
   double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
   const double cvis = s->P.mu / (g.dx * g.dx);
   const double rt2 = s->opt.rtol_u * s->opt.rtol_u;
-  k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x);
+  // start: u^n, or the last predictor (then 2 u*^n - u*^(n-1)) with extrapolated starts
+  const bool ex = s->opt.extrapolate && s->hist_u[D] >= 1;
+  if (ex) k_extrap<<<nb, TPB, 0, st>>>(n, s->hist_u[D] >= 2 ? 1 : 0, x, s->uprev[D]);
+  k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x, ex ? 0 : 1);
   k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);   // Jacobi-scaled
   smg_coarsen_all<R>(s, D, lv, st);
   k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, part, zero_flag);
@@ -767,6 +774,7 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
   vos_status stt = krylov_loop(s, ln, D, sc, s->opt.maxit_u, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
   k_mom_fix<D><<<nb, TPB, 0, st>>>(g, s->P.u_in, x);
+  if (s->opt.extrapolate && conv) s->hist_u[D] = std::min(2, s->hist_u[D] + 1);
   const double bn2 = ln.host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "momentum predictor did not converge");
@@ -1520,6 +1528,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   auto D = [&](size_t o) { return (double *)(w + o); };
   s->eps = D(lo.eps); s->p = D(lo.p); s->c = D(lo.c); s->pn = D(lo.pn); s->cold = D(lo.cold);
   s->cprev = D(lo.cprev); s->pprev = D(lo.pprev);
+  for (int d = 0; d < 3; ++d) s->uprev[d] = D(lo.uprev[d]);
   s->rbar = D(lo.rbar); s->gmag = D(lo.gmag); s->pdiag = D(lo.pdiag); s->off = D(lo.off);
   for (int d = 0; d < 3; ++d) {
     s->nrm[d] = D(lo.nrm[d]); s->u[d] = D(lo.u[d]); s->ustar[d] = D(lo.ustar[d]); s->dmom[d] = D(lo.dmom[d]);
@@ -1546,6 +1555,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->it_p_fp64 = 0;
   s->p_fp64_sticky = false;
   s->hist_c = s->hist_p = false;
+  s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
   s->part2 = D(lo.part2);
@@ -1613,6 +1623,7 @@ vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device
   k_set_eps<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, src, s->P.eps_min, s->eps, bad);
   s->p_fp64_sticky = false;   // a new geometry: mixed precision tries the FP32 hierarchy again
   s->hist_c = s->hist_p = false;
+  s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, s->P.u_in, s->u[0]);
   HIP_TRY(hipGetLastError());
   int hbad = 0;
@@ -1632,6 +1643,7 @@ vos_status vos_set_params(vos_sim *s, const vos_params *params)
   s->prm = *params;
   drop_graphs(s);   // captured iterations hold mu / dx^2 by value
   s->hist_c = s->hist_p = false;
+  s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   Phys &P = s->P;
   P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
   P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
@@ -1651,6 +1663,7 @@ vos_status vos_set_field(vos_sim *s, int field, const double *src, int on_device
   if (!d) return fail(VOS_ERR_ARG, "unknown field");
   if (!wr) return fail(VOS_ERR_ARG, "field is read-only");
   s->hist_c = s->hist_p = false;
+  s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   HIP_TRY(hipMemcpyAsync(d, src, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                          s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));

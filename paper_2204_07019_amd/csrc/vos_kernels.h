@@ -176,7 +176,7 @@ __global__ void k_lambda(const double *__restrict__ part, int nb, int model, dou
 template <int D>
 __global__ void __launch_bounds__(TPB) k_mom_rhs(Dev g, Phys P, double dt, const double *__restrict__ eps,
                                                  const double *__restrict__ un, const double *__restrict__ pn,
-                                                 double *__restrict__ b, double *__restrict__ x0)
+                                                 double *__restrict__ b, double *__restrict__ x0, int start_un)
 {
   const double cvis = P.mu / (g.dx * g.dx);
   for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(TPB) k_mom_rhs(Dev g, Phys P, double dt, const
     const double pu = outlet ? P.p_out : pn[up];
     rhs -= ef * (pu - pl) / (outlet ? 0.5 * g.dx : g.dx);
     b[f] = rhs;
-    x0[f] = un[f];
+    if (start_un) x0[f] = un[f];   // else x0 holds an extrapolated start
   }
 }
 
