@@ -446,12 +446,13 @@ vos_status krylov_loop(vos_sim *s, const Lane &ln, int gid, double *sc, int maxi
   HIP_TRY(hipGetLastError());
   int launched = 0;
   const double *host = ln.host;
-  vos_status st = read_back(ln, sc, S_COUNT);
-  if (st) return st;
-  bool done = host[S_CONV] != 0.0;
+  vos_status st = VOS_OK;
+  // no read-back before the first chunk: when the start already meets the
+  // tolerance every kernel of the chunk finds the device flag set and returns
+  bool done = false;
   const int chunk = s->opt.check_every;
-  double mark = host[S_RES2];
-  int mark_its = (int)host[S_ITS];
+  double mark = HUGE_VAL;
+  int mark_its = 0;
   while (!done && launched < maxit) {
     if (s->use_graphs) {
       if (!s->gexec[gid]) {
