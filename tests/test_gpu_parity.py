@@ -185,6 +185,11 @@ LEVEL_CASES = [  # (shape, precision, extra options): 2-D tiled and 3-D marching
     ((70, 12, 9), 1, {"coarse_cells": 64, "mg_nu": 3}),
     ((64, 32, 16), 1, {"mg_nu": 1}),
     ((130, 20, 11), 0, {"coarse_cells": 64, "mg_nu": 2}),
+    # 2-D tails in LDS with 2 (65x30 = 1950 cells) and, in FP32, 4 (96x40 with a
+    # 4096-cell tail) cells per thread on their first level
+    ((130, 60, 1), 1, {}),
+    ((96, 40, 1), 1, {"coarse_cells": 4096}),
+    ((96, 40, 1), 0, {"coarse_cells": 4096, "extrapolate": 1}),
 ]
 
 
