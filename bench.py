@@ -210,11 +210,19 @@ def batch_bench(vos, inputs, scaling, n, steps, dt, seed=2, relax=5):
     diags = b.step(dt, steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the same instances advanced one after another (one host thread, no overlap
+    # between instances) for the same number of steps, continuing from there
+    t0 = time.perf_counter()
+    for s in b.sims:
+        s.step(dt, steps)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
     cells = sum(nx * ny for (nx, ny, *_r) in specs)
     out = {"workload": f"{n} RSA micromodels, sizes from {['%dx%d' % s for s in BATCH_SIZES]}, "
                        f"Pe logU[0.1,100], Da logU[1e-3,1], iVoS, mixed, dt={dt:g}s, rtol 1e-8",
            "instances": n, "cells": cells, "steps": steps,
            "value": cells * steps / el, "unit": "cell-steps/s", "ms_per_batch_step": el / steps * 1e3,
+           "sequential_value": cells * steps / el_seq,
            "tuned": tuned,
            "max_its_p": max(dg["it_p"] for dg in diags), "max_its_c": max(dg["it_c"] for dg in diags)}
     b.close()
@@ -478,7 +486,8 @@ def main():
     if not args.no_batch:
         log(f"batch of {args.batch_n} micromodels")
         bat = batch_bench(vos, inputs, scaling, args.batch_n, args.batch_steps, args.dt)
-        log(f"batch: {bat['value']:.3e} cell-steps/s, {bat['ms_per_batch_step']:.1f} ms per batch step")
+        log(f"batch: {bat['value']:.3e} cell-steps/s, {bat['ms_per_batch_step']:.1f} ms per batch step; "
+            f"one after another {bat['sequential_value']:.3e}")
     net = None
     if not args.no_unet:
         log(f"U-Net {args.unet_n}^3")

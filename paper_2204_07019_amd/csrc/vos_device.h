@@ -152,6 +152,32 @@ __device__ __forceinline__ double max_partials(const double *part, int q, int nb
   return block_max(s, lds);
 }
 
+// In-place Gauss-Jordan inverse of the n x n matrix M (n <= 64, in LDS, row
+// stride 65) without pivoting (the matrices are SPD), by the whole block.
+// Step k: piv = 1 / M[k][k]; row k is scaled by piv; every other element
+// takes M[i][j] - M[i][k] M[k][j] with the scaled row; column k becomes
+// -M[i][k] piv and M[k][k] = piv.  The scaled pivot row and the pivot column
+// are staged in rowk / colk (LDS, 64 each) first, so a step needs two
+// barriers.
+__device__ __forceinline__ void gauss_jordan_inverse(double (*M)[65], int n, double *rowk, double *colk)
+{
+  for (int k = 0; k < n; ++k) {
+    const double piv = 1.0 / M[k][k];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      rowk[j] = M[k][j] * piv;
+      colk[j] = M[j][k];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      if (i == k) M[i][j] = j == k ? piv : rowk[j];
+      else if (j == k) M[i][j] = -colk[i] * piv;
+      else M[i][j] -= colk[i] * rowk[j];
+    }
+    __syncthreads();
+  }
+}
+
 // van Leer (1974) correction to the upwind face value: with a = phi_C - phi_U and
 // b = phi_D - phi_C the face value is phi_C + a b / (a + b) when a b > 0, else phi_C.
 __device__ __forceinline__ double vanleer_corr(double pu, double pc, double pd)

@@ -189,22 +189,9 @@ __global__ void __launch_bounds__(TPB) k_mg_coarse_inverse(MgLevel<R> L, int nd,
     M[i][j] *= sc[i] * sc[j];
   }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double piv = 1.0 / M[k][k];
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += blockDim.x)
-      if (j != k) M[k][j] *= piv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int i = e / n, j = e % n;
-      if (i != k && j != k) M[i][j] -= M[i][k] * M[k][j];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-      if (i != k) M[i][k] = -M[i][k] * piv;
-    __syncthreads();
-    if (threadIdx.x == 0) M[k][k] = piv;
-    __syncthreads();
+  {
+    __shared__ double rowk[MG_COARSE_MAX], colk[MG_COARSE_MAX];
+    gauss_jordan_inverse(M, n, rowk, colk);
   }
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
