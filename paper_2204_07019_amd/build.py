@@ -15,7 +15,7 @@ SOURCES = ["vos_api.hip", "vos_unet.hip", "vos_batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed-FP32 instructions stay off
+    # no packed-FP32 instructions: the compiler would otherwise pair scalar FP32 operations
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

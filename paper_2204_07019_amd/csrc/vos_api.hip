@@ -728,7 +728,7 @@ template <typename R>
 void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, const double *dsc,
                 hipStream_t st)
 {
-  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.7, dsc, 1.0, sweeps(s, h), st);
+  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.85, dsc, 1.0, sweeps(s, h), st);
 }
 
 // ---------------------------------------------------------------- stage S2
@@ -1373,7 +1373,7 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
   int lc = 0;
   while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
   const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
-  const R om = (R)0.7;
+  const R om = (R)0.85;
   const double Rs = sizeof(R);
   double per_seq_bytes = 0.0;
   int per_seq_launches = 0;
