@@ -39,10 +39,11 @@ P_ITER_BYTES = {("mixed", 2): 136 + 83, ("fp64", 2): 136 + 144,
 # Krylov iterations per captured chunk on the micromodel (its solves take 7-27
 # iterations; longer chunks launch more kernels that only find the flag set).
 CHECK_EVERY = 4
-# Pressure and transport solves start from the linear extrapolation 2 x^n - x^(n-1)
-# of the last two steps (vos_opts.extrapolate); the start-from-x^n rate is reported
-# beside it.
-EXTRAPOLATE = 1
+# The solves start from an extrapolation of the last steps' solutions
+# (vos_opts.extrapolate = 2: 2 x^n - x^(n-1), or 3 x^n - 3 x^(n-1) + x^(n-2) where
+# that order predicted the last solution better); the start-from-x^n rate is
+# reported beside it.
+EXTRAPOLATE = 2
 # Solid-frozen steps after the flow is rescaled to the target Pe (setup_sim).
 SETUP_STEPS = 3
 # Per-step pressure setup (hierarchy build, right-hand side, initial residual):
@@ -323,7 +324,7 @@ def learned_3d(vos, inputs, n, dt, snapshots=60, iters=400, steps=10):
            "collect_s": round(t_collect, 2), "train_s": round(t_train, 2)}
     for name, prec, learned, ex in (("plain_fp64", vos.FP64, False, 0), ("mixed", vos.MIXED, False, 0),
                                     ("mixed_learned", vos.MIXED, True, 0),
-                                    ("mixed_extrapolated", vos.MIXED, False, 1)):
+                                    ("mixed_extrapolated", vos.MIXED, False, EXTRAPOLATE)):
         s = make(prec, ex)
         for k, v in state.items():
             s.set(k, v)
@@ -521,7 +522,9 @@ def main():
         "config": {"workload": f"{args.workload} {nx}x{ny}x{nz} dx=5um RSA discs seed 11, iVoS, "
                                f"Pe={args.pe:g} Da={args.da:g}, dt={args.dt:g}s, rtol 1e-8",
                    "precision": "mixed", "cells": cells,
-                   "solver_starts": "extrapolated 2x^n - x^(n-1)" if EXTRAPOLATE else "x^n"},
+                   "solver_starts": {0: "x^n", 1: "extrapolated 2x^n - x^(n-1)",
+                                     2: "extrapolated 2x^n - x^(n-1) or 3x^n - 3x^(n-1) + x^(n-2), "
+                                        "the order that predicted x^n better"}[EXTRAPOLATE]},
         "pressure_solve": {"GBs_algorithmic": round(p_gbs, 1), "frac_hbm": round(p_gbs / HBM_PEAK_GBS, 4),
                            "its_per_step": its_p / len(diags), "ms_per_step": t_p / len(diags) * 1e3},
         "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)],

@@ -124,6 +124,10 @@ typedef struct {
                        that history exists again after vos_create, vos_set_field,
                        vos_set_solid_fraction or vos_set_params; the pressure keeps p^n while
                        a warm-start network is attached); right-hand sides are unchanged.
+                       2: as 1, but a solve starts from the quadratic extrapolation
+                       3 x^n - 3 x^(n-1) + x^(n-2) whenever, at its previous start, the
+                       quadratic prediction of x^n from the three solutions before it was
+                       closer to x^n than the linear one (decided on the device).
                        0: start from x^n (u^n). */
 } vos_opts;
 

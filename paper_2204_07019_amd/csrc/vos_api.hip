@@ -148,6 +148,7 @@ int mg_hierarchy(const vos_grid &g, LevelDims *out)
 }
 
 constexpr int NVEC = 10;
+constexpr int NHIST = 3;  // earlier solutions kept per solve for extrapolated starts
 constexpr int NSMG = 4;   // stencil hierarchies: momentum x, y, z; transport
 
 struct SmgPlan {
@@ -158,8 +159,9 @@ struct SmgPlan {
 };
 
 struct Layout {
-  size_t uprev[3];
-  size_t eps, p, c, pn, cold, cprev, pprev, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
+  size_t uprev[3][NHIST];
+  size_t cprev[NHIST], pprev[NHIST];
+  size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
   size_t vec[NVEC];
   size_t part, part2, part_max, scal, ainv;
   size_t mgT[MG_MAX_LEVELS][3], mgdiag[MG_MAX_LEVELS], mgx[MG_MAX_LEVELS], mgb[MG_MAX_LEVELS], mgt[MG_MAX_LEVELS];
@@ -168,7 +170,7 @@ struct Layout {
   size_t total;
 };
 
-constexpr int NSC = 8;  // scalar blocks: mom x/y/z, pressure, transport, misc, diag, spare
+constexpr int NSC = 9;  // scalar blocks: mom x/y/z, pressure, transport, misc, diag, warm start, extrapolation
 // Iterations without the residual halving after which a mixed-precision
 // pressure solve continues with the FP64 hierarchy.
 constexpr int P_STALL_WINDOW = 400;
@@ -205,8 +207,10 @@ Layout make_layout(const vos_grid &g, int precision)
   Lo.c = P.take(nc * dbl);
   Lo.pn = P.take(nc * dbl);
   Lo.cold = P.take(nc * dbl);
-  Lo.cprev = P.take(nc * dbl);   // last step's solutions, for extrapolated starts
-  Lo.pprev = P.take(nc * dbl);
+  for (int k = 0; k < NHIST; ++k) {   // earlier steps' solutions, for extrapolated starts
+    Lo.cprev[k] = P.take(nc * dbl);
+    Lo.pprev[k] = P.take(nc * dbl);
+  }
   Lo.rbar = P.take(nc * dbl);
   Lo.gmag = P.take(nc * dbl);
   for (int d = 0; d < 3; ++d) Lo.nrm[d] = P.take(nc * dbl);
@@ -221,7 +225,7 @@ Layout make_layout(const vos_grid &g, int precision)
     Lo.af[d] = P.take(D0.nf[d] * dbl);
     Lo.T[d] = P.take(D0.nf[d] * dbl);
     Lo.w[d] = P.take(D0.nf[d] * dbl);
-    Lo.uprev[d] = P.take(D0.nf[d] * dbl);   // the predictor of the step before (extrapolated starts)
+    for (int k = 0; k < NHIST; ++k) Lo.uprev[d][k] = P.take(D0.nf[d] * dbl);   // earlier predictors
   }
   for (int k = 0; k < NVEC; ++k) Lo.vec[k] = P.take(nmax * dbl);
   Lo.part = P.take((size_t)NSLOT * MAXB * dbl);
@@ -307,10 +311,12 @@ struct vos_sim {
   int it_p_fp64;            // iterations of the last pressure solve run with the FP64 hierarchy (mixed)
   bool p_fp64_sticky;       // an FP32 pressure solve stalled on the current geometry (mixed)
   int nu_mom;               // sweeps per leg of the momentum hierarchies
-  double *cprev, *pprev;    // c and p of the previous step (extrapolated starts)
-  bool hist_c, hist_p;      // they hold a solution of this state's history
-  double *uprev[3];         // momentum predictors of the step before
-  int hist_u[3];            // 0: no predictor of this history, 1: ustar holds one, 2: uprev too
+  // extrapolated starts: the solutions of earlier steps, newest first (the host
+  // rotates the buffers), and how many of them belong to the current history
+  double *cprev[NHIST], *pprev[NHIST];
+  int hist_c, hist_p;
+  double *uprev[3][NHIST];  // earlier momentum predictors
+  int hist_u[3];            // 0: no predictor of this history, 1: ustar holds one, k > 1: k - 1 earlier ones too
   // two lanes for the momentum components, each with its own stream (created back to
   // back, so they land on different hardware queues), Krylov vectors, partials and
   // pinned read-back buffer; component 1 is driven from a second host thread
@@ -323,7 +329,7 @@ struct vos_sim {
 namespace {
 
 double *sc_block(vos_sim *s, int k) { return s->scal + (size_t)k * S_COUNT * 2; }
-enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6, SC_WS = 7 };
+enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6, SC_WS = 7, SC_EX = 8 };
 
 template <typename R>
 void fill_levels(vos_sim *s, MgLevel<R> *lv)
@@ -387,7 +393,7 @@ vos_status check_opts(const vos_opts *o)
     return fail(VOS_ERR_ARG, "coarse_cells must be 0 or in [64, 65536]");
   if (o->level_kernels != 0 && o->level_kernels != 1) return fail(VOS_ERR_ARG, "level_kernels must be 0 or 1");
   if (o->p_fp32_its < 0) return fail(VOS_ERR_ARG, "p_fp32_its must be >= 0");
-  if (o->extrapolate != 0 && o->extrapolate != 1) return fail(VOS_ERR_ARG, "extrapolate must be 0 or 1");
+  if (o->extrapolate < 0 || o->extrapolate > 2) return fail(VOS_ERR_ARG, "extrapolate must be 0, 1 or 2");
   return VOS_OK;
 }
 
@@ -505,14 +511,63 @@ void drop_graphs(vos_sim *s)
 
 // Start of a solve from the linear extrapolation in time of the last two
 // solutions: x = 2 x^n - x^(n-1) when have_prev, and prev = x^n either way.
-__global__ void __launch_bounds__(TPB) k_extrap(unsigned n, int have_prev, double *__restrict__ x,
-                                                double *__restrict__ prev)
+// Start of the next solve from x = x^n and the earlier solutions h[0] =
+// x^(n-1), h[1] = x^(n-2), h[2] = x^(n-3), hist of them valid: x^n (hist 0),
+// the linear extrapolation 2 x^n - x^(n-1), or, when quad is allowed and the
+// flag says the quadratic one predicted x^n better, 3 x^n - 3 x^(n-1) +
+// x^(n-2).  Partials: squared errors of the linear (hist >= 2) and quadratic
+// (hist >= 3) predictions of x^n.  x^n is stored over h[2], the buffer the
+// host then rotates to the front.
+__global__ void __launch_bounds__(TPB) k_extrap(unsigned n, int hist, int quad_ok, const double *__restrict__ flag,
+                                                double *__restrict__ x, const double *__restrict__ h0,
+                                                const double *__restrict__ h1, double *__restrict__ h2,
+                                                double *__restrict__ part)
 {
+  const bool quad = quad_ok && hist >= 2 && flag[0] != 0.0;
+  double e1 = 0.0, e2 = 0.0;
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
-    const double xn = x[i];
-    if (have_prev) x[i] = 2.0 * xn - prev[i];
-    prev[i] = xn;
+    const double xn = x[i], a = h0[i], b = h1[i], c = h2[i];
+    double st = xn;
+    if (hist >= 1) st = quad ? 3.0 * xn - 3.0 * a + b : 2.0 * xn - a;
+    x[i] = st;
+    h2[i] = xn;
+    if (hist >= 2) {
+      const double d = xn - (2.0 * a - b);
+      e1 += d * d;
+    }
+    if (hist >= 3) {
+      const double d = xn - (3.0 * a - 3.0 * b + c);
+      e2 += d * d;
+    }
   }
+  const double v[2] = {e1, e2};
+  write_partials<2>(v, part);
+}
+
+// The order of the next extrapolated start: quadratic (flag 1) when it
+// predicted the newest solution better than the linear one did.
+__global__ void k_extrap_order(const double *__restrict__ part, int nb, int hist, double *__restrict__ flag)
+{
+  const double e1 = sum_partials(part, 0, nb);
+  const double e2 = sum_partials(part, 1, nb);
+  if (threadIdx.x == 0) flag[0] = (hist >= 3 && e2 < e1) ? 1.0 : 0.0;
+}
+
+// Extrapolated start of x over the history h (hist valid entries, newest
+// first); rotates h so that h[0] = the old x; *hist grows to at most NHIST.
+// Slot f of the extrapolation scalar block keeps the order chosen for field f.
+void extrapolate(vos_sim *s, hipStream_t st, double *part, unsigned n, double *x, double **h, int *hist, int f)
+{
+  const int nb = grid_blocks(n);
+  double *flag = sc_block(s, SC_EX) + f;
+  const int quad = s->opt.extrapolate == 2;
+  k_extrap<<<nb, TPB, 0, st>>>(n, *hist, quad, flag, x, h[0], h[1], h[2], part);
+  if (quad) k_extrap_order<<<1, TPB, 0, st>>>(part, nb, *hist, flag);
+  double *t = h[2];
+  h[2] = h[1];
+  h[1] = h[0];
+  h[0] = t;
+  *hist = std::min(NHIST, *hist + 1);
 }
 
 // q = A x (pressure operator) with the partials of x.q in s->part; returns
@@ -747,9 +802,13 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
   double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
   const double cvis = s->P.mu / (g.dx * g.dx);
   const double rt2 = s->opt.rtol_u * s->opt.rtol_u;
-  // start: u^n, or the last predictor (then 2 u*^n - u*^(n-1)) with extrapolated starts
+  // start: u^n, or with extrapolated starts the last predictor extrapolated
+  // over the earlier ones
   const bool ex = s->opt.extrapolate && s->hist_u[D] >= 1;
-  if (ex) k_extrap<<<nb, TPB, 0, st>>>(n, s->hist_u[D] >= 2 ? 1 : 0, x, s->uprev[D]);
+  if (ex) {
+    int h = s->hist_u[D] - 1;
+    extrapolate(s, st, part, n, x, s->uprev[D], &h, D);
+  }
   k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x, ex ? 0 : 1);
   k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);   // Jacobi-scaled
   smg_coarsen_all<R>(s, D, lv, st);
@@ -775,7 +834,7 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
   vos_status stt = krylov_loop(s, ln, D, sc, s->opt.maxit_u, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
   k_mom_fix<D><<<nb, TPB, 0, st>>>(g, s->P.u_in, x);
-  if (s->opt.extrapolate && conv) s->hist_u[D] = std::min(2, s->hist_u[D] + 1);
+  if (s->opt.extrapolate) s->hist_u[D] = conv ? std::min(NHIST + 1, s->hist_u[D] + 1) : 0;
   const double bn2 = ln.host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "momentum predictor did not converge");
@@ -1031,8 +1090,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, doubl
   mg_setup<R>(s, lv);
   HIP_TRY(hipMemcpyAsync(s->pn, s->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (s->opt.extrapolate && !s->net) {   // the start only; the right-hand side keeps p^n (pn)
-    k_extrap<<<nb, TPB, 0, st>>>(n, s->hist_p ? 1 : 0, s->p, s->pprev);
-    s->hist_p = true;
+    extrapolate(s, st, s->part, n, s->p, s->pprev, &s->hist_p, 3);
   }
   k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b);
   if (s->net)
@@ -1139,8 +1197,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   const double rt2 = s->opt.rtol_c * s->opt.rtol_c;
   HIP_TRY(hipMemcpyAsync(s->cold, s->c, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (s->opt.extrapolate) {   // the start only; the deferred correction keeps c^n (cold)
-    k_extrap<<<nb, TPB, 0, st>>>(n, s->hist_c ? 1 : 0, s->c, s->cprev);
-    s->hist_c = true;
+    extrapolate(s, st, s->part, n, s->c, s->cprev, &s->hist_c, 4);
   }
   k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
                                      s->gmag, sc_block(s, SC_MISC), s->off, b, y);
@@ -1528,8 +1585,11 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   char *w = s->ws;
   auto D = [&](size_t o) { return (double *)(w + o); };
   s->eps = D(lo.eps); s->p = D(lo.p); s->c = D(lo.c); s->pn = D(lo.pn); s->cold = D(lo.cold);
-  s->cprev = D(lo.cprev); s->pprev = D(lo.pprev);
-  for (int d = 0; d < 3; ++d) s->uprev[d] = D(lo.uprev[d]);
+  for (int k = 0; k < NHIST; ++k) {
+    s->cprev[k] = D(lo.cprev[k]);
+    s->pprev[k] = D(lo.pprev[k]);
+    for (int d = 0; d < 3; ++d) s->uprev[d][k] = D(lo.uprev[d][k]);
+  }
   s->rbar = D(lo.rbar); s->gmag = D(lo.gmag); s->pdiag = D(lo.pdiag); s->off = D(lo.off);
   for (int d = 0; d < 3; ++d) {
     s->nrm[d] = D(lo.nrm[d]); s->u[d] = D(lo.u[d]); s->ustar[d] = D(lo.ustar[d]); s->dmom[d] = D(lo.dmom[d]);
@@ -1555,7 +1615,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->ws_res_prev = s->ws_res_guess = 0.0;
   s->it_p_fp64 = 0;
   s->p_fp64_sticky = false;
-  s->hist_c = s->hist_p = false;
+  s->hist_c = s->hist_p = 0;
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
@@ -1623,7 +1683,7 @@ vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device
   HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), st));
   k_set_eps<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, src, s->P.eps_min, s->eps, bad);
   s->p_fp64_sticky = false;   // a new geometry: mixed precision tries the FP32 hierarchy again
-  s->hist_c = s->hist_p = false;
+  s->hist_c = s->hist_p = 0;
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, s->P.u_in, s->u[0]);
   HIP_TRY(hipGetLastError());
@@ -1643,7 +1703,7 @@ vos_status vos_set_params(vos_sim *s, const vos_params *params)
   if (st) return st;
   s->prm = *params;
   drop_graphs(s);   // captured iterations hold mu / dx^2 by value
-  s->hist_c = s->hist_p = false;
+  s->hist_c = s->hist_p = 0;
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   Phys &P = s->P;
   P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
@@ -1663,7 +1723,7 @@ vos_status vos_set_field(vos_sim *s, int field, const double *src, int on_device
   double *d = field_ptr(s, field, &n, &wr);
   if (!d) return fail(VOS_ERR_ARG, "unknown field");
   if (!wr) return fail(VOS_ERR_ARG, "field is read-only");
-  s->hist_c = s->hist_p = false;
+  s->hist_c = s->hist_p = 0;
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   HIP_TRY(hipMemcpyAsync(d, src, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                          s->stream));

@@ -128,7 +128,7 @@ class Opts:
     coarse_cells: int = 0
     level_kernels: int = 0  # 0: fused fine-level multigrid kernels, 1: one plain kernel per sweep
     p_fp32_its: int = 0     # mixed: cap on FP32-preconditioned pressure iterations (0: stall detection only)
-    extrapolate: int = 0    # 1: solves start from 2 x^n - x^(n-1) of the last two steps
+    extrapolate: int = 0    # 1: solves start from 2 x^n - x^(n-1) of the last two steps; 2: adaptive quadratic
 
 
 class Sim:
