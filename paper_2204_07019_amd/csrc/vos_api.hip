@@ -627,7 +627,7 @@ void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv, hipStream_t st)
   const int L = s->snlev[h];
   for (int l = 0; l + 1 < L; ++l)
     k_smg_coarsen<R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
-  k_smg_coarse_inverse<R><<<1, TPB, 0, st>>>(lv[L - 1], nd, s->sainv[h]);
+  k_smg_coarse_inverse<R><<<1, GJ_TPB, 0, st>>>(lv[L - 1], nd, s->sainv[h]);
 }
 
 // Cells per thread on the first level of a coarse tail (levels lc..L-1) that
@@ -871,7 +871,7 @@ void mg_setup(vos_sim *s, MgLevel<R> *lv)
     k_mg_coarse_diag<R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
   }
   const MgLevel<R> &C = lv[s->nlev - 1];
-  if (C.nc <= (unsigned)MG_COARSE_MAX) k_mg_coarse_inverse<R><<<1, TPB, 0, st>>>(C, nd, s->ainv);
+  if (C.nc <= (unsigned)MG_COARSE_MAX) k_mg_coarse_inverse<R><<<1, GJ_TPB, 0, st>>>(C, nd, s->ainv);
 }
 
 template <typename R>

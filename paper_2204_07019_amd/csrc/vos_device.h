@@ -153,29 +153,57 @@ __device__ __forceinline__ double max_partials(const double *part, int q, int nb
 }
 
 // In-place Gauss-Jordan inverse of the n x n matrix M (n <= 64, in LDS, row
-// stride 65) without pivoting (the matrices are SPD), by the whole block.
-// Step k: piv = 1 / M[k][k]; row k is scaled by piv; every other element
-// takes M[i][j] - M[i][k] M[k][j] with the scaled row; column k becomes
-// -M[i][k] piv and M[k][k] = piv.  The scaled pivot row and the pivot column
-// are staged in rowk / colk (LDS, 64 each) first, so a step needs two
-// barriers.
-__device__ __forceinline__ void gauss_jordan_inverse(double (*M)[65], int n, double *rowk, double *colk)
+// stride 65) without pivoting (the matrices are SPD), by a block of
+// GJ_TPB threads.  Step k: piv = 1 / M[k][k]; row k is scaled by piv; every other
+// element takes M[i][j] - M[i][k] (M[k][j] piv); column k becomes
+// -M[i][k] piv and M[k][k] = piv.  Every thread keeps its own elements in
+// registers for all steps; only the pivot row and column travel through LDS
+// (rowk / colk, 2 x 64 each, double-buffered: the threads that update row and
+// column k + 1 in step k publish them for step k + 1), so a step needs one
+// barrier.
+// A block of 1024 threads: one to four elements per thread, so the few waves
+// of this single-block kernel do little work each between barriers.
+constexpr int GJ_TPB = 1024;
+__device__ __forceinline__ void gauss_jordan_inverse(double (*M)[65], int n, double (*rowk)[64], double (*colk)[64])
 {
-  for (int k = 0; k < n; ++k) {
-    const double piv = 1.0 / M[k][k];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      rowk[j] = M[k][j] * piv;
-      colk[j] = M[j][k];
+  constexpr int PER = (64 * 64 + GJ_TPB - 1) / GJ_TPB;
+  double v[PER];
+  int ei[PER], ej[PER];
+  const int nn = n * n;
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = min((int)threadIdx.x + m * GJ_TPB, nn - 1);
+    ei[m] = e / n;
+    ej[m] = e - ei[m] * n;
+    v[m] = M[ei[m]][ej[m]];
+    if ((int)threadIdx.x + m * GJ_TPB < nn) {
+      if (ei[m] == 0) rowk[0][ej[m]] = v[m];
+      if (ej[m] == 0) colk[0][ei[m]] = v[m];
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int i = e / n, j = e % n;
-      if (i == k) M[i][j] = j == k ? piv : rowk[j];
-      else if (j == k) M[i][j] = -colk[i] * piv;
-      else M[i][j] -= colk[i] * rowk[j];
-    }
-    __syncthreads();
   }
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    const double *rk = rowk[k & 1], *ck = colk[k & 1];
+    double *rn = rowk[(k + 1) & 1], *cn = colk[(k + 1) & 1];
+    const double piv = 1.0 / rk[k];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      if ((int)threadIdx.x + m * GJ_TPB >= nn) continue;
+      const int i = ei[m], j = ej[m];
+      double x = v[m];
+      if (i == k) x = j == k ? piv : rk[j] * piv;
+      else if (j == k) x = -ck[i] * piv;
+      else x -= ck[i] * (rk[j] * piv);
+      v[m] = x;
+      if (i == k + 1) rn[j] = x;
+      if (j == k + 1) cn[i] = x;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < PER; ++m)
+    if ((int)threadIdx.x + m * GJ_TPB < nn) M[ei[m]][ej[m]] = v[m];
+  __syncthreads();
 }
 
 // van Leer (1974) correction to the upwind face value: with a = phi_C - phi_U and

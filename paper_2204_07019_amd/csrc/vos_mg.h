@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(TPB) k_mg_coarsen(MgLevel<R> F, MgLevel<R> Cc,
 // Dense inverse of the coarsest operator (n <= 64), FP64, one block: build
 // A, scale to unit diagonal, Gauss-Jordan in place (SPD: no pivoting), unscale.
 template <typename R>
-__global__ void __launch_bounds__(TPB) k_mg_coarse_inverse(MgLevel<R> L, int nd, double *__restrict__ Ainv)
+__global__ void __launch_bounds__(GJ_TPB) k_mg_coarse_inverse(MgLevel<R> L, int nd, double *__restrict__ Ainv)
 {
   __shared__ double M[MG_COARSE_MAX][MG_COARSE_MAX + 1];
   __shared__ double sc[MG_COARSE_MAX];
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(TPB) k_mg_coarse_inverse(MgLevel<R> L, int nd,
   }
   __syncthreads();
   {
-    __shared__ double rowk[MG_COARSE_MAX], colk[MG_COARSE_MAX];
+    __shared__ double rowk[2][64], colk[2][64];
     gauss_jordan_inverse(M, n, rowk, colk);
   }
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {

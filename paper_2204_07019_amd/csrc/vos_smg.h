@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, i
 // scaled by the diagonal first (M = D^-1 A); the operators here are
 // diagonally dominant, so Gauss-Jordan needs no pivoting; Ainv = M^-1 D^-1.
 template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_coarse_inverse(SLevel<R> L, int nd, double *__restrict__ Ainv)
+__global__ void __launch_bounds__(GJ_TPB) k_smg_coarse_inverse(SLevel<R> L, int nd, double *__restrict__ Ainv)
 {
   __shared__ double M[SMG_COARSE_MAX][SMG_COARSE_MAX + 1];
   __shared__ double rs[SMG_COARSE_MAX];
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(TPB) k_smg_coarse_inverse(SLevel<R> L, int nd,
   }
   __syncthreads();
   {
-    __shared__ double rowk[SMG_COARSE_MAX], colk[SMG_COARSE_MAX];
+    __shared__ double rowk[2][64], colk[2][64];
     gauss_jordan_inverse(M, n, rowk, colk);
   }
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
