@@ -44,6 +44,10 @@ CHECK_EVERY = 4
 # that order predicted the last solution better); the start-from-x^n rate is
 # reported beside it.
 EXTRAPOLATE = 2
+# The multigrid hierarchies are rebuilt every second step (vos_opts.setup_every);
+# a solve in between is preconditioned with the previous step's hierarchy and
+# still meets its tolerance.
+SETUP_EVERY = 2
 # Solid-frozen steps after the flow is rescaled to the target Pe (setup_sim).
 SETUP_STEPS = 3
 # Per-step pressure setup (hierarchy build, right-hand side, initial residual):
@@ -60,7 +64,7 @@ def setup_sim(vos, inputs, scaling, workload, pe, da, precision, model, dt, rela
     nz, ny, nx = es.shape
     params = dict(prm, model=model)
     opts = vos.Opts(precision=precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=CHECK_EVERY,
-                    extrapolate=extrapolate)
+                    extrapolate=extrapolate, setup_every=SETUP_EVERY)
     sim = vos.Sim(nx, ny, nz, prm["dx"], dict(params, kc=0.0), opts)
     sim.set_solid_fraction(es)
     d = None
@@ -191,7 +195,7 @@ def batch_bench(vos, inputs, scaling, n, steps, dt, seed=2, relax=5):
     base = dict(inputs.BASE_PARAMS, model=0)
     specs = [(BATCH_SIZES[k][0], BATCH_SIZES[k][1], 1, 5e-6, dict(base, kc=0.0)) for k in picks]
     opts = vos.Opts(precision=vos.MIXED, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=8,
-                    extrapolate=EXTRAPOLATE)
+                    extrapolate=EXTRAPOLATE, setup_every=SETUP_EVERY)
     b = Batch(specs, opts)
     for i, (nx, ny, *_rest) in enumerate(specs):
         b.sims[i].set_solid_fraction(inputs.rsa_discs(nx, ny, seed=100 + i))
@@ -458,7 +462,7 @@ def main():
         for prec, ex in ((vos.FP64, EXTRAPOLATE), (vos.MIXED, 0)):
             sim2 = vos.Sim(nx, ny, nz, inputs.workload(args.workload)[1]["dx"], params,
                            vos.Opts(precision=prec, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8,
-                                    check_every=CHECK_EVERY, extrapolate=ex))
+                                    check_every=CHECK_EVERY, extrapolate=ex, setup_every=SETUP_EVERY))
             for k in ("eps", "ux", "uy", "uz", "p", "c"):
                 sim2.set(k, sim.get(k))
             # as many steps before the timed ones as the headline simulation had since
@@ -524,7 +528,8 @@ def main():
                    "precision": "mixed", "cells": cells,
                    "solver_starts": {0: "x^n", 1: "extrapolated 2x^n - x^(n-1)",
                                      2: "extrapolated 2x^n - x^(n-1) or 3x^n - 3x^(n-1) + x^(n-2), "
-                                        "the order that predicted x^n better"}[EXTRAPOLATE]},
+                                        "the order that predicted x^n better"}[EXTRAPOLATE],
+                   "multigrid_setup_every_steps": SETUP_EVERY},
         "pressure_solve": {"GBs_algorithmic": round(p_gbs, 1), "frac_hbm": round(p_gbs / HBM_PEAK_GBS, 4),
                            "its_per_step": its_p / len(diags), "ms_per_step": t_p / len(diags) * 1e3},
         "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)],

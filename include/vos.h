@@ -129,6 +129,14 @@ typedef struct {
                        quadratic prediction of x^n from the three solutions before it was
                        closer to x^n than the linear one (decided on the device).
                        0: start from x^n (u^n). */
+  int setup_every;  /* the momentum and pressure multigrid hierarchies (coarse operators and
+                       coarsest inverses) are rebuilt every this many steps and after every
+                       state change
+                       (vos_set_solid_fraction, vos_set_params, vos_set_field, a new time step
+                       size); in between, a solve is preconditioned with the hierarchy of an
+                       earlier step.  The Krylov iteration always applies the current operator,
+                       so every solve still meets its tolerance.  The transport hierarchy is
+                       rebuilt every step.  0 or 1: every step; <= 1000. */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */

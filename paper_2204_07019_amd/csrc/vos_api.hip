@@ -317,6 +317,10 @@ struct vos_sim {
   int hist_c, hist_p;
   double *uprev[3][NHIST];  // earlier momentum predictors
   int hist_u[3];            // 0: no predictor of this history, 1: ustar holds one, k > 1: k - 1 earlier ones too
+  // momentum and pressure hierarchies rebuilt every setup_every solves; solves since each
+  // was built: 0-2 momentum, 4 pressure, 5 the mixed pressure's FP64 one after a stall
+  int setup_every;
+  int mg_age[6];
   // two lanes for the momentum components, each with its own stream (created back to
   // back, so they land on different hardware queues), Krylov vectors, partials and
   // pinned read-back buffer; component 1 is driven from a second host thread
@@ -330,6 +334,21 @@ namespace {
 
 double *sc_block(vos_sim *s, int k) { return s->scal + (size_t)k * S_COUNT * 2; }
 enum { SC_MOM = 0, SC_P = 3, SC_C = 4, SC_MISC = 5, SC_DIAG = 6, SC_WS = 7, SC_EX = 8 };
+enum { H_MOM = 0, H_P = 4, H_P64 = 5 };
+
+// Whether hierarchy h is rebuilt for this solve (it is once setup_every solves
+// have used it, and after any state change); counts the solve.
+bool hierarchy_due(vos_sim *s, int h)
+{
+  const bool due = s->mg_age[h] >= s->setup_every;
+  s->mg_age[h] = due ? 1 : s->mg_age[h] + 1;
+  return due;
+}
+
+void hierarchies_stale(vos_sim *s)
+{
+  for (int h = 0; h < 6; ++h) s->mg_age[h] = 1 << 30;
+}
 
 template <typename R>
 void fill_levels(vos_sim *s, MgLevel<R> *lv)
@@ -394,6 +413,7 @@ vos_status check_opts(const vos_opts *o)
   if (o->level_kernels != 0 && o->level_kernels != 1) return fail(VOS_ERR_ARG, "level_kernels must be 0 or 1");
   if (o->p_fp32_its < 0) return fail(VOS_ERR_ARG, "p_fp32_its must be >= 0");
   if (o->extrapolate < 0 || o->extrapolate > 2) return fail(VOS_ERR_ARG, "extrapolate must be 0, 1 or 2");
+  if (o->setup_every < 0 || o->setup_every > 1000) return fail(VOS_ERR_ARG, "setup_every must be in [0, 1000]");
   return VOS_OK;
 }
 
@@ -810,8 +830,10 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
     extrapolate(s, st, part, n, x, s->uprev[D], &h, D);
   }
   k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x, ex ? 0 : 1);
-  k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);   // Jacobi-scaled
-  smg_coarsen_all<R>(s, D, lv, st);
+  if (hierarchy_due(s, H_MOM + D)) {
+    k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);   // Jacobi-scaled
+    smg_coarsen_all<R>(s, D, lv, st);
+  }
   k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, part, zero_flag);
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 0, part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, part, nb, rt2, sc);
@@ -1077,7 +1099,7 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double
 }
 
 template <typename R>
-vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, double *res)
+vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int h, int *its, double *res)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
@@ -1087,7 +1109,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, doubl
   double *sc = sc_block(s, SC_P);
   double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
   const double rt2 = s->opt.rtol_p * s->opt.rtol_p;
-  mg_setup<R>(s, lv);
+  if (hierarchy_due(s, h)) mg_setup<R>(s, lv);
   HIP_TRY(hipMemcpyAsync(s->pn, s->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (s->opt.extrapolate && !s->net) {   // the start only; the right-hand side keeps p^n (pn)
     extrapolate(s, st, s->part, n, s->p, s->pprev, &s->hist_p, 3);
@@ -1129,6 +1151,8 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int *its, doubl
     // continue the same flexible CG with an FP64 hierarchy built over the FP32 one's memory
     // (the next solve rebuilds the FP32 hierarchy)
     mg_setup<double>(s, s->mgd);
+    s->mg_age[H_P64] = 1;
+    s->mg_age[H_P] = 1 << 30;
     auto iter64 = [&]() {
       const int nbq = p_apply(s, pv, q, sc);
       k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nbq, rt2, sc);
@@ -1165,8 +1189,9 @@ vos_status solve_pressure(vos_sim *s, int *its, double *res)
 {
   // mixed precision: the FP32 hierarchy until one of its solves stalls on this geometry, then
   // FP64 (its iteration chunk captured under its own graph slot)
-  if (s->opt.precision == VOS_MIXED && !s->p_fp64_sticky) return solve_pressure_t<float>(s, s->mgf, 3, its, res);
-  return solve_pressure_t<double>(s, s->mgd, s->opt.precision == VOS_MIXED ? 5 : 3, its, res);
+  if (s->opt.precision == VOS_MIXED && !s->p_fp64_sticky) return solve_pressure_t<float>(s, s->mgf, 3, H_P, its, res);
+  const bool mixed = s->opt.precision == VOS_MIXED;
+  return solve_pressure_t<double>(s, s->mgd, mixed ? 5 : 3, mixed ? H_P64 : H_P, its, res);
 }
 
 // ---------------------------------------------------------------- stage S4
@@ -1201,6 +1226,8 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   }
   k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
                                      s->gmag, sc_block(s, SC_MISC), s->off, b, y);
+  // rebuilt every step: a transport hierarchy one step old can stall BiCGStab on
+  // strongly reactive instances (Da ~ 1), where the rows change most between steps
   k_smg_from_scaled<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, lv[0]);
   smg_coarsen_all<R>(s, H, lv, st);
   k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
@@ -1304,7 +1331,11 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   vos_status rc = VOS_OK, r2;
   HIP_TRY(hipEventRecord(s->ev[0], st));
   const double ps = pressure_scale(s, dt);
-  if (ps != s->p_scale) { drop_graphs(s); s->p_scale = ps; }   // captured V-cycles hold 1/p_scale
+  if (ps != s->p_scale) {   // captured V-cycles and the pressure hierarchy hold 1/p_scale
+    drop_graphs(s);
+    s->p_scale = ps;
+    s->mg_age[H_P] = s->mg_age[H_P64] = 1 << 30;
+  }
   launch_coefficients(s, dt);
   HIP_TRY(hipEventRecord(s->ev[1], st));
   // The momentum components are independent systems: components 0 (then 2)
@@ -1616,6 +1647,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->it_p_fp64 = 0;
   s->p_fp64_sticky = false;
   s->hist_c = s->hist_p = 0;
+  hierarchies_stale(s);
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
@@ -1648,6 +1680,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   if (s->opt.mg_nu == 0) s->opt.mg_nu = grid->nz == 1 ? 4 : 2;
   s->nu_mom = opts->mg_nu == 0 ? 2 : opts->mg_nu;
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? VC_TAIL_2D : VC_BLOCK_MAX);
+  s->setup_every = std::max(1, opts->setup_every);
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
 
@@ -1684,6 +1717,7 @@ vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device
   k_set_eps<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, src, s->P.eps_min, s->eps, bad);
   s->p_fp64_sticky = false;   // a new geometry: mixed precision tries the FP32 hierarchy again
   s->hist_c = s->hist_p = 0;
+  hierarchies_stale(s);
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, s->P.u_in, s->u[0]);
   HIP_TRY(hipGetLastError());
@@ -1704,6 +1738,7 @@ vos_status vos_set_params(vos_sim *s, const vos_params *params)
   s->prm = *params;
   drop_graphs(s);   // captured iterations hold mu / dx^2 by value
   s->hist_c = s->hist_p = 0;
+  hierarchies_stale(s);
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   Phys &P = s->P;
   P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
@@ -1724,6 +1759,7 @@ vos_status vos_set_field(vos_sim *s, int field, const double *src, int on_device
   if (!d) return fail(VOS_ERR_ARG, "unknown field");
   if (!wr) return fail(VOS_ERR_ARG, "field is read-only");
   s->hist_c = s->hist_p = 0;
+  hierarchies_stale(s);
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   HIP_TRY(hipMemcpyAsync(d, src, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                          s->stream));

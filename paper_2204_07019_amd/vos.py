@@ -50,7 +50,7 @@ class _Opts(C.Structure):
                 ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
                 ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int),
                 ("use_graphs", C.c_int), ("coarse_cells", C.c_int), ("level_kernels", C.c_int),
-                ("p_fp32_its", C.c_int), ("extrapolate", C.c_int)]
+                ("p_fp32_its", C.c_int), ("extrapolate", C.c_int), ("setup_every", C.c_int)]
 
 
 class _Diag(C.Structure):
@@ -129,6 +129,7 @@ class Opts:
     level_kernels: int = 0  # 0: fused fine-level multigrid kernels, 1: one plain kernel per sweep
     p_fp32_its: int = 0     # mixed: cap on FP32-preconditioned pressure iterations (0: stall detection only)
     extrapolate: int = 0    # 1: solves start from 2 x^n - x^(n-1) of the last two steps; 2: adaptive quadratic
+    setup_every: int = 0    # rebuild the multigrid hierarchies every this many steps (0, 1: every step)
 
 
 class Sim:

@@ -75,18 +75,20 @@ def test_post_20_steps(orc, precision):
     assert dg["solid_rate"] == pytest.approx(do["solid_rate"], rel=1e-6)
 
 
-@pytest.mark.parametrize("extrapolate", [1, 2])
+@pytest.mark.parametrize("extrapolate,setup_every", [(1, 1), (2, 1), (2, 3)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_extrapolated_starts_match_oracle(orc, precision, extrapolate):
+def test_extrapolated_starts_match_oracle(orc, precision, extrapolate, setup_every):
     """Solves started from 2 x^n - x^(n-1) (extrapolate 1) or, where it
-    predicted better, 3 x^n - 3 x^(n-1) + x^(n-2) (extrapolate 2): 12 post
-    steps within 1e-6 of the oracle, and the extrapolated starts do not skip
-    the solves (every step still iterates)."""
+    predicted better, 3 x^n - 3 x^(n-1) + x^(n-2) (extrapolate 2), also with
+    the multigrid hierarchies rebuilt only every third step: 12 post steps
+    within 1e-6 of the oracle, and the extrapolated starts do not skip the
+    solves (every step still iterates)."""
     from paper_2204_07019_amd import inputs
     es, prm = inputs.workload("post")
     prob = make_problem(es, prm, model=0, **TIGHT)
-    _say(f"post 256x64 extrapolate {extrapolate} precision {precision} 12 steps")
-    st, g, eps0, diags = run_both(es, prob, 1e-3, 12, precision=precision, extrapolate=extrapolate)
+    _say(f"post 256x64 extrapolate {extrapolate} setup_every {setup_every} precision {precision} 12 steps")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 12, precision=precision, extrapolate=extrapolate,
+                                  setup_every=setup_every)
     _compare(st, g, eps0)
     for _, dg in diags:
         assert dg["it_p"] >= 1 and dg["it_c"] >= 1, dg
@@ -193,6 +195,8 @@ LEVEL_CASES = [  # (shape, precision, extra options): 2-D tiled and 3-D marching
     ((96, 40, 1), 1, {"coarse_cells": 4096}),
     ((96, 40, 1), 0, {"coarse_cells": 4096, "extrapolate": 1}),
     ((96, 40, 1), 1, {"extrapolate": 2}),
+    ((96, 40, 1), 1, {"extrapolate": 2, "setup_every": 2}),
+    ((70, 12, 9), 1, {"coarse_cells": 64, "setup_every": 3}),
 ]
 
 
@@ -213,7 +217,7 @@ def test_level_kernels_bitwise(orc, shape, precision, extra):
     prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=5e-6), rtol_u=1e-9, rtol_p=1e-9, rtol_c=1e-9)
     out, its = [], []
     # quadratic starts need three earlier solutions and one step to compare the orders
-    steps = 7 if extra.get("extrapolate") == 2 else 3
+    steps = 7 if extra.get("extrapolate") == 2 or extra.get("setup_every", 1) > 1 else 3
     for lk in (0, 1):
         _say(f"level kernels {lk} {shape} precision {precision} {extra}")
         sim = gpu_sim(prob, precision, level_kernels=lk, **extra)
