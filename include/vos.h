@@ -100,7 +100,9 @@ typedef struct {
   int mg_nu;        /* Jacobi sweeps before and after each coarse correction of the pressure
                        and momentum hierarchies, 1..8; 0: pressure 4 and momentum 2 in 2-D,
                        2 in 3-D.  The transport hierarchy uses at most 2. */
-  int check_every;  /* Krylov iterations launched between host convergence checks, 1..256 */
+  int check_every;  /* Krylov iterations launched between host convergence checks, 1..256; the
+                       first check of a solve comes after as many such chunks as fit in the
+                       iterations the previous solve of the same system took */
   int use_graphs;   /* 1: capture each solve's chunk of check_every iterations in a HIP graph
                        once and replay it (iteration counts then round up to a multiple of
                        check_every in the worst case; results are identical); 0: plain launches.

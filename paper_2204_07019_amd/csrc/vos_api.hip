@@ -294,6 +294,7 @@ struct vos_sim {
   double p_scale;           // global scale of the pressure hierarchy (set per step)
   int coarse_cells;         // levels at or below this size run in the single-block kernel
   hipGraphExec_t gexec[8];  // one captured iteration chunk per solve
+  int last_its[8];          // iterations the last solve of each slot took (0: none yet)
 
   bool have_geometry;
   bool stepped;             // a step has run: the hierarchies hold live data
@@ -456,7 +457,9 @@ vos_status read_back(vos_sim *s, const double *dev, size_t n) { return read_back
 // Run iterations until the device flag says converged or maxit is reached.
 // With graphs on, a chunk of check_every iterations is captured once per
 // solve (gid) and replayed; every kernel in it returns at once after the flag
-// is set, so replaying a whole chunk past convergence changes nothing.
+// is set, so replaying a whole chunk past convergence changes nothing.  The
+// first host check comes after as many whole chunks as fit in the iterations
+// the last solve of the same slot took, later checks after every chunk.
 // Stall rule of a solve that may switch preconditioners: give up once the
 // residual has not halved within `window` iterations, or after `cap`
 // iterations (0: no cap).  window 0: never.
@@ -479,7 +482,8 @@ vos_status krylov_loop(vos_sim *s, const Lane &ln, int gid, double *sc, int maxi
   const int chunk = s->opt.check_every;
   double mark = HUGE_VAL;
   int mark_its = 0;
-  while (!done && launched < maxit) {
+  // one chunk of iterations: a replay of the captured graph, or plain launches
+  auto launch_chunk = [&]() -> vos_status {
     if (s->use_graphs) {
       if (!s->gexec[gid]) {
         hipGraph_t graph;
@@ -498,6 +502,13 @@ vos_status krylov_loop(vos_sim *s, const Lane &ln, int gid, double *sc, int maxi
       for (int i = 0; i < k; ++i) iter();
       launched += k;
     }
+    return VOS_OK;
+  };
+  int ahead = std::max(1, s->last_its[gid] / chunk);
+  while (!done && launched < maxit) {
+    for (int a = 0; a < ahead && launched < maxit; ++a)
+      if (vos_status e = launch_chunk()) return e;
+    ahead = 1;
     HIP_TRY(hipGetLastError());
     st = read_back(ln, sc, S_COUNT);
     if (st) return st;
@@ -517,6 +528,7 @@ vos_status krylov_loop(vos_sim *s, const Lane &ln, int gid, double *sc, int maxi
     }
   }
   *its = (int)host[S_ITS];
+  s->last_its[gid] = *its;
   *res2 = host[S_RES2];
   *tol2 = host[S_TOL2];
   *conv = (host[S_RES2] <= host[S_TOL2]) || (host[S_RES2] == 0.0);
@@ -1682,7 +1694,10 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? VC_TAIL_2D : VC_BLOCK_MAX);
   s->setup_every = std::max(1, opts->setup_every);
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
-  for (int k = 0; k < 8; ++k) s->gexec[k] = nullptr;
+  for (int k = 0; k < 8; ++k) {
+    s->gexec[k] = nullptr;
+    s->last_its[k] = 0;
+  }
 
   // initial state: fluid at rest, p = p_out, c = 0, eps = 1
   hipStream_t stq = s->stream;
