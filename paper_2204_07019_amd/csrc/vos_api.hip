@@ -155,12 +155,15 @@ struct SmgPlan {
   int nlev;
   int n[SMG_MAX_LEVELS][3];
   size_t off[SMG_MAX_LEVELS], diag[SMG_MAX_LEVELS], x[SMG_MAX_LEVELS], b[SMG_MAX_LEVELS], t[SMG_MAX_LEVELS];
+  size_t dif[SMG_MAX_LEVELS];   // diffusive parts (transport hierarchy only)
+  bool split;
   size_t ainv;
 };
 
 struct Layout {
   size_t uprev[3][NHIST];
   size_t cprev[NHIST], pprev[NHIST];
+  size_t tdiag, tdif;
   size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
   size_t vec[NVEC];
   size_t part, part2, part_max, scal, ainv;
@@ -176,10 +179,11 @@ constexpr int NSC = 9;  // scalar blocks: mom x/y/z, pressure, transport, misc, 
 constexpr int P_STALL_WINDOW = 400;
 
 // Aggregation hierarchy: ceil-halve every active dimension until <= SMG_COARSE_MAX cells.
-void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs)
+void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs, bool split)
 {
   int n[3] = {nx, ny, nz};
   S.nlev = 0;
+  S.split = split;
   while (S.nlev < SMG_MAX_LEVELS) {
     const int l = S.nlev++;
     for (int d = 0; d < 3; ++d) S.n[l][d] = n[d];
@@ -189,6 +193,7 @@ void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs)
     S.x[l] = P.take(nc * rs);
     S.b[l] = P.take(nc * rs);
     S.t[l] = P.take(nc * rs);
+    S.dif[l] = split ? P.take(6 * nc * rs) : 0;
     if (nc <= (size_t)SMG_COARSE_MAX) break;
     for (int d = 0; d < nd; ++d) n[d] = (n[d] + 1) / 2;
   }
@@ -216,6 +221,8 @@ Layout make_layout(const vos_grid &g, int precision)
   for (int d = 0; d < 3; ++d) Lo.nrm[d] = P.take(nc * dbl);
   Lo.pdiag = P.take(nc * dbl);
   Lo.off = P.take(6 * nc * dbl);
+  Lo.tdiag = P.take(nc * dbl);      // transport: diagonal and diffusive couplings of the unscaled rows
+  Lo.tdif = P.take(6 * nc * dbl);
   size_t nmax = nc;
   for (int d = 0; d < 3; ++d) {
     nmax = std::max(nmax, (size_t)D0.nf[d]);
@@ -248,12 +255,12 @@ Layout make_layout(const vos_grid &g, int precision)
   }
   const int nd = g.nz == 1 ? 2 : 3;
   for (int d = 0; d < 3; ++d) {
-    if (d < nd) plan_smg(P, Lo.smg[d], D0.fd[d][0], D0.fd[d][1], D0.fd[d][2], nd, rs);
+    if (d < nd) plan_smg(P, Lo.smg[d], D0.fd[d][0], D0.fd[d][1], D0.fd[d][2], nd, rs, false);
     else Lo.smg[d].nlev = 0;
   }
   // the transport hierarchy is FP64 in both precisions: its Galerkin coarse
   // diagonals of upwind-dominated rows cancel to near zero and break down in FP32
-  plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, sizeof(double));
+  plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, sizeof(double), true);
   Lo.total = P.off;
   return Lo;
 }
@@ -278,6 +285,7 @@ struct vos_sim {
   Layout lo;
   char *ws;
   double *eps, *p, *c, *pn, *cold, *rbar, *gmag, *nrm[3], *pdiag, *off;
+  double *tdiag, *tdif;     // transport rows before scaling: diagonal, diffusive couplings
   double *u[3], *ustar[3], *dmom[3], *af[3], *T[3], *w[3];
   double *vec[NVEC];
   double *part, *part_max, *scal, *ainv;
@@ -387,6 +395,7 @@ void fill_smg(vos_sim *s, int h, SLevel<R> *lv)
     L.x = (R *)(s->ws + S.x[l]);
     L.b = (R *)(s->ws + S.b[l]);
     L.t = (R *)(s->ws + S.t[l]);
+    L.dif = S.split ? (R *)(s->ws + S.dif[l]) : nullptr;
   }
   if (S.nlev) s->sainv[h] = (double *)(s->ws + S.ainv);
 }
@@ -1237,22 +1246,25 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
     extrapolate(s, st, s->part, n, s->c, s->cprev, &s->hist_c, 4);
   }
   k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
-                                     s->gmag, sc_block(s, SC_MISC), s->off, b, y);
+                                     s->gmag, sc_block(s, SC_MISC), s->off, b, s->tdiag, s->tdif);
   // rebuilt every step: a transport hierarchy one step old can stall BiCGStab on
   // strongly reactive instances (Da ~ 1), where the rows change most between steps
-  k_smg_from_scaled<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, lv[0]);
+  k_smg_from_transport<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, s->tdiag, s->tdif, lv[0]);
   smg_coarsen_all<R>(s, H, lv, st);
   k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
   k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
   k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
+  // b and y are free after the start: they carry the directions times the row
+  // diagonal, the input of the cycle built on the unscaled rows
+  double *pd = b, *sd = y;
   auto iter = [&]() {
-    k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, sc);
-    smg_vcycle<R>(s, H, lv, pv, ph, sc, nullptr, st);
+    k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, pd, s->tdiag, sc);
+    smg_vcycle<R>(s, H, lv, pd, ph, sc, nullptr, st);
     k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
-    k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, s->part, sc);
+    k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, sd, s->tdiag, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
-    smg_vcycle<R>(s, H, lv, sv, sh, sc, nullptr, st);
+    smg_vcycle<R>(s, H, lv, sd, sh, sc, nullptr, st);
     k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
     k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, rh, s->c, r, s->part, sc);
@@ -1634,6 +1646,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     for (int d = 0; d < 3; ++d) s->uprev[d][k] = D(lo.uprev[d][k]);
   }
   s->rbar = D(lo.rbar); s->gmag = D(lo.gmag); s->pdiag = D(lo.pdiag); s->off = D(lo.off);
+  s->tdiag = D(lo.tdiag); s->tdif = D(lo.tdif);
   for (int d = 0; d < 3; ++d) {
     s->nrm[d] = D(lo.nrm[d]); s->u[d] = D(lo.u[d]); s->ustar[d] = D(lo.ustar[d]); s->dmom[d] = D(lo.dmom[d]);
     s->af[d] = D(lo.af[d]); s->T[d] = D(lo.T[d]); s->w[d] = D(lo.w[d]);

@@ -360,7 +360,8 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
                                                       const double *__restrict__ w1, const double *__restrict__ w2,
                                                       const double *__restrict__ cold, const double *__restrict__ gmag,
                                                       const double *__restrict__ lam, double *__restrict__ off,
-                                                      double *__restrict__ b, double *__restrict__ dg)
+                                                      double *__restrict__ b, double *__restrict__ dg,
+                                                      double *__restrict__ dif)
 {
   const double *uu[3] = {u0, u1, u2};
   const double *ww[3] = {w0, w1, w2};
@@ -369,7 +370,7 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
     int x[3];
     unflat(g.n, id, x);
     const double ep = eps[id];
-    double diag = 0.0, rhs = 0.0, o[6] = {0, 0, 0, 0, 0, 0};
+    double diag = 0.0, rhs = 0.0, o[6] = {0, 0, 0, 0, 0, 0}, od[6] = {0, 0, 0, 0, 0, 0};
     for (int d = 0; d < g.nd; ++d) {
       const unsigned st = dstride(g.n, d);
       for (int s = -1; s <= 1; s += 2) {
@@ -388,6 +389,7 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
           const double G = P.D * 0.5 * (ep + eps[nb]) * g.S / g.dx;
           diag += G;
           o[slot] -= G;
+          od[slot] = -G;
           if (P.model == 0) {
             const double wf = ww[d][f];
             const double k = P.zeta * ep * (s * wf);
@@ -410,6 +412,7 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
     }
     const double inv = 1.0 / diag;
     for (int k = 0; k < 2 * g.nd; ++k) off[(size_t)k * g.nc + id] = o[k] * inv;
+    for (int k = 0; k < 6; ++k) dif[(size_t)k * g.nc + id] = od[k];
     b[id] = rhs * inv;
     dg[id] = diag;
   }
@@ -700,18 +703,24 @@ __global__ void __launch_bounds__(TPB) k_bi_init(unsigned n, const double *__res
   write_partials<3>(vv, part);
 }
 
-// p = r + beta (p - omega v)
+// p = r + beta (p - omega v); pd = p dg (the preconditioner's input)
 __global__ void __launch_bounds__(TPB) k_bi_p(unsigned n, const double *__restrict__ r, const double *__restrict__ v,
-                                              double *__restrict__ p, const double *__restrict__ sc)
+                                              double *__restrict__ p, double *__restrict__ pd,
+                                              const double *__restrict__ dg, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   const double beta = sc[S_BETA], om = sc[S_OMEGA];
-  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = r[i] + beta * (p[i] - om * v[i]);
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
+    const double pi = r[i] + beta * (p[i] - om * v[i]);
+    p[i] = pi;
+    pd[i] = pi * dg[i];
+  }
 }
 
-// s = r - alpha v, partial s.s
+// s = r - alpha v, sd = s dg (the preconditioner's input), partial s.s
 __global__ void __launch_bounds__(TPB) k_bi_s(unsigned n, const double *__restrict__ r, const double *__restrict__ v,
-                                              double *__restrict__ s, double *__restrict__ part,
+                                              double *__restrict__ s, double *__restrict__ sd,
+                                              const double *__restrict__ dg, double *__restrict__ part,
                                               const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
@@ -720,6 +729,7 @@ __global__ void __launch_bounds__(TPB) k_bi_s(unsigned n, const double *__restri
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double si = r[i] - al * v[i];
     s[i] = si;
+    sd[i] = si * dg[i];
     ss += si * si;
   }
   const double vv[1] = {ss};

@@ -26,7 +26,18 @@ struct SLevel {
   R *off;    // 6 * nc: -x, +x, -y, +y, -z, +z
   R *diag;
   R *x, *b, *t;
+  R *dif;    // transport only (else nullptr): the diffusive part of each off-diagonal, 6 * nc
 };
+
+// Piecewise-constant aggregation counts every diffusive coupling across a
+// coarse face from all the fine faces it covers, twice what the diffusion
+// operator rediscretised on the coarse cells holds (2-D: 2 faces of T each
+// against T; 3-D: 4 against 2 T), so its coarse-grid corrections of smooth
+// error come out half as large as they should.  The transport hierarchy keeps
+// the diffusive part of every coupling apart and scales it by this factor on
+// each coarser level; the advective and reactive parts (whose Galerkin sums
+// are the coarse fluxes) stay as they are.
+constexpr double SMG_DIFF_SCALE = 0.5;
 
 // A x at cell id, every load issued unconditionally (as mg_apply_cell):
 // d x, then + off x per existing neighbour in slot order.
@@ -55,15 +66,24 @@ __device__ __forceinline__ R smg_apply_cell(const SLevel<R> &L, int nd, const R 
   return v;
 }
 
-// Level 0 of the transport hierarchy: the row-scaled stencil (unit diagonal).
+// Level 0 of the transport hierarchy: the stencil without its row scaling
+// (off64 is scaled by the diagonal dg; dif64 holds the unscaled diffusive
+// parts), so the Galerkin products below are those of the operator itself.
+// Damped Jacobi does not see a row scaling, so level 0 smooths as the scaled
+// operator would; the cycle's input is the scaled residual times dg.
 template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_from_scaled(unsigned nc, int nd, const double *__restrict__ off64,
-                                                         SLevel<R> L)
+__global__ void __launch_bounds__(TPB) k_smg_from_transport(unsigned nc, int nd, const double *__restrict__ off64,
+                                                            const double *__restrict__ dg,
+                                                            const double *__restrict__ dif64, SLevel<R> L)
 {
   for (unsigned id = xbeg(nc); id < xend(nc); id += xstride()) {
-    L.diag[id] = (R)1;
-    for (int k = 0; k < 2 * nd; ++k) L.off[(size_t)k * nc + id] = (R)off64[(size_t)k * nc + id];
-    for (int k = 2 * nd; k < 6; ++k) L.off[(size_t)k * nc + id] = (R)0;
+    const double d = dg[id];
+    L.diag[id] = (R)d;
+    for (int k = 0; k < 6; ++k) {
+      const bool on = k < 2 * nd;
+      L.off[(size_t)k * nc + id] = on ? (R)(off64[(size_t)k * nc + id] * d) : (R)0;
+      L.dif[(size_t)k * nc + id] = on ? (R)dif64[(size_t)k * nc + id] : (R)0;
+    }
   }
 }
 
@@ -96,14 +116,17 @@ __global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, c
   }
 }
 
-// Galerkin coarse stencil of aggregate I.
+// Galerkin coarse stencil of aggregate I.  With diffusive parts (F.dif), the
+// coarse one is SMG_DIFF_SCALE times their Galerkin sum; the diffusion
+// operator has zero row sums, so the diagonal drops by the same amount.
 template <typename R>
 __global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, int nd)
 {
+  const bool split = F.dif != nullptr;
   for (unsigned I = xbeg(C.nc); I < xend(C.nc); I += xstride()) {
     int X[3];
     unflat(C.n, I, X);
-    R dg = 0, o[6] = {0, 0, 0, 0, 0, 0};
+    R dg = 0, o[6] = {0, 0, 0, 0, 0, 0}, q[6] = {0, 0, 0, 0, 0, 0};
     const int lim2 = nd == 3 ? 2 : 1;
     for (int cz = 0; cz < lim2; ++cz)
       for (int cy = 0; cy < 2; ++cy)
@@ -119,15 +142,28 @@ __global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, i
             const int half = (F.n[d] == 1) ? 0 : 1;  // aggregated in this dimension?
             for (int s = 0; s < 2; ++s) {
               const R a = F.off[(size_t)(2 * d + s) * F.nc + id];
+              const R a_d = split ? F.dif[(size_t)(2 * d + s) * F.nc + id] : (R)0;
               const int nbc = s ? cd + 1 : cd - 1;
               if (nbc < 0 || nbc >= F.n[d]) continue;
               const int aggI = half ? (cd >> 1) : cd;
               const int aggN = half ? (nbc >> 1) : nbc;
-              if (aggI == aggN) dg += a;
-              else o[2 * d + s] += a;
+              if (aggI == aggN) {
+                dg += a;
+              } else {
+                o[2 * d + s] += a;
+                q[2 * d + s] += a_d;
+              }
             }
           }
         }
+    if (split) {
+      const R keep = (R)(1.0 - SMG_DIFF_SCALE);
+      for (int k = 0; k < 6; ++k) {
+        o[k] -= keep * q[k];
+        dg += keep * q[k];
+        C.dif[(size_t)k * C.nc + I] = (R)SMG_DIFF_SCALE * q[k];
+      }
+    }
     C.diag[I] = dg;
     for (int k = 0; k < 6; ++k) C.off[(size_t)k * C.nc + I] = o[k];
   }
