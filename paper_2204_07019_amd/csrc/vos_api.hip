@@ -255,7 +255,7 @@ Layout make_layout(const vos_grid &g, int precision)
   }
   const int nd = g.nz == 1 ? 2 : 3;
   for (int d = 0; d < 3; ++d) {
-    if (d < nd) plan_smg(P, Lo.smg[d], D0.fd[d][0], D0.fd[d][1], D0.fd[d][2], nd, rs, false);
+    if (d < nd) plan_smg(P, Lo.smg[d], D0.fd[d][0], D0.fd[d][1], D0.fd[d][2], nd, rs, true);
     else Lo.smg[d].nlev = 0;
   }
   // the transport hierarchy is FP64 in both precisions: its Galerkin coarse
@@ -818,13 +818,12 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
 // iterations with 2, 1000-2300 with 4 on a Pe 47, Da 0.54 micromodel).
 int sweeps(const vos_sim *s, int h) { return h == 3 ? std::min(2, s->opt.mg_nu) : s->nu_mom; }
 
-// dsc: diagonal of the symmetrically scaled operator (momentum), nullptr for
-// the row-scaled transport operator.
+// z = cycle(r) on hierarchy h, whose level 0 is the unscaled operator (the
+// transport caller passes its row-scaled directions times the row diagonal).
 template <typename R>
-void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, const double *dsc,
-                hipStream_t st)
+void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, hipStream_t st)
 {
-  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.85, dsc, 1.0, sweeps(s, h), st);
+  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.85, nullptr, 1.0, sweeps(s, h), st);
 }
 
 // ---------------------------------------------------------------- stage S2
@@ -852,13 +851,13 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
   }
   k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x, ex ? 0 : 1);
   if (hierarchy_due(s, H_MOM + D)) {
-    k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);   // Jacobi-scaled
+    k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);
     smg_coarsen_all<R>(s, D, lv, st);
   }
   k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], x, q, part, zero_flag);
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 0, part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, part, nb, rt2, sc);
-  smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D], st);
+  smg_vcycle<R>(s, D, lv, r, z, sc, st);
   k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, part, sc);
   k_cg_scal<<<1, TPB, 0, st>>>(5, part, nb, rt2, sc);
   HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -867,7 +866,7 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
     k_cg_scal<<<1, TPB, 0, st>>>(1, part, nb, rt2, sc);
     k_cg_xr<<<nb, TPB, 0, st>>>(n, pv, q, s->dmom[D], x, r, z, 0, part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(3, part, nb, rt2, sc);
-    smg_vcycle<R>(s, D, lv, r, z, sc, s->dmom[D], st);
+    smg_vcycle<R>(s, D, lv, r, z, sc, st);
     k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(4, part, nb, rt2, sc);
     k_cg_p<<<nb, TPB, 0, st>>>(n, z, pv, sc);
@@ -1259,12 +1258,12 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   double *pd = b, *sd = y;
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, pd, s->tdiag, sc);
-    smg_vcycle<R>(s, H, lv, pd, ph, sc, nullptr, st);
+    smg_vcycle<R>(s, H, lv, pd, ph, sc, st);
     k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, sd, s->tdiag, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
-    smg_vcycle<R>(s, H, lv, sd, sh, sc, nullptr, st);
+    smg_vcycle<R>(s, H, lv, sd, sh, sc, st);
     k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
     k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, rh, s->c, r, s->part, sc);

@@ -87,9 +87,9 @@ __global__ void __launch_bounds__(TPB) k_smg_from_transport(unsigned nc, int nd,
   }
 }
 
-// Level 0 of the momentum hierarchy of component D on its face grid, scaled
-// symmetrically by the diagonal (D^-1/2 A D^-1/2: unit diagonal,
-// -mu/dx^2 / sqrt(d_f d_nb) towards unknown neighbours; fixed rows identity).
+// Level 0 of the momentum hierarchy of component D on its face grid: the
+// operator itself (diagonal dmom, -mu/dx^2 towards unknown neighbours; fixed
+// rows identity).  Every coupling is viscous, so all of it is diffusive.
 template <typename R, int D>
 __global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, const double *__restrict__ dmom,
                                                            SLevel<R> L)
@@ -98,20 +98,16 @@ __global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, c
   for (unsigned f = xbeg(nc); f < xend(nc); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
-    L.diag[f] = (R)1;
+    L.diag[f] = (R)dmom[f];
     const bool unk = mom_unknown<D>(g, x);
-    const double df = dmom[f];
     double fv;
     for (int e = 0; e < 3; ++e)
       for (int s = -1; s <= 1; s += 2) {
         const int slot = 2 * e + (s > 0);
         R v = 0;
-        if (unk && e < g.nd && mom_nb<D>(g, x, e, s, 0.0, &fv) == 0) {
-          const unsigned st = dstride(g.fd[D], e);
-          const double dn = dmom[s > 0 ? f + st : f - st];
-          v = (R)(-cvis / sqrt(df * dn));
-        }
+        if (unk && e < g.nd && mom_nb<D>(g, x, e, s, 0.0, &fv) == 0) v = (R)(-cvis);
         L.off[(size_t)slot * nc + f] = v;
+        L.dif[(size_t)slot * nc + f] = v;
       }
   }
 }
