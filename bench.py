@@ -45,10 +45,10 @@ CHECK_EVERY = 2
 # that order predicted the last solution better); the start-from-x^n rate is
 # reported beside it.
 EXTRAPOLATE = 2
-# The multigrid hierarchies are rebuilt every second step (vos_opts.setup_every);
-# a solve in between is preconditioned with the previous step's hierarchy and
-# still meets its tolerance.
-SETUP_EVERY = 2
+# The momentum and pressure hierarchies are rebuilt every fourth step
+# (vos_opts.setup_every); a solve in between is preconditioned with an earlier
+# step's hierarchy and still meets its tolerance.
+SETUP_EVERY = 4
 # Solid-frozen steps after the flow is rescaled to the target Pe (setup_sim).
 SETUP_STEPS = 3
 # Per-step pressure setup (hierarchy build, right-hand side, initial residual):

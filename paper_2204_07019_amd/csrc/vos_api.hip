@@ -1315,12 +1315,12 @@ void launch_reaction(vos_sim *s, double dt, int freeze)
 
 vos_status fill_diag(vos_sim *s, double dt, vos_diag *dg)
 {
-  vos_status st = read_back(s, sc_block(s, SC_MISC), 2);
-  if (st) return st;
+  // one synchronisation: lambda (misc block) to host[0], the 13 sums to host[2..14]
+  HIP_TRY(hipMemcpyAsync(s->host, sc_block(s, SC_MISC), 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->host + 2, sc_block(s, SC_DIAG), 13 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
   const double lam = s->host[0];
-  st = read_back(s, sc_block(s, SC_DIAG), 13);
-  if (st) return st;
-  const double *h = s->host;
+  const double *h = s->host + 2;
   const Dev &g = s->g;
   const double V = g.V;
   const double sink = h[0], rate = h[1];
