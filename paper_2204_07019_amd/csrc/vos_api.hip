@@ -666,8 +666,10 @@ void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv, hipStream_t st)
 {
   const int nd = s->g.nd;
   const int L = s->snlev[h];
-  for (int l = 0; l + 1 < L; ++l)
-    k_smg_coarsen<R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd);
+  for (int l = 0; l + 1 < L; ++l) {
+    if (nd == 3) k_smg_coarsen<R, 3><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1]);
+    else k_smg_coarsen<R, 2><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1]);
+  }
   k_smg_coarse_inverse<R><<<1, GJ_TPB, 0, st>>>(lv[L - 1], nd, s->sainv[h]);
 }
 

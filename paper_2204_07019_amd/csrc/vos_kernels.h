@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
     }
     const double inv = 1.0 / diag;
     for (int k = 0; k < 2 * g.nd; ++k) off[(size_t)k * g.nc + id] = o[k] * inv;
-    for (int k = 0; k < 6; ++k) dif[(size_t)k * g.nc + id] = od[k];
+    for (int k = 0; k < 2 * g.nd; ++k) dif[(size_t)k * g.nc + id] = od[k];
     b[id] = rhs * inv;
     dg[id] = diag;
   }

@@ -114,44 +114,65 @@ __global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, c
 
 // Galerkin coarse stencil of aggregate I.  With diffusive parts (F.dif), the
 // coarse one is SMG_DIFF_SCALE times their Galerkin sum; the diffusion
-// operator has zero row sums, so the diagonal drops by the same amount.
-template <typename R>
-__global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, int nd)
+// operator has zero row sums, so the diagonal drops by the same amount.  Per
+// plane of children (one in 2-D, two in 3-D) every load is issued first, at
+// clamped cells, and a missing child or neighbour is dropped by a select.
+template <typename R, int ND>
+__global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C)
 {
+  constexpr int NS = 2 * ND;
   const bool split = F.dif != nullptr;
+  const R *difs = split ? F.dif : F.off;   // read either way, used only when split
   for (unsigned I = xbeg(C.nc); I < xend(C.nc); I += xstride()) {
     int X[3];
     unflat(C.n, I, X);
     R dg = 0, o[6] = {0, 0, 0, 0, 0, 0}, q[6] = {0, 0, 0, 0, 0, 0};
-    const int lim2 = nd == 3 ? 2 : 1;
-    for (int cz = 0; cz < lim2; ++cz)
-      for (int cy = 0; cy < 2; ++cy)
-        for (int cx = 0; cx < 2; ++cx) {
-          const int c[3] = {2 * X[0] + cx, 2 * X[1] + cy, nd == 3 ? 2 * X[2] + cz : 0};
-          if (c[0] >= F.n[0] || c[1] >= F.n[1] || c[2] >= F.n[2]) continue;
-          // a dimension of extent 1 is not aggregated
-          if ((F.n[1] == 1 && cy) || (nd == 3 && F.n[2] == 1 && cz) || (F.n[0] == 1 && cx)) continue;
-          const unsigned id = (unsigned)c[0] + (unsigned)F.n[0] * ((unsigned)c[1] + (unsigned)F.n[1] * c[2]);
-          dg += F.diag[id];
-          for (int d = 0; d < nd; ++d) {
-            const int cd = c[d];
-            const int half = (F.n[d] == 1) ? 0 : 1;  // aggregated in this dimension?
-            for (int s = 0; s < 2; ++s) {
-              const R a = F.off[(size_t)(2 * d + s) * F.nc + id];
-              const R a_d = split ? F.dif[(size_t)(2 * d + s) * F.nc + id] : (R)0;
-              const int nbc = s ? cd + 1 : cd - 1;
-              if (nbc < 0 || nbc >= F.n[d]) continue;
-              const int aggI = half ? (cd >> 1) : cd;
-              const int aggN = half ? (nbc >> 1) : nbc;
-              if (aggI == aggN) {
-                dg += a;
-              } else {
-                o[2 * d + s] += a;
-                q[2 * d + s] += a_d;
-              }
-            }
+#pragma unroll
+    for (int cz = 0; cz < (ND == 3 ? 2 : 1); ++cz) {
+      unsigned id[4];
+      bool ok[4];
+      int cc[4][3];
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const int cx = ch & 1, cy = ch >> 1;
+        const int c[3] = {2 * X[0] + cx, 2 * X[1] + cy, ND == 3 ? 2 * X[2] + cz : 0};
+        // a dimension of extent 1 is not aggregated
+        ok[ch] = c[0] < F.n[0] && c[1] < F.n[1] && c[2] < F.n[2] &&
+                 !((F.n[1] == 1 && cy) || (ND == 3 && F.n[2] == 1 && cz) || (F.n[0] == 1 && cx));
+        for (int e = 0; e < 3; ++e) cc[ch][e] = min(c[e], F.n[e] - 1);
+        id[ch] = (unsigned)cc[ch][0] + (unsigned)F.n[0] * ((unsigned)cc[ch][1] + (unsigned)F.n[1] * cc[ch][2]);
+      }
+      R dv[4], av[4][NS], qv[4][NS];
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        dv[ch] = F.diag[id[ch]];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          av[ch][k] = F.off[(size_t)k * F.nc + id[ch]];
+          qv[ch][k] = difs[(size_t)k * F.nc + id[ch]];
+        }
+      }
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        dg = ok[ch] ? dg + dv[ch] : dg;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const int cd = cc[ch][d];
+          const int half = (F.n[d] == 1) ? 0 : 1;   // aggregated in this dimension?
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const int k = 2 * d + s;
+            const int nbc = s ? cd + 1 : cd - 1;
+            const bool has = ok[ch] && nbc >= 0 && nbc < F.n[d];
+            const bool inside = (half ? (cd >> 1) : cd) == (half ? (nbc >> 1) : nbc);
+            const R a = av[ch][k], a_d = split ? qv[ch][k] : (R)0;
+            dg = (has && inside) ? dg + a : dg;
+            o[k] = (has && !inside) ? o[k] + a : o[k];
+            q[k] = (has && !inside) ? q[k] + a_d : q[k];
           }
         }
+      }
+    }
     if (split) {
       const R keep = (R)(1.0 - SMG_DIFF_SCALE);
       for (int k = 0; k < 6; ++k) {
