@@ -246,52 +246,59 @@ __device__ __forceinline__ R lds_term(const SLevel<R> &, R v, R o, R xn) { retur
 template <typename R>
 __device__ __forceinline__ R lds_term(const MgLevel<R> &, R v, R o, R xn) { return v - (-o) * xn; }
 
-// A x at a tile cell from LDS arrays (lv_apply order); os[k] holds the
-// coefficient towards neighbour slot k (0 where there is no neighbour).
-template <typename Lv, typename R, int W, int H>
-__device__ __forceinline__ R tile_apply(const Lv &L, const R (*os)[H][W], R dg, const R (*x)[W], int lx, int ly,
+// A x at a tile cell (lv_apply order) from the iterate x in LDS and the
+// cell's own coefficients o[k] (towards neighbour slot k, 0 where there is
+// no neighbour) and diagonal dg, held in registers by the thread that owns
+// the cell.
+template <typename Lv, typename R, int W>
+__device__ __forceinline__ R tile_apply(const Lv &L, const R o[4], R dg, const R (*x)[W], int lx, int ly,
                                         const int c[3])
 {
   R v = dg * x[ly][lx];
-  if (c[0] > 0) v = lds_term(L, v, os[0][ly][lx], x[ly][lx - 1]);
-  if (c[0] < L.n[0] - 1) v = lds_term(L, v, os[1][ly][lx], x[ly][lx + 1]);
-  if (c[1] > 0) v = lds_term(L, v, os[2][ly][lx], x[ly - 1][lx]);
-  if (c[1] < L.n[1] - 1) v = lds_term(L, v, os[3][ly][lx], x[ly + 1][lx]);
+  if (c[0] > 0) v = lds_term(L, v, o[0], x[ly][lx - 1]);
+  if (c[0] < L.n[0] - 1) v = lds_term(L, v, o[1], x[ly][lx + 1]);
+  if (c[1] > 0) v = lds_term(L, v, o[2], x[ly - 1][lx]);
+  if (c[1] < L.n[1] - 1) v = lds_term(L, v, o[3], x[ly + 1][lx]);
   return v;
 }
 
 // A x in the k_v_pre / k_v_post order: d x + sum of off * x.
-template <typename Lv, typename R, int W, int H>
-__device__ __forceinline__ R tile_apply_off(const Lv &L, const R (*os)[H][W], R dg, const R (*x)[W], int lx, int ly,
+template <typename Lv, typename R, int W>
+__device__ __forceinline__ R tile_apply_off(const Lv &L, const R o[4], R dg, const R (*x)[W], int lx, int ly,
                                             const int c[3])
 {
   R v = dg * x[ly][lx];
-  if (c[0] > 0) v += os[0][ly][lx] * x[ly][lx - 1];
-  if (c[0] < L.n[0] - 1) v += os[1][ly][lx] * x[ly][lx + 1];
-  if (c[1] > 0) v += os[2][ly][lx] * x[ly - 1][lx];
-  if (c[1] < L.n[1] - 1) v += os[3][ly][lx] * x[ly + 1][lx];
+  if (c[0] > 0) v += o[0] * x[ly][lx - 1];
+  if (c[0] < L.n[0] - 1) v += o[1] * x[ly][lx + 1];
+  if (c[1] > 0) v += o[2] * x[ly - 1][lx];
+  if (c[1] < L.n[1] - 1) v += o[3] * x[ly + 1][lx];
   return v;
 }
 
-// Down leg of a 2-D fine level: NU damped-Jacobi sweeps from zero, then the
-// residual restricted to the coarse right-hand side.  F.x receives the
-// smoothed iterate (tile cells); with FROM64, F.b the scaled right-hand side.
-// Grid: tile_of(), block TPB.
-template <typename Lv, typename R, bool FROM64, int NU>
-__global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__restrict__ r64,
-                                                  const double *__restrict__ dsc, double rscale, R omega,
-                                                  const double *__restrict__ sc)
+// Cells of a staged tile-plus-halo that one thread owns for the whole
+// kernel: cell t = threadIdx.x + i TPB of the W x H array (i < PER), with its
+// right-hand side, diagonal and neighbour coefficients in registers.  Only
+// the iterates (which neighbours read) live in LDS, so a block needs two W x H
+// planes of LDS instead of eight and more blocks fit on a CU.
+template <typename R, int W, int H>
+struct TileCells {
+  static constexpr int PER = (W * H + TPB - 1) / TPB;
+  int lx[PER], ly[PER], gx[PER], gy[PER];
+  bool in[PER];   // inside the level (and inside the staged array)
+  R b[PER], d[PER], o[PER][4];
+};
+
+// Stage the owned cells of the tile whose LDS cell (0, 0) is level cell (X0,
+// Y0): every load first (coordinates clamped into the level, so no load sits
+// in a branch), then the values (defaults outside the level: b 0, diagonal 1,
+// no coefficients).
+template <typename Lv, typename R, int W, int H, bool FROM64>
+__device__ __forceinline__ void tile_stage(const Lv &F, int X0, int Y0, const double *__restrict__ r64,
+                                           const double *__restrict__ dsc, double rscale,
+                                           TileCells<R, W, H> &T)
 {
-  if (sc[S_CONV] != 0.0) return;
-  constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
-  __shared__ R bs[H][W], ds[H][W], xa[H][W], xb[H][W], os[4][H][W];
+  constexpr int PER = TileCells<R, W, H>::PER;
   const int nx = F.n[0], ny = F.n[1];
-  int tx, ty;
-  if (!tile_of(nx, ny, tx, ty)) return;
-  const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;   // global coords of LDS cell (0, 0)
-  // staging in two phases: every load of a thread first (coordinates clamped into the
-  // level, so no load sits in a branch), then the values (defaults outside the level)
-  constexpr int PER = (W * H + TPB - 1) / TPB;
   R rb[PER], rd[PER], ro[PER][4];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
@@ -308,20 +315,55 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int t = (int)threadIdx.x + i * TPB;
-    if (t >= W * H) break;
-    const int lx = t % W, ly = t / W;
-    const int gx = X0 + lx, gy = Y0 + ly;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const R bb = in ? rb[i] : (R)0, dg = in ? rd[i] : (R)1;
-    if (FROM64 && in && lx >= NU && lx < VT_X + NU && ly >= NU && ly < VT_Y + NU)
-      F.b[(unsigned)gx + (unsigned)nx * (unsigned)gy] = bb;
-    bs[ly][lx] = bb;
-    ds[ly][lx] = dg;
-    xa[ly][lx] = in ? omega * bb / dg : (R)0;
-    os[0][ly][lx] = in && gx > 0 ? ro[i][0] : (R)0;
-    os[1][ly][lx] = in && gx < nx - 1 ? ro[i][1] : (R)0;
-    os[2][ly][lx] = in && gy > 0 ? ro[i][2] : (R)0;
-    os[3][ly][lx] = in && gy < ny - 1 ? ro[i][3] : (R)0;
+    T.lx[i] = t % W;
+    T.ly[i] = t / W;
+    T.gx[i] = X0 + T.lx[i];
+    T.gy[i] = Y0 + T.ly[i];
+    const bool in = t < W * H && T.gx[i] >= 0 && T.gx[i] < nx && T.gy[i] >= 0 && T.gy[i] < ny;
+    T.in[i] = in;
+    T.b[i] = in ? rb[i] : (R)0;
+    T.d[i] = in ? rd[i] : (R)1;
+    T.o[i][0] = in && T.gx[i] > 0 ? ro[i][0] : (R)0;
+    T.o[i][1] = in && T.gx[i] < nx - 1 ? ro[i][1] : (R)0;
+    T.o[i][2] = in && T.gy[i] > 0 ? ro[i][2] : (R)0;
+    T.o[i][3] = in && T.gy[i] < ny - 1 ? ro[i][3] : (R)0;
+  }
+}
+
+// Owned cell i lies in the tile grown by h cells (the LDS array holds the tile
+// grown by NU).
+template <int NU, typename TC>
+__device__ __forceinline__ bool tile_within(const TC &T, int i, int h)
+{
+  return T.in[i] && T.lx[i] >= NU - h && T.lx[i] < NU + VT_X + h && T.ly[i] >= NU - h && T.ly[i] < NU + VT_Y + h;
+}
+
+// Down leg of a 2-D fine level: NU damped-Jacobi sweeps from zero, then the
+// residual restricted to the coarse right-hand side.  F.x receives the
+// smoothed iterate (tile cells); with FROM64, F.b the scaled right-hand side.
+// Grid: tile_of(), block TPB.
+template <typename Lv, typename R, bool FROM64, int NU>
+__global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__restrict__ r64,
+                                                  const double *__restrict__ dsc, double rscale, R omega,
+                                                  const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
+  __shared__ R xa[H][W], xb[H][W];
+  const int nx = F.n[0], ny = F.n[1];
+  int tx, ty;
+  if (!tile_of(nx, ny, tx, ty)) return;
+  const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;   // global coords of LDS cell (0, 0)
+  TileCells<R, W, H> T;
+  tile_stage<Lv, R, W, H, FROM64>(F, X0, Y0, r64, dsc, rscale, T);
+  constexpr int PER = TileCells<R, W, H>::PER;
+  // sweep 1 from zero on the whole staged array
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    if ((int)threadIdx.x + i * TPB >= W * H) continue;
+    if (FROM64 && T.in[i] && tile_within<NU>(T, i, 0))
+      F.b[(unsigned)T.gx[i] + (unsigned)nx * (unsigned)T.gy[i]] = T.b[i];
+    xa[T.ly[i]][T.lx[i]] = T.in[i] ? omega * T.b[i] / T.d[i] : (R)0;
   }
   __syncthreads();
   // sweeps 2..NU on a halo shrinking from NU - 1 to 1 (ping-pong xa -> xb -> xa ...)
@@ -330,38 +372,31 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
     const int h = NU - k + 1;
     R(*src)[W] = (k % 2 == 0) ? xa : xb;
     R(*dst)[W] = (k % 2 == 0) ? xb : xa;
-    for (int t = threadIdx.x; t < (VT_X + 2 * h) * (VT_Y + 2 * h); t += TPB) {
-      const int lx = NU - h + t % (VT_X + 2 * h), ly = NU - h + t / (VT_X + 2 * h);
-      const int gx = X0 + lx, gy = Y0 + ly;
-      if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-      const int c[3] = {gx, gy, 0};
-      const R dg = ds[ly][lx];
-      const R ax = (k == 2) ? tile_apply_off<Lv, R, W, H>(F, os, dg, src, lx, ly, c)
-                            : tile_apply<Lv, R, W, H>(F, os, dg, src, lx, ly, c);
-      dst[ly][lx] = src[ly][lx] + omega * (bs[ly][lx] - ax) / dg;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (!tile_within<NU>(T, i, h)) continue;
+      const int c[3] = {T.gx[i], T.gy[i], 0};
+      const int lx = T.lx[i], ly = T.ly[i];
+      const R ax = (k == 2) ? tile_apply_off<Lv, R, W>(F, T.o[i], T.d[i], src, lx, ly, c)
+                            : tile_apply<Lv, R, W>(F, T.o[i], T.d[i], src, lx, ly, c);
+      dst[ly][lx] = src[ly][lx] + omega * (T.b[i] - ax) / T.d[i];
     }
     __syncthreads();
   }
   R(*xf)[W] = (NU % 2 == 0) ? xb : xa;   // the last sweep's output
+  R(*rs)[W] = (NU % 2 == 0) ? xa : xb;   // free now: the tile's residuals
   // residual on the tile, x to F.x
-  constexpr int PT = (VT_X * VT_Y + TPB - 1) / TPB;
-  R res[PT];
-  int q = 0;
-  for (int t = threadIdx.x; t < VT_X * VT_Y; t += TPB, ++q) {
-    const int lx = NU + t % VT_X, ly = NU + t / VT_X;
-    const int gx = X0 + lx, gy = Y0 + ly;
-    res[q] = 0;
-    if (gx >= nx || gy >= ny) continue;
-    const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
-    const int c[3] = {gx, gy, 0};
-    F.x[id] = xf[ly][lx];
-    res[q] = bs[ly][lx] - tile_apply<Lv, R, W, H>(F, os, ds[ly][lx], xf, lx, ly, c);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    if (!tile_within<NU>(T, i, 0)) continue;
+    const int c[3] = {T.gx[i], T.gy[i], 0};
+    const int lx = T.lx[i], ly = T.ly[i];
+    F.x[(unsigned)T.gx[i] + (unsigned)nx * (unsigned)T.gy[i]] = xf[ly][lx];
+    rs[ly][lx] = T.b[i] - tile_apply<Lv, R, W>(F, T.o[i], T.d[i], xf, lx, ly, c);
   }
   __syncthreads();
-  q = 0;
-  for (int t = threadIdx.x; t < VT_X * VT_Y; t += TPB, ++q) bs[NU + t / VT_X][NU + t % VT_X] = res[q];
-  __syncthreads();
-  // restriction: sum over each 2 x 2 aggregate (cy outer, cx inner)
+  // restriction: sum over each 2 x 2 aggregate (cy outer, cx inner); the tile
+  // cells outside the level contribute nothing
   for (int t = threadIdx.x; t < (VT_X / 2) * (VT_Y / 2); t += TPB) {
     const int ix = t % (VT_X / 2), iy = t / (VT_X / 2);
     const int IX = tx * (VT_X / 2) + ix, IY = ty * (VT_Y / 2) + iy;
@@ -370,7 +405,7 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
     for (int cy = 0; cy < 2; ++cy)
       for (int cx = 0; cx < 2; ++cx) {
         if (2 * IX + cx >= nx || 2 * IY + cy >= ny) continue;
-        sum += bs[NU + 2 * iy + cy][NU + 2 * ix + cx];
+        sum += rs[NU + 2 * iy + cy][NU + 2 * ix + cx];
       }
     C.b[(unsigned)IX + (unsigned)C.n[0] * (unsigned)IY] = sum;
   }
@@ -386,60 +421,44 @@ __global__ void __launch_bounds__(TPB) k_v_up2d(Lv F, Lv C, R *__restrict__ xo, 
 {
   if (sc[S_CONV] != 0.0) return;
   constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
-  __shared__ R ya[H][W], yb[H][W], bs[H][W], ds[H][W], os[4][H][W];
+  __shared__ R ya[H][W], yb[H][W];
   const int nx = F.n[0], ny = F.n[1];
   int tx, ty;
   if (!tile_of(nx, ny, tx, ty)) return;
   const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;
-  // two-phase staging as in the down leg
-  constexpr int PER = (W * H + TPB - 1) / TPB;
-  R rv[PER], rb[PER], rd[PER], ro[PER][4];
+  constexpr int PER = TileCells<R, W, H>::PER;
+  // the prolonged iterate, loaded with the other staging loads
+  R rv[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int t = min((int)threadIdx.x + i * TPB, W * H - 1);
     const int gx = min(max(X0 + t % W, 0), nx - 1), gy = min(max(Y0 + t / W, 0), ny - 1);
-    const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
     const int c[3] = {gx, gy, 0};
-    rv[i] = F.x[id] + C.x[parent_of<R>(F.n, C.n, 2, c)];
-    rb[i] = F.b[id];
-    rd[i] = F.diag[id];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) ro[i][k] = lv_off(F, id, c, k);
+    rv[i] = F.x[(unsigned)gx + (unsigned)nx * (unsigned)gy] + C.x[parent_of<R>(F.n, C.n, 2, c)];
   }
+  TileCells<R, W, H> T;
+  tile_stage<Lv, R, W, H, false>(F, X0, Y0, nullptr, nullptr, 1.0, T);
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int t = (int)threadIdx.x + i * TPB;
-    if (t >= W * H) break;
-    const int lx = t % W, ly = t / W;
-    const int gx = X0 + lx, gy = Y0 + ly;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    ya[ly][lx] = in ? rv[i] : (R)0;
-    bs[ly][lx] = in ? rb[i] : (R)0;
-    ds[ly][lx] = in ? rd[i] : (R)1;
-    os[0][ly][lx] = in && gx > 0 ? ro[i][0] : (R)0;
-    os[1][ly][lx] = in && gx < nx - 1 ? ro[i][1] : (R)0;
-    os[2][ly][lx] = in && gy > 0 ? ro[i][2] : (R)0;
-    os[3][ly][lx] = in && gy < ny - 1 ? ro[i][3] : (R)0;
-  }
+  for (int i = 0; i < PER; ++i)
+    if ((int)threadIdx.x + i * TPB < W * H) ya[T.ly[i]][T.lx[i]] = T.in[i] ? rv[i] : (R)0;
   __syncthreads();
 #pragma unroll
   for (int k = 1; k <= NU; ++k) {
     const int h = NU - k;
     R(*src)[W] = (k % 2 == 1) ? ya : yb;
     R(*dst)[W] = (k % 2 == 1) ? yb : ya;
-    for (int t = threadIdx.x; t < (VT_X + 2 * h) * (VT_Y + 2 * h); t += TPB) {
-      const int lx = NU - h + t % (VT_X + 2 * h), ly = NU - h + t / (VT_X + 2 * h);
-      const int gx = X0 + lx, gy = Y0 + ly;
-      if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-      const int c[3] = {gx, gy, 0};
-      const R dg = ds[ly][lx];
-      const R ay = (k == 1) ? tile_apply_off<Lv, R, W, H>(F, os, dg, src, lx, ly, c)
-                            : tile_apply<Lv, R, W, H>(F, os, dg, src, lx, ly, c);
-      const R o = src[ly][lx] + omega * (bs[ly][lx] - ay) / dg;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (!tile_within<NU>(T, i, h)) continue;
+      const int c[3] = {T.gx[i], T.gy[i], 0};
+      const int lx = T.lx[i], ly = T.ly[i];
+      const R ay = (k == 1) ? tile_apply_off<Lv, R, W>(F, T.o[i], T.d[i], src, lx, ly, c)
+                            : tile_apply<Lv, R, W>(F, T.o[i], T.d[i], src, lx, ly, c);
+      const R o = src[ly][lx] + omega * (T.b[i] - ay) / T.d[i];
       if (k < NU) {
         dst[ly][lx] = o;
       } else {
-        const unsigned id = (unsigned)gx + (unsigned)nx * (unsigned)gy;
+        const unsigned id = (unsigned)T.gx[i] + (unsigned)nx * (unsigned)T.gy[i];
         xo[id] = o;
         if (OUT64) z[id] = unscale((double)o, dsc, id);
       }
