@@ -421,8 +421,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path "
+              "(slabs along the flow with halo exchange) is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
