@@ -457,13 +457,16 @@ def main():
 
     plain = None
     from_xn = None
+    every_step = None
     if not args.skip_plain:
         # the same relaxed state, (a) plain FP64 multigrid with the same options,
-        # (b) mixed precision with every solve started from x^n
-        for prec, ex in ((vos.FP64, EXTRAPOLATE), (vos.MIXED, 0)):
+        # (b) mixed precision with every solve started from x^n, (c) mixed
+        # precision with every hierarchy rebuilt every step
+        for prec, ex, se in ((vos.FP64, EXTRAPOLATE, SETUP_EVERY), (vos.MIXED, 0, SETUP_EVERY),
+                             (vos.MIXED, EXTRAPOLATE, 1)):
             sim2 = vos.Sim(nx, ny, nz, inputs.workload(args.workload)[1]["dx"], params,
                            vos.Opts(precision=prec, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8,
-                                    check_every=CHECK_EVERY, extrapolate=ex, setup_every=SETUP_EVERY))
+                                    check_every=CHECK_EVERY, extrapolate=ex, setup_every=se))
             for k in ("eps", "ux", "uy", "uz", "p", "c"):
                 sim2.set(k, sim.get(k))
             # as many steps before the timed ones as the headline simulation had since
@@ -479,6 +482,9 @@ def main():
             if prec == vos.FP64:
                 plain = res
                 log(f"fp64: {res['ms_per_step']:.2f} ms/step, {res['value']:.3e} cell-steps/s")
+            elif se == 1:
+                every_step = res
+                log(f"mixed, hierarchies rebuilt every step: {res['ms_per_step']:.2f} ms/step")
             else:
                 from_xn = res
                 log(f"mixed, solves started from x^n: {res['ms_per_step']:.2f} ms/step")
@@ -537,6 +543,7 @@ def main():
         "iterations": {"u": last["it_u"], "p": last["it_p"], "c": last["it_c"]},
         "plain_fp64": plain,
         "mixed_started_from_xn": from_xn,
+        "mixed_hierarchies_every_step": every_step,
         "roofline": roof,
         "roofline_other_kernels": others,
         "pressure_solve_3d": p3d,
