@@ -51,7 +51,7 @@ vos_status vos_batch_step(vos_batch *batch, const double *dt, int nsteps, int fl
                           vos_status *status);
 
 /* Autotuner.  For each candidate worker count (1, 2, 4, ... up to the batch's
- * maximum) and each candidate Krylov check interval (4, 8, 16, 32, chosen per
+ * maximum) and each candidate Krylov check interval (2, 4, 8, 16, 32, chosen per
  * grid-size class), time probe_steps solid-frozen steps of the whole batch
  * (VOS_FREEZE_SOLID: flow and transport advance, the geometry does not) and
  * keep the fastest setting.  Results do not depend on it (the check interval

@@ -204,7 +204,7 @@ vos_status vos_batch_tune(vos_batch *b, const double *dt, int probe_steps, int *
   std::vector<int> uniq = classes;
   std::sort(uniq.begin(), uniq.end());
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-  const int cands[4] = {4, 8, 16, 32};
+  const int cands[5] = {2, 4, 8, 16, 32};
   for (int cls : uniq) {
     int cur = 0, cc = 0;
     for (int i = 0; i < b->n; ++i)
