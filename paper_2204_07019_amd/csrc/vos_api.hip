@@ -57,11 +57,14 @@ struct Plan {
   }
 };
 
-// Blocks of a tiled 2-D V-cycle kernel (vos_vcycle.h, tile_of): the tile
-// count rounded up to a multiple of the 8 XCDs.
-unsigned tile_blocks(int nx, int ny)
+// Tile height of the tiled 2-D V-cycle kernels on a level of nc cells.
+int tile_height(unsigned nc) { return nc >= VT_BIG_CELLS ? VT_Y_BIG : VT_Y_SMALL; }
+
+// Blocks of a tiled 2-D V-cycle kernel (vos_vcycle.h, tile_of) with tiles
+// of height ty: the tile count rounded up to a multiple of the 8 XCDs.
+unsigned tile_blocks(int nx, int ny, int ty)
 {
-  const unsigned nt = (unsigned)((nx + VT_X - 1) / VT_X) * (unsigned)((ny + VT_Y - 1) / VT_Y);
+  const unsigned nt = (unsigned)((nx + VT_X - 1) / VT_X) * (unsigned)((ny + ty - 1) / ty);
   return (nt + NXCD - 1) / NXCD * NXCD;
 }
 
@@ -717,7 +720,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   const bool fused = s->opt.level_kernels == 0;
   // 2-D levels with 2..4 sweeps each way: one tiled kernel per leg (vos_vcycle.h)
   auto tiled = [&](const Lv &F) { return fused && nd == 2 && nu >= 2 && nu <= 4 && F.n[0] >= 2 && F.n[1] >= 2; };
-  auto tgrid = [](const Lv &F) { return dim3(tile_blocks(F.n[0], F.n[1])); };
+  auto tgrid = [](const Lv &F) { return dim3(tile_blocks(F.n[0], F.n[1], tile_height(F.nc))); };
   // 3-D levels at least half a tile wide: z-marching kernels (vos_march3d.h)
   auto zmarch = [&](const Lv &F) { return fused && nd == 3 && F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2; };
   for (int l = 0; l < lc; ++l) {
@@ -743,10 +746,14 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     }
     if (tiled(F)) {
       const dim3 gr = tgrid(F);
-#define VDOWN(NU_)                                                                                   \
-  if (l == 0) k_v_down2d<Lv, R, true, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc); \
-  else k_v_down2d<Lv, R, false, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc);
-      if (nu == 2) { VDOWN(2) } else if (nu == 3) { VDOWN(3) } else { VDOWN(4) }
+#define VDOWN(NU_, TY_)                                                                                   \
+  if (l == 0) k_v_down2d<Lv, R, true, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc); \
+  else k_v_down2d<Lv, R, false, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc);
+      if (tile_height(F.nc) == VT_Y_BIG) {
+        if (nu == 2) { VDOWN(2, VT_Y_BIG) } else if (nu == 3) { VDOWN(3, VT_Y_BIG) } else { VDOWN(4, VT_Y_BIG) }
+      } else {
+        if (nu == 2) { VDOWN(2, VT_Y_SMALL) } else if (nu == 3) { VDOWN(3, VT_Y_SMALL) } else { VDOWN(4, VT_Y_SMALL) }
+      }
 #undef VDOWN
       continue;
     }
@@ -791,10 +798,14 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     }
     if (tiled(F)) {
       const dim3 gr = tgrid(F);
-#define VUP(NU_)                                                                                      \
-  if (l == 0) k_v_up2d<Lv, R, true, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, sc);       \
-  else k_v_up2d<Lv, R, false, NU_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, sc);
-      if (nu == 2) { VUP(2) } else if (nu == 3) { VUP(3) } else { VUP(4) }
+#define VUP(NU_, TY_)                                                                                      \
+  if (l == 0) k_v_up2d<Lv, R, true, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, sc);       \
+  else k_v_up2d<Lv, R, false, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, sc);
+      if (tile_height(F.nc) == VT_Y_BIG) {
+        if (nu == 2) { VUP(2, VT_Y_BIG) } else if (nu == 3) { VUP(3, VT_Y_BIG) } else { VUP(4, VT_Y_BIG) }
+      } else {
+        if (nu == 2) { VUP(2, VT_Y_SMALL) } else if (nu == 3) { VUP(3, VT_Y_SMALL) } else { VUP(4, VT_Y_SMALL) }
+      }
 #undef VUP
       std::swap(F.x, F.t);
       continue;
@@ -1526,19 +1537,29 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_DOWN:
       case VOS_KERNEL_V_UP: {
         // the tiled 2-D kernels of the finest level
-        const dim3 gr(tile_blocks(lv[0].n[0], lv[0].n[1]));
+        const int ty = tile_height(lv[0].nc);
+        const dim3 gr(tile_blocks(lv[0].n[0], lv[0].n[1], ty));
         const int nu = sweeps(s, 3);
+        const SLevel<R> &F0 = lv[0], &F1 = lv[1];
+#define TDOWN(NU_, TY_) k_v_down2d<SLevel<R>, R, false, NU_, TY_><<<gr, TPB, 0, st>>>(F0, F1, nullptr, nullptr, 1.0, om, flag)
+#define TUP(NU_, TY_) k_v_up2d<SLevel<R>, R, false, NU_, TY_><<<gr, TPB, 0, st>>>(F0, F1, F0.t, om, nullptr, nullptr, flag)
         if (family == VOS_KERNEL_V_DOWN) {
-          if (nu == 2) k_v_down2d<SLevel<R>, R, false, 2><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
-          else if (nu == 3) k_v_down2d<SLevel<R>, R, false, 3><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
-          else k_v_down2d<SLevel<R>, R, false, 4><<<gr, TPB, 0, st>>>(lv[0], lv[1], nullptr, nullptr, 1.0, om, flag);
+          if (ty == VT_Y_BIG) {
+            if (nu == 2) TDOWN(2, VT_Y_BIG); else if (nu == 3) TDOWN(3, VT_Y_BIG); else TDOWN(4, VT_Y_BIG);
+          } else {
+            if (nu == 2) TDOWN(2, VT_Y_SMALL); else if (nu == 3) TDOWN(3, VT_Y_SMALL); else TDOWN(4, VT_Y_SMALL);
+          }
           if (count) { per_seq_bytes += (3.0 + 2 * nd) * Rs * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
         } else {
-          if (nu == 2) k_v_up2d<SLevel<R>, R, false, 2><<<gr, TPB, 0, st>>>(lv[0], lv[1], lv[0].t, om, nullptr, nullptr, flag);
-          else if (nu == 3) k_v_up2d<SLevel<R>, R, false, 3><<<gr, TPB, 0, st>>>(lv[0], lv[1], lv[0].t, om, nullptr, nullptr, flag);
-          else k_v_up2d<SLevel<R>, R, false, 4><<<gr, TPB, 0, st>>>(lv[0], lv[1], lv[0].t, om, nullptr, nullptr, flag);
+          if (ty == VT_Y_BIG) {
+            if (nu == 2) TUP(2, VT_Y_BIG); else if (nu == 3) TUP(3, VT_Y_BIG); else TUP(4, VT_Y_BIG);
+          } else {
+            if (nu == 2) TUP(2, VT_Y_SMALL); else if (nu == 3) TUP(3, VT_Y_SMALL); else TUP(4, VT_Y_SMALL);
+          }
           if (count) { per_seq_bytes += (4.0 + 2 * nd) * Rs * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
         }
+#undef TDOWN
+#undef TUP
         break;
       }
       case VOS_KERNEL_P_APPLY:

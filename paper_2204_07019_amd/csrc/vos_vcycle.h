@@ -209,22 +209,29 @@ __global__ void __launch_bounds__(TPB) k_v_post(Lv F, Lv C, int nd, R *__restric
 //
 // On a 2-D level the launches of a fine level (pre-smoothing sweeps,
 // restriction, prolongation + post-smoothing sweeps) become two: each block
-// owns a VT_X x VT_Y tile and recomputes the NU sweeps on a halo that shrinks
+// owns a VT_X x TY tile and recomputes the NU sweeps on a halo that shrinks
 // by one cell per sweep (tile + NU, ..., tile + 1, tile), so no grid-wide
 // synchronisation is needed between the sweeps.  Grid: tile_of().  Every cell value is formed by
 // the same expression, in the same order, as in the unfused kernels above
 // (sweeps 1-2 as k_v_pre, later pre-sweeps and the residual as k_v_jacobi /
 // k_v_restrict, the first post-sweep as k_v_post, later ones as k_v_jacobi).
 
-constexpr int VT_X = 32, VT_Y = 16;   // tile (both even: aggregates stay inside)
+// Tiles are VT_X wide and TY high (both even: aggregates stay inside): TY =
+// VT_Y_BIG on levels of at least VT_BIG_CELLS cells, where the larger tile
+// halves the halo overhead, VT_Y_SMALL below, where more, smaller blocks
+// shorten the latency-bound legs (micromodel step 2.00 ms with 16 everywhere,
+// 1.88 ms with 4 everywhere).
+constexpr int VT_X = 32, VT_Y_BIG = 16, VT_Y_SMALL = 4;
+constexpr unsigned VT_BIG_CELLS = 1u << 18;
 
 // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs
 // (block b on XCD b % 8), so block b takes tile (b % 8) * per + b / 8 -- each
 // XCD sweeps one contiguous band of tiles, and a tile's halo neighbours are
 // mostly in the same XCD's L2.  Launch per * 8 blocks, per = ceil(tiles / 8).
+template <int TY>
 __device__ __forceinline__ bool tile_of(int nx, int ny, int &tx, int &ty)
 {
-  const int gx = (nx + VT_X - 1) / VT_X, gy = (ny + VT_Y - 1) / VT_Y;
+  const int gx = (nx + VT_X - 1) / VT_X, gy = (ny + TY - 1) / TY;
   const unsigned ntiles = (unsigned)gx * (unsigned)gy;
   const unsigned per = (ntiles + NXCD - 1) / NXCD;
   const unsigned t = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
@@ -234,9 +241,9 @@ __device__ __forceinline__ bool tile_of(int nx, int ny, int &tx, int &ty)
   return true;
 }
 
-template <int NU>
+template <int NU, int TY>
 struct VHalo {
-  static constexpr int W = VT_X + 2 * NU, H = VT_Y + 2 * NU;
+  static constexpr int W = VT_X + 2 * NU, H = TY + 2 * NU;
 };
 
 // Neighbour term from an LDS coefficient: SLevel adds off * x, MgLevel
@@ -332,28 +339,28 @@ __device__ __forceinline__ void tile_stage(const Lv &F, int X0, int Y0, const do
 
 // Owned cell i lies in the tile grown by h cells (the LDS array holds the tile
 // grown by NU).
-template <int NU, typename TC>
+template <int NU, int TY, typename TC>
 __device__ __forceinline__ bool tile_within(const TC &T, int i, int h)
 {
-  return T.in[i] && T.lx[i] >= NU - h && T.lx[i] < NU + VT_X + h && T.ly[i] >= NU - h && T.ly[i] < NU + VT_Y + h;
+  return T.in[i] && T.lx[i] >= NU - h && T.lx[i] < NU + VT_X + h && T.ly[i] >= NU - h && T.ly[i] < NU + TY + h;
 }
 
 // Down leg of a 2-D fine level: NU damped-Jacobi sweeps from zero, then the
 // residual restricted to the coarse right-hand side.  F.x receives the
 // smoothed iterate (tile cells); with FROM64, F.b the scaled right-hand side.
 // Grid: tile_of(), block TPB.
-template <typename Lv, typename R, bool FROM64, int NU>
+template <typename Lv, typename R, bool FROM64, int NU, int TY>
 __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__restrict__ r64,
                                                   const double *__restrict__ dsc, double rscale, R omega,
                                                   const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
+  constexpr int W = VHalo<NU, TY>::W, H = VHalo<NU, TY>::H;
   __shared__ R xa[H][W], xb[H][W];
   const int nx = F.n[0], ny = F.n[1];
   int tx, ty;
-  if (!tile_of(nx, ny, tx, ty)) return;
-  const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;   // global coords of LDS cell (0, 0)
+  if (!tile_of<TY>(nx, ny, tx, ty)) return;
+  const int X0 = tx * VT_X - NU, Y0 = ty * TY - NU;   // global coords of LDS cell (0, 0)
   TileCells<R, W, H> T;
   tile_stage<Lv, R, W, H, FROM64>(F, X0, Y0, r64, dsc, rscale, T);
   constexpr int PER = TileCells<R, W, H>::PER;
@@ -361,7 +368,7 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     if ((int)threadIdx.x + i * TPB >= W * H) continue;
-    if (FROM64 && T.in[i] && tile_within<NU>(T, i, 0))
+    if (FROM64 && T.in[i] && tile_within<NU, TY>(T, i, 0))
       F.b[(unsigned)T.gx[i] + (unsigned)nx * (unsigned)T.gy[i]] = T.b[i];
     xa[T.ly[i]][T.lx[i]] = T.in[i] ? omega * T.b[i] / T.d[i] : (R)0;
   }
@@ -374,7 +381,7 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
     R(*dst)[W] = (k % 2 == 0) ? xb : xa;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      if (!tile_within<NU>(T, i, h)) continue;
+      if (!tile_within<NU, TY>(T, i, h)) continue;
       const int c[3] = {T.gx[i], T.gy[i], 0};
       const int lx = T.lx[i], ly = T.ly[i];
       const R ax = (k == 2) ? tile_apply_off<Lv, R, W>(F, T.o[i], T.d[i], src, lx, ly, c)
@@ -388,7 +395,7 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
   // residual on the tile, x to F.x
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    if (!tile_within<NU>(T, i, 0)) continue;
+    if (!tile_within<NU, TY>(T, i, 0)) continue;
     const int c[3] = {T.gx[i], T.gy[i], 0};
     const int lx = T.lx[i], ly = T.ly[i];
     F.x[(unsigned)T.gx[i] + (unsigned)nx * (unsigned)T.gy[i]] = xf[ly][lx];
@@ -397,9 +404,9 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
   __syncthreads();
   // restriction: sum over each 2 x 2 aggregate (cy outer, cx inner); the tile
   // cells outside the level contribute nothing
-  for (int t = threadIdx.x; t < (VT_X / 2) * (VT_Y / 2); t += TPB) {
+  for (int t = threadIdx.x; t < (VT_X / 2) * (TY / 2); t += TPB) {
     const int ix = t % (VT_X / 2), iy = t / (VT_X / 2);
-    const int IX = tx * (VT_X / 2) + ix, IY = ty * (VT_Y / 2) + iy;
+    const int IX = tx * (VT_X / 2) + ix, IY = ty * (TY / 2) + iy;
     if (IX >= C.n[0] || IY >= C.n[1]) continue;
     R sum = 0;
     for (int cy = 0; cy < 2; ++cy)
@@ -415,17 +422,17 @@ __global__ void __launch_bounds__(TPB) k_v_down2d(Lv F, Lv C, const double *__re
 // post-smoothing sweeps.  Reads F.x, F.b, C.x; writes the result to xo (a
 // buffer other than F.x: neighbouring tiles still read F.x) and, with OUT64,
 // z = unscale(result).
-template <typename Lv, typename R, bool OUT64, int NU>
+template <typename Lv, typename R, bool OUT64, int NU, int TY>
 __global__ void __launch_bounds__(TPB) k_v_up2d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z,
                                                 const double *__restrict__ dsc, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
-  constexpr int W = VHalo<NU>::W, H = VHalo<NU>::H;
+  constexpr int W = VHalo<NU, TY>::W, H = VHalo<NU, TY>::H;
   __shared__ R ya[H][W], yb[H][W];
   const int nx = F.n[0], ny = F.n[1];
   int tx, ty;
-  if (!tile_of(nx, ny, tx, ty)) return;
-  const int X0 = tx * VT_X - NU, Y0 = ty * VT_Y - NU;
+  if (!tile_of<TY>(nx, ny, tx, ty)) return;
+  const int X0 = tx * VT_X - NU, Y0 = ty * TY - NU;
   constexpr int PER = TileCells<R, W, H>::PER;
   // the prolonged iterate, loaded with the other staging loads
   R rv[PER];
@@ -449,7 +456,7 @@ __global__ void __launch_bounds__(TPB) k_v_up2d(Lv F, Lv C, R *__restrict__ xo, 
     R(*dst)[W] = (k % 2 == 1) ? yb : ya;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      if (!tile_within<NU>(T, i, h)) continue;
+      if (!tile_within<NU, TY>(T, i, h)) continue;
       const int c[3] = {T.gx[i], T.gy[i], 0};
       const int lx = T.lx[i], ly = T.ly[i];
       const R ay = (k == 1) ? tile_apply_off<Lv, R, W>(F, T.o[i], T.d[i], src, lx, ly, c)
