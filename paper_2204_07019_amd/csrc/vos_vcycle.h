@@ -219,9 +219,10 @@ __global__ void __launch_bounds__(TPB) k_v_post(Lv F, Lv C, int nd, R *__restric
 // Tiles are VT_X wide and TY high (both even: aggregates stay inside): TY =
 // VT_Y_BIG on levels of at least VT_BIG_CELLS cells, where the larger tile
 // halves the halo overhead, VT_Y_SMALL below, where more, smaller blocks
-// shorten the latency-bound legs (micromodel step 2.00 ms with 16 everywhere,
-// 1.88 ms with 4 everywhere).
-constexpr int VT_X = 32, VT_Y_BIG = 16, VT_Y_SMALL = 4;
+// shorten the latency-bound legs (micromodel step: 2.00 ms with 16
+// everywhere, 1.88 ms with 4 and 1.97 ms with 2 everywhere, 1.87 ms with
+// 16 / 4 and 1.83 ms with 16 / 2).
+constexpr int VT_X = 32, VT_Y_BIG = 16, VT_Y_SMALL = 2;
 constexpr unsigned VT_BIG_CELLS = 1u << 18;
 
 // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs
