@@ -197,6 +197,9 @@ LEVEL_CASES = [  # (shape, precision, extra options): 2-D tiled and 3-D marching
     ((96, 40, 1), 1, {"extrapolate": 2}),
     ((96, 40, 1), 1, {"extrapolate": 2, "setup_every": 2}),
     ((70, 12, 9), 1, {"coarse_cells": 64, "setup_every": 3}),
+    # a finest level of 2^18 cells: the legs there run on the tall tiles
+    ((1024, 256, 1), 0, {}),
+    ((1024, 256, 1), 1, {"extrapolate": 2}),
 ]
 
 
