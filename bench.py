@@ -28,14 +28,36 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per cell of one pressure PCG iteration (each array read or
-# written once per launch): outer FP64 CG 136 B in 2-D (apply 32, x/r update
-# 56, z.r/z.q 24, direction 24), 152 B in 3-D, plus one V-cycle.  2-D V-cycle
-# (tiled kernels): finest level down leg r 8 + diag + 2 face T + b + x + coarse
-# b/4, up leg x + coarse x/4 + b + diag + 2 face T + result + z 8, times 4/3
-# for the coarser levels: FP32 hierarchy 83 B, FP64 144 B.  3-D V-cycle
-# (one launch per sweep, the first two sweeps fused): FP32 187 B, FP64 318 B.
-P_ITER_BYTES = {("mixed", 2): 136 + 83, ("fp64", 2): 136 + 144,
-                ("mixed", 3): 152 + 187, ("fp64", 3): 152 + 318}
+# written once per launch).  Outer FP64 flexible CG: operator p + nd face T + q
+# (8 + 8 nd + 8), x/r update 56 (x, p, q, r, diagonal read; x, r written),
+# z.r and z.q 24, direction 24: 136 B in 2-D, 144 B in 3-D.  One V-cycle with
+# w-byte levels, per fine cell: level 0 reads the FP64 residual and writes the
+# FP64 result (16 B) and each level moves, per level cell,
+#   2-D (one tiled kernel per leg, any number of sweeps): down leg b, diag,
+#     2 face T, x, coarse b/4 (5.25 w); up leg x, coarse x/4, b, diag, 2 T,
+#     result (6.25 w); the coarser levels add 1/3;
+#   3-D (z-marching kernels, one per sweep, the first two down sweeps fused):
+#     first down launch b, diag, 3 face T, x (6 w); each further down sweep
+#     x, b, diag, 3 T, result (7 w); restriction 6 w + coarse b w/8;
+#     prolongation with the first up sweep 7 w + coarse x w/8; each further up
+#     sweep 7 w: (14 nu - 1.75) w, the coarser levels adding 1/7 of that.  On
+#     the finest level every launch but the first forms the diagonal from the
+#     faces it has loaded: 2 nu - 1 fewer reads of w.
+# Pressure sweeps per leg: the library's defaults.
+P_NU = {2: 4, 3: 3}
+
+
+def p_iter_bytes(nd, tag, nu=None):
+    nu = P_NU[nd] if nu is None else nu
+    w = 4 if tag == "mixed" else 8
+    cg = 8 + 8 * nd + 8 + 56 + 24 + 24
+    if nd == 2:
+        return cg + 16 + 11.5 * w * 4 / 3
+    assert nu >= 2, "the first two 3-D down sweeps run fused"
+    per_level = (14 * nu - 1.75) * w
+    return cg + 16 + per_level - (2 * nu - 1) * w + per_level / 7
+
+
 # Krylov iterations per captured chunk on the micromodel: the first host check
 # comes after as many chunks as the last solve of the same kind took, so short
 # chunks waste at most one early-exit iteration (4.00 -> 3.96 ms/step against 4).
@@ -166,7 +188,7 @@ def pressure_3d(vos, inputs, n, dt, precision=None):
     t_p = d["t_ms"][2] * 1e-3
     # iterations run with the FP64 hierarchy (a mixed solve after a stall) move FP64 bytes
     its64 = d["it_p"] if precision == vos.FP64 else d["it_p_fp64"]
-    pb = cells * (P_ITER_BYTES[(tag, 3)] * (d["it_p"] - its64) + P_ITER_BYTES[("fp64", 3)] * its64 +
+    pb = cells * (p_iter_bytes(3, tag) * (d["it_p"] - its64) + p_iter_bytes(3, "fp64") * its64 +
                   P_SETUP_BYTES[3])
     hier = "FP64" if precision == vos.FP64 else "FP32"
     out = {"workload": f"pack {n}^3 dx=4um porosity 0.23 seed 33, {hier} multigrid, rtol 1e-8",
@@ -452,7 +474,7 @@ def main():
     nd = info["ndim"]
     its_p = sum(d["it_p"] for d in diags)
     t_p = sum(d["t_ms"][2] for d in diags) * 1e-3
-    p_bytes = cells * (P_ITER_BYTES[("mixed", nd)] * its_p + P_SETUP_BYTES[nd] * len(diags))
+    p_bytes = cells * (p_iter_bytes(nd, "mixed") * its_p + P_SETUP_BYTES[nd] * len(diags))
     p_gbs = p_bytes / t_p / 1e9
 
     plain = None
@@ -475,7 +497,7 @@ def main():
             its2 = sum(d["it_p"] for d in d2)
             t2 = sum(d["t_ms"][2] for d in d2) * 1e-3
             tag = "fp64" if prec == vos.FP64 else "mixed"
-            pb2 = cells * (P_ITER_BYTES[(tag, nd)] * its2 + P_SETUP_BYTES[nd] * len(d2))
+            pb2 = cells * (p_iter_bytes(nd, tag) * its2 + P_SETUP_BYTES[nd] * len(d2))
             res = {"value": cells * args.steps / el2, "ms_per_step": el2 / args.steps * 1e3,
                    "pressure_its_per_step": its2 / len(d2), "pressure_GBs": pb2 / t2 / 1e9,
                    "transport_its_per_step": sum(d["it_c"] for d in d2) / len(d2)}

@@ -98,8 +98,8 @@ typedef struct {
   int maxit_u, maxit_p, maxit_c;
   int precision;    /* vos_precision (pressure multigrid) */
   int mg_nu;        /* Jacobi sweeps before and after each coarse correction of the pressure
-                       and momentum hierarchies, 1..8; 0: pressure 4 and momentum 2 in 2-D,
-                       2 in 3-D.  The transport hierarchy uses at most 2. */
+                       and momentum hierarchies, 1..8; 0: pressure 4 in 2-D and 3 in 3-D,
+                       momentum 2.  The transport hierarchy uses at most 2. */
   int check_every;  /* Krylov iterations launched between host convergence checks, 1..256; the
                        first check of a solve comes after as many such chunks as fit in the
                        iterations the previous solve of the same system took */

@@ -377,6 +377,7 @@ void fill_levels(vos_sim *s, MgLevel<R> *lv)
       L.T[d] = (R *)(s->ws + s->lo.mgT[l][d]);
     }
     L.nc = ld[l].nc;
+    L.dsum = l == 0;   // k_mg_diag builds the finest diagonal from the faces
     L.diag = (R *)(s->ws + s->lo.mgdiag[l]);
     L.x = (R *)(s->ws + s->lo.mgx[l]);
     L.b = (R *)(s->ws + s->lo.mgb[l]);
@@ -1720,11 +1721,12 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     return fail(VOS_ERR_DEVICE, std::string("stream / event creation: ") + hipGetErrorString(e));
   }
   s->p_scale = 0.0;
-  // defaults (0): in 2-D four sweeps with the tiled fine-level kernels and a
-  // 1024-cell single-block tail; in 3-D two sweeps and a 4096-cell tail
-  // automatic sweeps: 2-D pressure 4 (fewer iterations at the same launch count), 2-D momentum 2
-  // (measured faster per step than 3 or 4 on the micromodel), 3-D 2; transport at most 2
-  if (s->opt.mg_nu == 0) s->opt.mg_nu = grid->nz == 1 ? 4 : 2;
+  // defaults (0): a 1024-cell single-block tail in 2-D, 4096 cells in 3-D.
+  // Sweeps: 2-D pressure 4 (fewer iterations at the same launch count); 3-D
+  // pressure 3 (256^3 sphere pack to 1e-8: 564 iterations in 1.13 s, against
+  // 2158 in 3.25 s with 2 and 500 in 1.25 s with 4); momentum 2 (measured
+  // faster per step than 3 or 4 on the micromodel); transport at most 2
+  if (s->opt.mg_nu == 0) s->opt.mg_nu = grid->nz == 1 ? 4 : 3;
   s->nu_mom = opts->mg_nu == 0 ? 2 : opts->mg_nu;
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? VC_TAIL_2D : VC_BLOCK_MAX);
   s->setup_every = std::max(1, opts->setup_every);

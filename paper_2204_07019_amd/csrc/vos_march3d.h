@@ -75,13 +75,16 @@ __device__ __forceinline__ ZCoef<R> zcoef(const MgLevel<R> &L, unsigned id, cons
   const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
   const unsigned f2 = (unsigned)c[0] + (unsigned)L.fd[2][0] * ((unsigned)c[1] + (unsigned)L.fd[2][1] * c[2]);
   const unsigned sz = (unsigned)L.n[0] * L.n[1];
-  k.d = L.diag[id];
   k.o[0] = L.T[0][f0];
   k.o[1] = L.T[0][f0 + 1];
   k.o[2] = L.T[1][f1];
   k.o[3] = L.T[1][f1 + L.fd[1][0]];
   k.o[4] = L.T[2][f2];
   k.o[5] = L.T[2][f2 + sz];
+  // finest level: the diagonal from the six faces by k_mg_diag's expression
+  // (bitwise the stored value) instead of one more array read
+  if (L.dsum) k.d = (k.o[0] + k.o[1] + k.o[2] + k.o[3]) + (k.o[4] + k.o[5]);
+  else k.d = L.diag[id];
   return k;
 }
 

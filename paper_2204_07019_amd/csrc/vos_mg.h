@@ -29,6 +29,9 @@ struct MgLevel {
   R *T[3];
   R *diag;
   R *x, *b, *t;
+  // 1: diag is the sum of the cell's face coefficients in k_mg_diag's order
+  // (the finest level), so a kernel that has loaded them may form it instead
+  int dsum;
 };
 
 // A x at cell id.  Every load is issued unconditionally (a missing

@@ -122,7 +122,7 @@ class Opts:
     maxit_p: int = 2000
     maxit_c: int = 20000
     precision: int = FP64
-    mg_nu: int = 0          # 0: library default (4 in 2-D, 2 in 3-D)
+    mg_nu: int = 0          # 0: library default (pressure 4 in 2-D, 3 in 3-D; momentum 2)
     check_every: int = 8
     use_graphs: int = 1
     coarse_cells: int = 0
