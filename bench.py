@@ -77,6 +77,35 @@ SETUP_STEPS = 3
 P_SETUP_BYTES = {2: 150, 3: 200}
 
 
+def streaming_ceiling():
+    """HBM bandwidth that plain streaming kernels (torch's own reduction and
+    elementwise kernels) reach on 1 GiB FP64 arrays, beyond the Infinity
+    Cache: context for the roofline fractions, which stay against the
+    published 8 TB/s."""
+    import torch
+    n = 1 << 27
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.rand(n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(x)
+
+    def timed(f, reps=10):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    read = n * 8 / timed(lambda: x.sum()) / 1e9
+    triad = 3 * n * 8 / timed(lambda: torch.add(x, y, alpha=0.5, out=z)) / 1e9
+    del x, y, z
+    return {"read_GBs": round(read, 1), "triad_GBs": round(triad, 1), "arrays": "1 GiB FP64",
+            "kernels": "torch sum, torch add"}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -538,6 +567,8 @@ def main():
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(args.workload, params, args.dt, args.cpu_budget)
 
+    ceiling = streaming_ceiling()
+    log(f"streaming ceiling: read {ceiling['read_GBs']} GB/s, triad {ceiling['triad_GBs']} GB/s")
     last = diags[-1]
     out = {
         "metric": "cell-steps/s + pressure-solve HBM GB/s at 1e-8 residual; learned+mixed vs plain",
@@ -568,6 +599,7 @@ def main():
         "mixed_hierarchies_every_step": every_step,
         "roofline": roof,
         "roofline_other_kernels": others,
+        "hbm_streaming_ceiling": ceiling,
         "pressure_solve_3d": p3d,
         "pressure_solve_3d_mixed": p3d_mixed,
         "batch_micromodels": bat,
