@@ -43,7 +43,8 @@ class _Prob(C.Structure):
                 ("eps_min", C.c_double), ("u_in", C.c_double), ("p_out", C.c_double),
                 ("model", C.c_int),
                 ("rtol_u", C.c_double), ("rtol_p", C.c_double), ("rtol_c", C.c_double),
-                ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int)]
+                ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
+                ("deps_max", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -54,7 +55,7 @@ class _Diag(C.Structure):
                 ("acid_in", C.c_double), ("acid_out", C.c_double), ("acid_consumed", C.c_double),
                 ("solid_rate", C.c_double), ("acid_balance_rel", C.c_double),
                 ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
-                ("max_deps", C.c_double), ("alpha", C.c_double)]
+                ("max_deps", C.c_double), ("alpha", C.c_double), ("dt_solid", C.c_double)]
 
 
 class _Out(C.Structure):
@@ -116,6 +117,7 @@ class Problem:
     maxit_u: int = 200000
     maxit_p: int = 200000
     maxit_c: int = 200000
+    deps_max: float = 0.0   # > 0: largest change of eps per step (Appendix D), by a shorter solid step
 
     def c_struct(self) -> _Prob:
         return _Prob(**asdict(self))

@@ -55,6 +55,8 @@ typedef struct {
   int model;               /* 0 iVoS, 1 VoS-psi (lambda = 4), 2 VoS-psi' */
   double rtol_u, rtol_p, rtol_c;
   int maxit_u, maxit_p, maxit_c;
+  double deps_max;         /* > 0: the solid update's step is shortened so that no cell's
+                              eps changes by more than this (Appendix D); 0: dt */
 } orc_prob;
 
 typedef struct {
@@ -74,6 +76,7 @@ typedef struct {
   double clipped_volume;               /* sum (eps_unclipped - eps_clipped) V  [m3] */
   double max_deps;                     /* max |eps^{n+1} - eps^n| */
   double alpha;                        /* (1/a) sum c|g|V / sum eps c V */
+  double dt_solid;                     /* time step of the solid update        [s] */
 } orc_diag;
 
 /* Optional intermediate outputs of a step (any pointer may be NULL). */
@@ -663,6 +666,7 @@ static int check_prob(const orc_prob *P, double dt)
 {
   if (P->nx < 2 || P->ny < 1 || P->nz < 1 || P->dx <= 0.0 || dt <= 0.0) return ORC_ERR_ARG;
   if (P->mu <= 0.0 || P->rho <= 0.0 || P->k0 <= 0.0 || P->eps_min <= 0.0) return ORC_ERR_ARG;
+  if (!(P->deps_max >= 0.0)) return ORC_ERR_ARG;
   if (P->model < 0 || P->model > 2) return ORC_ERR_ARG;
   return ORC_OK;
 }
@@ -796,10 +800,25 @@ int orc_step(const orc_prob *P, double dt, double *eps, double *ux, double *uy, 
       ec += eps[id] * c[id] * V;
       area += C.gmag[id] * V;
     }
+    /* Appendix D: the largest change of the fluid fraction in a step is held
+       to deps_max, here by shortening the solid update's step when the rates
+       just computed would exceed it: dt_s = min(dt, deps_max / max |Vm Rbar|) */
+    double dts = dt;
+    if (P->deps_max > 0.0) {
+      double m = 0.0;
+      for (long id = 0; id < g.nc; ++id) {
+        double a = fabs(P->Vm * rbar[id]);
+        if (a > m) m = a;
+      }
+      if (m > 0.0) {
+        double lim = P->deps_max / m;
+        dts = lim < dt ? lim : dt;
+      }
+    }
     double clipped = 0.0, maxd = 0.0, dvol = 0.0, sv = 0.0, por = 0.0;
     for (long id = 0; id < g.nc; ++id) {
       double e0 = eps[id];
-      double e1 = e0 + dt * P->Vm * rbar[id];
+      double e1 = e0 + dts * P->Vm * rbar[id];
       double ec1 = e1 < P->eps_min ? P->eps_min : (e1 > 1.0 ? 1.0 : e1);
       clipped += (e1 - ec1) * V;
       dvol += (ec1 - e0) * V;
@@ -819,8 +838,9 @@ int orc_step(const orc_prob *P, double dt, double *eps, double *ux, double *uy, 
     dd.acid_consumed = P->zeta * acid_sink;
     dd.solid_rate = solid_rate;
     dd.acid_balance_rel = ain != 0.0 ? (ain - aout - dd.acid_consumed) / ain : 0.0;
-    double ref = dt * P->Vm * fabs(solid_rate);
-    dd.solid_balance_rel = ref > 0.0 ? (dvol - dt * P->Vm * solid_rate + clipped) / ref : 0.0;
+    double ref = dts * P->Vm * fabs(solid_rate);
+    dd.solid_balance_rel = ref > 0.0 ? (dvol - dts * P->Vm * solid_rate + clipped) / ref : 0.0;
+    dd.dt_solid = dts;
     dd.clipped_volume = clipped;
     dd.max_deps = maxd;
     double a = area / (g.nc * V);

@@ -337,3 +337,34 @@ def test_r_omega_reproduces_table(orc):
         for i, printed in enumerate(g["R_omega_mol_m3_s"][key]):
             r = orc.r_omega(rho_s, M_w, phi[i + 1] - phi[i], g["interval_s"])
             assert abs(r - printed) <= 0.0101, (key, i, r, printed)
+
+
+# ------------------------------------------- largest change of eps (App. D)
+
+def test_solid_step_limit(orc):
+    """Appendix D holds the largest change of the fluid fraction per step to
+    deps_max.  With the limit binding, the step's solves and rates are those
+    of the unlimited step, the change of eps is the unlimited change scaled by
+    dt_solid / dt in every cell that neither run clips, and the largest change
+    equals the limit; a limit above the largest change leaves the step alone."""
+    import copy
+    import dataclasses
+    prob, st = _random_state(orc, steps=2)
+    dt = 1e-3
+    e0 = st.eps.copy()
+    a, b, c = copy.deepcopy(st), copy.deepcopy(st), copy.deepcopy(st)
+    d0 = orc.step(prob, a, dt)
+    assert d0["dt_solid"] == dt and d0["max_deps"] > 0
+    lim = 0.25 * d0["max_deps"]
+    d1 = orc.step(dataclasses.replace(prob, deps_max=lim), b, dt)
+    assert 0 < d1["dt_solid"] < dt
+    assert d1["solid_rate"] == d0["solid_rate"] and d1["it_p"] == d0["it_p"]
+    free = (a.eps > prob.eps_min) & (a.eps < 1.0) & (b.eps > prob.eps_min) & (b.eps < 1.0)
+    assert free.sum() > 0
+    # eps is O(1): its change is known to a few units of 2^-52 after eps^n is subtracted
+    np.testing.assert_allclose((b.eps - e0)[free], (a.eps - e0)[free] * (d1["dt_solid"] / dt),
+                               rtol=1e-12, atol=4 * 2.0 ** -52)
+    assert d1["max_deps"] == pytest.approx(lim, rel=1e-12)
+    assert abs(d1["solid_balance_rel"]) < 1e-10
+    d2 = orc.step(dataclasses.replace(prob, deps_max=4 * d0["max_deps"]), c, dt)
+    assert d2["dt_solid"] == dt and np.array_equal(c.eps, a.eps)
