@@ -139,6 +139,10 @@ typedef struct {
                        earlier step.  The Krylov iteration always applies the current operator,
                        so every solve still meets its tolerance.  The transport hierarchy is
                        rebuilt every step.  0 or 1: every step; <= 1000. */
+  double deps_max;  /* Appendix D's bound on the change of eps per step: > 0 shortens the solid
+                       update of a step to dt_s = min(dt, deps_max / max |Vm Rbar|) over the
+                       cells, with Rbar the rates just computed (the flow and transport solves
+                       keep dt); vos_diag.dt_solid reports dt_s.  0: dt_s = dt.  Finite, >= 0. */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */
@@ -170,6 +174,8 @@ typedef struct {
                                     measured against the converged solution */
   int it_p_fp64;                 /* VOS_MIXED: pressure iterations run with the FP64 hierarchy
                                     after the FP32 one stalled or reached p_fp32_its (0: none) */
+  double dt_solid;               /* time step of the solid update (dt unless vos_opts.deps_max
+                                    shortened it)                          [s] */
 } vos_diag;
 
 /* Fields for vos_set_field / vos_get_field / vos_field_ptr. */

@@ -300,6 +300,7 @@ struct vos_sim {
   SLevel<double> smgd[NSMG][SMG_MAX_LEVELS];
   double *sainv[NSMG];
   double *host;       // pinned scalar read-back buffer
+  bool solid_dt_dev;  // the last solid update took its step from the device (k_solid_dt)
   hipEvent_t ev[7];
   bool use_graphs;
   double p_scale;           // global scale of the pressure hierarchy (set per step)
@@ -428,6 +429,8 @@ vos_status check_opts(const vos_opts *o)
   if (o->p_fp32_its < 0) return fail(VOS_ERR_ARG, "p_fp32_its must be >= 0");
   if (o->extrapolate < 0 || o->extrapolate > 2) return fail(VOS_ERR_ARG, "extrapolate must be 0, 1 or 2");
   if (o->setup_every < 0 || o->setup_every > 1000) return fail(VOS_ERR_ARG, "setup_every must be in [0, 1000]");
+  if (!(o->deps_max >= 0.0) || !std::isfinite(o->deps_max))
+    return fail(VOS_ERR_ARG, "deps_max must be finite and >= 0");
   return VOS_OK;
 }
 
@@ -1301,7 +1304,8 @@ vos_status solve_transport(vos_sim *s, int *its, double *res)
 // ---------------------------------------------------------------- stages S6-S7
 
 // Sum the reaction / update partials into the diag scalar block:
-// [0] sink sum, [1] rate sum, [2..11] k_eps_update slots 0..9, [12] max |d eps|.
+// [0] sink sum, [1] rate sum, [2..11] k_eps_update slots 0..9, [12] max |d eps|
+// ([13]: the shortened solid step, written by k_solid_dt).
 __global__ void k_diag_final(const double *__restrict__ prt, const double *__restrict__ pupd,
                              const double *__restrict__ pmax, int nb, double *__restrict__ out)
 {
@@ -1321,9 +1325,17 @@ void launch_reaction(vos_sim *s, double dt, int freeze)
   const int nb = grid_blocks(g.nc);
   double *prt = s->part + 12 * MAXB;    // 2 slots, kept apart from the update's 10
   k_react<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->c, s->cold, s->w[0], s->w[1], s->w[2], s->gmag,
-                              sc_block(s, SC_MISC), s->rbar, prt);
-  k_eps_update<<<nb, TPB, 0, st>>>(g, s->P, dt, freeze, s->eps, s->rbar, s->c, s->p, s->u[0], s->gmag, s->part,
-                                   s->part_max);
+                              sc_block(s, SC_MISC), s->rbar, prt, s->part_max);
+  // the solid step (slot 13 of the diag block) when it may be shortened;
+  // k_eps_update reuses part_max after k_solid_dt has read it
+  double *dts = nullptr;
+  s->solid_dt_dev = s->opt.deps_max > 0.0 && !freeze;
+  if (s->solid_dt_dev) {
+    dts = sc_block(s, SC_DIAG) + 13;
+    k_solid_dt<<<1, TPB, 0, st>>>(s->part_max, nb, dt, s->opt.deps_max, dts);
+  }
+  k_eps_update<<<nb, TPB, 0, st>>>(g, s->P, dt, dts, freeze, s->eps, s->rbar, s->c, s->p, s->u[0], s->gmag,
+                                   s->part, s->part_max);
   k_diag_final<<<1, TPB, 0, st>>>(prt, s->part, s->part_max, nb, sc_block(s, SC_DIAG));
 }
 
@@ -1331,7 +1343,7 @@ vos_status fill_diag(vos_sim *s, double dt, vos_diag *dg)
 {
   // one synchronisation: lambda (misc block) to host[0], the 13 sums to host[2..14]
   HIP_TRY(hipMemcpyAsync(s->host, sc_block(s, SC_MISC), 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipMemcpyAsync(s->host + 2, sc_block(s, SC_DIAG), 13 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->host + 2, sc_block(s, SC_DIAG), 14 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   const double lam = s->host[0];
   const double *h = s->host + 2;
@@ -1356,8 +1368,10 @@ vos_status fill_diag(vos_sim *s, double dt, vos_diag *dg)
   dg->acid_consumed = s->P.zeta * sink;
   dg->solid_rate = rate;
   dg->acid_balance_rel = dg->acid_in != 0.0 ? (dg->acid_in - dg->acid_out - dg->acid_consumed) / dg->acid_in : 0.0;
-  const double ref = dt * s->P.Vm * std::fabs(rate);
-  dg->solid_balance_rel = ref > 0.0 ? (dvol - dt * s->P.Vm * rate + dg->clipped_volume) / ref : 0.0;
+  dg->dt_solid = s->solid_dt_dev ? h[13] : dt;
+  const double dts = dg->dt_solid;
+  const double ref = dts * s->P.Vm * std::fabs(rate);
+  dg->solid_balance_rel = ref > 0.0 ? (dvol - dts * s->P.Vm * rate + dg->clipped_volume) / ref : 0.0;
   return VOS_OK;
 }
 

@@ -461,11 +461,11 @@ __global__ void __launch_bounds__(TPB) k_react(Dev g, Phys P, const double *__re
                                                const double *__restrict__ w0, const double *__restrict__ w1,
                                                const double *__restrict__ w2, const double *__restrict__ gmag,
                                                const double *__restrict__ lam, double *__restrict__ rbar,
-                                               double *__restrict__ part)
+                                               double *__restrict__ part, double *__restrict__ pmax)
 {
   const double *ww[3] = {w0, w1, w2};
   const double lambda = lam[0];
-  double s_sink = 0.0, s_rate = 0.0;
+  double s_sink = 0.0, s_rate = 0.0, mrate = 0.0;
   for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
@@ -509,19 +509,40 @@ __global__ void __launch_bounds__(TPB) k_react(Dev g, Phys P, const double *__re
       sk = P.kc * lambda * ep * (1.0 - ep) * gmag[id] * c[id] * g.V;
       R = sk;
     }
-    rbar[id] = R / g.V;
+    const double rb = R / g.V;
+    rbar[id] = rb;
+    mrate = fmax(mrate, fabs(P.Vm * rb));
     s_sink += sk;
     s_rate += R;
   }
   const double v[2] = {s_sink, s_rate};
   write_partials<2>(v, part);
+  __shared__ double lds[TPB / 64];
+  const double m = block_max(mrate, lds);
+  if (threadIdx.x == 0) pmax[blockIdx.x] = m;
+}
+
+// Time step of the solid update (Appendix D): min(dt, deps_max / max |Vm Rbar|)
+// from k_react's per-block maxima; dt when no cell reacts.
+__global__ void k_solid_dt(const double *__restrict__ pmax, int nb, double dt, double deps_max,
+                           double *__restrict__ out)
+{
+  const double m = max_partials(pmax, 0, nb);
+  if (threadIdx.x != 0) return;
+  double dts = dt;
+  if (m > 0.0) {
+    const double lim = deps_max / m;
+    dts = lim < dt ? lim : dt;
+  }
+  out[0] = dts;
 }
 
 // Solid update eps <- clip(eps + dt Vm Rbar, eps_min, 1) (Eq. mbs) and the
 // diagnostic sums: 0 clipped, 1 d(eps)V, 2 solid volume, 3 sum eps, 4 inlet
 // acid flux, 5 outlet acid flux, 6 inlet p, 7 sum c|g|V, 8 sum eps c V,
 // 9 sum |g| V; max |d eps| goes to the separate max slot array.
-__global__ void __launch_bounds__(TPB) k_eps_update(Dev g, Phys P, double dt, int freeze, double *__restrict__ eps,
+__global__ void __launch_bounds__(TPB) k_eps_update(Dev g, Phys P, double dt_arg, const double *__restrict__ dtp,
+                                                    int freeze, double *__restrict__ eps,
                                                     const double *__restrict__ rbar, const double *__restrict__ c,
                                                     const double *__restrict__ p, const double *__restrict__ u0,
                                                     const double *__restrict__ gmag, double *__restrict__ part,
@@ -529,6 +550,7 @@ __global__ void __launch_bounds__(TPB) k_eps_update(Dev g, Phys P, double dt, in
 {
   double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   double mx = 0.0;
+  const double dt = dtp ? dtp[0] : dt_arg;   // the shortened solid step when there is one
   for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);

@@ -50,7 +50,8 @@ class _Opts(C.Structure):
                 ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
                 ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int),
                 ("use_graphs", C.c_int), ("coarse_cells", C.c_int), ("level_kernels", C.c_int),
-                ("p_fp32_its", C.c_int), ("extrapolate", C.c_int), ("setup_every", C.c_int)]
+                ("p_fp32_its", C.c_int), ("extrapolate", C.c_int), ("setup_every", C.c_int),
+                ("deps_max", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -63,7 +64,7 @@ class _Diag(C.Structure):
                 ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
                 ("max_deps", C.c_double), ("alpha", C.c_double), ("t_ms", C.c_double * 6),
                 ("guess", C.c_int), ("res0_prev", C.c_double), ("res0_guess", C.c_double),
-                ("guess_error_drop", C.c_double), ("it_p_fp64", C.c_int)]
+                ("guess_error_drop", C.c_double), ("it_p_fp64", C.c_int), ("dt_solid", C.c_double)]
 
 
 _lib = None
@@ -130,6 +131,7 @@ class Opts:
     p_fp32_its: int = 0     # mixed: cap on FP32-preconditioned pressure iterations (0: stall detection only)
     extrapolate: int = 0    # 1: solves start from 2 x^n - x^(n-1) of the last two steps; 2: adaptive quadratic
     setup_every: int = 0    # rebuild the multigrid hierarchies every this many steps (0, 1: every step)
+    deps_max: float = 0.0   # > 0: the solid update's step is cut so that no eps changes by more (Appendix D)
 
 
 class Sim:

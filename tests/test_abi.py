@@ -46,7 +46,8 @@ def test_argument_errors_without_a_device():
     g = vos._Grid(64, 32, 1, 5e-6)
     assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(n)) == vos.VOS_OK
     assert n.value > 64 * 32 * 8 * 20
-    for field, value in (("mg_nu", 9), ("level_kernels", 2), ("p_fp32_its", -1), ("extrapolate", 3), ("setup_every", -1)):
+    for field, value in (("mg_nu", 9), ("level_kernels", 2), ("p_fp32_its", -1), ("extrapolate", 3), ("setup_every", -1),
+                         ("deps_max", -1.0), ("deps_max", float("nan"))):
         bad = vos._Opts(**dict(vos.asdict(vos.Opts()), **{field: value}))
         assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(n)) == vos.VOS_ERR_ARG, field
         assert field.encode() in L.vos_last_error()

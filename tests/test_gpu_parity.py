@@ -94,6 +94,30 @@ def test_extrapolated_starts_match_oracle(orc, precision, extrapolate, setup_eve
         assert dg["it_p"] >= 1 and dg["it_c"] >= 1, dg
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solid_step_limit_matches_oracle(orc, precision):
+    """Appendix D's bound on the change of eps per step (vos_opts.deps_max),
+    set to a third of the post's largest change so that it binds: 8 steps
+    within 1e-6 of the oracle, the shortened solid steps equal to the
+    oracle's, and no cell changing by more than the bound."""
+    import dataclasses
+    import oracle
+    from paper_2204_07019_amd import inputs
+    es, prm = inputs.workload("post")
+    prob = make_problem(es, prm, model=0, **TIGHT)
+    d0 = oracle.step(prob, oracle.initial_state(prob, es), 1e-3)
+    lim = d0["max_deps"] / 3
+    lprob = dataclasses.replace(prob, deps_max=lim)
+    _say(f"post 256x64 deps_max {lim:.3e} precision {precision} 8 steps")
+    st, g, eps0, diags = run_both(es, lprob, 1e-3, 8, precision=precision, deps_max=lim)
+    _compare(st, g, eps0)
+    for do, dg in diags:
+        assert do["dt_solid"] < 1e-3
+        assert dg["dt_solid"] == pytest.approx(do["dt_solid"], rel=1e-6)
+        assert dg["max_deps"] <= lim + 4 * 2.0 ** -52   # eps^n + d - eps^n rounds at the scale of eps
+        assert abs(dg["solid_balance_rel"]) < 1e-9
+
+
 def test_post_stagewise_one_step(orc):
     """Intermediate outputs of one step: momentum predictor, reaction rate, |grad eps|."""
     import oracle
