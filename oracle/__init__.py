@@ -44,7 +44,12 @@ class _Prob(C.Structure):
                 ("model", C.c_int),
                 ("rtol_u", C.c_double), ("rtol_p", C.c_double), ("rtol_c", C.c_double),
                 ("maxit_u", C.c_int), ("maxit_p", C.c_int), ("maxit_c", C.c_int),
-                ("deps_max", C.c_double)]
+                ("deps_max", C.c_double),
+                ("drive", C.c_int), ("p_in", C.c_double), ("convection", C.c_int),
+                ("grad_scheme", C.c_int), ("psi_kind", C.c_int), ("transient", C.c_int),
+                ("Vm_f", C.c_double), ("simple", C.c_int), ("outer_max", C.c_int),
+                ("outer_tol", C.c_double), ("relax_u", C.c_double), ("relax_p", C.c_double),
+                ("relax_c", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -55,7 +60,13 @@ class _Diag(C.Structure):
                 ("acid_in", C.c_double), ("acid_out", C.c_double), ("acid_consumed", C.c_double),
                 ("solid_rate", C.c_double), ("acid_balance_rel", C.c_double),
                 ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
-                ("max_deps", C.c_double), ("alpha", C.c_double), ("dt_solid", C.c_double)]
+                ("max_deps", C.c_double), ("alpha", C.c_double), ("dt_solid", C.c_double),
+                ("U_D", C.c_double), ("R_omega", C.c_double), ("acid_accum", C.c_double),
+                ("outer_its", C.c_int), ("outer_res", C.c_double), ("div_source", C.c_double)]
+
+
+class _Aux(C.Structure):
+    _fields_ = [("eps_prev", C.POINTER(C.c_double)), ("rbar_prev", C.POINTER(C.c_double))]
 
 
 class _Out(C.Structure):
@@ -74,16 +85,16 @@ def lib():
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         L.orc_step.argtypes = [C.POINTER(_Prob), C.c_double, dp, dp, dp, dp, dp, dp,
-                               C.POINTER(_Out), C.POINTER(_Diag)]
+                               C.POINTER(_Aux), C.POINTER(_Out), C.POINTER(_Diag)]
         L.orc_step.restype = C.c_int
         L.orc_eps_from_solid.argtypes = [C.POINTER(_Prob), dp, dp]
         L.orc_assemble.argtypes = [C.POINTER(_Prob), C.c_double, dp, dp, dp, dp, dp, dp,
-                                   C.c_int, dp, dp]
+                                   C.POINTER(_Aux), C.c_int, dp, dp]
         L.orc_assemble.restype = C.c_int
         L.orc_solve_stencil.argtypes = [C.POINTER(C.c_int), dp, dp, dp, C.c_int, C.c_double,
                                         C.c_int, C.POINTER(C.c_int), dp]
         L.orc_solve_stencil.restype = C.c_int
-        L.orc_reaction.argtypes = [C.POINTER(_Prob), C.c_double, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_reaction.argtypes = [C.POINTER(_Prob), C.c_double, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_reaction.restype = C.c_int
         L.orc_vanleer_face.argtypes = [C.c_double] * 3
         L.orc_vanleer_face.restype = C.c_double
@@ -118,6 +129,19 @@ class Problem:
     maxit_p: int = 200000
     maxit_c: int = 200000
     deps_max: float = 0.0   # > 0: largest change of eps per step (Appendix D), by a shorter solid step
+    drive: int = 0          # 0: inlet plug velocity u_in; 1: inlet pressure p_in
+    p_in: float = 0.0
+    convection: int = 0     # 1: explicit first-order upwind momentum convection (Eq. momentumDBS)
+    grad_scheme: int = 0    # 0: central gradient of eps; 1: decentred (VoS-psi variants only)
+    psi_kind: int = 0       # 0: psi = lambda eps (1 - eps); 1: psi = 1
+    transient: int = 0      # 1: storage d(eps c)/dt and the continuity source of Eq. contDBS
+    Vm_f: float = 1e-4      # M_ws / rho of the fluid [m3/mol] (calcite 0.1 kg/mol in water)
+    simple: int = 0         # 1: quasi-static SIMPLE outer loop (Appendices A, B)
+    outer_max: int = 50
+    outer_tol: float = 1e-8
+    relax_u: float = 0.3
+    relax_p: float = 0.3
+    relax_c: float = 1.0
 
     def c_struct(self) -> _Prob:
         return _Prob(**asdict(self))
@@ -150,10 +174,23 @@ class State:
     uz: np.ndarray
     p: np.ndarray
     c: np.ndarray
+    # carried for the transient terms: eps at the previous step's start and the
+    # previous step's reaction rate (None: eps and zeros)
+    eps_prev: np.ndarray = None
+    rbar_prev: np.ndarray = None
+
+    def __post_init__(self):
+        if self.eps_prev is None:
+            self.eps_prev = np.array(self.eps, dtype=np.float64, copy=True)
+        if self.rbar_prev is None:
+            self.rbar_prev = np.zeros_like(self.eps, dtype=np.float64)
 
     def copy(self) -> "State":
         return State(*(np.array(getattr(self, k), dtype=np.float64, copy=True)
-                       for k in ("eps", "ux", "uy", "uz", "p", "c")))
+                       for k in ("eps", "ux", "uy", "uz", "p", "c", "eps_prev", "rbar_prev")))
+
+    def aux(self) -> "_Aux":
+        return _Aux(_ptr(self.eps_prev), _ptr(self.rbar_prev))
 
 
 def eps_from_solid(prob: Problem, eps_s: np.ndarray) -> np.ndarray:
@@ -166,10 +203,11 @@ def eps_from_solid(prob: Problem, eps_s: np.ndarray) -> np.ndarray:
 
 
 def initial_state(prob: Problem, eps_s: np.ndarray) -> State:
-    """Fluid at rest, p = p_out, c = 0 (a seeded start both paths share)."""
+    """Fluid at rest, p = p_out, c = 0 (a seeded start both paths share); the
+    inlet faces carry u_in under the velocity drive, 0 under the pressure drive."""
     eps = eps_from_solid(prob, eps_s)
     ux = np.zeros(prob.face_shape(0))
-    ux[:, :, 0] = prob.u_in
+    ux[:, :, 0] = prob.u_in if prob.drive == 0 else 0.0
     return State(eps=eps, ux=ux, uy=np.zeros(prob.face_shape(1)), uz=np.zeros(prob.face_shape(2)),
                  p=np.full(prob.cell_shape, prob.p_out), c=np.zeros(prob.cell_shape))
 
@@ -191,8 +229,9 @@ def step(prob: Problem, st: State, dt: float, intermediates: bool = False, check
         out.rbar = _ptr(inter["rbar"])
         out.sink = _ptr(inter["sink"])
         out.gmag = _ptr(inter["gmag"])
+    ax = st.aux()
     rc = lib().orc_step(C.byref(pr), dt, _ptr(st.eps), _ptr(st.ux), _ptr(st.uy), _ptr(st.uz),
-                        _ptr(st.p), _ptr(st.c), C.byref(out), C.byref(dg))
+                        _ptr(st.p), _ptr(st.c), C.byref(ax), C.byref(out), C.byref(dg))
     d = {k: (list(getattr(dg, k)) if k in ("it_u", "res_u") else getattr(dg, k))
          for k, _ in _Diag._fields_}
     d["lambda"] = d.pop("lam")
@@ -213,8 +252,9 @@ def assemble(prob: Problem, st: State, dt: float, which: int):
     sten = np.zeros((7, N))
     rhs = np.zeros(N)
     pr = prob.c_struct()
+    ax = st.aux()
     rc = lib().orc_assemble(C.byref(pr), dt, _ptr(st.eps), _ptr(st.ux), _ptr(st.uy), _ptr(st.uz),
-                            _ptr(st.p), _ptr(st.c), which, _ptr(sten), _ptr(rhs))
+                            _ptr(st.p), _ptr(st.c), C.byref(ax), which, _ptr(sten), _ptr(rhs))
     if rc:
         raise RuntimeError(f"orc_assemble failed ({rc})")
     return sten, rhs, tuple(n)
@@ -251,9 +291,11 @@ def solve_stencil(sten: np.ndarray, dims, b: np.ndarray, x0=None, kind: int = 0,
     return x, rc, its.value, rr.value
 
 
-def reaction(prob: Problem, dt: float, eps: np.ndarray, c_new: np.ndarray, c_old=None):
-    """S1 + S6 with a prescribed concentration: returns (Rbar, sink, gmag,
-    lambda, eps_new)."""
+def reaction(prob: Problem, dt: float, eps: np.ndarray, c_new: np.ndarray, c_old=None,
+             return_dt: bool = False):
+    """S1 + S6 + the solid update with a prescribed concentration: returns
+    (Rbar, sink, gmag, lambda, eps_new), plus the solid step taken when
+    return_dt (dt, or shorter under prob.deps_max)."""
     e = np.array(eps, dtype=np.float64, copy=True).reshape(prob.cell_shape)
     cn = np.ascontiguousarray(c_new, dtype=np.float64).reshape(prob.cell_shape)
     co = cn if c_old is None else np.ascontiguousarray(c_old, dtype=np.float64).reshape(prob.cell_shape)
@@ -261,11 +303,14 @@ def reaction(prob: Problem, dt: float, eps: np.ndarray, c_new: np.ndarray, c_old
     sink = np.zeros(prob.cell_shape)
     gmag = np.zeros(prob.cell_shape)
     lam = C.c_double()
+    dts = C.c_double()
     pr = prob.c_struct()
     rc = lib().orc_reaction(C.byref(pr), dt, _ptr(e), _ptr(cn), _ptr(co), _ptr(rbar), _ptr(sink),
-                            _ptr(gmag), C.byref(lam))
+                            _ptr(gmag), C.byref(lam), C.byref(dts))
     if rc:
         raise RuntimeError(f"orc_reaction failed ({rc})")
+    if return_dt:
+        return rbar, sink, gmag, lam.value, e, dts.value
     return rbar, sink, gmag, lam.value, e
 
 
