@@ -21,7 +21,8 @@
  *    nx*ny*(nz+1), indexed the same way over their own dims; face i of the
  *    x grid sits between cells i-1 and i.  nz == 1 is a 2-D problem (no z
  *    faces are used).
- *  - Boundaries: x = 0 inlet (plug velocity u_in, concentration c_in),
+ *  - Boundaries: x = 0 inlet (plug velocity u_in, or with the pressure drive
+ *    pressure p_in and zero normal gradient of u; concentration c_in),
  *    x = nx*dx outlet (pressure p_out, zero normal gradient of u and c),
  *    all other sides no-slip, no-flux walls.
  *  - Memory: the library never allocates device memory.  The caller sizes a
@@ -85,9 +86,22 @@ typedef struct {
   double zeta;      /* stoichiometric coefficient of the acid */
   double c_in;      /* inlet concentration [mol/m3] */
   double eps_min;   /* porosity floor of the solid (Appendix C uses 1e-4) */
-  double u_in;      /* inlet plug velocity [m/s], >= 0 */
+  double u_in;      /* inlet plug velocity [m/s], >= 0 (drive 0) */
   double p_out;     /* outlet pressure [Pa] */
   int model;        /* vos_model */
+  int drive;        /* 0: inlet plug velocity u_in; 1: inlet pressure p_in (Section 3.3 drives its
+                       micro-CT sample at constant pressure); the inlet faces then are unknowns */
+  double p_in;      /* inlet pressure [Pa] (drive 1) */
+  int convection;   /* 1: explicit first-order upwind momentum convection, the u u / eps term of
+                       Eq. momentumDBS (0: creeping flow without it) */
+  int grad_scheme;  /* 0: central gradient of eps; 1: decentred (Section 2.4: per direction the
+                       one-sided difference toward the neighbour of larger eps); VoS-psi only */
+  int psi_kind;     /* 0: psi = lambda eps (1 - eps); 1: psi = 1, i.e. a_s = |grad eps| (Section 2.4);
+                       psi = 1 is for VOS_PSI (lambda is fitted to eps (1 - eps)) */
+  int transient;    /* 1: the transient terms of Section 2.2 -- storage d(eps c)/dt in the transport
+                       equation (Eq. concentrationDBS) and the dissolution source
+                       Rbar (Vm - Vm_f) of Eq. contDBS (lagged rates) in the continuity equation */
+  double Vm_f;      /* M_ws / rho of the fluid [m3/mol] (the source's second term), >= 0 */
 } vos_params;
 
 /* Solver options.  Tolerances are relative Jacobi-scaled residual norms:
@@ -140,9 +154,22 @@ typedef struct {
                        so every solve still meets its tolerance.  The transport hierarchy is
                        rebuilt every step.  0 or 1: every step; <= 1000. */
   double deps_max;  /* Appendix D's bound on the change of eps per step: > 0 shortens the solid
-                       update of a step to dt_s = min(dt, deps_max / max |Vm Rbar|) over the
-                       cells, with Rbar the rates just computed (the flow and transport solves
-                       keep dt); vos_diag.dt_solid reports dt_s.  0: dt_s = dt.  Finite, >= 0. */
+                       update of a step to dt_s = min(dt, deps_max / max |Vm Rbar|), the maximum
+                       over the cells whose distance to the clip bound in the direction of their
+                       change exceeds deps_max, with Rbar the rates just computed (the flow and
+                       transport solves keep dt); vos_diag.dt_solid reports dt_s.  0: dt_s = dt.
+                       Finite, >= 0. */
+  int simple;       /* 1: the quasi-static SIMPLE loop of Appendices A and B instead of one pass:
+                       with eps frozen, steady momentum (Eq. momentumDBSQS, no inertia) under
+                       implicit relaxation relax_u, the SIMPLE pressure correction, explicit
+                       pressure relaxation relax_p, transport (implicit relaxation relax_c),
+                       reaction rate -- repeated until the initial relative residual of every
+                       solve is <= outer_tol (or outer_max times), then the solid update.  dt
+                       then only caps the solid step (with deps_max: adaptive time stepping,
+                       Appendix D).  Not with extrapolate != 0. */
+  int outer_max;    /* SIMPLE: most outer iterations per step, >= 1 */
+  double outer_tol; /* SIMPLE: convergence tolerance on the solves' initial residuals, >= 0 */
+  double relax_u, relax_p, relax_c;  /* SIMPLE under-relaxation factors in (0, 1] (the paper: 0.3) */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */
@@ -153,12 +180,13 @@ typedef struct {
   double solid_volume;           /* sum (1 - eps) V after the update       [m3] */
   double surface_area;           /* sum |grad eps| V at the step's start    [m2] */
   double porosity;               /* mean eps after the update */
-  double dP;                     /* mean inlet-cell p - p_out              [Pa] */
-  double K;                      /* mu u_in (nx - 1/2) dx / dP             [m2] */
+  double dP;                     /* mean inlet-cell p - p_out (drive 1: p_in - p_out) [Pa] */
+  double K;                      /* mu U_D L_D / dP (Section 2.5); L_D = (nx - 1/2) dx from the
+                                    inlet cells (drive 0) or nx dx (drive 1)  [m2] */
   double acid_in, acid_out;      /* inlet / outlet acid flux            [mol/s] */
   double acid_consumed;          /* zeta * sum of the acid sink         [mol/s] */
   double solid_rate;             /* sum Rbar V                          [mol/s] */
-  double acid_balance_rel;       /* (in - out - consumed) / in */
+  double acid_balance_rel;       /* (in - out - consumed - storage) / in */
   double solid_balance_rel;      /* (sum d(eps)V - dt Vm sum Rbar V + clipped) / (dt Vm |sum Rbar V|) */
   double clipped_volume;         /* sum (eps_unclipped - eps_clipped) V    [m3] */
   double max_deps;               /* max |eps^{n+1} - eps^n| */
@@ -176,6 +204,13 @@ typedef struct {
                                     after the FP32 one stalled or reached p_fp32_its (0: none) */
   double dt_solid;               /* time step of the solid update (dt unless vos_opts.deps_max
                                     shortened it)                          [s] */
+  double U_D;                    /* Darcy velocity Q_in / A_in (Section 2.5)  [m/s] */
+  double R_omega;                /* Section 3.3's macroscopic rate: porosity change / (Vm dt_s)
+                                                                         [mol/m3/s] */
+  double acid_accum;             /* transient storage sum (eps c - eps_prev c0) V / dt [mol/s] */
+  int outer_its;                 /* outer iterations of the step (1 for one pass) */
+  double outer_res;              /* largest initial relative residual of the last outer iteration */
+  double div_source;             /* continuity source summed over the cells     [m3/s] */
 } vos_diag;
 
 /* Fields for vos_set_field / vos_get_field / vos_field_ptr. */
@@ -242,6 +277,44 @@ vos_status vos_step(vos_sim *sim, double dt, int nsteps, int flags, vos_diag *la
 /* Diagnostics of the current state without advancing it (iteration counts
  * and balances are those of the last step). */
 vos_status vos_diagnostics(vos_sim *sim, vos_diag *out);
+
+/* The pressure equation alone (stage S3; Eq. contDBSQS combined with the
+ * momentum equation, Appendix B): coefficients from the current eps for a
+ * step of dt [s] (the transmissibilities depend on it), right-hand side
+ * -div(u) + A p from the current face velocities taken as the predictor u*
+ * and the current p (plus the continuity source when transient), solved by
+ * the multigrid-preconditioned flexible CG to opts.rtol_p.  Starts from guess
+ * (nx*ny*nz doubles, device pointer if on_device, else host; NULL: the
+ * current p) and leaves the solution in the P field.  Velocities are not
+ * corrected; eps is not changed.  out (may be NULL) receives it_p, res_p,
+ * it_p_fp64 and t_ms[2].  VOS_ERR_NOCONV if the cap is reached (p then holds
+ * the last iterate). */
+vos_status vos_solve_pressure(vos_sim *sim, double dt, const double *guess, int on_device, vos_diag *out);
+
+/* The set-up of a run from a geometry (not timed): with eps frozen, repeat
+ * the flow stages (coefficients, momentum predictor, pressure, correction)
+ * with steps of dt until the initial relative residuals of the momentum and
+ * pressure solves are <= tol (at most max_iters times), then the
+ * concentration: one transport solve with pure upwind convection, then one
+ * with the van Leer correction lagged on that result.  out (may be NULL):
+ * outer_its (flow iterations), outer_res (the last largest initial residual),
+ * the solves' counts.  VOS_ERR_NOCONV if the flow has not settled within
+ * max_iters (the state is then the last iterate). */
+vos_status vos_initialize(vos_sim *sim, double dt, int max_iters, double tol, vos_diag *out);
+
+/* Checkpoint of the physical state: eps, the face velocities, p, c and the
+ * two arrays the transient terms carry between steps (eps at the previous
+ * step's start, the previous rates), with a header naming the grid.
+ * vos_state_bytes gives the size of that host buffer; vos_get_state fills it
+ * (bytes must be at least that size); vos_set_state restores it into a
+ * simulation of the same grid (VOS_ERR_ARG on a size, grid or format
+ * mismatch).  After a restore every solve starts from the restored state and
+ * rebuilds its hierarchies, so the run continues bitwise as it would have
+ * when extrapolate = 0 and setup_every <= 1, and within the solvers'
+ * tolerances otherwise (extrapolation histories are not part of the state). */
+vos_status vos_state_bytes(vos_sim *sim, size_t *bytes);
+vos_status vos_get_state(vos_sim *sim, void *buf, size_t bytes);
+vos_status vos_set_state(vos_sim *sim, const void *buf, size_t bytes);
 
 /* Kernel families for vos_time_kernel. */
 typedef enum {

@@ -47,8 +47,7 @@ class Batch:
         self.specs = list(specs)
         ol = opts if isinstance(opts, (list, tuple)) else [opts or vos.Opts()] * n
         self._grids = (vos._Grid * n)(*[vos._Grid(nx, ny, nz, dx) for (nx, ny, nz, dx, _) in specs])
-        keys = [k for k, _ in vos._Params._fields_]
-        self._params = (vos._Params * n)(*[vos._Params(**{k: p[k] for k in keys}) for (*_, p) in specs])
+        self._params = (vos._Params * n)(*[vos.make_params(p) for (*_, p) in specs])
         self._opts = (vos._Opts * n)(*[vos._Opts(**asdict(o)) for o in ol])
         nbytes = C.c_size_t()
         vos._check(lib().vos_batch_workspace_bytes(n, self._grids, self._opts, C.byref(nbytes)))

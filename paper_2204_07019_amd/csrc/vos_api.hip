@@ -168,6 +168,7 @@ struct Layout {
   size_t cprev[NHIST], pprev[NHIST];
   size_t tdiag, tdif;
   size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
+  size_t c0, eps_prev;   // transient storage: c at the step's start, eps at the previous step's start
   size_t vec[NVEC];
   size_t part, part2, part_max, scal, ainv;
   size_t mgT[MG_MAX_LEVELS][3], mgdiag[MG_MAX_LEVELS], mgx[MG_MAX_LEVELS], mgb[MG_MAX_LEVELS], mgt[MG_MAX_LEVELS];
@@ -220,6 +221,8 @@ Layout make_layout(const vos_grid &g, int precision)
     Lo.pprev[k] = P.take(nc * dbl);
   }
   Lo.rbar = P.take(nc * dbl);
+  Lo.c0 = P.take(nc * dbl);
+  Lo.eps_prev = P.take(nc * dbl);
   Lo.gmag = P.take(nc * dbl);
   for (int d = 0; d < 3; ++d) Lo.nrm[d] = P.take(nc * dbl);
   Lo.pdiag = P.take(nc * dbl);
@@ -289,6 +292,7 @@ struct vos_sim {
   char *ws;
   double *eps, *p, *c, *pn, *cold, *rbar, *gmag, *nrm[3], *pdiag, *off;
   double *tdiag, *tdif;     // transport rows before scaling: diagonal, diffusive couplings
+  double *c0, *eps_prev;    // transient storage: c at the step's start, eps at the previous step's start
   double *u[3], *ustar[3], *dmom[3], *af[3], *T[3], *w[3];
   double *vec[NVEC];
   double *part, *part_max, *scal, *ainv;
@@ -322,6 +326,7 @@ struct vos_sim {
   double ws_drop;           // decrease of the squared A-norm error the guess achieved
   double ws_frac;           // ws_drop / squared A-norm error of starting from p^n
   int it_p_fp64;            // iterations of the last pressure solve run with the FP64 hierarchy (mixed)
+  double p_res0;            // initial relative residual of the last pressure solve
   bool p_fp64_sticky;       // an FP32 pressure solve stalled on the current geometry (mixed)
   int nu_mom;               // sweeps per leg of the momentum hierarchies
   // extrapolated starts: the solutions of earlier steps, newest first (the host
@@ -431,6 +436,15 @@ vos_status check_opts(const vos_opts *o)
   if (o->setup_every < 0 || o->setup_every > 1000) return fail(VOS_ERR_ARG, "setup_every must be in [0, 1000]");
   if (!(o->deps_max >= 0.0) || !std::isfinite(o->deps_max))
     return fail(VOS_ERR_ARG, "deps_max must be finite and >= 0");
+  if (o->simple != 0 && o->simple != 1) return fail(VOS_ERR_ARG, "simple must be 0 or 1");
+  if (o->simple) {
+    if (o->outer_max < 1) return fail(VOS_ERR_ARG, "outer_max must be >= 1");
+    if (!(o->outer_tol >= 0.0) || !std::isfinite(o->outer_tol)) return fail(VOS_ERR_ARG, "outer_tol must be >= 0");
+    if (!(o->relax_u > 0.0 && o->relax_u <= 1.0) || !(o->relax_p > 0.0 && o->relax_p <= 1.0) ||
+        !(o->relax_c > 0.0 && o->relax_c <= 1.0))
+      return fail(VOS_ERR_ARG, "relaxation factors must be in (0, 1]");
+    if (o->extrapolate) return fail(VOS_ERR_ARG, "extrapolated starts belong to the one-pass step (simple = 0)");
+  }
   return VOS_OK;
 }
 
@@ -441,7 +455,31 @@ vos_status check_params(const vos_params *p)
       !(p->zeta >= 0) || !(p->eps_min > 0 && p->eps_min < 1) || !(p->u_in >= 0))
     return fail(VOS_ERR_ARG, "physical parameters out of range");
   if (p->model < 0 || p->model > 2) return fail(VOS_ERR_ARG, "unknown model");
+  if (p->drive != 0 && p->drive != 1) return fail(VOS_ERR_ARG, "drive must be 0 (velocity) or 1 (pressure)");
+  if (!std::isfinite(p->p_in) || !std::isfinite(p->p_out)) return fail(VOS_ERR_ARG, "pressures must be finite");
+  if (p->convection != 0 && p->convection != 1) return fail(VOS_ERR_ARG, "convection must be 0 or 1");
+  if (p->grad_scheme != 0 && p->grad_scheme != 1) return fail(VOS_ERR_ARG, "grad_scheme must be 0 or 1");
+  if (p->grad_scheme == 1 && p->model == VOS_IVOS)
+    return fail(VOS_ERR_ARG, "the decentred gradient is a VoS-psi variant (iVoS keeps its central normals)");
+  if (p->psi_kind != 0 && p->psi_kind != 1) return fail(VOS_ERR_ARG, "psi_kind must be 0 or 1");
+  if (p->psi_kind == 1 && p->model == VOS_PSI_PRIME)
+    return fail(VOS_ERR_ARG, "VoS-psi' fits lambda to eps (1 - eps): psi = 1 is for VoS-psi");
+  if (p->transient != 0 && p->transient != 1) return fail(VOS_ERR_ARG, "transient must be 0 or 1");
+  if (!(p->Vm_f >= 0.0) || !std::isfinite(p->Vm_f)) return fail(VOS_ERR_ARG, "Vm_f must be finite and >= 0");
   return VOS_OK;
+}
+
+// Device copy of the physical parameters (and the SIMPLE relaxations the kernels apply).
+void fill_phys(Phys &P, const vos_params *params, const vos_opts &o)
+{
+  P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
+  P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
+  P.u_in = params->u_in; P.p_out = params->p_out; P.model = params->model;
+  P.p_in = params->p_in; P.convection = params->convection; P.grad_scheme = params->grad_scheme;
+  P.psi_kind = params->psi_kind; P.transient = params->transient; P.Vm_f = params->Vm_f;
+  P.simple = o.simple;
+  P.relax_u = o.simple ? o.relax_u : 1.0;
+  P.relax_c = o.simple ? o.relax_c : 1.0;
 }
 
 // Host read of n doubles from device memory (synchronises the stream).
@@ -645,7 +683,7 @@ void launch_coefficients(vos_sim *s, double dt)
   if (g.nd == 3)
     k_face_coef<2><<<grid_blocks(g.nf[2]), TPB, 0, st>>>(g, s->P, dt, s->eps, s->dmom[2], s->af[2], s->T[2]);
   const int nb = grid_blocks(g.nc);
-  k_cell_grad<<<nb, TPB, 0, st>>>(g, s->eps, s->gmag, s->nrm[0], s->nrm[1], s->nrm[2], s->part);
+  k_cell_grad<<<nb, TPB, 0, st>>>(g, s->P.grad_scheme, s->eps, s->gmag, s->nrm[0], s->nrm[1], s->nrm[2], s->part);
   k_lambda<<<1, TPB, 0, st>>>(s->part, nb, s->P.model, sc_block(s, SC_MISC));
   k_face_w<0><<<grid_blocks(g.nf[0]), TPB, 0, st>>>(g, s->P.kc, s->nrm[0], s->w[0]);
   k_face_w<1><<<grid_blocks(g.nf[1]), TPB, 0, st>>>(g, s->P.kc, s->nrm[1], s->w[1]);
@@ -846,7 +884,7 @@ void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, co
 // ---------------------------------------------------------------- stage S2
 
 template <int D, typename R>
-vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt, int *its, double *res)
+vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt, int *its, double *res, double *res0)
 {
   const Dev &g = s->g;
   hipStream_t st = ln.st;
@@ -866,7 +904,7 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
     int h = s->hist_u[D] - 1;
     extrapolate(s, st, part, n, x, s->uprev[D], &h, D);
   }
-  k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->u[D], s->p, b, x, ex ? 0 : 1);
+  k_mom_rhs<D><<<nb, TPB, 0, st>>>(g, s->P, dt, s->eps, s->dmom[D], s->u[0], s->u[1], s->u[2], s->p, b, x, ex ? 0 : 1);
   if (hierarchy_due(s, H_MOM + D)) {
     k_smg_from_momentum<R, D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], lv[0]);
     smg_coarsen_all<R>(s, D, lv, st);
@@ -896,15 +934,16 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
   if (s->opt.extrapolate) s->hist_u[D] = conv ? std::min(NHIST + 1, s->hist_u[D] + 1) : 0;
   const double bn2 = ln.host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
+  *res0 = bn2 > 0 ? std::sqrt(ln.host[S_RES0] / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "momentum predictor did not converge");
   return VOS_OK;
 }
 
 template <int D>
-vos_status solve_momentum(vos_sim *s, const Lane &ln, double dt, int *its, double *res)
+vos_status solve_momentum(vos_sim *s, const Lane &ln, double dt, int *its, double *res, double *res0)
 {
-  if (s->opt.precision == VOS_MIXED) return solve_momentum_t<D, float>(s, ln, s->smgf[D], dt, its, res);
-  return solve_momentum_t<D, double>(s, ln, s->smgd[D], dt, its, res);
+  if (s->opt.precision == VOS_MIXED) return solve_momentum_t<D, float>(s, ln, s->smgf[D], dt, its, res, res0);
+  return solve_momentum_t<D, double>(s, ln, s->smgd[D], dt, its, res, res0);
 }
 
 // ---------------------------------------------------------------- stage S3
@@ -1135,8 +1174,16 @@ vos_status warm_start(vos_sim *s, const double *b, double *q, double *rd, double
   return VOS_OK;
 }
 
+// Sum of the continuity source's partials into slot 16 of the diag block.
+__global__ void k_src_sum(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+  const double v = sum_partials(part, 0, nb);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
 template <typename R>
-vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int h, int *its, double *res)
+vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int h, int *its, double *res, double *res0,
+                            const double *guess)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
@@ -1148,10 +1195,15 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int h, int *its
   const double rt2 = s->opt.rtol_p * s->opt.rtol_p;
   if (hierarchy_due(s, h)) mg_setup<R>(s, lv);
   HIP_TRY(hipMemcpyAsync(s->pn, s->p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (s->opt.extrapolate && !s->net) {   // the start only; the right-hand side keeps p^n (pn)
+  if (guess) {   // a caller's start (vos_solve_pressure); the right-hand side keeps p^n (pn)
+    HIP_TRY(hipMemcpyAsync(s->p, guess, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else if (s->opt.extrapolate && !s->net) {   // the start only; the right-hand side keeps p^n (pn)
     extrapolate(s, st, s->part, n, s->p, s->pprev, &s->hist_p, 3);
   }
-  k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b);
+  const bool src = s->P.transient != 0;
+  k_p_rhs<<<nb, TPB, 0, st>>>(g, s->T[0], s->T[1], s->T[2], s->pn, s->ustar[0], s->ustar[1], s->ustar[2], b,
+                              src ? s->rbar : nullptr, s->P.Vm - s->P.Vm_f, s->part);
+  if (src) k_src_sum<<<1, TPB, 0, st>>>(s->part, nb, sc_block(s, SC_DIAG) + 16);
   if (s->net)
     if (vos_status e = warm_start(s, b, q, z, pv, zero_flag)) return e;
   p_apply(s, s->p, q, zero_flag);
@@ -1182,6 +1234,7 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int h, int *its
   s->it_p_fp64 = 0;
   vos_status stt = krylov_loop(s, main_lane(s), gid, sc, s->opt.maxit_p, iter, its, &res2, &tol2, &conv, mixed ? &stall : nullptr);
   if (stt) return stt;
+  s->p_res0 = s->host[S_BN2] > 0 ? std::sqrt(s->host[S_RES0] / s->host[S_BN2]) : 0.0;
   if (!mixed && s->opt.precision == VOS_MIXED) s->it_p_fp64 = *its;   // a solve after an FP32 stall
   if (stall.hit && !conv) {
     if (!stall.by_cap) s->p_fp64_sticky = true;   // later solves of this geometry start in FP64
@@ -1218,17 +1271,19 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int h, int *its
   }
   const double bn2 = s->host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
+  *res0 = s->p_res0;
   if (!conv) return fail(VOS_ERR_NOCONV, "pressure solve did not converge");
   return VOS_OK;
 }
 
-vos_status solve_pressure(vos_sim *s, int *its, double *res)
+vos_status solve_pressure(vos_sim *s, int *its, double *res, double *res0, const double *guess = nullptr)
 {
   // mixed precision: the FP32 hierarchy until one of its solves stalls on this geometry, then
   // FP64 (its iteration chunk captured under its own graph slot)
-  if (s->opt.precision == VOS_MIXED && !s->p_fp64_sticky) return solve_pressure_t<float>(s, s->mgf, 3, H_P, its, res);
+  if (s->opt.precision == VOS_MIXED && !s->p_fp64_sticky)
+    return solve_pressure_t<float>(s, s->mgf, 3, H_P, its, res, res0, guess);
   const bool mixed = s->opt.precision == VOS_MIXED;
-  return solve_pressure_t<double>(s, s->mgd, mixed ? 5 : 3, mixed ? H_P64 : H_P, its, res);
+  return solve_pressure_t<double>(s, s->mgd, mixed ? 5 : 3, mixed ? H_P64 : H_P, its, res, res0, guess);
 }
 
 // ---------------------------------------------------------------- stage S4
@@ -1245,7 +1300,7 @@ void launch_correct(vos_sim *s)
 // ---------------------------------------------------------------- stage S5
 
 template <typename R>
-vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
+vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *its, double *res, double *res0)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
@@ -1261,8 +1316,12 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   if (s->opt.extrapolate) {   // the start only; the deferred correction keeps c^n (cold)
     extrapolate(s, st, s->part, n, s->c, s->cprev, &s->hist_c, 4);
   }
-  k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2], s->cold,
-                                     s->gmag, sc_block(s, SC_MISC), s->off, b, s->tdiag, s->tdif);
+  auto assemble = [&]() {
+    k_adr_assemble<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->u[0], s->u[1], s->u[2], s->w[0], s->w[1], s->w[2],
+                                       s->cold, s->gmag, sc_block(s, SC_MISC), s->off, b, s->tdiag, s->tdif, vl, dt,
+                                       s->eps_prev, s->c0);
+  };
+  assemble();
   // rebuilt every step: a transport hierarchy one step old can stall BiCGStab on
   // strongly reactive instances (Da ~ 1), where the rows change most between steps
   k_smg_from_transport<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, s->tdiag, s->tdif, lv[0]);
@@ -1290,60 +1349,98 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, int *its, double *res)
   bool conv;
   vos_status stt = krylov_loop(s, main_lane(s), 4, sc, s->opt.maxit_c, iter, its, &res2, &tol2, &conv);
   if (stt) return stt;
-  const double bn2 = s->host[S_BN2];
+  double bn2 = s->host[S_BN2];
+  *res0 = bn2 > 0 ? std::sqrt(s->host[S_RES0] / bn2) : 0.0;
+  // BiCGStab's recurrence residual drifts from b - A c; accept convergence only
+  // once the true residual meets the tolerance, else restart from the iterate
+  // (the right-hand side b served the iterations as scratch: it is assembled again)
+  for (int restart = 0; conv && restart < 4; ++restart) {
+    assemble();
+    k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
+    k_bi_true_res<<<nb, TPB, 0, st>>>(n, b, y, s->part);
+    k_bi_true_scal<<<1, TPB, 0, st>>>(s->part, nb, sc);
+    HIP_TRY(hipGetLastError());
+    if (vos_status e = read_back(s, sc, S_COUNT)) return e;
+    if (s->host[S_TRUE] <= s->host[S_TOL2]) { res2 = s->host[S_TRUE]; break; }
+    int more = 0;
+    k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
+    k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
+    stt = krylov_loop(s, main_lane(s), 4, sc, std::max(1, s->opt.maxit_c - *its), iter, &more, &res2, &tol2, &conv);
+    if (stt) return stt;
+    *its += more;
+  }
+  bn2 = s->host[S_BN2];
   *res = bn2 > 0 ? std::sqrt(res2 / bn2) : 0.0;
   if (!conv) return fail(VOS_ERR_NOCONV, "transport solve did not converge");
   return VOS_OK;
 }
 
-vos_status solve_transport(vos_sim *s, int *its, double *res)
+vos_status solve_transport(vos_sim *s, double dt, int *its, double *res, double *res0, int vl = 1)
 {
-  return solve_transport_t<double>(s, s->smgd[3], its, res);   // FP64 hierarchy in both precisions
+  return solve_transport_t<double>(s, s->smgd[3], dt, vl, its, res, res0);   // FP64 hierarchy in both precisions
 }
 
 // ---------------------------------------------------------------- stages S6-S7
 
 // Sum the reaction / update partials into the diag scalar block:
-// [0] sink sum, [1] rate sum, [2..11] k_eps_update slots 0..9, [12] max |d eps|
-// ([13]: the shortened solid step, written by k_solid_dt).
+// [0] sink sum, [1] rate sum, [2..13] k_eps_update slots 0..11, [14] max |d eps|
+// ([15]: the shortened solid step, written by k_solid_dt; [16]: the continuity
+// source sum, written by k_src_sum).
 __global__ void k_diag_final(const double *__restrict__ prt, const double *__restrict__ pupd,
                              const double *__restrict__ pmax, int nb, double *__restrict__ out)
 {
-  double v[13];
+  double v[15];
   v[0] = sum_partials(prt, 0, nb);
   v[1] = sum_partials(prt, 1, nb);
-  for (int q = 0; q < 10; ++q) v[2 + q] = sum_partials(pupd, q, nb);
-  v[12] = max_partials(pmax, 0, nb);
+  for (int q = 0; q < 12; ++q) v[2 + q] = sum_partials(pupd, q, nb);
+  v[14] = max_partials(pmax, 0, nb);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 13; ++q) out[q] = v[q];
+    for (int q = 0; q < 15; ++q) out[q] = v[q];
 }
 
-void launch_reaction(vos_sim *s, double dt, int freeze)
+// p = pn + relax (p - pn): SIMPLE's explicit pressure under-relaxation.
+__global__ void k_relax(unsigned n, double relax, const double *__restrict__ pn, double *__restrict__ p)
+{
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = pn[i] + relax * (p[i] - pn[i]);
+}
+
+// Partials of the rates: 2 slots after the update's 12.
+double *rate_partials(vos_sim *s) { return s->part + 12 * MAXB; }
+
+// Reaction rates Rbar from the current c (S6); the per-block maxima of the
+// rates that may set the solid step go to part_max.
+void launch_rates(vos_sim *s)
+{
+  const Dev &g = s->g;
+  k_react<<<grid_blocks(g.nc), TPB, 0, s->stream>>>(g, s->P, s->eps, s->c, s->cold, s->w[0], s->w[1], s->w[2],
+                                                     s->gmag, sc_block(s, SC_MISC), s->rbar, rate_partials(s),
+                                                     s->part_max, s->opt.deps_max);
+}
+
+// Solid update (S7) from the rates of launch_rates, and the diagnostic sums.
+void launch_update(vos_sim *s, double dt, int freeze)
 {
   const Dev &g = s->g;
   hipStream_t st = s->stream;
   const int nb = grid_blocks(g.nc);
-  double *prt = s->part + 12 * MAXB;    // 2 slots, kept apart from the update's 10
-  k_react<<<nb, TPB, 0, st>>>(g, s->P, s->eps, s->c, s->cold, s->w[0], s->w[1], s->w[2], s->gmag,
-                              sc_block(s, SC_MISC), s->rbar, prt, s->part_max);
-  // the solid step (slot 13 of the diag block) when it may be shortened;
+  // the solid step (slot 15 of the diag block) when it may be shortened;
   // k_eps_update reuses part_max after k_solid_dt has read it
   double *dts = nullptr;
   s->solid_dt_dev = s->opt.deps_max > 0.0 && !freeze;
   if (s->solid_dt_dev) {
-    dts = sc_block(s, SC_DIAG) + 13;
+    dts = sc_block(s, SC_DIAG) + 15;
     k_solid_dt<<<1, TPB, 0, st>>>(s->part_max, nb, dt, s->opt.deps_max, dts);
   }
   k_eps_update<<<nb, TPB, 0, st>>>(g, s->P, dt, dts, freeze, s->eps, s->rbar, s->c, s->p, s->u[0], s->gmag,
-                                   s->part, s->part_max);
-  k_diag_final<<<1, TPB, 0, st>>>(prt, s->part, s->part_max, nb, sc_block(s, SC_DIAG));
+                                   s->part, s->part_max, s->eps_prev, s->c0);
+  k_diag_final<<<1, TPB, 0, st>>>(rate_partials(s), s->part, s->part_max, nb, sc_block(s, SC_DIAG));
 }
 
 vos_status fill_diag(vos_sim *s, double dt, vos_diag *dg)
 {
-  // one synchronisation: lambda (misc block) to host[0], the 13 sums to host[2..14]
+  // one synchronisation: lambda (misc block) to host[0], the 17 sums to host[2..18]
   HIP_TRY(hipMemcpyAsync(s->host, sc_block(s, SC_MISC), 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipMemcpyAsync(s->host + 2, sc_block(s, SC_DIAG), 14 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->host + 2, sc_block(s, SC_DIAG), 17 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   const double lam = s->host[0];
   const double *h = s->host + 2;
@@ -1358,21 +1455,81 @@ vos_status fill_diag(vos_sim *s, double dt, vos_diag *dg)
   dg->acid_in = h[6];
   dg->acid_out = h[7];
   const double nin = (double)g.n[1] * g.n[2];
-  dg->dP = h[8] / nin - s->P.p_out;
-  dg->K = dg->dP != 0.0 ? s->P.mu * s->P.u_in * (g.n[0] - 0.5) * g.dx / dg->dP : 0.0;
+  dg->U_D = h[12] / (nin * g.S);
+  if (g.drive) {
+    dg->dP = s->P.p_in - s->P.p_out;
+    dg->K = dg->dP != 0.0 ? s->P.mu * dg->U_D * g.n[0] * g.dx / dg->dP : 0.0;
+  } else {
+    dg->dP = h[8] / nin - s->P.p_out;
+    dg->K = dg->dP != 0.0 ? s->P.mu * s->P.u_in * (g.n[0] - 0.5) * g.dx / dg->dP : 0.0;
+  }
   const double cg = h[9], ec = h[10], area = h[11];
   dg->surface_area = area;
   const double a = area / (g.nc * V);
   dg->alpha = (a > 0.0 && ec > 0.0) ? cg / (a * ec) : 0.0;
-  dg->max_deps = h[12];
+  dg->acid_accum = s->P.transient ? h[13] : 0.0;
+  dg->max_deps = h[14];
   dg->acid_consumed = s->P.zeta * sink;
   dg->solid_rate = rate;
-  dg->acid_balance_rel = dg->acid_in != 0.0 ? (dg->acid_in - dg->acid_out - dg->acid_consumed) / dg->acid_in : 0.0;
-  dg->dt_solid = s->solid_dt_dev ? h[13] : dt;
+  dg->acid_balance_rel =
+      dg->acid_in != 0.0 ? (dg->acid_in - dg->acid_out - dg->acid_consumed - dg->acid_accum) / dg->acid_in : 0.0;
+  dg->dt_solid = s->solid_dt_dev ? h[15] : dt;
+  dg->div_source = s->P.transient ? h[16] : 0.0;
   const double dts = dg->dt_solid;
   const double ref = dts * s->P.Vm * std::fabs(rate);
   dg->solid_balance_rel = ref > 0.0 ? (dvol - dts * s->P.Vm * rate + dg->clipped_volume) / ref : 0.0;
+  dg->R_omega = s->P.Vm > 0.0 ? dvol / ((double)g.nc * V) / (s->P.Vm * dts) : 0.0;
   return VOS_OK;
+}
+
+// The momentum predictor of every component (S2): components 0 (then 2) and 1
+// on the two momentum lanes, 1 driven from a second host thread; returns the
+// largest initial relative residual of the three solves in *r0.
+vos_status momentum_stage(vos_sim *s, double dt, vos_diag *dg, double *r0, vos_status *rc)
+{
+  hipStream_t st = s->stream;
+  HIP_TRY(hipEventRecord(s->fork, st));
+  HIP_TRY(hipStreamWaitEvent(s->lane_stream[0], s->fork, 0));
+  HIP_TRY(hipStreamWaitEvent(s->lane_stream[1], s->fork, 0));
+  vos_status r1 = VOS_OK;
+  std::string m1;
+  double q[3] = {0.0, 0.0, 0.0};
+  std::thread t1([&]() {
+    r1 = solve_momentum<1>(s, momentum_lane(s, 1), dt, &dg->it_u[1], &dg->res_u[1], &q[1]);
+    if (r1) m1 = vos_last_error();
+  });
+  const Lane l0 = momentum_lane(s, 0);
+  vos_status r0s = solve_momentum<0>(s, l0, dt, &dg->it_u[0], &dg->res_u[0], &q[0]);
+  std::string m0 = r0s ? std::string(vos_last_error()) : std::string();
+  vos_status r3 = VOS_OK;
+  if (s->g.nd == 3 && r0s != VOS_ERR_DEVICE) r3 = solve_momentum<2>(s, l0, dt, &dg->it_u[2], &dg->res_u[2], &q[2]);
+  std::string m3 = r3 ? std::string(vos_last_error()) : std::string();
+  t1.join();
+  for (int k = 0; k < 2; ++k) {
+    HIP_TRY(hipEventRecord(s->join[k], s->lane_stream[k]));
+    HIP_TRY(hipStreamWaitEvent(st, s->join[k], 0));
+  }
+  *r0 = std::max(q[0], std::max(q[1], q[2]));
+  // component order for the reported status: 0, 1, 2 (device errors end the step)
+  const vos_status rr[3] = {r0s, r1, r3};
+  const std::string *mm[3] = {&m0, &m1, &m3};
+  for (int k = 0; k < 3; ++k)
+    if (rr[k] == VOS_ERR_DEVICE) return fail(rr[k], *mm[k]);
+  for (int k = 0; k < 3; ++k)
+    if (rr[k] && !*rc) *rc = fail(rr[k], *mm[k]);
+  return VOS_OK;
+}
+
+// New time-step size: the captured V-cycles and the pressure hierarchy hold
+// 1/p_scale, which depends on it.
+void set_time_step(vos_sim *s, double dt)
+{
+  const double ps = pressure_scale(s, dt);
+  if (ps != s->p_scale) {
+    drop_graphs(s);
+    s->p_scale = ps;
+    s->mg_age[H_P] = s->mg_age[H_P64] = 1 << 30;
+  }
 }
 
 vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
@@ -1380,72 +1537,64 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
   hipStream_t st = s->stream;
   std::memset(dg, 0, sizeof(*dg));
   vos_status rc = VOS_OK, r2;
+  set_time_step(s, dt);
   HIP_TRY(hipEventRecord(s->ev[0], st));
-  const double ps = pressure_scale(s, dt);
-  if (ps != s->p_scale) {   // captured V-cycles and the pressure hierarchy hold 1/p_scale
-    drop_graphs(s);
-    s->p_scale = ps;
-    s->mg_age[H_P] = s->mg_age[H_P64] = 1 << 30;
-  }
+  if (s->P.transient)   // c at the step's start, for the storage term
+    HIP_TRY(hipMemcpyAsync(s->c0, s->c, s->g.nc * sizeof(double), hipMemcpyDeviceToDevice, st));
   launch_coefficients(s, dt);
-  HIP_TRY(hipEventRecord(s->ev[1], st));
-  // The momentum components are independent systems: components 0 (then 2)
-  // and 1 run on the two momentum lanes, 1 driven from a second host thread.
-  {
-    HIP_TRY(hipEventRecord(s->fork, st));
-    HIP_TRY(hipStreamWaitEvent(s->lane_stream[0], s->fork, 0));
-    HIP_TRY(hipStreamWaitEvent(s->lane_stream[1], s->fork, 0));
-    vos_status r1 = VOS_OK;
-    std::string m1;
-    std::thread t1([&]() {
-      r1 = solve_momentum<1>(s, momentum_lane(s, 1), dt, &dg->it_u[1], &dg->res_u[1]);
-      if (r1) m1 = vos_last_error();
-    });
-    const Lane l0 = momentum_lane(s, 0);
-    vos_status r0 = solve_momentum<0>(s, l0, dt, &dg->it_u[0], &dg->res_u[0]);
-    std::string m0 = r0 ? std::string(vos_last_error()) : std::string();
-    vos_status r3 = VOS_OK;
-    if (s->g.nd == 3 && r0 != VOS_ERR_DEVICE) r3 = solve_momentum<2>(s, l0, dt, &dg->it_u[2], &dg->res_u[2]);
-    std::string m3 = r3 ? std::string(vos_last_error()) : std::string();
-    t1.join();
-    for (int k = 0; k < 2; ++k) {
-      HIP_TRY(hipEventRecord(s->join[k], s->lane_stream[k]));
-      HIP_TRY(hipStreamWaitEvent(st, s->join[k], 0));
+  float ms = 0.f;
+  // one pass, or the SIMPLE loop (Appendix B) with eps frozen until every
+  // solve starts within outer_tol of its solution
+  const int nout = s->opt.simple ? s->opt.outer_max : 1;
+  for (int it = 0; it < nout; ++it) {
+    double q = 0.0, worst = 0.0;
+    HIP_TRY(hipEventRecord(s->ev[1], st));
+    if (vos_status e = momentum_stage(s, dt, dg, &q, &rc)) return e;
+    worst = std::max(worst, q);
+    HIP_TRY(hipEventRecord(s->ev[2], st));
+    r2 = solve_pressure(s, &dg->it_p, &dg->res_p, &q);
+    if (r2 == VOS_ERR_DEVICE) return r2;
+    if (r2 && !rc) rc = r2;
+    worst = std::max(worst, q);
+    dg->guess = s->net ? s->ws_used : -1;
+    dg->res0_prev = s->net ? s->ws_res_prev : 0.0;
+    dg->res0_guess = s->net ? s->ws_res_guess : 0.0;
+    dg->guess_error_drop = s->net ? s->ws_frac : 0.0;
+    dg->it_p_fp64 = s->it_p_fp64;
+    HIP_TRY(hipEventRecord(s->ev[3], st));
+    launch_correct(s);
+    if (s->opt.simple) k_relax<<<grid_blocks(s->g.nc), TPB, 0, st>>>(s->g.nc, s->opt.relax_p, s->pn, s->p);
+    HIP_TRY(hipEventRecord(s->ev[4], st));
+    r2 = solve_transport(s, dt, &dg->it_c, &dg->res_c, &q);
+    if (r2 == VOS_ERR_DEVICE) return r2;
+    if (r2 && !rc) rc = r2;
+    worst = std::max(worst, q);
+    HIP_TRY(hipEventRecord(s->ev[5], st));
+    launch_rates(s);
+    HIP_TRY(hipEventRecord(s->ev[6], st));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventSynchronize(s->ev[6]));
+    if (it == 0) {   // coefficients: from the step's start to the first momentum stage
+      HIP_TRY(hipEventElapsedTime(&ms, s->ev[0], s->ev[1]));
+      dg->t_ms[0] = ms;
     }
-    // component order for the reported status: 0, 1, 2 (device errors end the step)
-    const vos_status rr[3] = {r0, r1, r3};
-    const std::string *mm[3] = {&m0, &m1, &m3};
-    for (int k = 0; k < 3; ++k)
-      if (rr[k] == VOS_ERR_DEVICE) return fail(rr[k], *mm[k]);
-    for (int k = 0; k < 3; ++k)
-      if (rr[k] && !rc) rc = fail(rr[k], *mm[k]);
+    for (int k = 1; k < 6; ++k) {
+      HIP_TRY(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
+      dg->t_ms[k] += ms;
+    }
+    dg->outer_its = it + 1;
+    dg->outer_res = worst;
+    if (rc) break;
+    if (s->opt.simple && worst <= s->opt.outer_tol) break;
   }
-  HIP_TRY(hipEventRecord(s->ev[2], st));
-  r2 = solve_pressure(s, &dg->it_p, &dg->res_p);
-  if (r2 == VOS_ERR_DEVICE) return r2;
-  if (r2 && !rc) rc = r2;
-  dg->guess = s->net ? s->ws_used : -1;
-  dg->res0_prev = s->net ? s->ws_res_prev : 0.0;
-  dg->res0_guess = s->net ? s->ws_res_guess : 0.0;
-  dg->guess_error_drop = s->net ? s->ws_frac : 0.0;
-  dg->it_p_fp64 = s->it_p_fp64;
-  HIP_TRY(hipEventRecord(s->ev[3], st));
-  launch_correct(s);
-  HIP_TRY(hipEventRecord(s->ev[4], st));
-  r2 = solve_transport(s, &dg->it_c, &dg->res_c);
-  if (r2 == VOS_ERR_DEVICE) return r2;
-  if (r2 && !rc) rc = r2;
   HIP_TRY(hipEventRecord(s->ev[5], st));
-  launch_reaction(s, dt, flags & VOS_FREEZE_SOLID);
+  launch_update(s, dt, flags & VOS_FREEZE_SOLID);
   HIP_TRY(hipEventRecord(s->ev[6], st));
   HIP_TRY(hipGetLastError());
   r2 = fill_diag(s, dt, dg);
   if (r2) return r2;
-  for (int k = 0; k < 6; ++k) {
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
-    dg->t_ms[k] = ms;
-  }
+  HIP_TRY(hipEventElapsedTime(&ms, s->ev[5], s->ev[6]));
+  dg->t_ms[5] += ms;
   if (rc) {
     std::string m = g_err;
     return fail(rc, m);
@@ -1490,6 +1639,10 @@ __global__ void k_fill(unsigned n, double v, double *__restrict__ a)
 {
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) a[i] = v;
 }
+
+// Velocity the inlet faces start from: u_in under the velocity drive, rest
+// (0) under the pressure drive, where they are unknowns.
+double inlet_velocity(const vos_sim *s) { return s->g.drive ? 0.0 : s->P.u_in; }
 
 // Inlet faces (i = 0) of the x grid get u_in.
 __global__ void k_inlet(Dev g, double u_in, double *__restrict__ ux)
@@ -1670,10 +1823,9 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   }
   g.nc = (unsigned)grid->nx * grid->ny * grid->nz;
   g.dx = grid->dx; g.S = grid->dx * grid->dx; g.V = g.S * grid->dx;
+  g.drive = params->drive;
   Phys &P = s->P;
-  P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
-  P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
-  P.u_in = params->u_in; P.p_out = params->p_out; P.model = params->model;
+  fill_phys(P, params, *opts);
   char *w = s->ws;
   auto D = [&](size_t o) { return (double *)(w + o); };
   s->eps = D(lo.eps); s->p = D(lo.p); s->c = D(lo.c); s->pn = D(lo.pn); s->cold = D(lo.cold);
@@ -1683,6 +1835,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     for (int d = 0; d < 3; ++d) s->uprev[d][k] = D(lo.uprev[d][k]);
   }
   s->rbar = D(lo.rbar); s->gmag = D(lo.gmag); s->pdiag = D(lo.pdiag); s->off = D(lo.off);
+  s->c0 = D(lo.c0); s->eps_prev = D(lo.eps_prev);
   s->tdiag = D(lo.tdiag); s->tdif = D(lo.tdif);
   for (int d = 0; d < 3; ++d) {
     s->nrm[d] = D(lo.nrm[d]); s->u[d] = D(lo.u[d]); s->ustar[d] = D(lo.ustar[d]); s->dmom[d] = D(lo.dmom[d]);
@@ -1750,12 +1903,13 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
     s->last_its[k] = 0;
   }
 
-  // initial state: fluid at rest, p = p_out, c = 0, eps = 1
+  // initial state: fluid at rest, p = p_out, c = 0, eps = eps_prev = 1, no earlier rates
   hipStream_t stq = s->stream;
   HIP_TRY(hipMemsetAsync(s->ws, 0, lo.total, stq));
   k_fill<<<grid_blocks(g.nc), TPB, 0, stq>>>(g.nc, 1.0, s->eps);
+  k_fill<<<grid_blocks(g.nc), TPB, 0, stq>>>(g.nc, 1.0, s->eps_prev);
   k_fill<<<grid_blocks(g.nc), TPB, 0, stq>>>(g.nc, P.p_out, s->p);
-  k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, stq>>>(g, P.u_in, s->u[0]);
+  k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, stq>>>(g, inlet_velocity(s), s->u[0]);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(stq));
   *out = s;
@@ -1781,11 +1935,13 @@ vos_status vos_set_solid_fraction(vos_sim *s, const double *eps_s, int on_device
   int *bad = (int *)(s->vec[1]);
   HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), st));
   k_set_eps<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, src, s->P.eps_min, s->eps, bad);
+  HIP_TRY(hipMemcpyAsync(s->eps_prev, s->eps, g.nc * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k_fill<<<grid_blocks(g.nc), TPB, 0, st>>>(g.nc, 0.0, s->rbar);
   s->p_fp64_sticky = false;   // a new geometry: mixed precision tries the FP32 hierarchy again
   s->hist_c = s->hist_p = 0;
   hierarchies_stale(s);
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
-  k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, s->P.u_in, s->u[0]);
+  k_inlet<<<grid_blocks((size_t)g.n[1] * g.n[2]), TPB, 0, st>>>(g, inlet_velocity(s), s->u[0]);
   HIP_TRY(hipGetLastError());
   int hbad = 0;
   HIP_TRY(hipMemcpyAsync(s->host, bad, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1806,11 +1962,13 @@ vos_status vos_set_params(vos_sim *s, const vos_params *params)
   s->hist_c = s->hist_p = 0;
   hierarchies_stale(s);
   s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
-  Phys &P = s->P;
-  P.mu = params->mu; P.rho = params->rho; P.D = params->D; P.k0 = params->k0; P.kc = params->kc;
-  P.Vm = params->Vm; P.zeta = params->zeta; P.c_in = params->c_in; P.eps_min = params->eps_min;
-  P.u_in = params->u_in; P.p_out = params->p_out; P.model = params->model;
-  k_inlet<<<grid_blocks((size_t)s->g.n[1] * s->g.n[2]), TPB, 0, s->stream>>>(s->g, P.u_in, s->u[0]);
+  const int old_drive = s->g.drive;
+  fill_phys(s->P, params, s->opt);
+  s->g.drive = params->drive;
+  // the velocity drive imposes u_in on the inlet faces; under the pressure drive
+  // they are unknowns and keep their values (0 when switching from the velocity drive)
+  if (params->drive == 0 || old_drive == 0)
+    k_inlet<<<grid_blocks((size_t)s->g.n[1] * s->g.n[2]), TPB, 0, s->stream>>>(s->g, inlet_velocity(s), s->u[0]);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s->stream));
   return VOS_OK;
@@ -1890,6 +2048,175 @@ vos_status vos_diagnostics(vos_sim *s, vos_diag *out)
 {
   if (!s || !out) return fail(VOS_ERR_ARG, "NULL argument");
   *out = s->last;
+  return VOS_OK;
+}
+
+vos_status vos_solve_pressure(vos_sim *s, double dt, const double *guess, int on_device, vos_diag *out)
+{
+  if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
+  if (!(dt > 0.0)) return fail(VOS_ERR_ARG, "dt must be > 0");
+  if (!s->have_geometry) return fail(VOS_ERR_STATE, "set the solid fraction before solving");
+  const Dev &g = s->g;
+  hipStream_t st = s->stream;
+  set_time_step(s, dt);
+  launch_coefficients(s, dt);
+  // the current face velocities are the predictor
+  for (int d = 0; d < g.nd; ++d)
+    HIP_TRY(hipMemcpyAsync(s->ustar[d], s->u[d], g.nf[d] * sizeof(double), hipMemcpyDeviceToDevice, st));
+  const double *gs = nullptr;
+  if (guess) {
+    // staged in the history buffer the extrapolated starts use last (the
+    // solve copies it into p after saving p^n); a caller's start ends that history
+    double *buf = s->pprev[NHIST - 1];
+    HIP_TRY(hipMemcpyAsync(buf, guess, g.nc * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    gs = buf;
+    s->hist_p = 0;
+  }
+  vos_diag dg;
+  std::memset(&dg, 0, sizeof(dg));
+  double r0 = 0.0;
+  HIP_TRY(hipEventRecord(s->ev[2], st));
+  vos_status rc = solve_pressure(s, &dg.it_p, &dg.res_p, &r0, gs);
+  if (rc == VOS_ERR_DEVICE) return rc;
+  HIP_TRY(hipEventRecord(s->ev[3], st));
+  HIP_TRY(hipEventSynchronize(s->ev[3]));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, s->ev[2], s->ev[3]));
+  dg.t_ms[2] = ms;
+  dg.it_p_fp64 = s->it_p_fp64;
+  dg.outer_res = r0;
+  dg.outer_its = 1;
+  s->stepped = true;
+  if (out) *out = dg;
+  return rc;
+}
+
+vos_status vos_initialize(vos_sim *s, double dt, int max_iters, double tol, vos_diag *out)
+{
+  if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
+  if (!(dt > 0.0) || max_iters < 1 || !(tol >= 0.0)) return fail(VOS_ERR_ARG, "need dt > 0, max_iters >= 1, tol >= 0");
+  if (!s->have_geometry) return fail(VOS_ERR_STATE, "set the solid fraction before initializing");
+  if (s->opt.simple) return fail(VOS_ERR_ARG, "vos_initialize relaxes the one-pass flow (simple = 0)");
+  hipStream_t st = s->stream;
+  vos_diag dg;
+  std::memset(&dg, 0, sizeof(dg));
+  vos_status rc = VOS_OK;
+  set_time_step(s, dt);
+  launch_coefficients(s, dt);   // eps is frozen: the coefficients hold for every flow iteration
+  bool settled = false;
+  for (int it = 0; it < max_iters; ++it) {
+    double q = 0.0, worst = 0.0;
+    if (vos_status e = momentum_stage(s, dt, &dg, &q, &rc)) return e;
+    worst = std::max(worst, q);
+    vos_status r2 = solve_pressure(s, &dg.it_p, &dg.res_p, &q);
+    if (r2 == VOS_ERR_DEVICE) return r2;
+    if (r2 && !rc) rc = r2;
+    worst = std::max(worst, q);
+    launch_correct(s);
+    dg.outer_its = it + 1;
+    dg.outer_res = worst;
+    if (rc) break;
+    if (worst <= tol) { settled = true; break; }
+  }
+  if (!rc) {
+    // c^0: pure upwind, then one solve with the van Leer correction lagged on it
+    double q = 0.0;
+    vos_status r2 = solve_transport(s, dt, &dg.it_c, &dg.res_c, &q, 0);
+    if (!r2) r2 = solve_transport(s, dt, &dg.it_c, &dg.res_c, &q, 1);
+    if (r2 == VOS_ERR_DEVICE) return r2;
+    if (r2 && !rc) rc = r2;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  s->stepped = true;
+  if (out) *out = dg;
+  if (rc) {
+    std::string m = g_err;
+    return fail(rc, m);
+  }
+  if (!settled) return fail(VOS_ERR_NOCONV, "the flow did not settle within max_iters");
+  return VOS_OK;
+}
+
+// Checkpoint: a header of 8 64-bit words (magic, version, nx, ny, nz, field
+// count, doubles that follow, 0) and the fields in a fixed order.
+namespace {
+constexpr uint64_t STATE_MAGIC = 0x564f5353544154ULL;   // "VOSSTAT"
+constexpr uint64_t STATE_VERSION = 1;
+constexpr int STATE_FIELDS = 8;
+
+void state_fields(vos_sim *s, double *ptr[STATE_FIELDS], size_t n[STATE_FIELDS])
+{
+  const Dev &g = s->g;
+  double *a[STATE_FIELDS] = {s->eps, s->eps_prev, s->rbar, s->u[0], s->u[1], s->u[2], s->p, s->c};
+  const size_t m[STATE_FIELDS] = {g.nc, g.nc, g.nc, g.nf[0], g.nf[1], g.nf[2], g.nc, g.nc};
+  for (int k = 0; k < STATE_FIELDS; ++k) { ptr[k] = a[k]; n[k] = m[k]; }
+}
+
+size_t state_doubles(vos_sim *s)
+{
+  double *ptr[STATE_FIELDS];
+  size_t n[STATE_FIELDS], t = 0;
+  state_fields(s, ptr, n);
+  for (int k = 0; k < STATE_FIELDS; ++k) t += n[k];
+  return t;
+}
+}  // namespace
+
+vos_status vos_state_bytes(vos_sim *s, size_t *bytes)
+{
+  if (!s || !bytes) return fail(VOS_ERR_ARG, "NULL argument");
+  *bytes = 8 * sizeof(uint64_t) + state_doubles(s) * sizeof(double);
+  return VOS_OK;
+}
+
+vos_status vos_get_state(vos_sim *s, void *buf, size_t bytes)
+{
+  if (!s || !buf) return fail(VOS_ERR_ARG, "NULL argument");
+  const size_t nd = state_doubles(s);
+  if (bytes < 8 * sizeof(uint64_t) + nd * sizeof(double)) return fail(VOS_ERR_ARG, "state buffer too small");
+  uint64_t *h = (uint64_t *)buf;
+  h[0] = STATE_MAGIC; h[1] = STATE_VERSION;
+  h[2] = (uint64_t)s->grid.nx; h[3] = (uint64_t)s->grid.ny; h[4] = (uint64_t)s->grid.nz;
+  h[5] = STATE_FIELDS; h[6] = nd; h[7] = 0;
+  double *ptr[STATE_FIELDS];
+  size_t n[STATE_FIELDS];
+  state_fields(s, ptr, n);
+  char *dst = (char *)buf + 8 * sizeof(uint64_t);
+  for (int k = 0; k < STATE_FIELDS; ++k) {
+    HIP_TRY(hipMemcpyAsync(dst, ptr[k], n[k] * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    dst += n[k] * sizeof(double);
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return VOS_OK;
+}
+
+vos_status vos_set_state(vos_sim *s, const void *buf, size_t bytes)
+{
+  if (!s || !buf) return fail(VOS_ERR_ARG, "NULL argument");
+  const size_t nd = state_doubles(s);
+  if (bytes < 8 * sizeof(uint64_t)) return fail(VOS_ERR_ARG, "state buffer too small");
+  const uint64_t *h = (const uint64_t *)buf;
+  if (h[0] != STATE_MAGIC || h[1] != STATE_VERSION || h[5] != STATE_FIELDS)
+    return fail(VOS_ERR_ARG, "not a state written by vos_get_state (or another version)");
+  if (h[2] != (uint64_t)s->grid.nx || h[3] != (uint64_t)s->grid.ny || h[4] != (uint64_t)s->grid.nz || h[6] != nd)
+    return fail(VOS_ERR_ARG, "the state belongs to another grid");
+  if (bytes < 8 * sizeof(uint64_t) + nd * sizeof(double)) return fail(VOS_ERR_ARG, "state buffer truncated");
+  double *ptr[STATE_FIELDS];
+  size_t n[STATE_FIELDS];
+  state_fields(s, ptr, n);
+  const char *src = (const char *)buf + 8 * sizeof(uint64_t);
+  for (int k = 0; k < STATE_FIELDS; ++k) {
+    HIP_TRY(hipMemcpyAsync(ptr[k], src, n[k] * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    src += n[k] * sizeof(double);
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->hist_c = s->hist_p = 0;
+  s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
+  hierarchies_stale(s);
+  s->p_fp64_sticky = false;
+  s->have_geometry = true;
   return VOS_OK;
 }
 

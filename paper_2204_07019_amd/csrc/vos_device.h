@@ -14,6 +14,7 @@ constexpr int NSLOT = 16;        // partial-sum quantities one sweep may produce
 struct Dev {
   int n[3];
   int nd;                        // 2 (nz == 1) or 3
+  int drive;                     // 1: inlet pressure drive (the inlet x-faces are momentum unknowns)
   int fd[3][3];                  // face-grid dims
   unsigned nc;
   unsigned nf[3];
@@ -23,6 +24,14 @@ struct Dev {
 struct Phys {
   double mu, rho, D, k0, kc, Vm, zeta, c_in, eps_min, u_in, p_out;
   int model;
+  double p_in;                   // inlet pressure (pressure drive)
+  int convection;                // explicit upwind momentum convection
+  int grad_scheme;               // 0 central, 1 decentred gradient of eps (VoS-psi variants)
+  int psi_kind;                  // 0: psi = lambda eps (1 - eps); 1: psi = 1
+  int transient;                 // storage d(eps c)/dt and the continuity source
+  double Vm_f;                   // M_ws / rho of the fluid
+  int simple;                    // quasi-static SIMPLE loop: steady momentum with relaxation
+  double relax_u, relax_c;       // its implicit under-relaxation factors
 };
 
 __device__ __forceinline__ unsigned gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }

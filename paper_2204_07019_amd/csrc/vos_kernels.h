@@ -14,7 +14,10 @@ namespace vos {
 // Solver scalar block (device memory, one per Krylov solve).
 enum Scal {
   S_RZ = 0, S_ALPHA, S_BETA, S_BN2, S_RES2, S_TOL2, S_CONV, S_ITS, S_PQ, S_ZQ,
-  S_RHO, S_OMEGA, S_SHALF, S_BAD, S_COUNT = 16
+  S_RHO, S_OMEGA, S_SHALF, S_BAD,
+  S_RES0,          // squared residual norm at the solve's start (the SIMPLE loop's convergence test)
+  S_TRUE,          // squared norm of the true residual b - A x at a converged BiCGStab iterate
+  S_COUNT = 16
 };
 
 // ---------------------------------------------------------------- S1
@@ -29,8 +32,8 @@ __device__ __forceinline__ int mom_nb(const Dev &g, const int x[3], int e, int s
   const int y = x[e] + s;
   if (e == D) {
     if (D == 0) {
-      if (y == 0) { *fv = u_in; return 1; }
-      if (y > g.n[0]) return 3;
+      if (y == 0 && !g.drive) { *fv = u_in; return 1; }
+      if (y > g.n[0] || y < 0) return 3;
       return 0;
     }
     if (y == 0 || y == g.n[D]) return 1;
@@ -45,7 +48,7 @@ template <int D>
 __device__ __forceinline__ bool mom_unknown(const Dev &g, const int x[3])
 {
   const int q = x[D];
-  return (q > 0 && q < g.n[D]) || (D == 0 && q == g.n[0]);
+  return (q > 0 && q < g.n[D]) || (D == 0 && (q == g.n[0] || (q == 0 && g.drive)));
 }
 
 // eps on face (D, x): mean of the two cells inside, the adjacent cell on a boundary.
@@ -64,7 +67,9 @@ __device__ __forceinline__ double face_eps(const Dev &g, const double *eps, cons
 
 // Face coefficients of direction D: eps_f-scaled momentum diagonal dmom,
 // pressure-correction coefficient af = rho/(eps_f dt) + beta_f and
-// transmissibility T = S / (af d_f) (d_f = dx/2 on the outlet).
+// transmissibility T = S / (af d_f) (d_f = dx/2 on the outlet and, under the
+// pressure drive, the inlet).  SIMPLE: steady momentum diagonal a / relax_u
+// (no inertia) and the pressure correction of SIMPLE, af = dmom / eps_f.
 template <int D>
 __global__ void __launch_bounds__(TPB) k_face_coef(Dev g, Phys P, double dt, const double *__restrict__ eps,
                                                    double *__restrict__ dmom, double *__restrict__ af,
@@ -85,21 +90,31 @@ __global__ void __launch_bounds__(TPB) k_face_coef(Dev g, Phys P, double dt, con
         const int kd = mom_nb<D>(g, x, e, s, P.u_in, &fv);
         nbsum += kd == 2 ? 2.0 : (kd == 3 ? 0.0 : 1.0);
       }
-    const double dm = P.rho / dt + ef * beta + cvis * nbsum;
-    const double a = P.rho / (ef * dt) + beta;
-    const double dist = (D == 0 && x[0] == g.n[0]) ? 0.5 * g.dx : g.dx;
+    double dm, a;
+    if (P.simple) {
+      dm = (ef * beta + cvis * nbsum) / P.relax_u;
+      a = dm / ef;
+    } else {
+      dm = P.rho / dt + ef * beta + cvis * nbsum;
+      a = P.rho / (ef * dt) + beta;
+    }
+    const double dist = (D == 0 && (x[0] == g.n[0] || x[0] == 0)) ? 0.5 * g.dx : g.dx;
     dmom[f] = dm;
     af[f] = a;
     T[f] = g.S / (a * dist);
   }
 }
 
-// Cell gradient of eps (central, zero-gradient ghosts), |grad eps|, interface
-// normal n = -grad/|grad| (0 where |grad| <= 1e-10/dx), and the partial sums
-// of |g| and |g| eps (1 - eps) that VoS-psi' fits lambda with.
-__global__ void __launch_bounds__(TPB) k_cell_grad(Dev g, const double *__restrict__ eps, double *__restrict__ gmag,
-                                                   double *__restrict__ n0, double *__restrict__ n1,
-                                                   double *__restrict__ n2, double *__restrict__ part)
+// Cell gradient of eps (zero-gradient ghosts), |grad eps|, interface normal
+// n = -grad/|grad| (0 where |grad| <= 1e-10/dx), and the partial sums of |g|
+// and |g| eps (1 - eps) that VoS-psi' fits lambda with.  Central differences,
+// or (decentred, a VoS-psi variant of Section 2.4) per direction the one-sided
+// difference toward the neighbour of larger eps (ties: the + side), which puts
+// the area of a sharp interface in the cell holding the solid.
+__global__ void __launch_bounds__(TPB) k_cell_grad(Dev g, int decentred, const double *__restrict__ eps,
+                                                   double *__restrict__ gmag, double *__restrict__ n0,
+                                                   double *__restrict__ n1, double *__restrict__ n2,
+                                                   double *__restrict__ part)
 {
   const double tau = 1e-10 / g.dx;
   double s_num = 0.0, s_den = 0.0;
@@ -111,7 +126,12 @@ __global__ void __launch_bounds__(TPB) k_cell_grad(Dev g, const double *__restri
       const unsigned st = dstride(g.n, d);
       const double em = x[d] > 0 ? eps[id - st] : eps[id];
       const double ep = x[d] < g.n[d] - 1 ? eps[id + st] : eps[id];
-      gv[d] = (ep - em) / (2.0 * g.dx);
+      if (decentred) {
+        const double e0 = eps[id];
+        gv[d] = em > ep ? (e0 - em) / g.dx : (ep - e0) / g.dx;
+      } else {
+        gv[d] = (ep - em) / (2.0 * g.dx);
+      }
     }
     const double gm = sqrt(gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2]);
     gmag[id] = gm;
@@ -171,28 +191,93 @@ __global__ void k_lambda(const double *__restrict__ part, int nb, int model, dou
 
 // ---------------------------------------------------------------- S2
 
+// u_D / eps_f on face (D, y) of the D face grid.
+template <int D>
+__device__ __forceinline__ double conv_phi(const Dev &g, const double *eps, const double *uD, const int y[3])
+{
+  unsigned lo, hi;
+  const double ef = face_eps<D>(g, eps, y, &lo, &hi);
+  return uD[fidx(g, D, y[0], y[1], y[2])] / ef;
+}
+
+// Momentum convection (Eq. momentumDBS), explicit first-order upwind, on the
+// interior face (D, x): rho [div(u u / eps)]_f, the eps_f-scaled row's term.
+// Control volume: the cell-sized box centred on the face.  Across its faces
+// normal to D (at the centres of the two cells) the transport velocity is the
+// mean of that cell's two D-faces; across its faces normal to e != D the mean
+// of the two e-faces in that plane belonging to the cells on either side of
+// the face.  The transported u_D / eps_f is the box's own value when the flux
+// leaves it, else the neighbouring D-face's; beyond the domain 0 enters
+// (walls and the inlet carry no tangential momentum) and the outlet plane
+// takes the own value (zero gradient).
+template <int D>
+__device__ double conv_face(const Dev &g, const Phys &P, const double *eps, const double *const uu[3], const int x[3])
+{
+  double flux = 0.0;
+  const double own = conv_phi<D>(g, eps, uu[D], x);
+  for (int e = 0; e < g.nd; ++e)
+    for (int s = -1; s <= 1; s += 2) {
+      int xn[3] = {x[0], x[1], x[2]};
+      xn[e] += s;
+      double U, nb;
+      if (e == D) {
+        U = 0.5 * (uu[D][fidx(g, D, x[0], x[1], x[2])] + uu[D][fidx(g, D, xn[0], xn[1], xn[2])]);
+        nb = conv_phi<D>(g, eps, uu[D], xn);
+      } else {
+        const int q = x[e] + (s > 0);
+        int cl[3] = {x[0], x[1], x[2]}, cu[3] = {x[0], x[1], x[2]};
+        cl[D] -= 1;
+        cl[e] = q;
+        cu[e] = q;
+        U = 0.5 * (uu[e][fidx(g, e, cl[0], cl[1], cl[2])] + uu[e][fidx(g, e, cu[0], cu[1], cu[2])]);
+        if (xn[e] >= 0 && xn[e] < g.n[e]) nb = conv_phi<D>(g, eps, uu[D], xn);
+        else nb = (e == 0 && s > 0) ? own : 0.0;
+      }
+      const double out = s * U;
+      flux += out * (out >= 0.0 ? own : nb);
+    }
+  return P.rho * flux / g.dx;
+}
+
 // Right-hand side of the eps_f-scaled momentum row of component D and the
-// initial guess u^n (fixed rows: b = 0, x = 0).
+// initial guess u^n (fixed rows: b = 0, x = 0).  One pass: inertia rho/dt u^n;
+// SIMPLE: the relaxation term dmom (1 - relax_u) u^k.  Pressure gradient of
+// p^n across the face (p_out beyond the outlet, p_in before the inlet under
+// the pressure drive); explicit convection on interior faces when enabled.
 template <int D>
 __global__ void __launch_bounds__(TPB) k_mom_rhs(Dev g, Phys P, double dt, const double *__restrict__ eps,
-                                                 const double *__restrict__ un, const double *__restrict__ pn,
-                                                 double *__restrict__ b, double *__restrict__ x0, int start_un)
+                                                 const double *__restrict__ dmom, const double *__restrict__ u0,
+                                                 const double *__restrict__ u1, const double *__restrict__ u2,
+                                                 const double *__restrict__ pn, double *__restrict__ b,
+                                                 double *__restrict__ x0, int start_un)
 {
   const double cvis = P.mu / (g.dx * g.dx);
+  const double *const uu[3] = {u0, u1, u2};
+  const double *un = uu[D];
   for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
     if (!mom_unknown<D>(g, x)) { b[f] = 0.0; x0[f] = 0.0; continue; }
     unsigned lo, hi;
     const double ef = face_eps<D>(g, eps, x, &lo, &hi);
-    double rhs = P.rho / dt * un[f];
-    if (D == 0 && x[0] == 1) rhs += cvis * P.u_in;   // the fixed inlet face is a Laplacian neighbour
+    double rhs = P.simple ? dmom[f] * (1.0 - P.relax_u) * un[f] : P.rho / dt * un[f];
+    if (D == 0 && x[0] == 1 && !g.drive) rhs += cvis * P.u_in;   // the fixed inlet face is a Laplacian neighbour
     const bool outlet = (D == 0 && x[0] == g.n[0]);
-    const unsigned st = dstride(g.n, D);
-    const unsigned up = cidx(g, outlet ? g.n[0] - 1 : x[0], x[1], x[2]);
-    const double pl = outlet ? pn[up] : pn[up - st];
-    const double pu = outlet ? P.p_out : pn[up];
-    rhs -= ef * (pu - pl) / (outlet ? 0.5 * g.dx : g.dx);
+    const bool inlet = (D == 0 && x[0] == 0);   // an unknown only under the pressure drive
+    double pl, pu, dist;
+    if (inlet) {
+      pl = P.p_in;
+      pu = pn[cidx(g, 0, x[1], x[2])];
+      dist = 0.5 * g.dx;
+    } else {
+      const unsigned st = dstride(g.n, D);
+      const unsigned up = cidx(g, outlet ? g.n[0] - 1 : x[0], x[1], x[2]);
+      pl = outlet ? pn[up] : pn[up - st];
+      pu = outlet ? P.p_out : pn[up];
+      dist = outlet ? 0.5 * g.dx : g.dx;
+    }
+    rhs -= ef * (pu - pl) / dist;
+    if (P.convection && !inlet && !outlet) rhs -= conv_face<D>(g, P, eps, uu, x);
     b[f] = rhs;
     if (start_un) x0[f] = un[f];   // else x0 holds an extrapolated start
   }
@@ -287,12 +372,16 @@ __global__ void __launch_bounds__(TPB) k_p_apply(Dev g, const double *__restrict
   write_partials<1>(vv, part);
 }
 
-// b = A p^n - div(u*) and x0 = p^n; keeps p^n.
+// b = A p^n - div(u*) (+ the continuity source of Eq. contDBS, src_c Rbar V,
+// with the lagged rates rsrc when given; partial sums of it in part).
 __global__ void __launch_bounds__(TPB) k_p_rhs(Dev g, const double *__restrict__ T0, const double *__restrict__ T1,
                                                const double *__restrict__ T2, const double *__restrict__ pn,
                                                const double *__restrict__ u0, const double *__restrict__ u1,
-                                               const double *__restrict__ u2, double *__restrict__ b)
+                                               const double *__restrict__ u2, double *__restrict__ b,
+                                               const double *__restrict__ rsrc, double src_c,
+                                               double *__restrict__ part)
 {
+  double ssum = 0.0;
   for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
@@ -304,13 +393,25 @@ __global__ void __launch_bounds__(TPB) k_p_rhs(Dev g, const double *__restrict__
       const unsigned f2 = fidx(g, 2, x[0], x[1], x[2]);
       div += u2[f2 + (unsigned)g.n[0] * g.n[1]] - u2[f2];
     }
-    b[id] = ap - div * g.S;
+    double v = ap - div * g.S;
+    if (rsrc) {
+      const double sv = src_c * rsrc[id] * g.V;
+      v += sv;
+      ssum += sv;
+    }
+    b[id] = v;
+  }
+  if (rsrc) {
+    const double vv[1] = {ssum};
+    write_partials<1>(vv, part);
   }
 }
 
 // ---------------------------------------------------------------- S4
 
-// u = u* - [(p - p^n)_hi - (p - p^n)_lo] / (af d_f) on the momentum unknowns.
+// u = u* - [(p - p^n)_hi - (p - p^n)_lo] / (af d_f) on the momentum unknowns
+// (the increment vanishes at the Dirichlet outlet, and at the inlet under the
+// pressure drive).
 template <int D>
 __global__ void __launch_bounds__(TPB) k_correct(Dev g, const double *__restrict__ ustar, const double *__restrict__ af,
                                                  const double *__restrict__ p, const double *__restrict__ pn,
@@ -321,6 +422,11 @@ __global__ void __launch_bounds__(TPB) k_correct(Dev g, const double *__restrict
     unflat(g.fd[D], f, x);
     if (!mom_unknown<D>(g, x)) { u[f] = ustar[f]; continue; }
     const bool outlet = (D == 0 && x[0] == g.n[0]);
+    if (D == 0 && x[0] == 0) {
+      const unsigned c0 = cidx(g, 0, x[1], x[2]);
+      u[f] = ustar[f] - ((p[c0] - pn[c0]) - 0.0) / (af[f] * (0.5 * g.dx));
+      continue;
+    }
     const unsigned st = dstride(g.n, D);
     const unsigned up = cidx(g, outlet ? g.n[0] - 1 : x[0], x[1], x[2]);
     const unsigned lo = outlet ? up : up - st;
@@ -361,7 +467,9 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
                                                       const double *__restrict__ cold, const double *__restrict__ gmag,
                                                       const double *__restrict__ lam, double *__restrict__ off,
                                                       double *__restrict__ b, double *__restrict__ dg,
-                                                      double *__restrict__ dif)
+                                                      double *__restrict__ dif, int vl, double dt,
+                                                      const double *__restrict__ eps_prev,
+                                                      const double *__restrict__ c0)
 {
   const double *uu[3] = {u0, u1, u2};
   const double *ww[3] = {w0, w1, w2};
@@ -385,7 +493,7 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
           const unsigned lo = s > 0 ? id : id - st;
           const unsigned nb = s > 0 ? id + st : id - st;
           if (Fo >= 0.0) diag += Fo; else o[slot] += Fo;
-          rhs -= Fo * face_corr(cold, lo, st, xf_d, g.n[d], uf);
+          if (vl) rhs -= Fo * face_corr(cold, lo, st, xf_d, g.n[d], uf);
           const double G = P.D * 0.5 * (ep + eps[nb]) * g.S / g.dx;
           diag += G;
           o[slot] -= G;
@@ -394,10 +502,10 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
             const double wf = ww[d][f];
             const double k = P.zeta * ep * (s * wf);
             if (k >= 0.0) diag += k; else o[slot] += k;
-            rhs -= k * face_corr(cold, lo, st, xf_d, g.n[d], wf);
+            if (vl) rhs -= k * face_corr(cold, lo, st, xf_d, g.n[d], wf);
           }
         } else if (d == 0 && xf_d == 0) {
-          rhs -= Fo * P.c_in;
+          if (Fo < 0.0) rhs -= Fo * P.c_in; else diag += Fo;
           const double G = P.D * ep * g.S / (0.5 * g.dx);
           diag += G;
           rhs += G * P.c_in;
@@ -407,8 +515,17 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
       }
     }
     if (P.model != 0) {
-      const double e = ep;
-      diag += P.zeta * P.kc * lambda * e * (1.0 - e) * gmag[id] * g.V;
+      const double psi = P.psi_kind == 1 ? 1.0 : lambda * ep * (1.0 - ep);
+      diag += P.zeta * P.kc * psi * gmag[id] * g.V;
+    }
+    if (P.transient) {
+      diag += ep * g.V / dt;
+      rhs += eps_prev[id] * c0[id] * g.V / dt;
+    }
+    if (P.simple && P.relax_c < 1.0) {
+      const double dr = diag / P.relax_c;
+      rhs += (dr - diag) * cold[id];
+      diag = dr;
     }
     const double inv = 1.0 / diag;
     for (int k = 0; k < 2 * g.nd; ++k) off[(size_t)k * g.nc + id] = o[k] * inv;
@@ -455,13 +572,15 @@ __global__ void __launch_bounds__(TPB) k_adr_apply(Dev g, const double *__restri
 // sum_f w_f (eps c)^R_f with c^R_f the transport solve's face values (upwind
 // of c^{n+1} + van Leer correction lagged on c^n) and (eps c)^R_f the van
 // Leer face value of eps^n c^{n+1}; the acid sink is the first term.
-// psi models (Eq. RfVoSpsi): Rbar = kc lambda eps(1-eps) |grad eps| c.
+// psi models (Eq. RfVoSpsi): Rbar = kc psi |grad eps| c, psi = lambda eps(1-eps)
+// or 1.  Per block, the largest |Vm Rbar| over the cells free to move by more
+// than deps_max (pmax).
 __global__ void __launch_bounds__(TPB) k_react(Dev g, Phys P, const double *__restrict__ eps,
                                                const double *__restrict__ c, const double *__restrict__ cold,
                                                const double *__restrict__ w0, const double *__restrict__ w1,
                                                const double *__restrict__ w2, const double *__restrict__ gmag,
                                                const double *__restrict__ lam, double *__restrict__ rbar,
-                                               double *__restrict__ part, double *__restrict__ pmax)
+                                               double *__restrict__ part, double *__restrict__ pmax, double deps_max)
 {
   const double *ww[3] = {w0, w1, w2};
   const double lambda = lam[0];
@@ -506,12 +625,17 @@ __global__ void __launch_bounds__(TPB) k_react(Dev g, Phys P, const double *__re
       sk = ep * t1;
       R = sk - t2;
     } else {
-      sk = P.kc * lambda * ep * (1.0 - ep) * gmag[id] * c[id] * g.V;
+      const double psi = P.psi_kind == 1 ? 1.0 : lambda * ep * (1.0 - ep);
+      sk = P.kc * psi * gmag[id] * c[id] * g.V;
       R = sk;
     }
     const double rb = R / g.V;
     rbar[id] = rb;
-    mrate = fmax(mrate, fabs(P.Vm * rb));
+    // Appendix D's bound looks at the cells the clip does not hold within
+    // deps_max of their bound (a cell closer to it changes by at most that)
+    const double r = P.Vm * rb;
+    const double room = r > 0.0 ? 1.0 - ep : ep - P.eps_min;
+    if (room > deps_max) mrate = fmax(mrate, fabs(r));
     s_sink += sk;
     s_rate += R;
   }
@@ -540,15 +664,18 @@ __global__ void k_solid_dt(const double *__restrict__ pmax, int nb, double dt, d
 // Solid update eps <- clip(eps + dt Vm Rbar, eps_min, 1) (Eq. mbs) and the
 // diagnostic sums: 0 clipped, 1 d(eps)V, 2 solid volume, 3 sum eps, 4 inlet
 // acid flux, 5 outlet acid flux, 6 inlet p, 7 sum c|g|V, 8 sum eps c V,
-// 9 sum |g| V; max |d eps| goes to the separate max slot array.
+// 9 sum |g| V, 10 inlet volume flux, 11 transient storage sum
+// (eps c - eps_prev c0) V / dt; max |d eps| goes to the separate max slot
+// array.  Transient: eps_prev takes eps^n for the next step's storage term.
 __global__ void __launch_bounds__(TPB) k_eps_update(Dev g, Phys P, double dt_arg, const double *__restrict__ dtp,
                                                     int freeze, double *__restrict__ eps,
                                                     const double *__restrict__ rbar, const double *__restrict__ c,
                                                     const double *__restrict__ p, const double *__restrict__ u0,
                                                     const double *__restrict__ gmag, double *__restrict__ part,
-                                                    double *__restrict__ part_max)
+                                                    double *__restrict__ part_max, double *__restrict__ eps_prev,
+                                                    const double *__restrict__ c0)
 {
-  double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   double mx = 0.0;
   const double dt = dtp ? dtp[0] : dt_arg;   // the shortened solid step when there is one
   for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
@@ -557,13 +684,18 @@ __global__ void __launch_bounds__(TPB) k_eps_update(Dev g, Phys P, double dt_arg
     const double e0 = eps[id], cc = c[id];
     if (x[0] == 0) {
       const double ui = u0[fidx(g, 0, 0, x[1], x[2])];
-      v[4] += g.S * ui * P.c_in + P.D * e0 * g.S / (0.5 * g.dx) * (P.c_in - cc);
+      v[4] += g.S * ui * (ui > 0.0 ? P.c_in : cc) + P.D * e0 * g.S / (0.5 * g.dx) * (P.c_in - cc);
       v[6] += p[id];
+      v[10] += g.S * ui;
     }
     if (x[0] == g.n[0] - 1) v[5] += g.S * u0[fidx(g, 0, g.n[0], x[1], x[2])] * cc;
     v[7] += cc * gmag[id] * g.V;
     v[8] += e0 * cc * g.V;
     v[9] += gmag[id] * g.V;
+    if (P.transient) {
+      v[11] += (e0 * cc - eps_prev[id] * c0[id]) * g.V / dt_arg;
+      eps_prev[id] = e0;
+    }
     double e1c = e0;
     if (!freeze) {
       const double e1 = e0 + dt * P.Vm * rbar[id];
@@ -576,7 +708,7 @@ __global__ void __launch_bounds__(TPB) k_eps_update(Dev g, Phys P, double dt_arg
     v[2] += (1.0 - e1c) * g.V;
     v[3] += e1c;
   }
-  write_partials<10>(v, part);
+  write_partials<12>(v, part);
   __shared__ double lds[TPB / 64];
   const double m = block_max(mx, lds);
   if (threadIdx.x == 0) part_max[blockIdx.x] = m;
@@ -663,7 +795,7 @@ __global__ void k_cg_scal(int op, const double *__restrict__ part, int nb, doubl
   if (threadIdx.x != 0) return;
   switch (op) {
     case 0:
-      sc[S_RZ] = a; sc[S_RES2] = a; sc[S_BN2] = b; sc[S_TOL2] = rtol2 * b; sc[S_ITS] = 0.0;
+      sc[S_RZ] = a; sc[S_RES2] = a; sc[S_RES0] = a; sc[S_BN2] = b; sc[S_TOL2] = rtol2 * b; sc[S_ITS] = 0.0;
       sc[S_CONV] = (a <= rtol2 * b || a == 0.0) ? 1.0 : 0.0;
       sc[S_BAD] = 0.0;
       break;
@@ -782,6 +914,25 @@ __global__ void __launch_bounds__(TPB) k_bi_xr(unsigned n, const double *__restr
   write_partials<2>(vv, part);
 }
 
+// Partial sums of |b - y|^2 (y = A x): the true residual of a BiCGStab iterate.
+__global__ void __launch_bounds__(TPB) k_bi_true_res(unsigned n, const double *__restrict__ b,
+                                                     const double *__restrict__ y, double *__restrict__ part)
+{
+  double a = 0.0;
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
+    const double r = b[i] - y[i];
+    a += r * r;
+  }
+  const double vv[1] = {a};
+  write_partials<1>(vv, part);
+}
+
+__global__ void k_bi_true_scal(const double *__restrict__ part, int nb, double *__restrict__ sc)
+{
+  const double a = sum_partials(part, 0, nb);
+  if (threadIdx.x == 0) sc[S_TRUE] = a;
+}
+
 // BiCGStab scalars.
 //  op 0 (init): bn2 = b.b, res2 = r.r, rho = rh.r, alpha = omega = 1, beta = 0; conv test.
 //  op 1 (alpha): alpha = rho / rh.v (partial slot 0).
@@ -797,7 +948,7 @@ __global__ void k_bi_scal(int op, const double *__restrict__ part, int nb, doubl
   if (threadIdx.x != 0) return;
   switch (op) {
     case 0: {
-      sc[S_BN2] = a; sc[S_RES2] = b; sc[S_TOL2] = rtol2 * a; sc[S_ITS] = 0.0; sc[S_BAD] = 0.0;
+      sc[S_BN2] = a; sc[S_RES2] = b; sc[S_RES0] = b; sc[S_TOL2] = rtol2 * a; sc[S_ITS] = 0.0; sc[S_BAD] = 0.0;
       sc[S_ALPHA] = 1.0; sc[S_OMEGA] = 1.0; sc[S_SHALF] = 0.0;
       sc[S_CONV] = (b <= rtol2 * a || b == 0.0) ? 1.0 : 0.0;
       // first direction p = r: beta = 0, rho = rh.r

@@ -42,7 +42,20 @@ class _Params(C.Structure):
     _fields_ = [("mu", C.c_double), ("rho", C.c_double), ("D", C.c_double), ("k0", C.c_double),
                 ("kc", C.c_double), ("Vm", C.c_double), ("zeta", C.c_double), ("c_in", C.c_double),
                 ("eps_min", C.c_double), ("u_in", C.c_double), ("p_out", C.c_double),
-                ("model", C.c_int)]
+                ("model", C.c_int), ("drive", C.c_int), ("p_in", C.c_double), ("convection", C.c_int),
+                ("grad_scheme", C.c_int), ("psi_kind", C.c_int), ("transient", C.c_int),
+                ("Vm_f", C.c_double)]
+
+
+# vos_params fields a params dict may leave out (the single-pass step's settings)
+PARAM_DEFAULTS = {"drive": 0, "p_in": 0.0, "convection": 0, "grad_scheme": 0, "psi_kind": 0,
+                  "transient": 0, "Vm_f": 1e-4}
+
+
+def make_params(params: dict) -> "_Params":
+    """vos_params from a dict of its fields (the optional ones default)."""
+    keys = [k for k, _ in _Params._fields_]
+    return _Params(**{k: params[k] if k in params else PARAM_DEFAULTS[k] for k in keys})
 
 
 class _Opts(C.Structure):
@@ -51,7 +64,9 @@ class _Opts(C.Structure):
                 ("precision", C.c_int), ("mg_nu", C.c_int), ("check_every", C.c_int),
                 ("use_graphs", C.c_int), ("coarse_cells", C.c_int), ("level_kernels", C.c_int),
                 ("p_fp32_its", C.c_int), ("extrapolate", C.c_int), ("setup_every", C.c_int),
-                ("deps_max", C.c_double)]
+                ("deps_max", C.c_double), ("simple", C.c_int), ("outer_max", C.c_int),
+                ("outer_tol", C.c_double), ("relax_u", C.c_double), ("relax_p", C.c_double),
+                ("relax_c", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -64,7 +79,9 @@ class _Diag(C.Structure):
                 ("solid_balance_rel", C.c_double), ("clipped_volume", C.c_double),
                 ("max_deps", C.c_double), ("alpha", C.c_double), ("t_ms", C.c_double * 6),
                 ("guess", C.c_int), ("res0_prev", C.c_double), ("res0_guess", C.c_double),
-                ("guess_error_drop", C.c_double), ("it_p_fp64", C.c_int), ("dt_solid", C.c_double)]
+                ("guess_error_drop", C.c_double), ("it_p_fp64", C.c_int), ("dt_solid", C.c_double),
+                ("U_D", C.c_double), ("R_omega", C.c_double), ("acid_accum", C.c_double),
+                ("outer_its", C.c_int), ("outer_res", C.c_double), ("div_source", C.c_double)]
 
 
 _lib = None
@@ -91,10 +108,16 @@ def lib():
         L.vos_step.argtypes = [vp, C.c_double, C.c_int, C.c_int, C.POINTER(_Diag)]
         L.vos_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
         L.vos_time_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.vos_solve_pressure.argtypes = [vp, C.c_double, vp, C.c_int, C.POINTER(_Diag)]
+        L.vos_initialize.argtypes = [vp, C.c_double, C.c_int, C.c_double, C.POINTER(_Diag)]
+        L.vos_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.vos_get_state.argtypes = [vp, vp, C.c_size_t]
+        L.vos_set_state.argtypes = [vp, vp, C.c_size_t]
         L.vos_last_error.restype = C.c_char_p
         for name in ("vos_workspace_bytes", "vos_create", "vos_destroy", "vos_set_solid_fraction",
                      "vos_set_field", "vos_set_params", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics",
-                     "vos_time_kernel"):
+                     "vos_time_kernel", "vos_solve_pressure", "vos_initialize", "vos_state_bytes",
+                     "vos_get_state", "vos_set_state"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -132,6 +155,12 @@ class Opts:
     extrapolate: int = 0    # 1: solves start from 2 x^n - x^(n-1) of the last two steps; 2: adaptive quadratic
     setup_every: int = 0    # rebuild the multigrid hierarchies every this many steps (0, 1: every step)
     deps_max: float = 0.0   # > 0: the solid update's step is cut so that no eps changes by more (Appendix D)
+    simple: int = 0         # 1: quasi-static SIMPLE loop per step (Appendices A, B)
+    outer_max: int = 50
+    outer_tol: float = 1e-8
+    relax_u: float = 0.3
+    relax_p: float = 0.3
+    relax_c: float = 1.0
 
 
 class Sim:
@@ -146,8 +175,7 @@ class Sim:
         self.shape = (nz, ny, nx)
         self.nx, self.ny, self.nz = nx, ny, nz
         self.grid = _Grid(nx, ny, nz, dx)
-        keys = [k for k, _ in _Params._fields_]
-        self.params = _Params(**{k: params[k] for k in keys})
+        self.params = make_params(params)
         self.opts = _Opts(**asdict(opts or Opts()))
         nbytes = C.c_size_t()
         _check(lib().vos_workspace_bytes(C.byref(self.grid), C.byref(self.opts), C.byref(nbytes)))
@@ -171,8 +199,7 @@ class Sim:
         self.shape = (nz, ny, nx)
         self.nx, self.ny, self.nz = nx, ny, nz
         self.grid = _Grid(nx, ny, nz, dx)
-        keys = [k for k, _ in _Params._fields_]
-        self.params = _Params(**{k: params[k] for k in keys})
+        self.params = make_params(params)
         self._h = handle
         self._borrowed = True
         return self
@@ -254,3 +281,33 @@ class Sim:
         dg = _Diag()
         _check(lib().vos_diagnostics(self._h, C.byref(dg)))
         return diag_to_dict(dg)
+
+    def solve_pressure(self, dt: float, guess=None) -> dict:
+        """The pressure equation alone from the current state (vos_solve_pressure)."""
+        dg = _Diag()
+        ptr = None
+        if guess is not None:
+            g = self._as_device(guess, self.shape)
+            ptr = C.c_void_p(g.data_ptr())
+        rc = lib().vos_solve_pressure(self._h, dt, ptr, 1, C.byref(dg))
+        _check(rc, diag_to_dict(dg))
+        return diag_to_dict(dg)
+
+    def initialize(self, dt: float, max_iters: int = 200, tol: float = 1e-10) -> dict:
+        """Steady flow with eps frozen, then c^0 (vos_initialize)."""
+        dg = _Diag()
+        rc = lib().vos_initialize(self._h, dt, max_iters, tol, C.byref(dg))
+        _check(rc, diag_to_dict(dg))
+        return diag_to_dict(dg)
+
+    def get_state(self) -> bytes:
+        """Checkpoint of the physical state (vos_get_state) as bytes."""
+        n = C.c_size_t()
+        _check(lib().vos_state_bytes(self._h, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        _check(lib().vos_get_state(self._h, buf, n.value))
+        return bytes(buf)
+
+    def set_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        _check(lib().vos_set_state(self._h, buf, len(state)))

@@ -14,13 +14,20 @@ def make_problem(es, prm, model=0, nz=None, **tol):
     return oracle.Problem(nx=nx, ny=ny, nz=nz_, **kw)
 
 
+def gpu_params(prob):
+    """vos_params of an oracle problem (same names)."""
+    from paper_2204_07019_amd import vos
+    return {k: getattr(prob, k) for k, _ in vos._Params._fields_}
+
+
 def gpu_sim(prob, precision=0, **opt_overrides):
     from paper_2204_07019_amd import vos
-    params = {k: getattr(prob, k) for k in ("mu", "rho", "D", "k0", "kc", "Vm", "zeta", "c_in",
-                                             "eps_min", "u_in", "p_out", "model")}
+    params = gpu_params(prob)
     o = vos.Opts(rtol_u=prob.rtol_u, rtol_p=prob.rtol_p, rtol_c=prob.rtol_c,
                  maxit_u=prob.maxit_u, maxit_p=min(prob.maxit_p, 5000), maxit_c=prob.maxit_c,
-                 precision=precision)
+                 precision=precision, deps_max=prob.deps_max, simple=prob.simple,
+                 outer_max=prob.outer_max, outer_tol=prob.outer_tol, relax_u=prob.relax_u,
+                 relax_p=prob.relax_p, relax_c=prob.relax_c)
     for k, v in opt_overrides.items():
         setattr(o, k, v)
     return vos.Sim(prob.nx, prob.ny, prob.nz, prob.dx, params, o)

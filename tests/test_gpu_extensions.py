@@ -1,0 +1,284 @@
+"""GPU (through the C ABI) against the FP64 oracle for the options beyond the
+single projection pass, every diagnostic, the clip, and the boundary calls
+that are not a step (pressure alone, set-up, checkpoint).
+
+Bar: relative L2 <= 1e-6 on the fields after N steps from the same inputs
+(tight solver tolerances), as in test_gpu_parity.py.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_cases import gpu_sim, make_problem, rel_l2, run_both
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(rtol_u=1e-12, rtol_p=1e-12, rtol_c=1e-12)
+BAR = 1e-6
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_07019_amd import vos
+    vos.lib()
+
+
+def _fields(st, g, eps0, tol=BAR, p_live=True):
+    out = {k: rel_l2(g[k], getattr(st, k)) for k in ("ux", "uy", "c", "eps")}
+    live = st.eps > 2 * st.eps.min() if (p_live and st.eps.min() < 0.5) else np.ones(st.eps.shape, dtype=bool)
+    out["p"] = rel_l2(g["p"][live], st.p[live])
+    if st.eps.shape[0] > 1:
+        out["uz"] = rel_l2(g["uz"], st.uz)
+    if np.abs(st.eps - eps0).max() > 0:
+        out["deps"] = rel_l2(g["eps"] - eps0, st.eps - eps0)
+    print("[parity] rel L2 vs oracle:", {k: float(f"{v:.2e}") for k, v in out.items()}, flush=True)
+    for k, v in out.items():
+        assert v <= tol, (k, v, out)
+    return out
+
+
+def _rsa(nx=96, ny=40, seed=7):
+    from paper_2204_07019_amd import inputs
+    return inputs.rsa_discs(nx, ny, seed=seed, rmin=4, rmax=9, porosity=0.75)
+
+
+def _base(**kw):
+    from paper_2204_07019_amd import inputs
+    return dict(inputs.BASE_PARAMS, dx=5e-6, **kw)
+
+
+# ------------------------------------------------------------ new physics
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pressure_drive_matches_oracle(orc, precision):
+    """Inlet pressure drive (the inlet faces are momentum unknowns with a
+    Dirichlet pressure p_in): 6 steps of a ragged micromodel against the
+    oracle, with U_D, dP and K equal to the oracle's."""
+    es = _rsa()
+    prob = make_problem(es, _base(drive=1, p_in=0.3, p_out=0.0), model=0, **TIGHT)
+    _say(f"pressure drive 96x40 precision {precision}")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 6, precision=precision)
+    _fields(st, g, eps0)
+    do, dg = diags[-1]
+    for k in ("U_D", "dP", "K"):
+        assert dg[k] == pytest.approx(do[k], rel=1e-8), k
+    assert abs(dg["acid_balance_rel"]) < 1e-9
+
+
+@pytest.mark.parametrize("shape", [(96, 40, 1), (30, 12, 8)])
+def test_momentum_convection_matches_oracle(orc, shape):
+    """Explicit upwind momentum convection at a cell Reynolds number ~0.1
+    (u_in = 2e-2 m/s), 2-D and 3-D, against the oracle."""
+    nx, ny, nz = shape
+    if nz == 1:
+        es = _rsa(nx, ny)
+    else:
+        es = np.zeros((nz, ny, nx))
+        es[2:nz - 2, 3:ny - 3, nx // 3: nx // 3 + 5] = 1.0
+        es[:, 1, nx // 2] = 0.5
+    prob = make_problem(es, _base(convection=1, u_in=2e-2), model=0, **TIGHT)
+    _say(f"convection {shape}")
+    st, g, eps0, diags = run_both(es, prob, 1e-4, 5, precision=0)
+    _fields(st, g, eps0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_simple_loop_matches_oracle(orc, precision):
+    """The quasi-static SIMPLE loop (steady momentum, relaxation 0.3 on u and
+    p, 0.7 on c) with a fixed count of 8 outer iterations per step and
+    Appendix D's adaptive solid step: 3 steps against the oracle, the same
+    solid steps."""
+    es = _rsa(64, 32, seed=3)
+    prob = make_problem(es, _base(), model=0, **TIGHT)
+    prob = dataclasses.replace(prob, simple=1, outer_max=8, outer_tol=0.0, relax_u=0.3, relax_p=0.3,
+                               relax_c=0.7, deps_max=0.005)
+    _say(f"SIMPLE 64x32 8 outer iterations precision {precision}")
+    st, g, eps0, diags = run_both(es, prob, 10.0, 3, precision=precision)
+    _fields(st, g, eps0)
+    for do, dg in diags:
+        assert dg["outer_its"] == do["outer_its"] == 8
+        assert dg["dt_solid"] == pytest.approx(do["dt_solid"], rel=1e-6)
+        assert dg["max_deps"] == pytest.approx(0.005, rel=1e-9)
+
+
+def test_simple_loop_converges_with_the_oracle(orc):
+    """With a tolerance the loop stops where the oracle's does (the initial
+    residuals of the solves below 1e-7): same outer iteration count within
+    one, fields within the bar."""
+    es = _rsa(48, 24, seed=5)
+    prob = make_problem(es, _base(), model=0, **TIGHT)
+    prob = dataclasses.replace(prob, simple=1, outer_max=3000, outer_tol=1e-7, relax_u=0.7, relax_p=0.3)
+    _say("SIMPLE 48x24 to outer tolerance 1e-7")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 2, precision=0)
+    _fields(st, g, eps0, tol=5e-6)
+    for do, dg in diags:
+        assert abs(dg["outer_its"] - do["outer_its"]) <= 1, (dg["outer_its"], do["outer_its"])
+        assert dg["outer_res"] <= 1e-7
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_transient_terms_match_oracle(orc, precision):
+    """Storage d(eps c)/dt and the continuity source of Eq. contDBS (lagged
+    rates): 6 steps against the oracle with the state the oracle carries
+    (eps of the previous step, the previous rates); acid balance including
+    storage, and the source sum equal to the oracle's."""
+    from paper_2204_07019_amd import inputs
+    es = inputs.calcite_post(64, 32, 20, 16, 6)
+    prob = make_problem(es, _base(transient=1, Vm_f=1e-4), model=0, **TIGHT)
+    _say(f"transient 64x32 precision {precision}")
+    st, g, eps0, diags = run_both(es, prob, 2e-3, 6, precision=precision)
+    _fields(st, g, eps0)
+    for k, (do, dg) in enumerate(diags):
+        assert abs(dg["acid_balance_rel"]) < 1e-9
+        assert dg["acid_accum"] == pytest.approx(do["acid_accum"], rel=1e-6, abs=1e-12 * abs(do["acid_in"]))
+        assert dg["div_source"] == pytest.approx(do["div_source"], rel=1e-6, abs=1e-30)
+        if k > 0:
+            assert dg["div_source"] < 0
+
+
+@pytest.mark.parametrize("grad_scheme,psi_kind", [(0, 1), (1, 1), (1, 0)])
+def test_psi_variants_match_oracle(orc, grad_scheme, psi_kind):
+    """VoS-psi with psi = 1 and/or the decentred gradient (Section 2.4)."""
+    es = _rsa(64, 32, seed=9)
+    prob = make_problem(es, _base(grad_scheme=grad_scheme, psi_kind=psi_kind), model=1, **TIGHT)
+    _say(f"VoS-psi grad {grad_scheme} psi_kind {psi_kind}")
+    st, g, eps0, diags = run_both(es, prob, 2e-3, 5, precision=1)
+    _fields(st, g, eps0)
+
+
+# ------------------------------------------------------- diagnostics, clip
+
+DIAG_KEYS = ("solid_volume", "surface_area", "porosity", "dP", "K", "acid_in", "acid_out", "acid_consumed",
+             "solid_rate", "alpha", "max_deps", "U_D", "R_omega", "lambda")
+
+
+@pytest.mark.parametrize("model", [0, 2])
+def test_every_diagnostic_matches_oracle(orc, model):
+    """Every vos_diag quantity the oracle computes, step by step over 10 post
+    steps (balances are checked to their own 1e-9 bar)."""
+    from paper_2204_07019_amd import inputs
+    es, prm = inputs.workload("post")
+    prob = make_problem(es, prm, model=model, **TIGHT)
+    _say(f"diagnostics post model {model}")
+    st, g, eps0, diags = run_both(es, prob, 1e-3, 10, precision=0)
+    for do, dg in diags:
+        for k in DIAG_KEYS:
+            assert dg[k] == pytest.approx(do[k], rel=1e-6, abs=1e-30), (k, dg[k], do[k])
+        assert abs(dg["acid_balance_rel"]) < 1e-9 and abs(dg["solid_balance_rel"]) < 1e-9
+
+
+def test_complete_dissolution_clips(orc):
+    """A thin, partly dissolved strip in strong acid with long steps: cells
+    reach eps = 1 and clip there; the clipped volume, the solid volume and
+    the fields match the oracle, and the solid balance closes with the clip."""
+    nx, ny = 48, 20
+    es = np.zeros((1, ny, nx))
+    es[0, 4:16, 20] = 0.15
+    es[0, 4:16, 21] = 0.6
+    prob = make_problem(es, _base(kc=2e-3, c_in=50.0), model=0, **TIGHT)
+    _say("complete dissolution 48x20")
+    st, g, eps0, diags = run_both(es, prob, 0.5, 6, precision=0)
+    _fields(st, g, eps0)
+    clipped = [do["clipped_volume"] for do, _ in diags]
+    assert max(clipped) > 0, clipped
+    for do, dg in diags:
+        assert dg["clipped_volume"] == pytest.approx(do["clipped_volume"], rel=1e-6, abs=1e-28)
+        assert dg["solid_volume"] == pytest.approx(do["solid_volume"], rel=1e-9)
+        assert abs(dg["solid_balance_rel"]) < 1e-9
+    assert (g["eps"] == 1.0).sum() > (eps0 == 1.0).sum()
+
+
+# ------------------------------------------------------- boundary calls
+
+def test_checkpoint_restores_bitwise(orc):
+    """vos_get_state / vos_set_state: a run restored from a checkpoint
+    continues bitwise as the uninterrupted one (one-pass step, hierarchies
+    rebuilt every step), also with the transient terms carried in the state."""
+    from paper_2204_07019_amd import inputs
+    es = inputs.calcite_post(64, 32, 20, 16, 6)
+    prob = make_problem(es, _base(transient=1), model=0, rtol_u=1e-9, rtol_p=1e-9, rtol_c=1e-9)
+    _say("checkpoint 64x32")
+    a = gpu_sim(prob)
+    a.set_solid_fraction(es)
+    a.step(1e-3, 3)
+    chk = a.get_state()
+    a.step(1e-3, 3)
+    ref = {k: a.get_numpy(k) for k in ("eps", "ux", "uy", "p", "c")}
+    b = gpu_sim(prob)
+    b.set_state(chk)
+    b.step(1e-3, 3)
+    for k, v in ref.items():
+        assert np.array_equal(b.get_numpy(k), v), k
+    # a state of another grid is refused
+    other = gpu_sim(make_problem(np.zeros((1, 16, 32)), _base()))
+    from paper_2204_07019_amd import vos
+    with pytest.raises(vos.VosError) as e:
+        other.set_state(chk)
+    assert e.value.status == vos.VOS_ERR_ARG
+    for s in (a, b, other):
+        s.close()
+
+
+def test_solve_pressure_alone(orc):
+    """vos_solve_pressure: from the current state with its face velocities as
+    the predictor, the GPU pressure satisfies the oracle's assembled pressure
+    system to the tolerance; started from that solution it needs no iteration."""
+    import oracle
+    from paper_2204_07019_amd import inputs
+    from test_gpu_parity import _scaled_resid
+    es = _rsa(80, 40, seed=2)
+    prob = make_problem(es, _base(), model=0, rtol_p=1e-10)
+    st = oracle.initial_state(prob, es)
+    for _ in range(2):
+        oracle.step(prob, st, 1e-3)
+    st.ux[:, :, 1:-1] *= 1.01     # a predictor that is not divergence-free
+    sim = gpu_sim(prob)
+    for k in ("eps", "ux", "uy", "p", "c"):
+        sim.set(k, getattr(st, k))
+    _say("solve_pressure 80x40")
+    d = sim.solve_pressure(1e-3)
+    assert d["it_p"] > 0 and d["res_p"] <= 1e-10
+    sten, rhs, dims = oracle.assemble(prob, st, 1e-3, 3)
+    rel, _ = _scaled_resid(sten, rhs, dims, sim.get_numpy("p"), "sym")
+    assert rel <= 2e-10, rel
+    p1 = sim.get_numpy("p")
+    sim.set("p", st.p)
+    d2 = sim.solve_pressure(1e-3, guess=p1)
+    assert d2["it_p"] == 0
+    sim.close()
+
+
+def test_initialize_settles_flow_and_concentration(orc):
+    """vos_initialize: with eps frozen the flow reaches the steady equations
+    (the oracle's momentum rows with u^n = u hold to the tolerance, div u = 0)
+    and c^0 lies in [0, c_in]."""
+    import oracle
+    from test_gpu_parity import _scaled_resid
+    es = _rsa(64, 32, seed=4)
+    prob = make_problem(es, _base(), model=0, rtol_u=1e-11, rtol_p=1e-11, rtol_c=1e-11)
+    sim = gpu_sim(prob)
+    sim.set_solid_fraction(es)
+    _say("initialize 64x32")
+    d = sim.initialize(1e-3, max_iters=500, tol=1e-9)
+    assert d["outer_res"] <= 1e-9 and d["outer_its"] > 1
+    st = oracle.State(*(sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")))
+    for comp in (0, 1):
+        sten, rhs, dims = oracle.assemble(prob, st, 1e-3, comp)
+        x = getattr(st, "ux" if comp == 0 else "uy").ravel().copy()
+        x[(sten[0] == 1.0) & (rhs == 0.0)] = 0.0
+        rel, _ = _scaled_resid(sten, rhs, dims, x, "sym")
+        assert rel < 1e-7, (comp, rel)
+    div = (st.ux[:, :, 1:] - st.ux[:, :, :-1]) + (st.uy[:, 1:, :] - st.uy[:, :-1, :])
+    assert np.abs(div).max() <= 1e-9 * prob.u_in
+    assert st.c.min() >= -1e-12 and st.c.max() <= prob.c_in * (1 + 1e-12)
+    sim.close()

@@ -1,0 +1,137 @@
+"""GPU against the FP64 oracle on the 3-D grain pack: the seeded overlapping
+sphere pack with its one-voxel partial-volume ramp and 1 % interface noise
+(the 256^3 workload's geometry at 48^3, radius scaled with the box), every
+reaction model, both precisions, 5 steps; and one step of a 128^3 pack at the
+production launch shapes checked stage by stage against the oracle's own
+discrete equations assembled from the same input state.
+"""
+import multiprocessing as mp
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_cases import gpu_params, gpu_sim, make_problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(rtol_u=1e-12, rtol_p=1e-12, rtol_c=1e-12, maxit_p=400000)
+N = 48
+STEPS = 5
+DT = 1e-3
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _pack(n):
+    from paper_2204_07019_amd import inputs
+    return inputs.sphere_pack(n, seed=33, median_r=n / 12.8)
+
+
+def _problem(model):
+    from paper_2204_07019_amd import inputs
+    es = _pack(N)
+    return es, make_problem(es, dict(inputs.BASE_PARAMS, dx=4e-6), model=model, **TIGHT)
+
+
+def _oracle_run(model):
+    import oracle
+    es, prob = _problem(model)
+    st = oracle.initial_state(prob, es)
+    eps0 = st.eps.copy()
+    diags = [oracle.step(prob, st, DT) for _ in range(STEPS)]
+    return model, st, eps0, diags
+
+
+@pytest.fixture(scope="module")
+def oracle_runs():
+    """The three models' oracle trajectories, computed side by side in worker
+    processes (each is single-threaded C)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    oracle.build(force=False)
+    _say(f"oracle: {N}^3 pack, models 0-2, {STEPS} steps (worker processes)")
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(3) as pool:
+        res = pool.map(_oracle_run, [0, 1, 2])
+    return {m: (st, e0, d) for m, st, e0, d in res}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_sphere_pack_matches_oracle(orc, oracle_runs, model, precision):
+    st, eps0, odiags = oracle_runs[model]
+    es, prob = _problem(model)
+    _say(f"pack {N}^3 model {model} precision {precision} {STEPS} steps")
+    sim = gpu_sim(prob, precision)
+    sim.set_solid_fraction(es)
+    gd = [sim.step(DT) for _ in range(STEPS)]
+    g = {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
+    sim.close()
+    out = {k: rel_l2(g[k], getattr(st, k)) for k in ("ux", "uy", "uz", "c", "eps")}
+    live = st.eps > 2 * prob.eps_min
+    out["p"] = rel_l2(g["p"][live], st.p[live])
+    out["p_all"] = rel_l2(g["p"], st.p)
+    out["deps"] = rel_l2(g["eps"] - eps0, st.eps - eps0)
+    print("[parity] rel L2 vs oracle:", {k: float(f"{v:.2e}") for k, v in out.items()}, flush=True)
+    for k, v in out.items():
+        assert v <= (1e-5 if k == "p_all" else 1e-6), (k, v, out)
+    assert np.abs(st.eps - eps0).max() > 0
+    for do, dg in zip(odiags, gd):
+        assert dg["solid_rate"] == pytest.approx(do["solid_rate"], rel=1e-6)
+        assert dg["lambda"] == pytest.approx(do["lambda"], rel=1e-10)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("model", [0, 2])
+def test_pack_128_stagewise(orc, model):
+    """One mixed-precision step of a 128^3 pack (the production z-marching
+    kernels and tile shapes, rtol 1e-8): each stage's GPU output satisfies the
+    oracle's discrete equations assembled from the same state."""
+    import oracle
+    from paper_2204_07019_amd import inputs
+    from test_gpu_parity import _scaled_resid
+    n = 128
+    es = _pack(n)
+    prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=4e-6), model=model)
+    sim = gpu_sim(prob, 1, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000)
+    sim.set_solid_fraction(es)
+    _say(f"pack 128^3 stagewise model {model}")
+    sim.step(DT, 2)
+    before = {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
+    d = sim.step(DT)
+    after = {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c", "ustar_x", "ustar_y", "ustar_z",
+                                            "rbar")}
+    sim.close()
+    st = oracle.State(*(before[k].copy() for k in ("eps", "ux", "uy", "uz", "p", "c")))
+    for comp, name in ((0, "ustar_x"), (1, "ustar_y"), (2, "ustar_z")):
+        sten, rhs, dims = oracle.assemble(prob, st, DT, comp)
+        x = after[name].copy().ravel()
+        x[(sten[0] == 1.0) & (rhs == 0.0)] = 0.0
+        rel, _ = _scaled_resid(sten, rhs, dims, x, "sym")
+        _say(f"momentum {name} rel resid {rel:.2e}")
+        assert rel < 5e-8
+    st_p = st.copy()
+    st_p.ux[:], st_p.uy[:], st_p.uz[:] = after["ustar_x"], after["ustar_y"], after["ustar_z"]
+    sten, rhs, dims = oracle.assemble(prob, st_p, DT, 3)
+    rel, rp = _scaled_resid(sten, rhs, dims, after["p"], "sym")
+    _say(f"pressure rel resid {rel:.2e} (its {d['it_p']}, fp64 {d['it_p_fp64']})")
+    assert rel < 5e-8
+    div = ((after["ux"][:, :, 1:] - after["ux"][:, :, :-1]) + (after["uy"][:, 1:, :] - after["uy"][:, :-1, :]) +
+           (after["uz"][1:, :, :] - after["uz"][:-1, :, :])) * prob.dx ** 2
+    assert np.abs(div.ravel() + rp).max() <= 1e-9 * np.abs(rhs).max()
+    st_c = st.copy()
+    st_c.ux[:], st_c.uy[:], st_c.uz[:] = after["ux"], after["uy"], after["uz"]
+    sten, rhs, dims = oracle.assemble(prob, st_c, DT, 4)
+    rel, _ = _scaled_resid(sten, rhs, dims, after["c"], "row")
+    _say(f"transport rel resid {rel:.2e} (its {d['it_c']})")
+    assert rel < 5e-8
+    rbar, sink, gmag, lam, eps_new = oracle.reaction(prob, DT, before["eps"], after["c"], before["c"])
+    assert rel_l2(after["rbar"], rbar) < 1e-11
+    assert np.abs(after["eps"] - eps_new).max() < 1e-15
