@@ -293,13 +293,13 @@ vos_status vos_solve_pressure(vos_sim *sim, double dt, const double *guess, int 
 
 /* The set-up of a run from a geometry (not timed): with eps frozen, repeat
  * the flow stages (coefficients, momentum predictor, pressure, correction)
- * with steps of dt until the initial relative residuals of the momentum and
- * pressure solves are <= tol (at most max_iters times), then the
- * concentration: one transport solve with pure upwind convection, then one
+ * with steps of dt until the relative change of the face velocities over an
+ * iteration, ||u - u_prev|| / ||u||, is <= tol (at most max_iters times), then
+ * the concentration: one transport solve with pure upwind convection, then one
  * with the van Leer correction lagged on that result.  out (may be NULL):
- * outer_its (flow iterations), outer_res (the last largest initial residual),
- * the solves' counts.  VOS_ERR_NOCONV if the flow has not settled within
- * max_iters (the state is then the last iterate). */
+ * outer_its (flow iterations), outer_res (the last relative change), the
+ * solves' counts.  VOS_ERR_NOCONV if the flow has not settled within
+ * max_iters (the state is then the last iterate, c^0 included). */
 vos_status vos_initialize(vos_sim *sim, double dt, int max_iters, double tol, vos_diag *out);
 
 /* Checkpoint of the physical state: eps, the face velocities, p, c and the

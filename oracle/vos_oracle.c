@@ -469,8 +469,12 @@ static int compute_coefficients(const grid_t *g, const orc_prob *P, double dt,
   /* cell gradient of eps, zero-gradient at every boundary: central differences,
    * or (grad_scheme 1, a VoS-psi variant of Section 2.4) per direction the
    * one-sided difference toward the neighbour of larger eps, so that the area of
-   * a sharp interface lands in the cell that holds the solid (ties: the + side) */
-  const double tau = 1e-10 / dx;
+   * a sharp interface lands in the cell that holds the solid (ties: the + side).
+   * The normal -grad/|grad| of Section 2.3 is taken as 0 where eps varies by
+   * at most 1e-6 across a cell: eps is O(1) and stored to ~1e-16, so below that
+   * the direction of the gradient is set by rounding, and a unit reactive flux
+   * along it would turn rounding into acid sinks of order k_c c / dx */
+  const double tau = 1e-6 / dx;
   for (long id = 0; id < g->nc; ++id) {
     int x[3];
     unflatten(g->n, id, x);

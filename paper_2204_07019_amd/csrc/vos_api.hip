@@ -1404,6 +1404,33 @@ __global__ void k_relax(unsigned n, double relax, const double *__restrict__ pn,
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) p[i] = pn[i] + relax * (p[i] - pn[i]);
 }
 
+// Partials of sum (a - b)^2 and sum a^2 over n entries (slots 0 and 1 of part).
+__global__ void __launch_bounds__(TPB) k_du(unsigned n, const double *__restrict__ a, const double *__restrict__ b,
+                                            double *__restrict__ part)
+{
+  double d2 = 0.0, a2 = 0.0;
+  for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
+    const double d = a[i] - b[i];
+    d2 += d * d;
+    a2 += a[i] * a[i];
+  }
+  const double v[2] = {d2, a2};
+  write_partials<2>(v, part);
+}
+
+// out[0] = sqrt(sum (u - u_prev)^2 / sum u^2) over the face grids whose partials
+// k_du left at slots 0-1, 2-3 and 4-5 (nb2 = 0: no third grid).
+__global__ void k_du_final(const double *__restrict__ part, int nb0, int nb1, int nb2, double *__restrict__ out)
+{
+  double d2 = sum_partials(part, 0, nb0) + sum_partials(part, 2, nb1);
+  double a2 = sum_partials(part, 1, nb0) + sum_partials(part, 3, nb1);
+  if (nb2 > 0) {
+    d2 += sum_partials(part, 4, nb2);
+    a2 += sum_partials(part, 5, nb2);
+  }
+  if (threadIdx.x == 0) out[0] = a2 > 0.0 ? sqrt(d2 / a2) : 0.0;
+}
+
 // Partials of the rates: 2 slots after the update's 12.
 double *rate_partials(vos_sim *s) { return s->part + 12 * MAXB; }
 
@@ -2099,26 +2126,39 @@ vos_status vos_initialize(vos_sim *s, double dt, int max_iters, double tol, vos_
   if (!s->have_geometry) return fail(VOS_ERR_STATE, "set the solid fraction before initializing");
   if (s->opt.simple) return fail(VOS_ERR_ARG, "vos_initialize relaxes the one-pass flow (simple = 0)");
   hipStream_t st = s->stream;
+  const Dev &g = s->g;
   vos_diag dg;
   std::memset(&dg, 0, sizeof(dg));
   vos_status rc = VOS_OK;
   set_time_step(s, dt);
   launch_coefficients(s, dt);   // eps is frozen: the coefficients hold for every flow iteration
+  // the face velocities before each iteration go to the oldest predictor history
+  // buffers (the extrapolation history restarts afterwards anyway)
+  double *prev[3] = {s->uprev[0][NHIST - 1], s->uprev[1][NHIST - 1], s->uprev[2][NHIST - 1]};
+  double *sc = sc_block(s, SC_MISC) + 2;
   bool settled = false;
   for (int it = 0; it < max_iters; ++it) {
-    double q = 0.0, worst = 0.0;
+    for (int d = 0; d < g.nd; ++d)
+      HIP_TRY(hipMemcpyAsync(prev[d], s->u[d], g.nf[d] * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double q = 0.0;
     if (vos_status e = momentum_stage(s, dt, &dg, &q, &rc)) return e;
-    worst = std::max(worst, q);
     vos_status r2 = solve_pressure(s, &dg.it_p, &dg.res_p, &q);
     if (r2 == VOS_ERR_DEVICE) return r2;
     if (r2 && !rc) rc = r2;
-    worst = std::max(worst, q);
     launch_correct(s);
+    // relative change of the face velocities over the iteration
+    for (int d = 0; d < g.nd; ++d)
+      k_du<<<grid_blocks(g.nf[d]), TPB, 0, st>>>(g.nf[d], s->u[d], prev[d], s->part + 2 * d * MAXB);
+    k_du_final<<<1, TPB, 0, st>>>(s->part, grid_blocks(g.nf[0]), grid_blocks(g.nf[1]),
+                                  g.nd == 3 ? grid_blocks(g.nf[2]) : 0, sc);
+    HIP_TRY(hipGetLastError());
+    if (vos_status e = read_back(s, sc, 1)) return e;
     dg.outer_its = it + 1;
-    dg.outer_res = worst;
+    dg.outer_res = s->host[0];
     if (rc) break;
-    if (worst <= tol) { settled = true; break; }
+    if (s->host[0] <= tol) { settled = true; break; }
   }
+  s->hist_u[0] = s->hist_u[1] = s->hist_u[2] = 0;
   if (!rc) {
     // c^0: pure upwind, then one solve with the van Leer correction lagged on it
     double q = 0.0;

@@ -106,7 +106,8 @@ __global__ void __launch_bounds__(TPB) k_face_coef(Dev g, Phys P, double dt, con
 }
 
 // Cell gradient of eps (zero-gradient ghosts), |grad eps|, interface normal
-// n = -grad/|grad| (0 where |grad| <= 1e-10/dx), and the partial sums of |g|
+// n = -grad/|grad| (0 where |grad| <= 1e-6/dx: below that the direction is set
+// by the rounding of eps), and the partial sums of |g|
 // and |g| eps (1 - eps) that VoS-psi' fits lambda with.  Central differences,
 // or (decentred, a VoS-psi variant of Section 2.4) per direction the one-sided
 // difference toward the neighbour of larger eps (ties: the + side), which puts
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(TPB) k_cell_grad(Dev g, int decentred, const d
                                                    double *__restrict__ n1, double *__restrict__ n2,
                                                    double *__restrict__ part)
 {
-  const double tau = 1e-10 / g.dx;
+  const double tau = 1e-6 / g.dx;
   double s_num = 0.0, s_den = 0.0;
   for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];

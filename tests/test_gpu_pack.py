@@ -75,13 +75,29 @@ def test_sphere_pack_matches_oracle(orc, oracle_runs, model, precision):
     g = {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
     sim.close()
     out = {k: rel_l2(g[k], getattr(st, k)) for k in ("ux", "uy", "uz", "c", "eps")}
-    live = st.eps > 2 * prob.eps_min
-    out["p"] = rel_l2(g["p"][live], st.p[live])
-    out["p_all"] = rel_l2(g["p"], st.p)
     out["deps"] = rel_l2(g["eps"] - eps0, st.eps - eps0)
-    print("[parity] rel L2 vs oracle:", {k: float(f"{v:.2e}") for k, v in out.items()}, flush=True)
+    # Pressure.  Pores the solid seals off from the inlet and outlet couple to the
+    # flow only through intact solid (transmissibility ~1e-30): their pressure
+    # is a nearly free mode that a Jacobi-scaled stopping rule fixes only to
+    # O(rtol / sqrt(d)).  Compared: the pressure on the pore space connected to
+    # the inlet or outlet through cells with eps > 1/2, at the bar, and the
+    # difference over all cells in the D^1/2-weighted norm the solves control.
+    from scipy import ndimage
+    lab, _ = ndimage.label(st.eps > 0.5)
+    open_ids = np.union1d(np.unique(lab[:, :, 0]), np.unique(lab[:, :, -1]))
+    conn = np.isin(lab, open_ids[open_ids > 0])
+    out["p_connected"] = rel_l2(g["p"][conn], st.p[conn])
+    import oracle
+    sten, _, _ = oracle.assemble(prob, st, DT, 3)
+    w = np.sqrt(sten[0]).reshape(st.p.shape)
+    out["p_weighted"] = rel_l2(w * g["p"], w * st.p)
+    out["p_all_unweighted"] = rel_l2(g["p"], st.p)
+    print("[parity] rel L2 vs oracle:", {k: float(f"{v:.2e}") for k, v in out.items()},
+          f"connected pore cells {int(conn.sum())}", flush=True)
     for k, v in out.items():
-        assert v <= (1e-5 if k == "p_all" else 1e-6), (k, v, out)
+        if k != "p_all_unweighted":
+            assert v <= 1e-6, (k, v, out)
+    assert conn.sum() > 0.5 * (st.eps > 0.5).sum()
     assert np.abs(st.eps - eps0).max() > 0
     for do, dg in zip(odiags, gd):
         assert dg["solid_rate"] == pytest.approx(do["solid_rate"], rel=1e-6)
