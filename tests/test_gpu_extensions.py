@@ -271,8 +271,10 @@ def test_solve_pressure_alone(orc):
 
 def test_initialize_settles_flow_and_concentration(orc):
     """vos_initialize: with eps frozen the flow settles (its relative change
-    per iteration below 1e-8): the oracle's momentum rows with u^n = u hold,
-    div u vanishes, and c^0 lies in [0, c_in]."""
+    per iteration below 1e-11; the steady momentum residual on fluid faces
+    falls in proportion, ~1.5e4 times that change on this geometry in the
+    oracle's own iteration): the oracle's momentum rows with u^n = u hold to
+    1e-6, div u vanishes, and c^0 lies in [0, c_in]."""
     import oracle
     from test_gpu_parity import _scaled_resid
     es = _rsa(64, 32, seed=4)
@@ -280,15 +282,28 @@ def test_initialize_settles_flow_and_concentration(orc):
     sim = gpu_sim(prob)
     sim.set_solid_fraction(es)
     _say("initialize 64x32")
-    d = sim.initialize(1e-3, max_iters=2000, tol=1e-8)
-    assert d["outer_res"] <= 1e-8 and d["outer_its"] > 1
+    d = sim.initialize(1e-3, max_iters=8000, tol=1e-11)
+    assert d["outer_res"] <= 1e-11 and d["outer_its"] > 1
     st = oracle.State(*(sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")))
-    for comp in (0, 1):
+    # steady momentum rows on the faces between two fluid cells (in intact solid
+    # the pressure still drifts at speeds the flow does not see)
+    for comp, name in ((0, "ux"), (1, "uy")):
         sten, rhs, dims = oracle.assemble(prob, st, 1e-3, comp)
-        x = getattr(st, "ux" if comp == 0 else "uy").ravel().copy()
-        x[(sten[0] == 1.0) & (rhs == 0.0)] = 0.0
-        rel, _ = _scaled_resid(sten, rhs, dims, x, "sym")
-        assert rel < 1e-5, (comp, rel)
+        A = oracle.stencil_to_dense(sten, dims) if sten.shape[1] < 3000 else None
+        x = getattr(st, name).ravel().copy()
+        fixed = (sten[0] == 1.0) & (rhs == 0.0)
+        x[fixed] = 0.0
+        r = rhs - A @ x
+        e = st.eps[0]
+        if comp == 0:
+            ef = np.zeros((e.shape[0], e.shape[1] + 1))
+            ef[:, 1:-1] = np.minimum(e[:, 1:], e[:, :-1])
+        else:
+            ef = np.zeros((e.shape[0] + 1, e.shape[1]))
+            ef[1:-1, :] = np.minimum(e[1:, :], e[:-1, :])
+        m = (ef.ravel() > 0.5) & ~fixed
+        rel = np.linalg.norm(r[m]) / np.linalg.norm(rhs[m])
+        assert rel < 1e-6, (comp, rel)
     div = (st.ux[:, :, 1:] - st.ux[:, :, :-1]) + (st.uy[:, 1:, :] - st.uy[:, :-1, :])
     assert np.abs(div).max() <= 1e-7 * prob.u_in
     assert st.c.min() >= -1e-12 and st.c.max() <= prob.c_in * (1 + 1e-12)
