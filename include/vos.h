@@ -302,6 +302,24 @@ vos_status vos_solve_pressure(vos_sim *sim, double dt, const double *guess, int 
  * max_iters (the state is then the last iterate, c^0 included). */
 vos_status vos_initialize(vos_sim *sim, double dt, int max_iters, double tol, vos_diag *out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the pressure equation of
+ * vos_solve_pressure for a state the caller passes in, with no simulation
+ * handle and no workspace.  All inputs and outputs are device pointers on the
+ * current device: eps (cells), the face velocities ux, uy, uz (taken as the
+ * predictor u*; uz may be NULL in 2-D) and p (cells: the current pressure on
+ * entry, the solution on exit).  Every scratch buffer comes from one static
+ * device array of 48 MiB per GPU (held until the process ends), enough for
+ * about 2.0e5 cells in 2-D (512 x 384) and 2.4e5 in 3-D (62^3); larger grids
+ * give VOS_ERR_ARG with the bytes they would need.  Plain launches on hip_stream, no graph
+ * capture, no hipMalloc / hipFree or other allocating call.  Calls on one GPU
+ * share the array (and, in one process, a host control block): calls that
+ * overlap race, so serialise them.  params->transient must be 0 (no lagged
+ * rates for the continuity source).  out as for vos_solve_pressure. */
+vos_status vos_solve_pressure_noalloc(const vos_grid *grid, const vos_params *params, const vos_opts *opts,
+                                      double dt, const double *eps, const double *ux, const double *uy,
+                                      const double *uz, double *p, void *hip_stream, vos_diag *out);
+
 /* Checkpoint of the physical state: eps, the face velocities, p, c and the
  * two arrays the transient terms carry between steps (eps at the previous
  * step's start, the previous rates), with a header naming the grid.

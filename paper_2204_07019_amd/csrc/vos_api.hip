@@ -2321,3 +2321,163 @@ void get_tuning(const vos_sim *s, int *check_every, int *coarse_cells)
 }
 
 }  // namespace vosint
+
+// ====================================================================== no-allocation pressure solve
+//
+// vos_solve_pressure_noalloc: the pressure equation of a state the caller
+// passes in, with every scratch buffer (coefficients, Krylov vectors, the
+// multigrid hierarchy, partial sums, solver scalars) carved from one
+// file-scope device array instead of a caller workspace.  Host side it uses a
+// control block and a read-back buffer of static storage, plain launches (no
+// graph capture) and the caller's stream only.
+
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)48 << 20;   // 48 MiB per device
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];   // device address of `scratch`, per device (null until looked up)
+vos_sim g_noalloc_sim;                     // control block reused by every call of the process
+double g_noalloc_host[64];                 // solver scalars read back here
+
+// Offsets of the buffers the pressure stage needs within the scratch array:
+// face coefficients (dmom, af, T), pressure diagonal, p^n, five Krylov vectors,
+// partial sums, scalar blocks, the coarsest inverse and an FP64-sized hierarchy.
+Layout pressure_layout(const vos_grid &g)
+{
+  Layout Lo;
+  std::memset(&Lo, 0, sizeof(Lo));
+  Plan P;
+  LevelDims D0 = level_dims(g.nx, g.ny, g.nz);
+  const size_t nc = D0.nc, dbl = sizeof(double);
+  for (int d = 0; d < 3; ++d) {
+    Lo.dmom[d] = P.take(D0.nf[d] * dbl);
+    Lo.af[d] = P.take(D0.nf[d] * dbl);
+    Lo.T[d] = P.take(D0.nf[d] * dbl);
+  }
+  Lo.pdiag = P.take(nc * dbl);
+  Lo.pn = P.take(nc * dbl);
+  for (int k = 0; k < 5; ++k) Lo.vec[k] = P.take(nc * dbl);
+  Lo.part = P.take((size_t)NSLOT * MAXB * dbl);
+  Lo.scal = P.take((size_t)NSC * S_COUNT * 2 * dbl);
+  Lo.ainv = P.take((size_t)MG_COARSE_MAX * MG_COARSE_MAX * dbl);
+  LevelDims lv[MG_MAX_LEVELS];
+  Lo.nlev = mg_hierarchy(g, lv);
+  for (int l = 0; l < Lo.nlev; ++l) {
+    for (int d = 0; d < 3; ++d) Lo.mgT[l][d] = P.take(lv[l].nf[d] * dbl);
+    Lo.mgdiag[l] = P.take(lv[l].nc * dbl);
+    Lo.mgx[l] = P.take(lv[l].nc * dbl);
+    Lo.mgb[l] = P.take(lv[l].nc * dbl);
+    Lo.mgt[l] = P.take(lv[l].nc * dbl);
+  }
+  Lo.total = P.off;
+  return Lo;
+}
+
+}  // namespace
+
+extern "C" vos_status vos_solve_pressure_noalloc(const vos_grid *grid, const vos_params *params,
+                                                 const vos_opts *opts, double dt, const double *eps,
+                                                 const double *ux, const double *uy, const double *uz, double *p,
+                                                 void *hip_stream, vos_diag *out)
+{
+  vos_status st = check_grid(grid);
+  if (st) return st;
+  if ((st = check_params(params))) return st;
+  if ((st = check_opts(opts))) return st;
+  if (!(dt > 0.0)) return fail(VOS_ERR_ARG, "dt must be > 0");
+  const bool three = grid->nz > 1;
+  if (!eps || !ux || !uy || !p || (three && !uz)) return fail(VOS_ERR_ARG, "NULL field pointer");
+  if (params->transient) return fail(VOS_ERR_ARG, "the no-allocation pressure solve has no continuity source (transient = 0)");
+  const Layout lo = pressure_layout(*grid);
+  if (lo.total > NOALLOC_SCRATCH_BYTES)
+    return fail(VOS_ERR_ARG, "grid too large for the no-allocation pressure solve: needs " + std::to_string(lo.total) +
+                                 " bytes of scratch, the limit is " + std::to_string(NOALLOC_SCRATCH_BYTES));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(VOS_ERR_DEVICE, "device index beyond the supported range");
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(VOS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  char *base = (char *)g_scratch_ptr[dev];
+
+  // the control block: the state's fields are the caller's, every other buffer is scratch
+  vos_sim *s = &g_noalloc_sim;
+  s->grid = *grid;
+  s->prm = *params;
+  s->opt = *opts;
+  s->opt.extrapolate = 0;
+  s->opt.simple = 0;
+  s->stream = (hipStream_t)hip_stream;
+  s->lo = lo;
+  s->ws = base;
+  Dev &g = s->g;
+  g.n[0] = grid->nx; g.n[1] = grid->ny; g.n[2] = grid->nz;
+  g.nd = three ? 3 : 2;
+  g.drive = params->drive;
+  for (int d = 0; d < 3; ++d) {
+    for (int e = 0; e < 3; ++e) g.fd[d][e] = g.n[e] + (e == d);
+    g.nf[d] = (unsigned)g.fd[d][0] * g.fd[d][1] * g.fd[d][2];
+  }
+  g.nc = (unsigned)grid->nx * grid->ny * grid->nz;
+  g.dx = grid->dx; g.S = grid->dx * grid->dx; g.V = g.S * grid->dx;
+  fill_phys(s->P, params, s->opt);
+  auto D = [&](size_t o) { return (double *)(base + o); };
+  s->eps = const_cast<double *>(eps);
+  s->p = p;
+  s->pn = D(lo.pn);
+  s->pdiag = D(lo.pdiag);
+  const double *uu[3] = {ux, uy, three ? uz : ux};
+  for (int d = 0; d < 3; ++d) {
+    s->dmom[d] = D(lo.dmom[d]); s->af[d] = D(lo.af[d]); s->T[d] = D(lo.T[d]);
+    s->ustar[d] = const_cast<double *>(uu[d]);
+    s->u[d] = s->ustar[d];
+  }
+  for (int k = 0; k < 5; ++k) s->vec[k] = D(lo.vec[k]);
+  for (int k = 5; k < NVEC; ++k) s->vec[k] = nullptr;
+  s->part = D(lo.part); s->scal = D(lo.scal); s->ainv = D(lo.ainv);
+  s->rbar = nullptr;
+  s->nlev = lo.nlev;
+  fill_levels<float>(s, s->mgf);
+  fill_levels<double>(s, s->mgd);
+  s->host = g_noalloc_host;
+  s->net = nullptr;
+  s->ws_use = 0;
+  s->use_graphs = false;
+  for (int k = 0; k < 8; ++k) { s->gexec[k] = nullptr; s->last_its[k] = 0; }
+  s->p_scale = 0.0;
+  s->p_fp64_sticky = false;
+  s->it_p_fp64 = 0;
+  s->hist_p = 0;
+  s->setup_every = 1;
+  hierarchies_stale(s);
+  if (s->opt.mg_nu == 0) s->opt.mg_nu = three ? 3 : 4;
+  s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (three ? VC_BLOCK_MAX : VC_TAIL_2D);
+
+  hipStream_t stq = s->stream;
+  // the scalar blocks hold the convergence flags and the always-zero flag: cleared per call
+  k_fill<<<grid_blocks((size_t)NSC * S_COUNT * 2), TPB, 0, stq>>>((unsigned)(NSC * S_COUNT * 2), 0.0, s->scal);
+  set_time_step(s, dt);
+  k_face_coef<0><<<grid_blocks(g.nf[0]), TPB, 0, stq>>>(g, s->P, dt, s->eps, s->dmom[0], s->af[0], s->T[0]);
+  k_face_coef<1><<<grid_blocks(g.nf[1]), TPB, 0, stq>>>(g, s->P, dt, s->eps, s->dmom[1], s->af[1], s->T[1]);
+  if (three) k_face_coef<2><<<grid_blocks(g.nf[2]), TPB, 0, stq>>>(g, s->P, dt, s->eps, s->dmom[2], s->af[2], s->T[2]);
+  else k_fill<<<grid_blocks(g.nf[2]), TPB, 0, stq>>>(g.nf[2], 0.0, s->T[2]);
+  k_pdiag<<<grid_blocks(g.nc), TPB, 0, stq>>>(g, s->T[0], s->T[1], s->T[2], s->pdiag);
+  vos_diag dg;
+  std::memset(&dg, 0, sizeof(dg));
+  double r0 = 0.0;
+  vos_status rc = solve_pressure(s, &dg.it_p, &dg.res_p, &r0, nullptr);
+  if (rc == VOS_ERR_DEVICE) return rc;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(stq));
+  dg.it_p_fp64 = s->it_p_fp64;
+  dg.outer_res = r0;
+  dg.outer_its = 1;
+  if (out) *out = dg;
+  return rc;
+}

@@ -113,6 +113,9 @@ def lib():
         L.vos_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.vos_get_state.argtypes = [vp, vp, C.c_size_t]
         L.vos_set_state.argtypes = [vp, vp, C.c_size_t]
+        L.vos_solve_pressure_noalloc.argtypes = [C.POINTER(_Grid), C.POINTER(_Params), C.POINTER(_Opts), C.c_double,
+                                                 vp, vp, vp, vp, vp, vp, C.POINTER(_Diag)]
+        L.vos_solve_pressure_noalloc.restype = C.c_int
         L.vos_last_error.restype = C.c_char_p
         for name in ("vos_workspace_bytes", "vos_create", "vos_destroy", "vos_set_solid_fraction",
                      "vos_set_field", "vos_set_params", "vos_get_field", "vos_field_ptr", "vos_step", "vos_diagnostics",
@@ -311,3 +314,26 @@ class Sim:
     def set_state(self, state: bytes):
         buf = C.create_string_buffer(state, len(state))
         _check(lib().vos_set_state(self._h, buf, len(state)))
+
+
+def solve_pressure_noalloc(nx: int, ny: int, nz: int, dx: float, params: dict, opts: Opts, dt: float,
+                           eps, ux, uy, uz, p, stream=None) -> dict:
+    """vos_solve_pressure_noalloc on device tensors (float64, contiguous):
+    eps, ux, uy, uz are read, p is overwritten with the solution.  The library
+    allocates nothing; the tensors are the caller's."""
+    import torch
+    for t in (eps, ux, uy, p) + ((uz,) if nz > 1 else ()):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("device float64 contiguous tensors expected")
+    g = _Grid(nx, ny, nz, dx)
+    pr = make_params(params)
+    o = _Opts(**asdict(opts))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    torch.cuda.current_stream().synchronize()
+    dg = _Diag()
+    rc = lib().vos_solve_pressure_noalloc(C.byref(g), C.byref(pr), C.byref(o), dt, C.c_void_p(eps.data_ptr()),
+                                          C.c_void_p(ux.data_ptr()), C.c_void_p(uy.data_ptr()),
+                                          C.c_void_p(uz.data_ptr()) if nz > 1 else None,
+                                          C.c_void_p(p.data_ptr()), C.c_void_p(st.cuda_stream), C.byref(dg))
+    _check(rc, diag_to_dict(dg))
+    return diag_to_dict(dg)
