@@ -67,6 +67,14 @@ vos_status vos_unet_destroy(vos_unet *net);
 vos_status vos_unet_set_params(vos_unet *net, const float *theta, int on_device);
 vos_status vos_unet_get_params(vos_unet *net, float *theta, int on_device);
 
+/* Parameters to / from a file: 8 bytes "VOSUNET1", the parameter count as a
+ * uint64 in the host's byte order, then the flat FP32 vector in the order
+ * above.  vos_unet_load checks the header and the length (VOS_ERR_ARG on a
+ * mismatch, a missing file or non-finite values) and then behaves as
+ * vos_unet_set_params (the Adam state is cleared). */
+vos_status vos_unet_save(vos_unet *net, const char *path);
+vos_status vos_unet_load(vos_unet *net, const char *path);
+
 /* Gradient of the last vos_unet_loss_grad / vos_unet_train_step, flat order. */
 vos_status vos_unet_get_grads(vos_unet *net, float *grad, int on_device);
 

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -403,6 +404,43 @@ vos_status vos_unet_get_params(vos_unet *net, float *theta, int on_device)
 {
   if (!net || !theta) return fail(VOS_ERR_ARG, "NULL network or output");
   return copy_vec(theta, net->theta, n_params() * sizeof(float), on_device, false, net->stream);
+}
+
+// File of a network's parameters: 8 bytes "VOSUNET1", the parameter count
+// (uint64, little-endian as the host writes it), then the flat FP32 vector.
+vos_status vos_unet_save(vos_unet *net, const char *path)
+{
+  if (!net || !path) return fail(VOS_ERR_ARG, "NULL network or path");
+  const size_t P = n_params();
+  std::vector<float> h(P);
+  if (vos_status st = copy_vec(h.data(), net->theta, P * sizeof(float), 0, false, net->stream)) return st;
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(VOS_ERR_ARG, std::string("cannot open ") + path + " for writing");
+  const char magic[8] = {'V', 'O', 'S', 'U', 'N', 'E', 'T', '1'};
+  const uint64_t n = P;
+  bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&n, sizeof(n), 1, f) == 1 &&
+            std::fwrite(h.data(), sizeof(float), P, f) == P;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(VOS_ERR_ARG, std::string("write to ") + path + " failed");
+  return VOS_OK;
+}
+
+vos_status vos_unet_load(vos_unet *net, const char *path)
+{
+  if (!net || !path) return fail(VOS_ERR_ARG, "NULL network or path");
+  const size_t P = n_params();
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(VOS_ERR_ARG, std::string("cannot open ") + path);
+  char magic[8];
+  uint64_t n = 0;
+  std::vector<float> h(P);
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "VOSUNET1", 8) == 0 &&
+            std::fread(&n, sizeof(n), 1, f) == 1 && n == P && std::fread(h.data(), sizeof(float), P, f) == P;
+  char extra;
+  ok = ok && std::fread(&extra, 1, 1, f) == 0;   // nothing after the parameters
+  std::fclose(f);
+  if (!ok) return fail(VOS_ERR_ARG, std::string(path) + " is not a parameter file of this network");
+  return vos_unet_set_params(net, h.data(), 0);
 }
 
 vos_status vos_unet_get_grads(vos_unet *net, float *grad, int on_device)

@@ -7,6 +7,7 @@ stream of its own (default priority) unless one is given.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import Optional
 
 import numpy as np
@@ -44,6 +45,8 @@ def lib():
             "vos_unet_train_step": [vp, vp, vp, C.c_float, C.POINTER(C.c_double)],
             "vos_attach_unet": [vp, vp, C.POINTER(_WarmStart)],
             "vos_warm_start_sample": [vp, vp, vp],
+            "vos_unet_save": [vp, C.c_char_p],
+            "vos_unet_load": [vp, C.c_char_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -118,16 +121,18 @@ class UNet:
         vos._check(lib().vos_unet_get_params(self._h, out.ctypes.data_as(C.c_void_p), 0))
         return out
 
+    def save(self, path: str):
+        """Parameters to a file (vos_unet_save)."""
+        vos._check(lib().vos_unet_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Parameters from a file written by save (vos_unet_load)."""
+        vos._check(lib().vos_unet_load(self._h, os.fsencode(path)))
+
     def get_grads(self) -> np.ndarray:
         out = np.empty(self.n_params, np.float32)
         vos._check(lib().vos_unet_get_grads(self._h, out.ctypes.data_as(C.c_void_p), 0))
         return out
-
-    def save(self, path: str):
-        np.save(path, self.get_params())
-
-    def load(self, path: str):
-        self.set_params(np.load(path, allow_pickle=False))
 
     # ---------------------------------------------------------------- compute
     def forward(self, x):

@@ -136,10 +136,15 @@ def test_training_reduces_loss_and_params_roundtrip(tmp_path):
     print(losses[0], losses[-1])
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.3 * losses[0]
-    p = tmp_path / "w.npy"
-    net.save(str(p))
+    p = tmp_path / "w.vosunet"
+    net.save(str(p))                                   # vos_unet_save
     inf = UNet(2, 8, 8, 64, cin=4, train=False)
-    inf.load(str(p))
+    inf.load(str(p))                                   # vos_unet_load
+    np.testing.assert_array_equal(inf.get_params(), net.get_params())
+    # a truncated file is refused
+    (tmp_path / "short").write_bytes(p.read_bytes()[:-4])
+    with pytest.raises(Exception):
+        inf.load(str(tmp_path / "short"))
     y1 = net.forward(xt).cpu().numpy()
     y2 = inf.forward(xt).cpu().numpy()
     np.testing.assert_array_equal(y1, y2)
