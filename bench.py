@@ -1,17 +1,21 @@
 """Benchmark of the Volume-of-Solid step on one MI355X.
 
-Workload (default): the 1024x512 2-D polydisperse disc micromodel (dx = 5 um,
-RSA discs with radii 10-40 cells to porosity 0.6, seed 11), iVoS, dt = 1 ms,
-inlet velocity and k_c set for Pe = 10, Da = 0.1 from the measured
-permeability (L = sqrt(12 K / phi), U = U_D / phi).  A step is one pass of the
+Workload (default, the headline): the 256^3 synthetic grain pack (dx = 4 um,
+overlapping spheres of log-normal radius, median 20 voxels, sigma 0.3, seed
+33, to porosity 0.23, one-voxel partial-volume ramp and 1 % interface noise,
+2-voxel fluid bands at inlet and outlet), driven by a constant inlet pressure
+scaled to Pe = 10 (L = sqrt(8 K / phi), U = U_D / phi, phi without the bands)
+with Da = 1e-2, iVoS, dt = 1 ms, dissolving.  A step is one pass of the
 whole step: coefficients, momentum predictor, pressure equation
 (multigrid-preconditioned CG to a 1e-8 relative residual), correction,
 transport (BiCGStab), reaction and solid update.  Inputs stay resident in HBM.
 
 Prints ONE JSON line: cell-steps/s of the mixed-precision step (FP32
-multigrid inside FP64 Krylov), with the plain-FP64 step, the pressure-solve
-bandwidth, the live roofline of the dominant kernel and the CPU oracle beside
-it.
+multigrid inside FP64 Krylov), beside the plain-FP64 step on the same state,
+VoS-psi' on the same state, the pressure-solve bandwidth, the live roofline
+of the kernel that dominates the step's kernel time, the learned warm start,
+the 2-D micromodel (Infinity-Cache resident), the micromodel batch, and the
+CPU oracle on a bounded crop of the same pack.
 """
 from __future__ import annotations
 
@@ -20,6 +24,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -62,6 +68,8 @@ def p_iter_bytes(nd, tag, nu=None):
 # comes after as many chunks as the last solve of the same kind took, so short
 # chunks waste at most one early-exit iteration (4.00 -> 3.96 ms/step against 4).
 CHECK_EVERY = 2
+# ... and on the 3-D pack, where a pressure solve takes tens of iterations
+CHECK_EVERY_3D = 8
 # The solves start from an extrapolation of the last steps' solutions
 # (vos_opts.extrapolate = 2: 2 x^n - x^(n-1), or 3 x^n - 3 x^(n-1) + x^(n-2) where
 # that order predicted the last solution better); the start-from-x^n rate is
@@ -137,17 +145,79 @@ def setup_sim(vos, inputs, scaling, workload, pe, da, precision, model, dt, rela
     return sim, es, dict(params, u_in=u_in, kc=kc), dict(K=K, phi=phi, u_in=u_in, kc=kc, ndim=ndim)
 
 
-def timed_steps(sim, dt, steps, warmup):
+# Kernel families timed live on the pack (the pressure operator and the z-marching
+# kernels of the pressure hierarchy's finest level).
+PACK_TIMERS = ("p_apply", "p_pre3d", "p_sweep3d", "p_restrict3d", "p_post3d")
+# Settling of the pack's flow before it is rescaled to the target Pe: frozen-solid
+# iterations (vos_initialize) at a short step until the face velocities change
+# by at most PACK_SETTLE_TOL relative per iteration.  Each step of the
+# projection is one SIMPLE-like iteration whose implicit relaxation is set by
+# rho / dt against the viscous coupling mu / dx^2 (60x larger at dt = 1 ms,
+# dx = 4 um): at 1 ms the permeability approaches its steady value by ~1.5 %
+# per step, at 60 us it halves its distance every ~9 steps.
+PACK_SETTLE_DT = 6e-5
+PACK_SETTLE_TOL = 1e-4
+PACK_SETTLE_MAX = 150
+
+
+def setup_pack(vos, inputs, scaling, n, pe, da, precision, model, dt, extrapolate=EXTRAPOLATE):
+    """The grain pack under a constant inlet pressure: settle the flow to its
+    steady state with the solid frozen and no reaction, measure K and phi (phi without the 2-voxel
+    inlet/outlet bands), then rescale the (Stokes-linear) flow to the pressure
+    drop that gives Pe and set k_c for Da."""
+    import torch
+    es = inputs.sphere_pack(n, seed=33)
+    prm = dict(inputs.BASE_PARAMS, dx=4e-6)
+    p0 = 1.0
+    params = dict(prm, model=model, drive=1, p_in=prm["p_out"] + p0)
+    opts = vos.Opts(precision=precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000,
+                    check_every=CHECK_EVERY_3D, extrapolate=extrapolate, setup_every=SETUP_EVERY)
+    sim = vos.Sim(n, n, n, prm["dx"], dict(params, kc=0.0), opts)
+    sim.set_solid_fraction(es)
+    t0 = time.perf_counter()
+    dinit = sim.initialize(PACK_SETTLE_DT, PACK_SETTLE_MAX, PACK_SETTLE_TOL)
+    d = sim.step(PACK_SETTLE_DT, 1, freeze_solid=True)
+    settle = dict(iterations=dinit["outer_its"] + 1, last_rel_change=dinit["outer_res"],
+                  seconds=round(time.perf_counter() - t0, 1))
+    K = d["K"]
+    phi = float(sim.get("eps")[:, :, 2:-2].mean())
+    dp, kc = scaling.pressure_drop_for(pe, da, K, phi, prm["D"], prm["mu"], n * prm["dx"], 3)
+    r = dp / p0
+    for name in ("ux", "uy", "uz"):
+        sim.set(name, sim.get(name) * r)
+    sim.set("p", (sim.get("p") - prm["p_out"]) * r + prm["p_out"])
+    params = dict(params, p_in=prm["p_out"] + dp, kc=kc)
+    sim.set_params(params)
+    for _ in range(SETUP_STEPS):
+        sim.step(dt, 1, freeze_solid=True)
+    torch.cuda.synchronize()
+    return sim, es, params, dict(K=K, phi=phi, dp=dp, kc=kc, ndim=3, settle=settle)
+
+
+# Host clocks at the synchronised start and end of each timed run, by leg name
+# (bench.py --trace-window writes them for trace_window.py to cut a kernel trace).
+TRACE_WINDOWS = {}
+
+
+def _clocks():
+    return time.clock_gettime_ns(time.CLOCK_MONOTONIC), time.clock_gettime_ns(time.CLOCK_BOOTTIME)
+
+
+def timed_steps(sim, dt, steps, warmup, leg=None):
     import torch
     for _ in range(warmup):
         sim.step(dt)
     diags = []
     torch.cuda.synchronize()
+    c0 = _clocks()
     t0 = time.perf_counter()
     for _ in range(steps):
         diags.append(sim.step(dt))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    c1 = _clocks()
+    if leg:
+        TRACE_WINDOWS[leg] = {"monotonic": [c0[0], c1[0]], "boottime": [c0[1], c1[1]], "steps": steps}
     return el, diags
 
 
@@ -185,49 +255,6 @@ def roofline(sim, family, reps=200, with_traffic=True):
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(family) if with_traffic else None, "kernel": family,
             "avg_launch_us": round(t["avg_ms"] * 1e3, 3), "bytes_per_launch": round(t["bytes"])}
-
-
-def pressure_3d(vos, inputs, n, dt, precision=None):
-    """The pressure solve on the 256^3 sphere pack (dx = 4 um, seed 33), FP64
-    (or mixed-precision) multigrid, from a flow relaxed by two steps:
-    algorithmic GB/s of the pressure stage and the live roofline of the
-    pressure operator."""
-    import torch
-    precision = vos.FP64 if precision is None else precision
-    tag = "fp64" if precision == vos.FP64 else "mixed"
-    es = inputs.sphere_pack(n, seed=33)
-    prm = dict(inputs.BASE_PARAMS, dx=4e-6, model=0)
-    sim = vos.Sim(n, n, n, prm["dx"], dict(prm, kc=0.0),
-                  vos.Opts(precision=precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000))
-    sim.set_solid_fraction(es)
-    conv = True
-    try:
-        for _ in range(2):
-            sim.step(dt, 1, freeze_solid=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        d = sim.step(dt, 1, freeze_solid=True)
-    except vos.VosError as e:
-        # the pressure multigrid is weak on this geometry (thin partial-volume
-        # channels); report the unconverged solve instead of aborting
-        conv, d = False, e.diag
-        t0 = time.perf_counter()
-    el = time.perf_counter() - t0
-    cells = n ** 3
-    t_p = d["t_ms"][2] * 1e-3
-    # iterations run with the FP64 hierarchy (a mixed solve after a stall) move FP64 bytes
-    its64 = d["it_p"] if precision == vos.FP64 else d["it_p_fp64"]
-    pb = cells * (p_iter_bytes(3, tag) * (d["it_p"] - its64) + p_iter_bytes(3, "fp64") * its64 +
-                  P_SETUP_BYTES[3])
-    hier = "FP64" if precision == vos.FP64 else "FP32"
-    out = {"workload": f"pack {n}^3 dx=4um porosity 0.23 seed 33, {hier} multigrid, rtol 1e-8",
-           "converged": conv, "res_p": d["res_p"],
-           "its": d["it_p"], "its_fp64_hierarchy": d["it_p_fp64"] if precision != vos.FP64 else d["it_p"],
-           "pressure_ms": round(d["t_ms"][2], 2), "step_ms": round(el * 1e3, 1),
-           "GBs_algorithmic": round(pb / t_p / 1e9, 1), "frac_hbm": round(pb / t_p / 1e9 / HBM_PEAK_GBS, 4),
-           "p_apply_roofline": roofline(sim, "p_apply", with_traffic=False) if conv else None}
-    sim.close()
-    return out
 
 
 BATCH_SIZES = ((256, 128), (512, 256), (768, 384), (1024, 512))
@@ -403,20 +430,51 @@ def learned_3d(vos, inputs, n, dt, snapshots=60, iters=400, steps=10):
     return out
 
 
+def cpu_baseline_pack(n_crop, params, dt, budget_s):
+    """The oracle (plain C, one thread) on a bounded sample of the headline
+    workload: an n_crop^3 corner of the 256^3 pack with the same parameters
+    (the inlet pressure drop scaled with the crop's length, so the same
+    pressure gradient), from rest: one step to leave the cold start, then
+    steps until the budget is used."""
+    import oracle
+    from paper_2204_07019_amd import inputs
+    oracle.build(force=False)
+    es = np.ascontiguousarray(inputs.sphere_pack(256, seed=33)[:n_crop, :n_crop, :n_crop])
+    keys = ("mu", "rho", "D", "k0", "kc", "Vm", "zeta", "c_in", "eps_min", "u_in", "p_out", "model", "drive")
+    kw = {k: params[k] for k in keys}
+    kw["p_in"] = params["p_out"] + (params["p_in"] - params["p_out"]) * n_crop / 256.0
+    prob = oracle.Problem(nx=n_crop, ny=n_crop, nz=n_crop, dx=params["dx"], **kw, rtol_u=1e-8, rtol_p=1e-8,
+                          rtol_c=1e-8)
+    st = oracle.initial_state(prob, es)
+    t0 = time.perf_counter()
+    oracle.step(prob, st, dt, check=False)           # leave the cold start
+    t_cold = time.perf_counter() - t0
+    nsteps, t = 0, 0.0
+    while t < budget_s and nsteps < 20:
+        t0 = time.perf_counter()
+        oracle.step(prob, st, dt, check=False)
+        t += time.perf_counter() - t0
+        nsteps += 1
+    cells = n_crop ** 3
+    return {"value": cells * nsteps / t, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} steps of a {n_crop}^3 corner of the 256^3 pack (same parameters, pressure drop "
+                      f"scaled to the crop length, FP64, single-threaded C, rtol 1e-8), {t:.1f} s after a "
+                      f"{t_cold:.1f} s cold-start step"}
+
+
 def cpu_baseline(workload, params, dt, budget_s):
-    """The oracle (plain C, one thread) on a bounded sample of the workload:
-    a crop of the same geometry, one step at a time until the budget is used."""
-    import numpy as np
+    """The oracle (plain C, one thread) on a bounded sample of a 2-D
+    workload: a crop of the same geometry, one step at a time until the
+    budget is used."""
     import oracle
     from paper_2204_07019_amd import inputs
     oracle.build(force=False)
     es, prm = inputs.workload(workload)
     nz, ny, nx = es.shape
     cy, cx = max(1, ny // 4), max(2, nx // 4)
-    crop = np.ascontiguousarray(es[:, :cy, :cx]) if nz == 1 else np.ascontiguousarray(es[:cy, :cy, :cx])
-    cz = crop.shape[0]
+    crop = np.ascontiguousarray(es[:, :cy, :cx])
     keys = ("mu", "rho", "D", "k0", "kc", "Vm", "zeta", "c_in", "eps_min", "u_in", "p_out", "model")
-    prob = oracle.Problem(nx=crop.shape[2], ny=crop.shape[1], nz=cz, dx=prm["dx"],
+    prob = oracle.Problem(nx=crop.shape[2], ny=crop.shape[1], nz=1, dx=prm["dx"],
                           **{k: params[k] for k in keys}, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8)
     st = oracle.initial_state(prob, crop)
     oracle.step(prob, st, dt, check=False)           # leave the cold start
@@ -428,8 +486,91 @@ def cpu_baseline(workload, params, dt, budget_s):
         n += 1
     cells = prob.nx * prob.ny * prob.nz
     return {"value": cells * n / t, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} steps of a {prob.nx}x{prob.ny}x{prob.nz} crop of the {workload} geometry "
+            "sample": f"{n} steps of a {prob.nx}x{prob.ny} crop of the {workload} geometry "
                       f"(same parameters, FP64, single-threaded C), {t:.1f} s"}
+
+
+FIELDS = ("eps", "ux", "uy", "uz", "p", "c")
+
+
+def run_summary(diags, el, cells, steps, nd, tag, info=None, params=None):
+    """Rates, iterations and the pressure stage's algorithmic bandwidth of a timed run."""
+    its_p = sum(d["it_p"] for d in diags)
+    its64 = sum(d["it_p"] if tag == "fp64" else d["it_p_fp64"] for d in diags)
+    t_p = sum(d["t_ms"][2] for d in diags) * 1e-3
+    pb = cells * (p_iter_bytes(nd, tag) * (its_p - its64) + p_iter_bytes(nd, "fp64") * its64 +
+                  P_SETUP_BYTES[nd] * len(diags))
+    out = {"value": cells * steps / el, "ms_per_step": el / steps * 1e3,
+           "pressure_its_per_step": its_p / len(diags), "pressure_its_fp64_hierarchy": its64 / len(diags),
+           "momentum_its_per_step": [sum(d["it_u"][k] for d in diags) / len(diags) for k in range(3)],
+           "transport_its_per_step": sum(d["it_c"] for d in diags) / len(diags),
+           "pressure_ms_per_step": t_p / len(diags) * 1e3,
+           "pressure_GBs_algorithmic": round(pb / t_p / 1e9, 1) if t_p > 0 else None,
+           "pressure_frac_hbm": round(pb / t_p / 1e9 / HBM_PEAK_GBS, 4) if t_p > 0 else None,
+           "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)]}
+    if info is not None and params is not None:
+        from paper_2204_07019_amd import scaling
+        last = diags[-1]
+        sc = scaling.scales(last["K"], info["phi"], last["U_D"], params["D"], params["kc"], nd)
+        out["achieved"] = {"Pe": round(sc["Pe"], 3), "Da": round(sc["Da"], 5), "U_D": last["U_D"], "K": last["K"],
+                           "solid_rate_mol_s": last["solid_rate"], "max_deps": last["max_deps"]}
+    return out
+
+
+def pack_leg(vos, inputs, scaling, args):
+    """The headline (mixed precision, iVoS) on the pack, its live roofline,
+    then the plain-FP64 step and VoS-psi' continuing from the same relaxed
+    state for the same number of steps."""
+    import torch
+    n = args.n3d
+    cells = n ** 3
+    log(f"pack {n}^3: setup (frozen flow, Pe={args.pe:g}, Da={args.da:g})")
+    sim, es, params, info = setup_pack(vos, inputs, scaling, n, args.pe, args.da, vos.MIXED, args.model, args.dt)
+    log(f"K={info['K']:.3e} phi={info['phi']:.3f} dp={info['dp']:.3e} Pa kc={info['kc']:.3e}")
+    state = {k: sim.get(k) for k in FIELDS}
+    el, diags = timed_steps(sim, args.dt, args.steps, args.warmup, leg="headline")
+    head = run_summary(diags, el, cells, args.steps, 3, "mixed", info, params)
+    log(f"mixed iVoS: {head['ms_per_step']:.1f} ms/step, {head['value']:.3e} cell-steps/s, "
+        f"{head['pressure_its_per_step']:.1f} pressure its/step")
+    roof = roofline(sim, args.timer)
+    others = {k: roofline(sim, k, reps=20) for k in PACK_TIMERS if k != args.timer}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    comps = {}
+    for name, prec, model in (("plain_fp64", vos.FP64, args.model), ("psi_prime_mixed", vos.MIXED, 2)):
+        if args.skip_plain or args.only_headline:
+            break
+        opts = vos.Opts(precision=prec, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000,
+                        check_every=CHECK_EVERY_3D, extrapolate=EXTRAPOLATE, setup_every=SETUP_EVERY)
+        s2 = vos.Sim(n, n, n, params["dx"], dict(params, model=model), opts)
+        for k, v in state.items():
+            s2.set(k, v)
+        el2, d2 = timed_steps(s2, args.dt, args.steps, args.warmup, leg=name)
+        comps[name] = run_summary(d2, el2, cells, args.steps, 3, "fp64" if prec == vos.FP64 else "mixed",
+                                  info, dict(params, model=model))
+        log(f"{name}: {comps[name]['ms_per_step']:.1f} ms/step, {comps[name]['value']:.3e} cell-steps/s")
+        s2.close()
+        del s2
+        torch.cuda.empty_cache()
+    return head, roof, others, comps, params, info, cells
+
+
+def micromodel_leg(vos, inputs, scaling, steps, warmup, dt):
+    """The 1024x512 micromodel (Pe = 10, Da = 0.1), mixed precision: its
+    ~100 MB state lives in the 256 MB Infinity Cache, so its rates are
+    cache-resident, not HBM figures."""
+    sim, es, params, info = setup_sim(vos, inputs, scaling, "micromodel", 10.0, 0.1, vos.MIXED, 0, dt, 40)
+    nz, ny, nx = es.shape
+    el, diags = timed_steps(sim, dt, steps, warmup)
+    out = run_summary(diags, el, nx * ny * nz, steps, 2, "mixed")
+    out["workload"] = (f"micromodel {nx}x{ny} dx=5um RSA discs seed 11, iVoS, Pe=10 Da=0.1, dt={dt:g}s, "
+                       "rtol 1e-8, mixed precision; Infinity-Cache (MALL) resident")
+    out["roofline_mall_resident"] = {k: roofline(sim, k, with_traffic=False) for k in ("v_down", "v_up")}
+    for v in out["roofline_mall_resident"].values():
+        v["bound"] = "mall"
+    sim.close()
+    return out
 
 
 def main():
@@ -437,19 +578,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="micromodel")
     ap.add_argument("--pe", type=float, default=10.0)
-    ap.add_argument("--da", type=float, default=0.1)
+    ap.add_argument("--da", type=float, default=1e-2)
     ap.add_argument("--model", type=int, default=0)
     ap.add_argument("--dt", type=float, default=1e-3)
-    ap.add_argument("--relax", type=int, default=40)
-    ap.add_argument("--timer", default="v_down", help="kernel family for the live roofline")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D pressure-solve measurement")
     ap.add_argument("--n3d", type=int, default=256)
-    ap.add_argument("--only-3d", action="store_true", help="measure only the 3-D pressure solve and print it")
+    ap.add_argument("--timer", default="p_sweep3d", help="kernel family of the live roofline")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="the headline pack run alone (profiling): no comparisons or secondary legs")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-crop", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-micromodel", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-micromodel batch")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -457,6 +598,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--n-learned", type=int, default=128)
     ap.add_argument("--unet-n", type=int, default=128)
+    ap.add_argument("--trace-window", default=None,
+                    help="write the host-clock windows of the timed runs to this JSON file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -482,132 +625,70 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     vos.lib()
-    if args.only_3d:
-        print(json.dumps({"pressure_3d": pressure_3d(vos, inputs, args.n3d, args.dt),
-                          "pressure_3d_mixed": pressure_3d(vos, inputs, args.n3d, args.dt, vos.MIXED)}),
-              flush=True)
-        return
 
-    log(f"setup {args.workload} Pe={args.pe} Da={args.da}")
-    sim, es, params, info = setup_sim(vos, inputs, scaling, args.workload, args.pe, args.da,
-                                      vos.MIXED, args.model, args.dt, args.relax)
-    nz, ny, nx = es.shape
-    cells = nx * ny * nz
-    log(f"K={info['K']:.3e} phi={info['phi']:.3f} u_in={info['u_in']:.3e} kc={info['kc']:.3e}")
-
-    el, diags = timed_steps(sim, args.dt, args.steps, args.warmup)
-    value = cells * args.steps / el
-    ms_step = el / args.steps * 1e3
-    log(f"mixed: {ms_step:.2f} ms/step, {value:.3e} cell-steps/s")
-
-    nd = info["ndim"]
-    its_p = sum(d["it_p"] for d in diags)
-    t_p = sum(d["t_ms"][2] for d in diags) * 1e-3
-    p_bytes = cells * (p_iter_bytes(nd, "mixed") * its_p + P_SETUP_BYTES[nd] * len(diags))
-    p_gbs = p_bytes / t_p / 1e9
-
-    plain = None
-    from_xn = None
-    every_step = None
-    if not args.skip_plain:
-        # the same relaxed state, (a) plain FP64 multigrid with the same options,
-        # (b) mixed precision with every solve started from x^n, (c) mixed
-        # precision with every hierarchy rebuilt every step
-        for prec, ex, se in ((vos.FP64, EXTRAPOLATE, SETUP_EVERY), (vos.MIXED, 0, SETUP_EVERY),
-                             (vos.MIXED, EXTRAPOLATE, 1)):
-            sim2 = vos.Sim(nx, ny, nz, inputs.workload(args.workload)[1]["dx"], params,
-                           vos.Opts(precision=prec, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8,
-                                    check_every=CHECK_EVERY, extrapolate=ex, setup_every=se))
-            for k in ("eps", "ux", "uy", "uz", "p", "c"):
-                sim2.set(k, sim.get(k))
-            # as many steps before the timed ones as the headline simulation had since
-            # its last state change (setup's 3 + the warm-up): the same extrapolation history
-            el2, d2 = timed_steps(sim2, args.dt, args.steps, args.warmup + SETUP_STEPS)
-            its2 = sum(d["it_p"] for d in d2)
-            t2 = sum(d["t_ms"][2] for d in d2) * 1e-3
-            tag = "fp64" if prec == vos.FP64 else "mixed"
-            pb2 = cells * (p_iter_bytes(nd, tag) * its2 + P_SETUP_BYTES[nd] * len(d2))
-            res = {"value": cells * args.steps / el2, "ms_per_step": el2 / args.steps * 1e3,
-                   "pressure_its_per_step": its2 / len(d2), "pressure_GBs": pb2 / t2 / 1e9,
-                   "transport_its_per_step": sum(d["it_c"] for d in d2) / len(d2)}
-            if prec == vos.FP64:
-                plain = res
-                log(f"fp64: {res['ms_per_step']:.2f} ms/step, {res['value']:.3e} cell-steps/s")
-            elif se == 1:
-                every_step = res
-                log(f"mixed, hierarchies rebuilt every step: {res['ms_per_step']:.2f} ms/step")
-            else:
-                from_xn = res
-                log(f"mixed, solves started from x^n: {res['ms_per_step']:.2f} ms/step")
-            sim2.close()
-
-    roof = roofline(sim, args.timer)
-    others = {k: roofline(sim, k) for k in ("v_up", "v_coarse", "p_apply", "adr_apply")}
-    p3d = None if args.no_3d else pressure_3d(vos, inputs, args.n3d, args.dt)
-    p3d_mixed = None if args.no_3d else pressure_3d(vos, inputs, args.n3d, args.dt, vos.MIXED)
-    bat = None
-    if not args.no_batch:
-        log(f"batch of {args.batch_n} micromodels")
-        bat = batch_bench(vos, inputs, scaling, args.batch_n, args.batch_steps, args.dt)
-        log(f"batch: {bat['value']:.3e} cell-steps/s, {bat['ms_per_batch_step']:.1f} ms per batch step; "
-            f"one after another {bat['sequential_value']:.3e}")
-    net = None
-    if not args.no_unet:
-        log(f"U-Net {args.unet_n}^3")
-        net = unet_bench(inputs, args.unet_n, 2)
-    learned = None
-    if not args.no_learned:
-        log(f"learned warm start {args.n_learned}^3")
-        learned = learned_3d(vos, inputs, args.n_learned, 2e-3)
-        log("learned: " + ", ".join(f"{k} {learned[k]['ms_per_step']:.1f} ms/step"
-                                     for k in ("plain_fp64", "mixed", "mixed_learned")))
-
+    head, roof, others, comps, params, info, cells = pack_leg(vos, inputs, scaling, args)
+    n = args.n3d
+    extra = {}
+    if not args.only_headline:
+        if not args.no_learned:
+            log(f"learned warm start {args.n_learned}^3")
+            extra["learned_3d"] = learned_3d(vos, inputs, args.n_learned, 2e-3)
+            log("learned: " + ", ".join(f"{k} {extra['learned_3d'][k]['ms_per_step']:.1f} ms/step"
+                                         for k in ("plain_fp64", "mixed", "mixed_learned")))
+        if not args.no_micromodel:
+            log("micromodel 1024x512")
+            extra["micromodel_mall_resident"] = micromodel_leg(vos, inputs, scaling, 20, 3, args.dt)
+        if not args.no_batch:
+            log(f"batch of {args.batch_n} micromodels")
+            extra["batch_micromodels"] = batch_bench(vos, inputs, scaling, args.batch_n, args.batch_steps, args.dt)
+        if not args.no_unet:
+            log(f"U-Net {args.unet_n}^3")
+            extra["unet"] = unet_bench(inputs, args.unet_n, 2)
+        extra["hbm_streaming_ceiling"] = streaming_ceiling()
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.only_headline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(args.workload, params, args.dt, args.cpu_budget)
-
-    ceiling = streaming_ceiling()
-    log(f"streaming ceiling: read {ceiling['read_GBs']} GB/s, triad {ceiling['triad_GBs']} GB/s")
-    last = diags[-1]
+        cpu = cpu_baseline_pack(args.cpu_crop, params, args.dt, args.cpu_budget)
     out = {
         "metric": "cell-steps/s + pressure-solve HBM GB/s at 1e-8 residual; learned+mixed vs plain",
-        "value": value,
+        "value": head["value"],
         "unit": "cell-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64 (FP32 multigrid preconditioners)",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload} {nx}x{ny}x{nz} dx=5um RSA discs seed 11, iVoS, "
-                               f"Pe={args.pe:g} Da={args.da:g}, dt={args.dt:g}s, rtol 1e-8",
+        "config": {"workload": f"grain pack {n}^3 dx=4um, log-normal spheres (median 20 voxels, sigma 0.3) "
+                               f"seed 33 to porosity 0.23, 1% interface noise, constant-pressure drive at "
+                               f"Pe={args.pe:g}, Da={args.da:g}, iVoS, dt={args.dt:g}s, dissolving, rtol 1e-8",
                    "precision": "mixed", "cells": cells,
                    "solver_starts": {0: "x^n", 1: "extrapolated 2x^n - x^(n-1)",
                                      2: "extrapolated 2x^n - x^(n-1) or 3x^n - 3x^(n-1) + x^(n-2), "
                                         "the order that predicted x^n better"}[EXTRAPOLATE],
-                   "multigrid_setup_every_steps": SETUP_EVERY},
-        "pressure_solve": {"GBs_algorithmic": round(p_gbs, 1), "frac_hbm": round(p_gbs / HBM_PEAK_GBS, 4),
-                           "its_per_step": its_p / len(diags), "ms_per_step": t_p / len(diags) * 1e3},
-        "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)],
-        "iterations": {"u": last["it_u"], "p": last["it_p"], "c": last["it_c"]},
-        "plain_fp64": plain,
-        "mixed_started_from_xn": from_xn,
-        "mixed_hierarchies_every_step": every_step,
+                   "multigrid_setup_every_steps": SETUP_EVERY,
+                   "setup": {"K": info["K"], "phi_without_bands": info["phi"], "dp_Pa": info["dp"],
+                             "kc": info["kc"]}},
+        "pressure_solve": {"GBs_algorithmic": head["pressure_GBs_algorithmic"],
+                           "frac_hbm": head["pressure_frac_hbm"],
+                           "its_per_step": head["pressure_its_per_step"],
+                           "its_fp64_hierarchy_per_step": head["pressure_its_fp64_hierarchy"],
+                           "ms_per_step": head["pressure_ms_per_step"]},
+        "headline_run": head,
+        "plain_fp64": comps.get("plain_fp64"),
+        "psi_prime_mixed": comps.get("psi_prime_mixed"),
         "roofline": roof,
         "roofline_other_kernels": others,
-        "hbm_streaming_ceiling": ceiling,
-        "pressure_solve_3d": p3d,
-        "pressure_solve_3d_mixed": p3d_mixed,
-        "batch_micromodels": bat,
-        "unet": net,
-        "learned_3d": learned,
         "cpu_baseline": cpu,
     }
-    sim.close()
+    out.update(extra)
+    if args.trace_window:
+        os.makedirs(os.path.dirname(os.path.abspath(args.trace_window)), exist_ok=True)
+        with open(args.trace_window, "w") as f:
+            json.dump(TRACE_WINDOWS, f)
     print(json.dumps(out), flush=True)
 
 

@@ -343,7 +343,13 @@ typedef enum {
   VOS_KERNEL_P_APPLY = 4,     /* pressure operator application (FP64) */
   VOS_KERNEL_ADR_APPLY = 5,   /* transport operator application (FP64) */
   VOS_KERNEL_V_DOWN = 6,      /* 2-D tiled down leg (pre-sweeps + restriction), finest transport level */
-  VOS_KERNEL_V_UP = 7         /* 2-D tiled up leg (prolongation + post-sweeps), finest transport level */
+  VOS_KERNEL_V_UP = 7,        /* 2-D tiled up leg (prolongation + post-sweeps), finest transport level */
+  /* 3-D pressure hierarchy, finest level, z-marching kernels in the arithmetic of the
+     hierarchy the last pressure solve used (FP32 in mixed precision unless it fell back): */
+  VOS_KERNEL_P_PRE3D = 8,     /* first down launch: two damped-Jacobi sweeps from the FP64 residual */
+  VOS_KERNEL_P_SWEEP3D = 9,   /* one further damped-Jacobi sweep */
+  VOS_KERNEL_P_RESTRICT3D = 10, /* residual restricted to the next level */
+  VOS_KERNEL_P_POST3D = 11    /* prolongation fused with the first up sweep */
 } vos_kernel_family;
 
 /* Time `reps` back-to-back launch sequences of one kernel family on the live

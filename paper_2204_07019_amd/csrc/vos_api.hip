@@ -1551,11 +1551,13 @@ vos_status momentum_stage(vos_sim *s, double dt, vos_diag *dg, double *r0, vos_s
 // 1/p_scale, which depends on it.
 void set_time_step(vos_sim *s, double dt)
 {
+  // every matrix carries dt (the momentum diagonal rho eps / dt, the pressure
+  // transmissibilities through it): a new dt rebuilds every hierarchy at its next solve
   const double ps = pressure_scale(s, dt);
   if (ps != s->p_scale) {
     drop_graphs(s);
     s->p_scale = ps;
-    s->mg_age[H_P] = s->mg_age[H_P64] = 1 << 30;
+    hierarchies_stale(s);
   }
 }
 
@@ -1786,6 +1788,63 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
 }
 
 }  // namespace
+
+// Back-to-back launches of one z-marching kernel of the pressure hierarchy's
+// finest level (3-D), in the arithmetic of the hierarchy the last pressure
+// solve used, with the production launch shape.  They write only the level's
+// V-cycle buffers, which every V-cycle rebuilds from its input.  Bytes per
+// fine cell (w = bytes of the hierarchy's arithmetic; every array once; the
+// finest diagonal is formed from the faces except where a kernel reads it):
+//   pre (first down launch, two sweeps from the FP64 residual): r (8) + diag,
+//     3 face T, write b, write x (5 w);  sweep: x, 3 T, b, write (6 w);
+//   restrict: x, 3 T, b (5 w) + coarse b (w / 8);
+//   post (prolongation + first up sweep): x, 3 T, b, write (6 w) + coarse x (w / 8).
+template <typename R>
+vos_status time_p_kernel_t(vos_sim *s, MgLevel<R> *lv, int family, int reps, double *ms, double *bytes)
+{
+  hipStream_t st = s->stream;
+  if (s->g.nd != 3 || s->nlev < 2) return fail(VOS_ERR_ARG, "the pressure-level families time 3-D hierarchies");
+  MgLevel<R> F = lv[0];
+  if (!(F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2))
+    return fail(VOS_ERR_ARG, "the finest pressure level is too narrow for the z-marching kernels");
+  const int zl = zrun_len(F.n);
+  const dim3 gr(zrun_blocks(F.n, zl));
+  const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
+  const R om = (R)(6.0 / 7.0);
+  const double w = sizeof(R), nc = F.nc;
+  double per = 0.0;
+  auto launch = [&]() {
+    switch (family) {
+      case VOS_KERNEL_P_PRE3D:
+        k_v_pre3d<MgLevel<R>, R, RHS_R><<<gr, TPB, 0, st>>>(F, s->vec[1], nullptr, 1.0 / s->p_scale, om, zl, flag);
+        per = (8.0 + 5.0 * w) * nc;
+        break;
+      case VOS_KERNEL_P_SWEEP3D:
+        k_v_jacobi3d<MgLevel<R>, R, false><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, nullptr, nullptr, zl, flag);
+        per = 6.0 * w * nc;
+        break;
+      case VOS_KERNEL_P_RESTRICT3D:
+        k_v_restrict3d<MgLevel<R>, R><<<gr, TPB, 0, st>>>(F, lv[1], zl, flag);
+        per = 5.0 * w * nc + w * lv[1].nc;
+        break;
+      default:
+        k_v_post3d<MgLevel<R>, R, false><<<gr, TPB, 0, st>>>(F, lv[1], F.t, om, nullptr, nullptr, zl, flag);
+        per = 6.0 * w * nc + w * lv[1].nc;
+        break;
+    }
+  };
+  launch();   // warm-up
+  HIP_TRY(hipEventRecord(s->ev[0], st));
+  for (int k = 0; k < reps; ++k) launch();
+  HIP_TRY(hipEventRecord(s->ev[1], st));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventSynchronize(s->ev[1]));
+  float el = 0.f;
+  HIP_TRY(hipEventElapsedTime(&el, s->ev[0], s->ev[1]));
+  *ms = (double)el / reps;
+  *bytes = per;
+  return VOS_OK;
+}
 
 // Frees what vos_create made besides the workspace (the caller's); used on
 // creation failure and by vos_destroy.
@@ -2068,6 +2127,11 @@ vos_status vos_time_kernel(vos_sim *s, int family, int reps, double *avg_launch_
   if (!s || !avg_launch_ms || !bytes_per_launch) return fail(VOS_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 100000) return fail(VOS_ERR_ARG, "reps must be in [1, 100000]");
   if (!s->stepped) return fail(VOS_ERR_STATE, "run vos_step first");
+  if (family >= VOS_KERNEL_P_PRE3D && family <= VOS_KERNEL_P_POST3D) {
+    if (s->opt.precision == VOS_MIXED && !s->p_fp64_sticky)
+      return time_p_kernel_t<float>(s, s->mgf, family, reps, avg_launch_ms, bytes_per_launch);
+    return time_p_kernel_t<double>(s, s->mgd, family, reps, avg_launch_ms, bytes_per_launch);
+  }
   return time_kernel_t<double>(s, s->smgd[3], family, reps, avg_launch_ms, bytes_per_launch);
 }
 

@@ -27,3 +27,11 @@ def inlet_for(Pe: float, Da: float, K: float, phi: float, D: float, ndim: int):
     L = pore_length(K, phi, ndim)
     U = Pe * D / L
     return U * phi, Da * U
+
+
+def pressure_drop_for(Pe: float, Da: float, K: float, phi: float, D: float, mu: float, L_D: float, ndim: int):
+    """Pressure drop across L_D and reaction constant giving (Pe, Da) under a
+    pressure drive: the Darcy velocity U_D = U phi of inlet_for, dP = mu U_D L_D / K
+    (Section 2.5's permeability read backwards)."""
+    U_D, kc = inlet_for(Pe, Da, K, phi, D, ndim)
+    return mu * U_D * L_D / K, kc
