@@ -147,7 +147,24 @@ def setup_sim(vos, inputs, scaling, workload, pe, da, precision, model, dt, rela
 
 # Kernel families timed live on the pack (the pressure operator and the z-marching
 # kernels of the pressure hierarchy's finest level).
-PACK_TIMERS = ("p_apply", "p_pre3d", "p_sweep3d", "p_restrict3d", "p_post3d")
+PACK_TIMERS = ("c_pre3d", "c_sweep3d", "c_restrict3d", "c_post3d", "adr_apply",
+               "p_apply", "p_pre3d", "p_sweep3d", "p_restrict3d", "p_post3d")
+# The live roofline's kernel: the one with the most kernel time in the headline's
+# timed steps on the committed trace (the first post-smoothing launch of the
+# transport hierarchy's finest level, k_v_post3d<SLevel<double>>).
+ROOFLINE_FAMILY = "c_post3d"
+KERNEL_NAMES = {
+    "c_pre3d": "k_v_pre3d<SLevel<double>> transport hierarchy, finest level (two sweeps from the residual)",
+    "c_sweep3d": "k_v_jacobi3d<SLevel<double>> transport hierarchy, finest level (one sweep)",
+    "c_restrict3d": "k_v_restrict3d<SLevel<double>> transport hierarchy, finest level (residual restriction)",
+    "c_post3d": "k_v_post3d<SLevel<double>> transport hierarchy, finest level (prolongation + first up sweep)",
+    "adr_apply": "k_adr_apply transport operator (FP64)",
+    "p_apply": "k_p_apply3d pressure operator (FP64)",
+    "p_pre3d": "k_v_pre3d<MgLevel> pressure hierarchy, finest level",
+    "p_sweep3d": "k_v_jacobi3d<MgLevel> pressure hierarchy, finest level",
+    "p_restrict3d": "k_v_restrict3d<MgLevel> pressure hierarchy, finest level",
+    "p_post3d": "k_v_post3d<MgLevel> pressure hierarchy, finest level",
+}
 # Settling of the pack's flow before it is rescaled to the target Pe: frozen-solid
 # iterations (vos_initialize) at a short step until the face velocities change
 # by at most PACK_SETTLE_TOL relative per iteration.  Each step of the
@@ -221,16 +238,6 @@ def timed_steps(sim, dt, steps, warmup, leg=None):
     return el, diags
 
 
-def kernel_sources_sha() -> str:
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2204_07019_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(family):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     runs (profiles/hbm_traffic.json), or None if the kernels changed since."""
@@ -240,6 +247,7 @@ def measured_traffic(family):
             t = json.load(f)
     except OSError:
         return None
+    from paper_2204_07019_amd.trace_window import kernel_sources_sha
     if t.get("csrc_sha") != kernel_sources_sha():
         return None
     k = t.get("kernels", {}).get(family)
@@ -254,6 +262,7 @@ def roofline(sim, family, reps=200, with_traffic=True):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(family) if with_traffic else None, "kernel": family,
+            "kernel_name": KERNEL_NAMES.get(family, family),
             "avg_launch_us": round(t["avg_ms"] * 1e3, 3), "bytes_per_launch": round(t["bytes"])}
 
 
@@ -583,7 +592,7 @@ def main():
     ap.add_argument("--model", type=int, default=0)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--n3d", type=int, default=256)
-    ap.add_argument("--timer", default="p_sweep3d", help="kernel family of the live roofline")
+    ap.add_argument("--timer", default=ROOFLINE_FAMILY, help="kernel family of the live roofline")
     ap.add_argument("--only-headline", action="store_true",
                     help="the headline pack run alone (profiling): no comparisons or secondary legs")
     ap.add_argument("--skip-plain", action="store_true")

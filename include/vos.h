@@ -349,7 +349,12 @@ typedef enum {
   VOS_KERNEL_P_PRE3D = 8,     /* first down launch: two damped-Jacobi sweeps from the FP64 residual */
   VOS_KERNEL_P_SWEEP3D = 9,   /* one further damped-Jacobi sweep */
   VOS_KERNEL_P_RESTRICT3D = 10, /* residual restricted to the next level */
-  VOS_KERNEL_P_POST3D = 11    /* prolongation fused with the first up sweep */
+  VOS_KERNEL_P_POST3D = 11,   /* prolongation fused with the first up sweep */
+  /* the same four kernels on the finest level of the 3-D transport hierarchy (FP64): */
+  VOS_KERNEL_C_PRE3D = 12,
+  VOS_KERNEL_C_SWEEP3D = 13,
+  VOS_KERNEL_C_RESTRICT3D = 14,
+  VOS_KERNEL_C_POST3D = 15
 } vos_kernel_family;
 
 /* Time `reps` back-to-back launch sequences of one kernel family on the live

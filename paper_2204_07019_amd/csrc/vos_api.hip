@@ -1789,47 +1789,57 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
 
 }  // namespace
 
-// Back-to-back launches of one z-marching kernel of the pressure hierarchy's
-// finest level (3-D), in the arithmetic of the hierarchy the last pressure
-// solve used, with the production launch shape.  They write only the level's
-// V-cycle buffers, which every V-cycle rebuilds from its input.  Bytes per
-// fine cell (w = bytes of the hierarchy's arithmetic; every array once; the
-// finest diagonal is formed from the faces except where a kernel reads it):
-//   pre (first down launch, two sweeps from the FP64 residual): r (8) + diag,
-//     3 face T, write b, write x (5 w);  sweep: x, 3 T, b, write (6 w);
-//   restrict: x, 3 T, b (5 w) + coarse b (w / 8);
-//   post (prolongation + first up sweep): x, 3 T, b, write (6 w) + coarse x (w / 8).
+// Back-to-back launches of one z-marching kernel of a 3-D hierarchy's finest
+// level with the production launch shape: the pressure hierarchy (in the
+// arithmetic the last pressure solve used) or the transport hierarchy (FP64).
+// They write only the level's V-cycle buffers, which every V-cycle rebuilds
+// from its input.  Bytes per fine cell, every array once (w = bytes of the
+// hierarchy's arithmetic; cw = coefficient words per cell: 3 face arrays T for
+// the pressure levels, whose finest diagonal is the sum of the faces, 6
+// off-diagonals + the diagonal for the transport levels):
+//   pre (first down launch, two sweeps from the FP64 residual): r (8) +
+//     coefficients, write b, write x ((cw + 2) w);
+//   sweep: x, coefficients, b, write ((cw + 3) w);
+//   restrict: x, coefficients, b ((cw + 2) w) + coarse b (w / 8);
+//   post (prolongation + first up sweep): x, coefficients, b, write
+//     ((cw + 3) w) + coarse x (w / 8).
 template <typename R>
-vos_status time_p_kernel_t(vos_sim *s, MgLevel<R> *lv, int family, int reps, double *ms, double *bytes)
+constexpr double coef_words(const MgLevel<R> *) { return 3.0; }
+template <typename R>
+constexpr double coef_words(const SLevel<R> *) { return 7.0; }
+
+template <typename Lv, typename R>
+vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega, double rscale, int reps, double *ms,
+                           double *bytes)
 {
   hipStream_t st = s->stream;
-  if (s->g.nd != 3 || s->nlev < 2) return fail(VOS_ERR_ARG, "the pressure-level families time 3-D hierarchies");
-  MgLevel<R> F = lv[0];
+  if (s->g.nd != 3 || nlev < 2) return fail(VOS_ERR_ARG, "the z-marching level families time 3-D hierarchies");
+  Lv F = lv[0];
   if (!(F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2))
-    return fail(VOS_ERR_ARG, "the finest pressure level is too narrow for the z-marching kernels");
+    return fail(VOS_ERR_ARG, "the finest level is too narrow for the z-marching kernels");
   const int zl = zrun_len(F.n);
   const dim3 gr(zrun_blocks(F.n, zl));
   const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
-  const R om = (R)(6.0 / 7.0);
-  const double w = sizeof(R), nc = F.nc;
+  const R om = (R)omega;
+  const double w = sizeof(R), nc = F.nc, cw = coef_words(&F);
   double per = 0.0;
   auto launch = [&]() {
-    switch (family) {
-      case VOS_KERNEL_P_PRE3D:
-        k_v_pre3d<MgLevel<R>, R, RHS_R><<<gr, TPB, 0, st>>>(F, s->vec[1], nullptr, 1.0 / s->p_scale, om, zl, flag);
-        per = (8.0 + 5.0 * w) * nc;
+    switch (kind) {
+      case 0:
+        k_v_pre3d<Lv, R, RHS_R><<<gr, TPB, 0, st>>>(F, s->vec[1], nullptr, rscale, om, zl, flag);
+        per = (8.0 + (cw + 2.0) * w) * nc;
         break;
-      case VOS_KERNEL_P_SWEEP3D:
-        k_v_jacobi3d<MgLevel<R>, R, false><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, nullptr, nullptr, zl, flag);
-        per = 6.0 * w * nc;
+      case 1:
+        k_v_jacobi3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, nullptr, nullptr, zl, flag);
+        per = (cw + 3.0) * w * nc;
         break;
-      case VOS_KERNEL_P_RESTRICT3D:
-        k_v_restrict3d<MgLevel<R>, R><<<gr, TPB, 0, st>>>(F, lv[1], zl, flag);
-        per = 5.0 * w * nc + w * lv[1].nc;
+      case 2:
+        k_v_restrict3d<Lv, R><<<gr, TPB, 0, st>>>(F, lv[1], zl, flag);
+        per = (cw + 2.0) * w * nc + w * lv[1].nc;
         break;
       default:
-        k_v_post3d<MgLevel<R>, R, false><<<gr, TPB, 0, st>>>(F, lv[1], F.t, om, nullptr, nullptr, zl, flag);
-        per = 6.0 * w * nc + w * lv[1].nc;
+        k_v_post3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, lv[1], F.t, om, nullptr, nullptr, zl, flag);
+        per = (cw + 3.0) * w * nc + w * lv[1].nc;
         break;
     }
   };
@@ -2128,10 +2138,16 @@ vos_status vos_time_kernel(vos_sim *s, int family, int reps, double *avg_launch_
   if (reps < 1 || reps > 100000) return fail(VOS_ERR_ARG, "reps must be in [1, 100000]");
   if (!s->stepped) return fail(VOS_ERR_STATE, "run vos_step first");
   if (family >= VOS_KERNEL_P_PRE3D && family <= VOS_KERNEL_P_POST3D) {
+    const int kind = family - VOS_KERNEL_P_PRE3D;
     if (s->opt.precision == VOS_MIXED && !s->p_fp64_sticky)
-      return time_p_kernel_t<float>(s, s->mgf, family, reps, avg_launch_ms, bytes_per_launch);
-    return time_p_kernel_t<double>(s, s->mgd, family, reps, avg_launch_ms, bytes_per_launch);
+      return time_z_kernel_t<MgLevel<float>, float>(s, s->mgf, s->nlev, kind, 6.0 / 7.0, 1.0 / s->p_scale, reps,
+                                                     avg_launch_ms, bytes_per_launch);
+    return time_z_kernel_t<MgLevel<double>, double>(s, s->mgd, s->nlev, kind, 6.0 / 7.0, 1.0 / s->p_scale, reps,
+                                                     avg_launch_ms, bytes_per_launch);
   }
+  if (family >= VOS_KERNEL_C_PRE3D && family <= VOS_KERNEL_C_POST3D)
+    return time_z_kernel_t<SLevel<double>, double>(s, s->smgd[3], s->snlev[3], family - VOS_KERNEL_C_PRE3D, 0.85, 1.0,
+                                                    reps, avg_launch_ms, bytes_per_launch);
   return time_kernel_t<double>(s, s->smgd[3], family, reps, avg_launch_ms, bytes_per_launch);
 }
 

@@ -257,8 +257,9 @@ __global__ void __launch_bounds__(TPB) k_v_jacobi3d(Lv L, const R *__restrict__ 
       [&](bool in, unsigned id, const int c[3], const O &cur, const ZNb<R> &nb, const ZCoefB<R> &k) {
         if (!in) return;
         const R v = cur.s + omega * (k.b - zapply(L, zhas(L.n, c), k.a, cur.s, nb)) / k.a.d;
-        xo[id] = v;
+        // the cycle's last sweep: only its output z is read afterwards
         if (OUT64) z[id] = unscale((double)v, dsc, id);
+        else xo[id] = v;
       });
 }
 
@@ -361,8 +362,8 @@ __global__ void __launch_bounds__(TPB) k_v_post3d(Lv F, Lv C, R *__restrict__ xo
         const R dg = k.a.d;
         const R ay = zapply_off<Lv, R>(F, zhas(F.n, c), k.a, dg, cur.s, nb);
         const R v = cur.s + omega * (k.b - ay) / dg;
-        xo[id] = v;
         if (OUT64) z[id] = unscale((double)v, dsc, id);
+        else xo[id] = v;
       });
 }
 
