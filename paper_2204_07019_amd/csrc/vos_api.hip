@@ -68,41 +68,6 @@ unsigned tile_blocks(int nx, int ny, int ty)
   return (nt + NXCD - 1) / NXCD * NXCD;
 }
 
-// z-run length of the 3-D marching kernels (vos_march3d.h): about 2048 work
-// items per level, even (restriction aggregates pairs of planes), 2..64.
-int zrun_len(const int n[3])
-{
-  const long tiles = (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + ZT_Y - 1) / ZT_Y);
-  long zl = (long)n[2] * tiles / 2048;
-  zl = std::max(2L, std::min(64L, zl));
-  return (int)(zl & ~1L);
-}
-
-// Blocks of a 3-D marching kernel: its work items rounded up to a multiple of the 8 XCDs.
-unsigned zrun_blocks(const int n[3], int zlen)
-{
-  const unsigned nw = (unsigned)((n[0] + ZT_X - 1) / ZT_X) * (unsigned)((n[1] + ZT_Y - 1) / ZT_Y) *
-                      (unsigned)((n[2] + zlen - 1) / zlen);
-  return (nw + NXCD - 1) / NXCD * NXCD;
-}
-
-// The pressure operator marches through z on 3-D grids at least half a tile
-// wide whose tiles fit the MAXB partial slots; the z-run is lengthened until
-// the work items do.
-bool papply_marching(const Dev &g)
-{
-  const long tiles = (long)((g.n[0] + ZT_X - 1) / ZT_X) * ((g.n[1] + ZT_Y - 1) / ZT_Y);
-  return g.nd == 3 && g.n[0] >= ZT_X / 2 && g.n[1] >= 2 && g.n[2] >= 2 && tiles <= MAXB;
-}
-
-int papply_zlen(const Dev &g)
-{
-  const long tiles = (long)((g.n[0] + ZT_X - 1) / ZT_X) * ((g.n[1] + ZT_Y - 1) / ZT_Y);
-  int zl = zrun_len(g.n);
-  while (tiles * ((g.n[2] + zl - 1) / zl) > MAXB) zl += 2;
-  return zl;
-}
-
 // Blocks of a sweep over n items: one item per thread up to MAXB blocks,
 // rounded up to a multiple of the 8 XCDs (XCD-aware ranges, vos_device.h).
 int grid_blocks(size_t n)
@@ -150,7 +115,7 @@ int mg_hierarchy(const vos_grid &g, LevelDims *out)
   return L;
 }
 
-constexpr int NVEC = 10;
+constexpr int NVEC = 11;
 constexpr int NHIST = 3;  // earlier solutions kept per solve for extrapolated starts
 constexpr int NSMG = 4;   // stencil hierarchies: momentum x, y, z; transport
 
@@ -436,6 +401,8 @@ vos_status check_opts(const vos_opts *o)
   if (o->setup_every < 0 || o->setup_every > 1000) return fail(VOS_ERR_ARG, "setup_every must be in [0, 1000]");
   if (!(o->deps_max >= 0.0) || !std::isfinite(o->deps_max))
     return fail(VOS_ERR_ARG, "deps_max must be finite and >= 0");
+  if (!(o->solid_dt >= 0.0) || !std::isfinite(o->solid_dt))
+    return fail(VOS_ERR_ARG, "solid_dt must be finite and >= 0");
   if (o->simple != 0 && o->simple != 1) return fail(VOS_ERR_ARG, "simple must be 0 or 1");
   if (o->simple) {
     if (o->outer_max < 1) return fail(VOS_ERR_ARG, "outer_max must be >= 1");
@@ -468,6 +435,17 @@ vos_status check_params(const vos_params *p)
   if (!(p->Vm_f >= 0.0) || !std::isfinite(p->Vm_f)) return fail(VOS_ERR_ARG, "Vm_f must be finite and >= 0");
   return VOS_OK;
 }
+
+// Options that do not go with some parameters.
+vos_status check_combination(const vos_params *p, const vos_opts *o)
+{
+  if (o->solid_dt > 0.0 && p->transient)
+    return fail(VOS_ERR_ARG, "solid_dt separates the solid step from dt, which the transient storage terms take");
+  return VOS_OK;
+}
+
+// The solid update's step before the deps_max bound: solid_dt when set, else dt.
+double solid_nominal(const vos_sim *s, double dt);
 
 // Device copy of the physical parameters (and the SIMPLE relaxations the kernels apply).
 void fill_phys(Phys &P, const vos_params *params, const vos_opts &o)
@@ -1329,9 +1307,9 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *
   k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
   k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
   k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
-  // b and y are free after the start: they carry the directions times the row
-  // diagonal, the input of the cycle built on the unscaled rows
-  double *pd = b, *sd = y;
+  // the directions times the row diagonal, the input of the cycle built on the
+  // unscaled rows (y is free after the start; b stays for the true residual)
+  double *pd = s->vec[10], *sd = y;
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, pd, s->tdiag, sc);
     smg_vcycle<R>(s, H, lv, pd, ph, sc, st);
@@ -1353,9 +1331,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *
   *res0 = bn2 > 0 ? std::sqrt(s->host[S_RES0] / bn2) : 0.0;
   // BiCGStab's recurrence residual drifts from b - A c; accept convergence only
   // once the true residual meets the tolerance, else restart from the iterate
-  // (the right-hand side b served the iterations as scratch: it is assembled again)
   for (int restart = 0; conv && restart < 4; ++restart) {
-    assemble();
     k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
     k_bi_true_res<<<nb, TPB, 0, st>>>(n, b, y, s->part);
     k_bi_true_scal<<<1, TPB, 0, st>>>(s->part, nb, sc);
@@ -1443,6 +1419,8 @@ void launch_rates(vos_sim *s)
                                                      s->gmag, sc_block(s, SC_MISC), s->rbar, rate_partials(s),
                                                      s->part_max, s->opt.deps_max);
 }
+
+double solid_nominal(const vos_sim *s, double dt) { return s->opt.solid_dt > 0.0 ? s->opt.solid_dt : dt; }
 
 // Solid update (S7) from the rates of launch_rates, and the diagnostic sums.
 void launch_update(vos_sim *s, double dt, int freeze)
@@ -1617,10 +1595,10 @@ vos_status one_step(vos_sim *s, double dt, int flags, vos_diag *dg)
     if (s->opt.simple && worst <= s->opt.outer_tol) break;
   }
   HIP_TRY(hipEventRecord(s->ev[5], st));
-  launch_update(s, dt, flags & VOS_FREEZE_SOLID);
+  launch_update(s, solid_nominal(s, dt), flags & VOS_FREEZE_SOLID);
   HIP_TRY(hipEventRecord(s->ev[6], st));
   HIP_TRY(hipGetLastError());
-  r2 = fill_diag(s, dt, dg);
+  r2 = fill_diag(s, solid_nominal(s, dt), dg);
   if (r2) return r2;
   HIP_TRY(hipEventElapsedTime(&ms, s->ev[5], s->ev[6]));
   dg->t_ms[5] += ms;
@@ -1898,6 +1876,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   if (st) return st;
   if ((st = check_params(params))) return st;
   if ((st = check_opts(opts))) return st;
+  if ((st = check_combination(params, opts))) return st;
   if (!out) return fail(VOS_ERR_ARG, "out is NULL");
   if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return fail(VOS_ERR_ARG, "workspace must be 256-byte aligned");
   Layout lo = make_layout(*grid, opts->precision);
@@ -2053,6 +2032,7 @@ vos_status vos_set_params(vos_sim *s, const vos_params *params)
   if (!s) return fail(VOS_ERR_ARG, "sim is NULL");
   vos_status st = check_params(params);
   if (st) return st;
+  if ((st = check_combination(params, &s->opt))) return st;
   s->prm = *params;
   drop_graphs(s);   // captured iterations hold mu / dx^2 by value
   s->hist_c = s->hist_p = 0;

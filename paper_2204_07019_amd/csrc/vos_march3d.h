@@ -20,6 +20,8 @@
 // XCD b % 8 and takes item (b % 8) * per + b / 8, so each XCD walks one slab
 // of z-runs and the halos its tiles share stay in its L2.
 #pragma once
+#include <algorithm>
+
 #include "vos_vcycle.h"
 
 namespace vos {
@@ -45,6 +47,42 @@ __device__ __forceinline__ bool ztile_of(const int n[3], int zlen, ZTile &t)
   t.z0 = (int)zr * zlen;
   t.z1 = min(n[2], t.z0 + zlen);
   return true;
+}
+
+// Launch shapes (host side).
+// z-run length of the marching kernels: about 2048 work
+// items per level, even (restriction aggregates pairs of planes), 2..64.
+inline int zrun_len(const int n[3])
+{
+  const long tiles = (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + ZT_Y - 1) / ZT_Y);
+  long zl = (long)n[2] * tiles / 2048;
+  zl = std::max(2L, std::min(64L, zl));
+  return (int)(zl & ~1L);
+}
+
+// Blocks of a 3-D marching kernel: its work items rounded up to a multiple of the 8 XCDs.
+inline unsigned zrun_blocks(const int n[3], int zlen)
+{
+  const unsigned nw = (unsigned)((n[0] + ZT_X - 1) / ZT_X) * (unsigned)((n[1] + ZT_Y - 1) / ZT_Y) *
+                      (unsigned)((n[2] + zlen - 1) / zlen);
+  return (nw + NXCD - 1) / NXCD * NXCD;
+}
+
+// The pressure operator marches through z on 3-D grids at least half a tile
+// wide whose tiles fit the MAXB partial slots; the z-run is lengthened until
+// the work items do.
+inline bool papply_marching(const Dev &g)
+{
+  const long tiles = (long)((g.n[0] + ZT_X - 1) / ZT_X) * ((g.n[1] + ZT_Y - 1) / ZT_Y);
+  return g.nd == 3 && g.n[0] >= ZT_X / 2 && g.n[1] >= 2 && g.n[2] >= 2 && tiles <= MAXB;
+}
+
+inline int papply_zlen(const Dev &g)
+{
+  const long tiles = (long)((g.n[0] + ZT_X - 1) / ZT_X) * ((g.n[1] + ZT_Y - 1) / ZT_Y);
+  int zl = zrun_len(g.n);
+  while (tiles * ((g.n[2] + zl - 1) / zl) > MAXB) zl += 2;
+  return zl;
 }
 
 // One LDS plane: tile + one-cell halo, [y][x].
