@@ -49,7 +49,7 @@ class _Prob(C.Structure):
                 ("grad_scheme", C.c_int), ("psi_kind", C.c_int), ("transient", C.c_int),
                 ("Vm_f", C.c_double), ("simple", C.c_int), ("outer_max", C.c_int),
                 ("outer_tol", C.c_double), ("relax_u", C.c_double), ("relax_p", C.c_double),
-                ("relax_c", C.c_double)]
+                ("relax_c", C.c_double), ("solid_dt", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -142,6 +142,7 @@ class Problem:
     relax_u: float = 0.3
     relax_p: float = 0.3
     relax_c: float = 1.0
+    solid_dt: float = 0.0   # > 0: the solid update's own step; dt is then the flow's pseudo time step
 
     def c_struct(self) -> _Prob:
         return _Prob(**asdict(self))

@@ -82,6 +82,9 @@ typedef struct {
   int outer_max;           /* SIMPLE: most outer iterations per step */
   double outer_tol;        /* SIMPLE: stop once every solve's initial residual is <= this */
   double relax_u, relax_p, relax_c;   /* SIMPLE under-relaxation factors in (0, 1] */
+  double solid_dt;         /* > 0: the solid update's own step (before the deps_max bound),
+                              dt then serving the flow alone as its pseudo time step;
+                              0: the solid advances by dt */
 } orc_prob;
 
 typedef struct {
@@ -815,6 +818,8 @@ static int check_prob(const orc_prob *P, double dt)
   if (P->grad_scheme == 1 && P->model == 0) return ORC_ERR_ARG;  /* decentred: VoS-psi variants only */
   if (P->psi_kind != 0 && P->psi_kind != 1) return ORC_ERR_ARG;
   if (P->psi_kind == 1 && P->model == 2) return ORC_ERR_ARG;     /* lambda is fitted to eps (1 - eps) */
+  if (!(P->solid_dt >= 0.0) || P->solid_dt > 1e300) return ORC_ERR_ARG;
+  if (P->solid_dt > 0.0 && P->transient) return ORC_ERR_ARG;   /* the storage terms take dt */
   if (P->simple) {
     if (P->outer_max < 1 || !(P->outer_tol >= 0.0)) return ORC_ERR_ARG;
     if (!(P->relax_u > 0.0 && P->relax_u <= 1.0) || !(P->relax_p > 0.0 && P->relax_p <= 1.0) ||
@@ -823,12 +828,16 @@ static int check_prob(const orc_prob *P, double dt)
   return ORC_OK;
 }
 
-/* Time step of the solid update (Appendix D): dt, or with deps_max > 0
- * min(dt, deps_max / max |Vm Rbar|) where the maximum runs over the cells whose
+/* Time step of the solid update (Appendix D): the nominal step T -- dt, or
+ * solid_dt when that is set (Appendix A's quasi-static reading: flow and
+ * transport are steady, so dt is then only the flow's pseudo time step and the
+ * solid interface alone sets the physical step) -- or with deps_max > 0
+ * min(T, deps_max / max |Vm Rbar|) where the maximum runs over the cells whose
  * distance to the clip bound in the direction of their change exceeds deps_max
  * (a cell closer to its bound changes by at most that distance anyway). */
 static double solid_dt(const grid_t *g, const orc_prob *P, double dt, const double *eps, const double *rbar)
 {
+  if (P->solid_dt > 0.0) dt = P->solid_dt;
   double dts = dt;
   if (P->deps_max > 0.0) {
     double m = 0.0;
