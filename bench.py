@@ -582,6 +582,58 @@ def micromodel_leg(vos, inputs, scaling, steps, warmup, dt):
     return out
 
 
+# Upscaling workload: quasi-static steps (the SIMPLE loop of Appendix B to an
+# initial relative residual of UPSCALING_OUTER_TOL per solve, relaxation 0.7 /
+# 0.3), the solid step set by Appendix D's bound on the change of the fluid
+# fraction (the nominal step UPSCALING_DT only caps it).
+UPSCALING_DEPS_MAX = 0.005
+UPSCALING_DT = 1e3
+UPSCALING_OUTER_TOL = 1e-6
+
+
+def upscaling_leg(vos, inputs, scaling, budget_s, target_rel, dt_setup):
+    """A long dissolution run of the 1024x512 micromodel (iVoS, Pe 10, Da 0.1,
+    mixed precision) until its porosity has grown by target_rel (or the wall
+    time budget ends), with the K(phi) and alpha(phi) power-law fits."""
+    from paper_2204_07019_amd import upscaling as U
+    import torch
+    sim, es, params, info = setup_sim(vos, inputs, scaling, "micromodel", 10.0, 0.1, vos.MIXED, 0, dt_setup, 40)
+    nz, ny, nx = es.shape
+    state = {k: sim.get(k) for k in ("eps", "ux", "uy", "p", "c")}
+    dx = sim.grid.dx
+    sim.close()
+    del sim
+    opts = vos.Opts(precision=vos.MIXED, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, check_every=CHECK_EVERY,
+                    extrapolate=0, setup_every=SETUP_EVERY, deps_max=UPSCALING_DEPS_MAX, simple=1,
+                    outer_max=300, outer_tol=UPSCALING_OUTER_TOL, relax_u=0.7, relax_p=0.3, relax_c=1.0)
+    s = vos.Sim(nx, ny, nz, dx, params, opts)
+    for k, v in state.items():
+        s.set(k, v)
+    phi0 = float(state["eps"].mean().item())
+    rec = U.run(s, UPSCALING_DT, 1000000, target_porosity=phi0 * (1.0 + target_rel), time_budget=budget_s)
+    s.close()
+    torch.cuda.empty_cache()
+    n = len(rec["phi"])
+    out = {"workload": f"micromodel {nx}x{ny} dx=5um RSA discs seed 11, iVoS, Pe=10 Da=0.1, mixed precision, "
+                       f"quasi-static SIMPLE steps (relaxation 0.7/0.3, outer tolerance {UPSCALING_OUTER_TOL:g}), "
+                       f"deps_max={UPSCALING_DEPS_MAX}",
+           "steps": n, "wall_s": round(rec["wall_s"], 2), "ms_per_step": round(rec["wall_s"] / max(n, 1) * 1e3, 3),
+           "cell_steps_per_s": nx * ny * n / rec["wall_s"], "phi_start": phi0, "phi_end": rec["phi_end"],
+           "target_phi": phi0 * (1.0 + target_rel), "reached": rec["phi_end"] >= phi0 * (1.0 + target_rel),
+           "simulated_s": float(rec["t"][-1]) if n else 0.0,
+           "outer_its_per_step": float(np.mean(rec["outer_its"])) if n else 0.0}
+    if n >= 6:
+        for y in ("K", "alpha"):
+            c, e, rms = U.fit_power_law(rec["phi"], rec[y])
+            out[f"{y}_fit"] = {"C": c, "exponent": e, "rms_log": rms}
+            k, f1, f2 = U.fit_two_power_laws(rec["phi"], rec[y], min_points=max(3, n // 10))
+            out[f"{y}_two_laws"] = {"split_phi": float(rec["phi"][k]), "first": {"C": f1[0], "exponent": f1[1]},
+                                    "second": {"C": f2[0], "exponent": f2[1]}}
+        sel = np.linspace(0, n - 1, min(n, 12)).astype(int)
+        out["samples"] = {k: [float(rec[k][i]) for i in sel] for k in ("phi", "K", "alpha")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +657,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net timing")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
+    ap.add_argument("--no-upscaling", action="store_true", help="skip the long upscaling run")
+    ap.add_argument("--upscaling-budget", type=float, default=40.0, help="wall seconds of the upscaling run")
+    ap.add_argument("--only-upscaling", action="store_true", help="the upscaling run alone")
     ap.add_argument("--n-learned", type=int, default=128)
     ap.add_argument("--unet-n", type=int, default=128)
     ap.add_argument("--trace-window", default=None,
@@ -635,6 +690,9 @@ def main():
         sys.exit(1)
     vos.lib()
 
+    if args.only_upscaling:
+        print(json.dumps({"upscaling": upscaling_leg(vos, inputs, scaling, args.upscaling_budget, 0.2, args.dt)}))
+        return
     head, roof, others, comps, params, info, cells = pack_leg(vos, inputs, scaling, args)
     n = args.n3d
     extra = {}
@@ -644,6 +702,11 @@ def main():
             extra["learned_3d"] = learned_3d(vos, inputs, args.n_learned, 2e-3)
             log("learned: " + ", ".join(f"{k} {extra['learned_3d'][k]['ms_per_step']:.1f} ms/step"
                                          for k in ("plain_fp64", "mixed", "mixed_learned")))
+        if not args.no_upscaling:
+            log("upscaling run (micromodel, to +20 % porosity)")
+            extra["upscaling"] = upscaling_leg(vos, inputs, scaling, args.upscaling_budget, 0.2, args.dt)
+            u = extra["upscaling"]
+            log(f"upscaling: {u['steps']} steps in {u['wall_s']} s, phi {u['phi_start']:.4f} -> {u['phi_end']:.4f}")
         if not args.no_micromodel:
             log("micromodel 1024x512")
             extra["micromodel_mall_resident"] = micromodel_leg(vos, inputs, scaling, 20, 3, args.dt)

@@ -170,6 +170,12 @@ typedef struct {
   int outer_max;    /* SIMPLE: most outer iterations per step, >= 1 */
   double outer_tol; /* SIMPLE: convergence tolerance on the solves' initial residuals, >= 0 */
   double relax_u, relax_p, relax_c;  /* SIMPLE under-relaxation factors in (0, 1] (the paper: 0.3) */
+  double solid_dt;  /* > 0: the solid update's own nominal step (before the deps_max bound), dt
+                       then serving the flow alone, as the pseudo time step of its backward-Euler
+                       inertia (Appendix A's quasi-static reading: flow and transport are steady,
+                       the solid interface alone sets the physical step).  0: the solid advances
+                       by dt.  Finite, >= 0; not with params->transient (its storage terms take
+                       dt). */
 } vos_opts;
 
 /* Per-step diagnostics (Section 2.5 and Section 3.3 quantities, balances). */

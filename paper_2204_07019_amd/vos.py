@@ -67,7 +67,7 @@ class _Opts(C.Structure):
                 ("p_fp32_its", C.c_int), ("extrapolate", C.c_int), ("setup_every", C.c_int),
                 ("deps_max", C.c_double), ("simple", C.c_int), ("outer_max", C.c_int),
                 ("outer_tol", C.c_double), ("relax_u", C.c_double), ("relax_p", C.c_double),
-                ("relax_c", C.c_double)]
+                ("relax_c", C.c_double), ("solid_dt", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -165,6 +165,7 @@ class Opts:
     relax_u: float = 0.3
     relax_p: float = 0.3
     relax_c: float = 1.0
+    solid_dt: float = 0.0   # > 0: the solid update's own step; dt is then the flow's pseudo time step
 
 
 class Sim:

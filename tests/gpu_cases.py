@@ -27,7 +27,7 @@ def gpu_sim(prob, precision=0, **opt_overrides):
                  maxit_u=prob.maxit_u, maxit_p=min(prob.maxit_p, 5000), maxit_c=prob.maxit_c,
                  precision=precision, deps_max=prob.deps_max, simple=prob.simple,
                  outer_max=prob.outer_max, outer_tol=prob.outer_tol, relax_u=prob.relax_u,
-                 relax_p=prob.relax_p, relax_c=prob.relax_c)
+                 relax_p=prob.relax_p, relax_c=prob.relax_c, solid_dt=prob.solid_dt)
     for k, v in opt_overrides.items():
         setattr(o, k, v)
     return vos.Sim(prob.nx, prob.ny, prob.nz, prob.dx, params, o)

@@ -53,6 +53,9 @@ def test_argument_errors_without_a_device():
         bad = vos._Opts(**dict(vos.asdict(vos.Opts()), **{field: value}))
         assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(n)) == vos.VOS_ERR_ARG, field
         assert field.encode() in L.vos_last_error()
+    bad = vos._Opts(**dict(vos.asdict(vos.Opts()), solid_dt=-1.0))
+    assert L.vos_workspace_bytes(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(n)) == vos.VOS_ERR_ARG
+    assert b"solid_dt" in L.vos_last_error()
     # the SIMPLE loop's options are checked when it is on
     for field, value in (("relax_u", 0.0), ("relax_p", 1.5), ("relax_c", -1.0), ("outer_max", 0),
                          ("outer_tol", -1.0), ("extrapolate", 1)):
@@ -119,3 +122,8 @@ def test_parameter_combinations_rejected():
         pr = vos.make_params(dict(inputs.BASE_PARAMS, **kw))
         rc = L.vos_create(ctypes.byref(g), ctypes.byref(pr), ctypes.byref(o), ws, 1 << 40, None, ctypes.byref(h))
         assert rc == vos.VOS_ERR_ARG, kw
+    # a separate solid step does not go with the transient storage terms
+    pr = vos.make_params(dict(inputs.BASE_PARAMS, model=0, transient=1))
+    os_ = vos._Opts(**dict(vos.asdict(vos.Opts()), solid_dt=1.0))
+    rc = L.vos_create(ctypes.byref(g), ctypes.byref(pr), ctypes.byref(os_), ws, 1 << 40, None, ctypes.byref(h))
+    assert rc == vos.VOS_ERR_ARG and b"solid_dt" in L.vos_last_error()
