@@ -103,3 +103,33 @@ def test_failing_instance_is_isolated():
     d = b.sims[0].diagnostics()
     assert d["it_p"] > 0 and b.sims[2].diagnostics()["it_p"] > 0
     b.close()
+
+
+def test_batch_instance_matches_oracle(orc):
+    """One instance of a concurrent batch (VoS-psi', the largest grid, mixed
+    precision) against the FP64 oracle after 3 steps, at the 1e-6 bar."""
+    from paper_2204_07019_amd import vos
+    from paper_2204_07019_amd.batch import Batch
+    from gpu_cases import make_problem, rel_l2
+    sp = specs()
+    tight = vos.Opts(precision=vos.MIXED, rtol_u=1e-12, rtol_p=1e-12, rtol_c=1e-12, maxit_p=20000)
+    b = Batch(sp, tight, workers=4)
+    for k, (nx, ny, _, _, _) in enumerate(sp):
+        b.sims[k].set_solid_fraction(geometry(k, nx, ny))
+    dt = [1e-3] * len(sp)
+    k = 2   # 128 x 64, model 2
+    print(f"batch of {len(sp)}; instance {k} against the oracle", flush=True)
+    for _ in range(3):
+        b.step(dt)
+    g = {f: b.sims[k].get_numpy(f) for f in FIELDS}
+    b.close()
+    nx, ny, nz, dx, p = sp[k]
+    es = geometry(k, nx, ny).reshape(1, ny, nx)
+    prob = make_problem(es, dict(p, dx=dx), model=p["model"])
+    st = orc.initial_state(prob, es)
+    for _ in range(3):
+        orc.step(prob, st, dt[k])
+    err = {f: rel_l2(g[f], getattr(st, f)) for f in FIELDS}
+    print("[parity] batch instance vs oracle:", {f: float(f"{v:.2e}") for f, v in err.items()}, flush=True)
+    for f, v in err.items():
+        assert v <= 1e-6, (f, v)
