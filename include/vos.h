@@ -360,7 +360,11 @@ typedef enum {
   VOS_KERNEL_C_PRE3D = 12,
   VOS_KERNEL_C_SWEEP3D = 13,
   VOS_KERNEL_C_RESTRICT3D = 14,
-  VOS_KERNEL_C_POST3D = 15
+  VOS_KERNEL_C_POST3D = 15,
+  /* the fused legs of that level (levels of >= 2^20 cells): both pre-sweeps and the
+     restriction; the prolongation and both post-sweeps with the FP64 output */
+  VOS_KERNEL_C_DOWN3D = 16,
+  VOS_KERNEL_C_UP3D = 17
 } vos_kernel_family;
 
 /* Time `reps` back-to-back launch sequences of one kernel family on the live

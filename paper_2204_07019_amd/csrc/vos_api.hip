@@ -293,6 +293,7 @@ struct vos_sim {
   int it_p_fp64;            // iterations of the last pressure solve run with the FP64 hierarchy (mixed)
   double p_res0;            // initial relative residual of the last pressure solve
   bool p_fp64_sticky;       // an FP32 pressure solve stalled on the current geometry (mixed)
+  int n_cu;                 // compute units of the device (launch shapes of the fused legs)
   int nu_mom;               // sweeps per leg of the momentum hierarchies
   // extrapolated starts: the solutions of earlier steps, newest first (the host
   // rotates the buffers), and how many of them belong to the current history
@@ -434,6 +435,16 @@ vos_status check_params(const vos_params *p)
   if (p->transient != 0 && p->transient != 1) return fail(VOS_ERR_ARG, "transient must be 0 or 1");
   if (!(p->Vm_f >= 0.0) || !std::isfinite(p->Vm_f)) return fail(VOS_ERR_ARG, "Vm_f must be finite and >= 0");
   return VOS_OK;
+}
+
+// Compute units of the current device (256 if the query fails).
+int device_cus()
+{
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+    n = 256;
+  return n;
 }
 
 // Options that do not go with some parameters.
@@ -746,6 +757,14 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   for (int l = 0; l < lc; ++l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
+    if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
+      // both pre-sweeps and the restriction in one march
+      const int zl = zrun_len_fused(F.n, s->n_cu * zfused_blocks_per_cu<R>());
+      const dim3 gr(zrun_blocks(F.n, zl));
+      if (l == 0) k_v_down3d<Lv, R, RHS_R><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
+      else k_v_down3d<Lv, R, RHS_B><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
+      continue;
+    }
     if (zmarch(F)) {
       const int zl = zrun_len(F.n);
       const dim3 gr(zrun_blocks(F.n, zl));
@@ -803,6 +822,18 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   for (int l = lc - 1; l >= 0; --l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
+    if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
+      // prolongation and both post-sweeps in one march
+      const int zl = zrun_len_fused(F.n, s->n_cu * zfused_blocks_per_cu<R>());
+      const dim3 gr(zrun_blocks(F.n, zl));
+      if (l == 0) {
+        k_v_up3d<Lv, R, true><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, zl, sc);
+      } else {
+        k_v_up3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, zl, sc);
+        std::swap(F.x, F.t);
+      }
+      continue;
+    }
     if (zmarch(F)) {
       const int zl = zrun_len(F.n);
       const dim3 gr(zrun_blocks(F.n, zl));
@@ -1780,7 +1811,11 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
 //   sweep: x, coefficients, b, write ((cw + 3) w);
 //   restrict: x, coefficients, b ((cw + 2) w) + coarse b (w / 8);
 //   post (prolongation + first up sweep): x, coefficients, b, write
-//     ((cw + 3) w) + coarse x (w / 8).
+//     ((cw + 3) w) + coarse x (w / 8);
+//   fused down leg (two sweeps from the FP64 residual and the restriction):
+//     r (8) + coefficients, write b, write x ((cw + 2) w) + coarse b (w / 8);
+//   fused up leg (prolongation and two sweeps, FP64 output): x, coefficients,
+//     b ((cw + 2) w), write (8) + coarse x (w / 8).
 template <typename R>
 constexpr double coef_words(const MgLevel<R> *) { return 3.0; }
 template <typename R>
@@ -1795,8 +1830,9 @@ vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega,
   Lv F = lv[0];
   if (!(F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2))
     return fail(VOS_ERR_ARG, "the finest level is too narrow for the z-marching kernels");
-  const int zl = zrun_len(F.n);
-  const dim3 gr(zrun_blocks(F.n, zl));
+  const int zl = zrun_len(F.n), zlf = zrun_len_fused(F.n, s->n_cu * zfused_blocks_per_cu<R>());
+  const dim3 gr(zrun_blocks(F.n, zl)), grf(zrun_blocks(F.n, zlf));
+  if (kind >= 4 && !zfused_level(F.n)) return fail(VOS_ERR_ARG, "the fused legs run on levels of >= 2^20 cells");
   const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
   const R om = (R)omega;
   const double w = sizeof(R), nc = F.nc, cw = coef_words(&F);
@@ -1815,9 +1851,17 @@ vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega,
         k_v_restrict3d<Lv, R><<<gr, TPB, 0, st>>>(F, lv[1], zl, flag);
         per = (cw + 2.0) * w * nc + w * lv[1].nc;
         break;
-      default:
+      case 3:
         k_v_post3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, lv[1], F.t, om, nullptr, nullptr, zl, flag);
         per = (cw + 3.0) * w * nc + w * lv[1].nc;
+        break;
+      case 4:
+        k_v_down3d<Lv, R, RHS_R><<<grf, TPB, 0, st>>>(F, lv[1], s->vec[1], rscale, om, zlf, flag);
+        per = (8.0 + (cw + 2.0) * w) * nc + w * lv[1].nc;
+        break;
+      default:
+        k_v_up3d<Lv, R, true><<<grf, TPB, 0, st>>>(F, lv[1], F.t, om, s->vec[2], nullptr, zlf, flag);
+        per = ((cw + 2.0) * w + 8.0) * nc + w * lv[1].nc;
         break;
     }
   };
@@ -1887,6 +1931,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->prm = *params;
   s->opt = *opts;
   s->stream = (hipStream_t)hip_stream;
+  s->n_cu = device_cus();
   s->lo = lo;
   s->ws = (char *)workspace;
   Dev &g = s->g;
@@ -2125,7 +2170,7 @@ vos_status vos_time_kernel(vos_sim *s, int family, int reps, double *avg_launch_
     return time_z_kernel_t<MgLevel<double>, double>(s, s->mgd, s->nlev, kind, 6.0 / 7.0, 1.0 / s->p_scale, reps,
                                                      avg_launch_ms, bytes_per_launch);
   }
-  if (family >= VOS_KERNEL_C_PRE3D && family <= VOS_KERNEL_C_POST3D)
+  if (family >= VOS_KERNEL_C_PRE3D && family <= VOS_KERNEL_C_UP3D)
     return time_z_kernel_t<SLevel<double>, double>(s, s->smgd[3], s->snlev[3], family - VOS_KERNEL_C_PRE3D, 0.85, 1.0,
                                                     reps, avg_launch_ms, bytes_per_launch);
   return time_kernel_t<double>(s, s->smgd[3], family, reps, avg_launch_ms, bytes_per_launch);
@@ -2468,6 +2513,7 @@ extern "C" vos_status vos_solve_pressure_noalloc(const vos_grid *grid, const vos
 
   // the control block: the state's fields are the caller's, every other buffer is scratch
   vos_sim *s = &g_noalloc_sim;
+  s->n_cu = device_cus();
   s->grid = *grid;
   s->prm = *params;
   s->opt = *opts;

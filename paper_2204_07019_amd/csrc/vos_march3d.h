@@ -68,6 +68,30 @@ inline unsigned zrun_blocks(const int n[3], int zlen)
   return (nw + NXCD - 1) / NXCD * NXCD;
 }
 
+// The fused two-sweep legs (k_v_down3d / k_v_up3d) recompute a few planes at
+// the start of every z-run and hold more LDS and registers per block than the
+// separate kernels, so fewer blocks are resident per CU.  Their z-runs are cut
+// so that all work items are resident at once (slots = CUs x resident blocks
+// per CU; a second, partial round of blocks would leave most CUs idle at the
+// end), and are at least 8 planes long.  They run on levels of at least 2^20
+// cells (the smaller levels keep the separate kernels).
+inline int zrun_len_fused(const int n[3], int slots)
+{
+  const long tiles = (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + ZT_Y - 1) / ZT_Y);
+  const long runs = std::max(1L, (long)slots / tiles);
+  long zl = ((long)n[2] + runs - 1) / runs;
+  zl = std::max(8L, zl + (zl & 1));
+  return (int)zl;
+}
+// Resident blocks per CU of the fused legs: LDS (six planes of 68 x 8 values
+// and the restriction's two 64 x 4 planes) and registers allow 5 in FP64, 8 in FP32.
+template <typename R>
+constexpr int zfused_blocks_per_cu() { return sizeof(R) == 8 ? 5 : 8; }
+inline bool zfused_level(const int n[3])
+{
+  return (unsigned long)n[0] * (unsigned long)n[1] * (unsigned long)n[2] >= (1ul << 20);
+}
+
 // The pressure operator marches through z on 3-D grids at least half a tile
 // wide whose tiles fit the MAXB partial slots; the z-run is lengthened until
 // the work items do.
@@ -403,6 +427,338 @@ __global__ void __launch_bounds__(TPB) k_v_post3d(Lv F, Lv C, R *__restrict__ xo
         if (OUT64) z[id] = unscale((double)v, dsc, id);
         else xo[id] = v;
       });
+}
+
+// ---------------------------------------------------------------------------
+// Fused finest-level legs of a V-cycle with two sweeps each way.  The separate
+// kernels above read the level's coefficients four times per cycle (two
+// pre-sweeps, restriction, prolongation + first up sweep, second up sweep).
+// Here one march does two stencil passes: stage 0 forms a pointwise value v on
+// the tile plus a two-cell x/y halo (plane z + 2), stage 1 applies the first
+// stencil to v on the tile plus a one-cell halo (plane z + 1), stage 2 applies
+// the second stencil on the tile itself (plane z).  The halo cells' stage-1
+// values are recomputed by both blocks that need them (their coefficients
+// mostly come from L2), so each tile cell's coefficients cross HBM once per
+// leg.  Every value is formed by the expression of the separate kernel it
+// replaces (k_v_pre3d + k_v_restrict3d down, k_v_post3d + k_v_jacobi3d up), so
+// the cycle's results are bitwise those of the separate kernels.
+//
+// LDS: four v planes (2-halo; a plane is read by three consecutive stage-1
+// passes, so four slots let stage 0 run one plane ahead with one barrier per
+// plane) and two u planes (1-halo).  A thread owns its tile cell (stages 0-2),
+// at most one cell of the one-cell ring (stages 0-1) and at most one of the
+// two-cell ring (stage 0).
+constexpr int ZH2_X = ZT_X + 4, ZH2_Y = ZT_Y + 4;   // two-cell halo plane
+constexpr int ZH1_X = ZT_X + 2, ZH1_Y = ZT_Y + 2;   // one-cell halo plane
+constexpr int ZRING1 = 2 * ZH1_X + 2 * ZT_Y;        // 140 cells
+constexpr int ZRING2 = 2 * ZH2_X + 2 * (ZT_Y + 2);  // 148 cells
+static_assert(ZRING1 <= TPB && ZRING2 <= TPB, "one ring cell per thread");
+
+// Position (in two-halo plane coordinates) of the thread's cell of class k:
+// 0 its tile cell, 1 its one-cell-ring cell, 2 its two-cell-ring cell;
+// false when the thread has none.
+__device__ __forceinline__ bool zfused_cell(int k, int &hx, int &hy)
+{
+  const int h = threadIdx.x;
+  if (k == 0) {
+    hx = h % ZT_X + 2;
+    hy = h / ZT_X + 2;
+    return true;
+  }
+  if (k == 1) {
+    if (h >= ZRING1) return false;
+    int x1, y1;   // one-halo coordinates
+    if (h < ZH1_X) { x1 = h; y1 = 0; }
+    else if (h < 2 * ZH1_X) { x1 = h - ZH1_X; y1 = ZH1_Y - 1; }
+    else if (h < 2 * ZH1_X + ZT_Y) { x1 = 0; y1 = h - 2 * ZH1_X + 1; }
+    else { x1 = ZH1_X - 1; y1 = h - 2 * ZH1_X - ZT_Y + 1; }
+    hx = x1 + 1;
+    hy = y1 + 1;
+    return true;
+  }
+  if (h >= ZRING2) return false;
+  if (h < ZH2_X) { hx = h; hy = 0; }
+  else if (h < 2 * ZH2_X) { hx = h - ZH2_X; hy = ZH2_Y - 1; }
+  else if (h < 2 * ZH2_X + ZT_Y + 2) { hx = 0; hy = h - 2 * ZH2_X + 1; }
+  else { hx = ZH2_X - 1; hy = h - 2 * ZH2_X - (ZT_Y + 2) + 1; }
+  return true;
+}
+
+// A cell of the march: its two-halo plane position, level coordinates and column.
+struct ZCell {
+  int hx, hy, gx, gy;
+  bool has, in;     // the thread has this cell; it lies inside the level (x, y)
+  unsigned col;     // gx + nx gy (0 outside)
+};
+
+__device__ __forceinline__ ZCell zfused_at(int k, const ZTile &t, const int n[3])
+{
+  ZCell c;
+  c.has = zfused_cell(k, c.hx, c.hy);
+  if (!c.has) { c.hx = c.hy = 2; }   // a position whose neighbours are in the plane (never stored)
+  c.gx = t.x0 + c.hx - 2;
+  c.gy = t.y0 + c.hy - 2;
+  c.in = c.has && c.gx >= 0 && c.gx < n[0] && c.gy >= 0 && c.gy < n[1];
+  c.col = c.in ? (unsigned)c.gx + (unsigned)n[0] * (unsigned)c.gy : 0u;
+  return c;
+}
+
+// In-plane neighbours of two-halo position (hx, hy) from a two-halo plane,
+// z neighbours from the planes below and above.
+template <typename R>
+__device__ __forceinline__ ZNb<R> znb2(const R (*pl)[ZH2_X], const R (*lo)[ZH2_X], const R (*hi)[ZH2_X], int hx,
+                                       int hy)
+{
+  ZNb<R> nb;
+  nb.w = pl[hy][hx - 1];
+  nb.e = pl[hy][hx + 1];
+  nb.s = pl[hy - 1][hx];
+  nb.n = pl[hy + 1][hx];
+  nb.b = lo[hy][hx];
+  nb.t = hi[hy][hx];
+  return nb;
+}
+
+// Down leg: the two pre-smoothing sweeps of k_v_pre3d (from the FP64 residual,
+// RHS_R, or the level's b, RHS_B) and the residual restriction of
+// k_v_restrict3d, in one march.  Writes the level's b (RHS_R), x (after the
+// second sweep) and the coarse b.  zlen even.
+template <typename Lv, typename R, int RHS>
+__global__ void __launch_bounds__(TPB) k_v_down3d(Lv F, Lv C, const double *__restrict__ r64, double rscale, R omega,
+                                                  int zlen, const double *__restrict__ sc)
+{
+  static_assert(RHS == RHS_R || RHS == RHS_B, "no diagonal scaling in the fused leg");
+  if (sc[S_CONV] != 0.0) return;
+  ZTile t;
+  if (!ztile_of(F.n, zlen, t)) return;
+  __shared__ R vpl[4][ZH2_Y][ZH2_X];
+  __shared__ R upl[2][ZH2_Y][ZH2_X];   // one-halo values, kept in two-halo coordinates
+  __shared__ R rs[2][ZT_Y][ZT_X];
+  const int nz = F.n[2];
+  const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
+  const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
+  auto rhs = [&](unsigned id) -> R {
+    if (RHS == RHS_R) return (R)(rscale * r64[id]);
+    return F.b[id];
+  };
+  // stage 0: v = omega b / d (the first sweep from x = 0), 0 outside the level
+  auto stage0 = [&](int z) {
+    const int s = z & 3;
+    const bool zin = z >= 0 && z < nz;
+    const ZCell *cs[3] = {&c0, &c1, &c2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const ZCell &c = *cs[k];
+      const bool ok = c.in && zin;
+      const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
+      const R v = omega * rhs(id) / F.diag[id];
+      if (c.has) vpl[s][c.hy][c.hx] = ok ? v : (R)0;
+    }
+  };
+  // stage 1 for one cell at plane z: the second sweep (k_v_pre3d's expression);
+  // its loads (load1) are issued before the plane's barrier, the arithmetic
+  // (apply1) after it
+  struct S1 { R u, bb, dg; ZCoef<R> k; };
+  auto load1 = [&](const ZCell &c, int z) -> S1 {
+    S1 o;
+    const bool ok = c.in && z >= 0 && z < nz;
+    const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
+    const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
+    o.bb = rhs(id);
+    o.dg = F.diag[id];
+    o.k = zcoef(F, id, cc);
+    o.u = (R)0;
+    return o;
+  };
+  auto apply1 = [&](const ZCell &c, int z, S1 &o) {
+    const bool ok = c.in && z >= 0 && z < nz;
+    const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
+    const R s = vpl[z & 3][c.hy][c.hx];
+    const ZNb<R> nb = znb2<R>(vpl[z & 3], vpl[(z - 1) & 3], vpl[(z + 1) & 3], c.hx, c.hy);
+    const R ax = zapply_off<Lv, R>(F, zhas(F.n, cc), o.k, o.dg, s, nb);
+    o.u = ok ? s + omega * (o.bb - ax) / o.dg : (R)0;
+  };
+  auto stage1 = [&](const ZCell &c, int z) -> S1 {
+    S1 o = load1(c, z);
+    apply1(c, z, o);
+    return o;
+  };
+  const int lx = threadIdx.x % ZT_X, ly = threadIdx.x / ZT_X;
+  // prologue: v on planes z0-2 .. z0+1, u on planes z0-1 and z0
+  for (int z = t.z0 - 2; z <= t.z0 + 1; ++z) stage0(z);
+  __syncthreads();
+  R u_prev, u_cur;
+  ZCoef<R> k_cur;
+  R b_cur;
+  {
+    const S1 a = stage1(c0, t.z0 - 1);
+    const S1 a1 = stage1(c1, t.z0 - 1);
+    if (c1.has) upl[(t.z0 - 1) & 1][c1.hy][c1.hx] = a1.u;
+    upl[(t.z0 - 1) & 1][c0.hy][c0.hx] = a.u;
+    u_prev = a.u;
+    const S1 b = stage1(c0, t.z0);
+    const S1 b1 = stage1(c1, t.z0);
+    if (c1.has) upl[t.z0 & 1][c1.hy][c1.hx] = b1.u;
+    upl[t.z0 & 1][c0.hy][c0.hx] = b.u;
+    u_cur = b.u;
+    k_cur = b.k;
+    b_cur = b.bb;
+    if (c0.in) {
+      const unsigned id = c0.col + sz * (unsigned)t.z0;
+      if (RHS != RHS_B) F.b[id] = b.bb;
+      F.x[id] = b.u;
+    }
+  }
+  for (int z = t.z0; z < t.z1; ++z) {
+    S1 a = load1(c0, z + 1), a1 = load1(c1, z + 1);
+    stage0(z + 2);
+    __syncthreads();
+    // stage 1 on plane z + 1
+    apply1(c0, z + 1, a);
+    apply1(c1, z + 1, a1);
+    if (c1.has) upl[(z + 1) & 1][c1.hy][c1.hx] = a1.u;
+    upl[(z + 1) & 1][c0.hy][c0.hx] = a.u;
+    if (c0.in && z + 1 < t.z1) {
+      const unsigned id = c0.col + sz * (unsigned)(z + 1);
+      if (RHS != RHS_B) F.b[id] = a.bb;
+      F.x[id] = a.u;
+    }
+    // stage 2 on plane z: the residual of the second sweep (k_v_restrict3d's expression)
+    {
+      const int cc[3] = {c0.gx, c0.gy, z};
+      ZNb<R> nb;
+      nb.w = upl[z & 1][c0.hy][c0.hx - 1];
+      nb.e = upl[z & 1][c0.hy][c0.hx + 1];
+      nb.s = upl[z & 1][c0.hy - 1][c0.hx];
+      nb.n = upl[z & 1][c0.hy + 1][c0.hx];
+      nb.b = u_prev;
+      nb.t = a.u;
+      rs[z & 1][ly][lx] = c0.in ? b_cur - zapply(F, zhas(F.n, cc), k_cur, u_cur, nb) : (R)0;
+    }
+    u_prev = u_cur;
+    u_cur = a.u;
+    k_cur = a.k;
+    b_cur = a.bb;
+    if ((z & 1) == 0 && z + 1 < nz) continue;   // block-uniform
+    __syncthreads();
+    if (threadIdx.x < (ZT_X / 2) * (ZT_Y / 2)) {
+      const int ix = threadIdx.x % (ZT_X / 2), iy = threadIdx.x / (ZT_X / 2);
+      const int IX = t.x0 / 2 + ix, IY = t.y0 / 2 + iy, IZ = z >> 1;
+      if (IX < C.n[0] && IY < C.n[1]) {
+        R sum = 0;
+        for (int cz = 0; cz < 2; ++cz)
+          for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+              if (2 * IX + cx >= F.n[0] || 2 * IY + cy >= F.n[1] || 2 * IZ + cz >= F.n[2]) continue;
+              sum += rs[cz][2 * iy + cy][2 * ix + cx];
+            }
+        C.b[(unsigned)IX + (unsigned)C.n[0] * ((unsigned)IY + (unsigned)C.n[1] * (unsigned)IZ)] = sum;
+      }
+    }
+  }
+}
+
+// Up leg: the prolongation with the first post-smoothing sweep of k_v_post3d
+// and the second sweep of k_v_jacobi3d, in one march.  Writes the result to
+// xo, or with OUT64 (the cycle's last sweep) only to the FP64 output z.
+template <typename Lv, typename R, bool OUT64>
+__global__ void __launch_bounds__(TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z64,
+                                                const double *__restrict__ dsc, int zlen,
+                                                const double *__restrict__ sc)
+{
+  if (sc[S_CONV] != 0.0) return;
+  ZTile t;
+  if (!ztile_of(F.n, zlen, t)) return;
+  __shared__ R vpl[4][ZH2_Y][ZH2_X];
+  __shared__ R upl[2][ZH2_Y][ZH2_X];
+  const int nz = F.n[2];
+  const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
+  const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
+  // stage 0: y = x + the coarse correction of the cell's aggregate
+  auto stage0 = [&](int z) {
+    const int s = z & 3;
+    const bool zin = z >= 0 && z < nz;
+    const ZCell *cs[3] = {&c0, &c1, &c2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const ZCell &c = *cs[k];
+      const bool ok = c.in && zin;
+      const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
+      const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
+      const R v = F.x[id] + C.x[parent_of<R>(F.n, C.n, 3, cc)];
+      if (c.has) vpl[s][c.hy][c.hx] = ok ? v : (R)0;
+    }
+  };
+  // stage 1: the first up sweep (k_v_post3d's expression), loads before the
+  // plane's barrier (load1), arithmetic after it (apply1)
+  struct S1 { R u; ZCoefB<R> k; };
+  auto load1 = [&](const ZCell &c, int z) -> S1 {
+    S1 o;
+    const bool ok = c.in && z >= 0 && z < nz;
+    const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
+    const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
+    o.k = ZCoefB<R>{zcoef(F, id, cc), F.b[id]};
+    o.u = (R)0;
+    return o;
+  };
+  auto apply1 = [&](const ZCell &c, int z, S1 &o) {
+    const bool ok = c.in && z >= 0 && z < nz;
+    const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
+    const R y = vpl[z & 3][c.hy][c.hx];
+    const ZNb<R> nb = znb2<R>(vpl[z & 3], vpl[(z - 1) & 3], vpl[(z + 1) & 3], c.hx, c.hy);
+    const R dg = o.k.a.d;
+    const R ay = zapply_off<Lv, R>(F, zhas(F.n, cc), o.k.a, dg, y, nb);
+    o.u = ok ? y + omega * (o.k.b - ay) / dg : (R)0;
+  };
+  auto stage1 = [&](const ZCell &c, int z) -> S1 {
+    S1 o = load1(c, z);
+    apply1(c, z, o);
+    return o;
+  };
+  R u_prev, u_cur;
+  ZCoefB<R> k_cur;
+  for (int z = t.z0 - 2; z <= t.z0 + 1; ++z) stage0(z);
+  __syncthreads();
+  {
+    const S1 a = stage1(c0, t.z0 - 1);
+    const S1 a1 = stage1(c1, t.z0 - 1);
+    if (c1.has) upl[(t.z0 - 1) & 1][c1.hy][c1.hx] = a1.u;
+    upl[(t.z0 - 1) & 1][c0.hy][c0.hx] = a.u;
+    u_prev = a.u;
+    const S1 b = stage1(c0, t.z0);
+    const S1 b1 = stage1(c1, t.z0);
+    if (c1.has) upl[t.z0 & 1][c1.hy][c1.hx] = b1.u;
+    upl[t.z0 & 1][c0.hy][c0.hx] = b.u;
+    u_cur = b.u;
+    k_cur = b.k;
+  }
+  for (int z = t.z0; z < t.z1; ++z) {
+    S1 a = load1(c0, z + 1), a1 = load1(c1, z + 1);
+    stage0(z + 2);
+    __syncthreads();
+    apply1(c0, z + 1, a);
+    apply1(c1, z + 1, a1);
+    if (c1.has) upl[(z + 1) & 1][c1.hy][c1.hx] = a1.u;
+    upl[(z + 1) & 1][c0.hy][c0.hx] = a.u;
+    // stage 2 on plane z: the second sweep (k_v_jacobi3d's expression)
+    if (c0.in) {
+      const int cc[3] = {c0.gx, c0.gy, z};
+      const unsigned id = c0.col + sz * (unsigned)z;
+      ZNb<R> nb;
+      nb.w = upl[z & 1][c0.hy][c0.hx - 1];
+      nb.e = upl[z & 1][c0.hy][c0.hx + 1];
+      nb.s = upl[z & 1][c0.hy - 1][c0.hx];
+      nb.n = upl[z & 1][c0.hy + 1][c0.hx];
+      nb.b = u_prev;
+      nb.t = a.u;
+      const R v = u_cur + omega * (k_cur.b - zapply(F, zhas(F.n, cc), k_cur.a, u_cur, nb)) / k_cur.a.d;
+      if (OUT64) z64[id] = unscale((double)v, dsc, id);
+      else xo[id] = v;
+    }
+    u_prev = u_cur;
+    u_cur = a.u;
+    k_cur = a.k;
+  }
 }
 
 // Pressure operator q = A p in papply_cell's expression order, with the

@@ -6,7 +6,8 @@
 // (zrun_len / zrun_blocks / papply_zlen from the same header), on every level
 // of the hierarchies that the library builds for a grid: the pressure
 // hierarchy (FP32 and FP64), the transport hierarchy (FP64) and the three
-// momentum hierarchies on the face grids (FP32 and FP64).  Every array is its
+// momentum hierarchies on the face grids (FP32 and FP64), with the fused
+// two-sweep legs where the library uses them.  Every array is its
 // own heap allocation of exactly the size the library gives it, and the LDS
 // planes are static arrays, so AddressSanitizer reports any read or write
 // outside an array or an LDS plane and the program stops with a non-zero
@@ -140,6 +141,15 @@ void run_levels(const char *name, std::vector<Lv> &lv)
     launch(nb, [&] { k_v_post3d<Lv, R, true>(F, C, F.t, om, z, dsc, zl, sc); });
     std::printf("  %s level %zu: %d x %d x %d, z-run %d, %u blocks: 8 launches in bounds\n", name, l, F.n[0], F.n[1],
                 F.n[2], zl, nb);
+    if (zfused_level(F.n)) {
+      const int zf = zrun_len_fused(F.n, 256 * zfused_blocks_per_cu<R>());
+      const unsigned nf = zrun_blocks(F.n, zf);
+      launch(nf, [&] { k_v_down3d<Lv, R, RHS_R>(F, C, r64, 1.0, om, zf, sc); });
+      launch(nf, [&] { k_v_down3d<Lv, R, RHS_B>(F, C, r64, 1.0, om, zf, sc); });
+      launch(nf, [&] { k_v_up3d<Lv, R, true>(F, C, F.t, om, z, nullptr, zf, sc); });
+      launch(nf, [&] { k_v_up3d<Lv, R, false>(F, C, F.t, om, nullptr, nullptr, zf, sc); });
+      std::printf("  %s level %zu fused legs: z-run %d, %u blocks: 4 launches in bounds\n", name, l, zf, nf);
+    }
   }
 }
 

@@ -224,6 +224,10 @@ LEVEL_CASES = [  # (shape, precision, extra options): 2-D tiled and 3-D marching
     # a finest level of 2^18 cells: the legs there run on the tall tiles
     ((1024, 256, 1), 0, {}),
     ((1024, 256, 1), 1, {"extrapolate": 2}),
+    # 3-D levels of >= 2^20 cells with two sweeps per leg: the fused down and
+    # up legs (transport, momentum; with mg_nu 2 the pressure levels too)
+    ((130, 70, 130), 0, {}),
+    ((130, 70, 130), 1, {"mg_nu": 2, "extrapolate": 2}),
 ]
 
 
