@@ -296,15 +296,27 @@ __global__ void __launch_bounds__(TPB) k_mom_apply(Dev g, double cvis, const dou
   for (unsigned f = xbeg(g.nf[D]); f < xend(g.nf[D]); f += xstride()) {
     int x[3];
     unflat(g.fd[D], f, x);
+    const bool unk = mom_unknown<D>(g, x);
+    // the neighbour values, loaded together (index of a missing one clamped
+    // to the face itself, its term dropped by a select in the same order)
+    double pn[6];
+    bool use[6];
+    double fv;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const bool de = e < g.nd;
+      const unsigned st = de ? dstride(g.fd[D], e) : 0u;
+      use[2 * e] = de && unk && mom_nb<D>(g, x, e, -1, 0.0, &fv) == 0;
+      use[2 * e + 1] = de && unk && mom_nb<D>(g, x, e, +1, 0.0, &fv) == 0;
+      pn[2 * e] = p[use[2 * e] ? f - st : f];
+      pn[2 * e + 1] = p[use[2 * e + 1] ? f + st : f];
+    }
     const double pf = p[f];
     double v = dmom[f] * pf;
-    if (mom_unknown<D>(g, x)) {
-      double nb = 0.0, fv;
-      for (int e = 0; e < g.nd; ++e) {
-        const unsigned st = dstride(g.fd[D], e);
-        if (mom_nb<D>(g, x, e, -1, 0.0, &fv) == 0) nb += p[f - st];
-        if (mom_nb<D>(g, x, e, +1, 0.0, &fv) == 0) nb += p[f + st];
-      }
+    if (unk) {
+      double nb = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) nb = use[k] ? nb + pn[k] : nb;
       v -= cvis * nb;
     }
     q[f] = v;
@@ -461,6 +473,22 @@ __device__ __forceinline__ double face_corr(const double *phi, unsigned lo, unsi
 // the iVoS acid sink eps_P sum_f w_f c^R_f (same treatment along w), the psi
 // sink kc psi |grad eps| V c_P (implicit).  Inlet: Dirichlet c_in; outlet:
 // zero gradient; walls: no flux.
+// face_corr on the face between the cell (coordinate x along the direction, n
+// cells) and its neighbour on side s, from the five values of phi at offsets
+// -2..+2 along the direction (loaded beforehand; an offset outside the grid
+// holds any value, never used): the same upwind, central and downwind values
+// as face_corr, so the same correction.
+__device__ __forceinline__ double face_corr5(const double (&ph)[5], int s, int x, int n, double vel)
+{
+  if (s > 0) {   // lo = the cell, hi = x + 1
+    if (vel >= 0.0) return vanleer_corr(x - 1 >= 0 ? ph[1] : ph[2], ph[2], ph[3]);
+    return vanleer_corr(x + 2 < n ? ph[4] : ph[3], ph[3], ph[2]);
+  }
+  // lo = x - 1, hi = the cell
+  if (vel >= 0.0) return vanleer_corr(x - 2 >= 0 ? ph[0] : ph[1], ph[1], ph[2]);
+  return vanleer_corr(x + 1 < n ? ph[3] : ph[2], ph[2], ph[1]);
+}
+
 __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const double *__restrict__ eps,
                                                       const double *__restrict__ u0, const double *__restrict__ u1,
                                                       const double *__restrict__ u2, const double *__restrict__ w0,
@@ -478,32 +506,55 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
   for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
+    // every value the row needs, loaded before any arithmetic (indices clamped
+    // into the arrays; the ones a boundary does not use are dropped below)
     const double ep = eps[id];
+    double uf[3][2], wf[3][2], enb[3][2], ph[3][5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d >= g.nd) {   // 2-D: no z faces (block-uniform)
+        uf[d][0] = uf[d][1] = wf[d][0] = wf[d][1] = enb[d][0] = enb[d][1] = 0.0;
+        for (int k = 0; k < 5; ++k) ph[d][k] = 0.0;
+        continue;
+      }
+      const int xd = x[d], nd_ = g.n[d];
+      const unsigned st = dstride(g.n, d);
+      const unsigned flo = fidx(g, d, x[0], x[1], x[2]);
+      const unsigned fhi = flo + dstride(g.fd[d], d);
+      uf[d][0] = uu[d][flo];
+      uf[d][1] = uu[d][fhi];
+      wf[d][0] = ww[d][flo];
+      wf[d][1] = ww[d][fhi];
+      enb[d][0] = eps[xd > 0 ? id - st : id];
+      enb[d][1] = eps[xd + 1 < nd_ ? id + st : id];
+#pragma unroll
+      for (int k = -2; k <= 2; ++k) {
+        const bool in = xd + k >= 0 && xd + k < nd_;
+        ph[d][k + 2] = cold[in ? (k < 0 ? id - (unsigned)(-k) * st : id + (unsigned)k * st) : id];
+      }
+    }
+    const double gm = gmag[id];
+    const double epv = P.transient ? eps_prev[id] : 0.0, c0v = P.transient ? c0[id] : 0.0;
+    const double cv = cold[id];
     double diag = 0.0, rhs = 0.0, o[6] = {0, 0, 0, 0, 0, 0}, od[6] = {0, 0, 0, 0, 0, 0};
     for (int d = 0; d < g.nd; ++d) {
-      const unsigned st = dstride(g.n, d);
       for (int s = -1; s <= 1; s += 2) {
         const int xf_d = x[d] + (s > 0);
-        int xf[3] = {x[0], x[1], x[2]};
-        xf[d] = xf_d;
-        const unsigned f = fidx(g, d, xf[0], xf[1], xf[2]);
-        const double uf = uu[d][f];
-        const double Fo = s * g.S * uf;
+        const double ufc = uf[d][s > 0];
+        const double Fo = s * g.S * ufc;
         const int slot = 2 * d + (s > 0);
         if (xf_d > 0 && xf_d < g.n[d]) {
-          const unsigned lo = s > 0 ? id : id - st;
-          const unsigned nb = s > 0 ? id + st : id - st;
           if (Fo >= 0.0) diag += Fo; else o[slot] += Fo;
-          if (vl) rhs -= Fo * face_corr(cold, lo, st, xf_d, g.n[d], uf);
-          const double G = P.D * 0.5 * (ep + eps[nb]) * g.S / g.dx;
+          if (vl) rhs -= Fo * face_corr5(ph[d], s, x[d], g.n[d], ufc);
+          const double G = P.D * 0.5 * (ep + enb[d][s > 0]) * g.S / g.dx;
           diag += G;
           o[slot] -= G;
           od[slot] = -G;
           if (P.model == 0) {
-            const double wf = ww[d][f];
-            const double k = P.zeta * ep * (s * wf);
+            const double wfc = wf[d][s > 0];
+            const double k = P.zeta * ep * (s * wfc);
             if (k >= 0.0) diag += k; else o[slot] += k;
-            if (vl) rhs -= k * face_corr(cold, lo, st, xf_d, g.n[d], wf);
+            if (vl) rhs -= k * face_corr5(ph[d], s, x[d], g.n[d], wfc);
           }
         } else if (d == 0 && xf_d == 0) {
           if (Fo < 0.0) rhs -= Fo * P.c_in; else diag += Fo;
@@ -517,15 +568,15 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
     }
     if (P.model != 0) {
       const double psi = P.psi_kind == 1 ? 1.0 : lambda * ep * (1.0 - ep);
-      diag += P.zeta * P.kc * psi * gmag[id] * g.V;
+      diag += P.zeta * P.kc * psi * gm * g.V;
     }
     if (P.transient) {
       diag += ep * g.V / dt;
-      rhs += eps_prev[id] * c0[id] * g.V / dt;
+      rhs += epv * c0v * g.V / dt;
     }
     if (P.simple && P.relax_c < 1.0) {
       const double dr = diag / P.relax_c;
-      rhs += (dr - diag) * cold[id];
+      rhs += (dr - diag) * cv;
       diag = dr;
     }
     const double inv = 1.0 / diag;
@@ -595,28 +646,39 @@ __global__ void __launch_bounds__(TPB) k_react(Dev g, Phys P, const double *__re
       double t1 = 0.0, t2 = 0.0;
       for (int d = 0; d < g.nd; ++d) {
         const unsigned st = dstride(g.n, d);
+        const int xd = x[d], nd_ = g.n[d];
+        // w on the cell's two faces, eps, c and c^n at offsets -2..+2 along d,
+        // all loaded before the arithmetic (indices clamped into the grid; a
+        // value outside it is never used)
+        const unsigned flo = fidx(g, d, x[0], x[1], x[2]);
+        const double wlo = ww[d][flo], whi = ww[d][flo + dstride(g.fd[d], d)];
+        double e5[5], c5[5], o5[5];
+#pragma unroll
+        for (int k = -2; k <= 2; ++k) {
+          const bool in = xd + k >= 0 && xd + k < nd_;
+          const unsigned j = in ? (k < 0 ? id - (unsigned)(-k) * st : id + (unsigned)k * st) : id;
+          e5[k + 2] = eps[j];
+          c5[k + 2] = c[j];
+          o5[k + 2] = cold[j];
+        }
         for (int s = -1; s <= 1; s += 2) {
-          const int xf_d = x[d] + (s > 0);
-          if (xf_d == 0 || xf_d == g.n[d]) continue;
-          int xf[3] = {x[0], x[1], x[2]};
-          xf[d] = xf_d;
-          const double wf = ww[d][fidx(g, d, xf[0], xf[1], xf[2])];
+          const int xf_d = xd + (s > 0);
+          if (xf_d == 0 || xf_d == nd_) continue;
+          const double wf = s > 0 ? whi : wlo;
           const double wo = s * wf;
-          const unsigned lo = s > 0 ? id : id - st;
-          const unsigned hi = lo + st;
-          // upwind cells along w for c and for q = eps c
-          const unsigned cu = wf >= 0.0 ? lo : hi;
-          const double cR = c[cu] + face_corr(cold, lo, st, xf_d, g.n[d], wf);
-          // van Leer of q = eps * c on the fly
+          // the face's lower and upper cells in the five-value window
+          const int L = s > 0 ? 2 : 1, H = L + 1;
+          // upwind cell along w for c; van Leer of c^n lagged, and of q = eps c
+          const double cR = c5[wf >= 0.0 ? L : H] + face_corr5(o5, s, xd, nd_, wf);
           double qU, qC, qD;
           if (wf >= 0.0) {
-            qC = eps[lo] * c[lo];
-            qD = eps[hi] * c[hi];
-            qU = (xf_d - 2 >= 0) ? eps[lo - st] * c[lo - st] : qC;
+            qC = e5[L] * c5[L];
+            qD = e5[H] * c5[H];
+            qU = (xf_d - 2 >= 0) ? e5[L - 1] * c5[L - 1] : qC;
           } else {
-            qC = eps[hi] * c[hi];
-            qD = eps[lo] * c[lo];
-            qU = (xf_d + 1 < g.n[d]) ? eps[hi + st] * c[hi + st] : qC;
+            qC = e5[H] * c5[H];
+            qD = e5[L] * c5[L];
+            qU = (xf_d + 1 < nd_) ? e5[H + 1] * c5[H + 1] : qC;
           }
           const double qR = qC + vanleer_corr(qU, qC, qD);
           t1 += wo * cR;
