@@ -69,6 +69,9 @@ def test_post_20_steps(orc, precision):
     st, g, eps0, diags = run_both(es, prob, 1e-3, 20, precision=precision)
     r = _compare(st, g, eps0)
     _say(f"post rel L2 {r}")
+    # measured ~3e-11 for c and the change of eps (with the interface normal
+    # cut at 1e-6 / dx, which keeps the step well posed): held at 1e-9
+    assert r["c"] <= 1e-9 and r["deps"] <= 1e-9, r
     do, dg = diags[-1]
     assert abs(dg["acid_balance_rel"]) < 1e-9
     assert abs(dg["solid_balance_rel"]) < 1e-9
@@ -136,7 +139,7 @@ def test_post_stagewise_one_step(orc):
     assert rel_l2(sim.get_numpy("ustar_x"), it["ustar_x"]) < 1e-9
     assert rel_l2(sim.get_numpy("ustar_y"), it["ustar_y"]) < 1e-9
     assert rel_l2(sim.get_numpy("gmag"), it["gmag"]) < 1e-13
-    assert rel_l2(sim.get_numpy("rbar"), it["rbar"]) < 1e-7
+    assert rel_l2(sim.get_numpy("rbar"), it["rbar"]) < 1e-10
     sim.close()
 
 
