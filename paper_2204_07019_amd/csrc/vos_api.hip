@@ -740,6 +740,25 @@ void launch_coarse(int c0, const LevelPack<Lv> &pack, int lc, int L, int nd, int
 }
 
 // z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
+// Blocks a CU holds at once of the fused legs of one level type (their LDS and
+// registers decide it; queried once per instantiation), times the CUs.
+template <typename Lv, typename R>
+int fused_slots(const vos_sim *s)
+{
+  static int per_cu = 0;   // kernel attributes: the same for every simulation of the process
+  if (per_cu == 0) {
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, reinterpret_cast<const void *>(k_v_down3d<Lv, R, RHS_R>),
+                                                     ZF_TPB, 0) != hipSuccess || a < 1)
+      a = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(k_v_up3d<Lv, R, true>),
+                                                     ZF_TPB, 0) != hipSuccess || b < 1)
+      b = 1;
+    per_cu = std::min(a, b);
+  }
+  return s->n_cu * per_cu;
+}
+
 template <typename Lv, typename R>
 void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, double *z, const double *sc,
             double omega, const double *dsc, double rscale, int nu, hipStream_t st)
@@ -759,10 +778,10 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     const int nb = grid_blocks(F.nc);
     if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
       // both pre-sweeps and the restriction in one march
-      const int zl = zrun_len_fused(F.n, s->n_cu * zfused_blocks_per_cu<R>());
-      const dim3 gr(zrun_blocks(F.n, zl));
-      if (l == 0) k_v_down3d<Lv, R, RHS_R><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
-      else k_v_down3d<Lv, R, RHS_B><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
+      const int zl = zrun_len_fused(F.n, fused_slots<Lv, R>(s));
+      const dim3 gr(zrun_blocks_fused(F.n, zl));
+      if (l == 0) k_v_down3d<Lv, R, RHS_R><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
+      else k_v_down3d<Lv, R, RHS_B><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
       continue;
     }
     if (zmarch(F)) {
@@ -824,12 +843,13 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     const int nb = grid_blocks(F.nc);
     if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
       // prolongation and both post-sweeps in one march
-      const int zl = zrun_len_fused(F.n, s->n_cu * zfused_blocks_per_cu<R>());
-      const dim3 gr(zrun_blocks(F.n, zl));
+      const int zl = zrun_len_fused(F.n, fused_slots<Lv, R>(s));
+      const dim3 gr(zrun_blocks_fused(F.n, zl));
       if (l == 0) {
-        k_v_up3d<Lv, R, true><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, zl, sc);
+        k_v_up3d<Lv, R, true><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, r, rscale, zl, sc);
       } else {
-        k_v_up3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, zl, sc);
+        k_v_up3d<Lv, R, false><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, nullptr, 1.0, zl,
+                                                      sc);
         std::swap(F.x, F.t);
       }
       continue;
@@ -1830,8 +1850,8 @@ vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega,
   Lv F = lv[0];
   if (!(F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2))
     return fail(VOS_ERR_ARG, "the finest level is too narrow for the z-marching kernels");
-  const int zl = zrun_len(F.n), zlf = zrun_len_fused(F.n, s->n_cu * zfused_blocks_per_cu<R>());
-  const dim3 gr(zrun_blocks(F.n, zl)), grf(zrun_blocks(F.n, zlf));
+  const int zl = zrun_len(F.n), zlf = zrun_len_fused(F.n, fused_slots<Lv, R>(s));
+  const dim3 gr(zrun_blocks(F.n, zl)), grf(zrun_blocks_fused(F.n, zlf));
   if (kind >= 4 && !zfused_level(F.n)) return fail(VOS_ERR_ARG, "the fused legs run on levels of >= 2^20 cells");
   const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
   const R om = (R)omega;
@@ -1856,12 +1876,13 @@ vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega,
         per = (cw + 3.0) * w * nc + w * lv[1].nc;
         break;
       case 4:
-        k_v_down3d<Lv, R, RHS_R><<<grf, TPB, 0, st>>>(F, lv[1], s->vec[1], rscale, om, zlf, flag);
-        per = (8.0 + (cw + 2.0) * w) * nc + w * lv[1].nc;
+        k_v_down3d<Lv, R, RHS_R><<<grf, ZF_TPB, 0, st>>>(F, lv[1], s->vec[1], rscale, om, zlf, flag);
+        per = (8.0 + (cw + 1.0) * w) * nc + w * lv[1].nc;
         break;
       default:
-        k_v_up3d<Lv, R, true><<<grf, TPB, 0, st>>>(F, lv[1], F.t, om, s->vec[2], nullptr, zlf, flag);
-        per = ((cw + 2.0) * w + 8.0) * nc + w * lv[1].nc;
+        k_v_up3d<Lv, R, true><<<grf, ZF_TPB, 0, st>>>(F, lv[1], F.t, om, s->vec[2], nullptr, s->vec[1], rscale, zlf,
+                                                     flag);
+        per = ((cw + 1.0) * w + 16.0) * nc + w * lv[1].nc;
         break;
     }
   };

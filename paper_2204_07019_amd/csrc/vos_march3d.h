@@ -75,18 +75,20 @@ inline unsigned zrun_blocks(const int n[3], int zlen)
 // per CU; a second, partial round of blocks would leave most CUs idle at the
 // end), and are at least 8 planes long.  They run on levels of at least 2^20
 // cells (the smaller levels keep the separate kernels).
+inline long zfused_tiles(const int n[3]) { return (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + 7) / 8); }
 inline int zrun_len_fused(const int n[3], int slots)
 {
-  const long tiles = (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + ZT_Y - 1) / ZT_Y);
-  const long runs = std::max(1L, (long)slots / tiles);
+  const long runs = std::max(1L, (long)slots / zfused_tiles(n));
   long zl = ((long)n[2] + runs - 1) / runs;
   zl = std::max(8L, zl + (zl & 1));
   return (int)zl;
 }
-// Resident blocks per CU of the fused legs: LDS (six planes of 68 x 8 values
-// and the restriction's two 64 x 4 planes) and registers allow 5 in FP64, 8 in FP32.
-template <typename R>
-constexpr int zfused_blocks_per_cu() { return sizeof(R) == 8 ? 5 : 8; }
+// Blocks of a fused-leg launch: its work items rounded up to a multiple of the 8 XCDs.
+inline unsigned zrun_blocks_fused(const int n[3], int zlen)
+{
+  const unsigned nw = (unsigned)zfused_tiles(n) * (unsigned)((n[2] + zlen - 1) / zlen);
+  return (nw + NXCD - 1) / NXCD * NXCD;
+}
 inline bool zfused_level(const int n[3])
 {
   return (unsigned long)n[0] * (unsigned long)n[1] * (unsigned long)n[2] >= (1ul << 20);
@@ -437,22 +439,44 @@ __global__ void __launch_bounds__(TPB) k_v_post3d(Lv F, Lv C, R *__restrict__ xo
 // the tile plus a two-cell x/y halo (plane z + 2), stage 1 applies the first
 // stencil to v on the tile plus a one-cell halo (plane z + 1), stage 2 applies
 // the second stencil on the tile itself (plane z).  The halo cells' stage-1
-// values are recomputed by both blocks that need them (their coefficients
-// mostly come from L2), so each tile cell's coefficients cross HBM once per
-// leg.  Every value is formed by the expression of the separate kernel it
-// replaces (k_v_pre3d + k_v_restrict3d down, k_v_post3d + k_v_jacobi3d up), so
-// the cycle's results are bitwise those of the separate kernels.
+// values are recomputed by both blocks that need them, so each tile cell's
+// coefficients cross HBM about once per leg.  Every value is formed by the
+// expression of the separate kernel it replaces (k_v_pre3d + k_v_restrict3d
+// down, k_v_post3d + k_v_jacobi3d up), so the cycle's results are bitwise
+// those of the separate kernels.
 //
-// LDS: four v planes (2-halo; a plane is read by three consecutive stage-1
-// passes, so four slots let stage 0 run one plane ahead with one barrier per
-// plane) and two u planes (1-halo).  A thread owns its tile cell (stages 0-2),
-// at most one cell of the one-cell ring (stages 0-1) and at most one of the
-// two-cell ring (stage 0).
-constexpr int ZH2_X = ZT_X + 4, ZH2_Y = ZT_Y + 4;   // two-cell halo plane
-constexpr int ZH1_X = ZT_X + 2, ZH1_Y = ZT_Y + 2;   // one-cell halo plane
-constexpr int ZRING1 = 2 * ZH1_X + 2 * ZT_Y;        // 140 cells
-constexpr int ZRING2 = 2 * ZH2_X + 2 * (ZT_Y + 2);  // 148 cells
-static_assert(ZRING1 <= TPB && ZRING2 <= TPB, "one ring cell per thread");
+// Tiles are ZT_X x ZF_Y (64 x 8) with a block of 512 threads (the halo rings
+// then carry 29 % of the tile's cells in the first ring instead of 55 % with 4
+// rows).  LDS: four v planes (two-cell halo; a plane is read by three
+// consecutive stage-1 passes, so four slots let stage 0 run one plane ahead
+// with one barrier per plane) and two u planes (one-cell halo).  A thread
+// owns its tile cell (stages 0-2), at most one cell of the one-cell ring
+// (stages 0-1) and at most one of the two-cell ring (stage 0).
+constexpr int ZF_Y = 8;
+constexpr int ZF_TPB = ZT_X * ZF_Y;                 // 512 threads
+constexpr int ZH2_X = ZT_X + 4, ZH2_Y = ZF_Y + 4;   // two-cell halo plane
+constexpr int ZH1_X = ZT_X + 2, ZH1_Y = ZF_Y + 2;   // one-cell halo plane
+constexpr int ZRING1 = 2 * ZH1_X + 2 * ZF_Y;        // 148 cells
+constexpr int ZRING2 = 2 * ZH2_X + 2 * (ZF_Y + 2);  // 156 cells
+static_assert(ZRING1 <= ZF_TPB && ZRING2 <= ZF_TPB, "one ring cell per thread");
+static_assert(ZF_Y % 2 == 0, "restriction aggregates stay inside a tile");
+
+// Work item of a fused-leg block: as ztile_of, with ZT_X x ZF_Y tiles.
+__device__ __forceinline__ bool zftile_of(const int n[3], int zlen, ZTile &t)
+{
+  const unsigned gx = (unsigned)(n[0] + ZT_X - 1) / ZT_X, gy = (unsigned)(n[1] + ZF_Y - 1) / ZF_Y;
+  const unsigned gz = (unsigned)(n[2] + zlen - 1) / (unsigned)zlen;
+  const unsigned tiles = gx * gy, nw = tiles * gz;
+  const unsigned per = (nw + NXCD - 1) / NXCD;
+  const unsigned w = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  if (w >= nw) return false;
+  const unsigned zr = w / tiles, tt = w - zr * tiles;
+  t.x0 = (int)(tt % gx) * ZT_X;
+  t.y0 = (int)(tt / gx) * ZF_Y;
+  t.z0 = (int)zr * zlen;
+  t.z1 = min(n[2], t.z0 + zlen);
+  return true;
+}
 
 // Position (in two-halo plane coordinates) of the thread's cell of class k:
 // 0 its tile cell, 1 its one-cell-ring cell, 2 its two-cell-ring cell;
@@ -470,8 +494,8 @@ __device__ __forceinline__ bool zfused_cell(int k, int &hx, int &hy)
     int x1, y1;   // one-halo coordinates
     if (h < ZH1_X) { x1 = h; y1 = 0; }
     else if (h < 2 * ZH1_X) { x1 = h - ZH1_X; y1 = ZH1_Y - 1; }
-    else if (h < 2 * ZH1_X + ZT_Y) { x1 = 0; y1 = h - 2 * ZH1_X + 1; }
-    else { x1 = ZH1_X - 1; y1 = h - 2 * ZH1_X - ZT_Y + 1; }
+    else if (h < 2 * ZH1_X + ZF_Y) { x1 = 0; y1 = h - 2 * ZH1_X + 1; }
+    else { x1 = ZH1_X - 1; y1 = h - 2 * ZH1_X - ZF_Y + 1; }
     hx = x1 + 1;
     hy = y1 + 1;
     return true;
@@ -479,8 +503,8 @@ __device__ __forceinline__ bool zfused_cell(int k, int &hx, int &hy)
   if (h >= ZRING2) return false;
   if (h < ZH2_X) { hx = h; hy = 0; }
   else if (h < 2 * ZH2_X) { hx = h - ZH2_X; hy = ZH2_Y - 1; }
-  else if (h < 2 * ZH2_X + ZT_Y + 2) { hx = 0; hy = h - 2 * ZH2_X + 1; }
-  else { hx = ZH2_X - 1; hy = h - 2 * ZH2_X - (ZT_Y + 2) + 1; }
+  else if (h < 2 * ZH2_X + ZF_Y + 2) { hx = 0; hy = h - 2 * ZH2_X + 1; }
+  else { hx = ZH2_X - 1; hy = h - 2 * ZH2_X - (ZF_Y + 2) + 1; }
   return true;
 }
 
@@ -521,19 +545,20 @@ __device__ __forceinline__ ZNb<R> znb2(const R (*pl)[ZH2_X], const R (*lo)[ZH2_X
 
 // Down leg: the two pre-smoothing sweeps of k_v_pre3d (from the FP64 residual,
 // RHS_R, or the level's b, RHS_B) and the residual restriction of
-// k_v_restrict3d, in one march.  Writes the level's b (RHS_R), x (after the
-// second sweep) and the coarse b.  zlen even.
+// k_v_restrict3d, in one march.  Writes x (after the second sweep) and the
+// coarse b.  With RHS_R the level's b is not stored: the finest level's up leg
+// forms it again from the same residual by the same expression.  zlen even.
 template <typename Lv, typename R, int RHS>
-__global__ void __launch_bounds__(TPB) k_v_down3d(Lv F, Lv C, const double *__restrict__ r64, double rscale, R omega,
+__global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *__restrict__ r64, double rscale, R omega,
                                                   int zlen, const double *__restrict__ sc)
 {
   static_assert(RHS == RHS_R || RHS == RHS_B, "no diagonal scaling in the fused leg");
   if (sc[S_CONV] != 0.0) return;
   ZTile t;
-  if (!ztile_of(F.n, zlen, t)) return;
+  if (!zftile_of(F.n, zlen, t)) return;
   __shared__ R vpl[4][ZH2_Y][ZH2_X];
   __shared__ R upl[2][ZH2_Y][ZH2_X];   // one-halo values, kept in two-halo coordinates
-  __shared__ R rs[2][ZT_Y][ZT_X];
+  __shared__ R rs[2][ZF_Y][ZT_X];
   const int nz = F.n[2];
   const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
   const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
@@ -603,11 +628,7 @@ __global__ void __launch_bounds__(TPB) k_v_down3d(Lv F, Lv C, const double *__re
     u_cur = b.u;
     k_cur = b.k;
     b_cur = b.bb;
-    if (c0.in) {
-      const unsigned id = c0.col + sz * (unsigned)t.z0;
-      if (RHS != RHS_B) F.b[id] = b.bb;
-      F.x[id] = b.u;
-    }
+    if (c0.in) F.x[c0.col + sz * (unsigned)t.z0] = b.u;
   }
   for (int z = t.z0; z < t.z1; ++z) {
     S1 a = load1(c0, z + 1), a1 = load1(c1, z + 1);
@@ -618,11 +639,7 @@ __global__ void __launch_bounds__(TPB) k_v_down3d(Lv F, Lv C, const double *__re
     apply1(c1, z + 1, a1);
     if (c1.has) upl[(z + 1) & 1][c1.hy][c1.hx] = a1.u;
     upl[(z + 1) & 1][c0.hy][c0.hx] = a.u;
-    if (c0.in && z + 1 < t.z1) {
-      const unsigned id = c0.col + sz * (unsigned)(z + 1);
-      if (RHS != RHS_B) F.b[id] = a.bb;
-      F.x[id] = a.u;
-    }
+    if (c0.in && z + 1 < t.z1) F.x[c0.col + sz * (unsigned)(z + 1)] = a.u;
     // stage 2 on plane z: the residual of the second sweep (k_v_restrict3d's expression)
     {
       const int cc[3] = {c0.gx, c0.gy, z};
@@ -641,7 +658,7 @@ __global__ void __launch_bounds__(TPB) k_v_down3d(Lv F, Lv C, const double *__re
     b_cur = a.bb;
     if ((z & 1) == 0 && z + 1 < nz) continue;   // block-uniform
     __syncthreads();
-    if (threadIdx.x < (ZT_X / 2) * (ZT_Y / 2)) {
+    if (threadIdx.x < (ZT_X / 2) * (ZF_Y / 2)) {
       const int ix = threadIdx.x % (ZT_X / 2), iy = threadIdx.x / (ZT_X / 2);
       const int IX = t.x0 / 2 + ix, IY = t.y0 / 2 + iy, IZ = z >> 1;
       if (IX < C.n[0] && IY < C.n[1]) {
@@ -660,15 +677,17 @@ __global__ void __launch_bounds__(TPB) k_v_down3d(Lv F, Lv C, const double *__re
 
 // Up leg: the prolongation with the first post-smoothing sweep of k_v_post3d
 // and the second sweep of k_v_jacobi3d, in one march.  Writes the result to
-// xo, or with OUT64 (the cycle's last sweep) only to the FP64 output z.
+// xo, or with OUT64 (the finest level: the cycle's last sweep) only to the
+// FP64 output z; there the right-hand side is (R)(rscale r64), the down leg's
+// expression, since that leg did not store it.
 template <typename Lv, typename R, bool OUT64>
-__global__ void __launch_bounds__(TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z64,
-                                                const double *__restrict__ dsc, int zlen,
-                                                const double *__restrict__ sc)
+__global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z64,
+                                                const double *__restrict__ dsc, const double *__restrict__ r64,
+                                                double rscale, int zlen, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   ZTile t;
-  if (!ztile_of(F.n, zlen, t)) return;
+  if (!zftile_of(F.n, zlen, t)) return;
   __shared__ R vpl[4][ZH2_Y][ZH2_X];
   __shared__ R upl[2][ZH2_Y][ZH2_X];
   const int nz = F.n[2];
@@ -697,7 +716,7 @@ __global__ void __launch_bounds__(TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, 
     const bool ok = c.in && z >= 0 && z < nz;
     const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
     const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
-    o.k = ZCoefB<R>{zcoef(F, id, cc), F.b[id]};
+    o.k = ZCoefB<R>{zcoef(F, id, cc), OUT64 ? (R)(rscale * r64[id]) : F.b[id]};
     o.u = (R)0;
     return o;
   };

@@ -31,13 +31,13 @@ namespace {
 long g_launches = 0;
 
 template <typename F>
-void launch(unsigned blocks, F &&kernel)
+void launch(unsigned blocks, F &&kernel, unsigned tpb = TPB)
 {
   gridDim.x = blocks;
-  blockDim.x = TPB;
+  blockDim.x = tpb;
   for (unsigned b = 0; b < blocks; ++b) {
     blockIdx.x = b;
-    for (unsigned t = 0; t < (unsigned)TPB; ++t) {
+    for (unsigned t = 0; t < tpb; ++t) {
       threadIdx.x = t;
       kernel();
     }
@@ -142,13 +142,18 @@ void run_levels(const char *name, std::vector<Lv> &lv)
     std::printf("  %s level %zu: %d x %d x %d, z-run %d, %u blocks: 8 launches in bounds\n", name, l, F.n[0], F.n[1],
                 F.n[2], zl, nb);
     if (zfused_level(F.n)) {
-      const int zf = zrun_len_fused(F.n, 256 * zfused_blocks_per_cu<R>());
-      const unsigned nf = zrun_blocks(F.n, zf);
-      launch(nf, [&] { k_v_down3d<Lv, R, RHS_R>(F, C, r64, 1.0, om, zf, sc); });
-      launch(nf, [&] { k_v_down3d<Lv, R, RHS_B>(F, C, r64, 1.0, om, zf, sc); });
-      launch(nf, [&] { k_v_up3d<Lv, R, true>(F, C, F.t, om, z, nullptr, zf, sc); });
-      launch(nf, [&] { k_v_up3d<Lv, R, false>(F, C, F.t, om, nullptr, nullptr, zf, sc); });
-      std::printf("  %s level %zu fused legs: z-run %d, %u blocks: 4 launches in bounds\n", name, l, zf, nf);
+      // one and three resident blocks per CU of 256 CUs: long and short z-runs
+      for (int slots : {256, 768}) {
+        const int zf = zrun_len_fused(F.n, slots);
+        const unsigned nf = zrun_blocks_fused(F.n, zf);
+        launch(nf, [&] { k_v_down3d<Lv, R, RHS_R>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+        launch(nf, [&] { k_v_down3d<Lv, R, RHS_B>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+        launch(nf, [&] { k_v_up3d<Lv, R, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZF_TPB);
+        launch(nf, [&] { k_v_up3d<Lv, R, false>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zf, sc); }, ZF_TPB);
+      }
+      const int zf = zrun_len_fused(F.n, 768);
+      const unsigned nf = zrun_blocks_fused(F.n, zf);
+      std::printf("  %s level %zu fused legs: z-run %d, %u blocks (and a longer run): 8 launches in bounds\n", name, l, zf, nf);
     }
   }
 }
