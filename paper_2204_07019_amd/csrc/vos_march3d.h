@@ -21,6 +21,7 @@
 // of z-runs and the halos its tiles share stay in its L2.
 #pragma once
 #include <algorithm>
+#include <type_traits>
 
 #include "vos_vcycle.h"
 
@@ -157,6 +158,35 @@ __device__ __forceinline__ ZCoef<R> zcoef(const SLevel<R> &L, unsigned id, const
 {
   ZCoef<R> k;
   k.d = L.diag[id];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) k.o[q] = L.off[(size_t)q * L.nc + id];
+  return k;
+}
+
+// As zcoef, with the cell's stored diagonal dg already loaded by the caller.
+template <typename R>
+__device__ __forceinline__ ZCoef<R> zcoef_dg(const MgLevel<R> &L, unsigned, const int c[3], R dg)
+{
+  ZCoef<R> k;
+  const unsigned f0 = (unsigned)c[0] + (unsigned)L.fd[0][0] * ((unsigned)c[1] + (unsigned)L.fd[0][1] * c[2]);
+  const unsigned f1 = (unsigned)c[0] + (unsigned)L.fd[1][0] * ((unsigned)c[1] + (unsigned)L.fd[1][1] * c[2]);
+  const unsigned f2 = (unsigned)c[0] + (unsigned)L.fd[2][0] * ((unsigned)c[1] + (unsigned)L.fd[2][1] * c[2]);
+  const unsigned sz = (unsigned)L.n[0] * L.n[1];
+  k.o[0] = L.T[0][f0];
+  k.o[1] = L.T[0][f0 + 1];
+  k.o[2] = L.T[1][f1];
+  k.o[3] = L.T[1][f1 + L.fd[1][0]];
+  k.o[4] = L.T[2][f2];
+  k.o[5] = L.T[2][f2 + sz];
+  k.d = L.dsum ? (k.o[0] + k.o[1] + k.o[2] + k.o[3]) + (k.o[4] + k.o[5]) : dg;
+  return k;
+}
+
+template <typename R>
+__device__ __forceinline__ ZCoef<R> zcoef_dg(const SLevel<R> &L, unsigned id, const int *, R dg)
+{
+  ZCoef<R> k;
+  k.d = dg;
 #pragma unroll
   for (int q = 0; q < 6; ++q) k.o[q] = L.off[(size_t)q * L.nc + id];
   return k;
@@ -562,36 +592,68 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
   const int nz = F.n[2];
   const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
   const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
-  auto rhs = [&](unsigned id) -> R {
-    if (RHS == RHS_R) return (R)(rscale * r64[id]);
-    return F.b[id];
+  // the right-hand side as loaded (the FP64 residual or the level's b) and as
+  // used, (R)(rscale r) or b: loads carry the raw word, so that no arithmetic
+  // ahead of a plane's barrier waits for them
+  using RB = typename std::conditional<RHS == RHS_R, double, R>::type;
+  auto rhs_raw = [&](unsigned id) -> RB {
+    if constexpr (RHS == RHS_R) return r64[id];
+    else return F.b[id];
   };
-  // stage 0: v = omega b / d (the first sweep from x = 0), 0 outside the level
-  auto stage0 = [&](int z) {
-    const int s = z & 3;
+  auto rhs = [&](RB raw) -> R {
+    if constexpr (RHS == RHS_R) return (R)(rscale * raw);
+    else return raw;
+  };
+  // stage 0: v = omega b / d (the first sweep from x = 0), 0 outside the level.
+  // Its inputs for the thread's three cells are loaded one plane ahead (load0,
+  // every index inside the arrays) and carried in registers to put0.
+  const ZCell *cs[3] = {&c0, &c1, &c2};
+  struct P0 { RB b[3]; R d[3]; };
+  auto load0 = [&](int z) -> P0 {
+    P0 p;
     const bool zin = z >= 0 && z < nz;
-    const ZCell *cs[3] = {&c0, &c1, &c2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const ZCell &c = *cs[k];
-      const bool ok = c.in && zin;
-      const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
-      const R v = omega * rhs(id) / F.diag[id];
-      if (c.has) vpl[s][c.hy][c.hx] = ok ? v : (R)0;
+      const unsigned id = cs[k]->in && zin ? cs[k]->col + sz * (unsigned)z : 0u;
+      p.b[k] = rhs_raw(id);
+      p.d[k] = F.diag[id];
+    }
+    return p;
+  };
+  auto put0 = [&](int z, const P0 &p) {
+    const int s = z & 3;
+    const bool zin = z >= 0 && z < nz;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R v = omega * rhs(p.b[k]) / p.d[k];
+      if (cs[k]->has) vpl[s][cs[k]->hy][cs[k]->hx] = cs[k]->in && zin ? v : (R)0;
     }
   };
   // stage 1 for one cell at plane z: the second sweep (k_v_pre3d's expression);
   // its loads (load1) are issued before the plane's barrier, the arithmetic
   // (apply1) after it
-  struct S1 { R u, bb, dg; ZCoef<R> k; };
+  struct S1 { R u; RB bb; R dg; ZCoef<R> k; };
   auto load1 = [&](const ZCell &c, int z) -> S1 {
     S1 o;
     const bool ok = c.in && z >= 0 && z < nz;
     const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
     const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
-    o.bb = rhs(id);
+    o.bb = rhs_raw(id);
     o.dg = F.diag[id];
     o.k = zcoef(F, id, cc);
+    o.u = (R)0;
+    return o;
+  };
+  // the same, with b and d of class-k cell c taken from stage 0's loads p of
+  // that plane (the same words): only the off-diagonals are loaded
+  auto load1p = [&](const ZCell &c, int z, const P0 &p, int k) -> S1 {
+    S1 o;
+    const bool ok = c.in && z >= 0 && z < nz;
+    const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
+    const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
+    o.bb = p.b[k];
+    o.dg = p.d[k];
+    o.k = zcoef_dg(F, id, cc, p.d[k]);
     o.u = (R)0;
     return o;
   };
@@ -601,7 +663,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     const R s = vpl[z & 3][c.hy][c.hx];
     const ZNb<R> nb = znb2<R>(vpl[z & 3], vpl[(z - 1) & 3], vpl[(z + 1) & 3], c.hx, c.hy);
     const R ax = zapply_off<Lv, R>(F, zhas(F.n, cc), o.k, o.dg, s, nb);
-    o.u = ok ? s + omega * (o.bb - ax) / o.dg : (R)0;
+    o.u = ok ? s + omega * (rhs(o.bb) - ax) / o.dg : (R)0;
   };
   auto stage1 = [&](const ZCell &c, int z) -> S1 {
     S1 o = load1(c, z);
@@ -609,8 +671,12 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     return o;
   };
   const int lx = threadIdx.x % ZT_X, ly = threadIdx.x / ZT_X;
-  // prologue: v on planes z0-2 .. z0+1, u on planes z0-1 and z0
-  for (int z = t.z0 - 2; z <= t.z0 + 1; ++z) stage0(z);
+  // prologue: v on planes z0-2 .. z0+1, u on planes z0-1 and z0; stage 0's
+  // loads of plane z+1 (held) and z+2 (ahead) enter the march's plane z
+  for (int z = t.z0 - 2; z <= t.z0; ++z) put0(z, load0(z));
+  P0 held = load0(t.z0 + 1);
+  put0(t.z0 + 1, held);
+  P0 ahead = load0(t.z0 + 2);
   __syncthreads();
   R u_prev, u_cur;
   ZCoef<R> k_cur;
@@ -627,12 +693,15 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     upl[t.z0 & 1][c0.hy][c0.hx] = b.u;
     u_cur = b.u;
     k_cur = b.k;
-    b_cur = b.bb;
+    b_cur = rhs(b.bb);
     if (c0.in) F.x[c0.col + sz * (unsigned)t.z0] = b.u;
   }
   for (int z = t.z0; z < t.z1; ++z) {
-    S1 a = load1(c0, z + 1), a1 = load1(c1, z + 1);
-    stage0(z + 2);
+    S1 a = load1p(c0, z + 1, held, 0), a1 = load1p(c1, z + 1, held, 1);
+    const P0 next = load0(z + 3);
+    put0(z + 2, ahead);
+    held = ahead;
+    ahead = next;
     __syncthreads();
     // stage 1 on plane z + 1
     apply1(c0, z + 1, a);
@@ -655,7 +724,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     u_prev = u_cur;
     u_cur = a.u;
     k_cur = a.k;
-    b_cur = a.bb;
+    b_cur = rhs(a.bb);
     if ((z & 1) == 0 && z + 1 < nz) continue;   // block-uniform
     __syncthreads();
     if (threadIdx.x < (ZT_X / 2) * (ZF_Y / 2)) {
@@ -693,30 +762,49 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
   const int nz = F.n[2];
   const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
   const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
-  // stage 0: y = x + the coarse correction of the cell's aggregate
-  auto stage0 = [&](int z) {
-    const int s = z & 3;
+  // stage 0: y = x + the coarse correction of the cell's aggregate; inputs
+  // loaded one plane ahead as in the down leg
+  const ZCell *cs[3] = {&c0, &c1, &c2};
+  struct P0 { R x[3], e[3]; };
+  auto load0 = [&](int z) -> P0 {
+    P0 p;
     const bool zin = z >= 0 && z < nz;
-    const ZCell *cs[3] = {&c0, &c1, &c2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const ZCell &c = *cs[k];
-      const bool ok = c.in && zin;
-      const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
-      const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
-      const R v = F.x[id] + C.x[parent_of<R>(F.n, C.n, 3, cc)];
-      if (c.has) vpl[s][c.hy][c.hx] = ok ? v : (R)0;
+      const bool ok = cs[k]->in && zin;
+      const int cc[3] = {ok ? cs[k]->gx : 0, ok ? cs[k]->gy : 0, ok ? z : 0};
+      const unsigned id = ok ? cs[k]->col + sz * (unsigned)z : 0u;
+      p.x[k] = F.x[id];
+      p.e[k] = C.x[parent_of<R>(F.n, C.n, 3, cc)];
+    }
+    return p;
+  };
+  auto put0 = [&](int z, const P0 &p) {
+    const int s = z & 3;
+    const bool zin = z >= 0 && z < nz;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R v = p.x[k] + p.e[k];
+      if (cs[k]->has) vpl[s][cs[k]->hy][cs[k]->hx] = cs[k]->in && zin ? v : (R)0;
     }
   };
   // stage 1: the first up sweep (k_v_post3d's expression), loads before the
-  // plane's barrier (load1), arithmetic after it (apply1)
-  struct S1 { R u; ZCoefB<R> k; };
+  // plane's barrier (load1), arithmetic after it (apply1); the right-hand side
+  // is carried as loaded (the FP64 residual with OUT64) and formed at its use
+  using RB = typename std::conditional<OUT64, double, R>::type;
+  auto rhs = [&](RB raw) -> R {
+    if constexpr (OUT64) return (R)(rscale * raw);
+    else return raw;
+  };
+  struct S1 { R u; ZCoef<R> k; RB b; };
   auto load1 = [&](const ZCell &c, int z) -> S1 {
     S1 o;
     const bool ok = c.in && z >= 0 && z < nz;
     const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
     const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
-    o.k = ZCoefB<R>{zcoef(F, id, cc), OUT64 ? (R)(rscale * r64[id]) : F.b[id]};
+    o.k = zcoef(F, id, cc);
+    if constexpr (OUT64) o.b = r64[id];
+    else o.b = F.b[id];
     o.u = (R)0;
     return o;
   };
@@ -725,18 +813,19 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
     const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
     const R y = vpl[z & 3][c.hy][c.hx];
     const ZNb<R> nb = znb2<R>(vpl[z & 3], vpl[(z - 1) & 3], vpl[(z + 1) & 3], c.hx, c.hy);
-    const R dg = o.k.a.d;
-    const R ay = zapply_off<Lv, R>(F, zhas(F.n, cc), o.k.a, dg, y, nb);
-    o.u = ok ? y + omega * (o.k.b - ay) / dg : (R)0;
+    const R dg = o.k.d;
+    const R ay = zapply_off<Lv, R>(F, zhas(F.n, cc), o.k, dg, y, nb);
+    o.u = ok ? y + omega * (rhs(o.b) - ay) / dg : (R)0;
   };
   auto stage1 = [&](const ZCell &c, int z) -> S1 {
     S1 o = load1(c, z);
     apply1(c, z, o);
     return o;
   };
-  R u_prev, u_cur;
-  ZCoefB<R> k_cur;
-  for (int z = t.z0 - 2; z <= t.z0 + 1; ++z) stage0(z);
+  R u_prev, u_cur, b_cur;
+  ZCoef<R> k_cur;
+  for (int z = t.z0 - 2; z <= t.z0 + 1; ++z) put0(z, load0(z));
+  P0 ahead = load0(t.z0 + 2);
   __syncthreads();
   {
     const S1 a = stage1(c0, t.z0 - 1);
@@ -750,10 +839,13 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
     upl[t.z0 & 1][c0.hy][c0.hx] = b.u;
     u_cur = b.u;
     k_cur = b.k;
+    b_cur = rhs(b.b);
   }
   for (int z = t.z0; z < t.z1; ++z) {
     S1 a = load1(c0, z + 1), a1 = load1(c1, z + 1);
-    stage0(z + 2);
+    const P0 next = load0(z + 3);
+    put0(z + 2, ahead);
+    ahead = next;
     __syncthreads();
     apply1(c0, z + 1, a);
     apply1(c1, z + 1, a1);
@@ -770,13 +862,14 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
       nb.n = upl[z & 1][c0.hy + 1][c0.hx];
       nb.b = u_prev;
       nb.t = a.u;
-      const R v = u_cur + omega * (k_cur.b - zapply(F, zhas(F.n, cc), k_cur.a, u_cur, nb)) / k_cur.a.d;
+      const R v = u_cur + omega * (b_cur - zapply(F, zhas(F.n, cc), k_cur, u_cur, nb)) / k_cur.d;
       if (OUT64) z64[id] = unscale((double)v, dsc, id);
       else xo[id] = v;
     }
     u_prev = u_cur;
     u_cur = a.u;
     k_cur = a.k;
+    b_cur = rhs(a.b);
   }
 }
 
