@@ -364,7 +364,11 @@ typedef enum {
   /* the fused legs of that level (levels of >= 2^20 cells): both pre-sweeps and the
      restriction; the prolongation and both post-sweeps with the FP64 output */
   VOS_KERNEL_C_DOWN3D = 16,
-  VOS_KERNEL_C_UP3D = 17
+  VOS_KERNEL_C_UP3D = 17,
+  /* the same two fused legs on the finest level of the x-momentum hierarchy (the
+     (nx+1) x ny x nz face grid; FP32 in mixed precision, else FP64): */
+  VOS_KERNEL_M_DOWN3D = 18,
+  VOS_KERNEL_M_UP3D = 19
 } vos_kernel_family;
 
 /* Time `reps` back-to-back launch sequences of one kernel family on the live

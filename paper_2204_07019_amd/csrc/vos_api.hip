@@ -124,7 +124,8 @@ struct SmgPlan {
   int n[SMG_MAX_LEVELS][3];
   size_t off[SMG_MAX_LEVELS], diag[SMG_MAX_LEVELS], x[SMG_MAX_LEVELS], b[SMG_MAX_LEVELS], t[SMG_MAX_LEVELS];
   size_t dif[SMG_MAX_LEVELS];   // diffusive parts (transport hierarchy only)
-  bool split;
+  size_t off32;                 // FP32 off-diagonals of the finest level (when has32)
+  bool split, has32;
   size_t ainv;
 };
 
@@ -148,11 +149,13 @@ constexpr int NSC = 9;  // scalar blocks: mom x/y/z, pressure, transport, misc, 
 constexpr int P_STALL_WINDOW = 400;
 
 // Aggregation hierarchy: ceil-halve every active dimension until <= SMG_COARSE_MAX cells.
-void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs, bool split)
+void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs, bool split, bool off32 = false)
 {
   int n[3] = {nx, ny, nz};
   S.nlev = 0;
   S.split = split;
+  S.has32 = off32;
+  S.off32 = off32 ? P.take(6 * (size_t)nx * ny * nz * sizeof(float)) : 0;
   while (S.nlev < SMG_MAX_LEVELS) {
     const int l = S.nlev++;
     for (int d = 0; d < 3; ++d) S.n[l][d] = n[d];
@@ -230,8 +233,10 @@ Layout make_layout(const vos_grid &g, int precision)
     else Lo.smg[d].nlev = 0;
   }
   // the transport hierarchy is FP64 in both precisions: its Galerkin coarse
-  // diagonals of upwind-dominated rows cancel to near zero and break down in FP32
-  plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, sizeof(double), true);
+  // diagonals of upwind-dominated rows cancel to near zero and break down in
+  // FP32.  In mixed precision its finest 3-D level's smoothing reads FP32
+  // copies of the off-diagonals (FP64 arithmetic, FP64 diagonal).
+  plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, sizeof(double), true, precision == VOS_MIXED && nd == 3);
   Lo.total = P.off;
   return Lo;
 }
@@ -372,6 +377,7 @@ void fill_smg(vos_sim *s, int h, SLevel<R> *lv)
     L.b = (R *)(s->ws + S.b[l]);
     L.t = (R *)(s->ws + S.t[l]);
     L.dif = S.split ? (R *)(s->ws + S.dif[l]) : nullptr;
+    L.off32 = l == 0 && S.has32 ? (float *)(s->ws + S.off32) : nullptr;
   }
   if (S.nlev) s->sainv[h] = (double *)(s->ws + S.ainv);
 }
@@ -742,21 +748,80 @@ void launch_coarse(int c0, const LevelPack<Lv> &pack, int lc, int L, int nd, int
 // z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
 // Blocks a CU holds at once of the fused legs of one level type (their LDS and
 // registers decide it; queried once per instantiation), times the CUs.
-template <typename Lv, typename R>
+template <typename Lv, typename R, bool O32>
 int fused_slots(const vos_sim *s)
 {
   static int per_cu = 0;   // kernel attributes: the same for every simulation of the process
   if (per_cu == 0) {
     int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, reinterpret_cast<const void *>(k_v_down3d<Lv, R, RHS_R>),
-                                                     ZF_TPB, 0) != hipSuccess || a < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &a, reinterpret_cast<const void *>(k_v_down3d<Lv, R, RHS_R, O32>), ZF_TPB, 0) != hipSuccess ||
+        a < 1)
       a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(k_v_up3d<Lv, R, true>),
-                                                     ZF_TPB, 0) != hipSuccess || b < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &b, reinterpret_cast<const void *>(k_v_up3d<Lv, R, true, O32>), ZF_TPB, 0) != hipSuccess ||
+        b < 1)
       b = 1;
     per_cu = std::min(a, b);
   }
   return s->n_cu * per_cu;
+}
+
+// Only the FP64 aggregation levels carry FP32 off-diagonal copies (the finest
+// transport level in mixed precision); the fused legs' O32 variant exists for them.
+template <typename Lv>
+constexpr bool lv_can32 = false;
+template <>
+constexpr bool lv_can32<SLevel<double>> = true;
+template <typename Lv>
+bool lv_has32(const Lv &)
+{
+  return false;
+}
+template <typename R>
+bool lv_has32(const SLevel<R> &L)
+{
+  return L.off32 != nullptr;
+}
+
+// The fused legs of level F (coarse level C): the down leg from the FP64
+// residual r (finest level, RHS_R) or from F's b; the up leg into the FP64
+// output z (finest level) or into F.t.
+template <typename Lv, typename R, bool O32>
+void fused_down_t(vos_sim *s, const Lv &F, const Lv &C, bool finest, const double *r, double rscale, R om,
+                  const double *sc, hipStream_t st)
+{
+  const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s));
+  const dim3 gr(zrun_blocks_fused(F.n, zl));
+  if (finest) k_v_down3d<Lv, R, RHS_R, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, rscale, om, zl, sc);
+  else k_v_down3d<Lv, R, RHS_B, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, rscale, om, zl, sc);
+}
+template <typename Lv, typename R, bool O32>
+void fused_up_t(vos_sim *s, const Lv &F, const Lv &C, bool finest, double *z, const double *r, double rscale, R om,
+                const double *sc, hipStream_t st)
+{
+  const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s));
+  const dim3 gr(zrun_blocks_fused(F.n, zl));
+  if (finest) k_v_up3d<Lv, R, true, O32><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, z, nullptr, r, rscale, zl, sc);
+  else k_v_up3d<Lv, R, false, O32><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zl, sc);
+}
+template <typename Lv, typename R>
+void fused_down(vos_sim *s, const Lv &F, const Lv &C, bool finest, const double *r, double rscale, R om,
+                const double *sc, hipStream_t st)
+{
+  if constexpr (lv_can32<Lv>) {
+    if (lv_has32(F)) return fused_down_t<Lv, R, true>(s, F, C, finest, r, rscale, om, sc, st);
+  }
+  fused_down_t<Lv, R, false>(s, F, C, finest, r, rscale, om, sc, st);
+}
+template <typename Lv, typename R>
+void fused_up(vos_sim *s, const Lv &F, const Lv &C, bool finest, double *z, const double *r, double rscale, R om,
+              const double *sc, hipStream_t st)
+{
+  if constexpr (lv_can32<Lv>) {
+    if (lv_has32(F)) return fused_up_t<Lv, R, true>(s, F, C, finest, z, r, rscale, om, sc, st);
+  }
+  fused_up_t<Lv, R, false>(s, F, C, finest, z, r, rscale, om, sc, st);
 }
 
 template <typename Lv, typename R>
@@ -778,10 +843,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     const int nb = grid_blocks(F.nc);
     if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
       // both pre-sweeps and the restriction in one march
-      const int zl = zrun_len_fused(F.n, fused_slots<Lv, R>(s));
-      const dim3 gr(zrun_blocks_fused(F.n, zl));
-      if (l == 0) k_v_down3d<Lv, R, RHS_R><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
-      else k_v_down3d<Lv, R, RHS_B><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], r, rscale, om, zl, sc);
+      fused_down<Lv, R>(s, F, lv[l + 1], l == 0, r, rscale, om, sc, st);
       continue;
     }
     if (zmarch(F)) {
@@ -843,15 +905,8 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
     const int nb = grid_blocks(F.nc);
     if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
       // prolongation and both post-sweeps in one march
-      const int zl = zrun_len_fused(F.n, fused_slots<Lv, R>(s));
-      const dim3 gr(zrun_blocks_fused(F.n, zl));
-      if (l == 0) {
-        k_v_up3d<Lv, R, true><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, r, rscale, zl, sc);
-      } else {
-        k_v_up3d<Lv, R, false><<<gr, ZF_TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, nullptr, 1.0, zl,
-                                                      sc);
-        std::swap(F.x, F.t);
-      }
+      fused_up<Lv, R>(s, F, lv[l + 1], l == 0, z, r, rscale, om, sc, st);
+      if (l > 0) std::swap(F.x, F.t);
       continue;
     }
     if (zmarch(F)) {
@@ -1725,6 +1780,8 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
   const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
   const R om = (R)0.85;
   const double Rs = sizeof(R);
+  // bytes of a level's 2 nd off-diagonals (FP32 copies where the level keeps them)
+  auto offb = [&](int l) { return 2.0 * nd * (lv[l].off32 ? sizeof(float) : Rs); };
   double per_seq_bytes = 0.0;
   int per_seq_launches = 0;
   auto seq = [&](bool count) {
@@ -1732,21 +1789,21 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_RESTRICT:
         for (int l = 0; l < lc; ++l) {
           k_v_restrict<SLevel<R>, R><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd, flag);
-          if (count) { per_seq_bytes += (3.0 + 2 * nd) * Rs * lv[l].nc + Rs * lv[l + 1].nc; ++per_seq_launches; }
+          if (count) { per_seq_bytes += (3.0 * Rs + offb(l)) * lv[l].nc + Rs * lv[l + 1].nc; ++per_seq_launches; }
         }
         break;
       case VOS_KERNEL_V_POST:
         for (int l = 0; l < lc; ++l) {
           k_v_post<SLevel<R>, R, false><<<grid_blocks(lv[l].nc), TPB, 0, st>>>(lv[l], lv[l + 1], nd, lv[l].t, om,
                                                                                nullptr, nullptr, flag);
-          if (count) { per_seq_bytes += (4.0 + 2 * nd) * Rs * lv[l].nc + Rs * lv[l + 1].nc; ++per_seq_launches; }
+          if (count) { per_seq_bytes += (4.0 * Rs + offb(l)) * lv[l].nc + Rs * lv[l + 1].nc; ++per_seq_launches; }
         }
         break;
       case VOS_KERNEL_V_PRE:
         for (int l = 1; l < lc; ++l) {
           k_v_pre<SLevel<R>, R, false, 2><<<grid_blocks(lv[l].nc), TPB, 0, st>>>(lv[l], nd, nullptr, nullptr, 1.0,
                                                                                  om, flag);
-          if (count) { per_seq_bytes += (3.0 + 2 * nd) * Rs * lv[l].nc; ++per_seq_launches; }
+          if (count) { per_seq_bytes += (3.0 * Rs + offb(l)) * lv[l].nc; ++per_seq_launches; }
         }
         break;
       case VOS_KERNEL_V_COARSE: {
@@ -1775,14 +1832,14 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
           } else {
             if (nu == 2) TDOWN(2, VT_Y_SMALL); else if (nu == 3) TDOWN(3, VT_Y_SMALL); else TDOWN(4, VT_Y_SMALL);
           }
-          if (count) { per_seq_bytes += (3.0 + 2 * nd) * Rs * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
+          if (count) { per_seq_bytes += (3.0 * Rs + offb(0)) * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
         } else {
           if (ty == VT_Y_BIG) {
             if (nu == 2) TUP(2, VT_Y_BIG); else if (nu == 3) TUP(3, VT_Y_BIG); else TUP(4, VT_Y_BIG);
           } else {
             if (nu == 2) TUP(2, VT_Y_SMALL); else if (nu == 3) TUP(3, VT_Y_SMALL); else TUP(4, VT_Y_SMALL);
           }
-          if (count) { per_seq_bytes += (4.0 + 2 * nd) * Rs * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
+          if (count) { per_seq_bytes += (4.0 * Rs + offb(0)) * lv[0].nc + Rs * lv[1].nc; ++per_seq_launches; }
         }
 #undef TDOWN
 #undef TUP
@@ -1820,26 +1877,27 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
 
 // Back-to-back launches of one z-marching kernel of a 3-D hierarchy's finest
 // level with the production launch shape: the pressure hierarchy (in the
-// arithmetic the last pressure solve used) or the transport hierarchy (FP64).
-// They write only the level's V-cycle buffers, which every V-cycle rebuilds
-// from its input.  Bytes per fine cell, every array once (w = bytes of the
-// hierarchy's arithmetic; cw = coefficient words per cell: 3 face arrays T for
-// the pressure levels, whose finest diagonal is the sum of the faces, 6
-// off-diagonals + the diagonal for the transport levels):
+// arithmetic the last pressure solve used), the transport hierarchy (FP64) or
+// the x-momentum hierarchy.  They write only the level's V-cycle buffers,
+// which every V-cycle rebuilds from its input.  Bytes per fine cell, every
+// array once (w = bytes of the hierarchy's arithmetic; cb = coefficient bytes
+// per cell: 3 face arrays T for the pressure levels, whose finest diagonal is
+// the sum of the faces, else the diagonal and 6 off-diagonals, these in FP32
+// where the level keeps FP32 copies):
 //   pre (first down launch, two sweeps from the FP64 residual): r (8) +
-//     coefficients, write b, write x ((cw + 2) w);
-//   sweep: x, coefficients, b, write ((cw + 3) w);
-//   restrict: x, coefficients, b ((cw + 2) w) + coarse b (w / 8);
+//     coefficients, write b, write x (cb + 2 w);
+//   sweep: x, coefficients, b, write (cb + 3 w);
+//   restrict: x, coefficients, b (cb + 2 w) + coarse b (w / 8);
 //   post (prolongation + first up sweep): x, coefficients, b, write
-//     ((cw + 3) w) + coarse x (w / 8);
+//     (cb + 3 w) + coarse x (w / 8);
 //   fused down leg (two sweeps from the FP64 residual and the restriction):
-//     r (8) + coefficients, write b, write x ((cw + 2) w) + coarse b (w / 8);
-//   fused up leg (prolongation and two sweeps, FP64 output): x, coefficients,
-//     b ((cw + 2) w), write (8) + coarse x (w / 8).
+//     r (8) + coefficients, write x (cb + w) + coarse b (w / 8);
+//   fused up leg (prolongation and two sweeps, FP64 output): x, coefficients
+//     (cb + w), r (8), write (8) + coarse x (w / 8).
 template <typename R>
-constexpr double coef_words(const MgLevel<R> *) { return 3.0; }
+double coef_bytes(const MgLevel<R> &) { return 3.0 * sizeof(R); }
 template <typename R>
-constexpr double coef_words(const SLevel<R> *) { return 7.0; }
+double coef_bytes(const SLevel<R> &L) { return sizeof(R) + 6.0 * (L.off32 ? sizeof(float) : sizeof(R)); }
 
 template <typename Lv, typename R>
 vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega, double rscale, int reps, double *ms,
@@ -1850,39 +1908,38 @@ vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega,
   Lv F = lv[0];
   if (!(F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2))
     return fail(VOS_ERR_ARG, "the finest level is too narrow for the z-marching kernels");
-  const int zl = zrun_len(F.n), zlf = zrun_len_fused(F.n, fused_slots<Lv, R>(s));
-  const dim3 gr(zrun_blocks(F.n, zl)), grf(zrun_blocks_fused(F.n, zlf));
+  const int zl = zrun_len(F.n);
+  const dim3 gr(zrun_blocks(F.n, zl));
   if (kind >= 4 && !zfused_level(F.n)) return fail(VOS_ERR_ARG, "the fused legs run on levels of >= 2^20 cells");
   const double *flag = sc_block(s, SC_MISC) + S_COUNT;   // always unconverged
   const R om = (R)omega;
-  const double w = sizeof(R), nc = F.nc, cw = coef_words(&F);
+  const double w = sizeof(R), nc = F.nc, cb = coef_bytes(F);
   double per = 0.0;
   auto launch = [&]() {
     switch (kind) {
       case 0:
         k_v_pre3d<Lv, R, RHS_R><<<gr, TPB, 0, st>>>(F, s->vec[1], nullptr, rscale, om, zl, flag);
-        per = (8.0 + (cw + 2.0) * w) * nc;
+        per = (8.0 + cb + 2.0 * w) * nc;
         break;
       case 1:
         k_v_jacobi3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, F.x, F.t, om, nullptr, nullptr, zl, flag);
-        per = (cw + 3.0) * w * nc;
+        per = (cb + 3.0 * w) * nc;
         break;
       case 2:
         k_v_restrict3d<Lv, R><<<gr, TPB, 0, st>>>(F, lv[1], zl, flag);
-        per = (cw + 2.0) * w * nc + w * lv[1].nc;
+        per = (cb + 2.0 * w) * nc + w * lv[1].nc;
         break;
       case 3:
         k_v_post3d<Lv, R, false><<<gr, TPB, 0, st>>>(F, lv[1], F.t, om, nullptr, nullptr, zl, flag);
-        per = (cw + 3.0) * w * nc + w * lv[1].nc;
+        per = (cb + 3.0 * w) * nc + w * lv[1].nc;
         break;
       case 4:
-        k_v_down3d<Lv, R, RHS_R><<<grf, ZF_TPB, 0, st>>>(F, lv[1], s->vec[1], rscale, om, zlf, flag);
-        per = (8.0 + (cw + 1.0) * w) * nc + w * lv[1].nc;
+        fused_down<Lv, R>(s, F, lv[1], true, s->vec[1], rscale, om, flag, st);
+        per = (8.0 + cb + w) * nc + w * lv[1].nc;
         break;
       default:
-        k_v_up3d<Lv, R, true><<<grf, ZF_TPB, 0, st>>>(F, lv[1], F.t, om, s->vec[2], nullptr, s->vec[1], rscale, zlf,
-                                                     flag);
-        per = ((cw + 1.0) * w + 16.0) * nc + w * lv[1].nc;
+        fused_up<Lv, R>(s, F, lv[1], true, s->vec[2], s->vec[1], rscale, om, flag, st);
+        per = (cb + w + 16.0) * nc + w * lv[1].nc;
         break;
     }
   };
@@ -2190,6 +2247,14 @@ vos_status vos_time_kernel(vos_sim *s, int family, int reps, double *avg_launch_
                                                      avg_launch_ms, bytes_per_launch);
     return time_z_kernel_t<MgLevel<double>, double>(s, s->mgd, s->nlev, kind, 6.0 / 7.0, 1.0 / s->p_scale, reps,
                                                      avg_launch_ms, bytes_per_launch);
+  }
+  if (family == VOS_KERNEL_M_DOWN3D || family == VOS_KERNEL_M_UP3D) {
+    const int kind = 4 + (family - VOS_KERNEL_M_DOWN3D);
+    if (s->opt.precision == VOS_MIXED)
+      return time_z_kernel_t<SLevel<float>, float>(s, s->smgf[0], s->snlev[0], kind, 0.85, 1.0, reps, avg_launch_ms,
+                                                   bytes_per_launch);
+    return time_z_kernel_t<SLevel<double>, double>(s, s->smgd[0], s->snlev[0], kind, 0.85, 1.0, reps, avg_launch_ms,
+                                                   bytes_per_launch);
   }
   if (family >= VOS_KERNEL_C_PRE3D && family <= VOS_KERNEL_C_UP3D)
     return time_z_kernel_t<SLevel<double>, double>(s, s->smgd[3], s->snlev[3], family - VOS_KERNEL_C_PRE3D, 0.85, 1.0,

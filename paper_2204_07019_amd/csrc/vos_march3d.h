@@ -159,7 +159,7 @@ __device__ __forceinline__ ZCoef<R> zcoef(const SLevel<R> &L, unsigned id, const
   ZCoef<R> k;
   k.d = L.diag[id];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) k.o[q] = L.off[(size_t)q * L.nc + id];
+  for (int q = 0; q < 6; ++q) k.o[q] = smg_off(L, q, id);
   return k;
 }
 
@@ -188,8 +188,50 @@ __device__ __forceinline__ ZCoef<R> zcoef_dg(const SLevel<R> &L, unsigned id, co
   ZCoef<R> k;
   k.d = dg;
 #pragma unroll
+  for (int q = 0; q < 6; ++q) k.o[q] = smg_off(L, q, id);
+  return k;
+}
+
+// The fused legs' coefficient loads: the level's own words (the FP32 copies
+// of an SLevel are loaded by the legs' FP32 variant itself, as raw words).
+template <typename R>
+__device__ __forceinline__ ZCoef<R> zcoef_own(const MgLevel<R> &L, unsigned id, const int c[3])
+{
+  return zcoef(L, id, c);
+}
+template <typename R>
+__device__ __forceinline__ ZCoef<R> zcoef_own(const SLevel<R> &L, unsigned id, const int *)
+{
+  ZCoef<R> k;
+  k.d = L.diag[id];
+#pragma unroll
   for (int q = 0; q < 6; ++q) k.o[q] = L.off[(size_t)q * L.nc + id];
   return k;
+}
+template <typename R>
+__device__ __forceinline__ ZCoef<R> zcoef_own_dg(const MgLevel<R> &L, unsigned id, const int c[3], R dg)
+{
+  return zcoef_dg(L, id, c, dg);
+}
+template <typename R>
+__device__ __forceinline__ ZCoef<R> zcoef_own_dg(const SLevel<R> &L, unsigned id, const int *, R dg)
+{
+  ZCoef<R> k;
+  k.d = dg;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) k.o[q] = L.off[(size_t)q * L.nc + id];
+  return k;
+}
+// FP32 off-diagonal copies of an SLevel as loaded (O32 variant of the fused legs).
+template <typename Lv>
+__device__ __forceinline__ void zoff32_load(const Lv &, unsigned, float (&)[6])
+{
+}
+template <typename R>
+__device__ __forceinline__ void zoff32_load(const SLevel<R> &L, unsigned id, float (&o)[6])
+{
+#pragma unroll
+  for (int q = 0; q < 6; ++q) o[q] = L.off32[(size_t)q * L.nc + id];
 }
 
 // Which neighbour slots exist.
@@ -577,8 +619,10 @@ __device__ __forceinline__ ZNb<R> znb2(const R (*pl)[ZH2_X], const R (*lo)[ZH2_X
 // RHS_R, or the level's b, RHS_B) and the residual restriction of
 // k_v_restrict3d, in one march.  Writes x (after the second sweep) and the
 // coarse b.  With RHS_R the level's b is not stored: the finest level's up leg
-// forms it again from the same residual by the same expression.  zlen even.
-template <typename Lv, typename R, int RHS>
+// forms it again from the same residual by the same expression.  O32: the
+// level's off-diagonals are read from its FP32 copies, carried as loaded and
+// widened after the plane's barrier.  zlen even.
+template <typename Lv, typename R, int RHS, bool O32>
 __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *__restrict__ r64, double rscale, R omega,
                                                   int zlen, const double *__restrict__ sc)
 {
@@ -632,7 +676,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
   // stage 1 for one cell at plane z: the second sweep (k_v_pre3d's expression);
   // its loads (load1) are issued before the plane's barrier, the arithmetic
   // (apply1) after it
-  struct S1 { R u; RB bb; R dg; ZCoef<R> k; };
+  struct S1 { R u; RB bb; R dg; ZCoef<R> k; float k32[6]; };
   auto load1 = [&](const ZCell &c, int z) -> S1 {
     S1 o;
     const bool ok = c.in && z >= 0 && z < nz;
@@ -640,7 +684,12 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
     o.bb = rhs_raw(id);
     o.dg = F.diag[id];
-    o.k = zcoef(F, id, cc);
+    if constexpr (O32) {
+      o.k.d = o.dg;
+      zoff32_load(F, id, o.k32);
+    } else {
+      o.k = zcoef_own(F, id, cc);
+    }
     o.u = (R)0;
     return o;
   };
@@ -653,11 +702,20 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
     o.bb = p.b[k];
     o.dg = p.d[k];
-    o.k = zcoef_dg(F, id, cc, p.d[k]);
+    if constexpr (O32) {
+      o.k.d = p.d[k];
+      zoff32_load(F, id, o.k32);
+    } else {
+      o.k = zcoef_own_dg(F, id, cc, p.d[k]);
+    }
     o.u = (R)0;
     return o;
   };
   auto apply1 = [&](const ZCell &c, int z, S1 &o) {
+    if constexpr (O32) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) o.k.o[q] = (R)o.k32[q];
+    }
     const bool ok = c.in && z >= 0 && z < nz;
     const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
     const R s = vpl[z & 3][c.hy][c.hx];
@@ -748,8 +806,8 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
 // and the second sweep of k_v_jacobi3d, in one march.  Writes the result to
 // xo, or with OUT64 (the finest level: the cycle's last sweep) only to the
 // FP64 output z; there the right-hand side is (R)(rscale r64), the down leg's
-// expression, since that leg did not store it.
-template <typename Lv, typename R, bool OUT64>
+// expression, since that leg did not store it.  O32 as in the down leg.
+template <typename Lv, typename R, bool OUT64, bool O32>
 __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z64,
                                                 const double *__restrict__ dsc, const double *__restrict__ r64,
                                                 double rscale, int zlen, const double *__restrict__ sc)
@@ -796,19 +854,28 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
     if constexpr (OUT64) return (R)(rscale * raw);
     else return raw;
   };
-  struct S1 { R u; ZCoef<R> k; RB b; };
+  struct S1 { R u; ZCoef<R> k; RB b; float k32[6]; };
   auto load1 = [&](const ZCell &c, int z) -> S1 {
     S1 o;
     const bool ok = c.in && z >= 0 && z < nz;
     const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
     const unsigned id = ok ? c.col + sz * (unsigned)z : 0u;
-    o.k = zcoef(F, id, cc);
+    if constexpr (O32) {
+      o.k.d = F.diag[id];
+      zoff32_load(F, id, o.k32);
+    } else {
+      o.k = zcoef_own(F, id, cc);
+    }
     if constexpr (OUT64) o.b = r64[id];
     else o.b = F.b[id];
     o.u = (R)0;
     return o;
   };
   auto apply1 = [&](const ZCell &c, int z, S1 &o) {
+    if constexpr (O32) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) o.k.o[q] = (R)o.k32[q];
+    }
     const bool ok = c.in && z >= 0 && z < nz;
     const int cc[3] = {ok ? c.gx : 0, ok ? c.gy : 0, ok ? z : 0};
     const R y = vpl[z & 3][c.hy][c.hx];

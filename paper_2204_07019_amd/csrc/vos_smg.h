@@ -27,7 +27,21 @@ struct SLevel {
   R *diag;
   R *x, *b, *t;
   R *dif;    // transport only (else nullptr): the diffusive part of each off-diagonal, 6 * nc
+  // FP32 copies of off (6 * nc) that the smoother and the cycle's residuals read
+  // instead, or nullptr.  Set on the finest level of the 3-D transport
+  // hierarchy in mixed precision: arithmetic, the diagonal and the Galerkin
+  // products (which read off) stay FP64.
+  float *off32;
 };
+
+// Off-diagonal of cell id towards neighbour slot k as the cycle's smoothing
+// and residual arithmetic reads it.
+template <typename R>
+__device__ __forceinline__ R smg_off(const SLevel<R> &L, int k, unsigned id)
+{
+  if (L.off32) return (R)L.off32[(size_t)k * L.nc + id];
+  return L.off[(size_t)k * L.nc + id];
+}
 
 // Piecewise-constant aggregation counts every diffusive coupling across a
 // coarse face from all the fine faces it covers, twice what the diffusion
@@ -49,7 +63,7 @@ __device__ __forceinline__ R smg_apply_cell(const SLevel<R> &L, int nd, const R 
   const R xc = x[id];
   const R xw = x[hw ? id - 1 : id], xe = x[he ? id + 1 : id];
   const R xs = x[hs ? id - sy : id], xn = x[hn ? id + sy : id];
-  const R ow = L.off[id], oe = L.off[nc + id], os = L.off[2 * nc + id], on = L.off[3 * nc + id];
+  const R ow = smg_off(L, 0, id), oe = smg_off(L, 1, id), os = smg_off(L, 2, id), on = smg_off(L, 3, id);
   R v = L.diag[id] * xc;
   v = hw ? v + ow * xw : v;
   v = he ? v + oe * xe : v;
@@ -59,7 +73,7 @@ __device__ __forceinline__ R smg_apply_cell(const SLevel<R> &L, int nd, const R 
     const unsigned sz = (unsigned)L.n[0] * L.n[1];
     const bool hb = c[2] > 0, ht = c[2] < L.n[2] - 1;
     const R xb = x[hb ? id - sz : id], xt = x[ht ? id + sz : id];
-    const R ob = L.off[4 * nc + id], ot = L.off[5 * nc + id];
+    const R ob = smg_off(L, 4, id), ot = smg_off(L, 5, id);
     v = hb ? v + ob * xb : v;
     v = ht ? v + ot * xt : v;
   }
@@ -81,8 +95,10 @@ __global__ void __launch_bounds__(TPB) k_smg_from_transport(unsigned nc, int nd,
     L.diag[id] = (R)d;
     for (int k = 0; k < 6; ++k) {
       const bool on = k < 2 * nd;
-      L.off[(size_t)k * nc + id] = on ? (R)(off64[(size_t)k * nc + id] * d) : (R)0;
+      const double o = off64[(size_t)k * nc + id] * d;
+      L.off[(size_t)k * nc + id] = on ? (R)o : (R)0;
       L.dif[(size_t)k * nc + id] = on ? (R)dif64[(size_t)k * nc + id] : (R)0;
+      if (L.off32) L.off32[(size_t)k * nc + id] = on ? (float)o : 0.0f;
     }
   }
 }

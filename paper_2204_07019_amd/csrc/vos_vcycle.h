@@ -70,7 +70,7 @@ template <typename R>
 __device__ __forceinline__ R lv_off(const SLevel<R> &L, unsigned id, const int c[3], int k)
 {
   (void)c;
-  return L.off[(size_t)k * L.nc + id];
+  return smg_off(L, k, id);
 }
 
 template <typename R>
@@ -596,7 +596,7 @@ __device__ __forceinline__ CCoef<R> ccoef(const MgLevel<R> &L, unsigned id, cons
 template <typename R>
 __device__ __forceinline__ CCoef<R> ccoef(const SLevel<R> &L, unsigned id, const int *)
 {
-  return CCoef<R>{L.diag[id], {L.off[id], L.off[L.nc + id], L.off[2 * L.nc + id], L.off[3 * L.nc + id]}};
+  return CCoef<R>{L.diag[id], {smg_off(L, 0, id), smg_off(L, 1, id), smg_off(L, 2, id), smg_off(L, 3, id)}};
 }
 
 template <typename R>

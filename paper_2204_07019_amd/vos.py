@@ -23,7 +23,8 @@ FP64, MIXED = 0, 1
 FREEZE_SOLID = 1
 KERNELS = {"v_restrict": 0, "v_post": 1, "v_pre": 2, "v_coarse": 3, "p_apply": 4, "adr_apply": 5,
            "v_down": 6, "v_up": 7, "p_pre3d": 8, "p_sweep3d": 9, "p_restrict3d": 10, "p_post3d": 11,
-           "c_pre3d": 12, "c_sweep3d": 13, "c_restrict3d": 14, "c_post3d": 15, "c_down3d": 16, "c_up3d": 17}
+           "c_pre3d": 12, "c_sweep3d": 13, "c_restrict3d": 14, "c_post3d": 15, "c_down3d": 16, "c_up3d": 17,
+           "m_down3d": 18, "m_up3d": 19}
 FIELDS = {"eps": 0, "ux": 1, "uy": 2, "uz": 3, "p": 4, "c": 5, "ustar_x": 6, "ustar_y": 7,
           "ustar_z": 8, "rbar": 9, "gmag": 10, "pdiag": 11}
 

@@ -146,10 +146,17 @@ void run_levels(const char *name, std::vector<Lv> &lv)
       for (int slots : {256, 768}) {
         const int zf = zrun_len_fused(F.n, slots);
         const unsigned nf = zrun_blocks_fused(F.n, zf);
-        launch(nf, [&] { k_v_down3d<Lv, R, RHS_R>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
-        launch(nf, [&] { k_v_down3d<Lv, R, RHS_B>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
-        launch(nf, [&] { k_v_up3d<Lv, R, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZF_TPB);
-        launch(nf, [&] { k_v_up3d<Lv, R, false>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zf, sc); }, ZF_TPB);
+        launch(nf, [&] { k_v_down3d<Lv, R, RHS_R, false>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+        launch(nf, [&] { k_v_down3d<Lv, R, RHS_B, false>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+        launch(nf, [&] { k_v_up3d<Lv, R, true, false>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZF_TPB);
+        launch(nf, [&] { k_v_up3d<Lv, R, false, false>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zf, sc); },
+               ZF_TPB);
+        if constexpr (std::is_same<Lv, SLevel<double>>::value) {
+          if (F.off32) {   // the variant reading the FP32 off-diagonal copies
+            launch(nf, [&] { k_v_down3d<Lv, R, RHS_R, true>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+            launch(nf, [&] { k_v_up3d<Lv, R, true, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZF_TPB);
+          }
+        }
       }
       const int zf = zrun_len_fused(F.n, 768);
       const unsigned nf = zrun_blocks_fused(F.n, zf);
@@ -209,6 +216,14 @@ int main(int argc, char **argv)
       Arrays<double> A;
       auto lv = s_levels(A, nx, ny, nz);
       run_levels<SLevel<double>, double>("transport FP64", lv);
+    }
+    {
+      // mixed precision: the finest level's smoothing reads FP32 off-diagonal copies
+      Arrays<double> A;
+      Arrays<float> A32;
+      auto lv = s_levels(A, nx, ny, nz);
+      lv[0].off32 = A32.make(6 * (size_t)lv[0].nc);
+      run_levels<SLevel<double>, double>("transport FP64, FP32 finest off-diagonals", lv);
     }
     const int fn[3][3] = {{nx + 1, ny, nz}, {nx, ny + 1, nz}, {nx, ny, nz + 1}};
     for (int d = 0; d < 3; ++d) {
