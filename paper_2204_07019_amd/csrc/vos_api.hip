@@ -124,8 +124,9 @@ struct SmgPlan {
   int n[SMG_MAX_LEVELS][3];
   size_t off[SMG_MAX_LEVELS], diag[SMG_MAX_LEVELS], x[SMG_MAX_LEVELS], b[SMG_MAX_LEVELS], t[SMG_MAX_LEVELS];
   size_t dif[SMG_MAX_LEVELS];   // diffusive parts (transport hierarchy only)
-  size_t off32;                 // FP32 off-diagonals of the finest level (when has32)
-  bool split, has32;
+  size_t off32[SMG_MAX_LEVELS];   // FP32 off-diagonal copies of the level (when has32)
+  bool has32[SMG_MAX_LEVELS];
+  bool split;
   size_t ainv;
 };
 
@@ -154,8 +155,7 @@ void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs, bo
   int n[3] = {nx, ny, nz};
   S.nlev = 0;
   S.split = split;
-  S.has32 = off32;
-  S.off32 = off32 ? P.take(6 * (size_t)nx * ny * nz * sizeof(float)) : 0;
+
   while (S.nlev < SMG_MAX_LEVELS) {
     const int l = S.nlev++;
     for (int d = 0; d < 3; ++d) S.n[l][d] = n[d];
@@ -166,6 +166,9 @@ void plan_smg(Plan &P, SmgPlan &S, int nx, int ny, int nz, int nd, size_t rs, bo
     S.b[l] = P.take(nc * rs);
     S.t[l] = P.take(nc * rs);
     S.dif[l] = split ? P.take(6 * nc * rs) : 0;
+    // FP32 copies on the levels that run the fused legs
+    S.has32[l] = off32 && zfused_level(n);
+    S.off32[l] = S.has32[l] ? P.take(6 * nc * sizeof(float)) : 0;
     if (nc <= (size_t)SMG_COARSE_MAX) break;
     for (int d = 0; d < nd; ++d) n[d] = (n[d] + 1) / 2;
   }
@@ -234,8 +237,9 @@ Layout make_layout(const vos_grid &g, int precision)
   }
   // the transport hierarchy is FP64 in both precisions: its Galerkin coarse
   // diagonals of upwind-dominated rows cancel to near zero and break down in
-  // FP32.  In mixed precision its finest 3-D level's smoothing reads FP32
-  // copies of the off-diagonals (FP64 arithmetic, FP64 diagonal).
+  // FP32.  In mixed precision the smoothing of its 3-D levels of >= 2^20
+  // cells reads FP32 copies of their off-diagonals (FP64 arithmetic, FP64
+  // diagonal, FP64 Galerkin products).
   plan_smg(P, Lo.smg[3], g.nx, g.ny, g.nz, nd, sizeof(double), true, precision == VOS_MIXED && nd == 3);
   Lo.total = P.off;
   return Lo;
@@ -377,7 +381,7 @@ void fill_smg(vos_sim *s, int h, SLevel<R> *lv)
     L.b = (R *)(s->ws + S.b[l]);
     L.t = (R *)(s->ws + S.t[l]);
     L.dif = S.split ? (R *)(s->ws + S.dif[l]) : nullptr;
-    L.off32 = l == 0 && S.has32 ? (float *)(s->ws + S.off32) : nullptr;
+    L.off32 = S.has32[l] ? (float *)(s->ws + S.off32[l]) : nullptr;
   }
   if (S.nlev) s->sainv[h] = (double *)(s->ws + S.ainv);
 }

@@ -28,9 +28,9 @@ struct SLevel {
   R *x, *b, *t;
   R *dif;    // transport only (else nullptr): the diffusive part of each off-diagonal, 6 * nc
   // FP32 copies of off (6 * nc) that the smoother and the cycle's residuals read
-  // instead, or nullptr.  Set on the finest level of the 3-D transport
-  // hierarchy in mixed precision: arithmetic, the diagonal and the Galerkin
-  // products (which read off) stay FP64.
+  // instead, or nullptr.  Set on the levels of >= 2^20 cells of the 3-D
+  // transport hierarchy in mixed precision: arithmetic, the diagonal and the
+  // Galerkin products (which read off) stay FP64.
   float *off32;
 };
 
@@ -199,6 +199,8 @@ __global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C)
     }
     C.diag[I] = dg;
     for (int k = 0; k < 6; ++k) C.off[(size_t)k * C.nc + I] = o[k];
+    if (C.off32)
+      for (int k = 0; k < 6; ++k) C.off32[(size_t)k * C.nc + I] = (float)o[k];
   }
 }
 

@@ -218,12 +218,14 @@ int main(int argc, char **argv)
       run_levels<SLevel<double>, double>("transport FP64", lv);
     }
     {
-      // mixed precision: the finest level's smoothing reads FP32 off-diagonal copies
+      // mixed precision: the levels that run the fused legs smooth with FP32
+      // off-diagonal copies (the finest level always carries them here)
       Arrays<double> A;
       Arrays<float> A32;
       auto lv = s_levels(A, nx, ny, nz);
-      lv[0].off32 = A32.make(6 * (size_t)lv[0].nc);
-      run_levels<SLevel<double>, double>("transport FP64, FP32 finest off-diagonals", lv);
+      for (size_t l = 0; l < lv.size(); ++l)
+        if (l == 0 || zfused_level(lv[l].n)) lv[l].off32 = A32.make(6 * (size_t)lv[l].nc);
+      run_levels<SLevel<double>, double>("transport FP64, FP32 off-diagonal copies", lv);
     }
     const int fn[3][3] = {{nx + 1, ny, nz}, {nx, ny + 1, nz}, {nx, ny, nz + 1}};
     for (int d = 0; d < 3; ++d) {
