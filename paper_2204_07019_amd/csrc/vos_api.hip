@@ -1001,9 +1001,9 @@ vos_status solve_momentum_t(vos_sim *s, const Lane &ln, SLevel<R> *lv, double dt
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->dmom[D], r, z, pv, 0, part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, part, nb, rt2, sc);
   smg_vcycle<R>(s, D, lv, r, z, sc, st);
-  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, part, sc);
+  // the first direction is z (written here; unused when the start has converged)
+  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, part, sc, pv);
   k_cg_scal<<<1, TPB, 0, st>>>(5, part, nb, rt2, sc);
-  HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
     k_mom_apply<D><<<nb, TPB, 0, st>>>(g, cvis, s->dmom[D], pv, q, part, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(1, part, nb, rt2, sc);
@@ -1298,9 +1298,9 @@ vos_status solve_pressure_t(vos_sim *s, MgLevel<R> *lv, int gid, int h, int *its
   k_cg_init<<<nb, TPB, 0, st>>>(n, b, q, s->pdiag, r, z, pv, 0, s->part);
   k_cg_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
   mg_vcycle<R>(s, lv, r, z, sc);
-  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc);
+  // the first direction is z (written here; unused when the start has converged)
+  k_cg_zdots<<<nb, TPB, 0, st>>>(n, z, r, q, s->part, sc, pv);
   k_cg_scal<<<1, TPB, 0, st>>>(5, s->part, nb, rt2, sc);
-  HIP_TRY(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   auto iter = [&]() {
     const int nbq = p_apply(s, pv, q, sc);
     k_cg_scal<<<1, TPB, 0, st>>>(1, s->part, nbq, rt2, sc);

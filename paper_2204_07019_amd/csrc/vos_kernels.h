@@ -819,16 +819,19 @@ __global__ void __launch_bounds__(TPB) k_cg_xr(unsigned n, const double *__restr
   write_partials<1>(v, part);
 }
 
-// Partials z.r and z.q (flexible CG after a non-Jacobi preconditioner).
+// Partials z.r and z.q (flexible CG after a non-Jacobi preconditioner); with
+// p (the start of a solve) also the first direction p = z.
 __global__ void __launch_bounds__(TPB) k_cg_zdots(unsigned n, const double *__restrict__ z, const double *__restrict__ r,
                                                   const double *__restrict__ q, double *__restrict__ part,
-                                                  const double *__restrict__ sc)
+                                                  const double *__restrict__ sc, double *__restrict__ p = nullptr)
 {
   if (sc[S_CONV] != 0.0) return;
   double zr = 0.0, zq = 0.0;
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
-    zr += z[i] * r[i];
-    zq += z[i] * q[i];
+    const double zi = z[i];
+    if (p) p[i] = zi;
+    zr += zi * r[i];
+    zq += zi * q[i];
   }
   const double v[2] = {zr, zq};
   write_partials<2>(v, part);
