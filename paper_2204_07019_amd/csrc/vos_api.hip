@@ -1394,8 +1394,9 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *
   hipStream_t st = s->stream;
   const unsigned n = g.nc;
   const int nb = grid_blocks(n);
-  double *b = s->vec[0], *r = s->vec[1], *rh = s->vec[2], *pv = s->vec[3], *v = s->vec[4], *sv = s->vec[5],
-         *t = s->vec[6], *y = s->vec[7], *ph = s->vec[8], *sh = s->vec[9];
+  // the shadow residual rh is a hash of the cell index, formed where it is read
+  double *b = s->vec[0], *r = s->vec[1], *pv = s->vec[3], *v = s->vec[4], *sv = s->vec[5], *t = s->vec[6],
+         *y = s->vec[7], *ph = s->vec[8], *sh = s->vec[9];
   double *sc = sc_block(s, SC_C);
   double *zero_flag = sc_block(s, SC_MISC) + S_COUNT;
   const int H = 3;
@@ -1415,7 +1416,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *
   k_smg_from_transport<R><<<nb, TPB, 0, st>>>(n, g.nd, s->off, s->tdiag, s->tdif, lv[0]);
   smg_coarsen_all<R>(s, H, lv, st);
   k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, s->c, y, s->c, s->part, zero_flag);
-  k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
+  k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, nullptr, pv, v, s->part);
   k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
   // the directions times the row diagonal, the input of the cycle built on the
   // unscaled rows (y is free after the start; b stays for the true residual)
@@ -1423,14 +1424,14 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, pd, s->tdiag, sc);
     smg_vcycle<R>(s, H, lv, pd, ph, sc, st);
-    k_adr_apply<1><<<nb, TPB, 0, st>>>(g, s->off, ph, v, rh, s->part, sc);
+    k_adr_apply<1, true><<<nb, TPB, 0, st>>>(g, s->off, ph, v, nullptr, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, sd, s->tdiag, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
     smg_vcycle<R>(s, H, lv, sd, sh, sc, st);
     k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
-    k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, rh, s->c, r, s->part, sc);
+    k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, s->c, r, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(4, s->part, nb, rt2, sc);
   };
   double res2, tol2;
@@ -1449,7 +1450,7 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *
     if (vos_status e = read_back(s, sc, S_COUNT)) return e;
     if (s->host[S_TRUE] <= s->host[S_TOL2]) { res2 = s->host[S_TRUE]; break; }
     int more = 0;
-    k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, rh, pv, v, s->part);
+    k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, nullptr, pv, v, s->part);
     k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
     stt = krylov_loop(s, main_lane(s), 4, sc, std::max(1, s->opt.maxit_c - *its), iter, &more, &res2, &tol2, &conv);
     if (stt) return stt;

@@ -587,9 +587,21 @@ __global__ void __launch_bounds__(TPB) k_adr_assemble(Dev g, Phys P, const doubl
   }
 }
 
+// splitmix64 (Steele, Lea & Flood 2014) of counter i, as a double in [-1, 1).
+__device__ __forceinline__ double splitmix_unit(unsigned long long i)
+{
+  unsigned long long z = (i + 1ULL) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
 // y = A x for the scaled transport rows (unit diagonal), with up to two dot
 // partials: slot 0 <y, w>, slot 1 <y, y> (NDOT = 1 or 2, w may be y's partner).
-template <int NDOT>
+// HW: w is BiCGStab's shadow residual splitmix_unit(cell), formed in place
+// (the w argument is not read).
+template <int NDOT, bool HW = false>
 __global__ void __launch_bounds__(TPB) k_adr_apply(Dev g, const double *__restrict__ off, const double *__restrict__ xv,
                                                    double *__restrict__ y, const double *__restrict__ w,
                                                    double *__restrict__ part, const double *__restrict__ sc)
@@ -611,7 +623,7 @@ __global__ void __launch_bounds__(TPB) k_adr_apply(Dev g, const double *__restri
       if (x[2] < g.n[2] - 1) v += off[5 * (size_t)g.nc + id] * xv[id + sz];
     }
     y[id] = v;
-    d0 += v * w[id];
+    d0 += v * (HW ? splitmix_unit(id) : w[id]);
     if (NDOT == 2) d1 += v * v;
   }
   if (NDOT == 1) { const double vv[1] = {d0}; write_partials<1>(vv, part); }
@@ -893,16 +905,6 @@ __global__ void k_cg_scal(int op, const double *__restrict__ part, int nb, doubl
 
 // ---------------------------------------------------------------- BiCGStab vector kernels
 
-// splitmix64 (Steele, Lea & Flood 2014) of counter i, as a double in [-1, 1).
-__device__ __forceinline__ double splitmix_unit(unsigned long long i)
-{
-  unsigned long long z = (i + 1ULL) * 0x9E3779B97F4A7C15ULL;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  z = z ^ (z >> 31);
-  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
-}
-
 // r = b - y; rh = fixed pseudo-random shadow residual (global support, so
 // rh.r cannot vanish as a cold-start residual travels downstream); p = v = 0;
 // partials b.b, r.r, rh.r
@@ -914,7 +916,8 @@ __global__ void __launch_bounds__(TPB) k_bi_init(unsigned n, const double *__res
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double ri = b[i] - y[i];
     const double h = splitmix_unit(i);
-    r[i] = ri; rh[i] = h; p[i] = 0.0; v[i] = 0.0;
+    r[i] = ri; p[i] = 0.0; v[i] = 0.0;
+    if (rh) rh[i] = h;
     bb += b[i] * b[i];
     rr += ri * ri;
     hr += h * ri;
@@ -957,12 +960,12 @@ __global__ void __launch_bounds__(TPB) k_bi_s(unsigned n, const double *__restri
 }
 
 // x += alpha ph + omega sh; r = s - omega t (or only x += alpha ph after an
-// early exit on s); partials r.r, rh.r.  ph, sh: preconditioned directions.
+// early exit on s); partials r.r, rh.r with rh the shadow residual
+// splitmix_unit(i), formed in place.  ph, sh: preconditioned directions.
 __global__ void __launch_bounds__(TPB) k_bi_xr(unsigned n, const double *__restrict__ ph, const double *__restrict__ sh,
                                                const double *__restrict__ s, const double *__restrict__ t,
-                                               const double *__restrict__ rh, double *__restrict__ x,
-                                               double *__restrict__ r, double *__restrict__ part,
-                                               double *__restrict__ sc)
+                                               double *__restrict__ x, double *__restrict__ r,
+                                               double *__restrict__ part, double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   const double al = sc[S_ALPHA], om = sc[S_OMEGA];
@@ -974,7 +977,7 @@ __global__ void __launch_bounds__(TPB) k_bi_xr(unsigned n, const double *__restr
     const double ri = s[i] - om * t[i];
     r[i] = ri;
     rr += ri * ri;
-    rhr += rh[i] * ri;
+    rhr += splitmix_unit(i) * ri;
   }
   const double vv[2] = {rr, rhr};
   write_partials<2>(vv, part);
