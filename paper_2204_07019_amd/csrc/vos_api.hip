@@ -749,7 +749,6 @@ void launch_coarse(int c0, const LevelPack<Lv> &pack, int lc, int L, int nd, int
   else k_v_coarse_cycle<Lv, R><<<1, VC_COARSE_TPB, 0, st>>>(pack, lc, L, nd, nu, om, Ainv, sc);
 }
 
-// z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
 // Blocks a CU holds at once of the fused legs of one level type (their LDS and
 // registers decide it; queried once per instantiation), times the CUs.
 template <typename Lv, typename R, bool O32>
@@ -791,51 +790,81 @@ bool lv_has32(const SLevel<R> &L)
 // The fused legs of level F (coarse level C): the down leg from the FP64
 // residual r (finest level, RHS_R) or from F's b; the up leg into the FP64
 // output z (finest level) or into F.t.
+// rg: the finest level's input is r times its diagonal (RHS_RG); only the
+// FP64 aggregation levels (the transport hierarchy) take it.
 template <typename Lv, typename R, bool O32>
 void fused_down_t(vos_sim *s, const Lv &F, const Lv &C, bool finest, const double *r, double rscale, R om,
-                  const double *sc, hipStream_t st)
+                  const double *sc, hipStream_t st, bool rg)
 {
   const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s));
   const dim3 gr(zrun_blocks_fused(F.n, zl));
+  if constexpr (lv_can32<Lv>) {
+    if (finest && rg) return (void)(k_v_down3d<Lv, R, RHS_RG, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, 1.0, om, zl, sc));
+  }
   if (finest) k_v_down3d<Lv, R, RHS_R, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, rscale, om, zl, sc);
   else k_v_down3d<Lv, R, RHS_B, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, rscale, om, zl, sc);
 }
 template <typename Lv, typename R, bool O32>
 void fused_up_t(vos_sim *s, const Lv &F, const Lv &C, bool finest, double *z, const double *r, double rscale, R om,
-                const double *sc, hipStream_t st)
+                const double *sc, hipStream_t st, bool rg)
 {
   const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s));
   const dim3 gr(zrun_blocks_fused(F.n, zl));
+  if constexpr (lv_can32<Lv>) {
+    if (finest && rg)
+      return (void)(k_v_up3d<Lv, R, true, O32, true><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, z, nullptr, r, 1.0, zl,
+                                                                              sc));
+  }
   if (finest) k_v_up3d<Lv, R, true, O32><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, z, nullptr, r, rscale, zl, sc);
   else k_v_up3d<Lv, R, false, O32><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zl, sc);
 }
 template <typename Lv, typename R>
 void fused_down(vos_sim *s, const Lv &F, const Lv &C, bool finest, const double *r, double rscale, R om,
-                const double *sc, hipStream_t st)
+                const double *sc, hipStream_t st, bool rg = false)
 {
   if constexpr (lv_can32<Lv>) {
-    if (lv_has32(F)) return fused_down_t<Lv, R, true>(s, F, C, finest, r, rscale, om, sc, st);
+    if (lv_has32(F)) return fused_down_t<Lv, R, true>(s, F, C, finest, r, rscale, om, sc, st, rg);
   }
-  fused_down_t<Lv, R, false>(s, F, C, finest, r, rscale, om, sc, st);
+  fused_down_t<Lv, R, false>(s, F, C, finest, r, rscale, om, sc, st, rg);
 }
 template <typename Lv, typename R>
 void fused_up(vos_sim *s, const Lv &F, const Lv &C, bool finest, double *z, const double *r, double rscale, R om,
-              const double *sc, hipStream_t st)
+              const double *sc, hipStream_t st, bool rg = false)
 {
   if constexpr (lv_can32<Lv>) {
-    if (lv_has32(F)) return fused_up_t<Lv, R, true>(s, F, C, finest, z, r, rscale, om, sc, st);
+    if (lv_has32(F)) return fused_up_t<Lv, R, true>(s, F, C, finest, z, r, rscale, om, sc, st, rg);
   }
-  fused_up_t<Lv, R, false>(s, F, C, finest, z, r, rscale, om, sc, st);
+  fused_up_t<Lv, R, false>(s, F, C, finest, z, r, rscale, om, sc, st, rg);
 }
 
+// First level of a hierarchy's coarse tail (the levels of at most coarse_cells).
+template <typename Lv>
+int coarse_start(const vos_sim *s, const Lv *lv, int L)
+{
+  int lc = 0;
+  while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
+  return lc;
+}
+
+// Level F of a V-cycle with nu sweeps a leg runs the fused 3-D legs.
+template <typename Lv>
+bool fused_level(const vos_sim *s, const Lv &F, int nu, const double *dsc)
+{
+  return s->opt.level_kernels == 0 && s->g.nd == 3 && F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2 && nu == 2 &&
+         !dsc && zfused_level(F.n);
+}
+
+// z = V-cycle(r) on a hierarchy of L levels (generic over the level type).
+// rg: the input is r d with d the finest level's diagonal, formed by the
+// finest level's fused legs from r (callers pass it only where
+// fused_level holds for that level, which precedes the coarse tail).
 template <typename Lv, typename R>
 void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, double *z, const double *sc,
-            double omega, const double *dsc, double rscale, int nu, hipStream_t st)
+            double omega, const double *dsc, double rscale, int nu, hipStream_t st, bool rg = false)
 {
   const int nd = s->g.nd;
   const R om = (R)omega;
-  int lc = 0;
-  while (lc < L - 1 && lv[lc].nc > (unsigned)s->coarse_cells) ++lc;
+  const int lc = coarse_start(s, lv, L);
   const bool fused = s->opt.level_kernels == 0;
   // 2-D levels with 2..4 sweeps each way: one tiled kernel per leg (vos_vcycle.h)
   auto tiled = [&](const Lv &F) { return fused && nd == 2 && nu >= 2 && nu <= 4 && F.n[0] >= 2 && F.n[1] >= 2; };
@@ -845,9 +874,9 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   for (int l = 0; l < lc; ++l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
-    if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
+    if (fused_level(s, F, nu, dsc)) {
       // both pre-sweeps and the restriction in one march
-      fused_down<Lv, R>(s, F, lv[l + 1], l == 0, r, rscale, om, sc, st);
+      fused_down<Lv, R>(s, F, lv[l + 1], l == 0, r, rscale, om, sc, st, rg && l == 0);
       continue;
     }
     if (zmarch(F)) {
@@ -907,9 +936,9 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   for (int l = lc - 1; l >= 0; --l) {
     Lv &F = lv[l];
     const int nb = grid_blocks(F.nc);
-    if (zmarch(F) && nu == 2 && !dsc && zfused_level(F.n)) {
+    if (fused_level(s, F, nu, dsc)) {
       // prolongation and both post-sweeps in one march
-      fused_up<Lv, R>(s, F, lv[l + 1], l == 0, z, r, rscale, om, sc, st);
+      fused_up<Lv, R>(s, F, lv[l + 1], l == 0, z, r, rscale, om, sc, st, rg && l == 0);
       if (l > 0) std::swap(F.x, F.t);
       continue;
     }
@@ -964,9 +993,17 @@ int sweeps(const vos_sim *s, int h) { return h == 3 ? std::min(2, s->opt.mg_nu) 
 // z = cycle(r) on hierarchy h, whose level 0 is the unscaled operator (the
 // transport caller passes its row-scaled directions times the row diagonal).
 template <typename R>
-void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, hipStream_t st)
+void smg_vcycle(vos_sim *s, int h, SLevel<R> *lv, const double *r, double *z, const double *sc, hipStream_t st,
+                bool rg = false)
 {
-  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.85, nullptr, 1.0, sweeps(s, h), st);
+  vcycle<SLevel<R>, R>(s, lv, s->snlev[h], s->sainv[h], r, z, sc, 0.85, nullptr, 1.0, sweeps(s, h), st, rg);
+}
+
+// The V-cycle of aggregation hierarchy h runs its finest level's fused legs.
+template <typename R>
+bool smg_finest_fused(const vos_sim *s, int h, const SLevel<R> *lv)
+{
+  return coarse_start(s, lv, s->snlev[h]) > 0 && fused_level(s, lv[0], sweeps(s, h), nullptr);
 }
 
 // ---------------------------------------------------------------- stage S2
@@ -1419,16 +1456,19 @@ vos_status solve_transport_t(vos_sim *s, SLevel<R> *lv, double dt, int vl, int *
   k_bi_init<<<nb, TPB, 0, st>>>(n, b, y, r, nullptr, pv, v, s->part);
   k_bi_scal<<<1, TPB, 0, st>>>(0, s->part, nb, rt2, sc);
   // the directions times the row diagonal, the input of the cycle built on the
-  // unscaled rows (y is free after the start; b stays for the true residual)
-  double *pd = s->vec[10], *sd = y;
+  // unscaled rows (y is free after the start; b stays for the true residual);
+  // where the cycle's finest level runs the fused legs they form it from the
+  // directions and the level's diagonal (= the row diagonal) themselves
+  const bool rg = smg_finest_fused(s, H, lv);
+  double *pd = rg ? nullptr : s->vec[10], *sd = rg ? nullptr : y;
   auto iter = [&]() {
     k_bi_p<<<nb, TPB, 0, st>>>(n, r, v, pv, pd, s->tdiag, sc);
-    smg_vcycle<R>(s, H, lv, pd, ph, sc, st);
+    smg_vcycle<R>(s, H, lv, rg ? pv : pd, ph, sc, st, rg);
     k_adr_apply<1, true><<<nb, TPB, 0, st>>>(g, s->off, ph, v, nullptr, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(1, s->part, nb, rt2, sc);
     k_bi_s<<<nb, TPB, 0, st>>>(n, r, v, sv, sd, s->tdiag, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(2, s->part, nb, rt2, sc);
-    smg_vcycle<R>(s, H, lv, sd, sh, sc, st);
+    smg_vcycle<R>(s, H, lv, rg ? sv : sd, sh, sc, st, rg);
     k_adr_apply<2><<<nb, TPB, 0, st>>>(g, s->off, sh, t, sv, s->part, sc);
     k_bi_scal<<<1, TPB, 0, st>>>(3, s->part, nb, rt2, sc);
     k_bi_xr<<<nb, TPB, 0, st>>>(n, ph, sh, sv, t, s->c, r, s->part, sc);
@@ -1906,7 +1946,7 @@ double coef_bytes(const SLevel<R> &L) { return sizeof(R) + 6.0 * (L.off32 ? size
 
 template <typename Lv, typename R>
 vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega, double rscale, int reps, double *ms,
-                           double *bytes)
+                           double *bytes, bool rg = false)
 {
   hipStream_t st = s->stream;
   if (s->g.nd != 3 || nlev < 2) return fail(VOS_ERR_ARG, "the z-marching level families time 3-D hierarchies");
@@ -1939,11 +1979,11 @@ vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega,
         per = (cb + 3.0 * w) * nc + w * lv[1].nc;
         break;
       case 4:
-        fused_down<Lv, R>(s, F, lv[1], true, s->vec[1], rscale, om, flag, st);
+        fused_down<Lv, R>(s, F, lv[1], true, s->vec[1], rscale, om, flag, st, rg);
         per = (8.0 + cb + w) * nc + w * lv[1].nc;
         break;
       default:
-        fused_up<Lv, R>(s, F, lv[1], true, s->vec[2], s->vec[1], rscale, om, flag, st);
+        fused_up<Lv, R>(s, F, lv[1], true, s->vec[2], s->vec[1], rscale, om, flag, st, rg);
         per = (cb + w + 16.0) * nc + w * lv[1].nc;
         break;
     }
@@ -2263,7 +2303,8 @@ vos_status vos_time_kernel(vos_sim *s, int family, int reps, double *avg_launch_
   }
   if (family >= VOS_KERNEL_C_PRE3D && family <= VOS_KERNEL_C_UP3D)
     return time_z_kernel_t<SLevel<double>, double>(s, s->smgd[3], s->snlev[3], family - VOS_KERNEL_C_PRE3D, 0.85, 1.0,
-                                                    reps, avg_launch_ms, bytes_per_launch);
+                                                    reps, avg_launch_ms, bytes_per_launch,
+                                                    smg_finest_fused(s, 3, s->smgd[3]));
   return time_kernel_t<double>(s, s->smgd[3], family, reps, avg_launch_ms, bytes_per_launch);
 }
 

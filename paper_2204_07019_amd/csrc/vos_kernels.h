@@ -926,7 +926,8 @@ __global__ void __launch_bounds__(TPB) k_bi_init(unsigned n, const double *__res
   write_partials<3>(vv, part);
 }
 
-// p = r + beta (p - omega v); pd = p dg (the preconditioner's input)
+// p = r + beta (p - omega v); pd = p dg (the preconditioner's input; not
+// stored when pd is null)
 __global__ void __launch_bounds__(TPB) k_bi_p(unsigned n, const double *__restrict__ r, const double *__restrict__ v,
                                               double *__restrict__ p, double *__restrict__ pd,
                                               const double *__restrict__ dg, const double *__restrict__ sc)
@@ -936,11 +937,12 @@ __global__ void __launch_bounds__(TPB) k_bi_p(unsigned n, const double *__restri
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double pi = r[i] + beta * (p[i] - om * v[i]);
     p[i] = pi;
-    pd[i] = pi * dg[i];
+    if (pd) pd[i] = pi * dg[i];
   }
 }
 
-// s = r - alpha v, sd = s dg (the preconditioner's input), partial s.s
+// s = r - alpha v, sd = s dg (the preconditioner's input; not stored when sd
+// is null), partial s.s
 __global__ void __launch_bounds__(TPB) k_bi_s(unsigned n, const double *__restrict__ r, const double *__restrict__ v,
                                               double *__restrict__ s, double *__restrict__ sd,
                                               const double *__restrict__ dg, double *__restrict__ part,
@@ -952,7 +954,7 @@ __global__ void __launch_bounds__(TPB) k_bi_s(unsigned n, const double *__restri
   for (unsigned i = xbeg(n); i < xend(n); i += xstride()) {
     const double si = r[i] - al * v[i];
     s[i] = si;
-    sd[i] = si * dg[i];
+    if (sd) sd[i] = si * dg[i];
     ss += si * si;
   }
   const double vv[1] = {ss};

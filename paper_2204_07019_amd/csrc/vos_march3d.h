@@ -401,8 +401,21 @@ __global__ void __launch_bounds__(TPB) k_v_jacobi3d(Lv L, const R *__restrict__ 
 
 // Right-hand side of a pre-smoothing kernel: the level's b (RHS_B), or on
 // level 0 the FP64 residual (R)(rscale r) (RHS_R) or (R)(rscale r / sqrt(dsc))
-// (RHS_RD) -- k_v_pre's FROM64 expression with the dsc test taken on the host.
-enum { RHS_B = 0, RHS_R = 1, RHS_RD = 2 };
+// (RHS_RD) -- k_v_pre's FROM64 expression with the dsc test taken on the host
+// -- or, in the fused legs only, the FP64 vector r times the level's own
+// diagonal, (R)(r d) (RHS_RG: the cycle's input formed where the diagonal is
+// already loaded; the product is rounded on its own, never contracted into a
+// later fused multiply-add, so it is bitwise the vector r d that the caller
+// would otherwise store).
+enum { RHS_B = 0, RHS_R = 1, RHS_RD = 2, RHS_RG = 3 };
+
+// a b rounded to FP64 on its own: the product never enters a fused
+// multiply-add with the arithmetic that consumes it.
+__device__ __forceinline__ double mul_rounded(double a, double b)
+{
+#pragma clang fp contract(off)
+  return a * b;
+}
 
 // Pre-smoothing sweeps 1 and 2 (k_v_pre with two sweeps).
 template <typename Lv, typename R, int RHS>
@@ -626,7 +639,7 @@ template <typename Lv, typename R, int RHS, bool O32>
 __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *__restrict__ r64, double rscale, R omega,
                                                   int zlen, const double *__restrict__ sc)
 {
-  static_assert(RHS == RHS_R || RHS == RHS_B, "no diagonal scaling in the fused leg");
+  static_assert(RHS == RHS_R || RHS == RHS_B || RHS == RHS_RG, "no dsc scaling in the fused leg");
   if (sc[S_CONV] != 0.0) return;
   ZTile t;
   if (!zftile_of(F.n, zlen, t)) return;
@@ -636,16 +649,18 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
   const int nz = F.n[2];
   const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
   const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
-  // the right-hand side as loaded (the FP64 residual or the level's b) and as
-  // used, (R)(rscale r) or b: loads carry the raw word, so that no arithmetic
-  // ahead of a plane's barrier waits for them
-  using RB = typename std::conditional<RHS == RHS_R, double, R>::type;
+  // the right-hand side as loaded (the FP64 vector r or the level's b) and as
+  // used with the cell's diagonal d, (R)(rscale r), (R)(r d) or b: loads carry
+  // the raw word, so that no arithmetic ahead of a plane's barrier waits for them
+  constexpr bool R64 = RHS == RHS_R || RHS == RHS_RG;
+  using RB = typename std::conditional<R64, double, R>::type;
   auto rhs_raw = [&](unsigned id) -> RB {
-    if constexpr (RHS == RHS_R) return r64[id];
+    if constexpr (R64) return r64[id];
     else return F.b[id];
   };
-  auto rhs = [&](RB raw) -> R {
+  auto rhs = [&](RB raw, R d) -> R {
     if constexpr (RHS == RHS_R) return (R)(rscale * raw);
+    else if constexpr (RHS == RHS_RG) return (R)mul_rounded(raw, (double)d);
     else return raw;
   };
   // stage 0: v = omega b / d (the first sweep from x = 0), 0 outside the level.
@@ -669,7 +684,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     const bool zin = z >= 0 && z < nz;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const R v = omega * rhs(p.b[k]) / p.d[k];
+      const R v = omega * rhs(p.b[k], p.d[k]) / p.d[k];
       if (cs[k]->has) vpl[s][cs[k]->hy][cs[k]->hx] = cs[k]->in && zin ? v : (R)0;
     }
   };
@@ -721,7 +736,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     const R s = vpl[z & 3][c.hy][c.hx];
     const ZNb<R> nb = znb2<R>(vpl[z & 3], vpl[(z - 1) & 3], vpl[(z + 1) & 3], c.hx, c.hy);
     const R ax = zapply_off<Lv, R>(F, zhas(F.n, cc), o.k, o.dg, s, nb);
-    o.u = ok ? s + omega * (rhs(o.bb) - ax) / o.dg : (R)0;
+    o.u = ok ? s + omega * (rhs(o.bb, o.dg) - ax) / o.dg : (R)0;
   };
   auto stage1 = [&](const ZCell &c, int z) -> S1 {
     S1 o = load1(c, z);
@@ -751,7 +766,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     upl[t.z0 & 1][c0.hy][c0.hx] = b.u;
     u_cur = b.u;
     k_cur = b.k;
-    b_cur = rhs(b.bb);
+    b_cur = rhs(b.bb, b.dg);
     if (c0.in) F.x[c0.col + sz * (unsigned)t.z0] = b.u;
   }
   for (int z = t.z0; z < t.z1; ++z) {
@@ -782,7 +797,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     u_prev = u_cur;
     u_cur = a.u;
     k_cur = a.k;
-    b_cur = rhs(a.bb);
+    b_cur = rhs(a.bb, a.dg);
     if ((z & 1) == 0 && z + 1 < nz) continue;   // block-uniform
     __syncthreads();
     if (threadIdx.x < (ZT_X / 2) * (ZF_Y / 2)) {
@@ -806,8 +821,9 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
 // and the second sweep of k_v_jacobi3d, in one march.  Writes the result to
 // xo, or with OUT64 (the finest level: the cycle's last sweep) only to the
 // FP64 output z; there the right-hand side is (R)(rscale r64), the down leg's
-// expression, since that leg did not store it.  O32 as in the down leg.
-template <typename Lv, typename R, bool OUT64, bool O32>
+// expression, since that leg did not store it, or with RG (R)(r64 d), the
+// RHS_RG expression with the cell's diagonal d.  O32 as in the down leg.
+template <typename Lv, typename R, bool OUT64, bool O32, bool RG = false>
 __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z64,
                                                 const double *__restrict__ dsc, const double *__restrict__ r64,
                                                 double rscale, int zlen, const double *__restrict__ sc)
@@ -849,9 +865,11 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
   // stage 1: the first up sweep (k_v_post3d's expression), loads before the
   // plane's barrier (load1), arithmetic after it (apply1); the right-hand side
   // is carried as loaded (the FP64 residual with OUT64) and formed at its use
+  static_assert(OUT64 || !RG, "the diagonal-scaled input is the finest level's");
   using RB = typename std::conditional<OUT64, double, R>::type;
-  auto rhs = [&](RB raw) -> R {
-    if constexpr (OUT64) return (R)(rscale * raw);
+  auto rhs = [&](RB raw, R d) -> R {
+    if constexpr (RG) return (R)mul_rounded(raw, (double)d);
+    else if constexpr (OUT64) return (R)(rscale * raw);
     else return raw;
   };
   struct S1 { R u; ZCoef<R> k; RB b; float k32[6]; };
@@ -882,7 +900,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
     const ZNb<R> nb = znb2<R>(vpl[z & 3], vpl[(z - 1) & 3], vpl[(z + 1) & 3], c.hx, c.hy);
     const R dg = o.k.d;
     const R ay = zapply_off<Lv, R>(F, zhas(F.n, cc), o.k, dg, y, nb);
-    o.u = ok ? y + omega * (rhs(o.b) - ay) / dg : (R)0;
+    o.u = ok ? y + omega * (rhs(o.b, dg) - ay) / dg : (R)0;
   };
   auto stage1 = [&](const ZCell &c, int z) -> S1 {
     S1 o = load1(c, z);
@@ -906,7 +924,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
     upl[t.z0 & 1][c0.hy][c0.hx] = b.u;
     u_cur = b.u;
     k_cur = b.k;
-    b_cur = rhs(b.b);
+    b_cur = rhs(b.b, b.k.d);
   }
   for (int z = t.z0; z < t.z1; ++z) {
     S1 a = load1(c0, z + 1), a1 = load1(c1, z + 1);
@@ -936,7 +954,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ x
     u_prev = u_cur;
     u_cur = a.u;
     k_cur = a.k;
-    b_cur = rhs(a.b);
+    b_cur = rhs(a.b, a.k.d);
   }
 }
 

@@ -58,7 +58,7 @@ constexpr double SMG_DIFF_SCALE = 0.5;
 template <typename R>
 __device__ __forceinline__ R smg_apply_cell(const SLevel<R> &L, int nd, const R *x, unsigned id, const int c[3])
 {
-  const unsigned nc = L.nc, sy = (unsigned)L.n[0];
+  const unsigned sy = (unsigned)L.n[0];
   const bool hw = c[0] > 0, he = c[0] < L.n[0] - 1, hs = c[1] > 0, hn = c[1] < L.n[1] - 1;
   const R xc = x[id];
   const R xw = x[hw ? id - 1 : id], xe = x[he ? id + 1 : id];

@@ -152,9 +152,16 @@ void run_levels(const char *name, std::vector<Lv> &lv)
         launch(nf, [&] { k_v_up3d<Lv, R, false, false>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zf, sc); },
                ZF_TPB);
         if constexpr (std::is_same<Lv, SLevel<double>>::value) {
-          if (F.off32) {   // the variant reading the FP32 off-diagonal copies
+          // the input scaled by the level's diagonal inside the legs (transport)
+          launch(nf, [&] { k_v_down3d<Lv, R, RHS_RG, false>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+          launch(nf, [&] { k_v_up3d<Lv, R, true, false, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); },
+                 ZF_TPB);
+          if (F.off32) {   // the variants reading the FP32 off-diagonal copies
             launch(nf, [&] { k_v_down3d<Lv, R, RHS_R, true>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
             launch(nf, [&] { k_v_up3d<Lv, R, true, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZF_TPB);
+            launch(nf, [&] { k_v_down3d<Lv, R, RHS_RG, true>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+            launch(nf, [&] { k_v_up3d<Lv, R, true, true, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); },
+                   ZF_TPB);
           }
         }
       }
