@@ -34,18 +34,24 @@ def _gpu():
     vos.lib()
 
 
+# Pressure over all cells, intact solid included: the largest value measured
+# over this module's cases is 2.2e-8 (the stopping norm's weight in intact solid,
+# see _compare), so 1e-7 leaves a factor of ~4.
+P_ALL_BAR = 1e-7
+
+
 def _compare(st, g, eps0, tol=BAR):
     """Relative L2 of every field.  Pressure: over the cells that carry flow
     (eps > eps_min, i.e. all but intact solid) at the 1e-6 bar, and over all
-    cells at 1e-5 -- inside intact solid the transmissibility is ~1e-30 and
-    the Jacobi-scaled stopping norm of any CG fixes p there only to
+    cells at P_ALL_BAR -- inside intact solid the transmissibility is ~1e-30
+    and the Jacobi-scaled stopping norm of any CG fixes p there only to
     O(rtol / sqrt(d)), not to the flow's accuracy."""
     out = {k: rel_l2(g[k], getattr(st, k)) for k in ("ux", "uy", "c", "eps")}
     emin = st.eps.min()
     live = st.eps > 2 * emin if emin < 0.5 else np.ones_like(st.eps, dtype=bool)
     out["p"] = rel_l2(g["p"][live], st.p[live])
     p_all = rel_l2(g["p"], st.p)
-    assert p_all <= 10 * tol, ("p (all cells)", p_all)
+    assert p_all <= P_ALL_BAR, ("p (all cells)", p_all)
     if st.eps.shape[0] > 1:
         out["uz"] = rel_l2(g["uz"], st.uz)
     out["deps"] = rel_l2(g["eps"] - eps0, st.eps - eps0)
