@@ -115,7 +115,7 @@ int mg_hierarchy(const vos_grid &g, LevelDims *out)
   return L;
 }
 
-constexpr int NVEC = 11;
+constexpr int NVEC = 15;   // transport 0-10; momentum lanes 0-4, 5-9, 10-14
 constexpr int NHIST = 3;  // earlier solutions kept per solve for extrapolated starts
 constexpr int NSMG = 4;   // stencil hierarchies: momentum x, y, z; transport
 
@@ -137,7 +137,7 @@ struct Layout {
   size_t eps, p, c, pn, cold, rbar, gmag, nrm[3], pdiag, off, u[3], ustar[3], dmom[3], af[3], T[3], w[3];
   size_t c0, eps_prev;   // transient storage: c at the step's start, eps at the previous step's start
   size_t vec[NVEC];
-  size_t part, part2, part_max, scal, ainv;
+  size_t part, part2, part3, part_max, scal, ainv;
   size_t mgT[MG_MAX_LEVELS][3], mgdiag[MG_MAX_LEVELS], mgx[MG_MAX_LEVELS], mgb[MG_MAX_LEVELS], mgt[MG_MAX_LEVELS];
   int nlev;
   SmgPlan smg[NSMG];
@@ -213,7 +213,8 @@ Layout make_layout(const vos_grid &g, int precision)
   }
   for (int k = 0; k < NVEC; ++k) Lo.vec[k] = P.take(nmax * dbl);
   Lo.part = P.take((size_t)NSLOT * MAXB * dbl);
-  Lo.part2 = P.take((size_t)NSLOT * MAXB * dbl);   // partials of the momentum solve on the second lane
+  Lo.part2 = P.take((size_t)NSLOT * MAXB * dbl);   // partials of the momentum solves on the second and third lanes
+  Lo.part3 = P.take((size_t)NSLOT * MAXB * dbl);
   Lo.part_max = P.take((size_t)MAXB * dbl);
   Lo.scal = P.take((size_t)NSC * S_COUNT * 2 * dbl);
   Lo.ainv = P.take((size_t)MG_COARSE_MAX * MG_COARSE_MAX * dbl);
@@ -317,10 +318,10 @@ struct vos_sim {
   // two lanes for the momentum components, each with its own stream (created back to
   // back, so they land on different hardware queues), Krylov vectors, partials and
   // pinned read-back buffer; component 1 is driven from a second host thread
-  hipStream_t lane_stream[2];
-  double *part2;            // block partials of lane 1
-  double *host2;            // pinned read-back buffer of lane 1
-  hipEvent_t fork, join[2];
+  hipStream_t lane_stream[3];   // momentum lanes (the third in 3-D only)
+  double *part2, *part3;        // block partials of lanes 1 and 2
+  double *host2, *host3;        // pinned read-back buffers of lanes 1 and 2
+  hipEvent_t fork, join[3];
 };
 
 namespace {
@@ -495,7 +496,9 @@ struct Lane {
 Lane main_lane(vos_sim *s) { return Lane{s->stream, s->vec, s->part, s->host}; }
 Lane momentum_lane(vos_sim *s, int k)
 {
-  return k == 0 ? Lane{s->lane_stream[0], s->vec, s->part, s->host} : Lane{s->lane_stream[1], s->vec + 5, s->part2, s->host2};
+  if (k == 0) return Lane{s->lane_stream[0], s->vec, s->part, s->host};
+  if (k == 1) return Lane{s->lane_stream[1], s->vec + 5, s->part2, s->host2};
+  return Lane{s->lane_stream[2], s->vec + 10, s->part3, s->host3};
 }
 
 vos_status read_back(const Lane &ln, const double *dev, size_t n)
@@ -1638,30 +1641,33 @@ vos_status fill_diag(vos_sim *s, double dt, vos_diag *dg)
   return VOS_OK;
 }
 
-// The momentum predictor of every component (S2): components 0 (then 2) and 1
-// on the two momentum lanes, 1 driven from a second host thread; returns the
-// largest initial relative residual of the three solves in *r0.
+// The momentum predictor of every component (S2): each component on its own
+// momentum lane, components 1 and 2 driven from further host threads; returns
+// the largest initial relative residual of the solves in *r0.
 vos_status momentum_stage(vos_sim *s, double dt, vos_diag *dg, double *r0, vos_status *rc)
 {
   hipStream_t st = s->stream;
+  const int nl = s->g.nd == 3 ? 3 : 2;
   HIP_TRY(hipEventRecord(s->fork, st));
-  HIP_TRY(hipStreamWaitEvent(s->lane_stream[0], s->fork, 0));
-  HIP_TRY(hipStreamWaitEvent(s->lane_stream[1], s->fork, 0));
-  vos_status r1 = VOS_OK;
-  std::string m1;
+  for (int k = 0; k < nl; ++k) HIP_TRY(hipStreamWaitEvent(s->lane_stream[k], s->fork, 0));
+  vos_status r1 = VOS_OK, r3 = VOS_OK;
+  std::string m1, m3;
   double q[3] = {0.0, 0.0, 0.0};
   std::thread t1([&]() {
     r1 = solve_momentum<1>(s, momentum_lane(s, 1), dt, &dg->it_u[1], &dg->res_u[1], &q[1]);
     if (r1) m1 = vos_last_error();
   });
-  const Lane l0 = momentum_lane(s, 0);
-  vos_status r0s = solve_momentum<0>(s, l0, dt, &dg->it_u[0], &dg->res_u[0], &q[0]);
+  std::thread t2;
+  if (nl == 3)
+    t2 = std::thread([&]() {
+      r3 = solve_momentum<2>(s, momentum_lane(s, 2), dt, &dg->it_u[2], &dg->res_u[2], &q[2]);
+      if (r3) m3 = vos_last_error();
+    });
+  vos_status r0s = solve_momentum<0>(s, momentum_lane(s, 0), dt, &dg->it_u[0], &dg->res_u[0], &q[0]);
   std::string m0 = r0s ? std::string(vos_last_error()) : std::string();
-  vos_status r3 = VOS_OK;
-  if (s->g.nd == 3 && r0s != VOS_ERR_DEVICE) r3 = solve_momentum<2>(s, l0, dt, &dg->it_u[2], &dg->res_u[2], &q[2]);
-  std::string m3 = r3 ? std::string(vos_last_error()) : std::string();
   t1.join();
-  for (int k = 0; k < 2; ++k) {
+  if (t2.joinable()) t2.join();
+  for (int k = 0; k < nl; ++k) {
     HIP_TRY(hipEventRecord(s->join[k], s->lane_stream[k]));
     HIP_TRY(hipStreamWaitEvent(st, s->join[k], 0));
   }
@@ -2005,18 +2011,19 @@ vos_status time_z_kernel_t(vos_sim *s, Lv *lv, int nlev, int kind, double omega,
 // creation failure and by vos_destroy.
 void release(vos_sim *s)
 {
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 3; ++k)
     if (s->lane_stream[k]) (void)hipStreamSynchronize(s->lane_stream[k]);
   drop_graphs(s);
   for (int k = 0; k < 7; ++k)
     if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
   if (s->fork) (void)hipEventDestroy(s->fork);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     if (s->join[k]) (void)hipEventDestroy(s->join[k]);
     if (s->lane_stream[k]) (void)hipStreamDestroy(s->lane_stream[k]);
   }
   if (s->host) (void)hipHostFree(s->host);
   if (s->host2) (void)hipHostFree(s->host2);
+  if (s->host3) (void)hipHostFree(s->host3);
   delete s;
 }
 
@@ -2110,22 +2117,26 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   s->ws_drop = s->ws_frac = 0.0;
   std::memset(&s->last, 0, sizeof(s->last));
   s->part2 = D(lo.part2);
-  s->host = s->host2 = nullptr;
-  s->lane_stream[0] = s->lane_stream[1] = nullptr;
-  s->fork = s->join[0] = s->join[1] = nullptr;
+  s->part3 = D(lo.part3);
+  s->host = s->host2 = s->host3 = nullptr;
+  s->lane_stream[0] = s->lane_stream[1] = s->lane_stream[2] = nullptr;
+  s->fork = s->join[0] = s->join[1] = s->join[2] = nullptr;
   for (int k = 0; k < 7; ++k) s->ev[k] = nullptr;
   hipError_t e = hipHostMalloc((void **)&s->host, 64 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&s->host2, 64 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&s->host3, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     release(s);
     return fail(VOS_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
-  // default priority; created back to back so they land on different hardware queues
+  // default priority; created back to back so they land on different hardware
+  // queues (the sim's stream and three lanes: the four queues of a process)
   e = hipStreamCreateWithFlags(&s->lane_stream[0], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->lane_stream[1], hipStreamNonBlocking);
+  if (e == hipSuccess && s->g.nd == 3) e = hipStreamCreateWithFlags(&s->lane_stream[2], hipStreamNonBlocking);
   for (int k = 0; k < 7 && e == hipSuccess; ++k) e = hipEventCreate(&s->ev[k]);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming);
   if (e != hipSuccess) {
     release(s);
     return fail(VOS_ERR_DEVICE, std::string("stream / event creation: ") + hipGetErrorString(e));
