@@ -761,11 +761,11 @@ int fused_slots(const vos_sim *s)
   if (per_cu == 0) {
     int a = 0, b = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &a, reinterpret_cast<const void *>(k_v_down3d<Lv, R, RHS_R, O32>), ZF_TPB, 0) != hipSuccess ||
+            &a, reinterpret_cast<const void *>(k_v_down3d<Lv, R, RHS_R, O32>), ZT_X * zf_rows<R>, 0) != hipSuccess ||
         a < 1)
       a = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &b, reinterpret_cast<const void *>(k_v_up3d<Lv, R, true, O32>), ZF_TPB, 0) != hipSuccess ||
+            &b, reinterpret_cast<const void *>(k_v_up3d<Lv, R, true, O32>), ZT_X * zf_rows<R>, 0) != hipSuccess ||
         b < 1)
       b = 1;
     per_cu = std::min(a, b);
@@ -799,27 +799,29 @@ template <typename Lv, typename R, bool O32>
 void fused_down_t(vos_sim *s, const Lv &F, const Lv &C, bool finest, const double *r, double rscale, R om,
                   const double *sc, hipStream_t st, bool rg)
 {
-  const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s));
-  const dim3 gr(zrun_blocks_fused(F.n, zl));
+  constexpr int FY = zf_rows<R>, TPB_F = ZT_X * FY;
+  const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s), FY);
+  const dim3 gr(zrun_blocks_fused(F.n, zl, FY));
   if constexpr (lv_can32<Lv>) {
-    if (finest && rg) return (void)(k_v_down3d<Lv, R, RHS_RG, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, 1.0, om, zl, sc));
+    if (finest && rg) return (void)(k_v_down3d<Lv, R, RHS_RG, O32><<<gr, TPB_F, 0, st>>>(F, C, r, 1.0, om, zl, sc));
   }
-  if (finest) k_v_down3d<Lv, R, RHS_R, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, rscale, om, zl, sc);
-  else k_v_down3d<Lv, R, RHS_B, O32><<<gr, ZF_TPB, 0, st>>>(F, C, r, rscale, om, zl, sc);
+  if (finest) k_v_down3d<Lv, R, RHS_R, O32><<<gr, TPB_F, 0, st>>>(F, C, r, rscale, om, zl, sc);
+  else k_v_down3d<Lv, R, RHS_B, O32><<<gr, TPB_F, 0, st>>>(F, C, r, rscale, om, zl, sc);
 }
 template <typename Lv, typename R, bool O32>
 void fused_up_t(vos_sim *s, const Lv &F, const Lv &C, bool finest, double *z, const double *r, double rscale, R om,
                 const double *sc, hipStream_t st, bool rg)
 {
-  const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s));
-  const dim3 gr(zrun_blocks_fused(F.n, zl));
+  constexpr int FY = zf_rows<R>, TPB_F = ZT_X * FY;
+  const int zl = zrun_len_fused(F.n, fused_slots<Lv, R, O32>(s), FY);
+  const dim3 gr(zrun_blocks_fused(F.n, zl, FY));
   if constexpr (lv_can32<Lv>) {
     if (finest && rg)
-      return (void)(k_v_up3d<Lv, R, true, O32, true><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, z, nullptr, r, 1.0, zl,
+      return (void)(k_v_up3d<Lv, R, true, O32, true><<<gr, TPB_F, 0, st>>>(F, C, F.t, om, z, nullptr, r, 1.0, zl,
                                                                               sc));
   }
-  if (finest) k_v_up3d<Lv, R, true, O32><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, z, nullptr, r, rscale, zl, sc);
-  else k_v_up3d<Lv, R, false, O32><<<gr, ZF_TPB, 0, st>>>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zl, sc);
+  if (finest) k_v_up3d<Lv, R, true, O32><<<gr, TPB_F, 0, st>>>(F, C, F.t, om, z, nullptr, r, rscale, zl, sc);
+  else k_v_up3d<Lv, R, false, O32><<<gr, TPB_F, 0, st>>>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zl, sc);
 }
 template <typename Lv, typename R>
 void fused_down(vos_sim *s, const Lv &F, const Lv &C, bool finest, const double *r, double rscale, R om,

@@ -75,19 +75,25 @@ inline unsigned zrun_blocks(const int n[3], int zlen)
 // so that all work items are resident at once (slots = CUs x resident blocks
 // per CU; a second, partial round of blocks would leave most CUs idle at the
 // end), and are at least 8 planes long.  They run on levels of at least 2^20
-// cells (the smaller levels keep the separate kernels).
-inline long zfused_tiles(const int n[3]) { return (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + 7) / 8); }
-inline int zrun_len_fused(const int n[3], int slots)
+// cells (the smaller levels keep the separate kernels).  Their tiles are
+// ZT_X x zf_rows<R> cells for a level of R values, one thread per cell: 16
+// rows for FP64 levels (fewer halo cells per tile cell; one 1024-thread block
+// per CU), 8 for FP32 ones (three 512-thread blocks per CU fit their registers
+// and LDS, which their latency-bound marches need more than a smaller halo).
+template <typename R>
+constexpr int zf_rows = sizeof(R) == 8 ? 16 : 8;
+inline long zfused_tiles(const int n[3], int fy) { return (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + fy - 1) / fy); }
+inline int zrun_len_fused(const int n[3], int slots, int fy)
 {
-  const long runs = std::max(1L, (long)slots / zfused_tiles(n));
+  const long runs = std::max(1L, (long)slots / zfused_tiles(n, fy));
   long zl = ((long)n[2] + runs - 1) / runs;
   zl = std::max(8L, zl + (zl & 1));
   return (int)zl;
 }
 // Blocks of a fused-leg launch: its work items rounded up to a multiple of the 8 XCDs.
-inline unsigned zrun_blocks_fused(const int n[3], int zlen)
+inline unsigned zrun_blocks_fused(const int n[3], int zlen, int fy)
 {
-  const unsigned nw = (unsigned)zfused_tiles(n) * (unsigned)((n[2] + zlen - 1) / zlen);
+  const unsigned nw = (unsigned)zfused_tiles(n, fy) * (unsigned)((n[2] + zlen - 1) / zlen);
   return (nw + NXCD - 1) / NXCD * NXCD;
 }
 inline bool zfused_level(const int n[3])
@@ -530,26 +536,30 @@ __global__ void __launch_bounds__(TPB) k_v_post3d(Lv F, Lv C, R *__restrict__ xo
 // down, k_v_post3d + k_v_jacobi3d up), so the cycle's results are bitwise
 // those of the separate kernels.
 //
-// Tiles are ZT_X x ZF_Y (64 x 8) with a block of 512 threads (the halo rings
-// then carry 29 % of the tile's cells in the first ring instead of 55 % with 4
-// rows).  LDS: four v planes (two-cell halo; a plane is read by three
-// consecutive stage-1 passes, so four slots let stage 0 run one plane ahead
-// with one barrier per plane) and two u planes (one-cell halo).  A thread
-// owns its tile cell (stages 0-2), at most one cell of the one-cell ring
-// (stages 0-1) and at most one of the two-cell ring (stage 0).
-constexpr int ZF_Y = 8;
-constexpr int ZF_TPB = ZT_X * ZF_Y;                 // 512 threads
-constexpr int ZH2_X = ZT_X + 4, ZH2_Y = ZF_Y + 4;   // two-cell halo plane
-constexpr int ZH1_X = ZT_X + 2, ZH1_Y = ZF_Y + 2;   // one-cell halo plane
-constexpr int ZRING1 = 2 * ZH1_X + 2 * ZF_Y;        // 148 cells
-constexpr int ZRING2 = 2 * ZH2_X + 2 * (ZF_Y + 2);  // 156 cells
-static_assert(ZRING1 <= ZF_TPB && ZRING2 <= ZF_TPB, "one ring cell per thread");
-static_assert(ZF_Y % 2 == 0, "restriction aggregates stay inside a tile");
+// Tiles are ZT_X x FY cells (FY = zf_rows<R>) with one thread per cell: the
+// first halo ring carries 2 (ZT_X + 2 + FY) cells, 29 % of a 64 x 8 tile's
+// cells, 16 % of a 64 x 16 one's (55 % with 4 rows).  LDS: four v planes
+// (two-cell halo; a plane is read by three consecutive stage-1 passes, so
+// four slots let stage 0 run one plane ahead with one barrier per plane) and
+// two u planes (one-cell halo).  A thread owns its tile cell (stages 0-2), at
+// most one cell of the one-cell ring (stages 0-1) and at most one of the
+// two-cell ring (stage 0).
+constexpr int ZH2_X = ZT_X + 4;   // two-cell halo plane width
+constexpr int ZH1_X = ZT_X + 2;   // one-cell halo plane width
+template <int FY>
+struct ZFS {   // the shape of an FY-row fused tile
+  static constexpr int TPB = ZT_X * FY;
+  static constexpr int H2Y = FY + 4, H1Y = FY + 2;   // halo plane heights
+  static constexpr int RING1 = 2 * ZH1_X + 2 * FY, RING2 = 2 * ZH2_X + 2 * (FY + 2);
+  static_assert(RING1 <= TPB && RING2 <= TPB, "one ring cell per thread");
+  static_assert(FY % 2 == 0, "restriction aggregates stay inside a tile");
+};
 
-// Work item of a fused-leg block: as ztile_of, with ZT_X x ZF_Y tiles.
+// Work item of a fused-leg block: as ztile_of, with ZT_X x FY tiles.
+template <int FY>
 __device__ __forceinline__ bool zftile_of(const int n[3], int zlen, ZTile &t)
 {
-  const unsigned gx = (unsigned)(n[0] + ZT_X - 1) / ZT_X, gy = (unsigned)(n[1] + ZF_Y - 1) / ZF_Y;
+  const unsigned gx = (unsigned)(n[0] + ZT_X - 1) / ZT_X, gy = (unsigned)(n[1] + FY - 1) / FY;
   const unsigned gz = (unsigned)(n[2] + zlen - 1) / (unsigned)zlen;
   const unsigned tiles = gx * gy, nw = tiles * gz;
   const unsigned per = (nw + NXCD - 1) / NXCD;
@@ -557,7 +567,7 @@ __device__ __forceinline__ bool zftile_of(const int n[3], int zlen, ZTile &t)
   if (w >= nw) return false;
   const unsigned zr = w / tiles, tt = w - zr * tiles;
   t.x0 = (int)(tt % gx) * ZT_X;
-  t.y0 = (int)(tt / gx) * ZF_Y;
+  t.y0 = (int)(tt / gx) * FY;
   t.z0 = (int)zr * zlen;
   t.z1 = min(n[2], t.z0 + zlen);
   return true;
@@ -566,8 +576,10 @@ __device__ __forceinline__ bool zftile_of(const int n[3], int zlen, ZTile &t)
 // Position (in two-halo plane coordinates) of the thread's cell of class k:
 // 0 its tile cell, 1 its one-cell-ring cell, 2 its two-cell-ring cell;
 // false when the thread has none.
+template <int FY>
 __device__ __forceinline__ bool zfused_cell(int k, int &hx, int &hy)
 {
+  using S = ZFS<FY>;
   const int h = threadIdx.x;
   if (k == 0) {
     hx = h % ZT_X + 2;
@@ -575,21 +587,21 @@ __device__ __forceinline__ bool zfused_cell(int k, int &hx, int &hy)
     return true;
   }
   if (k == 1) {
-    if (h >= ZRING1) return false;
+    if (h >= S::RING1) return false;
     int x1, y1;   // one-halo coordinates
     if (h < ZH1_X) { x1 = h; y1 = 0; }
-    else if (h < 2 * ZH1_X) { x1 = h - ZH1_X; y1 = ZH1_Y - 1; }
-    else if (h < 2 * ZH1_X + ZF_Y) { x1 = 0; y1 = h - 2 * ZH1_X + 1; }
-    else { x1 = ZH1_X - 1; y1 = h - 2 * ZH1_X - ZF_Y + 1; }
+    else if (h < 2 * ZH1_X) { x1 = h - ZH1_X; y1 = S::H1Y - 1; }
+    else if (h < 2 * ZH1_X + FY) { x1 = 0; y1 = h - 2 * ZH1_X + 1; }
+    else { x1 = ZH1_X - 1; y1 = h - 2 * ZH1_X - FY + 1; }
     hx = x1 + 1;
     hy = y1 + 1;
     return true;
   }
-  if (h >= ZRING2) return false;
+  if (h >= S::RING2) return false;
   if (h < ZH2_X) { hx = h; hy = 0; }
-  else if (h < 2 * ZH2_X) { hx = h - ZH2_X; hy = ZH2_Y - 1; }
-  else if (h < 2 * ZH2_X + ZF_Y + 2) { hx = 0; hy = h - 2 * ZH2_X + 1; }
-  else { hx = ZH2_X - 1; hy = h - 2 * ZH2_X - (ZF_Y + 2) + 1; }
+  else if (h < 2 * ZH2_X) { hx = h - ZH2_X; hy = S::H2Y - 1; }
+  else if (h < 2 * ZH2_X + FY + 2) { hx = 0; hy = h - 2 * ZH2_X + 1; }
+  else { hx = ZH2_X - 1; hy = h - 2 * ZH2_X - (FY + 2) + 1; }
   return true;
 }
 
@@ -600,10 +612,11 @@ struct ZCell {
   unsigned col;     // gx + nx gy (0 outside)
 };
 
+template <int FY>
 __device__ __forceinline__ ZCell zfused_at(int k, const ZTile &t, const int n[3])
 {
   ZCell c;
-  c.has = zfused_cell(k, c.hx, c.hy);
+  c.has = zfused_cell<FY>(k, c.hx, c.hy);
   if (!c.has) { c.hx = c.hy = 2; }   // a position whose neighbours are in the plane (never stored)
   c.gx = t.x0 + c.hx - 2;
   c.gy = t.y0 + c.hy - 2;
@@ -636,19 +649,21 @@ __device__ __forceinline__ ZNb<R> znb2(const R (*pl)[ZH2_X], const R (*lo)[ZH2_X
 // level's off-diagonals are read from its FP32 copies, carried as loaded and
 // widened after the plane's barrier.  zlen even.
 template <typename Lv, typename R, int RHS, bool O32>
-__global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *__restrict__ r64, double rscale, R omega,
+__global__ void __launch_bounds__(ZT_X * zf_rows<R>) k_v_down3d(Lv F, Lv C, const double *__restrict__ r64, double rscale,
+                                                              R omega,
                                                   int zlen, const double *__restrict__ sc)
 {
   static_assert(RHS == RHS_R || RHS == RHS_B || RHS == RHS_RG, "no dsc scaling in the fused leg");
   if (sc[S_CONV] != 0.0) return;
   ZTile t;
-  if (!zftile_of(F.n, zlen, t)) return;
-  __shared__ R vpl[4][ZH2_Y][ZH2_X];
-  __shared__ R upl[2][ZH2_Y][ZH2_X];   // one-halo values, kept in two-halo coordinates
-  __shared__ R rs[2][ZF_Y][ZT_X];
+  constexpr int FY = zf_rows<R>, H2Y = ZFS<FY>::H2Y;
+  if (!zftile_of<FY>(F.n, zlen, t)) return;
+  __shared__ R vpl[4][H2Y][ZH2_X];
+  __shared__ R upl[2][H2Y][ZH2_X];   // one-halo values, kept in two-halo coordinates
+  __shared__ R rs[2][FY][ZT_X];
   const int nz = F.n[2];
   const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
-  const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
+  const ZCell c0 = zfused_at<FY>(0, t, F.n), c1 = zfused_at<FY>(1, t, F.n), c2 = zfused_at<FY>(2, t, F.n);
   // the right-hand side as loaded (the FP64 vector r or the level's b) and as
   // used with the cell's diagonal d, (R)(rscale r), (R)(r d) or b: loads carry
   // the raw word, so that no arithmetic ahead of a plane's barrier waits for them
@@ -800,7 +815,7 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
     b_cur = rhs(a.bb, a.dg);
     if ((z & 1) == 0 && z + 1 < nz) continue;   // block-uniform
     __syncthreads();
-    if (threadIdx.x < (ZT_X / 2) * (ZF_Y / 2)) {
+    if (threadIdx.x < (ZT_X / 2) * (FY / 2)) {
       const int ix = threadIdx.x % (ZT_X / 2), iy = threadIdx.x / (ZT_X / 2);
       const int IX = t.x0 / 2 + ix, IY = t.y0 / 2 + iy, IZ = z >> 1;
       if (IX < C.n[0] && IY < C.n[1]) {
@@ -824,18 +839,20 @@ __global__ void __launch_bounds__(ZF_TPB) k_v_down3d(Lv F, Lv C, const double *_
 // expression, since that leg did not store it, or with RG (R)(r64 d), the
 // RHS_RG expression with the cell's diagonal d.  O32 as in the down leg.
 template <typename Lv, typename R, bool OUT64, bool O32, bool RG = false>
-__global__ void __launch_bounds__(ZF_TPB) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, R omega, double *__restrict__ z64,
+__global__ void __launch_bounds__(ZT_X * zf_rows<R>) k_v_up3d(Lv F, Lv C, R *__restrict__ xo, R omega,
+                                                            double *__restrict__ z64,
                                                 const double *__restrict__ dsc, const double *__restrict__ r64,
                                                 double rscale, int zlen, const double *__restrict__ sc)
 {
   if (sc[S_CONV] != 0.0) return;
   ZTile t;
-  if (!zftile_of(F.n, zlen, t)) return;
-  __shared__ R vpl[4][ZH2_Y][ZH2_X];
-  __shared__ R upl[2][ZH2_Y][ZH2_X];
+  constexpr int FY = zf_rows<R>, H2Y = ZFS<FY>::H2Y;
+  if (!zftile_of<FY>(F.n, zlen, t)) return;
+  __shared__ R vpl[4][H2Y][ZH2_X];
+  __shared__ R upl[2][H2Y][ZH2_X];
   const int nz = F.n[2];
   const unsigned sz = (unsigned)F.n[0] * (unsigned)F.n[1];
-  const ZCell c0 = zfused_at(0, t, F.n), c1 = zfused_at(1, t, F.n), c2 = zfused_at(2, t, F.n);
+  const ZCell c0 = zfused_at<FY>(0, t, F.n), c1 = zfused_at<FY>(1, t, F.n), c2 = zfused_at<FY>(2, t, F.n);
   // stage 0: y = x + the coarse correction of the cell's aggregate; inputs
   // loaded one plane ahead as in the down leg
   const ZCell *cs[3] = {&c0, &c1, &c2};

@@ -142,31 +142,32 @@ void run_levels(const char *name, std::vector<Lv> &lv)
     std::printf("  %s level %zu: %d x %d x %d, z-run %d, %u blocks: 8 launches in bounds\n", name, l, F.n[0], F.n[1],
                 F.n[2], zl, nb);
     if (zfused_level(F.n)) {
+      constexpr int FY = zf_rows<R>;
       // one and three resident blocks per CU of 256 CUs: long and short z-runs
       for (int slots : {256, 768}) {
-        const int zf = zrun_len_fused(F.n, slots);
-        const unsigned nf = zrun_blocks_fused(F.n, zf);
-        launch(nf, [&] { k_v_down3d<Lv, R, RHS_R, false>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
-        launch(nf, [&] { k_v_down3d<Lv, R, RHS_B, false>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
-        launch(nf, [&] { k_v_up3d<Lv, R, true, false>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZF_TPB);
+        const int zf = zrun_len_fused(F.n, slots, FY);
+        const unsigned nf = zrun_blocks_fused(F.n, zf, FY);
+        launch(nf, [&] { k_v_down3d<Lv, R, RHS_R, false>(F, C, r64, 1.0, om, zf, sc); }, ZT_X * FY);
+        launch(nf, [&] { k_v_down3d<Lv, R, RHS_B, false>(F, C, r64, 1.0, om, zf, sc); }, ZT_X * FY);
+        launch(nf, [&] { k_v_up3d<Lv, R, true, false>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZT_X * FY);
         launch(nf, [&] { k_v_up3d<Lv, R, false, false>(F, C, F.t, om, nullptr, nullptr, nullptr, 1.0, zf, sc); },
-               ZF_TPB);
+               ZT_X * FY);
         if constexpr (std::is_same<Lv, SLevel<double>>::value) {
           // the input scaled by the level's diagonal inside the legs (transport)
-          launch(nf, [&] { k_v_down3d<Lv, R, RHS_RG, false>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+          launch(nf, [&] { k_v_down3d<Lv, R, RHS_RG, false>(F, C, r64, 1.0, om, zf, sc); }, ZT_X * FY);
           launch(nf, [&] { k_v_up3d<Lv, R, true, false, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); },
-                 ZF_TPB);
+                 ZT_X * FY);
           if (F.off32) {   // the variants reading the FP32 off-diagonal copies
-            launch(nf, [&] { k_v_down3d<Lv, R, RHS_R, true>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
-            launch(nf, [&] { k_v_up3d<Lv, R, true, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZF_TPB);
-            launch(nf, [&] { k_v_down3d<Lv, R, RHS_RG, true>(F, C, r64, 1.0, om, zf, sc); }, ZF_TPB);
+            launch(nf, [&] { k_v_down3d<Lv, R, RHS_R, true>(F, C, r64, 1.0, om, zf, sc); }, ZT_X * FY);
+            launch(nf, [&] { k_v_up3d<Lv, R, true, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); }, ZT_X * FY);
+            launch(nf, [&] { k_v_down3d<Lv, R, RHS_RG, true>(F, C, r64, 1.0, om, zf, sc); }, ZT_X * FY);
             launch(nf, [&] { k_v_up3d<Lv, R, true, true, true>(F, C, F.t, om, z, nullptr, r64, 1.0, zf, sc); },
-                   ZF_TPB);
+                   ZT_X * FY);
           }
         }
       }
-      const int zf = zrun_len_fused(F.n, 768);
-      const unsigned nf = zrun_blocks_fused(F.n, zf);
+      const int zf = zrun_len_fused(F.n, 768, FY);
+      const unsigned nf = zrun_blocks_fused(F.n, zf, FY);
       std::printf("  %s level %zu fused legs: z-run %d, %u blocks (and a longer run): 8 launches in bounds\n", name, l, zf, nf);
     }
   }
