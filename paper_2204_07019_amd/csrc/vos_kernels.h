@@ -608,20 +608,25 @@ __global__ void __launch_bounds__(TPB) k_adr_apply(Dev g, const double *__restri
 {
   if (sc[S_CONV] != 0.0) return;
   double d0 = 0.0, d1 = 0.0;
+  const unsigned sy = (unsigned)g.n[0], sz = (unsigned)g.n[0] * g.n[1];
   for (unsigned id = xbeg(g.nc); id < xend(g.nc); id += xstride()) {
     int x[3];
     unflat(g.n, id, x);
-    double v = xv[id];
-    if (x[0] > 0) v += off[id] * xv[id - 1];
-    if (x[0] < g.n[0] - 1) v += off[(size_t)g.nc + id] * xv[id + 1];
-    const unsigned sy = (unsigned)g.n[0];
-    if (x[1] > 0) v += off[2 * (size_t)g.nc + id] * xv[id - sy];
-    if (x[1] < g.n[1] - 1) v += off[3 * (size_t)g.nc + id] * xv[id + sy];
-    if (g.nd == 3) {
-      const unsigned sz = (unsigned)g.n[0] * g.n[1];
-      if (x[2] > 0) v += off[4 * (size_t)g.nc + id] * xv[id - sz];
-      if (x[2] < g.n[2] - 1) v += off[5 * (size_t)g.nc + id] * xv[id + sz];
+    // every load issued together (a missing neighbour's index clamped to the
+    // cell itself, its term dropped by a select in the same order: -x, +x,
+    // -y, +y, -z, +z; a 2-D grid has no z neighbours)
+    const bool h[6] = {x[0] > 0, x[0] < g.n[0] - 1, x[1] > 0, x[1] < g.n[1] - 1, x[2] > 0, x[2] < g.n[2] - 1};
+    const unsigned nb[6] = {h[0] ? id - 1 : id, h[1] ? id + 1 : id, h[2] ? id - sy : id,
+                            h[3] ? id + sy : id, h[4] ? id - sz : id, h[5] ? id + sz : id};
+    double xn[6], o[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      xn[k] = xv[nb[k]];
+      o[k] = off[(size_t)k * g.nc + id];
     }
+    double v = xv[id];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v = h[k] ? v + o[k] * xn[k] : v;
     y[id] = v;
     d0 += v * (HW ? splitmix_unit(id) : w[id]);
     if (NDOT == 2) d1 += v * v;
