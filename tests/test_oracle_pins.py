@@ -121,6 +121,29 @@ def test_uniform_concentration_is_steady(orc):
     assert np.abs(st.c - prob.c_in).max() < 1e-9 * prob.c_in
 
 
+def test_alpha_is_inverse_porosity_for_uniform_concentration(orc):
+    """The correction factor alpha = sum c |grad eps| V / (a sum eps c V) with
+    a = sum |grad eps| V / V_domain (Section 2.5): for a uniform c it is
+    V_domain / sum eps V = 1 / phi, whatever the geometry and the value of c.
+    A c missing from one of the sums (c_in != 1), an area normalised by
+    anything but the domain volume, or an eps weighting of another field
+    fails here.  No reaction (kc = 0) keeps c uniform and eps fixed."""
+    for nz, cin in ((1, 2.5), (1, 0.4), (6, 3.0)):
+        prob = orc.Problem(nx=24, ny=12, nz=nz, kc=0.0, c_in=cin, rtol_c=1e-14, rtol_u=1e-13, rtol_p=1e-13)
+        es = np.zeros((nz, 12, 24))
+        es[:, 4:8, 8:14] = 1.0
+        es[:, 3, 8:14] = 0.35          # partial cells: |grad eps| varies along the interface
+        es[:, 2:9, 15] = 0.6
+        st = orc.initial_state(prob, es)
+        for _ in range(2):
+            orc.step(prob, st, 1e-3)
+        st.c[:] = cin
+        d = orc.step(prob, st, 1e-3)
+        phi = float(np.mean(st.eps))
+        assert d["alpha"] == pytest.approx(1.0 / phi, rel=1e-9), (nz, cin)
+        assert d["porosity"] == pytest.approx(phi, rel=1e-14)
+
+
 # ------------------------------------------------------- reaction rate
 
 def _plane(orc, model, m=6, nx=16, ny=4, eps_front=None, c=3.0):
