@@ -618,9 +618,10 @@ __global__ void __launch_bounds__(TPB) k_adr_apply(Dev g, const double *__restri
     const bool h[6] = {x[0] > 0, x[0] < g.n[0] - 1, x[1] > 0, x[1] < g.n[1] - 1, x[2] > 0, x[2] < g.n[2] - 1};
     const unsigned nb[6] = {h[0] ? id - 1 : id, h[1] ? id + 1 : id, h[2] ? id - sy : id,
                             h[3] ? id + sy : id, h[4] ? id - sz : id, h[5] ? id + sz : id};
-    double xn[6], o[6];
+    double xn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, o[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
+      if (k >= 4 && g.nd != 3) continue;   // uniform: a 2-D grid reads no z slots
       xn[k] = xv[nb[k]];
       o[k] = off[(size_t)k * g.nc + id];
     }
