@@ -757,8 +757,10 @@ void launch_coarse(int c0, const LevelPack<Lv> &pack, int lc, int L, int nd, int
 template <typename Lv, typename R, bool O32>
 int fused_slots(const vos_sim *s)
 {
-  static int per_cu = 0;   // kernel attributes: the same for every simulation of the process
-  if (per_cu == 0) {
+  // kernel attributes: the same for every simulation of the process; the
+  // initialisation of a function-local static is thread-safe (the momentum
+  // lanes reach it from their own host threads)
+  static const int per_cu = []() {
     int a = 0, b = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &a, reinterpret_cast<const void *>(k_v_down3d<Lv, R, RHS_R, O32>), ZT_X * zf_rows<R>, 0) != hipSuccess ||
@@ -768,8 +770,8 @@ int fused_slots(const vos_sim *s)
             &b, reinterpret_cast<const void *>(k_v_up3d<Lv, R, true, O32>), ZT_X * zf_rows<R>, 0) != hipSuccess ||
         b < 1)
       b = 1;
-    per_cu = std::min(a, b);
-  }
+    return std::min(a, b);
+  }();
   return s->n_cu * per_cu;
 }
 
