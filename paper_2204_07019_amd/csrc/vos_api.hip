@@ -382,6 +382,9 @@ void fill_smg(vos_sim *s, int h, SLevel<R> *lv)
     L.b = (R *)(s->ws + S.b[l]);
     L.t = (R *)(s->ws + S.t[l]);
     L.dif = S.split ? (R *)(s->ws + S.dif[l]) : nullptr;
+    // the 3-D transport level 0's diffusive parts are the assembly's own
+    if constexpr (std::is_same<R, double>::value)
+      if (h == 3 && l == 0 && s->g.nd == 3) L.dif = s->tdif;
     L.off32 = S.has32[l] ? (float *)(s->ws + S.off32[l]) : nullptr;
   }
   if (S.nlev) s->sainv[h] = (double *)(s->ws + S.ainv);
@@ -714,8 +717,15 @@ void smg_coarsen_all(vos_sim *s, int h, SLevel<R> *lv, hipStream_t st)
   const int nd = s->g.nd;
   const int L = s->snlev[h];
   for (int l = 0; l + 1 < L; ++l) {
-    if (nd == 3) k_smg_coarsen<R, 3><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1]);
-    else k_smg_coarsen<R, 2><<<grid_blocks(lv[l + 1].nc), TPB, 0, st>>>(lv[l], lv[l + 1]);
+    const dim3 gr(grid_blocks(lv[l + 1].nc));
+    if (l == 0 && h == 3 && lv[0].off32) {   // level 0's FP64 off-diagonals formed from the assembly
+      if (nd == 3) k_smg_coarsen<R, 3, true><<<gr, TPB, 0, st>>>(lv[0], lv[1], s->off, s->tdiag);
+      else k_smg_coarsen<R, 2, true><<<gr, TPB, 0, st>>>(lv[0], lv[1], s->off, s->tdiag);
+    } else if (nd == 3) {
+      k_smg_coarsen<R, 3><<<gr, TPB, 0, st>>>(lv[l], lv[l + 1]);
+    } else {
+      k_smg_coarsen<R, 2><<<gr, TPB, 0, st>>>(lv[l], lv[l + 1]);
+    }
   }
   k_smg_coarse_inverse<R><<<1, GJ_TPB, 0, st>>>(lv[L - 1], nd, s->sainv[h]);
 }

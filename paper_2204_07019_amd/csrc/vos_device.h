@@ -35,6 +35,15 @@ struct Phys {
 };
 
 __device__ __forceinline__ unsigned gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
+
+// a b rounded to FP64 on its own: the product never enters a fused
+// multiply-add with the arithmetic that consumes it (so it equals the same
+// product stored to memory and read back).
+__device__ __forceinline__ double mul_rounded(double a, double b)
+{
+#pragma clang fp contract(off)
+  return a * b;
+}
 __device__ __forceinline__ unsigned gstride() { return gridDim.x * blockDim.x; }
 
 // XCD-aware sweep ranges.  Workgroups are dispatched round-robin over the 8

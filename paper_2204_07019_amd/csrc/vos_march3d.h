@@ -415,13 +415,6 @@ __global__ void __launch_bounds__(TPB) k_v_jacobi3d(Lv L, const R *__restrict__ 
 // would otherwise store).
 enum { RHS_B = 0, RHS_R = 1, RHS_RD = 2, RHS_RG = 3 };
 
-// a b rounded to FP64 on its own: the product never enters a fused
-// multiply-add with the arithmetic that consumes it.
-__device__ __forceinline__ double mul_rounded(double a, double b)
-{
-#pragma clang fp contract(off)
-  return a * b;
-}
 
 // Pre-smoothing sweeps 1 and 2 (k_v_pre with two sweeps).
 template <typename Lv, typename R, int RHS>

@@ -83,6 +83,11 @@ __device__ __forceinline__ R smg_apply_cell(const SLevel<R> &L, int nd, const R 
 // Level 0 of the transport hierarchy: the stencil without its row scaling
 // (off64 is scaled by the diagonal dg; dif64 holds the unscaled diffusive
 // parts), so the Galerkin products below are those of the operator itself.
+// Where the level keeps FP32 copies of its off-diagonals (its smoothing reads
+// only those), the FP64 ones are not stored: the Galerkin product forms them
+// from off64 and dg itself (k_smg_coarsen's L0 form).  Where the level's
+// diffusive parts are dif64 itself (3-D: every slot of dif64 is written),
+// they are not copied.
 // Damped Jacobi does not see a row scaling, so level 0 smooths as the scaled
 // operator would; the cycle's input is the scaled residual times dg.
 template <typename R>
@@ -95,10 +100,10 @@ __global__ void __launch_bounds__(TPB) k_smg_from_transport(unsigned nc, int nd,
     L.diag[id] = (R)d;
     for (int k = 0; k < 6; ++k) {
       const bool on = k < 2 * nd;
-      const double o = off64[(size_t)k * nc + id] * d;
-      L.off[(size_t)k * nc + id] = on ? (R)o : (R)0;
-      L.dif[(size_t)k * nc + id] = on ? (R)dif64[(size_t)k * nc + id] : (R)0;
+      const double o = mul_rounded(off64[(size_t)k * nc + id], d);
       if (L.off32) L.off32[(size_t)k * nc + id] = on ? (float)o : 0.0f;
+      else L.off[(size_t)k * nc + id] = on ? (R)o : (R)0;
+      if ((const void *)L.dif != (const void *)dif64) L.dif[(size_t)k * nc + id] = on ? (R)dif64[(size_t)k * nc + id] : (R)0;
     }
   }
 }
@@ -128,13 +133,16 @@ __global__ void __launch_bounds__(TPB) k_smg_from_momentum(Dev g, double cvis, c
   }
 }
 
-// Galerkin coarse stencil of aggregate I.  With diffusive parts (F.dif), the
+// Galerkin coarse stencil of aggregate I.  L0: F is the transport
+// hierarchy's level 0 whose FP64 off-diagonals are not stored; they are
+// formed as k_smg_from_transport forms them, off64 times dg64.  With diffusive parts (F.dif), the
 // coarse one is SMG_DIFF_SCALE times their Galerkin sum; the diffusion
 // operator has zero row sums, so the diagonal drops by the same amount.  Per
 // plane of children (one in 2-D, two in 3-D) every load is issued first, at
 // clamped cells, and a missing child or neighbour is dropped by a select.
-template <typename R, int ND>
-__global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C)
+template <typename R, int ND, bool L0 = false>
+__global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C, const double *__restrict__ off64 = nullptr,
+                                                     const double *__restrict__ dg64 = nullptr)
 {
   constexpr int NS = 2 * ND;
   const bool split = F.dif != nullptr;
@@ -162,9 +170,11 @@ __global__ void __launch_bounds__(TPB) k_smg_coarsen(SLevel<R> F, SLevel<R> C)
 #pragma unroll
       for (int ch = 0; ch < 4; ++ch) {
         dv[ch] = F.diag[id[ch]];
+        const double d64 = L0 ? dg64[id[ch]] : 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          av[ch][k] = F.off[(size_t)k * F.nc + id[ch]];
+          if constexpr (L0) av[ch][k] = (R)mul_rounded(off64[(size_t)k * F.nc + id[ch]], d64);
+          else av[ch][k] = F.off[(size_t)k * F.nc + id[ch]];
           qv[ch][k] = difs[(size_t)k * F.nc + id[ch]];
         }
       }
