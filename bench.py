@@ -681,7 +681,7 @@ def main():
     ap.add_argument("--no-micromodel", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-micromodel batch")
     ap.add_argument("--batch-n", type=int, default=64)
-    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net timing")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--no-upscaling", action="store_true", help="skip the long upscaling run")
