@@ -306,6 +306,10 @@ def batch_bench(vos, inputs, scaling, n, steps, dt, seed=2, relax=5):
         s.set_params(dict(base, u_in=u_in, kc=kc))
     b.step(dt, 2, freeze_solid=True)
     tuned = b.tune(dt, probe_steps=1)
+    # the settings the tuner chose per grid size (check interval, tall-tile threshold)
+    tuned["per_size"] = {}
+    for i, (nx, ny, *_r) in enumerate(specs):
+        tuned["per_size"].setdefault(f"{nx}x{ny}", b.tuning(i))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     diags = b.step(dt, steps)

@@ -51,14 +51,22 @@ vos_status vos_batch_step(vos_batch *batch, const double *dt, int nsteps, int fl
                           vos_status *status);
 
 /* Autotuner.  For each candidate worker count (1, 2, 4, ... up to the batch's
- * maximum) and each candidate Krylov check interval (2, 4, 8, 16, 32, chosen per
- * grid-size class), time probe_steps solid-frozen steps of the whole batch
- * (VOS_FREEZE_SOLID: flow and transport advance, the geometry does not) and
- * keep the fastest setting.  Results do not depend on it (the check interval
- * only decides how often the host looks at the device convergence flag).
- * Outputs (may be NULL): the chosen worker count and the best batch step time
- * [ms]. */
+ * maximum), each candidate Krylov check interval (2, 4, 8, 16, 32, chosen per
+ * grid-size class) and each candidate tile shape of the 2-D tiled V-cycle legs
+ * (the level size from which they take 32 x 16 instead of 32 x 2 tiles: 2^16,
+ * 2^18, 2^20 cells or never; per grid-size class), time probe_steps
+ * solid-frozen steps of the whole batch (VOS_FREEZE_SOLID: flow and transport
+ * advance, the geometry does not) and keep the fastest setting.  Results do
+ * not depend on it (the check interval only decides how often the host looks
+ * at the device convergence flag; every tile shape forms each value by the
+ * same expression).  Outputs (may be NULL): the chosen worker count and the
+ * best batch step time [ms]. */
 vos_status vos_batch_tune(vos_batch *batch, const double *dt, int probe_steps, int *workers, double *best_ms);
+
+/* The tuned settings of instance i (0 <= i < n; errors: VOS_ERR_ARG): its
+ * Krylov check interval and the level size from which its 2-D tiled V-cycle
+ * legs take the tall tiles (0xffffffff: never).  Outputs may be NULL. */
+vos_status vos_batch_tuning(vos_batch *batch, int i, int *check_every, unsigned *tile_big_cells);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,7 @@ def lib():
             "vos_batch_sim": [vp, C.c_int, C.POINTER(vp)],
             "vos_batch_step": [vp, vp, C.c_int, C.c_int, vp, vp],
             "vos_batch_tune": [vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)],
+            "vos_batch_tuning": [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_uint)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -95,3 +96,11 @@ class Batch:
         ms = C.c_double()
         vos._check(lib().vos_batch_tune(self._h, dts, probe_steps, C.byref(w), C.byref(ms)))
         return {"workers": w.value, "best_ms": ms.value}
+
+    def tuning(self, i: int) -> dict:
+        """Instance i's tuned Krylov check interval and the level size from
+        which its 2-D tiled V-cycle legs take the tall tiles."""
+        ce = C.c_int()
+        tb = C.c_uint()
+        vos._check(lib().vos_batch_tuning(self._h, i, C.byref(ce), C.byref(tb)))
+        return {"check_every": ce.value, "tile_big_cells": tb.value}

@@ -58,7 +58,9 @@ struct Plan {
 };
 
 // Tile height of the tiled 2-D V-cycle kernels on a level of nc cells.
-int tile_height(unsigned nc) { return nc >= VT_BIG_CELLS ? VT_Y_BIG : VT_Y_SMALL; }
+// (levels of at least `big` cells take the tall tiles; the simulation's
+// tile_big, VT_BIG_CELLS unless the batch tuner chose otherwise)
+int tile_height(unsigned nc, unsigned big) { return nc >= big ? VT_Y_BIG : VT_Y_SMALL; }
 
 // Blocks of a tiled 2-D V-cycle kernel (vos_vcycle.h, tile_of) with tiles
 // of height ty: the tile count rounded up to a multiple of the 8 XCDs.
@@ -284,6 +286,7 @@ struct vos_sim {
   bool use_graphs;
   double p_scale;           // global scale of the pressure hierarchy (set per step)
   int coarse_cells;         // levels at or below this size run in the single-block kernel
+  unsigned tile_big;        // 2-D tiled V-cycle legs: levels of at least this many cells take the tall tiles
   hipGraphExec_t gexec[8];  // one captured iteration chunk per solve
   int last_its[8];          // iterations the last solve of each slot took (0: none yet)
 
@@ -885,7 +888,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
   const bool fused = s->opt.level_kernels == 0;
   // 2-D levels with 2..4 sweeps each way: one tiled kernel per leg (vos_vcycle.h)
   auto tiled = [&](const Lv &F) { return fused && nd == 2 && nu >= 2 && nu <= 4 && F.n[0] >= 2 && F.n[1] >= 2; };
-  auto tgrid = [](const Lv &F) { return dim3(tile_blocks(F.n[0], F.n[1], tile_height(F.nc))); };
+  auto tgrid = [&](const Lv &F) { return dim3(tile_blocks(F.n[0], F.n[1], tile_height(F.nc, s->tile_big))); };
   // 3-D levels at least half a tile wide: z-marching kernels (vos_march3d.h)
   auto zmarch = [&](const Lv &F) { return fused && nd == 3 && F.n[0] >= ZT_X / 2 && F.n[1] >= 2 && F.n[2] >= 2; };
   for (int l = 0; l < lc; ++l) {
@@ -919,7 +922,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
 #define VDOWN(NU_, TY_)                                                                                   \
   if (l == 0) k_v_down2d<Lv, R, true, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc); \
   else k_v_down2d<Lv, R, false, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], r, dsc, rscale, om, sc);
-      if (tile_height(F.nc) == VT_Y_BIG) {
+      if (tile_height(F.nc, s->tile_big) == VT_Y_BIG) {
         if (nu == 2) { VDOWN(2, VT_Y_BIG) } else if (nu == 3) { VDOWN(3, VT_Y_BIG) } else { VDOWN(4, VT_Y_BIG) }
       } else {
         if (nu == 2) { VDOWN(2, VT_Y_SMALL) } else if (nu == 3) { VDOWN(3, VT_Y_SMALL) } else { VDOWN(4, VT_Y_SMALL) }
@@ -977,7 +980,7 @@ void vcycle(vos_sim *s, Lv *lv, int L, const double *Ainv, const double *r, doub
 #define VUP(NU_, TY_)                                                                                      \
   if (l == 0) k_v_up2d<Lv, R, true, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, z, dsc, sc);       \
   else k_v_up2d<Lv, R, false, NU_, TY_><<<gr, TPB, 0, st>>>(F, lv[l + 1], F.t, om, nullptr, nullptr, sc);
-      if (tile_height(F.nc) == VT_Y_BIG) {
+      if (tile_height(F.nc, s->tile_big) == VT_Y_BIG) {
         if (nu == 2) { VUP(2, VT_Y_BIG) } else if (nu == 3) { VUP(3, VT_Y_BIG) } else { VUP(4, VT_Y_BIG) }
       } else {
         if (nu == 2) { VUP(2, VT_Y_SMALL) } else if (nu == 3) { VUP(3, VT_Y_SMALL) } else { VUP(4, VT_Y_SMALL) }
@@ -1885,7 +1888,7 @@ vos_status time_kernel_t(vos_sim *s, SLevel<R> *lv, int family, int reps, double
       case VOS_KERNEL_V_DOWN:
       case VOS_KERNEL_V_UP: {
         // the tiled 2-D kernels of the finest level
-        const int ty = tile_height(lv[0].nc);
+        const int ty = tile_height(lv[0].nc, s->tile_big);
         const dim3 gr(tile_blocks(lv[0].n[0], lv[0].n[1], ty));
         const int nu = sweeps(s, 3);
         const SLevel<R> &F0 = lv[0], &F1 = lv[1];
@@ -2164,6 +2167,7 @@ vos_status vos_create(const vos_grid *grid, const vos_params *params, const vos_
   if (s->opt.mg_nu == 0) s->opt.mg_nu = grid->nz == 1 ? 4 : 3;
   s->nu_mom = opts->mg_nu == 0 ? 2 : opts->mg_nu;
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (grid->nz == 1 ? VC_TAIL_2D : VC_BLOCK_MAX);
+  s->tile_big = VT_BIG_CELLS;
   s->setup_every = std::max(1, opts->setup_every);
   s->use_graphs = opts->use_graphs != 0 && hip_stream != nullptr;   // the null stream cannot be captured
   for (int k = 0; k < 8; ++k) {
@@ -2582,6 +2586,17 @@ void get_tuning(const vos_sim *s, int *check_every, int *coarse_cells)
   *coarse_cells = s->opt.coarse_cells;
 }
 
+vos_status set_tile_big(vos_sim *s, unsigned cells)
+{
+  if (!s) return fail(VOS_ERR_ARG, "NULL simulation");
+  if (cells < 1) return fail(VOS_ERR_ARG, "tile_big must be >= 1");
+  if (cells != s->tile_big) drop_graphs(s);   // captured cycles hold the old tiles
+  s->tile_big = cells;
+  return VOS_OK;
+}
+
+unsigned get_tile_big(const vos_sim *s) { return s->tile_big; }
+
 }  // namespace vosint
 
 // ====================================================================== no-allocation pressure solve
@@ -2721,6 +2736,7 @@ extern "C" vos_status vos_solve_pressure_noalloc(const vos_grid *grid, const vos
   hierarchies_stale(s);
   if (s->opt.mg_nu == 0) s->opt.mg_nu = three ? 3 : 4;
   s->coarse_cells = opts->coarse_cells > 0 ? opts->coarse_cells : (three ? VC_BLOCK_MAX : VC_TAIL_2D);
+  s->tile_big = VT_BIG_CELLS;
 
   hipStream_t stq = s->stream;
   // the scalar blocks hold the convergence flags and the always-zero flag: cleared per call

@@ -231,8 +231,42 @@ vos_status vos_batch_tune(vos_batch *b, const double *dt, int probe_steps, int *
           if (vos_status st = vosint::set_tuning(b->sims[i], keep, k0)) return st;
       }
   }
+  // 3. tile shape of the 2-D tiled V-cycle legs per size class: the level size
+  // from which they take the tall tiles (the smaller, more numerous tiles
+  // suit the latency-bound middle levels of small grids)
+  const unsigned tcands[4] = {1u << 16, 1u << 18, 1u << 20, 0xffffffffu};
+  for (int cls : uniq) {
+    unsigned keep = 0;
+    for (int i = 0; i < b->n; ++i)
+      if (classes[i] == cls) { keep = vosint::get_tile_big(b->sims[i]); break; }
+    const unsigned cur = keep;
+    for (unsigned tb : tcands) {
+      if (tb == cur) continue;
+      for (int i = 0; i < b->n; ++i)
+        if (classes[i] == cls)
+          if (vos_status st = vosint::set_tile_big(b->sims[i], tb)) return st;
+      double t1 = 0.0;
+      if (vos_status st = time_pass(b->workers, &t1)) return st;   // captures the new cycles
+      if (vos_status st = time_pass(b->workers, &ms)) return st;   // replays
+      if (ms < best) { best = ms; keep = tb; }
+    }
+    for (int i = 0; i < b->n; ++i)
+      if (classes[i] == cls)
+        if (vos_status st = vosint::set_tile_big(b->sims[i], keep)) return st;
+  }
   if (workers) *workers = b->workers;
   if (best_ms) *best_ms = best;
+  return VOS_OK;
+}
+
+vos_status vos_batch_tuning(vos_batch *b, int i, int *check_every, unsigned *tile_big_cells)
+{
+  if (!b) return fail(VOS_ERR_ARG, "NULL batch");
+  if (i < 0 || i >= b->n) return fail(VOS_ERR_ARG, "instance index out of range");
+  int ce = 0, cc = 0;
+  vosint::get_tuning(b->sims[i], &ce, &cc);
+  if (check_every) *check_every = ce;
+  if (tile_big_cells) *tile_big_cells = vosint::get_tile_big(b->sims[i]);
   return VOS_OK;
 }
 

@@ -28,5 +28,9 @@ vos_status unet_forward_on(vos_unet *net, hipStream_t stream);
 // captured graphs.  Neither value changes the workspace layout.
 vos_status set_tuning(vos_sim *s, int check_every, int coarse_cells);
 void get_tuning(const vos_sim *s, int *check_every, int *coarse_cells);
+// Tile shape of the 2-D tiled V-cycle legs: levels of at least `cells` cells
+// take the tall tiles (results do not depend on it).
+vos_status set_tile_big(vos_sim *s, unsigned cells);
+unsigned get_tile_big(const vos_sim *s);
 
 }  // namespace vosint

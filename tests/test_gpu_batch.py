@@ -78,6 +78,13 @@ def test_tuned_batch_still_bitwise():
     t = b.tune(dt, probe_steps=1)
     print(t)
     assert 1 <= t["workers"] <= 16 and t["best_ms"] > 0
+    # the chosen check intervals and tile shapes (the standalone references
+    # below run with the defaults: every tile shape gives the same values)
+    for k in range(len(sp)):
+        tk = b.tuning(k)
+        print(k, tk, flush=True)
+        assert tk["check_every"] in (2, 4, 8, 16, 32) or tk["check_every"] == opts().check_every
+        assert tk["tile_big_cells"] in (1 << 16, 1 << 18, 1 << 20, 0xFFFFFFFF)
     start = [{f: b.sims[k].get_numpy(f) for f in ("eps", "ux", "uy", "uz", "p", "c")} for k in range(len(sp))]
     b.step(dt, 2)
     for k, s in enumerate(sp):
