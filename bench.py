@@ -596,6 +596,34 @@ def pack_leg(vos, inputs, scaling, args):
     return head, roof, others, comps, params, info, cells
 
 
+def micromodel_sweep(vos, inputs, scaling, steps, dt):
+    """The 1024x512 micromodel configuration's runs: Pe in {0.1, 10, 100} x Da
+    in {1e-3, 1e-1}, plain FP64 and mixed precision, `steps` dissolving steps
+    each (after 3 untimed ones).  Cache-resident rates (~100 MB of state)."""
+    import torch
+    runs = []
+    for pe in (0.1, 10.0, 100.0):
+        for da in (1e-3, 1e-1):
+            for prec, tag in ((vos.FP64, "fp64"), (vos.MIXED, "mixed")):
+                sim, es, params, info = setup_sim(vos, inputs, scaling, "micromodel", pe, da, prec, 0, dt, 40)
+                nz, ny, nx = es.shape
+                el, diags = timed_steps(sim, dt, steps, 3)
+                r = run_summary(diags, el, nx * ny * nz, steps, 2, tag, info, params)
+                runs.append({"Pe": pe, "Da": da, "precision": tag, "value": r["value"],
+                             "ms_per_step": round(r["ms_per_step"], 4),
+                             "pressure_its_per_step": r["pressure_its_per_step"],
+                             "momentum_its_per_step": r["momentum_its_per_step"][:2],
+                             "transport_its_per_step": r["transport_its_per_step"],
+                             "achieved": {k: r["achieved"][k] for k in ("Pe", "Da")},
+                             "porosity_change": float(sim.get("eps").mean()) - info["phi"]})
+                sim.close()
+                del sim
+                torch.cuda.empty_cache()
+    return {"workload": f"micromodel 1024x512 dx=5um RSA discs seed 11, iVoS, dt={dt:g}s, rtol 1e-8, "
+                        f"{steps} dissolving steps per run; Infinity-Cache (MALL) resident",
+            "steps": steps, "runs": runs}
+
+
 def micromodel_leg(vos, inputs, scaling, steps, warmup, dt):
     """The 1024x512 micromodel (Pe = 10, Da = 0.1), mixed precision: its
     ~100 MB state lives in the 256 MB Infinity Cache, so its rates are
@@ -668,7 +696,7 @@ def upscaling_leg(vos, inputs, scaling, budget_s, target_rel, dt_setup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)   # the pack configuration's 100 steps
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pe", type=float, default=10.0)
     ap.add_argument("--da", type=float, default=1e-2)
@@ -684,6 +712,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micromodel", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-micromodel batch")
+    ap.add_argument("--no-micromodel-sweep", action="store_true",
+                    help="skip the micromodel runs over Pe, Da and precision")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net timing")
@@ -741,6 +771,11 @@ def main():
         if not args.no_micromodel:
             log("micromodel 1024x512")
             extra["micromodel_mall_resident"] = micromodel_leg(vos, inputs, scaling, 20, 3, args.dt)
+        if not args.no_micromodel_sweep:
+            log("micromodel runs: Pe x Da x precision, 200 steps each")
+            extra["micromodel_sweep"] = micromodel_sweep(vos, inputs, scaling, 200, args.dt)
+            for r in extra["micromodel_sweep"]["runs"]:
+                log(f"  Pe {r['Pe']:g} Da {r['Da']:g} {r['precision']}: {r['ms_per_step']:.3f} ms/step")
         if not args.no_batch:
             log(f"batch of {args.batch_n} micromodels")
             extra["batch_micromodels"] = batch_bench(vos, inputs, scaling, args.batch_n, args.batch_steps, args.dt)
