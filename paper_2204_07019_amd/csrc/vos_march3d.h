@@ -777,7 +777,8 @@ __global__ void __launch_bounds__(ZT_X * zf_rows<R>) k_v_down3d(Lv F, Lv C, cons
     b_cur = rhs(b.bb, b.dg);
     if (c0.in) F.x[c0.col + sz * (unsigned)t.z0] = b.u;
   }
-  for (int z = t.z0; z < t.z1; ++z) {
+  // one plane of the march, called twice per loop trip as in the up leg
+  auto plane = [&](int z) {
     S1 a = load1p(c0, z + 1, held, 0), a1 = load1p(c1, z + 1, held, 1);
     const P0 next = load0(z + 3);
     put0(z + 2, ahead);
@@ -806,7 +807,7 @@ __global__ void __launch_bounds__(ZT_X * zf_rows<R>) k_v_down3d(Lv F, Lv C, cons
     u_cur = a.u;
     k_cur = a.k;
     b_cur = rhs(a.bb, a.dg);
-    if ((z & 1) == 0 && z + 1 < nz) continue;   // block-uniform
+    if ((z & 1) == 0 && z + 1 < nz) return;   // block-uniform
     __syncthreads();
     if (threadIdx.x < (ZT_X / 2) * (FY / 2)) {
       const int ix = threadIdx.x % (ZT_X / 2), iy = threadIdx.x / (ZT_X / 2);
@@ -822,7 +823,13 @@ __global__ void __launch_bounds__(ZT_X * zf_rows<R>) k_v_down3d(Lv F, Lv C, cons
         C.b[(unsigned)IX + (unsigned)C.n[0] * ((unsigned)IY + (unsigned)C.n[1] * (unsigned)IZ)] = sum;
       }
     }
+  };
+  int z = t.z0;
+  for (; z + 1 < t.z1; z += 2) {
+    plane(z);
+    plane(z + 1);
   }
+  if (z < t.z1) plane(z);   // block-uniform
 }
 
 // Up leg: the prolongation with the first post-smoothing sweep of k_v_post3d
@@ -936,7 +943,10 @@ __global__ void __launch_bounds__(ZT_X * zf_rows<R>) k_v_up3d(Lv F, Lv C, R *__r
     k_cur = b.k;
     b_cur = rhs(b.b, b.k.d);
   }
-  for (int z = t.z0; z < t.z1; ++z) {
+  // one plane of the march; called twice per loop trip (the compiler does not
+  // unroll a loop with a barrier itself), which saves some of the copies of the
+  // values carried from plane to plane
+  auto plane = [&](int z) {
     S1 a = load1(c0, z + 1), a1 = load1(c1, z + 1);
     const P0 next = load0(z + 3);
     put0(z + 2, ahead);
@@ -965,7 +975,13 @@ __global__ void __launch_bounds__(ZT_X * zf_rows<R>) k_v_up3d(Lv F, Lv C, R *__r
     u_cur = a.u;
     k_cur = a.k;
     b_cur = rhs(a.b, a.k.d);
+  };
+  int z = t.z0;
+  for (; z + 1 < t.z1; z += 2) {
+    plane(z);
+    plane(z + 1);
   }
+  if (z < t.z1) plane(z);   // block-uniform
 }
 
 // Pressure operator q = A p in papply_cell's expression order, with the
