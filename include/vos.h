@@ -122,7 +122,7 @@ typedef struct {
                        check_every in the worst case; results are identical); 0: plain launches.
                        Ignored (off) when vos_create() is given the null stream. */
   int coarse_cells; /* multigrid levels with at most this many cells run inside one single-block
-                       kernel, 64..65536 (0: 2048 in 2-D, 4096 in 3-D) */
+                       kernel, 64..65536 (0: 2048) */
   int level_kernels;/* kernels of the fine multigrid levels: 0 fused (2-D: one tiled kernel per
                        leg of a level; 3-D: sweeps that march through z with the neighbours in
                        LDS and registers); 1 one plain kernel per sweep.  Both form every value

@@ -23,7 +23,9 @@
 
 namespace vos {
 
-constexpr int VC_BLOCK_MAX = 4096;   // levels at or below this size run in the single-block kernel (3-D)
+// levels at or below this size run in the single-block kernel (3-D): a 16^3
+// level costs the block more than its own multi-block launches do
+constexpr int VC_BLOCK_MAX = 2048;
 constexpr int VC_TAIL_2D = 2048;     // the same in 2-D (the tail runs in LDS, k_v_coarse_lds)
 constexpr int VC_MAX_LEVELS = 20;
 constexpr int VC_COARSE_TPB = 1024;
