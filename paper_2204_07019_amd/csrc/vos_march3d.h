@@ -71,10 +71,14 @@ inline unsigned zrun_blocks(const int n[3], int zlen)
 
 // The fused two-sweep legs (k_v_down3d / k_v_up3d) recompute a few planes at
 // the start of every z-run and hold more LDS and registers per block than the
-// separate kernels, so fewer blocks are resident per CU.  Their z-runs are cut
-// so that all work items are resident at once (slots = CUs x resident blocks
-// per CU; a second, partial round of blocks would leave most CUs idle at the
-// end), and are at least 8 planes long.  They run on levels of at least 2^20
+// separate kernels, so fewer blocks are resident per CU (slots = CUs x
+// resident blocks per CU).  A launch then runs in rounds = ceil(blocks /
+// slots) waves of resident blocks, each taking about (z-run + 3) plane times,
+// so the runs are cut so that every block is resident at once, unless that
+// leaves more than a quarter of the slots idle: then the run count is the one
+// that minimises rounds x (z-run + 3) (384^3 with 144 FP64 tiles on 256
+// slots: 7 runs of 56 planes in 4 rounds instead of one 384-plane run on 144
+// CUs).  Runs are even and at least 8 planes long.  They run on levels of at least 2^20
 // cells (the smaller levels keep the separate kernels).  Their tiles are
 // ZT_X x zf_rows<R> cells for a level of R values, one thread per cell: 16
 // rows for FP64 levels (fewer halo cells per tile cell; one 1024-thread block
@@ -85,10 +89,23 @@ constexpr int zf_rows = sizeof(R) == 8 ? 16 : 8;
 inline long zfused_tiles(const int n[3], int fy) { return (long)((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + fy - 1) / fy); }
 inline int zrun_len_fused(const int n[3], int slots, int fy)
 {
-  const long runs = std::max(1L, (long)slots / zfused_tiles(n, fy));
-  long zl = ((long)n[2] + runs - 1) / runs;
-  zl = std::max(8L, zl + (zl & 1));
-  return (int)zl;
+  const long tiles = zfused_tiles(n, fy), sl = std::max(1, slots);
+  const long runs0 = std::max(1L, sl / tiles);
+  long z0 = ((long)n[2] + runs0 - 1) / runs0;
+  z0 = std::max(8L, z0 + (z0 & 1));
+  if (4 * tiles * (((long)n[2] + z0 - 1) / z0) >= 3 * sl) return (int)z0;
+  long best = z0, best_cost = -1;
+  for (long runs = 1; runs <= n[2]; ++runs) {
+    long zl = ((long)n[2] + runs - 1) / runs;
+    zl = std::max(8L, zl + (zl & 1));
+    const long blocks = tiles * (((long)n[2] + zl - 1) / zl);
+    const long cost = (blocks + sl - 1) / sl * (zl + 3);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = zl;
+    }
+  }
+  return (int)best;
 }
 // Blocks of a fused-leg launch: its work items rounded up to a multiple of the 8 XCDs.
 inline unsigned zrun_blocks_fused(const int n[3], int zlen, int fy)

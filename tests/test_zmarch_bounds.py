@@ -47,7 +47,14 @@ def test_pack_128_in_bounds(emu):
     assert "momentum x FP64 level 0: 129 x 128 x 128" in out
 
 
-@pytest.mark.skipif(os.environ.get("VOS_EMU_FULL") != "1", reason="set VOS_EMU_FULL=1 (about four minutes)")
+def test_partly_filled_fused_launch_in_bounds(emu):
+    # 144 FP64 tiles on 256 slots: the fused legs run short z-runs in several
+    # rounds of blocks instead of one run per tile
+    out = _run(emu, 384, 384, 32)
+    assert "transport FP64 level 0: 384 x 384 x 32" in out
+
+
+@pytest.mark.skipif(os.environ.get("VOS_EMU_FULL") != "1", reason="set VOS_EMU_FULL=1 (tens of minutes)")
 def test_pack_256_in_bounds(emu):
     out = _run(emu, 256, 256, 256, timeout=1800)
     assert "pressure operator: z-run" in out
