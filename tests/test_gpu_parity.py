@@ -237,6 +237,8 @@ LEVEL_CASES = [  # (shape, precision, extra options): 2-D tiled and 3-D marching
     # up legs (transport, momentum; with mg_nu 2 the pressure levels too)
     ((130, 70, 130), 0, {}),
     ((130, 70, 130), 1, {"mg_nu": 2, "extrapolate": 2}),
+    # 144 tiles of the FP64 legs for 256 CUs: short z-runs in several rounds of blocks
+    ((384, 384, 32), 1, {}),
 ]
 
 
