@@ -1,9 +1,9 @@
 """GPU against the FP64 oracle on the 3-D grain pack: the seeded overlapping
 sphere pack with its one-voxel partial-volume ramp and 1 % interface noise
 (the 256^3 workload's geometry at 48^3, radius scaled with the box), every
-reaction model, both precisions, 5 steps; and one step of a 128^3 pack at the
-production launch shapes checked stage by stage against the oracle's own
-discrete equations assembled from the same input state.
+reaction model, both precisions, 5 steps; and one step of a 128^3 and of a
+256^3 pack at the production launch shapes checked stage by stage against the
+oracle's own discrete equations assembled from the same input state.
 """
 import multiprocessing as mp
 import sys
@@ -104,21 +104,18 @@ def test_sphere_pack_matches_oracle(orc, oracle_runs, model, precision):
         assert dg["lambda"] == pytest.approx(do["lambda"], rel=1e-10)
 
 
-@pytest.mark.timeout(600)
-@pytest.mark.parametrize("model", [0, 2])
-def test_pack_128_stagewise(orc, model):
-    """One mixed-precision step of a 128^3 pack (the production z-marching
-    kernels and tile shapes, rtol 1e-8): each stage's GPU output satisfies the
-    oracle's discrete equations assembled from the same state."""
+def _stagewise(n, model):
+    """One mixed-precision step of an n^3 pack at rtol 1e-8: each stage's GPU
+    output satisfies the oracle's discrete equations assembled from the same
+    state."""
     import oracle
     from paper_2204_07019_amd import inputs
     from test_gpu_parity import _scaled_resid
-    n = 128
     es = _pack(n)
     prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=4e-6), model=model)
     sim = gpu_sim(prob, 1, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000)
     sim.set_solid_fraction(es)
-    _say(f"pack 128^3 stagewise model {model}")
+    _say(f"pack {n}^3 stagewise model {model}")
     sim.step(DT, 2)
     before = {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
     d = sim.step(DT)
@@ -151,3 +148,18 @@ def test_pack_128_stagewise(orc, model):
     rbar, sink, gmag, lam, eps_new = oracle.reaction(prob, DT, before["eps"], after["c"], before["c"])
     assert rel_l2(after["rbar"], rbar) < 1e-11
     assert np.abs(after["eps"] - eps_new).max() < 1e-15
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("model", [0, 2])
+def test_pack_128_stagewise(orc, model):
+    """128^3 (the production z-marching kernels and tile shapes)."""
+    _stagewise(128, model)
+
+
+@pytest.mark.timeout(900)
+def test_pack_256_stagewise(orc):
+    """256^3 iVoS: the grid, the geometry recipe and the launch shapes of the
+    benchmarked step (64-plane runs of the fused legs, the single-block tail
+    from 2048 cells)."""
+    _stagewise(256, 0)
