@@ -104,18 +104,18 @@ def test_sphere_pack_matches_oracle(orc, oracle_runs, model, precision):
         assert dg["lambda"] == pytest.approx(do["lambda"], rel=1e-10)
 
 
-def _stagewise(n, model):
-    """One mixed-precision step of an n^3 pack at rtol 1e-8: each stage's GPU
-    output satisfies the oracle's discrete equations assembled from the same
-    state."""
+def _stagewise(n, model, precision=1):
+    """One step of an n^3 pack (mixed precision by default) at rtol 1e-8: each
+    stage's GPU output satisfies the oracle's discrete equations assembled from
+    the same state."""
     import oracle
     from paper_2204_07019_amd import inputs
     from test_gpu_parity import _scaled_resid
     es = _pack(n)
     prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=4e-6), model=model)
-    sim = gpu_sim(prob, 1, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000)
+    sim = gpu_sim(prob, precision, rtol_u=1e-8, rtol_p=1e-8, rtol_c=1e-8, maxit_p=6000)
     sim.set_solid_fraction(es)
-    _say(f"pack {n}^3 stagewise model {model}")
+    _say(f"pack {n}^3 stagewise model {model} precision {precision}")
     sim.step(DT, 2)
     before = {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
     d = sim.step(DT)
@@ -158,8 +158,9 @@ def test_pack_128_stagewise(orc, model):
 
 
 @pytest.mark.timeout(900)
-def test_pack_256_stagewise(orc):
-    """256^3 iVoS: the grid, the geometry recipe and the launch shapes of the
-    benchmarked step (64-plane runs of the fused legs, the single-block tail
-    from 2048 cells)."""
-    _stagewise(256, 0)
+@pytest.mark.parametrize("precision", [1, 0])
+def test_pack_256_stagewise(orc, precision):
+    """256^3 iVoS, mixed and FP64: the grid, the geometry recipe and the launch
+    shapes of the benchmarked step (64-plane runs of the fused legs, the
+    single-block tail from 2048 cells)."""
+    _stagewise(256, 0, precision)
