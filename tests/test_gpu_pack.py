@@ -158,9 +158,10 @@ def test_pack_128_stagewise(orc, model):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("precision", [1, 0])
-def test_pack_256_stagewise(orc, precision):
-    """256^3 iVoS, mixed and FP64: the grid, the geometry recipe and the launch
-    shapes of the benchmarked step (64-plane runs of the fused legs, the
-    single-block tail from 2048 cells)."""
-    _stagewise(256, 0, precision)
+@pytest.mark.parametrize("model,precision", [(0, 1), (0, 0), (2, 1)])
+def test_pack_256_stagewise(orc, model, precision):
+    """256^3, the models and precisions the benchmark reports (iVoS mixed and
+    FP64, VoS-psi' mixed): the grid, the geometry recipe and the launch shapes
+    of the benchmarked step (64-plane runs of the fused legs, the single-block
+    tail from 2048 cells)."""
+    _stagewise(256, model, precision)
