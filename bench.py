@@ -547,7 +547,11 @@ def run_summary(diags, el, cells, steps, nd, tag, info=None, params=None):
            "pressure_ms_per_step": t_p / len(diags) * 1e3,
            "pressure_GBs_algorithmic": round(pb / t_p / 1e9, 1) if t_p > 0 else None,
            "pressure_frac_hbm": round(pb / t_p / 1e9 / HBM_PEAK_GBS, 4) if t_p > 0 else None,
-           "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)]}
+           "stage_ms": [round(sum(d["t_ms"][k] for d in diags) / len(diags), 3) for k in range(6)],
+           # worst per-step closure of the acid and solid balances (relative), a
+           # check of the timed steps themselves at the run's size
+           "max_balance_rel": {"acid": max(abs(d["acid_balance_rel"]) for d in diags),
+                               "solid": max(abs(d["solid_balance_rel"]) for d in diags)}}
     if info is not None and params is not None:
         from paper_2204_07019_amd import scaling
         last = diags[-1]

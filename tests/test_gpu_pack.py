@@ -143,8 +143,11 @@ def _stagewise(n, model, precision=1):
     st_c.ux[:], st_c.uy[:], st_c.uz[:] = after["ux"], after["uy"], after["uz"]
     sten, rhs, dims = oracle.assemble(prob, st_c, DT, 4)
     rel, _ = _scaled_resid(sten, rhs, dims, after["c"], "row")
-    _say(f"transport rel resid {rel:.2e} (its {d['it_c']})")
+    _say(f"transport rel resid {rel:.2e} (its {d['it_c']}); balances acid {d['acid_balance_rel']:.2e} "
+         f"solid {d['solid_balance_rel']:.2e}")
     assert rel < 5e-8
+    # the discretisation is conservative: both balances close to rounding
+    assert abs(d["acid_balance_rel"]) < 1e-9 and abs(d["solid_balance_rel"]) < 1e-9
     rbar, sink, gmag, lam, eps_new = oracle.reaction(prob, DT, before["eps"], after["c"], before["c"])
     assert rel_l2(after["rbar"], rbar) < 1e-11
     assert np.abs(after["eps"] - eps_new).max() < 1e-15
