@@ -146,8 +146,10 @@ def _stagewise(n, model, precision=1):
     _say(f"transport rel resid {rel:.2e} (its {d['it_c']}); balances acid {d['acid_balance_rel']:.2e} "
          f"solid {d['solid_balance_rel']:.2e}")
     assert rel < 5e-8
-    # the discretisation is conservative: both balances close to rounding
-    assert abs(d["acid_balance_rel"]) < 1e-9 and abs(d["solid_balance_rel"]) < 1e-9
+    # the discretisation is conservative: the acid balance closes to the
+    # transport solve's tolerance (rtol 1e-8; up to 7e-9 over the benchmark's
+    # 100 steps), the solid balance to rounding
+    assert abs(d["acid_balance_rel"]) < 1e-7 and abs(d["solid_balance_rel"]) < 1e-9
     rbar, sink, gmag, lam, eps_new = oracle.reaction(prob, DT, before["eps"], after["c"], before["c"])
     assert rel_l2(after["rbar"], rbar) < 1e-11
     assert np.abs(after["eps"] - eps_new).max() < 1e-15
