@@ -84,6 +84,50 @@ def test_post_20_steps(orc, precision):
     assert dg["solid_rate"] == pytest.approx(do["solid_rate"], rel=1e-6)
 
 
+LONG_STEPS = 200
+
+
+@pytest.fixture(scope="module")
+def micromodel_200():
+    """The oracle over the micromodel configuration's horizon: 200 dissolving
+    steps of 1 ms on a 128x64 RSA-disc micromodel (dx = 5 um, iVoS, tolerances
+    1e-12); computed once for both precisions."""
+    import oracle
+    from paper_2204_07019_amd import inputs
+    es = inputs.rsa_discs(128, 64, seed=11, rmin=3, rmax=10)
+    prob = make_problem(es, dict(inputs.BASE_PARAMS, dx=5e-6), model=0, **TIGHT)
+    _say(f"oracle: micromodel 128x64, {LONG_STEPS} steps")
+    st = oracle.initial_state(prob, es)
+    eps0 = st.eps.copy()
+    last = None
+    for _ in range(LONG_STEPS):
+        last = oracle.step(prob, st, 1e-3)
+    return es, prob, st, eps0, last
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_micromodel_200_steps(orc, micromodel_200, precision):
+    """The 200-step horizon of the micromodel runs: after 200 dissolving steps
+    every field is still within 1e-6 of the oracle, and the change of eps
+    (the dissolution itself) within 1e-9."""
+    es, prob, st, eps0, do = micromodel_200
+    _say(f"micromodel 128x64 {LONG_STEPS} steps precision {precision}")
+    sim = gpu_sim(prob, precision)
+    sim.set_solid_fraction(es)
+    worst = 0.0
+    for _ in range(LONG_STEPS):
+        dg = sim.step(1e-3)
+        worst = max(worst, abs(dg["acid_balance_rel"]))
+    g = {k: sim.get_numpy(k) for k in ("eps", "ux", "uy", "uz", "p", "c")}
+    sim.close()
+    r = _compare(st, g, eps0)
+    _say(f"micromodel 200 steps rel L2 {r}; worst acid balance {worst:.2e}")
+    assert r["deps"] <= 1e-9, r
+    assert worst < 1e-9
+    assert dg["solid_rate"] == pytest.approx(do["solid_rate"], rel=1e-6)
+
+
 @pytest.mark.parametrize("extrapolate,setup_every", [(1, 1), (2, 1), (2, 3)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_extrapolated_starts_match_oracle(orc, precision, extrapolate, setup_every):
